@@ -1,0 +1,369 @@
+"""Plain FP64 CPU oracle of the FiRE hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU leg of
+the benchmark may import this module; the product path never does.
+
+It is the dense definition of the method, evaluated walker-batched with
+torch float64 on the CPU:
+
+* every electron pair and every electron-nucleus pair is evaluated; the
+  cutoffs enter only through the smooth cutoff factor, which is exactly zero
+  at and beyond the cutoff, so the sum over all pairs equals the sum over the
+  finite-range neighbourhoods (Methods, "Finite-range embeddings");
+* every Metropolis proposal and every pseudopotential quadrature point is a
+  full re-evaluation (no low-rank update);
+* gradients, Laplacians and parameter gradients come from reverse/forward
+  automatic differentiation, not from the sparse forward Laplacian.
+
+Readings of the paper where it is silent (all listed in the design notes):
+spin-block determinants; exp(-sigma |r - R|) envelopes with exponents shared
+over orbitals; SiLU activations; a LLaMA-style GLU W_o[(LN(s)W_v+b_v) *
+SiLU(LN(s)W_g+b_g)] + b_o; filters 4 -> 16 -> 8 -> d with a 32-Gaussian radial
+part; the polynomial cutoff with p = 6; separate parallel/antiparallel
+message weights; no Jastrow factor (J = 1); semilocal l = 0, 1 pseudopotential
+channels with a 12-point icosahedral rule.
+
+Parity unpinned: none of the functions below is compared against a number
+the paper prints (it prints none for this path); each is pinned instead by
+the identities, limits and closed forms in tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+torch.set_default_dtype(torch.float64)
+DT = torch.float64
+FCUT_P = 6
+LN_EPS = 1e-5
+
+
+def silu(x):
+    return x * torch.sigmoid(x)
+
+
+def fcut(x):
+    """Polynomial cutoff of Gasteiger et al. with p = 6 (Methods, spatial
+    filters): 1 - (p+1)(p+2)/2 x^p + p(p+2) x^(p+1) - p(p+1)/2 x^(p+2) below
+    x = 1, exactly zero at and beyond 1."""
+    p = FCUT_P
+    poly = 1 - (p + 1) * (p + 2) / 2 * x ** p + p * (p + 2) * x ** (p + 1) - p * (p + 1) / 2 * x ** (p + 2)
+    return torch.where(x < 1.0, poly, torch.zeros_like(x))
+
+
+def _safe_norm(v, mask_zero=None):
+    """|v| along the last axis; entries flagged in mask_zero are computed on a
+    dummy unit vector so autodiff never sees the singular point (they are
+    multiplied by zero by the caller)."""
+    if mask_zero is not None:
+        dummy = torch.zeros_like(v)
+        dummy[..., 0] = 1.0
+        v = torch.where(mask_zero[..., None], dummy, v)
+    return torch.sqrt((v * v).sum(-1)), v
+
+
+def _log1p_over(r):
+    """log(1+r)/r with its limit 1 at r = 0."""
+    small = r < 1e-8
+    rs = torch.where(small, torch.ones_like(r), r)
+    return torch.where(small, 1.0 - 0.5 * r, torch.log1p(rs) / rs)
+
+
+class Oracle:
+    """Dense FP64 evaluation of one system with one parameter set."""
+
+    def __init__(self, system, model, params: Dict[str, np.ndarray]):
+        self.sys = system
+        self.model = model
+        self.n_up, self.n_dn = system.n_up, system.n_dn
+        self.n = system.n_el
+        self.Rn = torch.tensor(system.R_nuc, dtype=DT)
+        self.Z = torch.tensor(system.Z, dtype=DT)
+        self.nuc_type = torch.tensor(system.nuc_type, dtype=torch.long)
+        self.pp_width = torch.tensor(system.pp_width, dtype=DT)
+        self.p = {k: torch.tensor(v, dtype=DT) for k, v in params.items()}
+        spin = torch.zeros(self.n, dtype=torch.long)
+        spin[self.n_up:] = 1
+        self.spin = spin
+
+    # ------------------------------------------------------------------
+    # network pieces
+    # ------------------------------------------------------------------
+    def filter(self, feat, rho, W1, b1, W2, b2, W3, Wenv, sig, cutoff, per_nucleus=False):
+        """Gamma(x) = [SiLU(SiLU(x W1 + b1) W2 + b2) W3] * [chi(x_0) W_env],
+        chi(x_0) = f_cut(x_0/c) * exp(-sigma_k^2 x_0^2) (Methods, eq. for
+        Gamma_m and chi).  With per_nucleus, W1 [M,4,h] and b1 [M,h] differ
+        per nucleus (the third-from-last axis of feat)."""
+        if per_nucleus:
+            z = torch.einsum("bnmk,mkh->bnmh", feat, W1) + b1
+        else:
+            z = feat @ W1 + b1
+        z = silu(z)
+        z = silu(z @ W2 + b2)
+        radial = fcut(rho / cutoff)[..., None] * torch.exp(-(sig ** 2) * rho[..., None] ** 2)
+        return (z @ W3) * (radial @ Wenv)
+
+    def layernorm(self, s):
+        mu = s.mean(-1, keepdim=True)
+        var = ((s - mu) ** 2).mean(-1, keepdim=True)
+        return (s - mu) / torch.sqrt(var + LN_EPS) * self.p["ln_g"] + self.p["ln_b"]
+
+    def embed(self, R):
+        """All intermediate embeddings for walkers R [B,n,3]."""
+        p, cn, c = self.p, self.model.cutoff_nuc, self.model.cutoff
+        B, n = R.shape[0], self.n
+        out = {}
+        # --- electron-nucleus part: initial embedding h0 (Methods, h^0_i)
+        x = R[:, :, None, :] - self.Rn[None, None]                 # [B,n,M,3]
+        rho, _ = _safe_norm(x, (x.abs().sum(-1) == 0))
+        e = torch.cat([rho[..., None], x], -1)                     # [B,n,M,4]
+        ebar = _log1p_over(rho)[..., None] * e
+        t = self.nuc_type
+        gam = self.filter(e, rho, p["en_W1"][t], p["en_b1"][t], p["en_W2"], p["en_b2"],
+                          p["en_W3"], p["en_Wenv"], p["en_sig"], cn, per_nucleus=True)
+        val = p["nuc_emb"][t] + ebar @ p["en_Wn"]
+        s = (gam * val).sum(2)                                     # [B,n,d]
+        y = self.layernorm(s)
+        h0 = ((y @ p["glu_Wv"] + p["glu_bv"]) * silu(y @ p["glu_Wg"] + p["glu_bg"])) @ p["glu_Wo"] + p["glu_bo"]
+        out["s"], out["h0"] = s, h0
+        # --- one message-passing step over electron pairs (Methods, m^alpha_i)
+        dr = R[:, :, None, :] - R[:, None, :, :]                   # r_i - r_j  [B,n,n,3]
+        eye = torch.eye(n, dtype=torch.bool)[None].expand(B, n, n)
+        r, dr_s = _safe_norm(dr, eye)
+        ee = torch.cat([r[..., None], dr_s], -1)
+        eebar = _log1p_over(r)[..., None] * ee
+        same = (self.spin[:, None] == self.spin[None, :])
+        m = torch.zeros_like(h0)
+        out["m"] = []
+        for a in (0, 1):
+            mask = (~eye) & (same if a == 0 else ~same)[None]
+            gam = self.filter(ee, r, p["ee_W1"][a], p["ee_b1"][a], p["ee_W2"][a], p["ee_b2"][a],
+                              p["ee_W3"][a], p["ee_Wenv"][a], p["ee_sig"][a], c)
+            pre = (h0 @ p["msg_Wa"][a])[:, :, None, :] + (h0 @ p["msg_Wb"][a])[:, None, :, :] \
+                + eebar @ p["msg_We"][a] + p["msg_b"][a]
+            ma = (gam * silu(pre) * mask[..., None]).sum(2)
+            out["m"].append(ma)
+            m = m + ma
+        h = h0 + m
+        out["h1"] = h
+        # --- embedding MLP
+        for k in range(self.model.mlp_layers):
+            h = silu(h @ p["mlp_W"][k] + p["mlp_b"][k])
+        out["h"] = h
+        return out
+
+    def envelopes(self, R, spin):
+        """phi_l(r_i) = sum_{m,e} pi_{lme} exp(-sigma_me |r_i - R_m|) for the
+        electrons of one spin block, all determinants: [B,K,N,N]."""
+        p = self.p
+        nu = self.n_up
+        Rs = R[:, :nu] if spin == 0 else R[:, nu:]
+        dist = torch.sqrt(((Rs[:, :, None, :] - self.Rn[None, None]) ** 2).sum(-1))  # [B,N,M]
+        basis = torch.exp(-p["env_sigma"][None, None] * dist[..., None])              # [B,N,M,E]
+        pi = p["env_pi_up"] if spin == 0 else p["env_pi_dn"]                          # [K,N,M,E]
+        return torch.einsum("bime,klme->bkil", basis, pi)
+
+    def orbitals(self, R, h):
+        """Phi_{d,sigma}[i,l] = (h_i . W_{d,sigma}[:,l]) * phi_{d,sigma,l}(r_i)."""
+        nu = self.n_up
+        out = []
+        for spin, Wk in ((0, "orb_W_up"), (1, "orb_W_dn")):
+            hs = h[:, :nu] if spin == 0 else h[:, nu:]
+            proj = torch.einsum("bid,kdl->bkil", hs, self.p[Wk])
+            out.append(proj * self.envelopes(R, spin))
+        return out
+
+    def log_psi_parts(self, R):
+        """Per-determinant (sign, log|det|) and the signed log-sum-exp."""
+        h = self.embed(R)["h"]
+        phis = self.orbitals(R, h)
+        B, K = R.shape[0], self.model.n_det
+        sgn = torch.ones(B, K, dtype=DT)
+        ld = torch.zeros(B, K, dtype=DT)
+        for phi in phis:
+            if phi.shape[-1] == 0:
+                continue
+            s, l = torch.linalg.slogdet(phi)
+            sgn = sgn * s
+            ld = ld + l
+        lmax = ld.max(1, keepdim=True).values
+        tot = (sgn * torch.exp(ld - lmax)).sum(1)
+        sign = torch.sign(tot)
+        logpsi = lmax[:, 0] + torch.log(torch.abs(tot))
+        return sign, logpsi, sgn, ld, phis
+
+    def log_psi(self, R):
+        """(sign, log|psi|) for walkers R [B,n,3], psi = sum_d det Phi_d (J = 1)."""
+        R = torch.as_tensor(R, dtype=DT)
+        s, l, *_ = self.log_psi_parts(R)
+        return s, l
+
+    # ------------------------------------------------------------------
+    # Hamiltonian
+    # ------------------------------------------------------------------
+    def local_pp(self, r):
+        """v_loc,m(r) = -Z_m/r (bare) or -Z_m erf(r/w_m)/r (pseudo-atoms)."""
+        w = self.pp_width
+        Z = self.Z
+        bare = -Z / r
+        ws = torch.where(w > 0, w, torch.ones_like(w))
+        smooth = -Z * torch.erf(r / ws) / r
+        small = r < 1e-10
+        lim = -Z * 2.0 / (ws * math.sqrt(math.pi))
+        smooth = torch.where(small, lim, smooth)
+        return torch.where(w > 0, smooth, bare)
+
+    def potential(self, R):
+        """[V_ee, V_en, V_nn] per walker (Methods, Hamiltonian, with the local
+        pseudopotential replacing -Z/r on pseudo-atoms)."""
+        R = torch.as_tensor(R, dtype=DT)
+        B, n = R.shape[:2]
+        iu = torch.triu_indices(n, n, 1)
+        dr = R[:, iu[0]] - R[:, iu[1]]
+        vee = (1.0 / torch.sqrt((dr ** 2).sum(-1))).sum(1)
+        rim = torch.sqrt(((R[:, :, None] - self.Rn[None, None]) ** 2).sum(-1))
+        ven = self.local_pp(rim).sum((1, 2))
+        M = self.Rn.shape[0]
+        vnn = 0.0
+        for a in range(M):
+            for b in range(a + 1, M):
+                vnn += float(self.Z[a] * self.Z[b] / torch.linalg.norm(self.Rn[a] - self.Rn[b]))
+        return torch.stack([vee, ven, torch.full_like(vee, vnn)], 1)
+
+    def grad_lap(self, R, chunk: int = 64):
+        """grad log|psi| [B,n,3] and Laplacian of log|psi| [B], by reverse mode
+        for the gradient and forward-over-reverse for each diagonal Hessian
+        element (exact, no finite differences)."""
+        from torch.func import grad, jvp, vmap
+        R = torch.as_tensor(R, dtype=DT)
+        B, n = R.shape[:2]
+
+        def f(x):
+            return self.log_psi_parts(x.reshape(1, n, 3))[1][0]
+
+        g_fn = grad(f)
+        grads = torch.zeros(B, n * 3, dtype=DT)
+        laps = torch.zeros(B, dtype=DT)
+        eye = torch.eye(3 * n, dtype=DT)
+        for b in range(B):
+            x = R[b].reshape(-1).clone()
+            grads[b] = g_fn(x)
+            tot = 0.0
+            for c0 in range(0, 3 * n, chunk):
+                V = eye[c0:c0 + chunk]
+                hv = vmap(lambda v: jvp(g_fn, (x,), (v,))[1])(V)
+                tot = tot + (hv * V).sum()
+            laps[b] = tot
+        return grads.reshape(B, n, 3), laps
+
+    def kinetic(self, R, **kw):
+        g, lap = self.grad_lap(R, **kw)
+        return -0.5 * (lap + (g ** 2).sum((1, 2)))
+
+    def ecp_nonlocal(self, R, Q=None):
+        """Nonlocal pseudopotential: for every electron i and pseudo-atom I with
+        |r_i - R_I| < r_max, sum_l v_l(r)(2l+1) (1/12) sum_q P_l(cos) psi(r_i ->
+        R_I + r Q e_q)/psi, every ratio by full re-evaluation."""
+        from workloads import icosahedron_vertices
+        R = torch.as_tensor(R, dtype=DT)
+        B, n = R.shape[:2]
+        out = torch.zeros(B, dtype=DT)
+        if not self.sys.ecp:
+            return out
+        verts = torch.tensor(icosahedron_vertices(), dtype=DT)       # [12,3]
+        Qs = torch.eye(3, dtype=DT)[None].expand(B, 3, 3) if Q is None else torch.as_tensor(Q, dtype=DT)
+        s0, l0 = self.log_psi(R)
+        rmax = self.sys.ecp_rmax
+        for b in range(B):
+            pts = (Qs[b] @ verts.T).T                                 # rotated quadrature directions
+            jobs = []
+            for i in range(n):
+                for I in range(self.Rn.shape[0]):
+                    sp = int(self.sys.species[I])
+                    if sp not in self.sys.ecp:
+                        continue
+                    v = R[b, i] - self.Rn[I]
+                    r = float(torch.linalg.norm(v))
+                    if r >= rmax:
+                        continue
+                    jobs.append((i, I, sp, r, v / r))
+            if not jobs:
+                continue
+            Rq = R[b][None].repeat(len(jobs) * 12, 1, 1).clone()
+            for k, (i, I, sp, r, u) in enumerate(jobs):
+                Rq[12 * k:12 * k + 12, i] = self.Rn[I][None] + r * pts
+            sq, lq = self.log_psi(Rq)
+            ratio = (sq * s0[b]) * torch.exp(lq - l0[b])
+            tot = 0.0
+            for k, (i, I, sp, r, u) in enumerate(jobs):
+                cos = pts @ u
+                rk = ratio[12 * k:12 * k + 12]
+                for ch in self.sys.ecp[sp]:
+                    vl = float(np.sum(ch.a * np.exp(-ch.alpha * r * r)))
+                    Pl = torch.ones_like(cos) if ch.l == 0 else cos
+                    tot = tot + vl * (2 * ch.l + 1) * (Pl * rk).mean()
+            out[b] = tot
+        return out
+
+    def local_energy(self, R, Q=None, **kw):
+        """E_L = -1/2 (Lap log|psi| + |grad log|psi||^2) + V_ee + V_en + V_nn + V_NL
+        (Methods, local energy).  Returns (E_L [B], parts [B,5])."""
+        R = torch.as_tensor(R, dtype=DT)
+        kin = self.kinetic(R, **kw)
+        V = self.potential(R)
+        vnl = self.ecp_nonlocal(R, Q)
+        parts = torch.cat([kin[:, None], V, vnl[:, None]], 1)
+        return parts.sum(1), parts
+
+    # ------------------------------------------------------------------
+    # sampling and parameter gradients
+    # ------------------------------------------------------------------
+    def mcmc_sweep(self, R, step, noise, unif):
+        """Systematic-scan Metropolis with Gaussian single-electron moves:
+        r'_e = r_e + step*xi; accept iff u < (psi'/psi)^2; full recompute for
+        every proposal.  noise [S][n][B][3], unif [S][n][B]."""
+        R = torch.as_tensor(R, dtype=DT).clone()
+        noise = torch.as_tensor(noise, dtype=DT)
+        unif = torch.as_tensor(unif, dtype=DT)
+        S = noise.shape[0]
+        s, l = self.log_psi(R)
+        nacc = torch.zeros(R.shape[0], dtype=torch.long)
+        for t in range(S):
+            for e in range(self.n):
+                Rp = R.clone()
+                Rp[:, e] = R[:, e] + step * noise[t, e]
+                sp, lp = self.log_psi(Rp)
+                ratio2 = torch.exp(2.0 * (lp - l))
+                acc = unif[t, e] < ratio2
+                R = torch.where(acc[:, None, None], Rp, R)
+                s = torch.where(acc, sp, s)
+                l = torch.where(acc, lp, l)
+                nacc += acc.long()
+        return R, s, l, nacc
+
+    def grad_params(self, R, coeff):
+        """sum_w coeff_w d log|psi_w| / d theta, as a dict of arrays."""
+        R = torch.as_tensor(R, dtype=DT)
+        coeff = torch.as_tensor(coeff, dtype=DT)
+        leaves = {k: v.clone().requires_grad_(True) for k, v in self.p.items()}
+        saved = self.p
+        self.p = leaves
+        try:
+            _, l = self.log_psi(R)
+            tot = (coeff * l).sum()
+            grads = torch.autograd.grad(tot, list(leaves.values()), allow_unused=True)
+        finally:
+            self.p = saved
+        return {k: (g if g is not None else torch.zeros_like(leaves[k])).detach()
+                for k, g in zip(leaves.keys(), grads)}
+
+
+def energy_gradient(orc: Oracle, R, e_loc):
+    """E[(E_L - mean E_L) grad log|psi|] over the walker batch (Methods,
+    energy gradient without the factor 2 of d<E>/d theta)."""
+    e = torch.as_tensor(e_loc, dtype=DT)
+    W = e.shape[0]
+    return orc.grad_params(R, (e - e.mean()) / W)

@@ -1,0 +1,496 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test names the passage it follows.  None of them re-types an oracle
+formula: they check closed forms in special parameter settings, exact
+symmetries, limits, textbook routines and finite differences.
+"""
+import copy
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import Oracle, fcut, silu
+
+DT = torch.float64
+
+
+def _orc(cid=0, W=4, **model_kw):
+    w = wl.config(cid, walkers=W)
+    s, m, p = w.systems[0], copy.deepcopy(w.model), copy.deepcopy(w.params[0])
+    for k, v in model_kw.items():
+        setattr(m, k, v)
+    return s, m, p, w.R[0]
+
+
+def _small_c2(W=2, n_keep=None):
+    """Polyene with a narrow network so that CPU autodiff stays fast."""
+    R, sp = wl.polyene_c12h14()
+    s = wl.make_system("C12H14", R, sp, pseudo_c=True)
+    m = wl.make_model(s, width=16, mlp_layers=2, n_det=2, n_env=2, cutoff=5.0, cutoff_nuc=20.0)
+    rng = np.random.default_rng(7)
+    p = wl.init_params(s, m, rng)
+    return s, m, p, wl.init_walkers(s, W, rng)
+
+
+# --------------------------------------------------------------------------
+# cutoff function (Methods, spatial filters: smooth decay to 0 at the cutoff)
+# --------------------------------------------------------------------------
+def test_fcut_endpoints_and_smoothness():
+    x = torch.tensor([0.0, 1.0, 1.3, 7.0])
+    v = fcut(x)
+    assert v[0] == 1.0 and v[1] == 0.0 and v[2] == 0.0 and v[3] == 0.0
+    h = 1e-4
+    xs = torch.tensor([1.0 - 2 * h, 1.0 - h, 1.0])
+    f = fcut(xs)
+    # one-sided first and second differences at x = 1 vanish as O(h^2) and
+    # O(h): the function is C2 across the cutoff (leading term 56 (1-x)^3)
+    assert abs((f[2] - f[1]) / h) < 100 * h * h
+    assert abs((f[2] - 2 * f[1] + f[0]) / h ** 2) < 1000 * h
+    assert abs(float(f[1]) / h ** 3 - 56.0) < 0.1
+    # monotone decreasing on [0, 1]
+    g = fcut(torch.linspace(0, 1, 200))
+    assert torch.all(g[1:] <= g[:-1] + 1e-15)
+
+
+# --------------------------------------------------------------------------
+# hydrogen: exact ground state (Methods, Hamiltonian and local energy)
+# --------------------------------------------------------------------------
+def test_hydrogen_local_energy_is_minus_half():
+    s, m, p, R = wl.hydrogen_atom(W=12, seed=3)
+    o = Oracle(s, m, p)
+    e, parts = o.local_energy(R)
+    assert torch.allclose(e, torch.full_like(e, -0.5), atol=1e-10, rtol=0)
+    # kinetic = 1/r - 1/2 and V_en = -1/r separately
+    r = np.linalg.norm(R[:, 0], axis=1)
+    assert np.allclose(parts[:, 0].numpy(), 1.0 / r - 0.5, atol=1e-10)
+    assert np.allclose(parts[:, 2].numpy(), -1.0 / r, atol=1e-12)
+
+
+def test_zero_variance_energy_gradient_vanishes():
+    from oracle import energy_gradient
+    s, m, p, R = wl.hydrogen_atom(W=8, seed=4)
+    o = Oracle(s, m, p)
+    e, _ = o.local_energy(R)
+    g = energy_gradient(o, R, e)
+    assert max(float(v.abs().max()) for v in g.values() if v.numel()) < 1e-11
+
+
+def test_hydrogen_sampling_mean_radius():
+    """|psi|^2 = exp(-2r)/pi: <r> = 3/2 bohr (textbook 1s value)."""
+    s, m, p, R = wl.hydrogen_atom(W=512, seed=5)
+    o = Oracle(s, m, p)
+    rng = np.random.default_rng(11)
+    R = R * 0.5
+    rs = []
+    for blk in range(30):
+        xi, u = wl.mcmc_noise(10, 1, 512, rng)
+        R, _, _, _ = o.mcmc_sweep(R, 1.0, xi, u)
+        if blk >= 8:
+            rs.append(np.linalg.norm(R.numpy()[:, 0], axis=1).mean())
+    assert abs(np.mean(rs) - 1.5) < 0.03
+
+
+# --------------------------------------------------------------------------
+# symmetries (Introduction: antisymmetry from determinants; features are
+# differences of positions)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["h4", "c2"])
+def test_antisymmetry_same_spin_swap(which):
+    if which == "h4":
+        s, m, p, R = _orc(0, W=3)
+        pairs = [(0, 1), (2, 3)]
+    else:
+        s, m, p, R = _small_c2(W=2)
+        pairs = [(0, 5), (31, 40)]
+    o = Oracle(s, m, p)
+    s0, l0 = o.log_psi(R)
+    for i, j in pairs:
+        R2 = R.copy()
+        R2[:, [i, j]] = R2[:, [j, i]]
+        s1, l1 = o.log_psi(R2)
+        assert torch.all(s1 == -s0)
+        assert torch.allclose(l1, l0, atol=1e-12, rtol=0)
+
+
+def test_opposite_spin_swap_is_not_a_symmetry():
+    s, m, p, R = _orc(0, W=3)
+    o = Oracle(s, m, p)
+    _, l0 = o.log_psi(R)
+    R2 = R.copy()
+    R2[:, [0, 2]] = R2[:, [2, 0]]
+    _, l1 = o.log_psi(R2)
+    assert (l1 - l0).abs().max() > 1e-3
+
+
+def test_translation_invariance():
+    s, m, p, R = _small_c2(W=2)
+    o = Oracle(s, m, p)
+    _, l0 = o.log_psi(R)
+    shift = np.array([0.37, -1.21, 0.55])
+    s2 = copy.deepcopy(s)
+    s2.R_nuc = s.R_nuc + shift
+    o2 = Oracle(s2, m, p)
+    _, l1 = o2.log_psi(R + shift)
+    assert torch.allclose(l0, l1, atol=1e-9, rtol=1e-12)
+
+
+def test_same_spin_permutation_equivariance_of_embeddings():
+    s, m, p, R = _small_c2(W=1)
+    o = Oracle(s, m, p)
+    perm = np.arange(s.n_el)
+    perm[[3, 17]] = perm[[17, 3]]
+    h = o.embed(torch.tensor(R))["h"]
+    hp = o.embed(torch.tensor(R[:, perm]))["h"]
+    assert torch.allclose(hp, h[:, perm], atol=1e-12, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# locality (Introduction, finite-range neighbourhood N_i)
+# --------------------------------------------------------------------------
+def test_embedding_locality_and_dependence_within_cutoff():
+    s, m, p, R = _small_c2(W=1)
+    o = Oracle(s, m, p)
+    R = R.copy()
+    i, j = 0, 20
+    ri = R[0, i]
+    # place j farther than c from r_i, then move it to another far point
+    R[0, j] = ri + np.array([6.0, 0.0, 0.0])
+    h_a = o.embed(torch.tensor(R))["h"][0, i].clone()
+    R2 = R.copy()
+    R2[0, j] = ri + np.array([0.0, -7.5, 1.0])
+    h_b = o.embed(torch.tensor(R2))["h"][0, i]
+    assert torch.equal(h_a, h_b)
+    # within the cutoff the embedding does depend on r_j
+    R3 = R.copy()
+    R3[0, j] = ri + np.array([1.5, 0.3, 0.0])
+    h_c = o.embed(torch.tensor(R3))["h"][0, i]
+    assert (h_c - h_a).abs().max() > 1e-6
+
+
+# --------------------------------------------------------------------------
+# closed forms under special parameter choices
+# --------------------------------------------------------------------------
+def _shift(d, k=1):
+    P = np.zeros((d, d))
+    for c in range(d):
+        P[c, (c + k) % d] = 1.0     # (x P)[c+k] = x[c]
+    return P
+
+
+def test_message_closed_form():
+    """Filters reduced to SiLU(1) * f_cut(r/c) exp(-sigma_1^2 r^2) and the
+    message MLP to SiLU(h0_i[c-1] + x-direction feature + beta_alpha):
+    m^alpha_i[c] = sum over same/opposite spin j != i, |r_ij| <= c."""
+    s, m, p, R = _small_c2(W=1)
+    d = m.width
+    for a in (0, 1):
+        p["ee_W1"][a][:] = 0.0
+        p["ee_b1"][a][:] = 0.0
+        p["ee_W2"][a][:] = 0.0
+        p["ee_b2"][a][:] = 1.0
+        p["ee_W3"][a][:] = 1.0 / m.edge_hidden[1]
+        p["ee_Wenv"][a][:] = 0.0
+        p["ee_Wenv"][a][0, :] = 1.0
+        p["msg_Wa"][a] = _shift(d) if a == 0 else np.zeros((d, d))
+        p["msg_Wb"][a] = np.zeros((d, d)) if a == 0 else _shift(d, 2)
+        p["msg_We"][a][:] = 0.0
+        p["msg_We"][a][1, :] = 1.0
+        p["msg_b"][a][:] = 0.3 + a
+    o = Oracle(s, m, p)
+    out = o.embed(torch.tensor(R))
+    h0 = out["h0"][0].numpy()
+    n, nu = s.n_el, s.n_up
+    pos = R[0]
+    sig = p["ee_sig"][:, 0]
+    for a in (0, 1):
+        got = out["m"][a][0].numpy()
+        exp = np.zeros((n, d))
+        for i in range(n):
+            for j in range(n):
+                same = (i < nu) == (j < nu)
+                if i == j or same != (a == 0):
+                    continue
+                dv = pos[i] - pos[j]
+                r = np.linalg.norm(dv)
+                if r >= m.cutoff:
+                    continue
+                x = r / m.cutoff
+                u = 1 - 28 * x ** 6 + 48 * x ** 7 - 21 * x ** 8
+                gam = (1 / (1 + np.exp(-1.0))) * 1.0 * u * np.exp(-sig[a] ** 2 * r * r)
+                src = np.roll(h0[i], 1) if a == 0 else np.roll(h0[j], 2)
+                pre = src + math.log1p(r) / r * dv[0] + (0.3 + a)
+                exp[i] += gam * pre / (1 + np.exp(-pre))
+        assert np.allclose(got, exp, atol=1e-12, rtol=1e-12)
+
+
+def test_electron_nucleus_embedding_closed_form():
+    """Gamma_m reduced to SiLU(SiLU(b1_m)) f_cut(rho/c_n) exp(-sigma_1^2 rho^2)
+    with a per-nucleus bias; value part nuc_emb_m + log(1+rho)/rho * (x_i -
+    X_m)_y."""
+    s, m, p, R = _small_c2(W=1)
+    d = m.width
+    M = s.n_nuc
+    rng = np.random.default_rng(2)
+    p["en_W1"][:] = 0.0
+    p["en_b1"][:] = 0.0
+    p["en_b1"][:, 0] = rng.normal(size=M)
+    p["en_W2"][:] = 0.0
+    p["en_W2"][0, :] = 1.0
+    p["en_b2"][:] = 0.0
+    p["en_W3"][:] = 1.0 / m.edge_hidden[1]
+    p["en_Wenv"][:] = 0.0
+    p["en_Wenv"][0, :] = 1.0
+    p["en_Wn"][:] = 0.0
+    p["en_Wn"][2, :] = 1.0
+    o = Oracle(s, m, p)
+    got = o.embed(torch.tensor(R))["s"][0].numpy()
+    sl = lambda x: x / (1 + np.exp(-x))
+    exp = np.zeros((s.n_el, d))
+    for i in range(s.n_el):
+        for mm in range(M):
+            dv = R[0, i] - s.R_nuc[mm]
+            rho = np.linalg.norm(dv)
+            if rho >= m.cutoff_nuc:
+                continue
+            x = rho / m.cutoff_nuc
+            u = 1 - 28 * x ** 6 + 48 * x ** 7 - 21 * x ** 8
+            g = sl(sl(p["en_b1"][mm, 0])) * u * np.exp(-p["en_sig"][0] ** 2 * rho ** 2)
+            exp[i] += g * (p["nuc_emb"][mm] + math.log1p(rho) / rho * dv[1])
+    assert np.allclose(got, exp, atol=1e-11, rtol=1e-12)
+
+
+def test_layernorm_and_glu_orientation():
+    """LN over channels (mean beta, biased variance gamma^2 var/(var+eps));
+    GLU with W_v a cyclic shift, gate constant: h0 = SiLU(b_g) * LN(s) shifted."""
+    s, m, p, R = _small_c2(W=1)
+    d = m.width
+    p["glu_Wv"] = _shift(d, 3)
+    p["glu_bv"][:] = 0.0
+    p["glu_Wg"][:] = 0.0
+    p["glu_bg"][:] = 2.5
+    p["glu_Wo"] = np.eye(d)
+    p["glu_bo"][:] = 0.0
+    o = Oracle(s, m, p)
+    out = o.embed(torch.tensor(R))
+    sv = out["s"][0].numpy()
+    mu = sv.mean(1, keepdims=True)
+    var = sv.var(1, keepdims=True)
+    ln = (sv - mu) / np.sqrt(var + 1e-5)
+    assert np.allclose(ln.mean(1), 0.0, atol=1e-12)
+    exp = np.roll(ln, 3, axis=1) * (2.5 / (1 + math.exp(-2.5)))
+    assert np.allclose(out["h0"][0].numpy(), exp, atol=1e-12)
+
+
+def test_mlp_orientation():
+    s, m, p, R = _small_c2(W=1)
+    d = m.width
+    p["mlp_W"][0] = _shift(d, 1)
+    p["mlp_b"][0][:] = 0.1
+    p["mlp_W"][1] = np.eye(d)
+    p["mlp_b"][1][:] = 0.0
+    o = Oracle(s, m, p)
+    out = o.embed(torch.tensor(R))
+    h1 = out["h1"][0].numpy()
+    sl = lambda x: x / (1 + np.exp(-x))
+    exp = sl(sl(np.roll(h1, 1, axis=1) + 0.1))
+    assert np.allclose(out["h"][0].numpy(), exp, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# c = 0 limit (Introduction: c = 0 gives single-electron orbitals): textbook
+# Slater-determinant kinetic energy
+# --------------------------------------------------------------------------
+def test_zero_cutoff_slater_kinetic_textbook():
+    s, m, p, R = _orc(0, W=2)
+    m.cutoff = 1e-9
+    o = Oracle(s, m, p)
+    R = R.copy()
+    kin = o.kinetic(R).numpy()
+    _, lap = o.grad_lap(R)
+    nu, n = s.n_up, s.n_el
+    h = 2e-3
+
+    def orb_rows(Rw, i):
+        """Row i of the spin block of electron i, all dets: [K, N]."""
+        out = o.embed(torch.tensor(Rw[None]))["h"]
+        phis = o.orbitals(torch.tensor(Rw[None]), out)
+        blk = 0 if i < nu else 1
+        row = i if i < nu else i - nu
+        return phis[blk][0, :, row, :].numpy()
+
+    for w in range(R.shape[0]):
+        tot = 0.0
+        phis = o.orbitals(torch.tensor(R[w:w + 1]), o.embed(torch.tensor(R[w:w + 1]))["h"])
+        inv = [np.linalg.inv(ph[0, 0].numpy()) for ph in phis]
+        for i in range(n):
+            blk = 0 if i < nu else 1
+            row = i if i < nu else i - nu
+            lapl = np.zeros(inv[blk].shape[0])
+            f0 = orb_rows(R[w], i)[0]
+            for x in range(3):
+                acc = -30 * f0
+                for k, c in ((1, 16), (2, -1)):
+                    for sgn in (1, -1):
+                        Rp = R[w].copy()
+                        Rp[i, x] += sgn * k * h
+                        acc = acc + c * orb_rows(Rp, i)[0]
+                lapl += acc / (12 * h * h)
+            tot += lapl @ inv[blk][:, row]
+        assert abs(-0.5 * tot - kin[w]) < 1e-6 * max(1.0, abs(kin[w]))
+
+
+# --------------------------------------------------------------------------
+# derivatives against central finite differences (Methods, local energy)
+# --------------------------------------------------------------------------
+def test_gradient_and_laplacian_vs_finite_differences():
+    s, m, p, R = _orc(0, W=2)
+    o = Oracle(s, m, p)
+    g, lap = o.grad_lap(R)
+    h = 1e-3
+    for w in range(2):
+        x0 = R[w].copy()
+        f = lambda x: float(o.log_psi(x[None])[1][0])
+        l0 = f(x0)
+        fd_lap, fd_g = 0.0, np.zeros_like(x0)
+        for i in range(s.n_el):
+            for k in range(3):
+                vals = {}
+                for st in (-2, -1, 1, 2):
+                    x = x0.copy()
+                    x[i, k] += st * h
+                    vals[st] = f(x)
+                fd_g[i, k] = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * h)
+                fd_lap += (-vals[2] + 16 * vals[1] - 30 * l0 + 16 * vals[-1] - vals[-2]) / (12 * h * h)
+        assert np.allclose(g[w].numpy(), fd_g, atol=1e-7)
+        assert abs(float(lap[w]) - fd_lap) < 1e-5
+
+
+def test_logdet_derivative_identities():
+    """d log det / d Phi_ij = Phi^-1_ji and the Hessian -Phi^-1_jk Phi^-1_mi
+    (Methods, efficient Laplacian) on random matrices, by central FD."""
+    rng = np.random.default_rng(0)
+    A = rng.normal(size=(5, 5))
+    inv = np.linalg.inv(A)
+    f = lambda X: np.linalg.slogdet(X)[1]
+    h = 1e-5
+    for (i, j) in [(0, 1), (3, 2), (4, 4)]:
+        E = np.zeros_like(A)
+        E[i, j] = h
+        assert abs((f(A + E) - f(A - E)) / (2 * h) - inv[j, i]) < 1e-8
+    h = 1e-4
+    for (i, j, k, mm) in [(0, 1, 2, 3), (1, 1, 1, 1), (4, 0, 0, 2)]:
+        Eij = np.zeros_like(A); Eij[i, j] = h
+        Ekm = np.zeros_like(A); Ekm[k, mm] = h
+        fd = (f(A + Eij + Ekm) - f(A + Eij - Ekm) - f(A - Eij + Ekm) + f(A - Eij - Ekm)) / (4 * h * h)
+        assert abs(fd - (-inv[j, k] * inv[mm, i])) < 1e-6
+
+
+def test_theta_gradient_vs_finite_differences():
+    s, m, p, R = _orc(0, W=3)
+    o = Oracle(s, m, p)
+    coeff = np.array([0.7, -1.3, 0.4])
+    g = o.grad_params(R, coeff)
+    names = list(p.keys())
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        dirs = {k: rng.normal(size=p[k].shape) for k in names}
+        nrm = math.sqrt(sum((v ** 2).sum() for v in dirs.values()))
+        dirs = {k: v / nrm for k, v in dirs.items()}
+        h = 1e-5
+        def val(t):
+            q = {k: p[k] + t * dirs[k] for k in names}
+            return float((Oracle(s, m, q).log_psi(R)[1].numpy() * coeff).sum())
+        fd = (8 * (val(h) - val(-h)) - (val(2 * h) - val(-2 * h))) / (12 * h)
+        an = sum(float((g[k].numpy() * dirs[k]).sum()) for k in names)
+        assert abs(fd - an) < 1e-8 * max(1.0, abs(an))
+
+
+# --------------------------------------------------------------------------
+# determinant combination (Methods, eq. for Psi as a sum of determinants)
+# --------------------------------------------------------------------------
+def test_identical_determinants_add_log_k():
+    s, m, p, R = _orc(0, W=3)
+    o1 = Oracle(s, m, p)
+    _, l1 = o1.log_psi(R)
+    m3 = copy.deepcopy(m)
+    m3.n_det = 3
+    p3 = copy.deepcopy(p)
+    for k in ("orb_W_up", "orb_W_dn", "env_pi_up", "env_pi_dn"):
+        p3[k] = np.repeat(p[k], 3, axis=0)
+    _, l3 = Oracle(s, m3, p3).log_psi(R)
+    assert torch.allclose(l3, l1 + math.log(3), atol=1e-12, rtol=0)
+
+
+def test_cancelling_determinants_give_sign_zero():
+    s, m, p, R = _orc(0, W=2)
+    m2 = copy.deepcopy(m)
+    m2.n_det = 2
+    p2 = copy.deepcopy(p)
+    for k in ("orb_W_up", "orb_W_dn", "env_pi_up", "env_pi_dn"):
+        p2[k] = np.repeat(p[k], 2, axis=0)
+    p2["orb_W_up"][1][:, 0] *= -1.0          # flips the sign of det_2 (one column)
+    sgn, _ = Oracle(s, m2, p2).log_psi(R)
+    assert torch.all(sgn == 0)
+
+
+# --------------------------------------------------------------------------
+# potential (Methods, Hamiltonian) on hand-computed configurations
+# --------------------------------------------------------------------------
+def test_potential_hand_computed():
+    R = np.array([[0.0, 0, 0], [0, 0, 2.0]])
+    s = wl.make_system("HH", R, np.zeros(2, np.int32), pseudo_c=False)
+    m = wl.make_model(s, width=4, mlp_layers=1, n_det=1, n_env=1)
+    p = wl.init_params(s, m, np.random.default_rng(0))
+    o = Oracle(s, m, p)
+    el = np.array([[[0.0, 0, 1.0], [0.0, 3.0, 0]]])
+    V = o.potential(el).numpy()[0]
+    assert abs(V[0] - 1.0 / math.sqrt(1 + 9)) < 1e-14
+    ven = -(1 / 1.0 + 1 / 1.0 + 1 / 3.0 + 1 / math.sqrt(9 + 4))
+    assert abs(V[1] - ven) < 1e-14
+    assert abs(V[2] - 0.5) < 1e-14
+    # erf-smoothed local pseudopotential on a carbon with Z_eff = 4, width 0.5
+    sC = wl.make_system("C", np.zeros((1, 3)), np.ones(1, np.int32), pseudo_c=True, n_up=2, n_dn=2)
+    mC = wl.make_model(sC, width=4, mlp_layers=1, n_det=1, n_env=1)
+    oC = Oracle(sC, mC, wl.init_params(sC, mC, np.random.default_rng(0)))
+    el = np.array([[[0.3, 0, 0], [0, 1.0, 0], [0, 0, 2.0], [1.0, 1.0, 1.0]]])
+    V = oC.potential(el).numpy()[0]
+    rs = [0.3, 1.0, 2.0, math.sqrt(3)]
+    assert abs(V[1] - sum(-4 * math.erf(r / 0.5) / r for r in rs)) < 1e-13
+    assert V[2] == 0.0
+
+
+# --------------------------------------------------------------------------
+# pseudopotential quadrature (Methods, effective core potential)
+# --------------------------------------------------------------------------
+def test_icosahedron_is_a_spherical_5_design():
+    from numpy.polynomial import legendre
+    v = wl.icosahedron_vertices()
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        e = rng.normal(size=3)
+        e /= np.linalg.norm(e)
+        c = v @ e
+        for l in range(6):
+            Pl = legendre.legval(c, [0] * l + [1])
+            assert abs(Pl.mean() - (1.0 if l == 0 else 0.0)) < 1e-13
+
+
+def test_ecp_spherically_symmetric_wavefunction_gives_v0():
+    """With psi = exp(-r) centred on the pseudo-atom every ratio is 1 and the
+    angular average of P_l vanishes for l = 1: V_NL = v_0(r)."""
+    s, m, p, R = wl.hydrogen_atom(W=5, seed=9)
+    rng = np.random.default_rng(3)
+    s.species = np.ones(1, np.int32)
+    s.ecp = wl._ecp_tables(rng)
+    R = R / np.linalg.norm(R, axis=-1, keepdims=True) * rng.uniform(0.2, 1.9, size=(5, 1, 1))
+    o = Oracle(s, m, p)
+    Q = wl.haar_rotations(5, rng)
+    v = o.ecp_nonlocal(R, Q).numpy()
+    r = np.linalg.norm(R[:, 0], axis=1)
+    ch0 = s.ecp[1][0]
+    v0 = (ch0.a[None] * np.exp(-ch0.alpha[None] * r[:, None] ** 2)).sum(1)
+    assert np.allclose(v, v0, atol=1e-12)
