@@ -1,0 +1,200 @@
+/*
+ * libfire -- the finite-range-embedding (FiRE) neural-network VMC hot path on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Scherbela, Gao, Grohs, Guennemann, "Accurate Ab-initio Neural-network
+ * Solutions to Large-Scale Electronic Structure Problems" (arXiv 2504.06087),
+ * Methods section: wave-function ansatz (eq. wf), low-rank wave-function
+ * updates, efficient Laplacian (eqs. forward_lap_jac, forward_lap_lap,
+ * forward_lap_det_M, logdet_lowrank), variational Monte Carlo (Hamiltonian,
+ * local energy, energy gradient) and the effective core potential.
+ *
+ * Conventions of every entry point
+ *  - All tensor pointers are DEVICE pointers owned by the caller unless a
+ *    comment says "host".  All work is enqueued on the caller's hipStream_t;
+ *    no call synchronises the stream and no call allocates device memory.
+ *  - Positions are FP64 [W][n][3], electrons 0..n_up-1 spin up, the rest down.
+ *  - Errors the host can see (bad pointer, shape, precision, W > max_walkers)
+ *    are returned immediately as a negative fire_status and nothing is
+ *    enqueued.  Each call clears the caller's int32 status[W] and ORs into it
+ *    the conditions it finds on the device (FIRE_W_*); a flagged walker's
+ *    outputs are NaN and its sign 0.  Nothing is ever silently truncated.
+ *  - state/workspace/params buffers are sized by fire_sizes and owned by the
+ *    caller.  state must hold the result of fire_eval_logpsi (or of a sweep)
+ *    for the same positions before local_energy, ecp_nonlocal or grad_params.
+ *  - Calls on different streams with different state/workspace buffers may
+ *    overlap; calls sharing a workspace must be ordered by the caller.
+ */
+#ifndef FIRE_H
+#define FIRE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fire_status;
+#define FIRE_OK 0
+#define FIRE_ERR_ARG -1         /* null pointer or bad size */
+#define FIRE_ERR_SHAPE -2       /* dimensions outside what the kernels support */
+#define FIRE_ERR_PRECISION -3   /* unknown precision mode */
+#define FIRE_ERR_CAPACITY -4    /* W > max_walkers or a capacity below its minimum */
+#define FIRE_ERR_HIP -5         /* a HIP launch or copy failed */
+#define FIRE_ERR_STATE -6       /* parameters not set */
+
+/* per-walker device status bits */
+#define FIRE_W_NBR_OVERFLOW 1   /* more neighbours within c than cap_nbr */
+#define FIRE_W_UPD_OVERFLOW 2   /* update set larger than cap_upd */
+#define FIRE_W_SINGULAR 4       /* zero pivot in an orbital matrix or in A */
+#define FIRE_W_NONFINITE 8      /* a non-finite position or result */
+#define FIRE_W_DETSUM_ZERO 16   /* the determinants cancel exactly: psi = 0 */
+
+typedef enum {
+  FIRE_FP64 = 0,        /* every stage in FP64 */
+  FIRE_FP32 = 1,        /* FP32 everywhere (FP32 MFMA GEMMs, FP32 LU and inverse) */
+  FIRE_BF16_HYBRID = 2  /* BF16 GEMM operands with FP32 accumulation, FP32
+                           elementwise, FP64 LU / log-det / running inverse */
+} fire_precision;
+
+/* One semilocal pseudopotential channel v_l(r) = sum_k a_k exp(-alpha_k r^2)
+ * (Methods, effective core potential).  Host arrays. */
+typedef struct {
+  int species;
+  int l;               /* 0 or 1 */
+  int n_terms;         /* <= 4 */
+  const double* a;     /* host [n_terms] */
+  const double* alpha; /* host [n_terms] */
+} fire_ecp_channel;
+
+/* The molecule (Methods, Hamiltonian eq. hamiltonian).  Host arrays, copied. */
+typedef struct {
+  int n_nuc;
+  const double* R_nuc;     /* host [n_nuc][3] bohr */
+  const double* Z;         /* host [n_nuc]; effective charge for pseudo-atoms */
+  const int* species;      /* host [n_nuc] element id (selects ECP channels) */
+  const int* nuc_type;     /* host [n_nuc] row of per-nucleus parameter tables */
+  const double* pp_width;  /* host [n_nuc]; 0: -Z/r, w > 0: -Z erf(r/w)/r */
+  int n_up, n_dn;
+  int n_ecp;               /* number of channels (0: all-electron) */
+  const fire_ecp_channel* ecp;
+  double ecp_rmax;         /* quadrature applied iff |r_i - R_I| < ecp_rmax */
+} fire_system_desc;
+
+/* The ansatz (Methods, wave-function ansatz) and run limits. */
+typedef struct {
+  int width;          /* embedding width d */
+  int mlp_layers;     /* L */
+  int n_det;          /* K */
+  int n_env;          /* envelopes per nucleus */
+  int n_gauss;        /* radial Gaussians in the filters (32) */
+  int edge_h1, edge_h2; /* filter MLP widths (16, 8) */
+  int n_nuc_types;    /* rows of the per-nucleus tables */
+  double cutoff;      /* c, electron-electron */
+  double cutoff_nuc;  /* c_n, electron-nucleus */
+  int precision;      /* fire_precision */
+  int max_walkers;    /* W limit of every call on this handle */
+  int cap_nbr;        /* max |N_i| per electron (both spin classes) */
+  int cap_upd;        /* max |U| of a single-electron update */
+  int refresh_every;  /* sweeps between full FP64 re-evaluations */
+} fire_model_desc;
+
+typedef struct fire_handle fire_handle;
+
+typedef struct {
+  char name[32];
+  int64_t offset;     /* element offset into theta */
+  int32_t ndim;
+  int32_t shape[4];
+} fire_param_entry;
+
+/* Create/destroy a handle.  Copies the host arrays.  Returns FIRE_ERR_SHAPE
+ * outside the dimensions the kernels support (width <= 256, n_up, n_dn <=
+ * 128, n_gauss == 32, edge widths <= 16 and <= 8, K <= 32, L <= 16). */
+fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* model, fire_handle** out);
+fire_status fire_destroy(fire_handle* h);
+
+/* The FP64 parameter vector theta: names, offsets and shapes, in order.  *n
+ * holds the capacity of out on entry and the entry count on return (out may
+ * be NULL to query the count). */
+fire_status fire_param_layout(const fire_handle* h, fire_param_entry* out, int* n);
+fire_status fire_num_params(const fire_handle* h, int64_t* P);
+
+/* Bytes of the caller-owned buffers for W walkers. */
+fire_status fire_sizes(const fire_handle* h, int W, size_t* params_bytes, size_t* state_bytes,
+                       size_t* workspace_bytes);
+
+/* Byte offsets, within one walker's record of the state buffer, of the
+ * cached intermediates: offsets[0..9] = h0 [n][d], projections [n][4][d]
+ * (a_par, a_anti, b_par, b_anti), messages m [n][d], Phi [K][(n_up^2 +
+ * n_dn^2)] (per determinant the up block then the down block, row i =
+ * electron, column l = orbital), envelopes (same shape as Phi), G = Phi^-T
+ * (same shape: G[k][l] = (Phi^-1)[l][k], the derivative of log|det| by
+ * Phi[k][l]), determinant signs [K][2] and log|det| [K][2] (FP64), log|psi|
+ * and sign (FP64).  Arrays
+ * other than the FP64 ones use the precision's elementwise type (FP64 for
+ * FIRE_FP64, FP32 otherwise; Phi^-1 is FP64 except under FIRE_FP32).
+ * *stride is the record size; walker w's record starts at w * stride. */
+fire_status fire_state_layout(const fire_handle* h, size_t* offsets, size_t* stride);
+
+/* Pack theta (device FP64 [P]) and the molecule into params_buf in the
+ * layouts and precisions the kernels use.  params_buf must stay alive and
+ * unchanged for every later call on this handle. */
+fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t stream);
+
+/* log|psi| and its sign for W walkers (Methods, eq. wf with J = 1:
+ * psi = sum_d det Phi_d^up det Phi_d^down), and the cached intermediates the
+ * update, Laplacian and adjoint paths reuse (embeddings h0, projections,
+ * messages, Phi, Phi^-1, per-determinant sign and log|det|) written to
+ * state.  R: [W][n][3]; sign, logpsi: [W]; status: [W]. */
+fire_status fire_eval_logpsi(fire_handle* h, int W, const double* R, void* state, void* ws,
+                             double* sign, double* logpsi, int32_t* status, hipStream_t stream);
+
+/* n_sweeps systematic-scan Metropolis sweeps with Gaussian single-electron
+ * moves r_e' = r_e + step*xi (Methods, improved Monte Carlo sampling), each
+ * proposal evaluated by neighbour recompute and the matrix-determinant lemma
+ * (Methods, low-rank wave-function updates); accepted moves update Phi^-1 by
+ * the Woodbury identity.  State is refreshed by a full evaluation every
+ * refresh_every sweeps.  noise [S][n][W][3] and unif [S][n][W] are explicit
+ * random numbers (both non-NULL).  R is updated in place; n_accept [W] is
+ * incremented; logpsi/sign [W] receive the final values. */
+fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
+                            double step, const double* noise, const double* unif,
+                            int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
+                            hipStream_t stream);
+
+/* Local energy E_L = -1/2 (Lap log|psi| + |grad log|psi||^2) + V_ee + V_en +
+ * V_nn + V_NL (Methods, local energy and Hamiltonian) by the sparse forward
+ * Laplacian (Methods, efficient Laplacian).  quad_rot [W][3][3] rotates the
+ * pseudopotential quadrature (NULL: identity).  parts [W][5] (kinetic, V_ee,
+ * V_en, V_nn, V_NL) and grad_logpsi [W][n][3] are optional (NULL). */
+fire_status fire_local_energy(fire_handle* h, int W, const double* R, void* state, void* ws,
+                              const double* quad_rot, double* e_loc, double* parts,
+                              double* grad_logpsi, int32_t* status, hipStream_t stream);
+
+/* Nonlocal pseudopotential energy per walker (Methods, effective core
+ * potential): for every electron within ecp_rmax of a pseudo-atom, a 12-point
+ * icosahedral quadrature of psi ratios from single-electron low-rank updates. */
+fire_status fire_ecp_nonlocal(fire_handle* h, int W, const double* R, void* state, void* ws,
+                              const double* quad_rot, double* v_nl, int32_t* status,
+                              hipStream_t stream);
+
+/* grad[P] = sum_w coeff[w] d log|psi_w| / d theta (Methods, energy gradient
+ * with coeff_w = (E_L,w - mean E_L)/W), by a hand-written adjoint with
+ * per-layer recomputation.  grad is overwritten. */
+fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state, void* ws,
+                             const double* coeff, double* grad, int32_t* status,
+                             hipStream_t stream);
+
+/* OR of status[0..W-1] into *any_flags (host); synchronises the stream. */
+fire_status fire_sync_status(fire_handle* h, hipStream_t stream, const int32_t* status, int W,
+                             int32_t* any_flags);
+
+const char* fire_status_string(fire_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIRE_H */

@@ -1,0 +1,118 @@
+// Kernels shared by the full evaluation and the single-electron update path.
+#pragma once
+#include "forward.hpp"
+
+namespace fire {
+
+// ---------------------------------------------------------------------------
+// Pair features shared by the electron-nucleus and electron-electron filters:
+//   out[0..3]  rescaled features log(1+r)/r * [r, dx, dy, dz]
+//   out[4..4+h2) second hidden layer SiLU(SiLU(e W1 + b1) W2 + b2)
+//   out[12..44) radial part f_cut(r/c) exp(-sigma_k^2 r^2)
+//   out[44]    f_cut(r/c) (zero: the pair does not contribute)
+// ---------------------------------------------------------------------------
+template <typename T>
+FIRE_DEV void pair_features(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, const T* b2,
+                            const T* sig, T cut, const Dims& D, T* out) {
+  T r = sqrt(dx * dx + dy * dy + dz * dz);
+  T e4[4] = {r, dx, dy, dz};
+  T lo = log1p_over(r);
+  for (int k = 0; k < 4; ++k) out[k] = lo * e4[k];
+  T z1[kMaxH1];
+  for (int k = 0; k < D.h1; ++k) {
+    T a = b1[k];
+    for (int j = 0; j < 4; ++j) a += e4[j] * W1[j * D.h1 + k];
+    z1[k] = silu_(a);
+  }
+  for (int k = 0; k < D.h2; ++k) {
+    T a = b2[k];
+    for (int j = 0; j < D.h1; ++j) a += z1[j] * W2[j * D.h2 + k];
+    out[4 + k] = silu_(a);
+  }
+  T fc = fcut_(r / cut);
+  for (int k = 0; k < D.G; ++k) out[12 + k] = fc * exp(-(sig[k] * sig[k]) * r * r);
+  out[44] = fc;
+}
+constexpr int FEAT = 48;
+
+// ---------------------------------------------------------------------------
+// a2 + a3 (first half): s_i = sum_m Gamma_m(e_im) * (nuc_emb_m + ebar_im W_n),
+// then y_i = LayerNorm(s_i).  Workgroup: one thread per channel, EPB electrons.
+// ---------------------------------------------------------------------------
+constexpr int EPB = 8;
+constexpr int MCH = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __restrict__ R, int64_t nrows,
+                                                  T* __restrict__ y_out) {
+  const Dims& D = P.D;
+  __shared__ T feat[MCH * FEAT];
+  __shared__ T red[16];
+  const int c = threadIdx.x;
+  const bool act = c < D.d;
+  T w3[kMaxH2], wenv[kMaxG], wn[4];
+  if (act) {
+    for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
+    for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
+    for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
+  }
+  for (int el = 0; el < EPB; ++el) {
+    int64_t e = (int64_t)blockIdx.x * EPB + el;
+    if (e >= nrows) break;
+    const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
+    T s = 0;
+    for (int m0 = 0; m0 < D.M; m0 += MCH) {
+      int mc = D.M - m0 < MCH ? D.M - m0 : MCH;
+      __syncthreads();
+      if (threadIdx.x < mc) {
+        int m = m0 + threadIdx.x, t = P.ntype[m];
+        pair_features<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
+                         P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig,
+                         (T)D.cutn, D, feat + threadIdx.x * FEAT);
+      }
+      __syncthreads();
+      if (act) {
+        for (int k = 0; k < mc; ++k) {
+          const T* f = feat + k * FEAT;
+          if (f[44] == T(0)) continue;
+          T g1 = 0, g2 = 0;
+          for (int j = 0; j < D.h2; ++j) g1 += f[4 + j] * w3[j];
+          for (int j = 0; j < D.G; ++j) g2 += f[12 + j] * wenv[j];
+          T v = P.nuc_emb[P.ntype[m0 + k] * D.d + c] + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
+          s += g1 * g2 * v;
+        }
+      }
+    }
+    T mu = block_sum<T>(act ? s : T(0), red) / T(D.d);
+    T dv = act ? s - mu : T(0);
+    T var = block_sum<T>(dv * dv, red) / T(D.d);
+    if (act) y_out[e * D.d + c] = dv / sqrt(var + T(kLnEps)) * P.ln_g[c] + P.ln_b[c];
+  }
+}
+
+// GLU gate: t = u * SiLU(g) with [u | g] the two halves of each row of ug.
+template <typename T>
+__global__ void k_glu(const T* __restrict__ ug, T* __restrict__ out, int64_t nrows, int d) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nrows * d) return;
+  int64_t r = i / d;
+  int c = (int)(i % d);
+  T u = ug[r * 2 * d + c], g = ug[r * 2 * d + d + c];
+  out[i] = u * silu_(g);
+}
+
+// Envelope basis exp(-sigma_me |r_i - R_m|), row e = (w, i), column m*E + k.
+template <typename T>
+__global__ void k_env_basis(Net<T> P, const double* __restrict__ R, int64_t nrows, T* __restrict__ out) {
+  const Dims& D = P.D;
+  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nrows * D.B) return;
+  int64_t e = q / D.B;
+  int b = (int)(q % D.B), m = b / D.E;
+  double dx = R[3 * e] - P.Rn[3 * m], dy = R[3 * e + 1] - P.Rn[3 * m + 1], dz = R[3 * e + 2] - P.Rn[3 * m + 2];
+  T dist = (T)sqrt(dx * dx + dy * dy + dz * dz);
+  out[q] = exp(-P.env_sigma[b] * dist);
+}
+
+
+}  // namespace fire

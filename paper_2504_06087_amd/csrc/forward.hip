@@ -1,0 +1,393 @@
+// Forward evaluation of log|psi| for all walkers (Methods, wave-function
+// ansatz): neighbour lists, electron-nucleus filters and LayerNorm, GLU, one
+// message-passing step, the embedding MLP, envelopes and orbitals, FP64
+// Gauss-Jordan inversion with partial pivoting and the signed log-sum-exp
+// over determinants.
+#include "forward.hpp"
+#include "linalg.hpp"
+#include "embed_kernels.hpp"
+
+namespace fire {
+
+// ---------------------------------------------------------------------------
+// status helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// a1: neighbour lists.  One workgroup per walker; electron i lists every
+// j != i with |r_i - r_j| <= c, same-spin first, then opposite spin.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
+                                             double cut2, int cap, int16_t* __restrict__ idx,
+                                             int32_t* __restrict__ cnt, int32_t* status) {
+  __shared__ double pos[256 * 3];
+  int w = blockIdx.x;
+  const double* Rw = R + (int64_t)w * n * 3;
+  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) pos[t] = Rw[t];
+  __syncthreads();
+  int i = threadIdx.x;
+  if (i >= n) return;
+  double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) atomicOr(status + w, FIRE_W_NONFINITE);
+  int16_t* out = idx + ((int64_t)w * n + i) * cap;
+  int si = i < nu ? 0 : 1;
+  int c[2] = {0, 0};
+  int k = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      int sj = j < nu ? 0 : 1;
+      if ((sj == si) != (pass == 0)) continue;
+      double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+      if (dx * dx + dy * dy + dz * dz <= cut2) {
+        if (k < cap) out[k] = (int16_t)j;
+        ++k;
+        ++c[pass];
+      }
+    }
+  }
+  if (k > cap) {
+    atomicOr(status + w, FIRE_W_NBR_OVERFLOW);
+    c[0] = c[0] < cap ? c[0] : cap;
+    c[1] = cap - c[0] < c[1] ? cap - c[0] : c[1];
+  }
+  cnt[((int64_t)w * n + i) * 2 + 0] = c[0];
+  cnt[((int64_t)w * n + i) * 2 + 1] = c[1];
+}
+
+// ---------------------------------------------------------------------------
+// a4: m_i = sum_alpha sum_{j in N^alpha_i} Gamma^alpha(e_ij) *
+//           SiLU(a^alpha_i + b^alpha_j + ebar_ij W_e^alpha + b^alpha)
+// h1_i = h0_i + m_i.  proj rows hold [a^par | a^anti | b^par | b^anti].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_msg(Net<T> P, const double* __restrict__ R, int64_t nrows,
+                                             const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
+                                             const char* __restrict__ state, size_t srec, size_t off_h0,
+                                             size_t off_proj, size_t off_m, T* __restrict__ h1_out) {
+  const Dims& D = P.D;
+  __shared__ T feat[MCH * FEAT];
+  __shared__ int jn[MCH];
+  const int c = threadIdx.x;
+  const bool act = c < D.d;
+  const int n = D.n;
+  T acc[EPB];
+  for (int el = 0; el < EPB; ++el) acc[el] = 0;
+  for (int a = 0; a < 2; ++a) {
+    T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0;
+    if (act) {
+      for (int k = 0; k < D.h2; ++k) w3[k] = P.ee_W3[(a * D.h2 + k) * D.d + c];
+      for (int k = 0; k < D.G; ++k) wenv[k] = P.ee_Wenv[(a * D.G + k) * D.d + c];
+      for (int k = 0; k < 4; ++k) we[k] = P.msg_We[(a * 4 + k) * D.d + c];
+      bb = P.msg_b[a * D.d + c];
+    }
+    for (int el = 0; el < EPB; ++el) {
+      int64_t e = (int64_t)blockIdx.x * EPB + el;
+      if (e >= nrows) break;
+      int64_t w = e / n;
+      const char* rec = state + w * srec;
+      int i = (int)(e % n);
+      int c0 = ncnt[2 * e], c1 = ncnt[2 * e + 1];
+      int na = a == 0 ? c0 : c1, base = a == 0 ? 0 : c0;
+      const T* proj = (const T*)(rec + off_proj);
+      T ai = act ? proj[((int64_t)i * 4 + a) * D.d + c] : T(0);
+      const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
+      const double* Rw = R + w * n * 3;
+      for (int j0 = 0; j0 < na; j0 += MCH) {
+        int jc = na - j0 < MCH ? na - j0 : MCH;
+        __syncthreads();
+        if (threadIdx.x < jc) {
+          int j = nidx[e * D.cap_nbr + base + j0 + threadIdx.x];
+          jn[threadIdx.x] = j;
+          pair_features<T>((T)(rx - Rw[3 * j]), (T)(ry - Rw[3 * j + 1]), (T)(rz - Rw[3 * j + 2]),
+                           P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2,
+                           P.ee_b2 + a * D.h2, P.ee_sig + a * D.G, (T)D.cut, D, feat + threadIdx.x * FEAT);
+        }
+        __syncthreads();
+        if (act) {
+          for (int k = 0; k < jc; ++k) {
+            const T* f = feat + k * FEAT;
+            if (f[44] == T(0)) continue;
+            T g1 = 0, g2 = 0;
+            for (int q = 0; q < D.h2; ++q) g1 += f[4 + q] * w3[q];
+            for (int q = 0; q < D.G; ++q) g2 += f[12 + q] * wenv[q];
+            T bj = proj[((int64_t)jn[k] * 4 + 2 + a) * D.d + c];
+            T pre = ai + bj + f[0] * we[0] + f[1] * we[1] + f[2] * we[2] + f[3] * we[3] + bb;
+            acc[el] += g1 * g2 * silu_(pre);
+          }
+        }
+      }
+    }
+  }
+  if (!act) return;
+  for (int el = 0; el < EPB; ++el) {
+    int64_t e = (int64_t)blockIdx.x * EPB + el;
+    if (e >= nrows) break;
+    int64_t w = e / n;
+    int i = (int)(e % n);
+    char* rec = (char*)state + w * srec;
+    T* m = (T*)(rec + off_m);
+    const T* h0 = (const T*)(rec + off_h0);
+    m[(int64_t)i * D.d + c] = acc[el];
+    h1_out[e * D.d + c] = h0[(int64_t)i * D.d + c] + acc[el];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a7: in-place Gauss-Jordan inversion with partial (row) pivoting in FP64.
+// One workgroup per (walker, determinant) block of one spin.  Produces
+// Phi^-1 (TI), the sign and log|det| of the block.  det and inverse come
+// from the same elimination.
+// ---------------------------------------------------------------------------
+constexpr int LU_MAXN = 128;
+
+template <typename TP, typename TI>
+__global__ __launch_bounds__(256) void k_gj_inverse(const char* __restrict__ state_in, char* __restrict__ state_out,
+                                                    size_t srec, size_t off_phi, size_t off_inv, size_t off_ds,
+                                                    size_t off_dl, Dims D, int spin, int32_t* status) {
+  extern __shared__ double lds[];
+  const int N = spin == 0 ? D.nu : D.nd;
+  const int LD = N + 1;
+  double* A = lds;                 // [N][LD]
+  double* f = lds + N * LD;        // [N]
+  __shared__ int perm[LU_MAXN];
+  __shared__ double sc[2];
+  __shared__ int fl[2];
+  const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  const int64_t boff = det * phi_per_det(D) + phi_block_off(D, spin);
+  const TP* phi = (const TP*)(state_in + (int64_t)w * srec + off_phi) + boff;
+  TI* inv = (TI*)(state_out + (int64_t)w * srec + off_inv) + boff;
+  double* dsign = (double*)(state_out + (int64_t)w * srec + off_ds);
+  double* dlog = (double*)(state_out + (int64_t)w * srec + off_dl);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (N == 0) {
+    if (tid == 0) { dsign[det * 2 + spin] = 1.0; dlog[det * 2 + spin] = 0.0; }
+    return;
+  }
+  for (int q = tid; q < N * N; q += nt) A[(q / N) * LD + q % N] = (double)phi[q];
+  __syncthreads();
+  gj_block(A, N, LD, f, perm, sc, fl, true);
+  if (fl[1]) {
+    if (tid == 0) {
+      atomicOr(status + w, FIRE_W_SINGULAR);
+      dsign[det * 2 + spin] = 0.0;
+      dlog[det * 2 + spin] = -INFINITY;
+    }
+    return;
+  }
+  // store G = Phi^-T: G[k][l] = (Phi^-1)[l][k]
+  for (int q = tid; q < N * N; q += nt) inv[q] = (TI)A[(q % N) * LD + q / N];
+  if (tid == 0) {
+    dsign[det * 2 + spin] = sc[0];
+    dlog[det * 2 + spin] = sc[1];
+  }
+}
+
+// Signed log-sum-exp over determinants: log|psi| = l* + log|sum_d s_d e^(l_d - l*)|.
+__global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds, size_t off_dl, size_t off_lp,
+                            size_t off_sp, int W, int K, double* sign, double* logpsi, int32_t* status) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  char* rec = state + (int64_t)w * srec;
+  const double* ds = (const double*)(rec + off_ds);
+  const double* dl = (const double*)(rec + off_dl);
+  double lmax = -INFINITY;
+  for (int k = 0; k < K; ++k) {
+    double l = dl[2 * k] + dl[2 * k + 1];
+    if (ds[2 * k] * ds[2 * k + 1] != 0.0 && l > lmax) lmax = l;
+  }
+  double tot = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double sg = ds[2 * k] * ds[2 * k + 1];
+    if (sg != 0.0) tot += sg * exp(dl[2 * k] + dl[2 * k + 1] - lmax);
+  }
+  int32_t st = status[w];
+  double lp, sp;
+  if (tot == 0.0 || !isfinite(lmax)) {
+    st |= FIRE_W_DETSUM_ZERO;
+    atomicOr(status + w, FIRE_W_DETSUM_ZERO);
+  }
+  if (!isfinite(tot)) {
+    st |= FIRE_W_NONFINITE;
+    atomicOr(status + w, FIRE_W_NONFINITE);
+  }
+  if (st) {
+    lp = NAN;
+    sp = 0.0;
+  } else {
+    lp = lmax + log(fabs(tot));
+    sp = tot > 0 ? 1.0 : -1.0;
+  }
+  *(double*)(rec + off_lp) = lp;
+  *(double*)(rec + off_sp) = sp;
+  if (logpsi) logpsi[w] = lp;
+  if (sign) sign[w] = sp;
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+WsLayout ws_forward(const fire_handle* h, int W) {
+  const Dims& D = h->D;
+  WsLayout L{};
+  size_t o = 0, ts = h->tsize;
+  int64_t rows = (int64_t)W * D.n;
+  L.nbr_idx = o; o = align_up(o + rows * D.cap_nbr * sizeof(int16_t));
+  L.nbr_cnt = o; o = align_up(o + rows * 2 * sizeof(int32_t));
+  L.y = o;       o = align_up(o + rows * D.d * ts);
+  L.ug = o;      o = align_up(o + rows * 2 * D.d * ts);
+  L.hA = o;      o = align_up(o + rows * D.d * ts);
+  L.hB = o;      o = align_up(o + rows * D.d * ts);
+  L.basis = o;   o = align_up(o + rows * D.B * ts);
+  L.total = o;
+  return L;
+}
+
+#define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+template <typename T>
+hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, const double* R, char* state,
+                              char* ws, int32_t* status, hipStream_t s) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  const WsLayout L = ws_forward(h, W);
+  const int kind = gemm_kind(D.prec);
+  const int64_t rows = (int64_t)W * D.n;
+  const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
+  int16_t* nidx = (int16_t*)(ws + L.nbr_idx);
+  int32_t* ncnt = (int32_t*)(ws + L.nbr_cnt);
+  T* y = (T*)(ws + L.y);
+  T* ug = (T*)(ws + L.ug);
+  T* hA = (T*)(ws + L.hA);
+  T* hB = (T*)(ws + L.hB);
+  T* basis = (T*)(ws + L.basis);
+  const int64_t srecT = S.stride / sizeof(T);   // record stride in T elements
+
+  hipLaunchKernelGGL(k_nbr, dim3(W), dim3(256), 0, s, R, W, D.n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt, status);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y);
+  CHECK(hipGetLastError());
+  // GLU: [u | g] = y [W_v | W_g] + [b_v | b_g];  t = u * SiLU(g);  h0 = t W_o + b_o
+  {
+    GemmArgs g{};
+    g.A = y; g.amap = rows_dense(D.d); g.Bt = (const char*)h->params + h->pl.Wvg_t; g.ldb = D.d;
+    g.bias = P.b_vg; g.C = ug; g.cmap = rows_dense(2 * D.d); g.ccol = cols_dense();
+    g.M = (int)rows; g.N = 2 * D.d; g.K = D.d; g.act = ACT_NONE;
+    CHECK(gemm(kind, g, s));
+  }
+  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * D.d + 255) / 256)), dim3(256), 0, s, ug, y, rows, D.d);
+  CHECK(hipGetLastError());
+  {
+    GemmArgs g{};
+    g.A = y; g.amap = rows_dense(D.d); g.Bt = (const char*)h->params + h->pl.Wo_t; g.ldb = D.d;
+    g.bias = P.b_o; g.C = state + S.h0; g.cmap = RowMap{D.n, srecT, D.d}; g.ccol = cols_dense();
+    g.M = (int)rows; g.N = D.d; g.K = D.d;
+    CHECK(gemm(kind, g, s));
+  }
+  // node projections [a^par | a^anti | b^par | b^anti] = h0 W_proj
+  {
+    GemmArgs g{};
+    g.A = state + S.h0; g.amap = RowMap{D.n, srecT, D.d}; g.Bt = (const char*)h->params + h->pl.Wproj_t;
+    g.ldb = D.d; g.C = state + S.proj; g.cmap = RowMap{D.n, srecT, 4 * D.d}; g.ccol = cols_dense();
+    g.M = (int)rows; g.N = 4 * D.d; g.K = D.d;
+    CHECK(gemm(kind, g, s));
+  }
+  hipLaunchKernelGGL(k_msg<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, nidx, ncnt,
+                     state, S.stride, S.h0, S.proj, S.m, hA);
+  CHECK(hipGetLastError());
+  // MLP
+  T* hin = hA;
+  T* hout = hB;
+  for (int k = 0; k < D.L; ++k) {
+    GemmArgs g{};
+    g.A = hin; g.amap = rows_dense(D.d);
+    g.Bt = (const char*)h->params + h->pl.mlp_t + (size_t)k * D.d * D.d * h->gsize; g.ldb = D.d;
+    g.bias = P.mlp_b + (int64_t)k * D.d; g.C = hout; g.cmap = rows_dense(D.d); g.ccol = cols_dense();
+    g.M = (int)rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU;
+    CHECK(gemm(kind, g, s));
+    T* t = hin; hin = hout; hout = t;
+  }
+  // envelopes and orbitals per spin block
+  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, s, P, R, rows, basis);
+  CHECK(hipGetLastError());
+  for (int sp = 0; sp < 2; ++sp) {
+    const int N = D.nsig(sp), e0 = sp == 0 ? 0 : D.nu;
+    if (N == 0) continue;
+    const int64_t mrows = (int64_t)W * N;
+    // env[w][det][sp][i][l] = sum_b basis[w][e0+i][b] pi[(det,l)][b]   (cached in state)
+    const RowMap smap{N, srecT, N};
+    const ColMap scol{N, phi_per_det(D)};
+    GemmArgs g{};
+    g.A = basis + (int64_t)e0 * D.B; g.amap = RowMap{N, (int64_t)D.n * D.B, D.B};
+    g.Bt = (const char*)h->params + (sp == 0 ? h->pl.pi0 : h->pl.pi1); g.ldb = D.B;
+    g.C = state + S.env + phi_block_off(D, sp) * sizeof(T); g.cmap = smap; g.ccol = scol;
+    g.M = (int)mrows; g.N = D.K * N; g.K = D.B;
+    CHECK(gemm(kind, g, s));
+    // Phi[w][det][sp][i][l] = (h_i . W[:, (det,l)]) * env
+    GemmArgs o{};
+    o.A = hin + (int64_t)e0 * D.d; o.amap = RowMap{N, (int64_t)D.n * D.d, D.d};
+    o.Bt = (const char*)h->params + (sp == 0 ? h->pl.orb_t0 : h->pl.orb_t1); o.ldb = D.d;
+    o.aux = state + S.env + phi_block_off(D, sp) * sizeof(T); o.xmap = smap; o.xcol = scol;
+    o.C = state + S.phi + phi_block_off(D, sp) * sizeof(T);
+    o.cmap = smap;
+    o.ccol = scol;
+    o.M = (int)mrows; o.N = D.K * N; o.K = D.d;
+    CHECK(gemm(kind, o, s));
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, double* logpsi, int32_t* status,
+                        hipStream_t s) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int N = D.nsig(sp);
+    size_t lds = ((size_t)N * (N + 1) + N) * sizeof(double);
+    CHECK(hipFuncSetAttribute((const void*)k_gj_inverse<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+    CHECK(hipFuncSetAttribute((const void*)k_gj_inverse<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+    if (h->isize == 8)
+      hipLaunchKernelGGL((k_gj_inverse<T, double>), dim3(W * D.K), dim3(256), lds, s, state, state, S.stride,
+                         S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
+    else
+      hipLaunchKernelGGL((k_gj_inverse<T, float>), dim3(W * D.K), dim3(256), lds, s, state, state, S.stride,
+                         S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
+    CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_logsumexp, dim3((W + 127) / 128), dim3(128), 0, s, state, S.stride, S.dsign, S.dlog, S.lpsi,
+                     S.spsi, W, D.K, sign, logpsi, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t forward(const fire_handle* h, int W, const double* R, char* state, char* ws, double* sign,
+                   double* logpsi, int32_t* status, hipStream_t s) {
+  Net<T> P = make_net<T>(h);
+  CHECK(embed_and_orbitals<T>(h, P, W, R, state, ws, status, s));
+  return refresh_dets<T>(h, W, state, sign, logpsi, status, s);
+}
+
+template hipError_t forward<double>(const fire_handle*, int, const double*, char*, char*, double*, double*,
+                                    int32_t*, hipStream_t);
+template hipError_t forward<float>(const fire_handle*, int, const double*, char*, char*, double*, double*,
+                                   int32_t*, hipStream_t);
+template hipError_t refresh_dets<double>(const fire_handle*, int, char*, double*, double*, int32_t*, hipStream_t);
+template hipError_t refresh_dets<float>(const fire_handle*, int, char*, double*, double*, int32_t*, hipStream_t);
+template hipError_t embed_and_orbitals<double>(const fire_handle*, const Net<double>&, int, const double*, char*,
+                                               char*, int32_t*, hipStream_t);
+template hipError_t embed_and_orbitals<float>(const fire_handle*, const Net<float>&, int, const double*, char*,
+                                              char*, int32_t*, hipStream_t);
+
+}  // namespace fire

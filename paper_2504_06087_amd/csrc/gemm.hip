@@ -1,0 +1,240 @@
+// Tiled MFMA GEMM for gfx950 with row-mapped operands and a fused epilogue.
+//
+// One 256-thread workgroup (4 wave64s in a 2x2 arrangement) computes a BM x BN
+// tile of C, staging BK = 32 wide K-slices of A and Bt through LDS.  Every
+// lane reads eight consecutive K elements of its A row and Bt row; bf16 uses
+// one v_mfma_f32_16x16x32_bf16 per 16x16 sub-tile, f32/f64 split the eight
+// elements over eight 16x16x4 MFMAs (lane group g feeds k = 8g + t to the t-th
+// instruction, so the eight instructions together cover the 32-wide slice).
+#include "gemm.hpp"
+
+namespace fire {
+
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 32;
+
+template <int KIND> struct MK;
+template <> struct MK<MMA_F64> {
+  using TA = double; using TB = double; using TC = double; using TL = double; using Acc = d4v;
+  static constexpr int BM = 64, BN = 64, PAD = 2;
+};
+template <> struct MK<MMA_F32> {
+  using TA = float; using TB = float; using TC = float; using TL = float; using Acc = f4v;
+  static constexpr int BM = 128, BN = 128, PAD = 4;
+};
+template <> struct MK<MMA_BF16> {
+  using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
+  static constexpr int BM = 128, BN = 128, PAD = 8;
+};
+
+FIRE_DEV int64_t roff(const RowMap& m, int64_t r) { return (r / m.rpg) * m.gstride + (r % m.rpg) * m.rstride; }
+FIRE_DEV int64_t coff(const ColMap& m, int64_t c) { return (c / m.cpg) * m.cgstride + (c % m.cpg); }
+
+template <typename TL, typename TS> FIRE_DEV TL to_lds(TS v) { return (TL)v; }
+template <> FIRE_DEV bf16_t to_lds<bf16_t, float>(float v) { return f2bf(v); }
+template <> FIRE_DEV bf16_t to_lds<bf16_t, bf16_t>(bf16_t v) { return v; }
+
+// Load 4 consecutive elements (k..k+3) of a row; zero outside [0,K) or when !valid.
+template <typename TS> FIRE_DEV void load4(const TS* p, int k, int K, bool valid, bool vec, TS out[4]) {
+  if (valid && vec && k + 3 < K) {
+    if constexpr (sizeof(TS) == 4) {
+      float4 v = *reinterpret_cast<const float4*>(p + k);
+      out[0] = __builtin_bit_cast(TS, v.x); out[1] = __builtin_bit_cast(TS, v.y);
+      out[2] = __builtin_bit_cast(TS, v.z); out[3] = __builtin_bit_cast(TS, v.w);
+    } else if constexpr (sizeof(TS) == 8) {
+      double2 a = *reinterpret_cast<const double2*>(p + k);
+      double2 b = *reinterpret_cast<const double2*>(p + k + 2);
+      out[0] = a.x; out[1] = a.y; out[2] = b.x; out[3] = b.y;
+    } else {
+      uint2 v = *reinterpret_cast<const uint2*>(p + k);
+      out[0] = (TS)(v.x & 0xffff); out[1] = (TS)(v.x >> 16);
+      out[2] = (TS)(v.y & 0xffff); out[3] = (TS)(v.y >> 16);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t] = (valid && k + t < K) ? p[k + t] : (TS)0;
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
+  using P = MK<KIND>;
+  using TA = typename P::TA; using TB = typename P::TB; using TC = typename P::TC;
+  using TL = typename P::TL; using Acc = typename P::Acc;
+  constexpr int BM = P::BM, BN = P::BN, LDK = BK + P::PAD;
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int CA = BM * BK / 4 / 256;   // 4-element chunks per thread (A)
+  constexpr int CB = BN * BK / 4 / 256;
+  __shared__ __attribute__((aligned(16))) TL As[BM * LDK];
+  __shared__ __attribute__((aligned(16))) TL Bs[BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int nct = (g.N + BN - 1) / BN;
+  // XCD-aware remap: consecutive logical tiles on the same XCD share A rows in L2
+  const int nb = gridDim.x, per = nb / 8;
+  const int bid = blockIdx.x;
+  const int lid = (bid < per * 8) ? (bid % 8) * per + bid / 8 : bid;
+  const int rt = lid / nct, ct = lid % nct;
+  const int64_t row0 = (int64_t)rt * BM, col0 = (int64_t)ct * BN;
+  if (g.Mdev) {
+    int m = *g.Mdev;
+    if (m < g.M) g.M = m;
+    if (row0 >= g.M) return;
+  }
+
+  const TA* A = (const TA*)g.A;
+  const TB* Bt = (const TB*)g.Bt;
+  const TA* arow[CA];
+  bool aval[CA];
+  int ak[CA], ar[CA];
+#pragma unroll
+  for (int t = 0; t < CA; ++t) {
+    int q = tid + 256 * t;
+    ar[t] = q / (BK / 4);
+    ak[t] = (q % (BK / 4)) * 4;
+    int64_t r = row0 + ar[t];
+    aval[t] = r < g.M;
+    arow[t] = A + (aval[t] ? roff(g.amap, r) : 0);
+  }
+  const TB* brow[CB];
+  bool bval[CB];
+  int bk[CB], br[CB];
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    int q = tid + 256 * t;
+    br[t] = q / (BK / 4);
+    bk[t] = (q % (BK / 4)) * 4;
+    int64_t c = col0 + br[t];
+    bval[t] = c < g.N;
+    brow[t] = Bt + (bval[t] ? c * g.ldb : 0);
+  }
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+  TA ra[CA][4];
+  TB rb[CB][4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < CA; ++t) load4<TA>(arow[t], k0 + ak[t], g.K, aval[t], vecA, ra[t]);
+#pragma unroll
+    for (int t = 0; t < CB; ++t) load4<TB>(brow[t], k0 + bk[t], g.K, bval[t], vecB, rb[t]);
+  };
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lg = lane >> 4, l16 = lane & 15;
+
+  const int nk = (g.K + BK - 1) / BK;
+  gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int t = 0; t < CA; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[ar[t] * LDK + ak[t] + e] = to_lds<TL, TA>(ra[t][e]);
+#pragma unroll
+    for (int t = 0; t < CB; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[br[t] * LDK + bk[t] + e] = to_lds<TL, TB>(rb[t][e]);
+    __syncthreads();
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+
+    if constexpr (KIND == MMA_BF16) {
+      bf16x8v af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        af[i] = *reinterpret_cast<const bf16x8v*>(&As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bfr[j] = *reinterpret_cast<const bf16x8v*>(&Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    } else {
+      TL af[TM][8], bfr[TN][8];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) af[i][e] = As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg + e];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bfr[j][e] = Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg + e];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (KIND == MMA_F64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][e], bfr[j][e], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][e], bfr[j][e], acc[i][j], 0, 0, 0);
+          }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: each lane holds column l16 of a 16x16 sub-tile; register e is
+  // row 4*lg + e for the f32-accumulating MFMAs and row 4*e + lg for the f64 one
+  // (measured lane layouts of v_mfma_f32_16x16x{4f32,32_bf16} and
+  // v_mfma_f64_16x16x4f64 on gfx950)
+  const TC* bias = (const TC*)g.bias;
+  const TC* aux = (const TC*)g.aux;
+  TC* C = (TC*)g.C;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    int64_t c = col0 + wn * (BN / 2) + j * 16 + l16;
+    if (c >= g.N) continue;
+    TC bc = bias ? bias[c] : TC(0);
+    int64_t cco = coff(g.ccol, c);
+    int64_t xco = aux ? coff(g.xcol, c) : 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t r = row0 + wm * (BM / 2) + i * 16 + (KIND == MMA_F64 ? 4 * e + lg : 4 * lg + e);
+        if (r >= g.M) continue;
+        TC v = (TC)acc[i][j][e] + bc;
+        if (g.act == ACT_SILU) v = silu_(v);
+        if (aux) v *= aux[roff(g.xmap, r) + xco];
+        TC* dst = C + roff(g.cmap, r) + cco;
+        if (g.accumulate) v += *dst;
+        *dst = v;
+      }
+  }
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+template <int KIND> static hipError_t launch(const GemmArgs& g, hipStream_t s) {
+  using P = MK<KIND>;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  int64_t tiles = (int64_t)((g.M + P::BM - 1) / P::BM) * ((g.N + P::BN - 1) / P::BN);
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  int vecA = aligned16(g.A) && g.K % 4 == 0 && g.amap.gstride % 4 == 0 && (g.amap.rpg == 1 || g.amap.rstride % 4 == 0);
+  int vecB = aligned16(g.Bt) && g.K % 4 == 0 && g.ldb % 4 == 0;
+  hipLaunchKernelGGL(k_gemm<KIND>, dim3((unsigned)tiles), dim3(256), 0, s, g, vecA, vecB);
+  return hipGetLastError();
+}
+
+hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s) {
+  switch (kind) {
+    case MMA_F64: return launch<MMA_F64>(g, s);
+    case MMA_F32: return launch<MMA_F32>(g, s);
+    case MMA_BF16: return launch<MMA_BF16>(g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fire

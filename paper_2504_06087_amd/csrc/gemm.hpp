@@ -1,0 +1,49 @@
+// Row-mapped GEMM with fused epilogue on MFMA (gfx950).
+#pragma once
+#include "common.hpp"
+
+namespace fire {
+
+// off(r) = (r / rpg) * gstride + (r % rpg) * rstride     (elements)
+struct RowMap {
+  int64_t rpg, gstride, rstride;
+};
+// off(c) = (c / cpg) * cgstride + (c % cpg)               (elements)
+struct ColMap {
+  int64_t cpg, cgstride;
+};
+inline RowMap rows_dense(int64_t ld) { return RowMap{1, ld, 0}; }
+inline ColMap cols_dense() { return ColMap{1ll << 40, 0}; }
+
+enum GemmAct { ACT_NONE = 0, ACT_SILU = 1 };
+enum GemmKind { MMA_F64 = 0, MMA_F32 = 1, MMA_BF16 = 2 };
+
+// C[r][c] = epi( sum_k A[r][k] * Bt[c][k] )
+//   epi: v (+ bias[c]) -> act -> (* aux[r][c]) -> (+= C[r][c] if accumulate) -> store
+// A is of element type TA (double or float), Bt of TB (double, float or bf16
+// storage), C/aux/bias of TC.
+struct GemmArgs {
+  const void* A;
+  RowMap amap;
+  const void* Bt;
+  int64_t ldb;        // row stride of Bt (>= K)
+  const void* bias;   // [N] or nullptr
+  const void* aux;    // nullptr or multiplier
+  RowMap xmap;
+  ColMap xcol;
+  void* C;
+  RowMap cmap;
+  ColMap ccol;
+  int M, N, K;        // M: row capacity (grid size)
+  int act;
+  int accumulate;
+  const int* Mdev;    // optional device row count (<= M); rows beyond it are skipped
+};
+
+// Launch on stream; kind fixes the element types:
+//   MMA_F64: A double, Bt double, C double
+//   MMA_F32: A float,  Bt float,  C float
+//   MMA_BF16: A float, Bt bf16,   C float   (A rounded to bf16 when staged)
+hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s);
+
+}  // namespace fire

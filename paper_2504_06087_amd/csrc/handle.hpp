@@ -1,0 +1,90 @@
+// Internal handle, packed-parameter layout, state and workspace layouts.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace fire {
+
+struct ThetaEntry {
+  std::string name;
+  int64_t offset;
+  std::vector<int> shape;
+  int64_t size() const {
+    int64_t s = 1;
+    for (int v : shape) s *= v;
+    return s;
+  }
+};
+
+struct EcpChan {
+  int species, l, nterms;
+  double a[4], alpha[4];
+};
+
+// Byte offsets of every packed array inside params_buf.
+struct ParamsLayout {
+  // small arrays in the elementwise type T
+  size_t en_W1, en_b1, en_W2, en_b2, en_W3, en_Wenv, en_sig, nuc_emb, en_Wn, ln_g, ln_b;
+  size_t msg_We, msg_b, ee_W1, ee_b1, ee_W2, ee_b2, ee_W3, ee_Wenv, ee_sig;
+  size_t b_vg, b_o, mlp_b, env_sigma;
+  // GEMM operands Bt[N][K] in the GEMM type G
+  size_t Wvg_t, Wo_t, Wproj_t, mlp_t, orb_t0, orb_t1, pi0, pi1;
+  // GEMM operands in the adjoint orientation (B = W^T): Bt = W, type G
+  size_t Wvg_n, Wo_n, Wproj_n, mlp_n, orb_n0, orb_n1;
+  // molecule
+  size_t Rn, Zn, ppw, ntype;
+  size_t total;
+};
+
+// Per-walker record of cached intermediates (byte offsets within a record).
+struct StateRec {
+  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi;
+  size_t stride;
+};
+
+}  // namespace fire
+
+struct fire_handle {
+  fire::Dims D;
+  fire_model_desc model;
+  std::vector<double> Rn, Z, ppw;
+  std::vector<int> species, ntype;
+  std::vector<fire::EcpChan> ecp;
+  double ecp_rmax;
+  std::vector<fire::ThetaEntry> theta;
+  int64_t P;
+  fire::ParamsLayout pl;
+  fire::StateRec st;
+  size_t tsize, gsize, isize;   // bytes of T, G and the stored-inverse type
+  void* params;                 // device params buffer (set by fire_set_params)
+  const double* theta_dev;      // theta passed to fire_set_params
+};
+
+namespace fire {
+
+// Workspace regions for a batch of W walkers (byte offsets).
+struct WsLayout {
+  size_t nbr_idx, nbr_cnt, y, ug, hA, hB, basis;
+  size_t total;
+};
+WsLayout ws_forward(const fire_handle* h, int W);
+
+
+// Forward evaluation (all walkers): fills state and (sign, logpsi).
+template <typename T>
+hipError_t forward(const fire_handle* h, int W, const double* R, char* state, char* ws,
+                   double* sign, double* logpsi, int32_t* status, hipStream_t s);
+
+// Full re-evaluation of Phi^-1 and determinant logs from the cached Phi.
+template <typename T>
+hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, double* logpsi,
+                        int32_t* status, hipStream_t s);
+
+inline int gemm_kind(int prec) { return prec == FIRE_FP64 ? MMA_F64 : (prec == FIRE_FP32 ? MMA_F32 : MMA_BF16); }
+
+static inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+}  // namespace fire

@@ -1,0 +1,732 @@
+// Single-electron updates (Methods, low-rank wave-function updates) and the
+// Metropolis sweep built on them (Methods, improved Monte Carlo sampling).
+//
+// One step moves electron e of every walker.  The update set is
+//   U = {e} u N(r_e) u N(r_e'),
+// only h0_e, the messages of U and the MLP / orbital rows of U are recomputed,
+// and for every determinant and spin block the ratio comes from
+//   A = I + dPhi_U G_U^T,  det Phi' = det Phi det A,
+// with G = Phi^-T cached (row k of G is column k of Phi^-1).  Accepted moves
+// update G by the Woodbury identity in one read-modify-write pass:
+//   G' = G - (G dPhi_U^T) A^-T G_U.
+#include "update.hpp"
+
+#include "embed_kernels.hpp"
+#include "linalg.hpp"
+
+namespace fire {
+
+#define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+UpdLayout upd_layout(const fire_handle* h, int W) {
+  const Dims& D = h->D;
+  UpdLayout L{};
+  size_t o = 0, ts = h->tsize, is = h->isize;
+  L.capS[0] = D.cap_upd < D.nu ? D.cap_upd : D.nu;
+  L.capS[1] = D.cap_upd < D.nd ? D.cap_upd : D.nd;
+  L.capmax = L.capS[0] > L.capS[1] ? L.capS[0] : L.capS[1];
+  if (L.capmax < 1) L.capmax = 1;
+  const int64_t Wl = W;
+  auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
+  L.rnew = take(Wl * 3 * 8);
+  L.uidx = take(Wl * 2 * L.capmax * 4);
+  L.ucnt = take(Wl * 2 * 4);
+  L.off = take((Wl + 1) * 2 * 4);
+  L.acc = take(Wl * 4);
+  L.detA = take(Wl * D.K * 2 * 2 * 8);
+  L.y = take(Wl * D.d * ts);
+  L.ug = take(Wl * 2 * D.d * ts);
+  L.h0new = take(Wl * D.d * ts);
+  L.projnew = take(Wl * 4 * D.d * ts);
+  L.basis = take(Wl * D.B * ts);
+  int nmax = D.nu > D.nd ? D.nu : D.nd;
+  L.envnew = take(Wl * D.K * nmax * ts);
+  for (int s = 0; s < 2; ++s) {
+    int64_t rows = Wl * (L.capS[s] > 0 ? L.capS[s] : 1);
+    int N = D.nsig(s) > 0 ? D.nsig(s) : 1;
+    L.rowcap[s] = rows;
+    L.rowinfo[s] = take(rows * 2 * 4);
+    L.hseg[s][0] = take(rows * D.d * ts);
+    L.hseg[s][1] = take(rows * D.d * ts);
+    L.mseg[s] = take(rows * D.d * ts);
+    L.oseg[s] = take(rows * D.K * N * ts);
+    L.dphi[s] = take(rows * D.K * N * is);
+  }
+  L.total = o;
+  return L;
+}
+
+static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
+
+// LDS bytes of the Woodbury kernel for spin block s
+static size_t woodbury_lds(const Dims& D, const UpdLayout& L, int s) {
+  int N = D.nsig(s), k = L.capS[s];
+  return (size_t)(WB_RB * N + 2 * k * N + k * (k + 1) + 2 * WB_RB * k + N + 2 * k + 8) * sizeof(double);
+}
+bool update_fits(const fire_handle* h) {
+  UpdLayout L = upd_layout(h, 1);
+  for (int s = 0; s < 2; ++s)
+    if (h->D.nsig(s) > 0 && woodbury_lds(h->D, L, s) > 160 * 1024) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// propose: r_e' = r_e + step * xi and the update set, one wave per walker.
+// uidx[w][s][t]: spin-s members in ascending order, e first in its own list.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, Jobs jb, int n, int nu, int e,
+                                                 double cut2, int cap0, int cap1, int capmax,
+                                                 double* __restrict__ rnew, int* __restrict__ uidx,
+                                                 int* __restrict__ ucnt, int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= jb.J) return;
+  if (jb.Jdev && j >= *jb.Jdev) {
+    if (lane == 0) { ucnt[2 * j] = 0; ucnt[2 * j + 1] = 0; }
+    return;
+  }
+  const int w = jb.jw ? jb.jw[j] : j;
+  const double* Rw = R + (int64_t)w * n * 3;
+  const double ox = Rw[3 * e], oy = Rw[3 * e + 1], oz = Rw[3 * e + 2];
+  double nx, ny, nz;
+  if (jb.rexp) {
+    nx = jb.rexp[3 * j]; ny = jb.rexp[3 * j + 1]; nz = jb.rexp[3 * j + 2];
+  } else {
+    nx = ox + jb.step * jb.xi[3 * j]; ny = oy + jb.step * jb.xi[3 * j + 1]; nz = oz + jb.step * jb.xi[3 * j + 2];
+  }
+  if (lane == 0) {
+    rnew[3 * j] = nx; rnew[3 * j + 1] = ny; rnew[3 * j + 2] = nz;
+    if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) atomicOr(status + w, FIRE_W_NONFINITE);
+  }
+  const int se = e < nu ? 0 : 1;
+  int cnt[2] = {0, 0};
+  cnt[se] = 1;
+  int* u0 = uidx + (int64_t)j * 2 * capmax;
+  if (lane == 0) u0[se * capmax] = e;
+  const int cap[2] = {cap0, cap1};
+  bool over = false;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    int i = i0 + lane;
+    bool in = false;
+    if (i < n && i != e) {
+      double x = Rw[3 * i], y = Rw[3 * i + 1], z = Rw[3 * i + 2];
+      double d0 = (x - ox) * (x - ox) + (y - oy) * (y - oy) + (z - oz) * (z - oz);
+      double d1 = (x - nx) * (x - nx) + (y - ny) * (y - ny) + (z - nz) * (z - nz);
+      in = d0 <= cut2 || d1 <= cut2;
+    }
+    const int si = i < nu ? 0 : 1;
+    uint64_t m = __ballot(in);
+    uint64_t mup = __ballot(in && si == 0);
+    uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int pos = si == 0 ? __popcll(mup & below) : __popcll((m & ~mup) & below);
+    if (in) {
+      int t = cnt[si] + pos;
+      if (t < cap[si]) u0[si * capmax + t] = i;
+    }
+    cnt[0] += __popcll(mup);
+    cnt[1] += __popcll(m & ~mup);
+  }
+  for (int s = 0; s < 2; ++s)
+    if (cnt[s] > cap[s]) { over = true; cnt[s] = cap[s]; }
+  if (lane == 0) {
+    ucnt[2 * j] = cnt[0];
+    ucnt[2 * j + 1] = cnt[1];
+    if (over) atomicOr(status + w, FIRE_W_UPD_OVERFLOW);
+  }
+}
+
+// exclusive scan of the per-spin member counts: off[s][w], off[s][W] = total
+__global__ __launch_bounds__(1024) void k_scan_counts(const int* __restrict__ ucnt, int W, int* __restrict__ off) {
+  __shared__ int part[2][1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (W + nt - 1) / nt;
+  const int b = t * per, e = b + per < W ? b + per : W;
+  int s0 = 0, s1 = 0;
+  for (int w = b; w < e; ++w) { s0 += ucnt[2 * w]; s1 += ucnt[2 * w + 1]; }
+  part[0][t] = s0;
+  part[1][t] = s1;
+  __syncthreads();
+  if (t < 2) {
+    int acc = 0;
+    for (int k = 0; k < nt; ++k) { int v = part[t][k]; part[t][k] = acc; acc += v; }
+    off[t * (W + 1) + W] = acc;
+  }
+  __syncthreads();
+  int a0 = part[0][t], a1 = part[1][t];
+  for (int w = b; w < e; ++w) {
+    off[w] = a0;
+    off[(W + 1) + w] = a1;
+    a0 += ucnt[2 * w];
+    a1 += ucnt[2 * w + 1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// messages of the update set.  For u != e:
+//   m_u' = m_u - edge(u, e; r_e, b_e) + edge(u, e; r_e', b_e')
+// and m_e' is recomputed over the members within c of r_e'.  Writes h1' =
+// h0 + m' and m' for every member at its compact row, and the row's (w, u).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* __restrict__ jw, int e,
+                                                    const double* __restrict__ R,
+                                                    const double* __restrict__ rnew, const int* __restrict__ uidx,
+                                                    int capmax, const int* __restrict__ ucnt,
+                                                    const int* __restrict__ off, const char* __restrict__ state,
+                                                    StateRec S, const T* __restrict__ h0new,
+                                                    const T* __restrict__ projnew, T* hseg0, T* hseg1, T* mseg0,
+                                                    T* mseg1, int* rinfo0, int* rinfo1) {
+  const Dims& D = P.D;
+  constexpr int MPC = 21;               // members per chunk (3 pair feature sets each)
+  __shared__ T feat[3 * MPC * FEAT];
+  __shared__ int mem[MPC];
+  const int j = blockIdx.x;
+  if (ucnt[2 * j] + ucnt[2 * j + 1] == 0) return;   // inactive job
+  const int w = jw ? jw[j] : j;
+  const int c = threadIdx.x;
+  const bool act = c < D.d;
+  const int n = D.n, se = e < D.nu ? 0 : 1;
+  const char* rec = state + (int64_t)w * S.stride;
+  const T* h0 = (const T*)(rec + S.h0);
+  const T* proj = (const T*)(rec + S.proj);
+  const T* mold = (const T*)(rec + S.m);
+  const double* Rw = R + (int64_t)w * n * 3;
+  const double ox = Rw[3 * e], oy = Rw[3 * e + 1], oz = Rw[3 * e + 2];
+  const double nx = rnew[3 * j], ny = rnew[3 * j + 1], nz = rnew[3 * j + 2];
+  const T* pe_new = projnew + (int64_t)j * 4 * D.d;
+  T acc_e = 0;
+  for (int s = 0; s < 2; ++s) {
+    const int a = (s == se) ? 0 : 1;
+    const int cnt = ucnt[2 * j + s];
+    const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+    T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0;
+    if (act) {
+      for (int k = 0; k < D.h2; ++k) w3[k] = P.ee_W3[(a * D.h2 + k) * D.d + c];
+      for (int k = 0; k < D.G; ++k) wenv[k] = P.ee_Wenv[(a * D.G + k) * D.d + c];
+      for (int k = 0; k < 4; ++k) we[k] = P.msg_We[(a * 4 + k) * D.d + c];
+      bb = P.msg_b[a * D.d + c];
+    }
+    T* hseg = s == 0 ? hseg0 : hseg1;
+    T* mseg = s == 0 ? mseg0 : mseg1;
+    int* rinfo = s == 0 ? rinfo0 : rinfo1;
+    const int q0 = off[s * (W + 1) + j];
+    for (int t0 = 0; t0 < cnt; t0 += MPC) {
+      const int tc = cnt - t0 < MPC ? cnt - t0 : MPC;
+      __syncthreads();
+      if (threadIdx.x < 3 * tc) {
+        const int t = threadIdx.x / 3, kind = threadIdx.x % 3;
+        const int u = lst[t0 + t];
+        if (kind == 0) mem[t] = u;
+        const double ux = Rw[3 * u], uy = Rw[3 * u + 1], uz = Rw[3 * u + 2];
+        double dx, dy, dz;
+        if (kind == 0) { dx = ux - ox; dy = uy - oy; dz = uz - oz; }        // (u, e) old
+        else if (kind == 1) { dx = ux - nx; dy = uy - ny; dz = uz - nz; }   // (u, e) new
+        else { dx = nx - ux; dy = ny - uy; dz = nz - uz; }                  // (e, u) new
+        pair_features<T>((T)dx, (T)dy, (T)dz, P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1,
+                         P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2, P.ee_sig + a * D.G, (T)D.cut, D,
+                         feat + threadIdx.x * FEAT);
+      }
+      __syncthreads();
+      if (!act) continue;
+      for (int t = 0; t < tc; ++t) {
+        const int u = mem[t];
+        if (u == e) continue;
+        T mu = mold[(int64_t)u * D.d + c];
+        const T au = proj[((int64_t)u * 4 + a) * D.d + c];
+        for (int kind = 0; kind < 3; ++kind) {
+          const T* f = feat + (3 * t + kind) * FEAT;
+          if (f[44] == T(0)) continue;
+          T g1 = 0, g2 = 0;
+          for (int q = 0; q < D.h2; ++q) g1 += f[4 + q] * w3[q];
+          for (int q = 0; q < D.G; ++q) g2 += f[12 + q] * wenv[q];
+          const T ef = f[0] * we[0] + f[1] * we[1] + f[2] * we[2] + f[3] * we[3] + bb;
+          if (kind == 0) mu -= g1 * g2 * silu_(au + proj[((int64_t)e * 4 + 2 + a) * D.d + c] + ef);
+          else if (kind == 1) mu += g1 * g2 * silu_(au + pe_new[(2 + a) * D.d + c] + ef);
+          else acc_e += g1 * g2 * silu_(pe_new[a * D.d + c] + proj[((int64_t)u * 4 + 2 + a) * D.d + c] + ef);
+        }
+        const int64_t q = q0 + t0 + t;
+        hseg[q * D.d + c] = h0[(int64_t)u * D.d + c] + mu;
+        mseg[q * D.d + c] = mu;
+        if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = u; }
+      }
+    }
+  }
+  if (act) {
+    T* hseg = se == 0 ? hseg0 : hseg1;
+    T* mseg = se == 0 ? mseg0 : mseg1;
+    int* rinfo = se == 0 ? rinfo0 : rinfo1;
+    const int64_t q = off[se * (W + 1) + j];   // e is first in its list
+    hseg[q * D.d + c] = h0new[(int64_t)j * D.d + c] + acc_e;
+    mseg[q * D.d + c] = acc_e;
+    if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = e; }
+  }
+}
+
+// Phi' rows = o' * env (cached env, or the moved electron's new env) and
+// dPhi = Phi' - Phi in the inverse's precision.  One thread per element.
+template <typename T, typename TI>
+__global__ void k_dphi(const Dims D, int s, int e, const int* __restrict__ jw, const int* __restrict__ rinfo,
+                       const int* __restrict__ Mdev,
+                       T* __restrict__ oseg, const char* __restrict__ state, StateRec S,
+                       const T* __restrict__ envnew, TI* __restrict__ dphi) {
+  const int N = D.nsig(s);
+  const int KN = D.K * N;
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t rows = *Mdev;
+  if (q >= rows * KN) return;
+  const int64_t r = q / KN;
+  const int col = (int)(q % KN);
+  const int j = rinfo[2 * r], u = rinfo[2 * r + 1];
+  const int w = jw ? jw[j] : j;
+  const int det = col / N, l = col % N;
+  const int iloc = s == 0 ? u : u - D.nu;
+  const char* rec = state + (int64_t)w * S.stride;
+  const int64_t idx = det * phi_per_det(D) + phi_block_off(D, s) + (int64_t)iloc * N + l;
+  const T env = (u == e) ? envnew[(int64_t)j * KN + col] : ((const T*)(rec + S.env))[idx];
+  const T pn = oseg[q] * env;
+  const T po = ((const T*)(rec + S.phi))[idx];
+  oseg[q] = pn;
+  dphi[q] = (TI)pn - (TI)po;
+}
+
+// det A for every (walker, determinant, spin block); A = I + dPhi_U G_U^T.
+template <typename TI>
+__global__ __launch_bounds__(64) void k_detA(const Dims D, int W, const int* __restrict__ jw, int s,
+                                             const int* __restrict__ uidx, int capmax,
+                                             const int* __restrict__ ucnt, const int* __restrict__ off,
+                                             const TI* __restrict__ dphi, const char* __restrict__ state,
+                                             StateRec S, double* __restrict__ detA) {
+  extern __shared__ double lds[];
+  __shared__ double sc[2];
+  __shared__ int fl[2];
+  const int j = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  const int w = jw ? jw[j] : j;
+  const int N = D.nsig(s);
+  const int k = ucnt[2 * j + s];
+  double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
+  if (k == 0) {
+    if (threadIdx.x == 0) { out[0] = 1.0; out[1] = 0.0; }
+    return;
+  }
+  const int LD = k + 1;
+  double* A = lds;
+  double* f = lds + k * LD;
+  int* pm = (int*)(f + k);
+  const int q0 = off[s * (W + 1) + j];
+  const int e0 = s == 0 ? 0 : D.nu;
+  const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+  const TI* G = (const TI*)(state + (int64_t)w * S.stride + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+  const int KN = D.K * N;
+  for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
+    const int a = q / k, b = q % k;
+    const TI* dp = dphi + (int64_t)(q0 + a) * KN + det * N;
+    const TI* gb = G + (int64_t)(lst[b] - e0) * N;
+    double acc = (a == b) ? 1.0 : 0.0;
+    for (int l = 0; l < N; ++l) acc += (double)dp[l] * (double)gb[l];
+    A[a * LD + b] = acc;
+  }
+  __syncthreads();
+  gj_block(A, k, LD, f, pm, sc, fl, false);
+  if (threadIdx.x == 0) {
+    if (fl[1]) { out[0] = 0.0; out[1] = -INFINITY; }
+    else { out[0] = sc[0]; out[1] = sc[1]; }
+  }
+}
+
+// Acceptance: psi'/psi = sum_d s_d e^{l_d} prod_s det A_ds / sum_d s_d e^{l_d};
+// accept iff u < (psi'/psi)^2.  Updates the determinant logs and log|psi|.
+__global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, const double* __restrict__ rnew,
+                         const double* __restrict__ unif, char* __restrict__ state, StateRec S,
+                         const double* __restrict__ detA, int32_t* __restrict__ status, int* __restrict__ acc,
+                         int32_t* __restrict__ n_accept) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  char* rec = state + (int64_t)w * S.stride;
+  double* ds = (double*)(rec + S.dsign);
+  double* dl = (double*)(rec + S.dlog);
+  const double lp = *(double*)(rec + S.lpsi);
+  const double* dA = detA + (int64_t)w * D.K * 4;
+  double lmax = -INFINITY;
+  for (int k = 0; k < D.K; ++k) {
+    double sg = ds[2 * k] * ds[2 * k + 1] * dA[4 * k] * dA[4 * k + 2];
+    double l = dl[2 * k] + dl[2 * k + 1] + dA[4 * k + 1] + dA[4 * k + 3];
+    if (sg != 0.0 && l > lmax) lmax = l;
+  }
+  double tot = 0.0;
+  for (int k = 0; k < D.K; ++k) {
+    double sg = ds[2 * k] * ds[2 * k + 1] * dA[4 * k] * dA[4 * k + 2];
+    if (sg != 0.0) tot += sg * exp(dl[2 * k] + dl[2 * k + 1] + dA[4 * k + 1] + dA[4 * k + 3] - lmax);
+  }
+  int a = 0;
+  double lpn = 0.0;
+  if (status[w] == 0 && tot != 0.0 && isfinite(tot) && isfinite(lmax)) {
+    lpn = lmax + log(fabs(tot));
+    const double ratio2 = exp(2.0 * (lpn - lp));
+    a = unif[w] < ratio2;
+  }
+  acc[w] = a;
+  if (!a) return;
+  for (int k = 0; k < D.K; ++k)
+    for (int s = 0; s < 2; ++s) {
+      ds[2 * k + s] *= dA[4 * k + 2 * s];
+      dl[2 * k + s] += dA[4 * k + 2 * s + 1];
+    }
+  *(double*)(rec + S.lpsi) = lpn;
+  *(double*)(rec + S.spsi) = tot > 0 ? 1.0 : -1.0;
+  R[((int64_t)w * D.n + e) * 3 + 0] = rnew[3 * w];
+  R[((int64_t)w * D.n + e) * 3 + 1] = rnew[3 * w + 1];
+  R[((int64_t)w * D.n + e) * 3 + 2] = rnew[3 * w + 2];
+  n_accept[w] += 1;
+}
+
+// Woodbury update of G for accepted walkers and commit of the Phi rows of U.
+// Rows of G are processed in blocks of WB_RB rows staged through LDS.
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx,
+                                                  int capmax, const int* __restrict__ ucnt,
+                                                  const int* __restrict__ off, const int* __restrict__ acc,
+                                                  const TI* __restrict__ dphi, const T* __restrict__ oseg,
+                                                  char* __restrict__ state, StateRec S, int32_t* status) {
+  extern __shared__ double lds[];
+  __shared__ int perm[128];
+  __shared__ double sc[2];
+  __shared__ int fl[2];
+  const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  const int k = ucnt[2 * w + s];
+  if (!acc[w] || k == 0) return;
+  const int N = D.nsig(s);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* dP = lds;               // [k][N]
+  double* GU = dP + k * N;        // [k][N]
+  double* Ai = GU + k * N;        // [k][k+1]
+  double* GB = Ai + k * (k + 1);  // [WB_RB][N]
+  double* Z = GB + WB_RB * N;     // [WB_RB][k]
+  double* V = Z + WB_RB * k;      // [WB_RB][k]
+  double* f = V + WB_RB * k;      // [k]
+  const int LD = k + 1;
+  const int q0 = off[s * (W + 1) + w];
+  const int e0 = s == 0 ? 0 : D.nu;
+  const int* lst = uidx + ((int64_t)w * 2 + s) * capmax;
+  const int KN = D.K * N;
+  char* rec = state + (int64_t)w * S.stride;
+  TI* G = (TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+  T* phi = (T*)(rec + S.phi) + det * phi_per_det(D) + phi_block_off(D, s);
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q % N;
+    dP[q] = (double)dphi[(int64_t)(q0 + a) * KN + det * N + l];
+    GU[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
+  }
+  __syncthreads();
+  for (int q = tid; q < k * k; q += nt) {
+    const int a = q / k, b = q % k;
+    double v = (a == b) ? 1.0 : 0.0;
+    for (int l = 0; l < N; ++l) v += dP[a * N + l] * GU[b * N + l];
+    Ai[a * LD + b] = v;
+  }
+  __syncthreads();
+  gj_block(Ai, k, LD, f, perm, sc, fl, true);
+  if (fl[1]) {
+    if (tid == 0) atomicOr(status + w, FIRE_W_SINGULAR);
+    return;
+  }
+  for (int m0 = 0; m0 < N; m0 += WB_RB) {
+    const int rb = N - m0 < WB_RB ? N - m0 : WB_RB;
+    for (int q = tid; q < rb * N; q += nt) GB[q] = (double)G[(int64_t)m0 * N + q];
+    __syncthreads();
+    // Z[m][a] = sum_l G[m][l] dPhi[a][l]
+    for (int q = tid; q < rb * k; q += nt) {
+      const int m = q / k, a = q % k;
+      double v = 0.0;
+      for (int l = 0; l < N; ++l) v += GB[m * N + l] * dP[a * N + l];
+      Z[q] = v;
+    }
+    __syncthreads();
+    // V[m][b] = sum_a Z[m][a] (A^-1)[b][a]
+    for (int q = tid; q < rb * k; q += nt) {
+      const int m = q / k, b = q % k;
+      double v = 0.0;
+      for (int a = 0; a < k; ++a) v += Z[m * k + a] * Ai[b * LD + a];
+      V[q] = v;
+    }
+    __syncthreads();
+    // G'[m][l] = G[m][l] - sum_b V[m][b] G_U[b][l]
+    for (int q = tid; q < rb * N; q += nt) {
+      const int m = q / N, l = q % N;
+      double v = GB[q];
+      for (int b = 0; b < k; ++b) v -= V[m * k + b] * GU[b * N + l];
+      G[(int64_t)m0 * N + q] = (TI)v;
+    }
+    __syncthreads();
+  }
+  // commit the new Phi rows of this determinant and spin block
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q % N;
+    phi[(int64_t)(lst[a] - e0) * N + l] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
+  }
+}
+
+// Commit h0_e, projections of e, messages of U and the envelopes of e.
+template <typename T>
+__global__ __launch_bounds__(256) void k_commit(const Dims D, int W, int e, const int* __restrict__ acc,
+                                                const int* __restrict__ uidx, int capmax,
+                                                const int* __restrict__ ucnt, const int* __restrict__ off,
+                                                const T* __restrict__ h0new, const T* __restrict__ projnew,
+                                                const T* __restrict__ mseg0, const T* __restrict__ mseg1,
+                                                const T* __restrict__ envnew, char* __restrict__ state, StateRec S) {
+  const int w = blockIdx.x;
+  if (!acc[w]) return;
+  char* rec = state + (int64_t)w * S.stride;
+  T* h0 = (T*)(rec + S.h0);
+  T* proj = (T*)(rec + S.proj);
+  T* m = (T*)(rec + S.m);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = tid; c < D.d; c += nt) h0[(int64_t)e * D.d + c] = h0new[(int64_t)w * D.d + c];
+  for (int c = tid; c < 4 * D.d; c += nt) proj[(int64_t)e * 4 * D.d + c] = projnew[(int64_t)w * 4 * D.d + c];
+  for (int s = 0; s < 2; ++s) {
+    const int cnt = ucnt[2 * w + s];
+    const int q0 = off[s * (W + 1) + w];
+    const int* lst = uidx + ((int64_t)w * 2 + s) * capmax;
+    const T* ms = s == 0 ? mseg0 : mseg1;
+    for (int q = tid; q < cnt * D.d; q += nt) {
+      const int t = q / D.d, c = q % D.d;
+      m[(int64_t)lst[t] * D.d + c] = ms[(int64_t)(q0 + t) * D.d + c];
+    }
+  }
+  const int se = e < D.nu ? 0 : 1;
+  const int N = D.nsig(se);
+  const int iloc = se == 0 ? e : e - D.nu;
+  T* env = (T*)(rec + S.env);
+  for (int q = tid; q < D.K * N; q += nt) {
+    const int det = q / N, l = q % N;
+    env[det * phi_per_det(D) + phi_block_off(D, se) + (int64_t)iloc * N + l] = envnew[(int64_t)w * D.K * N + q];
+  }
+}
+
+__global__ void k_final_outputs(const Dims D, int W, const char* __restrict__ state, StateRec S,
+                                const int32_t* __restrict__ status, double* logpsi, double* sign) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const char* rec = state + (int64_t)w * S.stride;
+  const bool bad = status[w] != 0;
+  if (logpsi) logpsi[w] = bad ? NAN : *(const double*)(rec + S.lpsi);
+  if (sign) sign[w] = bad ? 0.0 : *(const double*)(rec + S.spsi);
+}
+
+__global__ void k_unit_detA(int nwd, int s, double* detA) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nwd) return;
+  detA[(int64_t)q * 4 + 2 * s] = 1.0;
+  detA[(int64_t)q * 4 + 2 * s + 1] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// one single-electron proposal for all walkers (shared by Metropolis and the
+// pseudopotential quadrature, which stops after det A)
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, int e, const double* R,
+                         char* state, char* ws, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  const int W = jb.J;
+  const UpdLayout L = upd_layout(h, W);
+  const int kind = gemm_kind(D.prec);
+  const int se = e < D.nu ? 0 : 1;
+  const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
+  double* rnew = (double*)(ws + L.rnew);
+  int* uidx = (int*)(ws + L.uidx);
+  int* ucnt = (int*)(ws + L.ucnt);
+  int* off = (int*)(ws + L.off);
+  T* y = (T*)(ws + L.y);
+  T* ug = (T*)(ws + L.ug);
+  T* h0new = (T*)(ws + L.h0new);
+  T* projnew = (T*)(ws + L.projnew);
+  T* basis = (T*)(ws + L.basis);
+  T* envnew = (T*)(ws + L.envnew);
+
+  hipLaunchKernelGGL(k_propose, dim3((W + 3) / 4), dim3(256), 0, st, R, jb, D.n, D.nu, e, D.cut * D.cut,
+                     L.capS[0], L.capS[1], L.capmax, rnew, uidx, ucnt, status);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off);
+  CHECK(hipGetLastError());
+  // h0 and projections of the moved electron
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((W + EPB - 1) / EPB), dim3(blk), 0, st, P, (const double*)rnew,
+                     (int64_t)W, y);
+  CHECK(hipGetLastError());
+  {
+    GemmArgs g{};
+    g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wvg_t; g.ldb = D.d; g.bias = P.b_vg;
+    g.C = ug; g.cmap = rows_dense(2 * D.d); g.ccol = cols_dense(); g.M = W; g.N = 2 * D.d; g.K = D.d;
+    CHECK(gemm(kind, g, st));
+  }
+  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)(((int64_t)W * D.d + 255) / 256)), dim3(256), 0, st, ug, y,
+                     (int64_t)W, D.d);
+  CHECK(hipGetLastError());
+  {
+    GemmArgs g{};
+    g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wo_t; g.ldb = D.d; g.bias = P.b_o;
+    g.C = h0new; g.cmap = rows_dense(D.d); g.ccol = cols_dense(); g.M = W; g.N = D.d; g.K = D.d;
+    CHECK(gemm(kind, g, st));
+    GemmArgs p{};
+    p.A = h0new; p.amap = rows_dense(D.d); p.Bt = P.Wproj_t; p.ldb = D.d;
+    p.C = projnew; p.cmap = rows_dense(4 * D.d); p.ccol = cols_dense(); p.M = W; p.N = 4 * D.d; p.K = D.d;
+    CHECK(gemm(kind, p, st));
+  }
+  T* hs[2][2];
+  T* ms[2];
+  int* ri[2];
+  for (int s = 0; s < 2; ++s) {
+    hs[s][0] = (T*)(ws + L.hseg[s][0]);
+    hs[s][1] = (T*)(ws + L.hseg[s][1]);
+    ms[s] = (T*)(ws + L.mseg[s]);
+    ri[s] = (int*)(ws + L.rowinfo[s]);
+  }
+  hipLaunchKernelGGL(k_msg_update<T>, dim3(W), dim3(blk), 0, st, P, W, jb.jw, e, R, (const double*)rnew,
+                     (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off, (const char*)state, S,
+                     (const T*)h0new, (const T*)projnew, hs[0][0], hs[1][0], ms[0], ms[1], ri[0], ri[1]);
+  CHECK(hipGetLastError());
+  // envelopes of the moved electron at r_e'
+  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)(((int64_t)W * D.B + 255) / 256)), dim3(256), 0, st, P,
+                     (const double*)rnew, (int64_t)W, basis);
+  CHECK(hipGetLastError());
+  {
+    const int N = D.nsig(se);
+    GemmArgs g{};
+    g.A = basis; g.amap = rows_dense(D.B); g.Bt = se == 0 ? P.pi0 : P.pi1; g.ldb = D.B;
+    g.C = envnew; g.cmap = rows_dense((int64_t)D.K * N); g.ccol = cols_dense(); g.M = W; g.N = D.K * N; g.K = D.B;
+    CHECK(gemm(kind, g, st));
+  }
+  for (int s = 0; s < 2; ++s) {
+    const int N = D.nsig(s);
+    if (N == 0) continue;
+    const int* Mdev = off + s * (W + 1) + W;
+    const int rows = (int)L.rowcap[s];
+    T* hin = hs[s][0];
+    T* hout = hs[s][1];
+    for (int k = 0; k < D.L; ++k) {
+      GemmArgs g{};
+      g.A = hin; g.amap = rows_dense(D.d);
+      g.Bt = (const char*)P.mlp_t + (size_t)k * D.d * D.d * h->gsize; g.ldb = D.d;
+      g.bias = P.mlp_b + (int64_t)k * D.d; g.C = hout; g.cmap = rows_dense(D.d); g.ccol = cols_dense();
+      g.M = rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU; g.Mdev = Mdev;
+      CHECK(gemm(kind, g, st));
+      T* t = hin; hin = hout; hout = t;
+    }
+    T* oseg = (T*)(ws + L.oseg[s]);
+    GemmArgs o{};
+    o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
+    o.C = oseg; o.cmap = rows_dense((int64_t)D.K * N); o.ccol = cols_dense();
+    o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
+    CHECK(gemm(kind, o, st));
+    const int64_t tot = (int64_t)rows * D.K * N;
+    if (h->isize == 8) {
+      hipLaunchKernelGGL((k_dphi<T, double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e,
+                         jb.jw, (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
+                         (double*)(ws + L.dphi[s]));
+      CHECK(hipGetLastError());
+      hipLaunchKernelGGL((k_detA<double>), dim3(W * D.K), dim3(64), detA_lds(L.capS[s]), st,
+                         D, W, jb.jw, s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const double*)(ws + L.dphi[s]), (const char*)state, S, (double*)(ws + L.detA));
+    } else {
+      hipLaunchKernelGGL((k_dphi<T, float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e,
+                         jb.jw, (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
+                         (float*)(ws + L.dphi[s]));
+      CHECK(hipGetLastError());
+      hipLaunchKernelGGL((k_detA<float>), dim3(W * D.K), dim3(64), detA_lds(L.capS[s]), st,
+                         D, W, jb.jw, s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const float*)(ws + L.dphi[s]), (const char*)state, S, (double*)(ws + L.detA));
+    }
+    CHECK(hipGetLastError());
+  }
+  // a spin block with no electrons contributes det A = 1
+  for (int s = 0; s < 2; ++s)
+    if (D.nsig(s) == 0) {
+      hipLaunchKernelGGL(k_unit_detA, dim3((W * D.K + 255) / 256), dim3(256), 0, st, W * D.K, s,
+                         (double*)(ws + L.detA));
+      CHECK(hipGetLastError());
+    }
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* R, const double* unif, char* state,
+                                    char* ws, int32_t* n_accept, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  const UpdLayout L = upd_layout(h, W);
+  int* acc = (int*)(ws + L.acc);
+  hipLaunchKernelGGL(k_accept, dim3((W + 127) / 128), dim3(128), 0, st, D, W, e, R, (const double*)(ws + L.rnew),
+                     unif, state, S, (const double*)(ws + L.detA), status, acc, n_accept);
+  CHECK(hipGetLastError());
+  for (int s = 0; s < 2; ++s) {
+    if (D.nsig(s) == 0) continue;
+    size_t lds = woodbury_lds(D, L, s);
+    if (h->isize == 8) {
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+      hipLaunchKernelGGL((k_woodbury<T, double>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
+                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                         (const int*)acc, (const double*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S,
+                         status);
+    } else {
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+      hipLaunchKernelGGL((k_woodbury<T, float>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
+                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                         (const int*)acc, (const float*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S,
+                         status);
+    }
+    CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_commit<T>, dim3(W), dim3(256), 0, st, D, W, e, (const int*)acc, (const int*)(ws + L.uidx),
+                     L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const T*)(ws + L.h0new),
+                     (const T*)(ws + L.projnew), (const T*)(ws + L.mseg[0]), (const T*)(ws + L.mseg[1]),
+                     (const T*)(ws + L.envnew), state, S);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
+                             const double* noise, const double* unif, int32_t* n_accept, double* logpsi,
+                             double* sign, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  Net<T> P = make_net<T>(h);
+  CHECK(fill_i32(status, W, 0, st));
+  const int refresh = h->model.refresh_every;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    for (int e = 0; e < D.n; ++e) {
+      Jobs jb{};
+      jb.J = W;
+      jb.xi = noise + ((int64_t)sw * D.n + e) * W * 3;
+      jb.step = step;
+      const double* u = unif + ((int64_t)sw * D.n + e) * W;
+      CHECK(propose_ratio<T>(h, P, jb, e, R, state, ws, status, st));
+      CHECK(accept_and_commit<T>(h, W, e, R, u, state, ws, n_accept, status, st));
+    }
+    if (refresh > 0 && (sw + 1) % refresh == 0) {
+      // full re-evaluation of every cached quantity from the positions (FP64 LU)
+      CHECK(embed_and_orbitals<T>(h, P, W, R, state, ws, status, st));
+      CHECK(refresh_dets<T>(h, W, state, nullptr, nullptr, status, st));
+    }
+  }
+  hipLaunchKernelGGL(k_final_outputs, dim3((W + 127) / 128), dim3(128), 0, st, D, W, (const char*)state, h->st,
+                     (const int32_t*)status, logpsi, sign);
+  return hipGetLastError();
+}
+
+hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
+                           const double* noise, const double* unif, int32_t* n_accept, double* logpsi,
+                           double* sign, int32_t* status, hipStream_t s) {
+  if (!update_fits(h)) return hipErrorInvalidValue;
+  return h->tsize == 8 ? sweep_impl<double>(h, W, R, state, ws, n_sweeps, step, noise, unif, n_accept, logpsi, sign,
+                                            status, s)
+                       : sweep_impl<float>(h, W, R, state, ws, n_sweeps, step, noise, unif, n_accept, logpsi, sign,
+                                           status, s);
+}
+
+template hipError_t propose_ratio<double>(const fire_handle*, const Net<double>&, const Jobs&, int,
+                                          const double*, char*, char*, int32_t*, hipStream_t);
+template hipError_t propose_ratio<float>(const fire_handle*, const Net<float>&, const Jobs&, int, const double*,
+                                         char*, char*, int32_t*, hipStream_t);
+
+}  // namespace fire

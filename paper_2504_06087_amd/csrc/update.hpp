@@ -1,0 +1,39 @@
+// Single-electron update machinery shared by Metropolis and the
+// pseudopotential quadrature.
+#pragma once
+#include "paths.hpp"
+
+namespace fire {
+
+constexpr int WB_RB = 16;   // rows of G per LDS block in the Woodbury kernel
+
+// A batch of single-electron proposals ("jobs") for one electron index e.
+// Job j moves electron e of walker jw[j] (identity when jw is null) to
+// rexp[j] when rexp is set, else to r_e + step * xi[j].  Jobs at or beyond
+// *Jdev (when set) are inactive.
+struct Jobs {
+  int J;
+  const int* Jdev;
+  const int* jw;
+  const double* rexp;
+  const double* xi;
+  double step;
+};
+
+struct UpdLayout {
+  int capS[2], capmax;
+  int64_t rowcap[2];
+  size_t rnew, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
+  size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2];
+  size_t total;
+};
+UpdLayout upd_layout(const fire_handle* h, int J);
+bool update_fits(const fire_handle* h);
+
+// Runs every step up to det A for each job: writes detA[j][det][spin] =
+// (sign, log|det A|) into the workspace (UpdLayout::detA).
+template <typename T>
+hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, int e, const double* R,
+                         char* state, char* ws, int32_t* status, hipStream_t st);
+
+}  // namespace fire

@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libfire (argument marshalling only).
+
+Every step of the hot path runs in the HIP kernels of libfire.so; PyTorch
+supplies device memory and the current stream.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfire.so")
+
+FIRE_FP64, FIRE_FP32, FIRE_BF16_HYBRID = 0, 1, 2
+PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
+W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
+
+EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
+           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep",
+           "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
+           "fire_status_string"]
+
+
+class FireEcpChannel(ctypes.Structure):
+    _fields_ = [("species", ctypes.c_int), ("l", ctypes.c_int), ("n_terms", ctypes.c_int),
+                ("a", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.POINTER(ctypes.c_double))]
+
+
+class FireSystemDesc(ctypes.Structure):
+    _fields_ = [("n_nuc", ctypes.c_int), ("R_nuc", ctypes.POINTER(ctypes.c_double)),
+                ("Z", ctypes.POINTER(ctypes.c_double)), ("species", ctypes.POINTER(ctypes.c_int)),
+                ("nuc_type", ctypes.POINTER(ctypes.c_int)), ("pp_width", ctypes.POINTER(ctypes.c_double)),
+                ("n_up", ctypes.c_int), ("n_dn", ctypes.c_int), ("n_ecp", ctypes.c_int),
+                ("ecp", ctypes.POINTER(FireEcpChannel)), ("ecp_rmax", ctypes.c_double)]
+
+
+class FireModelDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int), ("mlp_layers", ctypes.c_int), ("n_det", ctypes.c_int),
+                ("n_env", ctypes.c_int), ("n_gauss", ctypes.c_int), ("edge_h1", ctypes.c_int),
+                ("edge_h2", ctypes.c_int), ("n_nuc_types", ctypes.c_int), ("cutoff", ctypes.c_double),
+                ("cutoff_nuc", ctypes.c_double), ("precision", ctypes.c_int), ("max_walkers", ctypes.c_int),
+                ("cap_nbr", ctypes.c_int), ("cap_upd", ctypes.c_int), ("refresh_every", ctypes.c_int)]
+
+
+class FireParamEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("offset", ctypes.c_int64), ("ndim", ctypes.c_int32),
+                ("shape", ctypes.c_int32 * 4)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libfire.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfire.so not built at {LIB_PATH}; run paper_2504_06087_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    st = ctypes.c_int32
+    lib.fire_create.argtypes = [ctypes.POINTER(FireSystemDesc), ctypes.POINTER(FireModelDesc), ctypes.POINTER(P)]
+    lib.fire_destroy.argtypes = [P]
+    lib.fire_param_layout.argtypes = [P, ctypes.POINTER(FireParamEntry), ctypes.POINTER(I)]
+    lib.fire_num_params.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.fire_sizes.argtypes = [P, I, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.POINTER(ctypes.c_size_t)]
+    lib.fire_state_layout.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.fire_set_params.argtypes = [P, V, V, V]
+    lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
+    lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
+    lib.fire_local_energy.argtypes = [P, I, V, V, V, V, V, V, V, V, V]
+    lib.fire_ecp_nonlocal.argtypes = [P, I, V, V, V, V, V, V, V]
+    lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V]
+    lib.fire_sync_status.argtypes = [P, V, V, I, ctypes.POINTER(ctypes.c_int32)]
+    lib.fire_status_string.argtypes = [st]
+    lib.fire_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "fire_status_string":
+            getattr(lib, name).restype = st
+    _lib = lib
+    return lib
+
+
+class FireError(RuntimeError):
+    pass
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise FireError(f"{what}: {load().fire_status_string(code).decode()} ({code})")
+
+
+def _dp(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _f64(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
+
+
+class Fire:
+    """One handle of libfire for one molecule and one parameter set."""
+
+    def __init__(self, system, model, precision: str = "fp64", max_walkers: int = 1024,
+                 cap_nbr: Optional[int] = None, cap_upd: Optional[int] = None, refresh_every: int = 50,
+                 device: str = "cuda"):
+        lib = load()
+        self.system, self.model, self.precision = system, model, precision
+        self.device = torch.device(device)
+        n = system.n_el
+        self.n = n
+        M = system.n_nuc
+        self._host = dict(
+            R=np.ascontiguousarray(system.R_nuc, np.float64).reshape(-1),
+            Z=np.ascontiguousarray(system.Z, np.float64), sp=np.ascontiguousarray(system.species, np.int32),
+            nt=np.ascontiguousarray(system.nuc_type, np.int32), pw=np.ascontiguousarray(system.pp_width, np.float64))
+        chans = []
+        keep = []
+        for sp, lst in system.ecp.items():
+            for ch in lst:
+                a = np.ascontiguousarray(ch.a, np.float64)
+                al = np.ascontiguousarray(ch.alpha, np.float64)
+                keep += [a, al]
+                chans.append(FireEcpChannel(int(sp), int(ch.l), len(a),
+                                            a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            al.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        arr = (FireEcpChannel * max(1, len(chans)))(*chans)
+        dp = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+        h = self._host
+        sd = FireSystemDesc(M, dp(h["R"], ctypes.c_double), dp(h["Z"], ctypes.c_double), dp(h["sp"], ctypes.c_int),
+                            dp(h["nt"], ctypes.c_int), dp(h["pw"], ctypes.c_double), system.n_up, system.n_dn,
+                            len(chans), arr, float(system.ecp_rmax))
+        cap_nbr = cap_nbr if cap_nbr is not None else min(n - 1, 64) if n > 1 else 1
+        cap_upd = cap_upd if cap_upd is not None else min(n, 96)
+        self.cap_nbr, self.cap_upd = max(1, cap_nbr), max(1, cap_upd)
+        md = FireModelDesc(model.width, model.mlp_layers, model.n_det, model.n_env, model.n_gauss,
+                           int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
+                           float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], int(max_walkers),
+                           self.cap_nbr, self.cap_upd, int(refresh_every))
+        self.max_walkers = max_walkers
+        hd = ctypes.c_void_p()
+        _check(lib.fire_create(ctypes.byref(sd), ctypes.byref(md), ctypes.byref(hd)), "fire_create")
+        self.h = hd
+        cnt = ctypes.c_int(0)
+        _check(lib.fire_param_layout(self.h, None, ctypes.byref(cnt)), "fire_param_layout")
+        ents = (FireParamEntry * cnt.value)()
+        _check(lib.fire_param_layout(self.h, ents, ctypes.byref(cnt)), "fire_param_layout")
+        self.layout = [(e.name.decode(), int(e.offset), tuple(e.shape[:e.ndim])) for e in ents]
+        P = ctypes.c_int64(0)
+        _check(lib.fire_num_params(self.h, ctypes.byref(P)), "fire_num_params")
+        self.P = int(P.value)
+        offs = (ctypes.c_size_t * 10)()
+        stride = ctypes.c_size_t(0)
+        _check(lib.fire_state_layout(self.h, offs, ctypes.byref(stride)), "fire_state_layout")
+        self.state_offsets = list(offs)
+        self.state_stride = int(stride.value)
+        self.params_buf = None
+        self.theta = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None and _lib is not None:
+                _lib.fire_destroy(self.h)
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def flatten(self, params: Dict[str, np.ndarray]) -> np.ndarray:
+        """theta in the library's layout from named arrays (shapes checked)."""
+        out = np.zeros(self.P, np.float64)
+        for name, off, shape in self.layout:
+            a = np.asarray(params[name], np.float64)
+            if tuple(a.shape) != tuple(shape):
+                raise ValueError(f"{name}: shape {a.shape} != {shape}")
+            out[off:off + a.size] = a.reshape(-1)
+        return out
+
+    def unflatten(self, theta) -> Dict[str, np.ndarray]:
+        t = np.asarray(theta)
+        return {name: t[off:off + int(np.prod(shape))].reshape(shape) for name, off, shape in self.layout}
+
+    def sizes(self, W: int):
+        p, s, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().fire_sizes(self.h, int(W), ctypes.byref(p), ctypes.byref(s), ctypes.byref(w)), "fire_sizes")
+        return p.value, s.value, w.value
+
+    def set_params(self, params):
+        theta = params if isinstance(params, torch.Tensor) else _f64(self.flatten(params), self.device)
+        pb, _, _ = self.sizes(1)
+        self.params_buf = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.theta = theta
+        _check(load().fire_set_params(self.h, _dp(theta), _dp(self.params_buf), _stream()), "fire_set_params")
+
+    def buffers(self, W: int):
+        _, s, w = self.sizes(W)
+        return (torch.empty(s, dtype=torch.uint8, device=self.device),
+                torch.empty(w, dtype=torch.uint8, device=self.device))
+
+    # ------------------------------------------------------------------
+    def eval_logpsi(self, R, state, ws):
+        W = R.shape[0]
+        sign = torch.empty(W, dtype=torch.float64, device=self.device)
+        logpsi = torch.empty_like(sign)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_eval_logpsi(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(sign), _dp(logpsi),
+                                       _dp(status), _stream()), "fire_eval_logpsi")
+        return sign, logpsi, status
+
+    def mcmc_sweep(self, R, state, ws, n_sweeps, step, noise, unif, n_accept=None):
+        W = R.shape[0]
+        if n_accept is None:
+            n_accept = torch.zeros(W, dtype=torch.int32, device=self.device)
+        sign = torch.empty(W, dtype=torch.float64, device=self.device)
+        logpsi = torch.empty_like(sign)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_mcmc_sweep(self.h, W, _dp(R), _dp(state), _dp(ws), int(n_sweeps), float(step),
+                                      _dp(noise), _dp(unif), _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status),
+                                      _stream()), "fire_mcmc_sweep")
+        return n_accept, sign, logpsi, status
+
+    def local_energy(self, R, state, ws, quad_rot=None, want_grad=False):
+        W = R.shape[0]
+        e = torch.empty(W, dtype=torch.float64, device=self.device)
+        parts = torch.empty(W, 5, dtype=torch.float64, device=self.device)
+        g = torch.empty(W, self.n, 3, dtype=torch.float64, device=self.device) if want_grad else None
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_local_energy(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(quad_rot), _dp(e), _dp(parts),
+                                        _dp(g), _dp(status), _stream()), "fire_local_energy")
+        return e, parts, g, status
+
+    def ecp_nonlocal(self, R, state, ws, quad_rot=None):
+        W = R.shape[0]
+        v = torch.empty(W, dtype=torch.float64, device=self.device)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_ecp_nonlocal(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(quad_rot), _dp(v),
+                                        _dp(status), _stream()), "fire_ecp_nonlocal")
+        return v, status
+
+    def grad_params(self, R, state, ws, coeff):
+        W = R.shape[0]
+        g = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_grad_params(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(coeff), _dp(g), _dp(status),
+                                       _stream()), "fire_grad_params")
+        return g, status
+
+    # ------------------------------------------------------------------
+    def state_view(self, state, W, which: str):
+        """A typed view of one cached array for all W walkers (debug/tests)."""
+        names = ["h0", "proj", "m", "phi", "env", "inv", "dsign", "dlog", "lpsi", "spsi"]
+        k = names.index(which)
+        tsz = 8 if self.precision == "fp64" else 4
+        isz = 4 if self.precision == "fp32" else 8
+        n, d, K = self.n, self.model.width, self.model.n_det
+        ppd = self.system.n_up ** 2 + self.system.n_dn ** 2
+        count = {"h0": n * d, "proj": n * 4 * d, "m": n * d, "phi": K * ppd, "env": K * ppd, "inv": K * ppd,
+                 "dsign": 2 * K, "dlog": 2 * K, "lpsi": 1, "spsi": 1}[which]
+        esz = {"inv": isz, "dsign": 8, "dlog": 8, "lpsi": 8, "spsi": 8}.get(which, tsz)
+        dt = torch.float64 if esz == 8 else torch.float32
+        rec = state[:W * self.state_stride].view(W, self.state_stride)
+        off = self.state_offsets[k]
+        return rec[:, off:off + count * esz].contiguous().view(dt)
+
+
+def fire_status_string(code: int) -> str:
+    return load().fire_status_string(code).decode()

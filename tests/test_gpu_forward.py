@@ -1,0 +1,157 @@
+"""GPU parity of fire_eval_logpsi against the FP64 oracle (Methods, eq. wf).
+
+Tolerances: |d log|psi|| <= 1e-10 in FP64 and <= 1e-4 in FP32; signs equal.
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from gpu_common import dev, log, setup
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(F, R, state, ws):
+    Rd = dev(R)
+    sign, lp, st = F.eval_logpsi(Rd, state, ws)
+    torch.cuda.synchronize()
+    return sign.cpu().numpy(), lp.cpu().numpy(), st.cpu().numpy()
+
+
+def test_h4_fp64_parity(lib):
+    log("case: H4 fp64 W=64")
+    F, O, s, m, p, R, state, ws = setup(0, 64, "fp64")
+    sg, lp, st = _run(F, R, state, ws)
+    os_, ol = O.log_psi(R)
+    assert (st == 0).all()
+    assert np.array_equal(sg, os_.numpy())
+    err = np.abs(lp - ol.numpy()).max()
+    log("H4 fp64 max |dlogpsi|", err)
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("W", [1, 13])
+def test_polyene_fp64_parity_and_intermediates(lib, W):
+    log(f"case: C12H14 fp64 W={W}")
+    F, O, s, m, p, R, state, ws = setup(1, W, "fp64")
+    sg, lp, st = _run(F, R, state, ws)
+    out = O.embed(torch.tensor(R))
+    h0 = F.state_view(state, W, "h0").cpu().numpy().reshape(W, s.n_el, -1)
+    mm = F.state_view(state, W, "m").cpu().numpy().reshape(W, s.n_el, -1)
+    e_h0 = np.abs(h0 - out["h0"].numpy()).max()
+    e_m = np.abs(mm - (out["m"][0] + out["m"][1]).numpy()).max()
+    os_, ol = O.log_psi(R)
+    err = np.abs(lp - ol.numpy()).max()
+    log(f"C12H14 fp64 W={W}: |dh0| {e_h0:.3e} |dm| {e_m:.3e} |dlogpsi| {err:.3e} status {np.unique(st)}")
+    assert e_h0 <= 1e-11 and e_m <= 1e-11
+    assert (st == 0).all()
+    assert np.array_equal(sg, os_.numpy())
+    assert err <= 1e-10
+
+
+def test_polyene_fp32_parity(lib):
+    log("case: C12H14 fp32 W=32")
+    F, O, s, m, p, R, state, ws = setup(1, 32, "fp32")
+    sg, lp, st = _run(F, R, state, ws)
+    os_, ol = O.log_psi(R)
+    err = np.abs(lp - ol.numpy()).max()
+    out = O.embed(torch.tensor(R))
+    W, n = 32, s.n_el
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    h0 = F.state_view(state, W, "h0").cpu().numpy().reshape(W, n, -1)
+    mm = F.state_view(state, W, "m").cpu().numpy().reshape(W, n, -1)
+    phis = O.orbitals(torch.tensor(R), out["h"])
+    ph = F.state_view(state, W, "phi").cpu().numpy().reshape(W, m.n_det, -1)
+    nu = s.n_up
+    up = ph[:, :, :nu * nu].reshape(W, m.n_det, nu, nu)
+    # log|det| of the GPU's FP32 Phi evaluated in FP64 on the host: separates
+    # the error of Phi from that of the determinant stage
+    ld_host = np.linalg.slogdet(up.astype(np.float64))[1]
+    ld_orc = torch.linalg.slogdet(phis[0])[1].numpy()
+    log(f"C12H14 fp32: |dlogpsi| max {err:.2e} median {np.median(np.abs(lp - ol.numpy())):.2e}; "
+        f"rel h0 {rel(h0, out['h0'].numpy()):.2e} m {rel(mm, (out['m'][0] + out['m'][1]).numpy()):.2e} "
+        f"Phi_up {rel(up, phis[0].numpy()):.2e}; logdet_up(GPU Phi, fp64) err {np.abs(ld_host - ld_orc).max():.2e}")
+    assert (st == 0).all()
+    assert np.array_equal(sg, os_.numpy())
+    # FP32 entries carry ~1e-6 relative error; log|det| amplifies it by the
+    # first-order factor sum_il |Phi^-1_li Phi_il| of each block.  Median over
+    # walkers <= 1e-4, every walker within 4e-6 times that factor (summed over
+    # the determinants' blocks, weighted by their share of psi).
+    assert np.median(np.abs(lp - ol.numpy())) <= 1e-4
+    bound = np.zeros(W)
+    sgn, ld, *_ = O.log_psi_parts(torch.tensor(R))[2:4] + (None,)
+    wts = torch.softmax(ld, 1).numpy()
+    for blk in phis:
+        inv = torch.linalg.inv(blk)
+        amp = (inv.transpose(-1, -2).abs() * blk.abs()).sum((-1, -2)).numpy()   # [W,K]
+        bound += (wts * amp).sum(1)
+    assert (np.abs(lp - ol.numpy()) <= 4e-6 * bound + 1e-5).all()
+
+
+def test_flake_bf16_hybrid_logpsi_error_reported(lib):
+    log("case: C42H12 bf16 W=4")
+    F, O, s, m, p, R, state, ws = setup(3, 4, "bf16")
+    sg, lp, st = _run(F, R, state, ws)
+    F64, *_ = setup(3, 4, "fp64")
+    st64, ws64 = F64.buffers(4)
+    sg64, lp64, _ = _run(F64, R, st64, ws64)
+    os_, ol = O.log_psi(R)
+    e64 = np.abs(lp64 - ol.numpy()).max()
+    e16 = np.abs(lp - ol.numpy()).max()
+    log(f"C42H12: fp64 |dlogpsi| {e64:.3e}; bf16-hybrid |dlogpsi| {e16:.3e} (rel {e16/np.abs(ol.numpy()).max():.2e})")
+    assert (st == 0).all()
+    assert e64 <= 1e-9
+    assert e16 <= 1e-2 * np.abs(ol.numpy()).max()
+
+
+def test_antisymmetry_on_gpu(lib):
+    F, O, s, m, p, R, state, ws = setup(1, 4, "fp64")
+    sg, lp, _ = _run(F, R, state, ws)
+    R2 = R.copy()
+    R2[:, [2, 9]] = R2[:, [9, 2]]
+    sg2, lp2, _ = _run(F, R2, state, ws)
+    assert np.array_equal(sg2, -sg)
+    assert np.abs(lp2 - lp).max() <= 1e-11
+
+
+def test_dense_limit_large_cutoff(lib):
+    """c -> infinity: every pair is a neighbour (Introduction, dense limit)."""
+    F, O, s, m, p, R, state, ws = setup(0, 16, "fp64", model_kw={"cutoff": 1e6})
+    sg, lp, st = _run(F, R, state, ws)
+    _, ol = O.log_psi(R)
+    assert (st == 0).all()
+    assert np.abs(lp - ol.numpy()).max() <= 1e-10
+
+
+def test_status_flags(lib):
+    from paper_2504_06087_amd import fire
+    # neighbour overflow with capacity 1
+    F, O, s, m, p, R, state, ws = setup(1, 4, "fp64", cap_nbr=1)
+    sg, lp, st = _run(F, R, state, ws)
+    assert ((st & fire.W_NBR_OVERFLOW) != 0).all() and np.isnan(lp).all() and (sg == 0).all()
+    # coincident same-spin electrons: exactly singular spin block
+    F, O, s, m, p, R, state, ws = setup(0, 3, "fp64")
+    R2 = R.copy()
+    R2[1, 1] = R2[1, 0]
+    R2[2, 0, 0] = np.nan
+    sg, lp, st = _run(F, R2, state, ws)
+    assert st[0] == 0 and np.isfinite(lp[0])
+    assert st[1] & fire.W_SINGULAR and np.isnan(lp[1]) and sg[1] == 0
+    assert st[2] & fire.W_NONFINITE and np.isnan(lp[2])
+
+
+def test_cancelling_determinants_flag(lib):
+    from paper_2504_06087_amd import fire
+
+    def two_dets(s, m, p, R):
+        m.n_det = 2
+        for k in ("orb_W_up", "orb_W_dn", "env_pi_up", "env_pi_dn"):
+            p[k] = np.repeat(p[k], 2, axis=0)
+        p["orb_W_up"][1][:, 0] *= -1.0
+        return s, m, p, R
+    F, O, s, m, p, R, state, ws = setup(0, 4, "fp64", system_fn=two_dets)
+    sg, lp, st = _run(F, R, state, ws)
+    assert ((st & fire.W_DETSUM_ZERO) != 0).all() and (sg == 0).all()
