@@ -99,6 +99,10 @@ typedef struct {
   int cap_nbr;        /* max |N_i| per electron (both spin classes) */
   int cap_upd;        /* max |U| of a single-electron update */
   int refresh_every;  /* sweeps between full FP64 re-evaluations */
+  int bf16_split;     /* FIRE_BF16_HYBRID only: GEMM sites whose operands are
+                         split into bf16 high + low parts (three MFMA products,
+                         FP32 accumulation): bit 0 embedding/MLP rows, bit 1
+                         orbital/envelope rows, bit 2 Laplacian tangent rows */
 } fire_model_desc;
 
 typedef struct fire_handle fire_handle;

@@ -13,7 +13,7 @@ using namespace fire;
 // ---------------------------------------------------------------------------
 // parameter packing: dst[i0*t0 + i1*t1 + i2*t2] = src[i0*s0 + i1*s1 + i2*s2]
 // ---------------------------------------------------------------------------
-template <typename TD>
+template <typename TD, bool LO>
 __global__ void k_strided(TD* dst, const double* __restrict__ src, int n0, int n1, int n2, int64_t s0, int64_t s1,
                           int64_t s2, int64_t t0, int64_t t1, int64_t t2) {
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -25,8 +25,12 @@ __global__ void k_strided(TD* dst, const double* __restrict__ src, int n0, int n
   int i0 = (int)(r / n1);
   double v = src[i0 * s0 + i1 * s1 + i2 * s2];
   TD* o = dst + i0 * t0 + i1 * t1 + i2 * t2;
-  if constexpr (sizeof(TD) == 2) *o = f2bf((float)v);
-  else *o = (TD)v;
+  if constexpr (sizeof(TD) == 2) {
+    const bf16_t hi = f2bf((float)v);
+    *o = LO ? f2bf((float)(v - (double)bf2f(hi))) : hi;
+  } else {
+    *o = (TD)v;
+  }
 }
 
 struct Copy {
@@ -39,19 +43,24 @@ static Copy transposed(int nmat, int rows, int cols) {
   return Copy{nmat, cols, rows, (int64_t)rows * cols, 1, cols, (int64_t)rows * cols, rows, 1};
 }
 
-static hipError_t do_copy(int tbytes, void* dst, const double* src, const Copy& c, hipStream_t s) {
+static hipError_t do_copy(int tbytes, void* dst, const double* src, const Copy& c, hipStream_t s,
+                          size_t lo_delta = 0) {
   int64_t tot = (int64_t)c.n0 * c.n1 * c.n2;
   if (tot <= 0) return hipSuccess;
   dim3 grid((unsigned)((tot + 255) / 256));
   if (tbytes == 8)
-    hipLaunchKernelGGL(k_strided<double>, grid, dim3(256), 0, s, (double*)dst, src, c.n0, c.n1, c.n2, c.s0, c.s1,
-                       c.s2, c.t0, c.t1, c.t2);
+    hipLaunchKernelGGL((k_strided<double, false>), grid, dim3(256), 0, s, (double*)dst, src, c.n0, c.n1, c.n2, c.s0,
+                       c.s1, c.s2, c.t0, c.t1, c.t2);
   else if (tbytes == 4)
-    hipLaunchKernelGGL(k_strided<float>, grid, dim3(256), 0, s, (float*)dst, src, c.n0, c.n1, c.n2, c.s0, c.s1,
-                       c.s2, c.t0, c.t1, c.t2);
-  else
-    hipLaunchKernelGGL(k_strided<bf16_t>, grid, dim3(256), 0, s, (bf16_t*)dst, src, c.n0, c.n1, c.n2, c.s0, c.s1,
-                       c.s2, c.t0, c.t1, c.t2);
+    hipLaunchKernelGGL((k_strided<float, false>), grid, dim3(256), 0, s, (float*)dst, src, c.n0, c.n1, c.n2, c.s0,
+                       c.s1, c.s2, c.t0, c.t1, c.t2);
+  else {
+    hipLaunchKernelGGL((k_strided<bf16_t, false>), grid, dim3(256), 0, s, (bf16_t*)dst, src, c.n0, c.n1, c.n2, c.s0,
+                       c.s1, c.s2, c.t0, c.t1, c.t2);
+    if (lo_delta)
+      hipLaunchKernelGGL((k_strided<bf16_t, true>), grid, dim3(256), 0, s, (bf16_t*)((char*)dst + lo_delta), src,
+                         c.n0, c.n1, c.n2, c.s0, c.s1, c.s2, c.t0, c.t1, c.t2);
+  }
   return hipGetLastError();
 }
 
@@ -109,8 +118,17 @@ static void build_layouts(fire_handle* h) {
   L.Wvg_n = take((size_t)2 * D.d * D.d * G); L.Wo_n = take((size_t)D.d * D.d * G);
   L.Wproj_n = take((size_t)4 * D.d * D.d * G); L.mlp_n = take((size_t)D.L * D.d * D.d * G);
   L.orb_n0 = take((size_t)D.K * D.nu * D.d * G); L.orb_n1 = take((size_t)D.K * D.nd * D.d * G);
+  if (D.prec == FIRE_BF16_HYBRID) {
+    const size_t region = o - L.Wvg_t;
+    L.lo_delta = region;
+    o += region;
+    o = align_up(o);
+  } else {
+    L.lo_delta = 0;
+  }
   L.Rn = take((size_t)D.M * 3 * 8); L.Zn = take((size_t)D.M * 8); L.ppw = take((size_t)D.M * 8);
   L.ntype = take((size_t)D.M * 4);
+  L.species = take((size_t)D.M * 4);
   L.total = o;
 
   StateRec& S = h->st;
@@ -157,6 +175,7 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   D.G = md->n_gauss; D.h1 = md->edge_h1; D.h2 = md->edge_h2; D.B = D.M * D.E;
   D.cut = md->cutoff; D.cutn = md->cutoff_nuc; D.cap_nbr = md->cap_nbr; D.cap_upd = md->cap_upd;
   D.prec = md->precision;
+  D.split = md->precision == FIRE_BF16_HYBRID ? md->bf16_split : 0;
   if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > 128 || D.nd > 128 || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
   if (D.d < 1 || D.d > 256 || D.L < 0 || D.L > 16 || D.K < 1 || D.K > 32 || D.E < 1) return FIRE_ERR_SHAPE;
   if (D.G != kMaxG || D.h1 < 1 || D.h1 > kMaxH1 || D.h2 < 1 || D.h2 > kMaxH2) return FIRE_ERR_SHAPE;
@@ -260,27 +279,28 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
   DO(do_copy(T, b + L.b_vg, src("glu_bv"), plain(D.d), s));
   DO(do_copy(T, b + L.b_vg + (size_t)D.d * T, src("glu_bg"), plain(D.d), s));
   DO(cp(L.b_o, "glu_bo")); DO(cp(L.mlp_b, "mlp_b"));
-  // GEMM operands Bt[N][K]
+  // GEMM operands Bt[N][K] (and their low bf16 parts under the hybrid precision)
   const int64_t dd = (int64_t)D.d * D.d;
-  DO(do_copy(G, b + L.Wvg_t, src("glu_Wv"), transposed(1, D.d, D.d), s));
-  DO(do_copy(G, b + L.Wvg_t + dd * G, src("glu_Wg"), transposed(1, D.d, D.d), s));
-  DO(do_copy(G, b + L.Wo_t, src("glu_Wo"), transposed(1, D.d, D.d), s));
-  DO(do_copy(G, b + L.Wproj_t, src("msg_Wa"), transposed(2, D.d, D.d), s));
-  DO(do_copy(G, b + L.Wproj_t + 2 * dd * G, src("msg_Wb"), transposed(2, D.d, D.d), s));
-  DO(do_copy(G, b + L.mlp_t, src("mlp_W"), transposed(D.L, D.d, D.d), s));
-  DO(do_copy(G, b + L.orb_t0, src("orb_W_up"), transposed(D.K, D.d, D.nu), s));
-  DO(do_copy(G, b + L.orb_t1, src("orb_W_dn"), transposed(D.K, D.d, D.nd), s));
-  DO(do_copy(G, b + L.pi0, src("env_pi_up"), plain((int64_t)D.K * D.nu * D.B), s));
-  DO(do_copy(G, b + L.pi1, src("env_pi_dn"), plain((int64_t)D.K * D.nd * D.B), s));
+  const size_t LD = L.lo_delta;
+  DO(do_copy(G, b + L.Wvg_t, src("glu_Wv"), transposed(1, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.Wvg_t + dd * G, src("glu_Wg"), transposed(1, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.Wo_t, src("glu_Wo"), transposed(1, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.Wproj_t, src("msg_Wa"), transposed(2, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.Wproj_t + 2 * dd * G, src("msg_Wb"), transposed(2, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.mlp_t, src("mlp_W"), transposed(D.L, D.d, D.d), s, LD));
+  DO(do_copy(G, b + L.orb_t0, src("orb_W_up"), transposed(D.K, D.d, D.nu), s, LD));
+  DO(do_copy(G, b + L.orb_t1, src("orb_W_dn"), transposed(D.K, D.d, D.nd), s, LD));
+  DO(do_copy(G, b + L.pi0, src("env_pi_up"), plain((int64_t)D.K * D.nu * D.B), s, LD));
+  DO(do_copy(G, b + L.pi1, src("env_pi_dn"), plain((int64_t)D.K * D.nd * D.B), s, LD));
   // adjoint orientation: Bt = W with the output columns of the forward GEMM as K
   // Wvg_n[k][c]: c < d -> Wv[k][c], c >= d -> Wg[k][c-d]
-  DO(do_copy(G, b + L.Wvg_n, src("glu_Wv"), Copy{1, D.d, D.d, 0, D.d, 1, 0, 2 * D.d, 1}, s));
-  DO(do_copy(G, b + L.Wvg_n + (size_t)D.d * G, src("glu_Wg"), Copy{1, D.d, D.d, 0, D.d, 1, 0, 2 * D.d, 1}, s));
-  DO(do_copy(G, b + L.Wo_n, src("glu_Wo"), plain(dd), s));
+  DO(do_copy(G, b + L.Wvg_n, src("glu_Wv"), Copy{1, D.d, D.d, 0, D.d, 1, 0, 2 * D.d, 1}, s, LD));
+  DO(do_copy(G, b + L.Wvg_n + (size_t)D.d * G, src("glu_Wg"), Copy{1, D.d, D.d, 0, D.d, 1, 0, 2 * D.d, 1}, s, LD));
+  DO(do_copy(G, b + L.Wo_n, src("glu_Wo"), plain(dd), s, LD));
   // Wproj_n[k][q*d + c] = W_q[k][c] for q = (Wa0, Wa1, Wb0, Wb1)
-  DO(do_copy(G, b + L.Wproj_n, src("msg_Wa"), Copy{2, D.d, D.d, dd, D.d, 1, D.d, 4 * D.d, 1}, s));
-  DO(do_copy(G, b + L.Wproj_n + 2 * (size_t)D.d * G, src("msg_Wb"), Copy{2, D.d, D.d, dd, D.d, 1, D.d, 4 * D.d, 1}, s));
-  DO(do_copy(G, b + L.mlp_n, src("mlp_W"), plain((int64_t)D.L * dd), s));
+  DO(do_copy(G, b + L.Wproj_n, src("msg_Wa"), Copy{2, D.d, D.d, dd, D.d, 1, D.d, 4 * D.d, 1}, s, LD));
+  DO(do_copy(G, b + L.Wproj_n + 2 * (size_t)D.d * G, src("msg_Wb"), Copy{2, D.d, D.d, dd, D.d, 1, D.d, 4 * D.d, 1}, s, LD));
+  DO(do_copy(G, b + L.mlp_n, src("mlp_W"), plain((int64_t)D.L * dd), s, LD));
   // orb_n[k][det*N + l] = orb_W[det][k][l]
   DO(do_copy(G, b + L.orb_n0, src("orb_W_up"),
              Copy{D.d, D.K, D.nu, D.nu, (int64_t)D.d * D.nu, 1, (int64_t)D.K * D.nu, D.nu, 1}, s));
@@ -290,7 +310,8 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
   if (hipMemcpyAsync(b + L.Rn, h->Rn.data(), h->Rn.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(b + L.Zn, h->Z.data(), h->Z.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(b + L.ppw, h->ppw.data(), h->ppw.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(b + L.ntype, h->ntype.data(), h->ntype.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      hipMemcpyAsync(b + L.ntype, h->ntype.data(), h->ntype.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(b + L.species, h->species.data(), h->species.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return FIRE_ERR_HIP;
   // host vectors must outlive the async copies: wait for them
   if (hipStreamSynchronize(s) != hipSuccess) return FIRE_ERR_HIP;

@@ -32,6 +32,7 @@ struct Dims {
   double cut, cutn;   // c, c_n
   int cap_nbr, cap_upd;
   int prec;
+  int split;          // GEMM sites using split bf16 operands (hybrid precision)
   FIRE_HOST_DEVICE int nsig(int s) const { return s == 0 ? nu : nd; }
 };
 

@@ -1,0 +1,289 @@
+// Nonlocal pseudopotential energy by angular quadrature of psi ratios
+// (Methods, effective core potential; low-rank wave-function updates):
+//   V_NL = sum_{i, I: |r_i - R_I| < r_max} sum_l v_l(r_iI) (2l+1)
+//          (1/12) sum_q P_l(rhat_iI . Q e_q) psi(r_i -> R_I + r_iI Q e_q) / psi
+// with the 12 icosahedron vertices e_q.  Every ratio is one single-electron
+// update (neighbour recompute + det A), never a full re-evaluation.
+#include <vector>
+
+#include "laplacian.hpp"
+#include "update.hpp"
+
+namespace fire {
+
+#define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+constexpr int NQ = 12;
+constexpr int ECP_PMAX = 8;     // pseudo-atoms within r_max of one electron
+
+struct EcpTables {
+  int nchan;
+  int species[8], l[8], nterms[8];
+  double a[8][4], alpha[8][4];
+  double rmax;
+};
+
+static EcpTables tables(const fire_handle* h) {
+  EcpTables t{};
+  t.nchan = (int)h->ecp.size() < 8 ? (int)h->ecp.size() : 8;
+  for (int k = 0; k < t.nchan; ++k) {
+    const EcpChan& c = h->ecp[k];
+    t.species[k] = c.species; t.l[k] = c.l; t.nterms[k] = c.nterms;
+    for (int j = 0; j < 4; ++j) { t.a[k][j] = c.a[j]; t.alpha[k][j] = c.alpha[j]; }
+  }
+  t.rmax = h->ecp_rmax;
+  return t;
+}
+
+// icosahedron vertices: cyclic permutations of (0, +-1, +-phi), normalised
+FIRE_DEV void ico_vertex(int q, double v[3]) {
+  const double phi = 1.6180339887498948482, nrm = 1.0 / sqrt(1.0 + phi * phi);
+  const int cyc = q % 3, pair = q / 3;   // pair 0..3 -> the signs of (1, phi)
+  const double a = (pair & 2) ? -1.0 : 1.0, b = (pair & 1) ? -phi : phi;
+  double t[3];
+  if (cyc == 0) { t[0] = 0; t[1] = a; t[2] = b; }
+  else if (cyc == 1) { t[0] = a; t[1] = b; t[2] = 0; }
+  else { t[0] = b; t[1] = 0; t[2] = a; }
+  v[0] = t[0] * nrm; v[1] = t[1] * nrm; v[2] = t[2] * nrm;
+}
+
+FIRE_DEV bool is_ecp_species(const EcpTables& t, int sp) {
+  for (int k = 0; k < t.nchan; ++k)
+    if (t.species[k] == sp) return true;
+  return false;
+}
+
+// number of pseudo-atoms within r_max of electron e, per (e, w): cnt[e][w]
+__global__ void k_ecp_count(const Dims D, int W, const double* __restrict__ R, const double* __restrict__ Rn,
+                            const int* __restrict__ species, EcpTables t, int* __restrict__ cnt,
+                            int32_t* __restrict__ status) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)W * D.n) return;
+  const int w = (int)(q / D.n), e = (int)(q % D.n);
+  const double* r = R + q * 3;
+  int c = 0;
+  for (int m = 0; m < D.M; ++m) {
+    if (!is_ecp_species(t, species[m])) continue;
+    const double dx = r[0] - Rn[3 * m], dy = r[1] - Rn[3 * m + 1], dz = r[2] - Rn[3 * m + 2];
+    if (dx * dx + dy * dy + dz * dz < t.rmax * t.rmax) ++c;
+  }
+  if (c > ECP_PMAX) { atomicOr(status + w, FIRE_W_UPD_OVERFLOW); c = ECP_PMAX; }
+  cnt[(int64_t)e * W + w] = NQ * c;
+}
+
+// per electron e: exclusive scan over walkers of the job counts; tot[e]
+__global__ __launch_bounds__(1024) void k_ecp_scan(int W, const int* __restrict__ cnt, int* __restrict__ off,
+                                                   int* __restrict__ tot) {
+  __shared__ int part[1024];
+  const int e = blockIdx.x;
+  const int* c = cnt + (int64_t)e * W;
+  int* o = off + (int64_t)e * (W + 1);
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (W + nt - 1) / nt;
+  const int b = t * per, en = b + per < W ? b + per : W;
+  int s = 0;
+  for (int w = b; w < en; ++w) s += c[w];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < nt; ++k) { int v = part[k]; part[k] = acc; acc += v; }
+    o[W] = acc;
+    tot[e] = acc;
+  }
+  __syncthreads();
+  int a = part[t];
+  for (int w = b; w < en; ++w) { o[w] = a; a += c[w]; }
+}
+
+// jobs [j0, j0 + J) of electron e: walker, new position and quadrature weight
+__global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const double* __restrict__ R,
+                           const double* __restrict__ Rn, const int* __restrict__ species, EcpTables t,
+                           const double* __restrict__ quad_rot, const int* __restrict__ off, int* __restrict__ jw,
+                           double* __restrict__ rexp, double* __restrict__ cf) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int jg = j0 + j;
+  // walker: last w with off[w] <= jg
+  int lo = 0, hi = W - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (off[mid] <= jg) lo = mid; else hi = mid - 1;
+  }
+  const int w = lo;
+  const int loc = jg - off[w], p = loc / NQ, q = loc % NQ;
+  const double* r = R + ((int64_t)w * D.n + e) * 3;
+  int c = 0, I = -1;
+  for (int m = 0; m < D.M && I < 0; ++m) {
+    if (!is_ecp_species(t, species[m])) continue;
+    const double dx = r[0] - Rn[3 * m], dy = r[1] - Rn[3 * m + 1], dz = r[2] - Rn[3 * m + 2];
+    if (dx * dx + dy * dy + dz * dz < t.rmax * t.rmax) {
+      if (c == p) I = m;
+      ++c;
+    }
+  }
+  jw[j] = w;
+  if (I < 0) {   // cannot happen when the counts are consistent: a no-op job
+    rexp[3 * j] = r[0]; rexp[3 * j + 1] = r[1]; rexp[3 * j + 2] = r[2];
+    cf[j] = 0.0;
+    return;
+  }
+  const double dx = r[0] - Rn[3 * I], dy = r[1] - Rn[3 * I + 1], dz = r[2] - Rn[3 * I + 2];
+  const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+  double v[3], u[3];
+  ico_vertex(q, v);
+  if (quad_rot) {
+    const double* Q = quad_rot + (int64_t)w * 9;
+    for (int k = 0; k < 3; ++k) u[k] = Q[3 * k] * v[0] + Q[3 * k + 1] * v[1] + Q[3 * k + 2] * v[2];
+  } else {
+    u[0] = v[0]; u[1] = v[1]; u[2] = v[2];
+  }
+  rexp[3 * j] = Rn[3 * I] + rr * u[0];
+  rexp[3 * j + 1] = Rn[3 * I + 1] + rr * u[1];
+  rexp[3 * j + 2] = Rn[3 * I + 2] + rr * u[2];
+  const double cs = rr > 0 ? (dx * u[0] + dy * u[1] + dz * u[2]) / rr : 0.0;
+  double coef = 0.0;
+  for (int k = 0; k < t.nchan; ++k) {
+    if (t.species[k] != species[I]) continue;
+    double vl = 0.0;
+    for (int m = 0; m < t.nterms[k]; ++m) vl += t.a[k][m] * exp(-t.alpha[k][m] * rr * rr);
+    const double Pl = t.l[k] == 0 ? 1.0 : cs;
+    coef += vl * (2 * t.l[k] + 1) * Pl / NQ;
+  }
+  cf[j] = coef;
+}
+
+// contribution of each job: coefficient * psi'/psi with
+// psi'/psi = sum_d w_d prod_s det A_ds,  w_d = s_d e^{l_d} / psi
+__global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__ jw, const double* __restrict__ cf,
+                            const double* __restrict__ detA, const char* __restrict__ state, StateRec S,
+                            double* __restrict__ contrib) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int w = jw[j];
+  const char* rec = state + (int64_t)w * S.stride;
+  const double* ds = (const double*)(rec + S.dsign);
+  const double* dl = (const double*)(rec + S.dlog);
+  const double lp = *(const double*)(rec + S.lpsi), sp = *(const double*)(rec + S.spsi);
+  const double* dA = detA + (int64_t)j * D.K * 4;
+  double r = 0.0;
+  for (int k = 0; k < D.K; ++k) {
+    const double sg = ds[2 * k] * ds[2 * k + 1] * sp * dA[4 * k] * dA[4 * k + 2];
+    if (sg != 0.0) r += sg * exp(dl[2 * k] + dl[2 * k + 1] - lp + dA[4 * k + 1] + dA[4 * k + 3]);
+  }
+  contrib[j0 + j] = cf[j] * r;
+}
+
+__global__ void k_ecp_reduce(int W, const int* __restrict__ off, const double* __restrict__ contrib,
+                             double* __restrict__ vnl) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  double s = 0.0;
+  for (int j = off[w]; j < off[w + 1]; ++j) s += contrib[j];
+  vnl[w] += s;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+struct EcpLayout {
+  int Jc;
+  size_t cnt, off, tot, jw, rexp, cf, contrib, upd;
+  size_t total;
+};
+
+static EcpLayout ecp_layout(const fire_handle* h, int W) {
+  EcpLayout L{};
+  const Dims& D = h->D;
+  L.Jc = W < 8192 ? (W > 256 ? W : 256) : 8192;
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
+  L.cnt = take((size_t)D.n * W * 4);
+  L.off = take((size_t)D.n * (W + 1) * 4);
+  L.tot = take((size_t)D.n * 4);
+  L.jw = take((size_t)L.Jc * 4);
+  L.rexp = take((size_t)L.Jc * 3 * 8);
+  L.cf = take((size_t)L.Jc * 8);
+  L.contrib = take((size_t)W * ECP_PMAX * NQ * 8);
+  L.upd = o;
+  o += upd_layout(h, L.Jc).total;
+  L.total = align_up(o);
+  return L;
+}
+
+size_t ecp_ws_bytes(const fire_handle* h, int W) { return h->ecp.empty() ? 0 : ecp_layout(h, W).total; }
+
+template <typename T>
+static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* state, char* ws,
+                           const double* quad_rot, double* vnl, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  Net<T> P = make_net<T>(h);
+  const EcpLayout L = ecp_layout(h, W);
+  const EcpTables tb = tables(h);
+  const UpdLayout U = upd_layout(h, L.Jc);
+  int* cnt = (int*)(ws + L.cnt);
+  int* off = (int*)(ws + L.off);
+  int* tot = (int*)(ws + L.tot);
+  int* jw = (int*)(ws + L.jw);
+  double* rexp = (double*)(ws + L.rexp);
+  double* cf = (double*)(ws + L.cf);
+  double* contrib = (double*)(ws + L.contrib);
+  char* uws = ws + L.upd;
+  const int* sp_dev = (const int*)((const char*)h->params + h->pl.species);
+  hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, st, vnl, (int64_t)W, 0.0);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_ecp_count, dim3((unsigned)(((int64_t)W * D.n + 255) / 256)), dim3(256), 0, st, D, W, R, P.Rn,
+                     sp_dev, tb, cnt, status);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_ecp_scan, dim3(D.n), dim3(1024), 0, st, W, (const int*)cnt, off, tot);
+  CHECK(hipGetLastError());
+  std::vector<int> htot(D.n);
+  CHECK(hipMemcpyAsync(htot.data(), tot, (size_t)D.n * 4, hipMemcpyDeviceToHost, st));
+  CHECK(hipStreamSynchronize(st));
+  for (int e = 0; e < D.n; ++e) {
+    const int Te = htot[e];
+    const int* offe = off + (int64_t)e * (W + 1);
+    for (int j0 = 0; j0 < Te; j0 += L.Jc) {
+      const int J = Te - j0 < L.Jc ? Te - j0 : L.Jc;
+      hipLaunchKernelGGL(k_ecp_jobs, dim3((J + 255) / 256), dim3(256), 0, st, D, W, e, j0, J, R, P.Rn, sp_dev, tb,
+                         quad_rot, offe, jw, rexp, cf);
+      CHECK(hipGetLastError());
+      Jobs jb{};
+      jb.J = J;
+      jb.Jcap = L.Jc;
+      jb.jw = jw;
+      jb.rexp = rexp;
+      CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, st));
+      hipLaunchKernelGGL(k_ecp_ratio, dim3((J + 255) / 256), dim3(256), 0, st, D, J, j0, (const int*)jw,
+                         (const double*)cf, (const double*)(uws + U.detA), (const char*)state, S, contrib);
+      CHECK(hipGetLastError());
+    }
+    if (Te > 0) {
+      hipLaunchKernelGGL(k_ecp_reduce, dim3((W + 255) / 256), dim3(256), 0, st, W, offe, (const double*)contrib, vnl);
+      CHECK(hipGetLastError());
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t ecp_into(const fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,
+                    double* vnl, int32_t* status, hipStream_t st) {
+  if (!update_fits(h)) return hipErrorInvalidValue;
+  return h->tsize == 8 ? ecp_impl<double>(h, W, R, state, ws, quad_rot, vnl, status, st)
+                       : ecp_impl<float>(h, W, R, state, ws, quad_rot, vnl, status, st);
+}
+
+hipError_t ecp_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,
+                    double* v_nl, int32_t* status, hipStream_t s) {
+  CHECK(fill_i32(status, W, 0, s));
+  if (h->ecp.empty()) {
+    hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, s, v_nl, (int64_t)W, 0.0);
+    return hipGetLastError();
+  }
+  return ecp_into(h, W, R, state, ws, quad_rot, v_nl, status, s);
+}
+
+}  // namespace fire

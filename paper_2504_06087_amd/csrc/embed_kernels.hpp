@@ -5,6 +5,48 @@
 namespace fire {
 
 // ---------------------------------------------------------------------------
+// a1: neighbour lists.  One workgroup per walker; electron i lists every
+// j != i with |r_i - r_j| <= c, same-spin first, then opposite spin.
+// ---------------------------------------------------------------------------
+static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
+                                             double cut2, int cap, int16_t* __restrict__ idx,
+                                             int32_t* __restrict__ cnt, int32_t* status) {
+  __shared__ double pos[256 * 3];
+  int w = blockIdx.x;
+  const double* Rw = R + (int64_t)w * n * 3;
+  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) pos[t] = Rw[t];
+  __syncthreads();
+  int i = threadIdx.x;
+  if (i >= n) return;
+  double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) atomicOr(status + w, FIRE_W_NONFINITE);
+  int16_t* out = idx + ((int64_t)w * n + i) * cap;
+  int si = i < nu ? 0 : 1;
+  int c[2] = {0, 0};
+  int k = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      int sj = j < nu ? 0 : 1;
+      if ((sj == si) != (pass == 0)) continue;
+      double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+      if (dx * dx + dy * dy + dz * dz <= cut2) {
+        if (k < cap) out[k] = (int16_t)j;
+        ++k;
+        ++c[pass];
+      }
+    }
+  }
+  if (k > cap) {
+    atomicOr(status + w, FIRE_W_NBR_OVERFLOW);
+    c[0] = c[0] < cap ? c[0] : cap;
+    c[1] = cap - c[0] < c[1] ? cap - c[0] : c[1];
+  }
+  cnt[((int64_t)w * n + i) * 2 + 0] = c[0];
+  cnt[((int64_t)w * n + i) * 2 + 1] = c[1];
+}
+
+// ---------------------------------------------------------------------------
 // Pair features shared by the electron-nucleus and electron-electron filters:
 //   out[0..3]  rescaled features log(1+r)/r * [r, dx, dy, dz]
 //   out[4..4+h2) second hidden layer SiLU(SiLU(e W1 + b1) W2 + b2)

@@ -23,48 +23,6 @@ hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// a1: neighbour lists.  One workgroup per walker; electron i lists every
-// j != i with |r_i - r_j| <= c, same-spin first, then opposite spin.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
-                                             double cut2, int cap, int16_t* __restrict__ idx,
-                                             int32_t* __restrict__ cnt, int32_t* status) {
-  __shared__ double pos[256 * 3];
-  int w = blockIdx.x;
-  const double* Rw = R + (int64_t)w * n * 3;
-  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) pos[t] = Rw[t];
-  __syncthreads();
-  int i = threadIdx.x;
-  if (i >= n) return;
-  double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-  if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) atomicOr(status + w, FIRE_W_NONFINITE);
-  int16_t* out = idx + ((int64_t)w * n + i) * cap;
-  int si = i < nu ? 0 : 1;
-  int c[2] = {0, 0};
-  int k = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < n; ++j) {
-      if (j == i) continue;
-      int sj = j < nu ? 0 : 1;
-      if ((sj == si) != (pass == 0)) continue;
-      double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
-      if (dx * dx + dy * dy + dz * dz <= cut2) {
-        if (k < cap) out[k] = (int16_t)j;
-        ++k;
-        ++c[pass];
-      }
-    }
-  }
-  if (k > cap) {
-    atomicOr(status + w, FIRE_W_NBR_OVERFLOW);
-    c[0] = c[0] < cap ? c[0] : cap;
-    c[1] = cap - c[0] < c[1] ? cap - c[0] : c[1];
-  }
-  cnt[((int64_t)w * n + i) * 2 + 0] = c[0];
-  cnt[((int64_t)w * n + i) * 2 + 1] = c[1];
-}
-
-// ---------------------------------------------------------------------------
 // a4: m_i = sum_alpha sum_{j in N^alpha_i} Gamma^alpha(e_ij) *
 //           SiLU(a^alpha_i + b^alpha_j + ebar_ij W_e^alpha + b^alpha)
 // h1_i = h0_i + m_i.  proj rows hold [a^par | a^anti | b^par | b^anti].
@@ -260,7 +218,6 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
   const Dims& D = h->D;
   const StateRec& S = h->st;
   const WsLayout L = ws_forward(h, W);
-  const int kind = gemm_kind(D.prec);
   const int64_t rows = (int64_t)W * D.n;
   const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
   int16_t* nidx = (int16_t*)(ws + L.nbr_idx);
@@ -282,7 +239,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.A = y; g.amap = rows_dense(D.d); g.Bt = (const char*)h->params + h->pl.Wvg_t; g.ldb = D.d;
     g.bias = P.b_vg; g.C = ug; g.cmap = rows_dense(2 * D.d); g.ccol = cols_dense();
     g.M = (int)rows; g.N = 2 * D.d; g.K = D.d; g.act = ACT_NONE;
-    CHECK(gemm(kind, g, s));
+    CHECK(gemm_site(h, SITE_EMB, g, s));
   }
   hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * D.d + 255) / 256)), dim3(256), 0, s, ug, y, rows, D.d);
   CHECK(hipGetLastError());
@@ -291,7 +248,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.A = y; g.amap = rows_dense(D.d); g.Bt = (const char*)h->params + h->pl.Wo_t; g.ldb = D.d;
     g.bias = P.b_o; g.C = state + S.h0; g.cmap = RowMap{D.n, srecT, D.d}; g.ccol = cols_dense();
     g.M = (int)rows; g.N = D.d; g.K = D.d;
-    CHECK(gemm(kind, g, s));
+    CHECK(gemm_site(h, SITE_EMB, g, s));
   }
   // node projections [a^par | a^anti | b^par | b^anti] = h0 W_proj
   {
@@ -299,7 +256,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.A = state + S.h0; g.amap = RowMap{D.n, srecT, D.d}; g.Bt = (const char*)h->params + h->pl.Wproj_t;
     g.ldb = D.d; g.C = state + S.proj; g.cmap = RowMap{D.n, srecT, 4 * D.d}; g.ccol = cols_dense();
     g.M = (int)rows; g.N = 4 * D.d; g.K = D.d;
-    CHECK(gemm(kind, g, s));
+    CHECK(gemm_site(h, SITE_EMB, g, s));
   }
   hipLaunchKernelGGL(k_msg<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, nidx, ncnt,
                      state, S.stride, S.h0, S.proj, S.m, hA);
@@ -313,7 +270,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.Bt = (const char*)h->params + h->pl.mlp_t + (size_t)k * D.d * D.d * h->gsize; g.ldb = D.d;
     g.bias = P.mlp_b + (int64_t)k * D.d; g.C = hout; g.cmap = rows_dense(D.d); g.ccol = cols_dense();
     g.M = (int)rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU;
-    CHECK(gemm(kind, g, s));
+    CHECK(gemm_site(h, SITE_EMB, g, s));
     T* t = hin; hin = hout; hout = t;
   }
   // envelopes and orbitals per spin block
@@ -331,7 +288,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.Bt = (const char*)h->params + (sp == 0 ? h->pl.pi0 : h->pl.pi1); g.ldb = D.B;
     g.C = state + S.env + phi_block_off(D, sp) * sizeof(T); g.cmap = smap; g.ccol = scol;
     g.M = (int)mrows; g.N = D.K * N; g.K = D.B;
-    CHECK(gemm(kind, g, s));
+    CHECK(gemm_site(h, SITE_ORB, g, s));
     // Phi[w][det][sp][i][l] = (h_i . W[:, (det,l)]) * env
     GemmArgs o{};
     o.A = hin + (int64_t)e0 * D.d; o.amap = RowMap{N, (int64_t)D.n * D.d, D.d};
@@ -341,7 +298,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     o.cmap = smap;
     o.ccol = scol;
     o.M = (int)mrows; o.N = D.K * N; o.K = D.d;
-    CHECK(gemm(kind, o, s));
+    CHECK(gemm_site(h, SITE_ORB, o, s));
   }
   return hipSuccess;
 }

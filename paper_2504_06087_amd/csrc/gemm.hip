@@ -29,6 +29,10 @@ template <> struct MK<MMA_BF16> {
   using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
   static constexpr int BM = 128, BN = 128, PAD = 8;
 };
+template <> struct MK<MMA_BF16X3> {
+  using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
+  static constexpr int BM = 128, BN = 128, PAD = 8;
+};
 
 FIRE_DEV int64_t roff(const RowMap& m, int64_t r) { return (r / m.rpg) * m.gstride + (r % m.rpg) * m.rstride; }
 FIRE_DEV int64_t coff(const ColMap& m, int64_t c) { return (c / m.cpg) * m.cgstride + (c % m.cpg); }
@@ -68,8 +72,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int CA = BM * BK / 4 / 256;   // 4-element chunks per thread (A)
   constexpr int CB = BN * BK / 4 / 256;
+  constexpr bool SPLIT = KIND == MMA_BF16X3;
   __shared__ __attribute__((aligned(16))) TL As[BM * LDK];
   __shared__ __attribute__((aligned(16))) TL Bs[BN * LDK];
+  __shared__ __attribute__((aligned(16))) TL Asl[SPLIT ? BM * LDK : 8];
+  __shared__ __attribute__((aligned(16))) TL Bsl[SPLIT ? BN * LDK : 8];
 
   const int tid = threadIdx.x;
   const int nct = (g.N + BN - 1) / BN;
@@ -100,6 +107,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
     arow[t] = A + (aval[t] ? roff(g.amap, r) : 0);
   }
   const TB* brow[CB];
+  const TB* browl[CB];
   bool bval[CB];
   int bk[CB], br[CB];
 #pragma unroll
@@ -110,6 +118,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
     int64_t c = col0 + br[t];
     bval[t] = c < g.N;
     brow[t] = Bt + (bval[t] ? c * g.ldb : 0);
+    browl[t] = SPLIT ? (const TB*)g.Bt_lo + (bval[t] ? c * g.ldb : 0) : brow[t];
   }
 
   Acc acc[TM][TN];
@@ -122,11 +131,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
 
   TA ra[CA][4];
   TB rb[CB][4];
+  TB rbl[SPLIT ? CB : 1][4];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < CA; ++t) load4<TA>(arow[t], k0 + ak[t], g.K, aval[t], vecA, ra[t]);
 #pragma unroll
     for (int t = 0; t < CB; ++t) load4<TB>(brow[t], k0 + bk[t], g.K, bval[t], vecB, rb[t]);
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int t = 0; t < CB; ++t) load4<TB>(browl[t], k0 + bk[t], g.K, bval[t], vecB, rbl[t]);
+    }
   };
 
   const int lane = tid & 63, wave = tid >> 6;
@@ -136,18 +150,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   const int nk = (g.K + BK - 1) / BK;
   gload(0);
   for (int kt = 0; kt < nk; ++kt) {
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int t = 0; t < CA; ++t)
+      for (int t = 0; t < CA; ++t)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[ar[t] * LDK + ak[t] + e] = to_lds<TL, TA>(ra[t][e]);
+        for (int e = 0; e < 4; ++e) {
+          const float a = (float)ra[t][e];
+          const bf16_t hi = f2bf(a);
+          As[ar[t] * LDK + ak[t] + e] = hi;
+          Asl[ar[t] * LDK + ak[t] + e] = f2bf(a - bf2f(hi));
+        }
 #pragma unroll
-    for (int t = 0; t < CB; ++t)
+      for (int t = 0; t < CB; ++t)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[br[t] * LDK + bk[t] + e] = to_lds<TL, TB>(rb[t][e]);
+        for (int e = 0; e < 4; ++e) {
+          Bs[br[t] * LDK + bk[t] + e] = (bf16_t)rb[t][e];
+          Bsl[br[t] * LDK + bk[t] + e] = (bf16_t)rbl[t][e];
+        }
+    } else {
+#pragma unroll
+      for (int t = 0; t < CA; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[ar[t] * LDK + ak[t] + e] = to_lds<TL, TA>(ra[t][e]);
+#pragma unroll
+      for (int t = 0; t < CB; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[br[t] * LDK + bk[t] + e] = to_lds<TL, TB>(rb[t][e]);
+    }
     __syncthreads();
     if (kt + 1 < nk) gload((kt + 1) * BK);
 
-    if constexpr (KIND == MMA_BF16) {
+    if constexpr (KIND == MMA_BF16 || KIND == MMA_BF16X3) {
       bf16x8v af[TM], bfr[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -155,6 +188,23 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         bfr[j] = *reinterpret_cast<const bf16x8v*>(&Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
+      if constexpr (SPLIT) {
+        bf16x8v afl[TM], bfl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          afl[i] = *reinterpret_cast<const bf16x8v*>(&Asl[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bfl[j] = *reinterpret_cast<const bf16x8v*>(&Bsl[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
+        // small cross terms first, then the leading product
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+          }
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -205,7 +255,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
       for (int e = 0; e < 4; ++e) {
         int64_t r = row0 + wm * (BM / 2) + i * 16 + (KIND == MMA_F64 ? 4 * e + lg : 4 * lg + e);
         if (r >= g.M) continue;
-        TC v = (TC)acc[i][j][e] + bc;
+        TC v = (TC)acc[i][j][e] + ((g.bias_period > 0 && r % g.bias_period) ? TC(0) : bc);
         if (g.act == ACT_SILU) v = silu_(v);
         if (aux) v *= aux[roff(g.xmap, r) + xco];
         TC* dst = C + roff(g.cmap, r) + cco;
@@ -233,6 +283,7 @@ hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s) {
     case MMA_F64: return launch<MMA_F64>(g, s);
     case MMA_F32: return launch<MMA_F32>(g, s);
     case MMA_BF16: return launch<MMA_BF16>(g, s);
+    case MMA_BF16X3: return launch<MMA_BF16X3>(g, s);
   }
   return hipErrorInvalidValue;
 }

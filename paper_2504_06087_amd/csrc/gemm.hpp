@@ -16,7 +16,7 @@ inline RowMap rows_dense(int64_t ld) { return RowMap{1, ld, 0}; }
 inline ColMap cols_dense() { return ColMap{1ll << 40, 0}; }
 
 enum GemmAct { ACT_NONE = 0, ACT_SILU = 1 };
-enum GemmKind { MMA_F64 = 0, MMA_F32 = 1, MMA_BF16 = 2 };
+enum GemmKind { MMA_F64 = 0, MMA_F32 = 1, MMA_BF16 = 2, MMA_BF16X3 = 3 };
 
 // C[r][c] = epi( sum_k A[r][k] * Bt[c][k] )
 //   epi: v (+ bias[c]) -> act -> (* aux[r][c]) -> (+= C[r][c] if accumulate) -> store
@@ -38,12 +38,16 @@ struct GemmArgs {
   int act;
   int accumulate;
   const int* Mdev;    // optional device row count (<= M); rows beyond it are skipped
+  int bias_period;    // > 0: bias only on rows r with r % bias_period == 0
+  const void* Bt_lo;  // MMA_BF16X3: low bf16 part of Bt (Bt holds the high part)
 };
 
 // Launch on stream; kind fixes the element types:
 //   MMA_F64: A double, Bt double, C double
 //   MMA_F32: A float,  Bt float,  C float
 //   MMA_BF16: A float, Bt bf16,   C float   (A rounded to bf16 when staged)
+//   MMA_BF16X3: A float, Bt bf16 hi + lo, C float: A and B are split into
+//     bf16 high and low parts and C = Ah Bh + Ah Bl + Al Bh (FP32 accumulate)
 hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s);
 
 }  // namespace fire

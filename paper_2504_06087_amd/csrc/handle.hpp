@@ -34,8 +34,10 @@ struct ParamsLayout {
   size_t Wvg_t, Wo_t, Wproj_t, mlp_t, orb_t0, orb_t1, pi0, pi1;
   // GEMM operands in the adjoint orientation (B = W^T): Bt = W, type G
   size_t Wvg_n, Wo_n, Wproj_n, mlp_n, orb_n0, orb_n1;
+  // low bf16 parts of every GEMM operand above live at (offset + lo_delta)
+  size_t lo_delta;
   // molecule
-  size_t Rn, Zn, ppw, ntype;
+  size_t Rn, Zn, ppw, ntype, species;
   size_t total;
 };
 
@@ -84,6 +86,20 @@ hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, 
                         int32_t* status, hipStream_t s);
 
 inline int gemm_kind(int prec) { return prec == FIRE_FP64 ? MMA_F64 : (prec == FIRE_FP32 ? MMA_F32 : MMA_BF16); }
+
+// GEMM call sites (bits of Dims::split)
+enum GemmSite { SITE_EMB = 1, SITE_ORB = 2, SITE_JET = 4 };
+
+// Launch a GEMM whose Bt lies in the packed params buffer, choosing the MFMA
+// kind of the handle's precision for this site.
+inline hipError_t gemm_site(const fire_handle* h, int site, GemmArgs g, hipStream_t s) {
+  int kind = gemm_kind(h->D.prec);
+  if (kind == MMA_BF16 && (h->D.split & site)) {
+    kind = MMA_BF16X3;
+    g.Bt_lo = (const char*)g.Bt + h->pl.lo_delta;
+  }
+  return gemm(kind, g, s);
+}
 
 static inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

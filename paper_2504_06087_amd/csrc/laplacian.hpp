@@ -1,0 +1,23 @@
+// Local-energy and pseudopotential drivers.
+#pragma once
+#include "paths.hpp"
+
+namespace fire {
+
+struct LapLayout {
+  int Wc;
+  int64_t rowcap[2];
+  size_t nidx, ncnt, joff, jtot, yj, ugj, h0j, projj, hval, zval, basisj;
+  size_t jetA[2], jetB[2], envj[2], oval[2], dphi[2], gd, hd;
+  size_t total;
+};
+LapLayout lap_layout(const fire_handle* h, int W);
+size_t lap_ws_bytes(const fire_handle* h, int W);
+size_t lap_lds_needed(const fire_handle* h);
+
+size_t ecp_ws_bytes(const fire_handle* h, int W);
+// V_NL[w] for all walkers into vnl (overwritten); ws: scratch of ecp_ws_bytes
+hipError_t ecp_into(const fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,
+                    double* vnl, int32_t* status, hipStream_t st);
+
+}  // namespace fire

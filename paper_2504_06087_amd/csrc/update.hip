@@ -529,8 +529,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   const Dims& D = h->D;
   const StateRec& S = h->st;
   const int W = jb.J;
-  const UpdLayout L = upd_layout(h, W);
-  const int kind = gemm_kind(D.prec);
+  const UpdLayout L = upd_layout(h, jb.Jcap > 0 ? jb.Jcap : jb.J);
   const int se = e < D.nu ? 0 : 1;
   const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
   double* rnew = (double*)(ws + L.rnew);
@@ -557,7 +556,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     GemmArgs g{};
     g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wvg_t; g.ldb = D.d; g.bias = P.b_vg;
     g.C = ug; g.cmap = rows_dense(2 * D.d); g.ccol = cols_dense(); g.M = W; g.N = 2 * D.d; g.K = D.d;
-    CHECK(gemm(kind, g, st));
+    CHECK(gemm_site(h, SITE_EMB, g, st));
   }
   hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)(((int64_t)W * D.d + 255) / 256)), dim3(256), 0, st, ug, y,
                      (int64_t)W, D.d);
@@ -566,11 +565,11 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     GemmArgs g{};
     g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wo_t; g.ldb = D.d; g.bias = P.b_o;
     g.C = h0new; g.cmap = rows_dense(D.d); g.ccol = cols_dense(); g.M = W; g.N = D.d; g.K = D.d;
-    CHECK(gemm(kind, g, st));
+    CHECK(gemm_site(h, SITE_EMB, g, st));
     GemmArgs p{};
     p.A = h0new; p.amap = rows_dense(D.d); p.Bt = P.Wproj_t; p.ldb = D.d;
     p.C = projnew; p.cmap = rows_dense(4 * D.d); p.ccol = cols_dense(); p.M = W; p.N = 4 * D.d; p.K = D.d;
-    CHECK(gemm(kind, p, st));
+    CHECK(gemm_site(h, SITE_EMB, p, st));
   }
   T* hs[2][2];
   T* ms[2];
@@ -594,7 +593,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     GemmArgs g{};
     g.A = basis; g.amap = rows_dense(D.B); g.Bt = se == 0 ? P.pi0 : P.pi1; g.ldb = D.B;
     g.C = envnew; g.cmap = rows_dense((int64_t)D.K * N); g.ccol = cols_dense(); g.M = W; g.N = D.K * N; g.K = D.B;
-    CHECK(gemm(kind, g, st));
+    CHECK(gemm_site(h, SITE_ORB, g, st));
   }
   for (int s = 0; s < 2; ++s) {
     const int N = D.nsig(s);
@@ -609,7 +608,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
       g.Bt = (const char*)P.mlp_t + (size_t)k * D.d * D.d * h->gsize; g.ldb = D.d;
       g.bias = P.mlp_b + (int64_t)k * D.d; g.C = hout; g.cmap = rows_dense(D.d); g.ccol = cols_dense();
       g.M = rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU; g.Mdev = Mdev;
-      CHECK(gemm(kind, g, st));
+      CHECK(gemm_site(h, SITE_EMB, g, st));
       T* t = hin; hin = hout; hout = t;
     }
     T* oseg = (T*)(ws + L.oseg[s]);
@@ -617,7 +616,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
     o.C = oseg; o.cmap = rows_dense((int64_t)D.K * N); o.ccol = cols_dense();
     o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
-    CHECK(gemm(kind, o, st));
+    CHECK(gemm_site(h, SITE_ORB, o, st));
     const int64_t tot = (int64_t)rows * D.K * N;
     if (h->isize == 8) {
       hipLaunchKernelGGL((k_dphi<T, double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e,

@@ -13,6 +13,7 @@ constexpr int WB_RB = 16;   // rows of G per LDS block in the Woodbury kernel
 // *Jdev (when set) are inactive.
 struct Jobs {
   int J;
+  int Jcap;            // workspace layout capacity (>= J); 0 means J
   const int* Jdev;
   const int* jw;
   const double* rexp;

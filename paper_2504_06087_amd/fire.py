@@ -44,7 +44,8 @@ class FireModelDesc(ctypes.Structure):
                 ("n_env", ctypes.c_int), ("n_gauss", ctypes.c_int), ("edge_h1", ctypes.c_int),
                 ("edge_h2", ctypes.c_int), ("n_nuc_types", ctypes.c_int), ("cutoff", ctypes.c_double),
                 ("cutoff_nuc", ctypes.c_double), ("precision", ctypes.c_int), ("max_walkers", ctypes.c_int),
-                ("cap_nbr", ctypes.c_int), ("cap_upd", ctypes.c_int), ("refresh_every", ctypes.c_int)]
+                ("cap_nbr", ctypes.c_int), ("cap_upd", ctypes.c_int), ("refresh_every", ctypes.c_int),
+                ("bf16_split", ctypes.c_int)]
 
 
 class FireParamEntry(ctypes.Structure):
@@ -114,7 +115,7 @@ class Fire:
 
     def __init__(self, system, model, precision: str = "fp64", max_walkers: int = 1024,
                  cap_nbr: Optional[int] = None, cap_upd: Optional[int] = None, refresh_every: int = 50,
-                 device: str = "cuda"):
+                 device: str = "cuda", bf16_split: int = 0):
         lib = load()
         self.system, self.model, self.precision = system, model, precision
         self.device = torch.device(device)
@@ -147,7 +148,7 @@ class Fire:
         md = FireModelDesc(model.width, model.mlp_layers, model.n_det, model.n_env, model.n_gauss,
                            int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
                            float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], int(max_walkers),
-                           self.cap_nbr, self.cap_upd, int(refresh_every))
+                           self.cap_nbr, self.cap_upd, int(refresh_every), int(bf16_split))
         self.max_walkers = max_walkers
         hd = ctypes.c_void_p()
         _check(lib.fire_create(ctypes.byref(sd), ctypes.byref(md), ctypes.byref(hd)), "fire_create")

@@ -36,3 +36,24 @@ def setup(cid, W, precision=None, model_kw=None, system_fn=None, **fire_kw):
 
 def dev(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def small_polyene(W, width=32, n_det=2, n_env=2, ecp=False, seed=7, cutoff=5.0):
+    """The C12H14 geometry with a narrow network, so the oracle's autodiff
+    Laplacian and full-recompute quadrature stay fast."""
+    R, sp = wl.polyene_c12h14()
+    rng = np.random.default_rng(seed)
+    s = wl.make_system("C12H14", R, sp, pseudo_c=True, nonlocal_ecp=ecp, ecp_rng=rng)
+    m = wl.make_model(s, width=width, mlp_layers=2, n_det=n_det, n_env=n_env, cutoff=cutoff, cutoff_nuc=20.0)
+    p = wl.init_params(s, m, rng)
+    return s, m, p, wl.init_walkers(s, W, rng)
+
+
+def setup_custom(s, m, p, R, precision, **fire_kw):
+    from oracle import Oracle
+    from paper_2504_06087_amd import fire
+    W = R.shape[0]
+    F = fire.Fire(s, m, precision, max_walkers=W, **fire_kw)
+    F.set_params(p)
+    state, ws = F.buffers(W)
+    return F, Oracle(s, m, p), state, ws
