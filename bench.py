@@ -1,0 +1,199 @@
+"""Throughput of the FiRE hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of walkers of the
+180-electron C42H12 flake (4096 walkers, width 256, 3 layers, 16
+determinants, c = 5 bohr, nonlocal pseudopotential on C):
+  full evaluation of log|psi| (neighbours, embeddings, orbitals, FP64 LU),
+  one Metropolis sweep of single-electron moves by low-rank updates,
+  the local energy (sparse forward Laplacian, potential, nonlocal
+  pseudopotential quadrature by low-rank ratios),
+  the parameter gradient of sum_w c_w log|psi_w| (when available).
+The BF16/FP64-hybrid path is timed, then the same step in plain FP32.
+
+Prints one JSON line.  Inputs are seeded synthetic data resident in HBM when
+the timed region starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "local energies/s + MCMC walker-steps/s @180 e⁻, BF16-hybrid vs FP32 plain"
+HBM_PEAK = 8.0e12
+PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--walkers", type=int, default=4096)
+    ap.add_argument("--split", type=int, default=7, help="split-bf16 GEMM sites of the hybrid precision")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-plain comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-grad", action="store_true")
+    return ap.parse_args()
+
+
+def run_precision(prec, split, W, steps, warmup, want_grad, profile):
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    work = wl.config(3, walkers=W)
+    s, m, p, R0 = work.systems[0], work.model, work.params[0], work.R[0]
+    F = fire.Fire(s, m, prec, max_walkers=W, cap_nbr=48, cap_upd=64, refresh_every=50, bf16_split=split)
+    F.set_params(p)
+    state, ws = F.buffers(W)
+    R = torch.tensor(R0, dtype=torch.float64, device="cuda")
+    Q = torch.tensor(wl.haar_rotations(W, np.random.default_rng(7)), device="cuda")
+    n = s.n_el
+    nsw = steps + warmup + 1
+    xi, u = wl.noise_for(work, nsw, W)
+    xi = torch.tensor(xi, device="cuda")
+    u = torch.tensor(u, device="cuda")
+    coeff = torch.full((W,), 1.0 / W, dtype=torch.float64, device="cuda")
+    nacc = torch.zeros(W, dtype=torch.int32, device="cuda")
+    # 10 burn-in proposals per electron are not timed: start from one sweep
+    F.eval_logpsi(R, state, ws)
+    F.mcmc_sweep(R, state, ws, 1, work.step, xi[0:1].contiguous(), u[0:1].contiguous(), nacc)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ph = {"eval": 0.0, "sweep": 0.0, "local_energy": 0.0, "grad": 0.0}
+    acc0 = None
+    have_grad = want_grad
+    last_e = None
+    for it in range(warmup + steps):
+        timed = it >= warmup
+        if timed and acc0 is None:
+            acc0 = nacc.clone()
+            if profile:
+                F.profile_begin()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        F.eval_logpsi(R, state, ws)
+        ev[1].record(stream)
+        k = 1 + it
+        F.mcmc_sweep(R, state, ws, 1, work.step, xi[k:k + 1].contiguous(), u[k:k + 1].contiguous(), nacc)
+        ev[2].record(stream)
+        e, parts, _, st = F.local_energy(R, state, ws, Q)
+        ev[3].record(stream)
+        if have_grad:
+            try:
+                F.grad_params(R, state, ws, coeff)
+            except fire.FireError:
+                have_grad = False
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        if timed:
+            ph["eval"] += ev[0].elapsed_time(ev[1])
+            ph["sweep"] += ev[1].elapsed_time(ev[2])
+            ph["local_energy"] += ev[2].elapsed_time(ev[3])
+            ph["grad"] += ev[3].elapsed_time(ev[4])
+            last_e = e
+    prof = F.profile_end() if profile else None
+    acc_rate = float((nacc - acc0).sum().item()) / (steps * W * n)
+    ph = {k: v / steps for k, v in ph.items()}
+    e_np = last_e.cpu().numpy()
+    out = dict(phases_ms=ph, ms_per_step=sum(ph.values()), acceptance=acc_rate, have_grad=have_grad,
+               e_loc_mean=float(np.nanmean(e_np)), e_loc_nan=int(np.isnan(e_np).sum()))
+    out["local_energies_per_s"] = W / (ph["local_energy"] / 1e3)
+    out["walker_steps_per_s"] = W * n / (ph["sweep"] / 1e3)
+    out["walkers_per_s"] = W / (out["ms_per_step"] / 1e3)
+    out["prof"] = prof
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: one walker's forward pass, gradient, 12 of the 540 Hessian
+    diagonal entries and 24 pseudopotential ratios, scaled per walker."""
+    import torch
+    import workloads as wl
+    from oracle import Oracle
+
+    torch.set_num_threads(os.cpu_count() or 1)
+    work = wl.config(3, walkers=1)
+    s, m, p, R = work.systems[0], work.model, work.params[0], work.R[0]
+    O = Oracle(s, m, p)
+    t0 = time.time()
+    O.log_psi(R)
+    t_fwd = time.time() - t0
+    coords = np.arange(0, 3 * s.n_el, 45)[:12]
+    t0 = time.time()
+    O.grad_lap(R, chunk=12, coords=coords)
+    t_lap = time.time() - t0
+    # pseudopotential ratios of this walker: count pairs, time 24 full recomputes
+    d = np.linalg.norm(R[0][:, None, :] - s.R_nuc[None], axis=-1)
+    pairs = int(((d < s.ecp_rmax) & (s.species[None] == 1)).sum())
+    Rq = np.repeat(R, 24, axis=0)
+    t0 = time.time()
+    O.log_psi(Rq)
+    t_24 = time.time() - t0
+    t_el = t_fwd + t_lap * (3 * s.n_el / len(coords)) + t_24 * (12 * pairs / 24.0)
+    return {
+        "value": 1.0 / t_el, "unit": "local energies/s", "cores": torch.get_num_threads(), "kind": "oracle",
+        "walker_steps_per_s": 1.0 / t_fwd,
+        "sample": (f"1 walker of the same workload: forward ({t_fwd:.2f}s), gradient + 12 of {3 * s.n_el} Hessian "
+                   f"diagonal entries ({t_lap:.2f}s, scaled x{3 * s.n_el / len(coords):.0f}), 24 of {12 * pairs} "
+                   f"quadrature ratios ({t_24:.2f}s, scaled); a Metropolis walker-step is one full forward"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (walkers shard across GPUs "
+                                   "without communication inside a step, see the design notes)"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    W = a.walkers
+    hyb = run_precision("bf16", a.split, W, a.steps, a.warmup, not a.no_grad, profile=True)
+    print(f"# hybrid: {json.dumps({k: v for k, v in hyb.items() if k != 'prof'})}", flush=True)
+    print(f"# hybrid GEMM profile: {hyb['prof']}", flush=True)
+    fp32 = None
+    if not a.no_fp32:
+        torch.cuda.empty_cache()
+        fp32 = run_precision("fp32", 0, W, a.steps, a.warmup, not a.no_grad, profile=False)
+        print(f"# fp32: {json.dumps({k: v for k, v in fp32.items() if k != 'prof'})}", flush=True)
+    # roofline of the dominant kernel: the MFMA GEMM of the hybrid path
+    prof = hyb["prof"] or {}
+    kind = max(prof, key=lambda k: prof[k][1]) if prof else "bf16x3"
+    la, ms, fl = prof.get(kind, (0, 0.0, 0.0))
+    achieved = fl / (ms / 1e3) if ms > 0 else 0.0
+    roof = {"bound": "mfma", "kernel": f"k_gemm<{kind}>", "achieved": achieved / 1e12, "peak": PEAK[kind] / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK[kind], "traffic": None,
+            "launches": la, "kernel_ms_per_step": ms / a.steps, "flops_per_step": fl / a.steps}
+    cpu = None if a.no_cpu else cpu_baseline()
+    line = {
+        "metric": METRIC, "value": hyb["walkers_per_s"], "unit": "local energies/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": hyb["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "C42H12 flake, 180 valence electrons (90 up, 90 down), 4096 walkers, width 256, "
+                               "3 MLP layers, 16 determinants, c = 5 bohr, c_n = 20 bohr, nonlocal l = 0,1 "
+                               "pseudopotential on C with a 12-point rule; step = full evaluation + 1 Metropolis "
+                               "sweep + local energy + parameter gradient",
+                   "walkers": W, "electrons": 180, "precision": f"bf16 hybrid (split sites {a.split}), FP64 LU"},
+        "walker_steps_per_s": hyb["walker_steps_per_s"],
+        "local_energies_per_s_el_phase": hyb["local_energies_per_s"],
+        "phases_ms": hyb["phases_ms"], "acceptance": hyb["acceptance"], "grad_included": hyb["have_grad"],
+        "fp32_plain": None if fp32 is None else {
+            "value": fp32["walkers_per_s"], "ms_per_step": fp32["ms_per_step"], "phases_ms": fp32["phases_ms"],
+            "walker_steps_per_s": fp32["walker_steps_per_s"],
+            "local_energies_per_s_el_phase": fp32["local_energies_per_s"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

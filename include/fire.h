@@ -192,6 +192,16 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
                              const double* coeff, double* grad, int32_t* status,
                              hipStream_t stream);
 
+/* Kernel timing for roofline reports.  Between fire_profile_begin and
+ * fire_profile_end every MFMA GEMM launched on `stream` by this handle is
+ * bracketed by HIP events, and its actual row count is written (by the
+ * kernel) into counters (device, int32 [capacity]).  fire_profile_end
+ * synchronises the stream and returns, per GEMM kind (0 f64, 1 f32, 2 bf16,
+ * 3 split bf16), the launch count, summed kernel time (ms) and algorithmic
+ * flops 2*M*N*K (host arrays of 4).  Launches beyond capacity are not timed. */
+fire_status fire_profile_begin(fire_handle* h, hipStream_t stream, int32_t* counters, int capacity);
+fire_status fire_profile_end(fire_handle* h, hipStream_t stream, int64_t* launches, double* ms, double* flops);
+
 /* OR of status[0..W-1] into *any_flags (host); synchronises the stream. */
 fire_status fire_sync_status(fire_handle* h, hipStream_t stream, const int32_t* status, int W,
                              int32_t* any_flags);

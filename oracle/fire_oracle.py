@@ -233,10 +233,11 @@ class Oracle:
                 vnn += float(self.Z[a] * self.Z[b] / torch.linalg.norm(self.Rn[a] - self.Rn[b]))
         return torch.stack([vee, ven, torch.full_like(vee, vnn)], 1)
 
-    def grad_lap(self, R, chunk: int = 64):
+    def grad_lap(self, R, chunk: int = 64, coords=None):
         """grad log|psi| [B,n,3] and Laplacian of log|psi| [B], by reverse mode
         for the gradient and forward-over-reverse for each diagonal Hessian
-        element (exact, no finite differences)."""
+        element (exact, no finite differences).  coords (optional) restricts
+        the Hessian trace to a subset of the 3n coordinates (timing samples)."""
         from torch.func import grad, jvp, vmap
         R = torch.as_tensor(R, dtype=DT)
         B, n = R.shape[:2]
@@ -248,11 +249,13 @@ class Oracle:
         grads = torch.zeros(B, n * 3, dtype=DT)
         laps = torch.zeros(B, dtype=DT)
         eye = torch.eye(3 * n, dtype=DT)
+        if coords is not None:
+            eye = eye[torch.as_tensor(coords, dtype=torch.long)]
         for b in range(B):
             x = R[b].reshape(-1).clone()
             grads[b] = g_fn(x)
             tot = 0.0
-            for c0 in range(0, 3 * n, chunk):
+            for c0 in range(0, eye.shape[0], chunk):
                 V = eye[c0:c0 + chunk]
                 hv = vmap(lambda v: jvp(g_fn, (x,), (v,))[1])(V)
                 tot = tot + (hv * V).sum()

@@ -96,6 +96,9 @@ static const ThetaEntry& th(const fire_handle* h, const char* name) {
     if (t.name == name) return t;
   return h->theta[0];
 }
+namespace fire {
+int64_t theta_offset(const fire_handle* h, const char* name) { return th(h, name).offset; }
+}
 
 static void build_layouts(fire_handle* h) {
   const Dims& D = h->D;
@@ -118,6 +121,7 @@ static void build_layouts(fire_handle* h) {
   L.Wvg_n = take((size_t)2 * D.d * D.d * G); L.Wo_n = take((size_t)D.d * D.d * G);
   L.Wproj_n = take((size_t)4 * D.d * D.d * G); L.mlp_n = take((size_t)D.L * D.d * D.d * G);
   L.orb_n0 = take((size_t)D.K * D.nu * D.d * G); L.orb_n1 = take((size_t)D.K * D.nd * D.d * G);
+  L.pi_n0 = take((size_t)D.K * D.nu * D.B * G); L.pi_n1 = take((size_t)D.K * D.nd * D.B * G);
   if (D.prec == FIRE_BF16_HYBRID) {
     const size_t region = o - L.Wvg_t;
     L.lo_delta = region;
@@ -306,6 +310,9 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
              Copy{D.d, D.K, D.nu, D.nu, (int64_t)D.d * D.nu, 1, (int64_t)D.K * D.nu, D.nu, 1}, s));
   DO(do_copy(G, b + L.orb_n1, src("orb_W_dn"),
              Copy{D.d, D.K, D.nd, D.nd, (int64_t)D.d * D.nd, 1, (int64_t)D.K * D.nd, D.nd, 1}, s));
+  // pi_n[b][(det,l)] = env_pi[(det,l)][b]
+  DO(do_copy(G, b + L.pi_n0, src("env_pi_up"), transposed(1, D.K * D.nu, D.B), s, LD));
+  DO(do_copy(G, b + L.pi_n1, src("env_pi_dn"), transposed(1, D.K * D.nd, D.B), s, LD));
   // molecule
   if (hipMemcpyAsync(b + L.Rn, h->Rn.data(), h->Rn.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(b + L.Zn, h->Z.data(), h->Z.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -375,6 +382,16 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
   if (!coeff || !grad) return FIRE_ERR_ARG;
   hipError_t e = grad_path(h, W, R, (char*)state, (char*)ws, coeff, grad, status, s);
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+fire_status fire_profile_begin(fire_handle* h, hipStream_t stream, int32_t* counters, int capacity) {
+  if (!h || !counters || capacity < 1) return FIRE_ERR_ARG;
+  return profile_begin(counters, capacity, stream) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+fire_status fire_profile_end(fire_handle* h, hipStream_t s, int64_t* launches, double* ms, double* flops) {
+  if (!h || !launches || !ms || !flops) return FIRE_ERR_ARG;
+  return profile_end(s, launches, ms, flops) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
 fire_status fire_sync_status(fire_handle* h, hipStream_t s, const int32_t* status, int W, int32_t* any_flags) {

@@ -152,7 +152,8 @@ template <typename T> struct Net {
   const int* ntype;
   // packed GEMM weights (element type set by the precision)
   const void *Wvg_t, *Wo_t, *Wproj_t, *mlp_t, *orb_t0, *orb_t1, *pi0, *pi1;
-  // the same GEMM weights in FP32/FP64 transposed-back orientation for the adjoint
+  // the same GEMM weights in the adjoint orientation (Bt = W)
+  const void *Wvg_n, *Wo_n, *Wproj_n, *mlp_n, *orb_n0, *orb_n1, *pi_n0, *pi_n1;
 };
 
 // ---------------------------------------------------------------------------

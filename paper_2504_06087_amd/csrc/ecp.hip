@@ -197,7 +197,9 @@ struct EcpLayout {
 static EcpLayout ecp_layout(const fire_handle* h, int W) {
   EcpLayout L{};
   const Dims& D = h->D;
-  L.Jc = W < 8192 ? (W > 256 ? W : 256) : 8192;
+  // jobs per chunk: about 12 jobs per electron and walker, at most 16384
+  int64_t want = (int64_t)W * 12;
+  L.Jc = (int)(want < 16380 ? (want > 264 ? want : 264) : 16380);   // a multiple of 12
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.cnt = take((size_t)D.n * W * 4);
@@ -208,7 +210,7 @@ static EcpLayout ecp_layout(const fire_handle* h, int W) {
   L.cf = take((size_t)L.Jc * 8);
   L.contrib = take((size_t)W * ECP_PMAX * NQ * 8);
   L.upd = o;
-  o += upd_layout(h, L.Jc).total;
+  o += upd_layout(h, L.Jc, false).total;
   L.total = align_up(o);
   return L;
 }
@@ -223,7 +225,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   Net<T> P = make_net<T>(h);
   const EcpLayout L = ecp_layout(h, W);
   const EcpTables tb = tables(h);
-  const UpdLayout U = upd_layout(h, L.Jc);
+  const UpdLayout U = upd_layout(h, L.Jc, false);
   int* cnt = (int*)(ws + L.cnt);
   int* off = (int*)(ws + L.off);
   int* tot = (int*)(ws + L.tot);
@@ -254,6 +256,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       Jobs jb{};
       jb.J = J;
       jb.Jcap = L.Jc;
+      jb.group = NQ;
       jb.jw = jw;
       jb.rexp = rexp;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, st));

@@ -86,7 +86,7 @@ constexpr int MCH = 64;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __restrict__ R, int64_t nrows,
-                                                  T* __restrict__ y_out) {
+                                                  T* __restrict__ y_out, int epb) {
   const Dims& D = P.D;
   __shared__ T feat[MCH * FEAT];
   __shared__ T red[16];
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
     for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
     for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
   }
-  for (int el = 0; el < EPB; ++el) {
-    int64_t e = (int64_t)blockIdx.x * EPB + el;
+  for (int el = 0; el < epb; ++el) {
+    int64_t e = (int64_t)blockIdx.x * epb + el;
     if (e >= nrows) break;
     const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
     T s = 0;

@@ -231,7 +231,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
 
   hipLaunchKernelGGL(k_nbr, dim3(W), dim3(256), 0, s, R, W, D.n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt, status);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y);
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y, EPB);
   CHECK(hipGetLastError());
   // GLU: [u | g] = y [W_v | W_g] + [b_v | b_g];  t = u * SiLU(g);  h0 = t W_o + b_o
   {

@@ -27,6 +27,8 @@ template <typename T> inline Net<T> make_net(const fire_handle* h) {
   P.ntype = (const int*)(b + L.ntype);
   P.Wvg_t = b + L.Wvg_t; P.Wo_t = b + L.Wo_t; P.Wproj_t = b + L.Wproj_t; P.mlp_t = b + L.mlp_t;
   P.orb_t0 = b + L.orb_t0; P.orb_t1 = b + L.orb_t1; P.pi0 = b + L.pi0; P.pi1 = b + L.pi1;
+  P.Wvg_n = b + L.Wvg_n; P.Wo_n = b + L.Wo_n; P.Wproj_n = b + L.Wproj_n; P.mlp_n = b + L.mlp_n;
+  P.orb_n0 = b + L.orb_n0; P.orb_n1 = b + L.orb_n1; P.pi_n0 = b + L.pi_n0; P.pi_n1 = b + L.pi_n1;
   return P;
 }
 

@@ -34,8 +34,19 @@ template <> struct MK<MMA_BF16X3> {
   static constexpr int BM = 128, BN = 128, PAD = 8;
 };
 
-FIRE_DEV int64_t roff(const RowMap& m, int64_t r) { return (r / m.rpg) * m.gstride + (r % m.rpg) * m.rstride; }
-FIRE_DEV int64_t coff(const ColMap& m, int64_t c) { return (c / m.cpg) * m.cgstride + (c % m.cpg); }
+// rows and columns are < 2^31: 32-bit quotients, 64-bit offsets
+FIRE_DEV int64_t roff(const RowMap& m, int64_t r) {
+  if (m.rpg == 1) return r * m.gstride;
+  const uint32_t rr = (uint32_t)r, p = (uint32_t)m.rpg;
+  const uint32_t q = rr / p;
+  return (int64_t)q * m.gstride + (int64_t)(rr - q * p) * m.rstride;
+}
+FIRE_DEV int64_t coff(const ColMap& m, int64_t c) {
+  if (m.cpg >= (int64_t)1 << 31) return c;
+  const uint32_t cc = (uint32_t)c, p = (uint32_t)m.cpg;
+  const uint32_t q = cc / p;
+  return (int64_t)q * m.cgstride + (cc - q * p);
+}
 
 template <typename TL, typename TS> FIRE_DEV TL to_lds(TS v) { return (TL)v; }
 template <> FIRE_DEV bf16_t to_lds<bf16_t, float>(float v) { return f2bf(v); }
@@ -80,6 +91,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
 
   const int tid = threadIdx.x;
   const int nct = (g.N + BN - 1) / BN;
+  // split-K: blockIdx.y selects a K range and a C slice
+  int kbeg = 0, kend = g.K;
+  if (g.ksplit > 1) {
+    const int kc = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+    kbeg = blockIdx.y * kc;
+    kend = kbeg + kc < g.K ? kbeg + kc : g.K;
+    g.C = (char*)g.C + (int64_t)blockIdx.y * g.c_split_stride * (int64_t)sizeof(typename P::TC);
+  }
+  const int Kl = kend - kbeg;
   // XCD-aware remap: consecutive logical tiles on the same XCD share A rows in L2
   const int nb = gridDim.x, per = nb / 8;
   const int bid = blockIdx.x;
@@ -89,8 +109,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   if (g.Mdev) {
     int m = *g.Mdev;
     if (m < g.M) g.M = m;
-    if (row0 >= g.M) return;
   }
+  if (g.prof_rows && blockIdx.x == 0 && threadIdx.x == 0) *g.prof_rows = g.M;
+  if (row0 >= g.M) return;
 
   const TA* A = (const TA*)g.A;
   const TB* Bt = (const TB*)g.Bt;
@@ -134,12 +155,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   TB rbl[SPLIT ? CB : 1][4];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < CA; ++t) load4<TA>(arow[t], k0 + ak[t], g.K, aval[t], vecA, ra[t]);
+    for (int t = 0; t < CA; ++t) load4<TA>(arow[t], k0 + ak[t], Kl, aval[t], vecA, ra[t]);
 #pragma unroll
-    for (int t = 0; t < CB; ++t) load4<TB>(brow[t], k0 + bk[t], g.K, bval[t], vecB, rb[t]);
+    for (int t = 0; t < CB; ++t) load4<TB>(brow[t], k0 + bk[t], Kl, bval[t], vecB, rb[t]);
     if constexpr (SPLIT) {
 #pragma unroll
-      for (int t = 0; t < CB; ++t) load4<TB>(browl[t], k0 + bk[t], g.K, bval[t], vecB, rbl[t]);
+      for (int t = 0; t < CB; ++t) load4<TB>(browl[t], k0 + bk[t], Kl, bval[t], vecB, rbl[t]);
     }
   };
 
@@ -147,35 +168,56 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   const int wm = wave >> 1, wn = wave & 1;
   const int lg = lane >> 4, l16 = lane & 15;
 
-  const int nk = (g.K + BK - 1) / BK;
-  gload(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    if constexpr (SPLIT) {
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  // loads clamp to [0, kend): shift the row pointers to kbeg
 #pragma unroll
-      for (int t = 0; t < CA; ++t)
+  for (int t = 0; t < CA; ++t) arow[t] += kbeg;
+#pragma unroll
+  for (int t = 0; t < CB; ++t) { brow[t] += kbeg; browl[t] += kbeg; }
+  if (nk > 0) gload(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    if constexpr (sizeof(TL) == 2) {
+      // 4 bf16 per 8-byte LDS store
+#pragma unroll
+      for (int t = 0; t < CA; ++t) {
+        uint32_t h[4], l[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float a = (float)ra[t][e];
           const bf16_t hi = f2bf(a);
-          As[ar[t] * LDK + ak[t] + e] = hi;
-          Asl[ar[t] * LDK + ak[t] + e] = f2bf(a - bf2f(hi));
+          h[e] = hi;
+          if constexpr (SPLIT) l[e] = f2bf(a - bf2f(hi));
         }
+        *reinterpret_cast<uint2*>(&As[ar[t] * LDK + ak[t]]) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        if constexpr (SPLIT)
+          *reinterpret_cast<uint2*>(&Asl[ar[t] * LDK + ak[t]]) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+      }
 #pragma unroll
-      for (int t = 0; t < CB; ++t)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          Bs[br[t] * LDK + bk[t] + e] = (bf16_t)rb[t][e];
-          Bsl[br[t] * LDK + bk[t] + e] = (bf16_t)rbl[t][e];
-        }
-    } else {
+      for (int t = 0; t < CB; ++t) {
+        *reinterpret_cast<uint2*>(&Bs[br[t] * LDK + bk[t]]) =
+            make_uint2((uint32_t)rb[t][0] | ((uint32_t)rb[t][1] << 16), (uint32_t)rb[t][2] | ((uint32_t)rb[t][3] << 16));
+        if constexpr (SPLIT)
+          *reinterpret_cast<uint2*>(&Bsl[br[t] * LDK + bk[t]]) = make_uint2(
+              (uint32_t)rbl[t][0] | ((uint32_t)rbl[t][1] << 16), (uint32_t)rbl[t][2] | ((uint32_t)rbl[t][3] << 16));
+      }
+    } else if constexpr (sizeof(TL) == 4) {
 #pragma unroll
       for (int t = 0; t < CA; ++t)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) As[ar[t] * LDK + ak[t] + e] = to_lds<TL, TA>(ra[t][e]);
+        *reinterpret_cast<float4*>(&As[ar[t] * LDK + ak[t]]) = make_float4(ra[t][0], ra[t][1], ra[t][2], ra[t][3]);
 #pragma unroll
       for (int t = 0; t < CB; ++t)
+        *reinterpret_cast<float4*>(&Bs[br[t] * LDK + bk[t]]) = make_float4(rb[t][0], rb[t][1], rb[t][2], rb[t][3]);
+    } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Bs[br[t] * LDK + bk[t] + e] = to_lds<TL, TB>(rb[t][e]);
+      for (int t = 0; t < CA; ++t) {
+        *reinterpret_cast<double2*>(&As[ar[t] * LDK + ak[t]]) = make_double2(ra[t][0], ra[t][1]);
+        *reinterpret_cast<double2*>(&As[ar[t] * LDK + ak[t] + 2]) = make_double2(ra[t][2], ra[t][3]);
+      }
+#pragma unroll
+      for (int t = 0; t < CB; ++t) {
+        *reinterpret_cast<double2*>(&Bs[br[t] * LDK + bk[t]]) = make_double2(rb[t][0], rb[t][1]);
+        *reinterpret_cast<double2*>(&Bs[br[t] * LDK + bk[t] + 2]) = make_double2(rb[t][2], rb[t][3]);
+      }
     }
     __syncthreads();
     if (kt + 1 < nk) gload((kt + 1) * BK);
@@ -213,13 +255,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
     } else {
       TL af[TM][8], bfr[TN][8];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i) {
+        const TL* src = &As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) af[i][e] = As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg + e];
+        for (int e = 0; e < 8; ++e) af[i][e] = src[e];
+      }
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
+      for (int j = 0; j < TN; ++j) {
+        const TL* src = &Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bfr[j][e] = Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg + e];
+        for (int e = 0; e < 8; ++e) bfr[j][e] = src[e];
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e)
 #pragma unroll
@@ -242,6 +288,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   const TC* bias = (const TC*)g.bias;
   const TC* aux = (const TC*)g.aux;
   TC* C = (TC*)g.C;
+  int64_t rco[TM][4], rxo[TM][4];
+  bool rok[TM][4], rbias[TM][4];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t r = row0 + wm * (BM / 2) + i * 16 + (KIND == MMA_F64 ? 4 * e + lg : 4 * lg + e);
+      rok[i][e] = r < g.M;
+      rco[i][e] = rok[i][e] ? roff(g.cmap, r) : 0;
+      rxo[i][e] = (rok[i][e] && aux) ? roff(g.xmap, r) : 0;
+      rbias[i][e] = !(g.bias_period > 0 && (uint32_t)r % (uint32_t)g.bias_period);
+    }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     int64_t c = col0 + wn * (BN / 2) + j * 16 + l16;
@@ -253,12 +311,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int64_t r = row0 + wm * (BM / 2) + i * 16 + (KIND == MMA_F64 ? 4 * e + lg : 4 * lg + e);
-        if (r >= g.M) continue;
-        TC v = (TC)acc[i][j][e] + ((g.bias_period > 0 && r % g.bias_period) ? TC(0) : bc);
+        if (!rok[i][e]) continue;
+        TC v = (TC)acc[i][j][e] + (rbias[i][e] ? bc : TC(0));
         if (g.act == ACT_SILU) v = silu_(v);
-        if (aux) v *= aux[roff(g.xmap, r) + xco];
-        TC* dst = C + roff(g.cmap, r) + cco;
+        if (aux) v *= aux[rxo[i][e] + xco];
+        TC* dst = C + rco[i][e] + cco;
         if (g.accumulate) v += *dst;
         *dst = v;
       }
@@ -267,15 +324,81 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
-template <int KIND> static hipError_t launch(const GemmArgs& g, hipStream_t s) {
+GemmProfiler& gemm_profiler() {
+  static GemmProfiler p{};
+  return p;
+}
+
+template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
   using P = MK<KIND>;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   int64_t tiles = (int64_t)((g.M + P::BM - 1) / P::BM) * ((g.N + P::BN - 1) / P::BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   int vecA = aligned16(g.A) && g.K % 4 == 0 && g.amap.gstride % 4 == 0 && (g.amap.rpg == 1 || g.amap.rstride % 4 == 0);
-  int vecB = aligned16(g.Bt) && g.K % 4 == 0 && g.ldb % 4 == 0;
-  hipLaunchKernelGGL(k_gemm<KIND>, dim3((unsigned)tiles), dim3(256), 0, s, g, vecA, vecB);
-  return hipGetLastError();
+  int vecB = aligned16(g.Bt) && g.K % 4 == 0 && g.ldb % 4 == 0 &&
+             (KIND != MMA_BF16X3 || aligned16(g.Bt_lo));
+  GemmProfiler& pr = gemm_profiler();
+  const bool prof = pr.on && s == pr.stream && pr.used < pr.capacity;
+  hipEvent_t* evs = prof ? (hipEvent_t*)pr.ev : nullptr;
+  int slot = 0;
+  if (prof) {
+    slot = pr.used++;
+    g.prof_rows = pr.counters + slot;
+    pr.kinds[slot] = KIND;
+    pr.nk[slot] = g.N * g.K;
+    hipEventRecord(evs[2 * slot], s);
+  }
+  if (g.ksplit > 1) vecA = vecA && ((((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK) % 4 == 0);
+  hipLaunchKernelGGL(k_gemm<KIND>, dim3((unsigned)tiles, g.ksplit > 1 ? g.ksplit : 1), dim3(256), 0, s, g, vecA,
+                     vecB);
+  hipError_t e = hipGetLastError();
+  if (prof) hipEventRecord(evs[2 * slot + 1], s);
+  return e;
+}
+
+hipError_t profile_begin(int* counters, int capacity, hipStream_t s) {
+  GemmProfiler& pr = gemm_profiler();
+  if (pr.ev) {
+    hipEvent_t* e = (hipEvent_t*)pr.ev;
+    for (int k = 0; k < 2 * pr.capacity; ++k) hipEventDestroy(e[k]);
+    delete[] e;
+    delete[] pr.kinds;
+    delete[] pr.nk;
+  }
+  pr.ev = nullptr;
+  pr.capacity = capacity;
+  pr.counters = counters;
+  pr.used = 0;
+  pr.stream = s;
+  hipEvent_t* e = new hipEvent_t[2 * (size_t)capacity];
+  for (int k = 0; k < 2 * capacity; ++k)
+    if (hipEventCreate(&e[k]) != hipSuccess) return hipErrorOutOfMemory;
+  pr.ev = e;
+  pr.kinds = new int[capacity];
+  pr.nk = new int[capacity];
+  pr.on = true;
+  return hipSuccess;
+}
+
+hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flops) {
+  GemmProfiler& pr = gemm_profiler();
+  pr.on = false;
+  for (int k = 0; k < 4; ++k) { launches[k] = 0; ms[k] = 0; flops[k] = 0; }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  int* rows = new int[pr.used > 0 ? pr.used : 1];
+  if (pr.used > 0) e = hipMemcpy(rows, pr.counters, (size_t)pr.used * 4, hipMemcpyDeviceToHost);
+  hipEvent_t* ev = (hipEvent_t*)pr.ev;
+  for (int k = 0; k < pr.used && e == hipSuccess; ++k) {
+    float t = 0;
+    hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+    const int kd = pr.kinds[k];
+    launches[kd] += 1;
+    ms[kd] += t;
+    flops[kd] += 2.0 * (double)rows[k] * (double)pr.nk[k];
+  }
+  delete[] rows;
+  return e;
 }
 
 hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s) {

@@ -40,7 +40,24 @@ struct GemmArgs {
   const int* Mdev;    // optional device row count (<= M); rows beyond it are skipped
   int bias_period;    // > 0: bias only on rows r with r % bias_period == 0
   const void* Bt_lo;  // MMA_BF16X3: low bf16 part of Bt (Bt holds the high part)
+  int* prof_rows;     // when set, block 0 writes the row count actually processed
+  int ksplit;         // > 1: K is split into ksplit ranges; range z writes C + z * c_split_stride
+  int64_t c_split_stride;
 };
+
+// Optional timing of GEMM launches (one profiler per process, host side).
+struct GemmProfiler {
+  bool on;
+  int* counters;
+  int capacity, used;
+  hipStream_t stream;
+  void* ev;           // std::vector of event pairs (opaque)
+  int* kinds;
+  int* nk;            // N*K per launch (host)
+};
+GemmProfiler& gemm_profiler();
+hipError_t profile_begin(int* counters, int capacity, hipStream_t s);
+hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flops);
 
 // Launch on stream; kind fixes the element types:
 //   MMA_F64: A double, Bt double, C double

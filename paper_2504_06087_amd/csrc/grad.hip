@@ -1,0 +1,929 @@
+// Parameter gradient g = sum_w c_w d log|psi_w| / d theta by a hand-written
+// adjoint (Methods, variational Monte Carlo: energy gradient with
+// c_w = (E_L,w - mean E_L) / W).
+//
+// Per chunk of walkers the node-level forward activations are recomputed and
+// kept (they fit in HBM); edge-level quantities (filters and messages of every
+// electron pair and electron-nucleus pair) are recomputed inside the backward
+// kernels and never stored.  The chain:
+//   Phibar = c_w w_d Phi^-T              (d log|psi| / d Phi_d, w_d = s_d e^{l_d} / psi)
+//   obar = Phibar * env,  envbar = Phibar * o          (orbital projections, envelopes)
+//   MLP, messages (edge recompute), node projections, GLU, LayerNorm and
+//   electron-nucleus filters (edge recompute) in reverse;
+// weight gradients are split-K GEMMs over the (walker, electron) rows.
+#include <vector>
+
+#include "embed_kernels.hpp"
+
+namespace fire {
+
+#define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
+
+constexpr int GNS = 32;      // K-splits of the weight-gradient GEMMs
+constexpr int GBLK = 1024;   // persistent workgroups of the edge kernels
+constexpr int ECH = 32;      // pairs per LDS chunk in the edge kernels
+constexpr int EFEAT = 96;    // per-pair stored values (see edge_forward)
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+// out[c][r] = in[r][c] for r < R, c < C (in rows through a row map)
+template <typename T>
+__global__ void k_transpose(const T* __restrict__ in, RowMap m, int R, int C, T* __restrict__ out) {
+  __shared__ T tile[32][33];
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: ty 0..7
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < R && c < C) {
+      const uint32_t rr = (uint32_t)r, p = (uint32_t)m.rpg, q = rr / p;
+      tile[k][tx] = in[(int64_t)q * m.gstride + (int64_t)(rr - q * p) * m.rstride + c];
+    }
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (r < R && c < C) out[(int64_t)c * R + r] = tile[tx][k];
+  }
+}
+
+// grad[base + a*sa + (b/cpg)*sbg + (b%cpg)*sb] += sum_z part[z][a][b]
+template <typename T>
+__global__ void k_reduce_splits(const T* __restrict__ part, int ns, int M, int N, double* __restrict__ grad,
+                                int64_t base, int64_t sa, int64_t cpg, int64_t sbg, int64_t sb) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)M * N) return;
+  const int a = (int)(q / N), b = (int)(q % N);
+  double v = 0.0;
+  for (int z = 0; z < ns; ++z) v += (double)part[(int64_t)z * M * N + q];
+  grad[base + a * sa + (b / cpg) * sbg + (b % cpg) * sb] += v;
+}
+
+// part[z][c] = sum over rows r in chunk z of X[r][c]
+template <typename T>
+__global__ void k_colsum(const T* __restrict__ X, RowMap m, int R, int C, int ns, T* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (c >= C) return;
+  const int per = (R + ns - 1) / ns;
+  const int r0 = z * per, r1 = r0 + per < R ? r0 + per : R;
+  T v = 0;
+  for (int r = r0; r < r1; ++r) {
+    const uint32_t rr = (uint32_t)r, p = (uint32_t)m.rpg, q = rr / p;
+    v += X[(int64_t)q * m.gstride + (int64_t)(rr - q * p) * m.rstride + c];
+  }
+  part[(int64_t)z * C + c] = v;
+}
+
+// grad[base + j] += sum_b part[b][col0 + j], j < len
+__global__ void k_reduce_cols(const void* __restrict__ part, int tsize, int nb, int64_t stride, int64_t col0, int len,
+                              double* __restrict__ grad, int64_t base) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= len) return;
+  double v = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t q = (int64_t)b * stride + col0 + j;
+    v += tsize == 8 ? ((const double*)part)[q] : (double)((const float*)part)[q];
+  }
+  grad[base + j] += v;
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// h1 = h0 + m for the chunk rows, from the cached state
+template <typename T>
+__global__ void k_h1_from_state(const Dims D, int Wc, int w0, const char* __restrict__ state, StateRec S,
+                                T* __restrict__ h1) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)Wc * D.n * D.d) return;
+  const int64_t e = q / D.d;
+  const int c = (int)(q % D.d);
+  const int64_t w = w0 + e / D.n;
+  const int i = (int)(e % D.n);
+  const char* rec = state + w * S.stride;
+  h1[q] = ((const T*)(rec + S.h0))[(int64_t)i * D.d + c] + ((const T*)(rec + S.m))[(int64_t)i * D.d + c];
+}
+
+template <typename T>
+__global__ void k_silu_inplace(const T* __restrict__ z, T* __restrict__ h, int64_t n) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) h[q] = silu_(z[q]);
+}
+
+// zbar = hbar * SiLU'(z)
+template <typename T>
+__global__ void k_silu_bar(const T* __restrict__ z, const T* __restrict__ hbar, T* __restrict__ zbar, int64_t n) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  T f, f1, f2;
+  silu3(z[q], f, f1, f2);
+  zbar[q] = hbar[q] * f1;
+}
+
+// Phibar = c_w w_d G;  obar = Phibar * env;  envbar = Phibar * o  (envbar overwrites o)
+template <typename T, typename TI>
+__global__ void k_orb_bar(const Dims D, int s, int Wc, int w0, const char* __restrict__ state, StateRec S,
+                          const double* __restrict__ coeff, T* __restrict__ o, T* __restrict__ obar) {
+  const int N = D.nsig(s), KN = D.K * N;
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)Wc * N * KN) return;
+  const int64_t r = q / KN;
+  const int col = (int)(q % KN);
+  const int64_t w = w0 + r / N;
+  const int iloc = (int)(r % N);
+  const int det = col / N, l = col % N;
+  const char* rec = state + w * S.stride;
+  const double* ds = (const double*)(rec + S.dsign);
+  const double* dl = (const double*)(rec + S.dlog);
+  const double lp = *(const double*)(rec + S.lpsi), sp = *(const double*)(rec + S.spsi);
+  const double wd = ds[2 * det] * ds[2 * det + 1] * sp * exp(dl[2 * det] + dl[2 * det + 1] - lp);
+  const int64_t idx = det * phi_per_det(D) + phi_block_off(D, s) + (int64_t)iloc * N + l;
+  const double g = (double)((const TI*)(rec + S.inv))[idx];
+  const T pb = (T)(coeff[w] * wd * g);
+  const T env = ((const T*)(rec + S.env))[idx];
+  obar[q] = pb * env;
+  o[q] = pb * o[q];
+}
+
+// ubar = tbar * SiLU(g), gbar = tbar * u * SiLU'(g)
+template <typename T>
+__global__ void k_glu_bar(const T* __restrict__ ug, const T* __restrict__ tbar, T* __restrict__ ugbar, int64_t nrows,
+                          int d) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nrows * d) return;
+  const int64_t r = q / d;
+  const int c = (int)(q % d);
+  const T u = ug[r * 2 * d + c], g = ug[r * 2 * d + d + c];
+  T f, f1, f2;
+  silu3(g, f, f1, f2);
+  const T tb = tbar[q];
+  ugbar[r * 2 * d + c] = tb * f;
+  ugbar[r * 2 * d + d + c] = tb * u * f1;
+}
+
+// envelope exponents: sigmabar[b] partial over rows = sum_r basisbar * (-rho) * basis
+template <typename T>
+__global__ void k_envsig_bar(Net<T> P, const double* __restrict__ R, int e0, int N, int Wc, const T* __restrict__ bb,
+                             int ns, T* __restrict__ part) {
+  const Dims& D = P.D;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (b >= D.B) return;
+  const int m = b / D.E;
+  const int rows = Wc * N, per = (rows + ns - 1) / ns;
+  const int r0 = z * per, r1 = r0 + per < rows ? r0 + per : rows;
+  T v = 0;
+  for (int r = r0; r < r1; ++r) {
+    const int64_t e = (int64_t)(r / N) * D.n + e0 + r % N;
+    const double dx = R[3 * e] - P.Rn[3 * m], dy = R[3 * e + 1] - P.Rn[3 * m + 1], dz = R[3 * e + 2] - P.Rn[3 * m + 2];
+    const T rho = (T)sqrt(dx * dx + dy * dy + dz * dz);
+    v += bb[((int64_t)(r / N) * D.n + r % N) * D.B + b] * (-rho) * exp(-P.env_sigma[b] * rho);
+  }
+  part[(int64_t)z * D.B + b] = v;
+}
+
+// ---------------------------------------------------------------------------
+// pair features with the intermediates the backward pass needs:
+//   [0..4) e4 = [r, dx, dy, dz]      [4..8)  rescaled features
+//   [8..24) z1 pre-activations       [24..40) z1
+//   [40..48) z2 pre-activations      [48..56) z2
+//   [56..88) exp(-sigma_k^2 r^2)     [88] f_cut(r/c)
+// ---------------------------------------------------------------------------
+template <typename T>
+FIRE_DEV void edge_forward(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, const T* b2, const T* sig, T cut,
+                           const Dims& D, T* f) {
+  const T r = sqrt(dx * dx + dy * dy + dz * dz);
+  f[0] = r; f[1] = dx; f[2] = dy; f[3] = dz;
+  const T lo = log1p_over(r);
+  for (int k = 0; k < 4; ++k) f[4 + k] = lo * f[k];
+  for (int k = 0; k < D.h1; ++k) {
+    T a = b1[k];
+    for (int j = 0; j < 4; ++j) a += f[j] * W1[j * D.h1 + k];
+    f[8 + k] = a;
+    f[24 + k] = silu_(a);
+  }
+  for (int k = 0; k < D.h2; ++k) {
+    T a = b2[k];
+    for (int j = 0; j < D.h1; ++j) a += f[24 + j] * W2[j * D.h2 + k];
+    f[40 + k] = a;
+    f[48 + k] = silu_(a);
+  }
+  for (int k = 0; k < D.G; ++k) f[56 + k] = exp(-(sig[k] * sig[k]) * r * r);
+  f[88] = fcut_(r / cut);
+}
+
+// Backward of one pair's filter given zbar2 (h2) and chibar (G): accumulates
+// into acc = [W1 (4 h1) | b1 (h1) | W2 (h1 h2) | b2 (h2) | sigma (G)] (LDS).
+template <typename T>
+FIRE_DEV void edge_backward(const T* f, const T* zb2, const T* chib, const T* W2, const T* sig, const Dims& D,
+                            T* accW1, T* accb1, T* accW2, T* accb2, T* accsig) {
+  const T r = f[0], fc = f[88];
+  for (int k = 0; k < D.G; ++k) atomicAdd(&accsig[k], chib[k] * fc * f[56 + k] * (T(-2) * sig[k] * r * r));
+  T pre2b[kMaxH2];
+  for (int k = 0; k < D.h2; ++k) {
+    T s, s1, s2;
+    silu3(f[40 + k], s, s1, s2);
+    pre2b[k] = zb2[k] * s1;
+    atomicAdd(&accb2[k], pre2b[k]);
+  }
+  for (int j = 0; j < D.h1; ++j) {
+    T z1b = 0;
+    for (int k = 0; k < D.h2; ++k) {
+      atomicAdd(&accW2[j * D.h2 + k], pre2b[k] * f[24 + j]);
+      z1b += pre2b[k] * W2[j * D.h2 + k];
+    }
+    T s, s1, s2;
+    silu3(f[8 + j], s, s1, s2);
+    const T p1 = z1b * s1;
+    atomicAdd(&accb1[j], p1);
+    for (int i = 0; i < 4; ++i) atomicAdd(&accW1[i * D.h1 + j], p1 * f[i]);
+  }
+}
+
+// partial layout of one filter (shared by both edge kernels)
+struct FiltOff {
+  int W1, b1, W2, b2, W3, Wenv, sig, size;
+};
+FIRE_HOST_DEVICE FiltOff filt_off(const Dims& D) {
+  FiltOff o;
+  o.W1 = 0; o.b1 = 4 * D.h1; o.W2 = o.b1 + D.h1; o.b2 = o.W2 + D.h1 * D.h2; o.W3 = o.b2 + D.h2;
+  o.Wenv = o.W3 + D.h2 * D.d; o.sig = o.Wenv + D.G * D.d; o.size = o.sig + D.G;
+  return o;
+}
+// message partials per block: per alpha [filter | We (4d) | b (d)]
+FIRE_HOST_DEVICE int msg_part_size(const Dims& D) { return 2 * (filt_off(D).size + 5 * D.d); }
+
+// ---------------------------------------------------------------------------
+// message backward.  For edge (i, j) of class alpha and channel c:
+//   Gamma = g1 g2, g1 = z2 . W3[:,c], g2 = chi . Wenv[:,c], pre = a_i + b_j + ebar . We + b
+//   m_i += Gamma SiLU(pre)
+// mbar gives Gammabar = mbar SiLU(pre), prebar = mbar Gamma SiLU'(pre);
+// abar_i += prebar, bbar_j += prebar (atomic), and the weight partials.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
+                                                 const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
+                                                 const char* __restrict__ state, StateRec S,
+                                                 const T* __restrict__ mbar, T* __restrict__ projbar,
+                                                 T* __restrict__ part) {
+  const Dims& D = P.D;
+  const FiltOff fo = filt_off(D);
+  __shared__ T feat[ECH * EFEAT];
+  __shared__ T red[ECH * 40];
+  __shared__ int jn[ECH];
+  extern __shared__ char dyn[];
+  // LDS accumulators of the scalar filter parameters, per alpha:
+  // [W1 | b1 | W2 | b2] (offsets as in the partials) then sigma at fo.W3
+  const int astr = fo.W3 + D.G;
+  T* acc = (T*)dyn;
+  const int c = threadIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const bool act = c < D.d;
+  const int n = D.n, d = D.d;
+  for (int q = tid; q < 2 * astr; q += nt) acc[q] = T(0);
+  T aW3[2][kMaxH2], aWenv[2][kMaxG], aWe[2][4], ab[2];
+  for (int a = 0; a < 2; ++a) {
+    for (int k = 0; k < kMaxH2; ++k) aW3[a][k] = 0;
+    for (int k = 0; k < kMaxG; ++k) aWenv[a][k] = 0;
+    for (int k = 0; k < 4; ++k) aWe[a][k] = 0;
+    ab[a] = 0;
+  }
+  __syncthreads();
+  for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
+    const int64_t wl = e / n;
+    const int i = (int)(e % n);
+    const char* rec = state + (w0 + wl) * S.stride;
+    const T* proj = (const T*)(rec + S.proj);
+    const double* Rw = R + wl * n * 3;
+    const double rx = Rw[3 * i], ry = Rw[3 * i + 1], rz = Rw[3 * i + 2];
+    const T mb = act ? mbar[e * d + c] : T(0);
+    const int c0 = ncnt[2 * e], c1 = ncnt[2 * e + 1];
+    T abar[2] = {0, 0};
+    for (int a = 0; a < 2; ++a) {
+      const int na = a == 0 ? c0 : c1, sbase = a == 0 ? 0 : c0;
+      T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0, ai = 0;
+      if (act) {
+        for (int k = 0; k < D.h2; ++k) w3[k] = P.ee_W3[(a * D.h2 + k) * d + c];
+        for (int k = 0; k < D.G; ++k) wenv[k] = P.ee_Wenv[(a * D.G + k) * d + c];
+        for (int k = 0; k < 4; ++k) we[k] = P.msg_We[(a * 4 + k) * d + c];
+        bb = P.msg_b[a * d + c];
+        ai = proj[((int64_t)i * 4 + a) * d + c];
+      }
+      for (int j0 = 0; j0 < na; j0 += ECH) {
+        const int jc = na - j0 < ECH ? na - j0 : ECH;
+        __syncthreads();
+        if (tid < jc) {
+          const int j = nidx[e * D.cap_nbr + sbase + j0 + tid];
+          jn[tid] = j;
+          edge_forward<T>((T)(rx - Rw[3 * j]), (T)(ry - Rw[3 * j + 1]), (T)(rz - Rw[3 * j + 2]),
+                          P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2,
+                          P.ee_sig + a * D.G, (T)D.cut, D, feat + tid * EFEAT);
+        }
+        for (int q = tid; q < jc * 40; q += nt) red[q] = T(0);
+        __syncthreads();
+        for (int k = 0; k < jc; ++k) {
+          const T* f = feat + k * EFEAT;
+          T u1 = 0, u2 = 0;
+          if (act && f[88] != T(0)) {
+            T g1 = 0, g2 = 0;
+            for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
+            for (int q = 0; q < D.G; ++q) g2 += f[88] * f[56 + q] * wenv[q];
+            const T gam = g1 * g2;
+            const int j = jn[k];
+            const T pre = ai + ((const T*)(rec + S.proj))[((int64_t)j * 4 + 2 + a) * d + c] + f[4] * we[0] +
+                          f[5] * we[1] + f[6] * we[2] + f[7] * we[3] + bb;
+            T sf, s1, s2;
+            silu3(pre, sf, s1, s2);
+            const T gb = mb * sf, pb = mb * gam * s1;
+            abar[a] += pb;
+            atomicAdd(&projbar[((wl * n + j) * 4 + 2 + a) * d + c], pb);
+            for (int q = 0; q < 4; ++q) aWe[a][q] += pb * f[4 + q];
+            ab[a] += pb;
+            u1 = gb * g2;
+            u2 = gb * g1;
+            for (int q = 0; q < D.h2; ++q) aW3[a][q] += u1 * f[48 + q];
+            for (int q = 0; q < D.G; ++q) aWenv[a][q] += u2 * f[88] * f[56 + q];
+          }
+          // per-pair reductions over channels: zbar2_q = sum_c u1 W3[q][c], chibar_q = sum_c u2 Wenv[q][c]
+          for (int q = 0; q < D.h2; ++q) {
+            T v = wave_sum(act ? u1 * w3[q] : T(0));
+            if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+          }
+          for (int q = 0; q < D.G; ++q) {
+            T v = wave_sum(act ? u2 * wenv[q] : T(0));
+            if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+          }
+        }
+        __syncthreads();
+        if (tid < jc && feat[tid * EFEAT + 88] != T(0)) {
+          const T* f = feat + tid * EFEAT;
+          T chib[kMaxG];
+          for (int q = 0; q < D.G; ++q) chib[q] = red[tid * 40 + 8 + q];
+          // chi = f_cut * exp(-sigma^2 r^2): only the exponents are parameters
+          T* A = acc + a * astr;
+          edge_backward<T>(f, red + tid * 40, chib, P.ee_W2 + a * D.h1 * D.h2, P.ee_sig + a * D.G, D, A + fo.W1,
+                           A + fo.b1, A + fo.W2, A + fo.b2, A + fo.W3);
+        }
+      }
+    }
+    if (act) {
+      projbar[(e * 4 + 0) * d + c] += abar[0];
+      projbar[(e * 4 + 1) * d + c] += abar[1];
+    }
+  }
+  __syncthreads();
+  T* out = part + (int64_t)blockIdx.x * msg_part_size(D);
+  for (int a = 0; a < 2; ++a) {
+    T* o = out + a * (fo.size + 5 * D.d);
+    if (act) {
+      for (int q = 0; q < D.h2; ++q) o[fo.W3 + q * d + c] = aW3[a][q];
+      for (int q = 0; q < D.G; ++q) o[fo.Wenv + q * d + c] = aWenv[a][q];
+      for (int q = 0; q < 4; ++q) o[fo.size + q * d + c] = aWe[a][q];
+      o[fo.size + 4 * d + c] = ab[a];
+    }
+    for (int q = tid; q < fo.W3; q += nt) o[q] = acc[a * astr + q];
+    for (int q = tid; q < D.G; q += nt) o[fo.sig + q] = acc[a * astr + fo.W3 + q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LayerNorm backward: sbar from ybar, and the LayerNorm parameter partials.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_ln_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows,
+                                                const T* __restrict__ ybar, T* __restrict__ sbar,
+                                                T* __restrict__ part) {
+  const Dims& D = P.D;
+  __shared__ T feat[MCH * FEAT];
+  __shared__ T red[16];
+  const int c = threadIdx.x;
+  const bool act = c < D.d;
+  T w3[kMaxH2], wenv[kMaxG], wn[4];
+  if (act) {
+    for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
+    for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
+    for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
+  }
+  T ag = 0, abeta = 0;
+  for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
+    const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
+    T s = 0;
+    for (int m0 = 0; m0 < D.M; m0 += MCH) {
+      const int mc = D.M - m0 < MCH ? D.M - m0 : MCH;
+      __syncthreads();
+      if (threadIdx.x < mc) {
+        const int m = m0 + threadIdx.x, t = P.ntype[m];
+        pair_features<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
+                         P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig, (T)D.cutn, D,
+                         feat + threadIdx.x * FEAT);
+      }
+      __syncthreads();
+      if (act)
+        for (int k = 0; k < mc; ++k) {
+          const T* f = feat + k * FEAT;
+          if (f[44] == T(0)) continue;
+          T g1 = 0, g2 = 0;
+          for (int j = 0; j < D.h2; ++j) g1 += f[4 + j] * w3[j];
+          for (int j = 0; j < D.G; ++j) g2 += f[12 + j] * wenv[j];
+          const T v = P.nuc_emb[P.ntype[m0 + k] * D.d + c] + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
+          s += g1 * g2 * v;
+        }
+    }
+    const T inv_d = T(1) / T(D.d);
+    const T mu = block_sum<T>(act ? s : T(0), red) * inv_d;
+    const T dv = act ? s - mu : T(0);
+    const T var = block_sum<T>(dv * dv, red) * inv_d;
+    const T rs = T(1) / sqrt(var + T(kLnEps));
+    const T xh = dv * rs;
+    const T yb = act ? ybar[e * D.d + c] : T(0);
+    ag += yb * xh;
+    abeta += yb;
+    const T xb = act ? yb * P.ln_g[c] : T(0);
+    const T m1 = block_sum<T>(xb, red) * inv_d;
+    const T m2 = block_sum<T>(xb * xh, red) * inv_d;
+    if (act) sbar[e * D.d + c] = rs * (xb - m1 - xh * m2);
+  }
+  if (act) {
+    part[(int64_t)blockIdx.x * 2 * D.d + c] = ag;
+    part[(int64_t)blockIdx.x * 2 * D.d + D.d + c] = abeta;
+  }
+}
+
+// electron-nucleus partials per block: [nuc_emb NT d | W1 NT 4h1 | b1 NT h1 | W2 | b2 | W3 | Wenv | sig | Wn 4d]
+struct EnOff {
+  int nuc, W1, b1, W2, b2, W3, Wenv, sig, Wn, size;
+};
+FIRE_HOST_DEVICE EnOff en_off(const Dims& D) {
+  EnOff o;
+  o.nuc = 0; o.W1 = D.NT * D.d; o.b1 = o.W1 + D.NT * 4 * D.h1; o.W2 = o.b1 + D.NT * D.h1; o.b2 = o.W2 + D.h1 * D.h2;
+  o.W3 = o.b2 + D.h2; o.Wenv = o.W3 + D.h2 * D.d; o.sig = o.Wenv + D.G * D.d; o.Wn = o.sig + D.G;
+  o.size = o.Wn + 4 * D.d;
+  return o;
+}
+constexpr int ENCH = 32;   // nuclei per block column of the electron-nucleus backward
+
+// ---------------------------------------------------------------------------
+// electron-nucleus backward for nuclei [m0, m0 + ENCH) (blockIdx.y):
+// s_i = sum_m Gamma_m * v_m, v_m = nuc_emb_m + ebar_im W_n.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows,
+                                                const T* __restrict__ sbar, T* __restrict__ part) {
+  const Dims& D = P.D;
+  const EnOff eo = en_off(D);
+  const int m0 = blockIdx.y * ENCH;
+  const int mc = D.M - m0 < ENCH ? D.M - m0 : ENCH;
+  __shared__ T feat[ENCH * EFEAT];
+  __shared__ T red[ENCH * 40];
+  extern __shared__ char dyn[];
+  T* nucb = (T*)dyn;                       // [ENCH][d]
+  T* sW1 = nucb + ENCH * D.d;              // [ENCH][4 h1]
+  T* sb1 = sW1 + ENCH * 4 * D.h1;          // [ENCH][h1]
+  T* sW2 = sb1 + ENCH * D.h1;              // [h1 h2]
+  T* sb2 = sW2 + D.h1 * D.h2;              // [h2]
+  T* ssig = sb2 + D.h2;                    // [G]
+  const int nsc = ENCH * D.d + ENCH * 5 * D.h1 + D.h1 * D.h2 + D.h2 + D.G;
+  const int c = threadIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const bool act = c < D.d;
+  for (int q = tid; q < nsc; q += nt) nucb[q] = T(0);
+  T w3[kMaxH2], wenv[kMaxG], wn[4];
+  T aW3[kMaxH2], aWenv[kMaxG], aWn[4];
+  for (int k = 0; k < kMaxH2; ++k) aW3[k] = 0;
+  for (int k = 0; k < kMaxG; ++k) aWenv[k] = 0;
+  for (int k = 0; k < 4; ++k) aWn[k] = 0;
+  if (act) {
+    for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
+    for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
+    for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
+  }
+  for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
+    const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
+    const T sb = act ? sbar[e * D.d + c] : T(0);
+    __syncthreads();
+    if (tid < mc) {
+      const int m = m0 + tid, t = P.ntype[m];
+      edge_forward<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
+                      P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig, (T)D.cutn, D,
+                      feat + tid * EFEAT);
+    }
+    for (int q = tid; q < mc * 40; q += nt) red[q] = T(0);
+    __syncthreads();
+    for (int k = 0; k < mc; ++k) {
+      const T* f = feat + k * EFEAT;
+      T u1 = 0, u2 = 0;
+      if (act && f[88] != T(0)) {
+        T g1 = 0, g2 = 0;
+        for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
+        for (int q = 0; q < D.G; ++q) g2 += f[88] * f[56 + q] * wenv[q];
+        const T gam = g1 * g2;
+        const T v = P.nuc_emb[P.ntype[m0 + k] * D.d + c] + f[4] * wn[0] + f[5] * wn[1] + f[6] * wn[2] + f[7] * wn[3];
+        const T gb = sb * v, vb = sb * gam;
+        nucb[k * D.d + c] += vb;
+        for (int q = 0; q < 4; ++q) aWn[q] += vb * f[4 + q];
+        u1 = gb * g2;
+        u2 = gb * g1;
+        for (int q = 0; q < D.h2; ++q) aW3[q] += u1 * f[48 + q];
+        for (int q = 0; q < D.G; ++q) aWenv[q] += u2 * f[88] * f[56 + q];
+      }
+      for (int q = 0; q < D.h2; ++q) {
+        T v = wave_sum(act ? u1 * w3[q] : T(0));
+        if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+      }
+      for (int q = 0; q < D.G; ++q) {
+        T v = wave_sum(act ? u2 * wenv[q] : T(0));
+        if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+      }
+    }
+    __syncthreads();
+    if (tid < mc && feat[tid * EFEAT + 88] != T(0)) {
+      const T* f = feat + tid * EFEAT;
+      T chib[kMaxG];
+      for (int q = 0; q < D.G; ++q) chib[q] = red[tid * 40 + 8 + q];
+      edge_backward<T>(f, red + tid * 40, chib, P.en_W2, P.en_sig, D, sW1 + tid * 4 * D.h1, sb1 + tid * D.h1, sW2,
+                       sb2, ssig);
+    }
+  }
+  __syncthreads();
+  T* out = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * eo.size;
+  for (int q = tid; q < eo.size; q += nt) out[q] = T(0);
+  __syncthreads();
+  // per-nucleus accumulators into their type rows (one thread per column)
+  for (int k = 0; k < mc; ++k) {
+    const int t = P.ntype[m0 + k];
+    if (act) out[eo.nuc + t * D.d + c] += nucb[k * D.d + c];
+    for (int q = tid; q < 5 * D.h1; q += nt) {
+      if (q < 4 * D.h1) out[eo.W1 + t * 4 * D.h1 + q] += sW1[k * 4 * D.h1 + q];
+      else out[eo.b1 + t * D.h1 + q - 4 * D.h1] += sb1[k * D.h1 + q - 4 * D.h1];
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < D.h1 * D.h2; q += nt) out[eo.W2 + q] = sW2[q];
+  for (int q = tid; q < D.h2; q += nt) out[eo.b2 + q] = sb2[q];
+  for (int q = tid; q < D.G; q += nt) out[eo.sig + q] = ssig[q];
+  if (act) {
+    for (int q = 0; q < D.h2; ++q) out[eo.W3 + q * D.d + c] = aW3[q];
+    for (int q = 0; q < D.G; ++q) out[eo.Wenv + q * D.d + c] = aWenv[q];
+    for (int q = 0; q < 4; ++q) out[eo.Wn + q * D.d + c] = aWn[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+struct GradLayout {
+  int Wc;
+  size_t nidx, ncnt, y, ug, t, hk, zk, basis, o[2], obar[2], hbar, hbar2, zbar, h0bar, projbar, tbar, ugbar;
+  size_t ybar, sbar, bbar, trA, trB, split, epart;
+  size_t total;
+};
+
+static GradLayout grad_layout(const fire_handle* h, int W) {
+  const Dims& D = h->D;
+  GradLayout L{};
+  const size_t ts = h->tsize;
+  const int nmax = D.nu > D.nd ? D.nu : D.nd;
+  const int KNmax = D.K * nmax;
+  int widest = 4 * D.d;
+  if (KNmax > widest) widest = KNmax;
+  if (D.B > widest) widest = D.B;
+  const size_t per_walker = (size_t)D.n * ts *
+                            ((size_t)20 * D.d + 2 * (size_t)D.L * D.d + 2 * (size_t)D.B + 3 * (size_t)KNmax + 2 * widest);
+  const size_t budget = (size_t)24 << 30;
+  int wc = (int)(budget / per_walker);
+  if (wc < 1) wc = 1;
+  if (wc > W) wc = W;
+  L.Wc = wc;
+  const int64_t R = (int64_t)wc * D.n;
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
+  L.nidx = take(R * D.cap_nbr * 2);
+  L.ncnt = take(R * 2 * 4);
+  L.y = take(R * D.d * ts);
+  L.ug = take(R * 2 * D.d * ts);
+  L.t = take(R * D.d * ts);
+  L.hk = take((size_t)(D.L + 1) * R * D.d * ts);
+  L.zk = take((size_t)(D.L > 0 ? D.L : 1) * R * D.d * ts);
+  L.basis = take(R * D.B * ts);
+  for (int s = 0; s < 2; ++s) {
+    const int N = D.nsig(s) > 0 ? D.nsig(s) : 1;
+    L.o[s] = take((int64_t)wc * N * D.K * N * ts);
+    L.obar[s] = take((int64_t)wc * N * D.K * N * ts);
+  }
+  L.hbar = take(R * D.d * ts);
+  L.hbar2 = take(R * D.d * ts);
+  L.zbar = take(R * D.d * ts);
+  L.h0bar = take(R * D.d * ts);
+  L.projbar = take(R * 4 * D.d * ts);
+  L.tbar = take(R * D.d * ts);
+  L.ugbar = take(R * 2 * D.d * ts);
+  L.ybar = take(R * D.d * ts);
+  L.sbar = take(R * D.d * ts);
+  L.bbar = take(R * D.B * ts);
+  L.trA = take(R * widest * ts);
+  L.trB = take(R * widest * ts);
+  L.split = take((size_t)GNS * widest * widest * ts);
+  const size_t ep = (size_t)GBLK * ((size_t)msg_part_size(D) > (size_t)2 * D.d ? (size_t)msg_part_size(D) : 2 * D.d);
+  const size_t enp = (size_t)GBLK * ((D.M + ENCH - 1) / ENCH) * en_off(D).size;
+  L.epart = take((ep > enp ? ep : enp) * ts);
+  L.total = o;
+  return L;
+}
+
+size_t grad_ws_bytes(const fire_handle* h, int W) { return grad_layout(h, W).total; }
+
+// weight gradient C[a][b] = sum_r X[r][a] Y[r][b] (rows through maps), into grad
+template <typename T>
+static hipError_t wgrad(const fire_handle* h, const GradLayout& L, char* ws, const T* X, RowMap xm, int R, int A,
+                        const T* Y, RowMap ym, int B, double* grad, int64_t base, int64_t sa, int64_t cpg, int64_t sbg,
+                        int64_t sb, hipStream_t st) {
+  T* xt = (T*)(ws + L.trA);
+  T* yt = (T*)(ws + L.trB);
+  T* part = (T*)(ws + L.split);
+  hipLaunchKernelGGL(k_transpose<T>, dim3((R + 31) / 32, (A + 31) / 32), dim3(256), 0, st, X, xm, R, A, xt);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_transpose<T>, dim3((R + 31) / 32, (B + 31) / 32), dim3(256), 0, st, Y, ym, R, B, yt);
+  CHECK(hipGetLastError());
+  GemmArgs g{};
+  g.A = xt; g.amap = rows_dense(R); g.Bt = yt; g.ldb = R; g.C = part; g.cmap = rows_dense(B); g.ccol = cols_dense();
+  g.M = A; g.N = B; g.K = R; g.ksplit = GNS; g.c_split_stride = (int64_t)A * B;
+  CHECK(gemm(sizeof(T) == 8 ? MMA_F64 : MMA_F32, g, st));
+  hipLaunchKernelGGL(k_reduce_splits<T>, dim3((unsigned)(((int64_t)A * B + 255) / 256)), dim3(256), 0, st,
+                     (const T*)part, GNS, A, B, grad, base, sa, cpg, sbg, sb);
+  return hipGetLastError();
+}
+
+// bias gradient grad[base + c] += sum_r X[r][c]
+template <typename T>
+static hipError_t bgrad(const GradLayout& L, char* ws, const T* X, RowMap xm, int R, int C, double* grad, int64_t base,
+                        hipStream_t st) {
+  T* part = (T*)(ws + L.split);
+  hipLaunchKernelGGL(k_colsum<T>, dim3((C + 255) / 256, GNS), dim3(256), 0, st, X, xm, R, C, GNS, part);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_splits<T>, dim3((C + 255) / 256), dim3(256), 0, st, (const T*)part, GNS, 1, C, grad,
+                     base, (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int Wc, const double* R, char* state,
+                             char* ws, const double* coeff, double* grad, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  const GradLayout L = grad_layout(h, Wc);
+  const int n = D.n, d = D.d;
+  const int64_t rows = (int64_t)Wc * n;
+  const double* Rc = R + (int64_t)w0 * n * 3;
+  const int blk = d <= 64 ? 64 : (d + 63) / 64 * 64;
+  const int64_t srecT = S.stride / sizeof(T);
+  auto th = [&](const char* nm) { return theta_offset(h, nm); };
+  int16_t* nidx = (int16_t*)(ws + L.nidx);
+  int32_t* ncnt = (int32_t*)(ws + L.ncnt);
+  T* y = (T*)(ws + L.y);
+  T* ug = (T*)(ws + L.ug);
+  T* tt = (T*)(ws + L.t);
+  T* hk = (T*)(ws + L.hk);
+  T* zk = (T*)(ws + L.zk);
+  T* basis = (T*)(ws + L.basis);
+  T* hbar = (T*)(ws + L.hbar);
+  T* hbar2 = (T*)(ws + L.hbar2);
+  T* zbar = (T*)(ws + L.zbar);
+  T* h0bar = (T*)(ws + L.h0bar);
+  T* projbar = (T*)(ws + L.projbar);
+  T* tbar = (T*)(ws + L.tbar);
+  T* ugbar = (T*)(ws + L.ugbar);
+  T* ybar = (T*)(ws + L.ybar);
+  T* sbar = (T*)(ws + L.sbar);
+  T* bbar = (T*)(ws + L.bbar);
+  T* epart = (T*)(ws + L.epart);
+  const char* st_base = state + (int64_t)w0 * S.stride;
+  const RowMap h0map{n, srecT, d}, projmap{n, srecT, 4 * d};
+
+  // ---- forward recompute of node activations
+  hipLaunchKernelGGL(k_nbr, dim3(Wc), dim3(256), 0, st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
+                     status + w0);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, st, P, Rc, rows, y, EPB);
+  CHECK(hipGetLastError());
+  {
+    GemmArgs g{};
+    g.A = y; g.amap = rows_dense(d); g.Bt = P.Wvg_t; g.ldb = d; g.bias = P.b_vg;
+    g.C = ug; g.cmap = rows_dense(2 * d); g.ccol = cols_dense(); g.M = (int)rows; g.N = 2 * d; g.K = d;
+    CHECK(gemm_site(h, SITE_EMB, g, st));
+  }
+  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, (const T*)ug, tt, rows, d);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_h1_from_state<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, D, Wc, w0,
+                     (const char*)state, S, hk);
+  CHECK(hipGetLastError());
+  for (int k = 0; k < D.L; ++k) {
+    GemmArgs g{};
+    g.A = hk + (int64_t)k * rows * d; g.amap = rows_dense(d);
+    g.Bt = (const char*)P.mlp_t + (size_t)k * d * d * h->gsize; g.ldb = d; g.bias = P.mlp_b + (int64_t)k * d;
+    g.C = zk + (int64_t)k * rows * d; g.cmap = rows_dense(d); g.ccol = cols_dense(); g.M = (int)rows; g.N = d; g.K = d;
+    CHECK(gemm_site(h, SITE_EMB, g, st));
+    hipLaunchKernelGGL(k_silu_inplace<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st,
+                       (const T*)(zk + (int64_t)k * rows * d), hk + (int64_t)(k + 1) * rows * d, rows * d);
+    CHECK(hipGetLastError());
+  }
+  const T* hL = hk + (int64_t)D.L * rows * d;
+  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, st, P, Rc, rows, basis);
+  CHECK(hipGetLastError());
+
+  // ---- orbitals and envelopes backward
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, hbar, rows * d, T(0));
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, st, bbar, rows * D.B, T(0));
+  CHECK(hipGetLastError());
+  for (int s = 0; s < 2; ++s) {
+    const int N = D.nsig(s), e0 = s == 0 ? 0 : D.nu, KN = D.K * N;
+    if (N == 0) continue;
+    T* o = (T*)(ws + L.o[s]);
+    T* ob = (T*)(ws + L.obar[s]);
+    const RowMap sm{N, (int64_t)n * d, d};
+    GemmArgs g{};
+    g.A = hL + (int64_t)e0 * d; g.amap = sm; g.Bt = s == 0 ? P.orb_t0 : P.orb_t1; g.ldb = d;
+    g.C = o; g.cmap = rows_dense(KN); g.ccol = cols_dense(); g.M = Wc * N; g.N = KN; g.K = d;
+    CHECK(gemm_site(h, SITE_ORB, g, st));
+    const int64_t tot = (int64_t)Wc * N * KN;
+    if (h->isize == 8)
+      hipLaunchKernelGGL((k_orb_bar<T, double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, Wc, w0,
+                         (const char*)state, S, coeff, o, ob);
+    else
+      hipLaunchKernelGGL((k_orb_bar<T, float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, Wc, w0,
+                         (const char*)state, S, coeff, o, ob);
+    CHECK(hipGetLastError());
+    // W_orb grad: [d][K N] -> orb_W[det][k][l]
+    CHECK(wgrad<T>(h, L, ws, hL + (int64_t)e0 * d, sm, Wc * N, d, ob, rows_dense(KN), KN, grad,
+                   th(s == 0 ? "orb_W_up" : "orb_W_dn"), N, N, (int64_t)d * N, 1, st));
+    // pi grad: [B][K N] -> env_pi[(det,l)][b]
+    const RowMap bm{N, (int64_t)n * D.B, D.B};
+    CHECK(wgrad<T>(h, L, ws, basis + (int64_t)e0 * D.B, bm, Wc * N, D.B, o, rows_dense(KN), KN, grad,
+                   th(s == 0 ? "env_pi_up" : "env_pi_dn"), 1, (int64_t)1 << 40, 0, D.B, st));
+    // hbar = obar W^T,  basisbar = envbar pi
+    GemmArgs hb{};
+    hb.A = ob; hb.amap = rows_dense(KN); hb.Bt = s == 0 ? P.orb_n0 : P.orb_n1; hb.ldb = KN;
+    hb.C = hbar + (int64_t)e0 * d; hb.cmap = sm; hb.ccol = cols_dense(); hb.M = Wc * N; hb.N = d; hb.K = KN;
+    CHECK(gemm_site(h, SITE_GRAD, hb, st));
+    GemmArgs bb{};
+    bb.A = o; bb.amap = rows_dense(KN); bb.Bt = s == 0 ? P.pi_n0 : P.pi_n1; bb.ldb = KN;
+    bb.C = bbar + (int64_t)e0 * D.B; bb.cmap = bm; bb.ccol = cols_dense(); bb.M = Wc * N; bb.N = D.B; bb.K = KN;
+    CHECK(gemm_site(h, SITE_GRAD, bb, st));
+    // envelope exponents
+    T* part = (T*)(ws + L.split);
+    hipLaunchKernelGGL(k_envsig_bar<T>, dim3((D.B + 255) / 256, GNS), dim3(256), 0, st, P, Rc, e0, N, Wc,
+                       (const T*)(bbar + (int64_t)e0 * D.B), GNS, part);
+    CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_splits<T>, dim3((D.B + 255) / 256), dim3(256), 0, st, (const T*)part, GNS, 1, D.B,
+                       grad, th("env_sigma"), (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
+    CHECK(hipGetLastError());
+  }
+  // ---- MLP backward
+  T* hb_cur = hbar;
+  T* hb_nxt = hbar2;
+  for (int k = D.L - 1; k >= 0; --k) {
+    const T* z = zk + (int64_t)k * rows * d;
+    const T* hin = hk + (int64_t)k * rows * d;
+    hipLaunchKernelGGL(k_silu_bar<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, z,
+                       (const T*)hb_cur, zbar, rows * d);
+    CHECK(hipGetLastError());
+    CHECK(wgrad<T>(h, L, ws, hin, rows_dense(d), (int)rows, d, zbar, rows_dense(d), d, grad,
+                   th("mlp_W") + (int64_t)k * d * d, d, (int64_t)1 << 40, 0, 1, st));
+    CHECK(bgrad<T>(L, ws, zbar, rows_dense(d), (int)rows, d, grad, th("mlp_b") + (int64_t)k * d, st));
+    GemmArgs g{};
+    g.A = zbar; g.amap = rows_dense(d); g.Bt = (const char*)P.mlp_n + (size_t)k * d * d * h->gsize; g.ldb = d;
+    g.C = hb_nxt; g.cmap = rows_dense(d); g.ccol = cols_dense(); g.M = (int)rows; g.N = d; g.K = d;
+    CHECK(gemm_site(h, SITE_GRAD, g, st));
+    T* t = hb_cur; hb_cur = hb_nxt; hb_nxt = t;
+  }
+  // hb_cur = d/d h1 = mbar;  h0bar starts as h1bar
+  CHECK(hipMemcpyAsync(h0bar, hb_cur, (size_t)rows * d * sizeof(T), hipMemcpyDeviceToDevice, st));
+  // ---- messages backward
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)((rows * 4 * d + 255) / 256)), dim3(256), 0, st, projbar, rows * 4 * d,
+                     T(0));
+  CHECK(hipGetLastError());
+  const FiltOff fo = filt_off(D);
+  const size_t msg_lds = (size_t)2 * (fo.W3 + D.G) * sizeof(T);
+  CHECK(hipFuncSetAttribute((const void*)k_msg_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)msg_lds));
+  const int nb_msg = rows < GBLK ? (int)rows : GBLK;
+  hipLaunchKernelGGL(k_msg_bwd<T>, dim3(nb_msg), dim3(blk), msg_lds, st, P, Rc, rows, w0, (const int16_t*)nidx,
+                     (const int32_t*)ncnt, (const char*)state, S, (const T*)hb_cur, projbar, epart);
+  CHECK(hipGetLastError());
+  {
+    const int ps = msg_part_size(D);
+    for (int a = 0; a < 2; ++a) {
+      const int64_t o = (int64_t)a * (fo.size + 5 * d);
+      auto red = [&](int64_t col, int len, int64_t base) {
+        hipLaunchKernelGGL(k_reduce_cols, dim3((len + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
+                           nb_msg, (int64_t)ps, o + col, len, grad, base);
+        return hipGetLastError();
+      };
+      CHECK(red(fo.W1, 4 * D.h1, th("ee_W1") + a * 4 * D.h1));
+      CHECK(red(fo.b1, D.h1, th("ee_b1") + a * D.h1));
+      CHECK(red(fo.W2, D.h1 * D.h2, th("ee_W2") + a * D.h1 * D.h2));
+      CHECK(red(fo.b2, D.h2, th("ee_b2") + a * D.h2));
+      CHECK(red(fo.W3, D.h2 * d, th("ee_W3") + (int64_t)a * D.h2 * d));
+      CHECK(red(fo.Wenv, D.G * d, th("ee_Wenv") + (int64_t)a * D.G * d));
+      CHECK(red(fo.sig, D.G, th("ee_sig") + a * D.G));
+      CHECK(red(fo.size, 4 * d, th("msg_We") + (int64_t)a * 4 * d));
+      CHECK(red(fo.size + 4 * d, d, th("msg_b") + (int64_t)a * d));
+    }
+  }
+  // ---- node projections: W_proj grad and h0bar += projbar W_proj^T
+  CHECK(wgrad<T>(h, L, ws, (const T*)(st_base + S.h0), h0map, (int)rows, d, projbar, rows_dense(4 * d), 4 * d, grad,
+                 th("msg_Wa"), d, d, (int64_t)d * d, 1, st));
+  {
+    GemmArgs g{};
+    g.A = projbar; g.amap = rows_dense(4 * d); g.Bt = P.Wproj_n; g.ldb = 4 * d;
+    g.C = h0bar; g.cmap = rows_dense(d); g.ccol = cols_dense(); g.M = (int)rows; g.N = d; g.K = 4 * d;
+    g.accumulate = 1;
+    CHECK(gemm_site(h, SITE_GRAD, g, st));
+  }
+  // ---- GLU backward
+  CHECK(wgrad<T>(h, L, ws, tt, rows_dense(d), (int)rows, d, h0bar, rows_dense(d), d, grad, th("glu_Wo"), d,
+                 (int64_t)1 << 40, 0, 1, st));
+  CHECK(bgrad<T>(L, ws, h0bar, rows_dense(d), (int)rows, d, grad, th("glu_bo"), st));
+  {
+    GemmArgs g{};
+    g.A = h0bar; g.amap = rows_dense(d); g.Bt = P.Wo_n; g.ldb = d;
+    g.C = tbar; g.cmap = rows_dense(d); g.ccol = cols_dense(); g.M = (int)rows; g.N = d; g.K = d;
+    CHECK(gemm_site(h, SITE_GRAD, g, st));
+  }
+  hipLaunchKernelGGL(k_glu_bar<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, (const T*)ug,
+                     (const T*)tbar, ugbar, rows, d);
+  CHECK(hipGetLastError());
+  CHECK(wgrad<T>(h, L, ws, y, rows_dense(d), (int)rows, d, ugbar, rows_dense(2 * d), d, grad, th("glu_Wv"), d,
+                 (int64_t)1 << 40, 0, 1, st));
+  CHECK(wgrad<T>(h, L, ws, y, rows_dense(d), (int)rows, d, ugbar + d, rows_dense(2 * d), d, grad, th("glu_Wg"), d,
+                 (int64_t)1 << 40, 0, 1, st));
+  CHECK(bgrad<T>(L, ws, ugbar, rows_dense(2 * d), (int)rows, d, grad, th("glu_bv"), st));
+  CHECK(bgrad<T>(L, ws, ugbar + d, rows_dense(2 * d), (int)rows, d, grad, th("glu_bg"), st));
+  {
+    GemmArgs g{};
+    g.A = ugbar; g.amap = rows_dense(2 * d); g.Bt = P.Wvg_n; g.ldb = 2 * d;
+    g.C = ybar; g.cmap = rows_dense(d); g.ccol = cols_dense(); g.M = (int)rows; g.N = d; g.K = 2 * d;
+    CHECK(gemm_site(h, SITE_GRAD, g, st));
+  }
+  // ---- LayerNorm and electron-nucleus backward
+  const int nb_ln = rows < GBLK ? (int)rows : GBLK;
+  hipLaunchKernelGGL(k_ln_bwd<T>, dim3(nb_ln), dim3(blk), 0, st, P, Rc, rows, (const T*)ybar, sbar, epart);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_cols, dim3((d + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
+                     (int64_t)2 * d, (int64_t)0, d, grad, th("ln_g"));
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_cols, dim3((d + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
+                     (int64_t)2 * d, (int64_t)d, d, grad, th("ln_b"));
+  CHECK(hipGetLastError());
+  {
+    const EnOff eo = en_off(D);
+    const size_t en_lds = ((size_t)ENCH * d + ENCH * 5 * D.h1 + D.h1 * D.h2 + D.h2 + D.G) * sizeof(T);
+    CHECK(hipFuncSetAttribute((const void*)k_en_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)en_lds));
+    const int nmc = (D.M + ENCH - 1) / ENCH;
+    const int nbx = rows < GBLK ? (int)rows : GBLK;
+    hipLaunchKernelGGL(k_en_bwd<T>, dim3(nbx, nmc), dim3(blk), en_lds, st, P, Rc, rows, (const T*)sbar, epart);
+    CHECK(hipGetLastError());
+    const int nbt = nbx * nmc;
+    auto red = [&](int64_t col, int len, int64_t base) {
+      hipLaunchKernelGGL(k_reduce_cols, dim3((len + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
+                         nbt, (int64_t)eo.size, col, len, grad, base);
+      return hipGetLastError();
+    };
+    CHECK(red(eo.nuc, D.NT * d, th("nuc_emb")));
+    CHECK(red(eo.W1, D.NT * 4 * D.h1, th("en_W1")));
+    CHECK(red(eo.b1, D.NT * D.h1, th("en_b1")));
+    CHECK(red(eo.W2, D.h1 * D.h2, th("en_W2")));
+    CHECK(red(eo.b2, D.h2, th("en_b2")));
+    CHECK(red(eo.W3, D.h2 * d, th("en_W3")));
+    CHECK(red(eo.Wenv, D.G * d, th("en_Wenv")));
+    CHECK(red(eo.sig, D.G, th("en_sig")));
+    CHECK(red(eo.Wn, 4 * d, th("en_Wn")));
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff,
+                            double* grad, int32_t* status, hipStream_t st) {
+  Net<T> P = make_net<T>(h);
+  const GradLayout L = grad_layout(h, W);
+  CHECK(fill_i32(status, W, 0, st));
+  hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((h->P + 255) / 256)), dim3(256), 0, st, grad, (int64_t)h->P, 0.0);
+  CHECK(hipGetLastError());
+  for (int w0 = 0; w0 < W; w0 += L.Wc) {
+    const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
+    CHECK(grad_chunk<T>(h, P, w0, wc, R, state, ws, coeff, grad, status, st));
+  }
+  return hipSuccess;
+}
+
+hipError_t grad_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff, double* grad,
+                     int32_t* status, hipStream_t s) {
+  const Dims& D = h->D;
+  if (D.M > 4096 || D.d > 256) return hipErrorInvalidValue;
+  return h->tsize == 8 ? grad_impl<double>(h, W, R, state, ws, coeff, grad, status, s)
+                       : grad_impl<float>(h, W, R, state, ws, coeff, grad, status, s);
+}
+
+}  // namespace fire

@@ -33,7 +33,7 @@ struct ParamsLayout {
   // GEMM operands Bt[N][K] in the GEMM type G
   size_t Wvg_t, Wo_t, Wproj_t, mlp_t, orb_t0, orb_t1, pi0, pi1;
   // GEMM operands in the adjoint orientation (B = W^T): Bt = W, type G
-  size_t Wvg_n, Wo_n, Wproj_n, mlp_n, orb_n0, orb_n1;
+  size_t Wvg_n, Wo_n, Wproj_n, mlp_n, orb_n0, orb_n1, pi_n0, pi_n1;
   // low bf16 parts of every GEMM operand above live at (offset + lo_delta)
   size_t lo_delta;
   // molecule
@@ -88,7 +88,7 @@ hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, 
 inline int gemm_kind(int prec) { return prec == FIRE_FP64 ? MMA_F64 : (prec == FIRE_FP32 ? MMA_F32 : MMA_BF16); }
 
 // GEMM call sites (bits of Dims::split)
-enum GemmSite { SITE_EMB = 1, SITE_ORB = 2, SITE_JET = 4 };
+enum GemmSite { SITE_EMB = 1, SITE_ORB = 2, SITE_JET = 4, SITE_GRAD = 8 };
 
 // Launch a GEMM whose Bt lies in the packed params buffer, choosing the MFMA
 // kind of the handle's precision for this site.
@@ -102,5 +102,7 @@ inline hipError_t gemm_site(const fire_handle* h, int site, GemmArgs g, hipStrea
 }
 
 static inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+int64_t theta_offset(const fire_handle* h, const char* name);
 
 }  // namespace fire

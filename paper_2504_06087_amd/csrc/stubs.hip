@@ -1,13 +1,13 @@
-// Workspace sizing across entry points and the parameter-gradient entry (adjoint).
+// Workspace sizing across entry points.
 #include "laplacian.hpp"
 #include "update.hpp"
 namespace fire {
+size_t grad_ws_bytes(const fire_handle* h, int W);
 size_t workspace_bytes_for(const fire_handle* h, int W) {
-  size_t a = ws_forward(h, W).total, b = upd_layout(h, W).total, c = lap_ws_bytes(h, W), d = ecp_ws_bytes(h, W);
-  size_t m = a > b ? a : b;
-  m = m > c ? m : c;
-  return m > d ? m : d;
+  const size_t v[5] = {ws_forward(h, W).total, upd_layout(h, W).total, lap_ws_bytes(h, W), ecp_ws_bytes(h, W),
+                       grad_ws_bytes(h, W)};
+  size_t m = 0;
+  for (size_t x : v) m = x > m ? x : m;
+  return m;
 }
-hipError_t grad_path(fire_handle*, int, const double*, char*, char*, const double*, double*, int32_t*,
-                     hipStream_t) { return hipErrorNotSupported; }
-}
+}  // namespace fire

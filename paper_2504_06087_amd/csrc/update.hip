@@ -18,7 +18,7 @@ namespace fire {
 
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-UpdLayout upd_layout(const fire_handle* h, int W) {
+UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
   const Dims& D = h->D;
   UpdLayout L{};
   size_t o = 0, ts = h->tsize, is = h->isize;
@@ -42,7 +42,8 @@ UpdLayout upd_layout(const fire_handle* h, int W) {
   int nmax = D.nu > D.nd ? D.nu : D.nd;
   L.envnew = take(Wl * D.K * nmax * ts);
   for (int s = 0; s < 2; ++s) {
-    int64_t rows = Wl * (L.capS[s] > 0 ? L.capS[s] : 1);
+    const int per = L.capS[s] < kRowsPerJob ? L.capS[s] : kRowsPerJob;
+    int64_t rows = Wl * (per > 0 ? per : 1);
     int N = D.nsig(s) > 0 ? D.nsig(s) : 1;
     L.rowcap[s] = rows;
     L.rowinfo[s] = take(rows * 2 * 4);
@@ -50,24 +51,23 @@ UpdLayout upd_layout(const fire_handle* h, int W) {
     L.hseg[s][1] = take(rows * D.d * ts);
     L.mseg[s] = take(rows * D.d * ts);
     L.oseg[s] = take(rows * D.K * N * ts);
-    L.dphi[s] = take(rows * D.K * N * is);
+    L.dphi[s] = take(rows * D.K * N * ts);
+    L.bbuf[s] = with_woodbury ? take(rows * D.K * N * 8) : 0;
   }
   L.total = o;
   return L;
 }
 
 static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
-
-// LDS bytes of the Woodbury kernel for spin block s
-static size_t woodbury_lds(const Dims& D, const UpdLayout& L, int s) {
-  int N = D.nsig(s), k = L.capS[s];
-  return (size_t)(WB_RB * N + 2 * k * N + k * (k + 1) + 2 * WB_RB * k + N + 2 * k + 8) * sizeof(double);
+static size_t detA_staged_lds(int N, int capmax) {
+  return (size_t)(2 * KS * N + capmax * (capmax + 1) + 2 * capmax + 8) * sizeof(double);
 }
+static size_t wb_rows_lds(int N) { return (size_t)(2 * KS * N + WB_RB * N + WB_RB * KS + 8) * sizeof(double); }
+
 bool update_fits(const fire_handle* h) {
   UpdLayout L = upd_layout(h, 1);
-  for (int s = 0; s < 2; ++s)
-    if (h->D.nsig(s) > 0 && woodbury_lds(h->D, L, s) > 160 * 1024) return false;
-  return true;
+  const int N = h->D.nu > h->D.nd ? h->D.nu : h->D.nd;
+  return L.capmax <= 128 && detA_staged_lds(N, L.capmax) <= 160 * 1024 && wb_rows_lds(N) <= 160 * 1024;
 }
 
 // ---------------------------------------------------------------------------
@@ -135,8 +135,12 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
   }
 }
 
-// exclusive scan of the per-spin member counts: off[s][w], off[s][W] = total
-__global__ __launch_bounds__(1024) void k_scan_counts(const int* __restrict__ ucnt, int W, int* __restrict__ off) {
+// exclusive scan of the per-spin member counts: off[s][w], off[s][W] = total.
+// A job whose rows would end beyond the segment capacity gets zero members
+// (it is skipped) and its walker is flagged.
+__global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, int W, int* __restrict__ off,
+                                                      int64_t cap0, int64_t cap1, const int* __restrict__ jw,
+                                                      int32_t* __restrict__ status) {
   __shared__ int part[2][1024];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (W + nt - 1) / nt;
@@ -156,8 +160,19 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int* __restrict__ uc
   for (int w = b; w < e; ++w) {
     off[w] = a0;
     off[(W + 1) + w] = a1;
-    a0 += ucnt[2 * w];
-    a1 += ucnt[2 * w + 1];
+    const int c0 = ucnt[2 * w], c1 = ucnt[2 * w + 1];
+    if (a0 + c0 > cap0 || a1 + c1 > cap1) {
+      if (c0 + c1 > 0) atomicOr(status + (jw ? jw[w] : w), FIRE_W_UPD_OVERFLOW);
+      ucnt[2 * w] = 0;
+      ucnt[2 * w + 1] = 0;
+    }
+    a0 += c0;
+    a1 += c1;
+  }
+  __syncthreads();
+  if (t < 2) {
+    const int64_t cap = t == 0 ? cap0 : cap1;
+    if (off[t * (W + 1) + W] > cap) off[t * (W + 1) + W] = (int)cap;
   }
 }
 
@@ -264,11 +279,11 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
 
 // Phi' rows = o' * env (cached env, or the moved electron's new env) and
 // dPhi = Phi' - Phi in the inverse's precision.  One thread per element.
-template <typename T, typename TI>
+template <typename T>
 __global__ void k_dphi(const Dims D, int s, int e, const int* __restrict__ jw, const int* __restrict__ rinfo,
                        const int* __restrict__ Mdev,
                        T* __restrict__ oseg, const char* __restrict__ state, StateRec S,
-                       const T* __restrict__ envnew, TI* __restrict__ dphi) {
+                       const T* __restrict__ envnew, T* __restrict__ dphi) {
   const int N = D.nsig(s);
   const int KN = D.K * N;
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -286,50 +301,90 @@ __global__ void k_dphi(const Dims D, int s, int e, const int* __restrict__ jw, c
   const T pn = oseg[q] * env;
   const T po = ((const T*)(rec + S.phi))[idx];
   oseg[q] = pn;
-  dphi[q] = (TI)pn - (TI)po;
+  dphi[q] = pn - po;
 }
 
-// det A for every (walker, determinant, spin block); A = I + dPhi_U G_U^T.
-template <typename TI>
-__global__ __launch_bounds__(64) void k_detA(const Dims D, int W, const int* __restrict__ jw, int s,
-                                             const int* __restrict__ uidx, int capmax,
-                                             const int* __restrict__ ucnt, const int* __restrict__ off,
-                                             const TI* __restrict__ dphi, const char* __restrict__ state,
-                                             StateRec S, double* __restrict__ detA) {
+// A = I + dPhi_U G_U^T for one (job, determinant, spin block) into LDS:
+// one wave per row a, lanes over the orbital index l, G rows read coalesced.
+template <typename TD, typename TI>
+FIRE_DEV void build_A(double* A, int LD, int k, int N, const TD* __restrict__ dp_rows, int64_t dp_stride,
+                      const TI* __restrict__ G, const int* __restrict__ lst, int e0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int a = wave; a < k; a += nw) {
+    const TD* dp = dp_rows + (int64_t)a * dp_stride;
+    double x0 = lane < N ? (double)dp[lane] : 0.0;
+    double x1 = lane + 64 < N ? (double)dp[lane + 64] : 0.0;
+    for (int b = 0; b < k; ++b) {
+      const TI* gb = G + (int64_t)(lst[b] - e0) * N;
+      double v = x0 * (lane < N ? (double)gb[lane] : 0.0) + x1 * (lane + 64 < N ? (double)gb[lane + 64] : 0.0);
+      v = wave_sum(v);
+      if (lane == 0) A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
+    }
+  }
+}
+
+// det A for every (job, determinant, spin block); A = I + dPhi_U G_U^T.
+// A workgroup takes jg consecutive jobs of one determinant (the quadrature
+// points of one electron-atom pair share most G rows, which then hit cache);
+// rows are staged through LDS when |U_s| <= KS.
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __restrict__ jw, int s,
+                                              const int* __restrict__ uidx, int capmax,
+                                              const int* __restrict__ ucnt, const int* __restrict__ off,
+                                              const T* __restrict__ dphi, const char* __restrict__ state,
+                                              StateRec S, double* __restrict__ detA, int jg) {
   extern __shared__ double lds[];
   __shared__ double sc[2];
   __shared__ int fl[2];
-  const int j = blockIdx.x / D.K, det = blockIdx.x % D.K;
-  const int w = jw ? jw[j] : j;
-  const int N = D.nsig(s);
-  const int k = ucnt[2 * j + s];
-  double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
-  if (k == 0) {
-    if (threadIdx.x == 0) { out[0] = 1.0; out[1] = 0.0; }
-    return;
-  }
-  const int LD = k + 1;
-  double* A = lds;
-  double* f = lds + k * LD;
-  int* pm = (int*)(f + k);
-  const int q0 = off[s * (W + 1) + j];
+  const int g = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
-  const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
-  const TI* G = (const TI*)(state + (int64_t)w * S.stride + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
-  const int KN = D.K * N;
-  for (int q = threadIdx.x; q < k * k; q += blockDim.x) {
-    const int a = q / k, b = q % k;
-    const TI* dp = dphi + (int64_t)(q0 + a) * KN + det * N;
-    const TI* gb = G + (int64_t)(lst[b] - e0) * N;
-    double acc = (a == b) ? 1.0 : 0.0;
-    for (int l = 0; l < N; ++l) acc += (double)dp[l] * (double)gb[l];
-    A[a * LD + b] = acc;
-  }
-  __syncthreads();
-  gj_block(A, k, LD, f, pm, sc, fl, false);
-  if (threadIdx.x == 0) {
-    if (fl[1]) { out[0] = 0.0; out[1] = -INFINITY; }
-    else { out[0] = sc[0]; out[1] = sc[1]; }
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* Gs = lds;                      // [KS][N]
+  double* Ds = Gs + KS * N;              // [KS][N]
+  double* A = Ds + KS * N;               // [capmax][capmax+1]
+  double* f = A + capmax * (capmax + 1); // [capmax]
+  int* pm = (int*)(f + capmax);
+  for (int jj = 0; jj < jg; ++jj) {
+    const int j = g * jg + jj;
+    if (j >= W) break;
+    const int w = jw ? jw[j] : j;
+    const int k = ucnt[2 * j + s];
+    double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
+    if (k == 0) {
+      if (tid == 0) { out[0] = 1.0; out[1] = 0.0; }
+      continue;
+    }
+    const int LD = k + 1;
+    const int q0 = off[s * (W + 1) + j];
+    const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+    const TI* G = (const TI*)(state + (int64_t)w * S.stride + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+    const T* dp = dphi + (int64_t)q0 * KN + det * N;
+    if (k <= KS) {
+      for (int q = tid; q < k * N; q += nt) {
+        const int a = q / N, l = q - a * N;
+        Ds[q] = (double)dp[(int64_t)a * KN + l];
+        Gs[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
+      }
+      __syncthreads();
+      for (int q = tid; q < k * k; q += nt) {
+        const int a = q / k, b = q - a * k;
+        const double* da = Ds + a * N;
+        const double* gb = Gs + b * N;
+        double v = 0.0;
+        for (int l = 0; l < N; ++l) v += da[l] * gb[l];
+        A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
+      }
+    } else {
+      build_A<T, TI>(A, LD, k, N, dp, KN, G, lst, e0);
+    }
+    __syncthreads();
+    gj_block(A, k, LD, f, pm, sc, fl, false);
+    if (tid == 0) {
+      if (fl[1]) { out[0] = 0.0; out[1] = -INFINITY; }
+      else { out[0] = sc[0]; out[1] = sc[1]; }
+    }
+    __syncthreads();
   }
 }
 
@@ -379,14 +434,18 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
   n_accept[w] += 1;
 }
 
-// Woodbury update of G for accepted walkers and commit of the Phi rows of U.
-// Rows of G are processed in blocks of WB_RB rows staged through LDS.
+// Woodbury update of G for accepted walkers, in two kernels:
+//   k_woodbury_prep (per walker, determinant, spin block): A, A^-1 and
+//     B = A^-T G_U (k x N, into the workspace), and the commit of Phi rows;
+//   k_woodbury_rows (per block of WB_RB rows of G): Z = G dPhi_U^T and
+//     G' = G - Z B, one read and one write of every row of G.
 template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx,
-                                                  int capmax, const int* __restrict__ ucnt,
-                                                  const int* __restrict__ off, const int* __restrict__ acc,
-                                                  const TI* __restrict__ dphi, const T* __restrict__ oseg,
-                                                  char* __restrict__ state, StateRec S, int32_t* status) {
+__global__ __launch_bounds__(256) void k_woodbury_prep(const Dims D, int W, int s, const int* __restrict__ uidx,
+                                                       int capmax, const int* __restrict__ ucnt,
+                                                       const int* __restrict__ off, const int* __restrict__ acc,
+                                                       const T* __restrict__ dphi, const T* __restrict__ oseg,
+                                                       double* __restrict__ Bbuf, char* __restrict__ state,
+                                                       StateRec S, int32_t* status) {
   extern __shared__ double lds[];
   __shared__ int perm[128];
   __shared__ double sc[2];
@@ -396,72 +455,103 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
   if (!acc[w] || k == 0) return;
   const int N = D.nsig(s);
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* dP = lds;               // [k][N]
-  double* GU = dP + k * N;        // [k][N]
-  double* Ai = GU + k * N;        // [k][k+1]
-  double* GB = Ai + k * (k + 1);  // [WB_RB][N]
-  double* Z = GB + WB_RB * N;     // [WB_RB][k]
-  double* V = Z + WB_RB * k;      // [WB_RB][k]
-  double* f = V + WB_RB * k;      // [k]
   const int LD = k + 1;
+  double* Ai = lds;               // [k][k+1]
+  double* f = Ai + k * LD;        // [k]
   const int q0 = off[s * (W + 1) + w];
   const int e0 = s == 0 ? 0 : D.nu;
   const int* lst = uidx + ((int64_t)w * 2 + s) * capmax;
   const int KN = D.K * N;
   char* rec = state + (int64_t)w * S.stride;
-  TI* G = (TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+  const TI* G = (const TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
   T* phi = (T*)(rec + S.phi) + det * phi_per_det(D) + phi_block_off(D, s);
-  for (int q = tid; q < k * N; q += nt) {
-    const int a = q / N, l = q % N;
-    dP[q] = (double)dphi[(int64_t)(q0 + a) * KN + det * N + l];
-    GU[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
-  }
-  __syncthreads();
-  for (int q = tid; q < k * k; q += nt) {
-    const int a = q / k, b = q % k;
-    double v = (a == b) ? 1.0 : 0.0;
-    for (int l = 0; l < N; ++l) v += dP[a * N + l] * GU[b * N + l];
-    Ai[a * LD + b] = v;
-  }
+  build_A<T, TI>(Ai, LD, k, N, dphi + (int64_t)q0 * KN + det * N, KN, G, lst, e0);
   __syncthreads();
   gj_block(Ai, k, LD, f, perm, sc, fl, true);
   if (fl[1]) {
     if (tid == 0) atomicOr(status + w, FIRE_W_SINGULAR);
     return;
   }
-  for (int m0 = 0; m0 < N; m0 += WB_RB) {
-    const int rb = N - m0 < WB_RB ? N - m0 : WB_RB;
-    for (int q = tid; q < rb * N; q += nt) GB[q] = (double)G[(int64_t)m0 * N + q];
-    __syncthreads();
-    // Z[m][a] = sum_l G[m][l] dPhi[a][l]
-    for (int q = tid; q < rb * k; q += nt) {
-      const int m = q / k, a = q % k;
-      double v = 0.0;
-      for (int l = 0; l < N; ++l) v += GB[m * N + l] * dP[a * N + l];
-      Z[q] = v;
-    }
-    __syncthreads();
-    // V[m][b] = sum_a Z[m][a] (A^-1)[b][a]
-    for (int q = tid; q < rb * k; q += nt) {
-      const int m = q / k, b = q % k;
-      double v = 0.0;
-      for (int a = 0; a < k; ++a) v += Z[m * k + a] * Ai[b * LD + a];
-      V[q] = v;
-    }
-    __syncthreads();
-    // G'[m][l] = G[m][l] - sum_b V[m][b] G_U[b][l]
-    for (int q = tid; q < rb * N; q += nt) {
-      const int m = q / N, l = q % N;
-      double v = GB[q];
-      for (int b = 0; b < k; ++b) v -= V[m * k + b] * GU[b * N + l];
-      G[(int64_t)m0 * N + q] = (TI)v;
-    }
-    __syncthreads();
+  // B[a][l] = sum_b (A^-1)[b][a] G[u_b][l]
+  double* B = Bbuf + (int64_t)q0 * KN + det * N;
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q % N;
+    double v = 0.0;
+    for (int b = 0; b < k; ++b) v += Ai[b * LD + a] * (double)G[(int64_t)(lst[b] - e0) * N + l];
+    B[(int64_t)a * KN + l] = v;
   }
   // commit the new Phi rows of this determinant and spin block
   for (int q = tid; q < k * N; q += nt) {
     const int a = q / N, l = q % N;
     phi[(int64_t)(lst[a] - e0) * N + l] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
+  }
+}
+
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_woodbury_rows(const Dims D, int W, int s, const int* __restrict__ ucnt,
+                                                       const int* __restrict__ off, const int* __restrict__ acc,
+                                                       const T* __restrict__ dphi, const double* __restrict__ Bbuf,
+                                                       char* __restrict__ state, StateRec S,
+                                                       const int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int N = D.nsig(s);
+  const int nrb = (N + WB_RB - 1) / WB_RB;
+  const int rb = blockIdx.x % nrb;
+  const int det = (blockIdx.x / nrb) % D.K;
+  const int w = blockIdx.x / (nrb * D.K);
+  const int k = ucnt[2 * w + s];
+  if (!acc[w] || k == 0 || (status[w] & FIRE_W_SINGULAR)) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int q0 = off[s * (W + 1) + w];
+  const int KN = D.K * N;
+  TI* G = (TI*)(state + (int64_t)w * S.stride + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+  const T* dp = dphi + (int64_t)q0 * KN + det * N;
+  const double* B = Bbuf + (int64_t)q0 * KN + det * N;
+  const int m0 = rb * WB_RB;
+  const int rows = N - m0 < WB_RB ? N - m0 : WB_RB;
+  if (k <= KS) {
+    double* Ps = lds;                 // [k][N]
+    double* Bs = Ps + KS * N;         // [k][N]
+    double* Gr = Bs + KS * N;         // [rows][N]
+    double* Z = Gr + WB_RB * N;       // [rows][k]
+    for (int q = tid; q < k * N; q += nt) {
+      const int a = q / N, l = q - a * N;
+      Ps[q] = (double)dp[(int64_t)a * KN + l];
+      Bs[q] = B[(int64_t)a * KN + l];
+    }
+    for (int q = tid; q < rows * N; q += nt) Gr[q] = (double)G[(int64_t)m0 * N + q];
+    __syncthreads();
+    for (int q = tid; q < rows * k; q += nt) {
+      const int m = q / k, a = q - m * k;
+      double v = 0.0;
+      for (int l = 0; l < N; ++l) v += Gr[m * N + l] * Ps[a * N + l];
+      Z[q] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < rows * N; q += nt) {
+      const int m = q / N, l = q - m * N;
+      double v = Gr[q];
+      for (int a = 0; a < k; ++a) v -= Z[m * k + a] * Bs[a * N + l];
+      G[(int64_t)m0 * N + q] = (TI)v;
+    }
+    return;
+  }
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (int m = m0 + wave; m < m0 + rows; m += nw) {
+    TI* gm = G + (int64_t)m * N;
+    double g0 = lane < N ? (double)gm[lane] : 0.0;
+    double g1 = lane + 64 < N ? (double)gm[lane + 64] : 0.0;
+    double n0 = g0, n1 = g1;
+    for (int a = 0; a < k; ++a) {
+      const T* pa = dp + (int64_t)a * KN;
+      double z = g0 * (lane < N ? (double)pa[lane] : 0.0) + g1 * (lane + 64 < N ? (double)pa[lane + 64] : 0.0);
+      z = wave_sum(z);
+      const double* ba = B + (int64_t)a * KN;
+      if (lane < N) n0 -= z * ba[lane];
+      if (lane + 64 < N) n1 -= z * ba[lane + 64];
+    }
+    if (lane < N) gm[lane] = (TI)n0;
+    if (lane + 64 < N) gm[lane + 64] = (TI)n1;
   }
 }
 
@@ -529,7 +619,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   const Dims& D = h->D;
   const StateRec& S = h->st;
   const int W = jb.J;
-  const UpdLayout L = upd_layout(h, jb.Jcap > 0 ? jb.Jcap : jb.J);
+  const UpdLayout L = upd_layout(h, jb.Jcap > 0 ? jb.Jcap : jb.J, jb.woodbury);
   const int se = e < D.nu ? 0 : 1;
   const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
   double* rnew = (double*)(ws + L.rnew);
@@ -546,11 +636,13 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   hipLaunchKernelGGL(k_propose, dim3((W + 3) / 4), dim3(256), 0, st, R, jb, D.n, D.nu, e, D.cut * D.cut,
                      L.capS[0], L.capS[1], L.capmax, rnew, uidx, ucnt, status);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off, L.rowcap[0], L.rowcap[1], jb.jw,
+                     status);
   CHECK(hipGetLastError());
   // h0 and projections of the moved electron
-  hipLaunchKernelGGL(k_en_embed<T>, dim3((W + EPB - 1) / EPB), dim3(blk), 0, st, P, (const double*)rnew,
-                     (int64_t)W, y);
+  const int epb = W >= 32768 ? 4 : 1;
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((W + epb - 1) / epb), dim3(blk), 0, st, P, (const double*)rnew,
+                     (int64_t)W, y, epb);
   CHECK(hipGetLastError());
   {
     GemmArgs g{};
@@ -618,22 +710,24 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
     CHECK(gemm_site(h, SITE_ORB, o, st));
     const int64_t tot = (int64_t)rows * D.K * N;
+    hipLaunchKernelGGL((k_dphi<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e, jb.jw,
+                       (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew, (T*)(ws + L.dphi[s]));
+    CHECK(hipGetLastError());
+    const int jg = jb.group > 0 ? jb.group : 1;
+    const size_t lds = detA_staged_lds(N, L.capmax);
+    const unsigned nblk = (unsigned)(((W + jg - 1) / jg) * D.K);
     if (h->isize == 8) {
-      hipLaunchKernelGGL((k_dphi<T, double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e,
-                         jb.jw, (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
-                         (double*)(ws + L.dphi[s]));
-      CHECK(hipGetLastError());
-      hipLaunchKernelGGL((k_detA<double>), dim3(W * D.K), dim3(64), detA_lds(L.capS[s]), st,
-                         D, W, jb.jw, s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const double*)(ws + L.dphi[s]), (const char*)state, S, (double*)(ws + L.detA));
+      CHECK(hipFuncSetAttribute((const void*)k_detA<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+      hipLaunchKernelGGL((k_detA<T, double>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, (const int*)uidx,
+                         L.capmax, (const int*)ucnt, (const int*)off, (const T*)(ws + L.dphi[s]),
+                         (const char*)state, S, (double*)(ws + L.detA), jg);
     } else {
-      hipLaunchKernelGGL((k_dphi<T, float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e,
-                         jb.jw, (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
-                         (float*)(ws + L.dphi[s]));
-      CHECK(hipGetLastError());
-      hipLaunchKernelGGL((k_detA<float>), dim3(W * D.K), dim3(64), detA_lds(L.capS[s]), st,
-                         D, W, jb.jw, s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const float*)(ws + L.dphi[s]), (const char*)state, S, (double*)(ws + L.detA));
+      CHECK(hipFuncSetAttribute((const void*)k_detA<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+      hipLaunchKernelGGL((k_detA<T, float>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, (const int*)uidx,
+                         L.capmax, (const int*)ucnt, (const int*)off, (const T*)(ws + L.dphi[s]),
+                         (const char*)state, S, (double*)(ws + L.detA), jg);
     }
     CHECK(hipGetLastError());
   }
@@ -658,22 +752,33 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
                      unif, state, S, (const double*)(ws + L.detA), status, acc, n_accept);
   CHECK(hipGetLastError());
   for (int s = 0; s < 2; ++s) {
-    if (D.nsig(s) == 0) continue;
-    size_t lds = woodbury_lds(D, L, s);
+    const int N = D.nsig(s);
+    if (N == 0) continue;
+    const size_t lds = detA_lds(L.capS[s]);
+    double* Bbuf = (double*)(ws + L.bbuf[s]);
+    const int nrb = (N + WB_RB - 1) / WB_RB;
     if (h->isize == 8) {
-      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_woodbury<T, double>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
+      hipLaunchKernelGGL((k_woodbury_prep<T, double>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
                          (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
-                         (const int*)acc, (const double*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S,
-                         status);
+                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), Bbuf, state,
+                         S, status);
+      CHECK(hipGetLastError());
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)wb_rows_lds(N)));
+      hipLaunchKernelGGL((k_woodbury_rows<T, double>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
+                         (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
+                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status);
     } else {
-      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_woodbury<T, float>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
+      hipLaunchKernelGGL((k_woodbury_prep<T, float>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
                          (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
-                         (const int*)acc, (const float*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S,
-                         status);
+                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), Bbuf, state,
+                         S, status);
+      CHECK(hipGetLastError());
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)wb_rows_lds(N)));
+      hipLaunchKernelGGL((k_woodbury_rows<T, float>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
+                         (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
+                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status);
     }
     CHECK(hipGetLastError());
   }
@@ -696,6 +801,7 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
     for (int e = 0; e < D.n; ++e) {
       Jobs jb{};
       jb.J = W;
+      jb.woodbury = true;
       jb.xi = noise + ((int64_t)sw * D.n + e) * W * 3;
       jb.step = step;
       const double* u = unif + ((int64_t)sw * D.n + e) * W;

@@ -5,7 +5,8 @@
 
 namespace fire {
 
-constexpr int WB_RB = 16;   // rows of G per LDS block in the Woodbury kernel
+constexpr int WB_RB = 16;   // rows of G per workgroup in the Woodbury row update
+constexpr int KS = 32;      // |U_s| up to which update-set rows are staged through LDS
 
 // A batch of single-electron proposals ("jobs") for one electron index e.
 // Job j moves electron e of walker jw[j] (identity when jw is null) to
@@ -19,16 +20,22 @@ struct Jobs {
   const double* rexp;
   const double* xi;
   double step;
+  bool woodbury;       // workspace laid out with the Woodbury buffers (Metropolis)
+  int group;           // consecutive jobs sharing most of their update set (cache locality)
 };
 
 struct UpdLayout {
   int capS[2], capmax;
   int64_t rowcap[2];
   size_t rnew, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
-  size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2];
+  size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2], bbuf[2];
   size_t total;
 };
-UpdLayout upd_layout(const fire_handle* h, int J);
+// Workspace of J jobs.  Each spin segment holds J * min(capS, kRowsPerJob)
+// rows; jobs whose rows would not fit are flagged FIRE_W_UPD_OVERFLOW and
+// skipped.  with_woodbury adds the Metropolis-only Woodbury buffer.
+constexpr int kRowsPerJob = 32;
+UpdLayout upd_layout(const fire_handle* h, int J, bool with_woodbury = true);
 bool update_fits(const fire_handle* h);
 
 // Runs every step up to det A for each job: writes detA[j][det][spin] =

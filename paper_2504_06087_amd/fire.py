@@ -23,7 +23,7 @@ W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
            "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
-           "fire_status_string"]
+           "fire_profile_begin", "fire_profile_end", "fire_status_string"]
 
 
 class FireEcpChannel(ctypes.Structure):
@@ -80,6 +80,9 @@ def load() -> ctypes.CDLL:
     lib.fire_ecp_nonlocal.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_sync_status.argtypes = [P, V, V, I, ctypes.POINTER(ctypes.c_int32)]
+    lib.fire_profile_begin.argtypes = [P, V, V, I]
+    lib.fire_profile_end.argtypes = [P, V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
     lib.fire_status_string.argtypes = [st]
     lib.fire_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -256,6 +259,19 @@ class Fire:
                                        _stream()), "fire_grad_params")
         return g, status
 
+    def profile_begin(self, capacity: int = 200000):
+        self._prof_counters = torch.zeros(capacity, dtype=torch.int32, device=self.device)
+        _check(load().fire_profile_begin(self.h, _stream(), _dp(self._prof_counters), capacity), "fire_profile_begin")
+
+    def profile_end(self):
+        """{kind: (launches, ms, flops)} for the GEMM kinds f64, f32, bf16, bf16x3."""
+        la = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * 4)()
+        fl = (ctypes.c_double * 4)()
+        _check(load().fire_profile_end(self.h, _stream(), la, ms, fl), "fire_profile_end")
+        names = ["f64", "f32", "bf16", "bf16x3"]
+        return {names[k]: (int(la[k]), float(ms[k]), float(fl[k])) for k in range(4) if la[k]}
+
     # ------------------------------------------------------------------
     def state_view(self, state, W, which: str):
         """A typed view of one cached array for all W walkers (debug/tests)."""
@@ -276,3 +292,26 @@ class Fire:
 
 def fire_status_string(code: int) -> str:
     return load().fire_status_string(code).decode()
+
+
+class FireLogPsi(torch.autograd.Function):
+    """log|psi(R; theta)| with the hand-written adjoint as its backward.
+
+    forward(theta, R, handle, state, ws): packs theta into the handle, runs
+    fire_eval_logpsi.  backward: fire_grad_params with coeff = grad_output,
+    i.e. d/d theta of sum_w grad_output_w log|psi_w|.  No gradient w.r.t. R.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, R, handle, state, ws):
+        handle.set_params(theta.detach().contiguous())
+        sign, lp, st = handle.eval_logpsi(R, state, ws)
+        ctx.handle, ctx.state, ctx.ws = handle, state, ws
+        ctx.save_for_backward(R)
+        return lp
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (R,) = ctx.saved_tensors
+        g, st = ctx.handle.grad_params(R, ctx.state, ctx.ws, grad_out.detach().to(torch.float64).contiguous())
+        return g, None, None, None, None
