@@ -32,7 +32,7 @@ PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--walkers", type=int, default=4096)
     ap.add_argument("--split", type=int, default=7, help="split-bf16 GEMM sites of the hybrid precision")
@@ -92,6 +92,8 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
                 have_grad = False
         ev[4].record(stream)
         torch.cuda.synchronize()
+        print(f"# {prec} step {it} ({'timed' if timed else 'warmup'}): "
+              f"{ev[0].elapsed_time(ev[4]):.0f} ms", file=sys.stderr, flush=True)
         if timed:
             ph["eval"] += ev[0].elapsed_time(ev[1])
             ph["sweep"] += ev[1].elapsed_time(ev[2])
