@@ -59,15 +59,12 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
 }
 
 static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
-static size_t detA_staged_lds(int N, int capmax) {
-  return (size_t)(2 * KS * N + capmax * (capmax + 1) + 2 * capmax + 8) * sizeof(double);
-}
 static size_t wb_rows_lds(int N) { return (size_t)(2 * KS * N + WB_RB * N + WB_RB * KS + 8) * sizeof(double); }
 
 bool update_fits(const fire_handle* h) {
   UpdLayout L = upd_layout(h, 1);
   const int N = h->D.nu > h->D.nd ? h->D.nu : h->D.nd;
-  return L.capmax <= 128 && detA_staged_lds(N, L.capmax) <= 160 * 1024 && wb_rows_lds(N) <= 160 * 1024;
+  return L.capmax <= 128 && detA_lds(L.capmax) <= 160 * 1024 && wb_rows_lds(N) <= 160 * 1024;
 }
 
 // ---------------------------------------------------------------------------
@@ -323,15 +320,36 @@ FIRE_DEV void build_A(double* A, int LD, int k, int N, const TD* __restrict__ dp
   }
 }
 
-// det A for every (job, determinant, spin block); A = I + dPhi_U G_U^T.
-// A workgroup takes jg consecutive jobs of one determinant (the quadrature
-// points of one electron-atom pair share most G rows, which then hit cache);
-// rows are staged through LDS when |U_s| <= KS.
+// Row a of dPhi_U for one (job, determinant): either read from the dPhi
+// segment or formed on the fly as o' env - Phi from the projections, the
+// cached envelopes (the new ones for the moved electron) and the cached Phi.
+template <typename T> struct DPhiRows {
+  const T* dphi;     // [rows][K N], or null when fused
+  const T* oseg;     // [rows][K N] projections o'
+  const T* envnew;   // [job][K N]
+  const T* envc;     // cached envelopes of this (walker, det, spin) block
+  const T* phic;     // cached Phi of this block
+  int64_t row0, KN, det, N;
+  int e, e0, j;
+  FIRE_DEV double at(int a, int u, int l) const {
+    const int64_t q = (row0 + a) * KN + det * N + l;
+    if (dphi) return (double)dphi[q];
+    const int iloc = u - e0;
+    const T en = u == e ? envnew[(int64_t)j * KN + det * N + l] : envc[(int64_t)iloc * N + l];
+    return (double)(oseg[q] * en - phic[(int64_t)iloc * N + l]);
+  }
+};
+
+// det A for update sets with |U_s| > 32 (rare; the wave kernel below takes
+// the rest).  One workgroup per (job group, determinant); A = I + dPhi_U G_U^T
+// is built one wave per row (lanes over the orbital index, G rows read
+// coalesced) into LDS, then Gauss-Jordan with partial pivoting.
 template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __restrict__ jw, int s,
+__global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                               const int* __restrict__ uidx, int capmax,
                                               const int* __restrict__ ucnt, const int* __restrict__ off,
-                                              const T* __restrict__ dphi, const char* __restrict__ state,
+                                              const T* __restrict__ dphi, const T* __restrict__ oseg,
+                                              const T* __restrict__ envnew, const char* __restrict__ state,
                                               StateRec S, double* __restrict__ detA, int jg) {
   extern __shared__ double lds[];
   __shared__ double sc[2];
@@ -339,10 +357,9 @@ __global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __
   const int g = blockIdx.x / D.K, det = blockIdx.x % D.K;
   const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* Gs = lds;                      // [KS][N]
-  double* Ds = Gs + KS * N;              // [KS][N]
-  double* A = Ds + KS * N;               // [capmax][capmax+1]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double* A = lds;                       // [capmax][capmax+1]
   double* f = A + capmax * (capmax + 1); // [capmax]
   int* pm = (int*)(f + capmax);
   for (int jj = 0; jj < jg; ++jj) {
@@ -351,32 +368,24 @@ __global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __
     const int w = jw ? jw[j] : j;
     const int k = ucnt[2 * j + s];
     double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
-    if (k == 0) {
-      if (tid == 0) { out[0] = 1.0; out[1] = 0.0; }
-      continue;
-    }
+    if (k <= 32) continue;   // handled by k_detA_wave
     const int LD = k + 1;
-    const int q0 = off[s * (W + 1) + j];
     const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
-    const TI* G = (const TI*)(state + (int64_t)w * S.stride + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
-    const T* dp = dphi + (int64_t)q0 * KN + det * N;
-    if (k <= KS) {
-      for (int q = tid; q < k * N; q += nt) {
-        const int a = q / N, l = q - a * N;
-        Ds[q] = (double)dp[(int64_t)a * KN + l];
-        Gs[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
+    const char* rec = state + (int64_t)w * S.stride;
+    const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
+    const TI* G = (const TI*)(rec + S.inv) + boff;
+    DPhiRows<T> dr{dphi, oseg, envnew, (const T*)(rec + S.env) + boff, (const T*)(rec + S.phi) + boff,
+                   (int64_t)off[s * (W + 1) + j], (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
+    for (int a = wave; a < k; a += nw) {
+      const int ua = lst[a];
+      const double x0 = lane < N ? dr.at(a, ua, lane) : 0.0;
+      const double x1 = lane + 64 < N ? dr.at(a, ua, lane + 64) : 0.0;
+      for (int b = 0; b < k; ++b) {
+        const TI* gb = G + (int64_t)(lst[b] - e0) * N;
+        double v = x0 * (lane < N ? (double)gb[lane] : 0.0) + x1 * (lane + 64 < N ? (double)gb[lane + 64] : 0.0);
+        v = wave_sum(v);
+        if (lane == 0) A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
       }
-      __syncthreads();
-      for (int q = tid; q < k * k; q += nt) {
-        const int a = q / k, b = q - a * k;
-        const double* da = Ds + a * N;
-        const double* gb = Gs + b * N;
-        double v = 0.0;
-        for (int l = 0; l < N; ++l) v += da[l] * gb[l];
-        A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
-      }
-    } else {
-      build_A<T, TI>(A, LD, k, N, dp, KN, G, lst, e0);
     }
     __syncthreads();
     gj_block(A, k, LD, f, pm, sc, fl, false);
@@ -385,6 +394,158 @@ __global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __
       else { out[0] = sc[0]; out[1] = sc[1]; }
     }
     __syncthreads();
+  }
+}
+
+typedef double d4v_ __attribute__((ext_vector_type(4)));
+
+// a double from one lane (the lane index must be wave-uniform)
+FIRE_DEV double readlane_f64(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// log|det A| and its sign of a k x k matrix (k <= 32) held one row per lane
+// (lane r holds row r, columns in registers).  Gaussian elimination with
+// partial pivoting that never moves rows: the pivot of column p is the
+// largest |A_rp| among the rows not yet used (ties to the lower row), its row
+// is broadcast with readlane, and the sign of the row permutation is counted
+// as inversions.  Every register index is a compile-time constant.
+FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, bool& sing) {
+  const int lane = threadIdx.x & 63;
+  uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+  int inv = 0;
+  sgn = 1.0;
+  logd = 0.0;
+  sing = false;
+#pragma unroll
+  for (int p = 0; p < 32; ++p) {
+    if (p < k && !sing) {
+      // pivot key: |A_rp| in float with the low 5 bits replaced by 31 - r
+      const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
+      const float av = (float)fabs(row[p]);
+      uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) {
+        const uint32_t ok = (uint32_t)__shfl_xor((int)key, o, 64);
+        key = ok > key ? ok : key;
+      }
+      const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)key);
+      const int idx = 31 - (int)(best & 31u);
+      const double pv = readlane_f64(row[p], idx);
+      if ((best & ~31u) == 0u || !(fabs(pv) > 0.0)) {
+        sing = true;
+      } else {
+        unused &= ~(1u << idx);
+        inv += __popc(unused & ((1u << idx) - 1u));
+        logd += log(fabs(pv));
+        if (pv < 0) sgn = -sgn;
+        const bool live = lane < 32 && ((unused >> (lane & 31)) & 1u);
+        const double f = live ? row[p] / pv : 0.0;
+#pragma unroll
+        for (int c = p + 1; c < 32; ++c)
+          if (c < k) row[c] -= f * readlane_f64(row[c], idx);
+      }
+    }
+  }
+  if (inv & 1) sgn = -sgn;
+}
+
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const int* __restrict__ jw, int s, int e,
+                                                   const int* __restrict__ uidx, int capmax,
+                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
+                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
+                                                   const T* __restrict__ envnew, int fused,
+                                                   const char* __restrict__ state, StateRec S,
+                                                   double* __restrict__ detA, int jg) {
+  __shared__ double abuf[4][32 * 33];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  const int ngroups = (W + jg - 1) / jg;
+  if (item >= (int64_t)ngroups * D.K * jg) return;
+  const int gq = (int)(item % jg);
+  const int det = (int)((item / jg) % D.K);
+  const int g = (int)(item / ((int64_t)jg * D.K));
+  const int j = g * jg + gq;
+  if (j >= W) return;
+  const int k = ucnt[2 * j + s];
+  double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
+  if (k == 0) {
+    if (lane == 0) { out[0] = 1.0; out[1] = 0.0; }
+    return;
+  }
+  if (k > 32) return;   // handled by k_detA
+  const int w = jw ? jw[j] : j;
+  const int N = D.nsig(s), KN = D.K * N;
+  const int e0 = s == 0 ? 0 : D.nu;
+  const int q0 = off[s * (W + 1) + j];
+  const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+  const char* rec = state + (int64_t)w * S.stride;
+  const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
+  const TI* G = (const TI*)(rec + S.inv) + boff;
+  const DPhiRows<T> dr{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
+                       (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int KT = k > 16 ? 2 : 1;
+  int ua[2];
+  for (int t = 0; t < 2; ++t) {
+    const int a = 16 * t + r16;
+    ua[t] = a < k ? lst[a] : -1;
+  }
+  d4v_ acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
+  // operands of 8 MFMA steps (32 orbital columns) are loaded before any is
+  // used, so the loads of a chunk are in flight together
+  constexpr int CH = 8;
+  for (int cb = 0; cb < N; cb += 4 * CH) {
+    double af[CH][2], bf[CH][2];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int col = cb + 4 * u + kq;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int a = 16 * t + r16;
+        const bool ok = t < KT && a < k && col < N;
+        af[u][t] = ok ? dr.at(a, ua[t], col) : 0.0;
+        bf[u][t] = ok ? (double)G[(int64_t)(ua[t] - e0) * N + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (cb + 4 * u >= N) break;
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][0], bf[u][0], acc[0][0], 0, 0, 0);
+      if (KT > 1) {
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][0], bf[u][1], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][1], bf[u][0], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][1], bf[u][1], acc[1][1], 0, 0, 0);
+      }
+    }
+  }
+  // f64 16x16x4 output: register i of lane l holds row 4 i + l/16, column l%16
+  double* ab = abuf[wave];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      if (x < KT && y < KT)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ab[(16 * x + 4 * i + kq) * 33 + 16 * y + r16] = acc[x][y][i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  double row[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;
+  double sg, ld;
+  bool sing;
+  wave_lu_det(row, k, sg, ld, sing);
+  if (lane == 0) {
+    if (sing) { out[0] = 0.0; out[1] = -INFINITY; }
+    else { out[0] = sg; out[1] = ld; }
   }
 }
 
@@ -710,26 +871,45 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
     CHECK(gemm_site(h, SITE_ORB, o, st));
     const int64_t tot = (int64_t)rows * D.K * N;
-    hipLaunchKernelGGL((k_dphi<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e, jb.jw,
-                       (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew, (T*)(ws + L.dphi[s]));
-    CHECK(hipGetLastError());
-    const int jg = jb.group > 0 ? jb.group : 1;
-    const size_t lds = detA_staged_lds(N, L.capmax);
-    const unsigned nblk = (unsigned)(((W + jg - 1) / jg) * D.K);
-    if (h->isize == 8) {
-      CHECK(hipFuncSetAttribute((const void*)k_detA<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_detA<T, double>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, (const int*)uidx,
-                         L.capmax, (const int*)ucnt, (const int*)off, (const T*)(ws + L.dphi[s]),
-                         (const char*)state, S, (double*)(ws + L.detA), jg);
-    } else {
-      CHECK(hipFuncSetAttribute((const void*)k_detA<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_detA<T, float>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, (const int*)uidx,
-                         L.capmax, (const int*)ucnt, (const int*)off, (const T*)(ws + L.dphi[s]),
-                         (const char*)state, S, (double*)(ws + L.detA), jg);
+    const int fused = jb.woodbury ? 0 : 1;   // Metropolis keeps dPhi for the Woodbury update
+    if (!fused) {
+      hipLaunchKernelGGL((k_dphi<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e, jb.jw,
+                         (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
+                         (T*)(ws + L.dphi[s]));
+      CHECK(hipGetLastError());
     }
+    const int jg = jb.group > 0 ? jb.group : 1;
+    const int64_t items = (int64_t)((W + jg - 1) / jg) * jg * D.K;
+    if (h->isize == 8)
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+                         s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
+                         (double*)(ws + L.detA), jg);
+    else
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+                         s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
+                         (double*)(ws + L.detA), jg);
     CHECK(hipGetLastError());
+    if (L.capS[s] > 32) {
+      const size_t lds = detA_lds(L.capmax);
+      const unsigned nblk = (unsigned)(((W + jg - 1) / jg) * D.K);
+      const T* dp = fused ? nullptr : (const T*)(ws + L.dphi[s]);
+      if (h->isize == 8) {
+        CHECK(hipFuncSetAttribute((const void*)k_detA<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+        hipLaunchKernelGGL((k_detA<T, double>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, e, (const int*)uidx,
+                           L.capmax, (const int*)ucnt, (const int*)off, dp, (const T*)oseg, (const T*)envnew,
+                           (const char*)state, S, (double*)(ws + L.detA), jg);
+      } else {
+        CHECK(hipFuncSetAttribute((const void*)k_detA<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+        hipLaunchKernelGGL((k_detA<T, float>), dim3(nblk), dim3(256), lds, st, D, W, jb.jw, s, e, (const int*)uidx,
+                           L.capmax, (const int*)ucnt, (const int*)off, dp, (const T*)oseg, (const T*)envnew,
+                           (const char*)state, S, (double*)(ws + L.detA), jg);
+      }
+      CHECK(hipGetLastError());
+    }
   }
   // a spin block with no electrons contributes det A = 1
   for (int s = 0; s < 2; ++s)
