@@ -11,8 +11,12 @@
  *
  * Conventions of every entry point
  *  - All tensor pointers are DEVICE pointers owned by the caller unless a
- *    comment says "host".  All work is enqueued on the caller's hipStream_t;
- *    no call synchronises the stream and no call allocates device memory.
+ *    comment says "host".  All work is enqueued on the caller's hipStream_t
+ *    and no call allocates device memory.  No compute call synchronises the
+ *    stream, with one exception: on a system with nonlocal pseudopotential
+ *    channels, fire_local_energy and fire_ecp_nonlocal read the per-electron
+ *    quadrature job counts back to the host once per call (one stream
+ *    synchronisation) to size their launches.
  *  - Positions are FP64 [W][n][3], electrons 0..n_up-1 spin up, the rest down.
  *  - Errors the host can see (bad pointer, shape, precision, W > max_walkers)
  *    are returned immediately as a negative fire_status and nothing is

@@ -23,9 +23,10 @@ part; the polynomial cutoff with p = 6; separate parallel/antiparallel
 message weights; no Jastrow factor (J = 1); semilocal l = 0, 1 pseudopotential
 channels with a 12-point icosahedral rule.
 
-Parity unpinned: none of the functions below is compared against a number
-the paper prints (it prints none for this path); each is pinned instead by
-the identities, limits and closed forms in tests/test_oracle_pins.py.
+The paper prints no worked example for this path, so no function here is
+compared with a printed number; every function is pinned instead by the
+identities, limits, closed forms and brute-force checks in
+tests/test_oracle_pins.py (each test names the function it pins).
 """
 from __future__ import annotations
 
