@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the uneven 16-system batch")
+    ap.add_argument("--c5-walkers", type=int, default=512)
     return ap.parse_args()
 
 
@@ -113,6 +115,86 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     return out
 
 
+def run_c5(split, W, steps, warmup):
+    """The uneven batch: 16 systems (H chains and C/H flakes, 20-180 valence
+    electrons) x W walkers, shared embedding, per-system orbitals; one step =
+    evaluation + 1 sweep + local energy + energy gradient for every system,
+    replayed as one captured graph after an autotuning step."""
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    work = wl.config(4, walkers=W)
+    shared, private = wl.batch_params(work.params)
+    nsys = len(work.systems)
+    B = fire.FireBatch(work.systems, work.model, "bf16", [W] * nsys, cap_nbr=48, cap_upd=64, bf16_split=split)
+    B.set_params(B.flatten(shared, private))
+    R = B.concat(work.R)
+    nsw = steps + warmup + 2
+    per = [wl.noise_for(work, nsw, W, system=k) for k in range(nsys)]
+    xi_all = [B.concat([per[k][0][t:t + 1] for k in range(nsys)]) for t in range(nsw)]
+    u_all = [B.concat([per[k][1][t:t + 1] for k in range(nsys)]) for t in range(nsw)]
+    xi, u = xi_all[0].clone(), u_all[0].clone()
+    state, ws = B.buffers(1)
+    nacc = torch.zeros(nsys * W, dtype=torch.int32, device="cuda")
+    out = B.outputs()
+    stream = torch.cuda.current_stream()
+    # eager step with the tile autotuner on
+    fire.autotune_clear()
+    fire.autotune(True)
+    t0 = time.time()
+    B.step(R, state, ws, 1, work.step, xi, u, nacc, out=out)
+    torch.cuda.synchronize()
+    t_tune = time.time() - t0
+    fire.autotune(False)
+    tuned = fire.autotune_count()
+    # eager step (tuned tiles)
+    xi.copy_(xi_all[1])
+    u.copy_(u_all[1])
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    B.step(R, state, ws, 1, work.step, xi, u, nacc, out=out)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    eager_ms = ev[0].elapsed_time(ev[1])
+    print(f"# c5 eager step: {eager_ms:.0f} ms (tuning step {t_tune:.1f} s, {tuned} shapes)", file=sys.stderr,
+          flush=True)
+    t0 = time.time()
+    G = B.graph(R, state, ws, 1, work.step, xi, u, nacc, out)
+    t_cap = time.time() - t0
+    ms = 0.0
+    acc0 = None
+    for it in range(warmup + steps):
+        xi.copy_(xi_all[2 + it])
+        u.copy_(u_all[2 + it])
+        if it == warmup:
+            acc0 = nacc.clone()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        G.launch()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1])
+        print(f"# c5 graph step {it} ({'timed' if it >= warmup else 'warmup'}): {t:.0f} ms", file=sys.stderr,
+              flush=True)
+        if it >= warmup:
+            ms += t
+    ms /= steps
+    e = out[0]
+    n_el = [s.n_el for s in work.systems]
+    tot_w = nsys * W
+    acc = float((nacc - acc0).sum().item()) / (steps * W * sum(n_el))
+    return {
+        "workload": f"16 systems (H chains and C/H flakes), valence electrons {sorted(n_el)}, {W} walkers each, "
+                    f"width 256, 3 layers, 4 determinants, c = 5 bohr, local pseudopotential on C; step = "
+                    f"evaluation + 1 sweep + local energy + energy gradient per system, one graph launch",
+        "ms_per_step": ms, "eager_ms_per_step": eager_ms, "walkers_per_s": tot_w / (ms / 1e3),
+        "walker_steps_per_s_incl_step": W * sum(n_el) / (ms / 1e3), "acceptance": acc,
+        "tuned_gemm_shapes": tuned, "capture_s": t_cap,
+        "e_loc_nan": int(torch.isnan(e).sum().item()),
+    }
+
+
 def cpu_baseline():
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: one walker's forward pass, gradient, 12 of the 540 Hessian
@@ -174,12 +256,17 @@ def main():
     roof = {"bound": "mfma", "kernel": f"k_gemm<{kind}>", "achieved": achieved / 1e12, "peak": PEAK[kind] / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK[kind], "traffic": None,
             "launches": la, "kernel_ms_per_step": ms / a.steps, "flops_per_step": fl / a.steps}
+    c5 = None
+    if not a.no_c5:
+        torch.cuda.empty_cache()
+        c5 = run_c5(a.split, a.c5_walkers, a.steps, a.warmup)
+        print(f"# c5: {json.dumps(c5)}", flush=True)
     cpu = None if a.no_cpu else cpu_baseline()
     line = {
         "metric": METRIC, "value": hyb["walkers_per_s"], "unit": "local energies/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": hyb["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": "C42H12 flake, 180 valence electrons (90 up, 90 down), 4096 walkers, width 256, "
+        "config": {"workload": f"C42H12 flake, 180 valence electrons (90 up, 90 down), {W} walkers, width 256, "
                                "3 MLP layers, 16 determinants, c = 5 bohr, c_n = 20 bohr, nonlocal l = 0,1 "
                                "pseudopotential on C with a 12-point rule; step = full evaluation + 1 Metropolis "
                                "sweep + local energy + parameter gradient",
@@ -192,6 +279,7 @@ def main():
             "walker_steps_per_s": fp32["walker_steps_per_s"],
             "local_energies_per_s_el_phase": fp32["local_energies_per_s"]},
         "roofline": roof,
+        "uneven_batch": c5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

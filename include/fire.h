@@ -206,6 +206,73 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
 fire_status fire_profile_begin(fire_handle* h, hipStream_t stream, int32_t* counters, int capacity);
 fire_status fire_profile_end(fire_handle* h, hipStream_t stream, int64_t* launches, double* ms, double* flops);
 
+/* ---------------------------------------------------------------------------
+ * Uneven multi-system batches.  n_systems molecules with different electron
+ * counts share one model: every theta entry before the orbital block
+ * (filters, per-species nuclear tables -- nuc_type must index species --,
+ * LayerNorm/GLU, messages, MLP) is shared, the orbital weights and envelope
+ * parameters (orb_W_up .. env_sigma) are per system (Methods, wave function
+ * ansatz: the embedding network does not depend on the molecule).  The batch
+ * theta is [shared | private of system 0 | private of system 1 | ...];
+ * system s's private block starts at the offset fire_batch_system returns.
+ * Per-system caps are min(cap_nbr, n_s - 1) and min(cap_upd, n_s); the
+ * model's max_walkers bounds every W[s].  At most 32 systems.
+ *
+ * Buffers are concatenations in system order: R [sum_s W_s n_s 3], noise
+ * [sum_s S n_s W_s 3] (system s's block is its [S][n_s][W_s][3] array),
+ * unif [sum_s S n_s W_s], n_accept / e_loc / status [sum_s W_s].
+ */
+typedef struct fire_batch fire_batch;
+typedef struct fire_graph fire_graph;
+
+fire_status fire_batch_create(const fire_system_desc* systems, int n_systems, const fire_model_desc* model,
+                              fire_batch** out);
+fire_status fire_batch_destroy(fire_batch* b);
+/* *P_total: batch theta length; *P_shared (may be NULL): shared entries. */
+fire_status fire_batch_num_params(const fire_batch* b, int64_t* P_total, int64_t* P_shared);
+/* System s's handle (owned by the batch; usable with every single-system
+ * call once fire_batch_set_params has run) and its private-block offset. */
+fire_status fire_batch_system(const fire_batch* b, int s, fire_handle** h, int64_t* priv_offset);
+/* Bytes of the caller-owned batch buffers; W: host [n_systems]. */
+fire_status fire_batch_sizes(const fire_batch* b, const int* W, int n_sweeps, size_t* params_bytes,
+                             size_t* state_bytes, size_t* workspace_bytes);
+/* Pack the batch theta (device FP64 [P_total]) into params_buf. */
+fire_status fire_batch_set_params(fire_batch* b, const double* theta, void* params_buf, hipStream_t stream);
+/* One step for every system: full evaluation; n_sweeps Metropolis sweeps
+ * (noise/unif as fire_mcmc_sweep; n_accept incremented); local energy;
+ * c_w = (E_L,w - mean_s E_L)/W_s over the finite E_L of each system (Methods,
+ * energy gradient; flagged walkers get c_w = 0); grad [P_total] = the
+ * per-system sums of c_w d log|psi_w|/d theta, the shared entries summed over
+ * systems.  status collects every condition of the step.  The systems run on
+ * up to four internal streams forked from and joined back to `stream`. */
+fire_status fire_batch_step(fire_batch* b, const int* W, double* R, void* state, void* ws, int n_sweeps,
+                            double step, const double* noise, const double* unif, int32_t* n_accept,
+                            double* e_loc, double* grad, int32_t* status, hipStream_t stream);
+/* Capture fire_batch_step with these exact arguments into a HIP graph (the
+ * buffers are bound into it: a replay reads their contents at launch time).
+ * Refused (FIRE_ERR_ARG) when a system has nonlocal pseudopotential channels,
+ * whose launches are sized on the host. */
+fire_status fire_batch_graph_create(fire_batch* b, const int* W, double* R, void* state, void* ws, int n_sweeps,
+                                    double step, const double* noise, const double* unif, int32_t* n_accept,
+                                    double* e_loc, double* grad, int32_t* status, fire_graph** out);
+/* Replay the whole captured step as one launch on `stream`. */
+fire_status fire_graph_launch(fire_graph* g, hipStream_t stream);
+fire_status fire_graph_destroy(fire_graph* g);
+
+/* GEMM tile autotuner (process-wide).  While on, the first launch of every
+ * new GEMM shape (kind, ceil log2 of the row capacity, N, K, K-split) on a
+ * stream that is not capturing times each tile shape (128x128, 128x64,
+ * 64x128, 64x64; one warm-up and one timed launch each, synchronising the
+ * stream) and keeps the fastest; later launches of that shape use it, also
+ * inside captured graphs.  Every tile shape sums K in the same order, so the
+ * choice never changes results.  GEMMs that accumulate into their output
+ * are not timed.  save/load write/read the choices as text. */
+fire_status fire_autotune(int on);
+fire_status fire_autotune_count(int* n_shapes);
+fire_status fire_autotune_clear(void);
+fire_status fire_autotune_save(const char* path);
+fire_status fire_autotune_load(const char* path);
+
 /* OR of status[0..W-1] into *any_flags (host); synchronises the stream. */
 fire_status fire_sync_status(fire_handle* h, hipStream_t stream, const int32_t* status, int W,
                              int32_t* any_flags);

@@ -210,6 +210,7 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   h->isize = D.prec == FIRE_FP32 ? 4 : 8;
   h->params = nullptr;
   h->theta_dev = nullptr;
+  h->lap_budget = (size_t)48 << 30;
   build_theta(h);
   build_layouts(h);
   *out = h;
@@ -264,13 +265,24 @@ fire_status fire_state_layout(const fire_handle* h, size_t* offsets, size_t* str
   return FIRE_OK;
 }
 
-fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t s) {
-  if (!h || !theta || !params_buf) return FIRE_ERR_ARG;
+}  // extern "C"
+
+// Pack theta into params_buf.  Entries before the orbital block are read
+// from `shared`, the orbital/envelope entries from `priv` (laid out as they
+// follow the shared block in theta); fire_set_params passes theta and
+// theta + (offset of the orbital block).
+fire_status fire::set_params_split(fire_handle* h, const double* shared, const double* priv, void* params_buf,
+                                   hipStream_t s) {
+  if (!h || !shared || !priv || !params_buf) return FIRE_ERR_ARG;
   const Dims& D = h->D;
   char* b = (char*)params_buf;
   const ParamsLayout& L = h->pl;
   int T = (int)h->tsize, G = (int)h->gsize;
-  auto src = [&](const char* name) { return theta + th(h, name).offset; };
+  const int64_t P0 = th(h, "orb_W_up").offset;
+  auto src = [&](const char* name) {
+    const int64_t o = th(h, name).offset;
+    return o < P0 ? shared + o : priv + (o - P0);
+  };
   auto cp = [&](size_t dst, const char* name) { return do_copy(T, b + dst, src(name), plain(th(h, name).size()), s); };
   hipError_t e = hipSuccess;
 #define DO(x) do { e = (x); if (e != hipSuccess) return FIRE_ERR_HIP; } while (0)
@@ -324,8 +336,15 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
   if (hipStreamSynchronize(s) != hipSuccess) return FIRE_ERR_HIP;
 #undef DO
   h->params = params_buf;
-  h->theta_dev = theta;
+  h->theta_dev = shared;
   return FIRE_OK;
+}
+
+extern "C" {
+
+fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t s) {
+  if (!h || !theta || !params_buf) return FIRE_ERR_ARG;
+  return fire::set_params_split(h, theta, theta + th(h, "orb_W_up").offset, params_buf, s);
 }
 
 static fire_status check_call(const fire_handle* h, int W, const void* R, const void* state, const void* ws,

@@ -8,6 +8,10 @@
 // instruction, so the eight instructions together cover the 32-wide slice).
 #include "gemm.hpp"
 
+#include <cstdio>
+#include <map>
+#include <mutex>
+
 namespace fire {
 
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
@@ -19,19 +23,19 @@ constexpr int BK = 32;
 template <int KIND> struct MK;
 template <> struct MK<MMA_F64> {
   using TA = double; using TB = double; using TC = double; using TL = double; using Acc = d4v;
-  static constexpr int BM = 64, BN = 64, PAD = 2;
+  static constexpr int PAD = 2;
 };
 template <> struct MK<MMA_F32> {
   using TA = float; using TB = float; using TC = float; using TL = float; using Acc = f4v;
-  static constexpr int BM = 128, BN = 128, PAD = 4;
+  static constexpr int PAD = 4;
 };
 template <> struct MK<MMA_BF16> {
   using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
-  static constexpr int BM = 128, BN = 128, PAD = 8;
+  static constexpr int PAD = 8;
 };
 template <> struct MK<MMA_BF16X3> {
   using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
-  static constexpr int BM = 128, BN = 128, PAD = 8;
+  static constexpr int PAD = 8;
 };
 
 // rows and columns are < 2^31: 32-bit quotients, 64-bit offsets
@@ -74,12 +78,12 @@ template <typename TS> FIRE_DEV void load4(const TS* p, int k, int K, bool valid
   }
 }
 
-template <int KIND>
+template <int KIND, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   using P = MK<KIND>;
   using TA = typename P::TA; using TB = typename P::TB; using TC = typename P::TC;
   using TL = typename P::TL; using Acc = typename P::Acc;
-  constexpr int BM = P::BM, BN = P::BN, LDK = BK + P::PAD;
+  constexpr int LDK = BK + P::PAD;
   constexpr int TM = BM / 32, TN = BN / 32;
   constexpr int CA = BM * BK / 4 / 256;   // 4-element chunks per thread (A)
   constexpr int CB = BN * BK / 4 / 256;
@@ -329,16 +333,117 @@ GemmProfiler& gemm_profiler() {
   return p;
 }
 
-template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
-  using P = MK<KIND>;
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  int64_t tiles = (int64_t)((g.M + P::BM - 1) / P::BM) * ((g.N + P::BN - 1) / P::BN);
+// ---------------------------------------------------------------------------
+// Tile shapes and the autotuner.  Variant v of the f32/bf16 kinds is a BM x BN
+// tile with (BM, BN) = (128,128), (128,64), (64,128), (64,64); f64 has one
+// 64 x 64 variant.  Every variant sums K in the same order (32-wide slices,
+// one MFMA chain per 16 x 16 sub-tile), so all produce bit-identical C.
+// While tuning is on, the first launch of each new shape (kind, log2 M, N, K,
+// split) on a stream that is not capturing times every variant on the real
+// operands and keeps the fastest; GEMMs that accumulate into C are not timed
+// (running them twice would add twice) and keep variant 0.
+constexpr int kVariants = 4;
+static const int kTileM[kVariants] = {128, 128, 64, 64};
+static const int kTileN[kVariants] = {128, 64, 128, 64};
+
+struct TuneKey {
+  int kind, lgm, n, k, split;
+  bool operator<(const TuneKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (lgm != o.lgm) return lgm < o.lgm;
+    if (n != o.n) return n < o.n;
+    if (k != o.k) return k < o.k;
+    return split < o.split;
+  }
+};
+struct Tuner {
+  std::mutex mu;
+  std::map<TuneKey, int> choice;
+  bool on = false;
+};
+static Tuner& tuner() {
+  static Tuner t;
+  return t;
+}
+static TuneKey key_of(int kind, const GemmArgs& g) {
+  int lg = 0;
+  while ((1ll << lg) < (int64_t)g.M) ++lg;
+  return TuneKey{kind, lg, g.N, g.K, g.ksplit > 1 ? g.ksplit : 1};
+}
+
+template <int KIND, int BM, int BN> static hipError_t launch_tile(const GemmArgs& g, hipStream_t s, int vecA,
+                                                                  int vecB) {
+  const int64_t tiles = (int64_t)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_gemm<KIND, BM, BN>), dim3((unsigned)tiles, g.ksplit > 1 ? g.ksplit : 1), dim3(256), 0, s,
+                     g, vecA, vecB);
+  return hipGetLastError();
+}
+
+template <int KIND> static hipError_t launch_variant(int v, const GemmArgs& g, hipStream_t s, int vecA, int vecB) {
+  if constexpr (KIND == MMA_F64) {
+    return launch_tile<KIND, 64, 64>(g, s, vecA, vecB);
+  } else {
+    switch (v) {
+      case 1: return launch_tile<KIND, 128, 64>(g, s, vecA, vecB);
+      case 2: return launch_tile<KIND, 64, 128>(g, s, vecA, vecB);
+      case 3: return launch_tile<KIND, 64, 64>(g, s, vecA, vecB);
+      default: return launch_tile<KIND, 128, 128>(g, s, vecA, vecB);
+    }
+  }
+}
+
+// time every variant of this shape once (after one warm-up launch each)
+template <int KIND> static int tune_shape(const GemmArgs& g, hipStream_t s, int vecA, int vecB) {
+  const int nv = KIND == MMA_F64 ? 1 : kVariants;
+  if (nv == 1) return 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return 0; }
+  int best = 0;
+  float best_ms = 0.f;
+  for (int v = 0; v < nv; ++v) {
+    if (launch_variant<KIND>(v, g, s, vecA, vecB) != hipSuccess) continue;
+    (void)hipEventRecord(e0, s);
+    if (launch_variant<KIND>(v, g, s, vecA, vecB) != hipSuccess) continue;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (v == 0 || ms < best_ms) { best = v; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+template <int KIND> static int pick_variant(const GemmArgs& g, hipStream_t s, int vecA, int vecB) {
+  if (KIND == MMA_F64) return 0;
+  Tuner& t = tuner();
+  const TuneKey key = key_of(KIND, g);
+  {
+    std::lock_guard<std::mutex> lk(t.mu);
+    auto it = t.choice.find(key);
+    if (it != t.choice.end()) return it->second;
+    if (!t.on || g.accumulate || g.prof_rows) return 0;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
+  const int v = tune_shape<KIND>(g, s, vecA, vecB);
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.choice[key] = v;
+  return v;
+}
+
+template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
   int vecA = aligned16(g.A) && g.K % 4 == 0 && g.amap.gstride % 4 == 0 && (g.amap.rpg == 1 || g.amap.rstride % 4 == 0);
   int vecB = aligned16(g.Bt) && g.K % 4 == 0 && g.ldb % 4 == 0 &&
              (KIND != MMA_BF16X3 || aligned16(g.Bt_lo));
+  if (g.ksplit > 1) vecA = vecA && ((((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK) % 4 == 0);
   GemmProfiler& pr = gemm_profiler();
   const bool prof = pr.on && s == pr.stream && pr.used < pr.capacity;
+  const int v = pick_variant<KIND>(g, s, vecA, vecB);
   hipEvent_t* evs = prof ? (hipEvent_t*)pr.ev : nullptr;
   int slot = 0;
   if (prof) {
@@ -346,21 +451,75 @@ template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
     g.prof_rows = pr.counters + slot;
     pr.kinds[slot] = KIND;
     pr.nk[slot] = g.N * g.K;
-    hipEventRecord(evs[2 * slot], s);
+    (void)hipEventRecord(evs[2 * slot], s);
   }
-  if (g.ksplit > 1) vecA = vecA && ((((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK) % 4 == 0);
-  hipLaunchKernelGGL(k_gemm<KIND>, dim3((unsigned)tiles, g.ksplit > 1 ? g.ksplit : 1), dim3(256), 0, s, g, vecA,
-                     vecB);
-  hipError_t e = hipGetLastError();
-  if (prof) hipEventRecord(evs[2 * slot + 1], s);
+  hipError_t e = launch_variant<KIND>(v, g, s, vecA, vecB);
+  if (prof) (void)hipEventRecord(evs[2 * slot + 1], s);
   return e;
+}
+
+hipError_t autotune_set(int on) {
+  Tuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.on = on != 0;
+  return hipSuccess;
+}
+
+int autotune_count() {
+  Tuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  return (int)t.choice.size();
+}
+
+void autotune_clear() {
+  Tuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.choice.clear();
+}
+
+// one line per shape: kind log2M N K split variant
+bool autotune_save(const char* path) {
+  Tuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return false;
+  fprintf(f, "# kind log2M N K split variant(0:128x128 1:128x64 2:64x128 3:64x64)\n");
+  for (auto& kv : t.choice)
+    fprintf(f, "%d %d %d %d %d %d\n", kv.first.kind, kv.first.lgm, kv.first.n, kv.first.k, kv.first.split,
+            kv.second);
+  return fclose(f) == 0;
+}
+
+bool autotune_load(const char* path) {
+  Tuner& t = tuner();
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  std::map<TuneKey, int> m;
+  bool ok = true;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    TuneKey k{};
+    int v = 0;
+    if (sscanf(line, "%d %d %d %d %d %d", &k.kind, &k.lgm, &k.n, &k.k, &k.split, &v) != 6 || v < 0 ||
+        v >= kVariants || k.kind < 0 || k.kind > 3) {
+      ok = false;
+      break;
+    }
+    m[k] = k.kind == MMA_F64 ? 0 : v;
+  }
+  fclose(f);
+  if (!ok) return false;
+  std::lock_guard<std::mutex> lk(t.mu);
+  for (auto& kv : m) t.choice[kv.first] = kv.second;
+  return true;
 }
 
 hipError_t profile_begin(int* counters, int capacity, hipStream_t s) {
   GemmProfiler& pr = gemm_profiler();
   if (pr.ev) {
     hipEvent_t* e = (hipEvent_t*)pr.ev;
-    for (int k = 0; k < 2 * pr.capacity; ++k) hipEventDestroy(e[k]);
+    for (int k = 0; k < 2 * pr.capacity; ++k) (void)hipEventDestroy(e[k]);
     delete[] e;
     delete[] pr.kinds;
     delete[] pr.nk;
@@ -391,7 +550,7 @@ hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flo
   hipEvent_t* ev = (hipEvent_t*)pr.ev;
   for (int k = 0; k < pr.used && e == hipSuccess; ++k) {
     float t = 0;
-    hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
+    (void)hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
     const int kd = pr.kinds[k];
     launches[kd] += 1;
     ms[kd] += t;

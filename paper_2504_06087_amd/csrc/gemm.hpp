@@ -67,4 +67,12 @@ hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flo
 //     bf16 high and low parts and C = Ah Bh + Ah Bl + Al Bh (FP32 accumulate)
 hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s);
 
+// Tile autotuner (process-wide): on/off, number of tuned shapes, clear,
+// save/load of the choices as text.
+hipError_t autotune_set(int on);
+int autotune_count();
+void autotune_clear();
+bool autotune_save(const char* path);
+bool autotune_load(const char* path);
+
 }  // namespace fire

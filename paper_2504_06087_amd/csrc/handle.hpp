@@ -62,6 +62,7 @@ struct fire_handle {
   fire::StateRec st;
   size_t tsize, gsize, isize;   // bytes of T, G and the stored-inverse type
   void* params;                 // device params buffer (set by fire_set_params)
+  size_t lap_budget;            // workspace bytes the Laplacian's walker chunks may use
   const double* theta_dev;      // theta passed to fire_set_params
 };
 
@@ -104,5 +105,10 @@ inline hipError_t gemm_site(const fire_handle* h, int site, GemmArgs g, hipStrea
 static inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 int64_t theta_offset(const fire_handle* h, const char* name);
+
+// Pack parameters with the shared (embedding) entries read from `shared` and
+// the orbital/envelope entries from `priv`.
+fire_status set_params_split(fire_handle* h, const double* shared, const double* priv, void* params_buf,
+                             hipStream_t s);
 
 }  // namespace fire

@@ -30,7 +30,7 @@ LapLayout lap_layout(const fire_handle* h, int W) {
   const int nmax = D.nu > D.nd ? D.nu : D.nd;
   const size_t per_walker = (size_t)D.n * jet_rows_max(D) * ((size_t)2 * D.d + (size_t)D.K * nmax) * ts +
                             (size_t)D.n * 5 * ((size_t)8 * D.d + D.B + (size_t)D.K * nmax) * ts;
-  const size_t budget = (size_t)48 << 30;
+  const size_t budget = h->lap_budget;
   int wc = (int)(budget / (per_walker > 0 ? per_walker : 1));
   if (wc < 1) wc = 1;
   if (wc > 512) wc = 512;

@@ -23,7 +23,11 @@ W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
            "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
-           "fire_profile_begin", "fire_profile_end", "fire_status_string"]
+           "fire_profile_begin", "fire_profile_end", "fire_status_string",
+           "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
+           "fire_batch_sizes", "fire_batch_set_params", "fire_batch_step", "fire_batch_graph_create",
+           "fire_graph_launch", "fire_graph_destroy", "fire_autotune", "fire_autotune_count",
+           "fire_autotune_clear", "fire_autotune_save", "fire_autotune_load"]
 
 
 class FireEcpChannel(ctypes.Structure):
@@ -83,6 +87,24 @@ def load() -> ctypes.CDLL:
     lib.fire_profile_begin.argtypes = [P, V, V, I]
     lib.fire_profile_end.argtypes = [P, V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
+    lib.fire_batch_create.argtypes = [ctypes.POINTER(FireSystemDesc), I, ctypes.POINTER(FireModelDesc),
+                                      ctypes.POINTER(P)]
+    lib.fire_batch_destroy.argtypes = [P]
+    lib.fire_batch_num_params.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.fire_batch_system.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
+    lib.fire_batch_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int), I, ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.fire_batch_set_params.argtypes = [P, V, V, V]
+    lib.fire_batch_step.argtypes = [P, ctypes.POINTER(ctypes.c_int), V, V, V, I, D, V, V, V, V, V, V, V]
+    lib.fire_batch_graph_create.argtypes = [P, ctypes.POINTER(ctypes.c_int), V, V, V, I, D, V, V, V, V, V, V,
+                                            ctypes.POINTER(P)]
+    lib.fire_graph_launch.argtypes = [P, V]
+    lib.fire_graph_destroy.argtypes = [P]
+    lib.fire_autotune.argtypes = [I]
+    lib.fire_autotune_count.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    lib.fire_autotune_clear.argtypes = []
+    lib.fire_autotune_save.argtypes = [ctypes.c_char_p]
+    lib.fire_autotune_load.argtypes = [ctypes.c_char_p]
     lib.fire_status_string.argtypes = [st]
     lib.fire_status_string.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -113,6 +135,39 @@ def _f64(x, dev):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev).contiguous()
 
 
+def _system_desc(system, keep: list) -> FireSystemDesc:
+    """The C descriptor of a molecule; host arrays it points to go in keep."""
+    h = dict(R=np.ascontiguousarray(system.R_nuc, np.float64).reshape(-1),
+             Z=np.ascontiguousarray(system.Z, np.float64), sp=np.ascontiguousarray(system.species, np.int32),
+             nt=np.ascontiguousarray(system.nuc_type, np.int32),
+             pw=np.ascontiguousarray(system.pp_width, np.float64))
+    keep.append(h)
+    chans = []
+    for sp, lst in system.ecp.items():
+        for ch in lst:
+            a = np.ascontiguousarray(ch.a, np.float64)
+            al = np.ascontiguousarray(ch.alpha, np.float64)
+            keep += [a, al]
+            chans.append(FireEcpChannel(int(sp), int(ch.l), len(a),
+                                        a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        al.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    arr = (FireEcpChannel * max(1, len(chans)))(*chans)
+    keep.append(arr)
+    dp = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    return FireSystemDesc(system.n_nuc, dp(h["R"], ctypes.c_double), dp(h["Z"], ctypes.c_double),
+                          dp(h["sp"], ctypes.c_int), dp(h["nt"], ctypes.c_int), dp(h["pw"], ctypes.c_double),
+                          system.n_up, system.n_dn, len(chans), arr, float(system.ecp_rmax))
+
+
+def _param_layout(h):
+    lib = load()
+    cnt = ctypes.c_int(0)
+    _check(lib.fire_param_layout(h, None, ctypes.byref(cnt)), "fire_param_layout")
+    ents = (FireParamEntry * cnt.value)()
+    _check(lib.fire_param_layout(h, ents, ctypes.byref(cnt)), "fire_param_layout")
+    return [(e.name.decode(), int(e.offset), tuple(e.shape[:e.ndim])) for e in ents]
+
+
 class Fire:
     """One handle of libfire for one molecule and one parameter set."""
 
@@ -124,27 +179,8 @@ class Fire:
         self.device = torch.device(device)
         n = system.n_el
         self.n = n
-        M = system.n_nuc
-        self._host = dict(
-            R=np.ascontiguousarray(system.R_nuc, np.float64).reshape(-1),
-            Z=np.ascontiguousarray(system.Z, np.float64), sp=np.ascontiguousarray(system.species, np.int32),
-            nt=np.ascontiguousarray(system.nuc_type, np.int32), pw=np.ascontiguousarray(system.pp_width, np.float64))
-        chans = []
-        keep = []
-        for sp, lst in system.ecp.items():
-            for ch in lst:
-                a = np.ascontiguousarray(ch.a, np.float64)
-                al = np.ascontiguousarray(ch.alpha, np.float64)
-                keep += [a, al]
-                chans.append(FireEcpChannel(int(sp), int(ch.l), len(a),
-                                            a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                            al.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        arr = (FireEcpChannel * max(1, len(chans)))(*chans)
-        dp = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
-        h = self._host
-        sd = FireSystemDesc(M, dp(h["R"], ctypes.c_double), dp(h["Z"], ctypes.c_double), dp(h["sp"], ctypes.c_int),
-                            dp(h["nt"], ctypes.c_int), dp(h["pw"], ctypes.c_double), system.n_up, system.n_dn,
-                            len(chans), arr, float(system.ecp_rmax))
+        self._keep = []
+        sd = _system_desc(system, self._keep)
         cap_nbr = cap_nbr if cap_nbr is not None else min(n - 1, 64) if n > 1 else 1
         cap_upd = cap_upd if cap_upd is not None else min(n, 96)
         self.cap_nbr, self.cap_upd = max(1, cap_nbr), max(1, cap_upd)
@@ -156,11 +192,7 @@ class Fire:
         hd = ctypes.c_void_p()
         _check(lib.fire_create(ctypes.byref(sd), ctypes.byref(md), ctypes.byref(hd)), "fire_create")
         self.h = hd
-        cnt = ctypes.c_int(0)
-        _check(lib.fire_param_layout(self.h, None, ctypes.byref(cnt)), "fire_param_layout")
-        ents = (FireParamEntry * cnt.value)()
-        _check(lib.fire_param_layout(self.h, ents, ctypes.byref(cnt)), "fire_param_layout")
-        self.layout = [(e.name.decode(), int(e.offset), tuple(e.shape[:e.ndim])) for e in ents]
+        self.layout = _param_layout(self.h)
         P = ctypes.c_int64(0)
         _check(lib.fire_num_params(self.h, ctypes.byref(P)), "fire_num_params")
         self.P = int(P.value)
@@ -288,6 +320,179 @@ class Fire:
         rec = state[:W * self.state_stride].view(W, self.state_stride)
         off = self.state_offsets[k]
         return rec[:, off:off + count * esz].contiguous().view(dt)
+
+
+PRIVATE_NAMES = ("orb_W_up", "orb_W_dn", "env_pi_up", "env_pi_dn", "env_sigma")
+
+
+class FireBatch:
+    """Several molecules of uneven electron counts under one model: shared
+    embedding parameters, per-system orbitals and envelopes.  A step runs
+    evaluation, sweeps, local energy and the parameter gradient for every
+    system; it can be captured once into a HIP graph and replayed."""
+
+    def __init__(self, systems, model, precision: str = "bf16", walkers=(512,), cap_nbr: int = 48,
+                 cap_upd: int = 64, refresh_every: int = 50, bf16_split: int = 0, device: str = "cuda"):
+        lib = load()
+        self.systems, self.model, self.precision = list(systems), model, precision
+        self.device = torch.device(device)
+        self.W = [int(w) for w in walkers]
+        if len(self.W) != len(self.systems):
+            raise ValueError("one walker count per system")
+        self.n = [s.n_el for s in self.systems]
+        self._keep = []
+        descs = (FireSystemDesc * len(self.systems))(*[_system_desc(s, self._keep) for s in self.systems])
+        self._keep.append(descs)
+        md = FireModelDesc(model.width, model.mlp_layers, model.n_det, model.n_env, model.n_gauss,
+                           int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
+                           float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], max(self.W),
+                           int(cap_nbr), int(cap_upd), int(refresh_every), int(bf16_split))
+        b = ctypes.c_void_p()
+        _check(lib.fire_batch_create(descs, len(self.systems), ctypes.byref(md), ctypes.byref(b)),
+               "fire_batch_create")
+        self.b = b
+        pt, ps = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fire_batch_num_params(self.b, ctypes.byref(pt), ctypes.byref(ps)), "fire_batch_num_params")
+        self.P, self.P_shared = int(pt.value), int(ps.value)
+        self.handles, self.priv_off, self.layouts = [], [], []
+        for k in range(len(self.systems)):
+            h, o = ctypes.c_void_p(), ctypes.c_int64()
+            _check(lib.fire_batch_system(self.b, k, ctypes.byref(h), ctypes.byref(o)), "fire_batch_system")
+            self.handles.append(h)
+            self.priv_off.append(int(o.value))
+            self.layouts.append(_param_layout(h))
+        self._Wc = (ctypes.c_int * len(self.W))(*self.W)
+        self.params_buf = None
+        self.theta = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "b", None) is not None and _lib is not None:
+                _lib.fire_batch_destroy(self.b)
+        except Exception:
+            pass
+
+    def flatten(self, shared: Dict[str, np.ndarray], private) -> np.ndarray:
+        """Batch theta: shared entries once, then each system's private block."""
+        out = np.zeros(self.P, np.float64)
+        for name, off, shape in self.layouts[0]:
+            if off < self.P_shared:
+                a = np.asarray(shared[name], np.float64)
+                if tuple(a.shape) != tuple(shape):
+                    raise ValueError(f"{name}: shape {a.shape} != {shape}")
+                out[off:off + a.size] = a.reshape(-1)
+        for k, lay in enumerate(self.layouts):
+            for name, off, shape in lay:
+                if off >= self.P_shared:
+                    a = np.asarray(private[k][name], np.float64)
+                    if tuple(a.shape) != tuple(shape):
+                        raise ValueError(f"system {k} {name}: shape {a.shape} != {shape}")
+                    o = self.priv_off[k] + off - self.P_shared
+                    out[o:o + a.size] = a.reshape(-1)
+        return out
+
+    def system_theta(self, theta, k: int) -> np.ndarray:
+        """System k's own theta (the layout of a single-system handle)."""
+        t = np.asarray(theta)
+        Pk = self.layouts[k][-1][1] + int(np.prod(self.layouts[k][-1][2]))
+        return np.concatenate([t[:self.P_shared], t[self.priv_off[k]:self.priv_off[k] + Pk - self.P_shared]])
+
+    def sizes(self, n_sweeps: int):
+        p, s, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().fire_batch_sizes(self.b, self._Wc, int(n_sweeps), ctypes.byref(p), ctypes.byref(s),
+                                       ctypes.byref(w)), "fire_batch_sizes")
+        return p.value, s.value, w.value
+
+    def set_params(self, theta):
+        theta = theta if isinstance(theta, torch.Tensor) else _f64(theta, self.device)
+        pb, _, _ = self.sizes(0)
+        self.params_buf = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.theta = theta
+        _check(load().fire_batch_set_params(self.b, _dp(theta), _dp(self.params_buf), _stream()),
+               "fire_batch_set_params")
+
+    def buffers(self, n_sweeps: int):
+        _, s, w = self.sizes(n_sweeps)
+        return (torch.empty(s, dtype=torch.uint8, device=self.device),
+                torch.empty(w, dtype=torch.uint8, device=self.device))
+
+    def concat(self, arrays, per_walker_axis: int = 0) -> torch.Tensor:
+        """Concatenate per-system arrays (flattened, system order) on the device."""
+        return _f64(np.concatenate([np.ascontiguousarray(a, np.float64).reshape(-1) for a in arrays]), self.device)
+
+    def split_walkers(self, t: torch.Tensor):
+        """Per-system views of a [sum W] tensor."""
+        out, o = [], 0
+        for w in self.W:
+            out.append(t[o:o + w])
+            o += w
+        return out
+
+    def split_positions(self, R: torch.Tensor):
+        out, o = [], 0
+        for w, n in zip(self.W, self.n):
+            out.append(R[o:o + w * n * 3].view(w, n, 3))
+            o += w * n * 3
+        return out
+
+    def outputs(self):
+        tot = sum(self.W)
+        return (torch.empty(tot, dtype=torch.float64, device=self.device),
+                torch.empty(self.P, dtype=torch.float64, device=self.device),
+                torch.empty(tot, dtype=torch.int32, device=self.device))
+
+    def step(self, R, state, ws, n_sweeps, step, noise, unif, n_accept, out=None):
+        e, g, st = out if out is not None else self.outputs()
+        _check(load().fire_batch_step(self.b, self._Wc, _dp(R), _dp(state), _dp(ws), int(n_sweeps), float(step),
+                                      _dp(noise), _dp(unif), _dp(n_accept), _dp(e), _dp(g), _dp(st), _stream()),
+               "fire_batch_step")
+        return e, g, st
+
+    def graph(self, R, state, ws, n_sweeps, step, noise, unif, n_accept, out):
+        """Capture one step with these buffers; returns a FireGraph."""
+        e, g, st = out
+        gp = ctypes.c_void_p()
+        _check(load().fire_batch_graph_create(self.b, self._Wc, _dp(R), _dp(state), _dp(ws), int(n_sweeps),
+                                              float(step), _dp(noise), _dp(unif), _dp(n_accept), _dp(e), _dp(g),
+                                              _dp(st), ctypes.byref(gp)), "fire_batch_graph_create")
+        return FireGraph(gp, self)
+
+
+class FireGraph:
+    def __init__(self, ptr, owner):
+        self.g, self.owner = ptr, owner
+
+    def launch(self):
+        _check(load().fire_graph_launch(self.g, _stream()), "fire_graph_launch")
+
+    def __del__(self):
+        try:
+            if getattr(self, "g", None) is not None and _lib is not None:
+                _lib.fire_graph_destroy(self.g)
+        except Exception:
+            pass
+
+
+def autotune(on: bool):
+    _check(load().fire_autotune(1 if on else 0), "fire_autotune")
+
+
+def autotune_count() -> int:
+    n = ctypes.c_int(0)
+    _check(load().fire_autotune_count(ctypes.byref(n)), "fire_autotune_count")
+    return int(n.value)
+
+
+def autotune_clear():
+    _check(load().fire_autotune_clear(), "fire_autotune_clear")
+
+
+def autotune_save(path: str):
+    _check(load().fire_autotune_save(path.encode()), "fire_autotune_save")
+
+
+def autotune_load(path: str):
+    _check(load().fire_autotune_load(path.encode()), "fire_autotune_load")
 
 
 def fire_status_string(code: int) -> str:

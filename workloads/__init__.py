@@ -432,7 +432,6 @@ def config(config_id: int, walkers: Optional[int] = None, seed_offset: int = 0) 
     elif config_id == 4:
         rs = np.random.default_rng(ss[STREAM_SYSTEMS])
         systems = []
-        ecp = _ecp_tables(re)
         for k in range(16):
             n = int(rs.integers(20, 181))
             if rs.uniform() < 0.5:
@@ -440,7 +439,8 @@ def config(config_id: int, walkers: Optional[int] = None, seed_offset: int = 0) 
             else:
                 R, sp = grown_flake(n)
             sk = make_system(f"S{k}_n{n}", R, sp, pseudo_c=True, per_species=True)
-            sk.ecp = ecp if (sp == 1).any() else {}
+            # the uneven batch names no nonlocal channels: local pseudopotential on C only
+            sk.ecp = {}
             systems.append(sk)
         m = Model(width=256, mlp_layers=3, n_det=4, n_env=8, cutoff=5.0, cutoff_nuc=20.0,
                   n_nuc_types=2)
@@ -496,3 +496,23 @@ def zero_network(p: Dict[str, np.ndarray]):
     p["ln_g"][:] = 1.0
     p["ln_b"][:] = 0.0
     p["mlp_b"][-1][:] = 1.0
+
+
+# entries of theta that belong to one molecule (orbital weights and
+# envelopes); every entry before them is shared by an uneven batch
+PRIVATE_NAMES = ("orb_W_up", "orb_W_dn", "env_pi_up", "env_pi_dn", "env_sigma")
+
+
+def batch_params(params_list):
+    """(shared, private) for an uneven batch: the shared entries are taken
+    from the first system's parameters, the private ones from each system."""
+    shared = {k: v for k, v in params_list[0].items() if k not in PRIVATE_NAMES}
+    private = [{k: p[k] for k in PRIVATE_NAMES} for p in params_list]
+    return shared, private
+
+
+def system_params(shared, private_k):
+    """One system's full parameter set inside an uneven batch."""
+    out = dict(shared)
+    out.update(private_k)
+    return out
