@@ -63,7 +63,9 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     u = torch.tensor(u, device="cuda")
     coeff = torch.full((W,), 1.0 / W, dtype=torch.float64, device="cuda")
     nacc = torch.zeros(W, dtype=torch.int32, device="cuda")
-    # 10 burn-in proposals per electron are not timed: start from one sweep
+    # 10 burn-in proposals per electron are not timed: start from one sweep;
+    # GEMM tile shapes are autotuned during the untimed burn-in and warm-up
+    fire.autotune(True)
     F.eval_logpsi(R, state, ws)
     F.mcmc_sweep(R, state, ws, 1, work.step, xi[0:1].contiguous(), u[0:1].contiguous(), nacc)
     torch.cuda.synchronize()
@@ -74,6 +76,8 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     last_e = None
     for it in range(warmup + steps):
         timed = it >= warmup
+        if timed:
+            fire.autotune(False)
         if timed and acc0 is None:
             acc0 = nacc.clone()
             if profile:
