@@ -60,11 +60,16 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
 
 static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
 static size_t wb_rows_lds(int N) { return (size_t)(2 * KS * N + WB_RB * N + WB_RB * KS + 8) * sizeof(double); }
+// k_woodbury: G_U/row block, B, A, f in FP64 and dPhi_U in the elementwise type
+static size_t wb_fused_lds(int N, int tsize) {
+  return (size_t)(2 * KS * N + KS * (KS + 1) + KS) * sizeof(double) + (size_t)KS * N * tsize + 16;
+}
 
 bool update_fits(const fire_handle* h) {
   UpdLayout L = upd_layout(h, 1);
   const int N = h->D.nu > h->D.nd ? h->D.nu : h->D.nd;
-  return L.capmax <= 128 && detA_lds(L.capmax) <= 160 * 1024 && wb_rows_lds(N) <= 160 * 1024;
+  return L.capmax <= 128 && detA_lds(L.capmax) <= 160 * 1024 && wb_rows_lds(N) <= 160 * 1024 &&
+         wb_fused_lds(N, 8) <= 160 * 1024;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,6 +600,102 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
   n_accept[w] += 1;
 }
 
+// Woodbury update of G for one accepted (walker, determinant, spin block)
+// with |U_s| <= KS, in one workgroup (Methods, low-rank wave function
+// updates; with G = Phi^-T the update reads G' = G - (G dPhi_U^T) A^-T G_U):
+//   stage dPhi_U and G_U in LDS, A = I + dPhi_U G_U^T, A^-1 by Gauss-Jordan,
+//   B = A^-T G_U (kept in LDS), commit the new Phi rows, then stream G in
+//   blocks of WB_RB rows: Z = G_blk dPhi_U^T, G_blk -= Z B.
+// Larger update sets use k_woodbury_prep + k_woodbury_rows.
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx, int capmax,
+                                                  const int* __restrict__ ucnt, const int* __restrict__ off,
+                                                  const int* __restrict__ acc, const T* __restrict__ dphi,
+                                                  const T* __restrict__ oseg, char* __restrict__ state, StateRec S,
+                                                  int32_t* status) {
+  extern __shared__ double lds[];
+  __shared__ int perm[KS];
+  __shared__ double sc[2];
+  __shared__ int fl[2];
+  const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  const int k = ucnt[2 * w + s];
+  if (!acc[w] || k == 0 || k > KS) return;
+  const int N = D.nsig(s);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int LD = k + 1;
+  // LDS: GU [KS][N] (later the G row block and Z), B [KS][N], A [KS][KS+1],
+  // f [KS], P [KS][N] in T
+  double* GU = lds;
+  double* B = GU + KS * N;
+  double* Ai = B + KS * N;
+  double* f = Ai + KS * (KS + 1);
+  T* P = (T*)(f + KS);
+  const int q0 = off[s * (W + 1) + w];
+  const int e0 = s == 0 ? 0 : D.nu;
+  const int* lst = uidx + ((int64_t)w * 2 + s) * capmax;
+  const int KN = D.K * N;
+  char* rec = state + (int64_t)w * S.stride;
+  TI* G = (TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
+  T* phi = (T*)(rec + S.phi) + det * phi_per_det(D) + phi_block_off(D, s);
+  const T* dp = dphi + (int64_t)q0 * KN + det * N;
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q - a * N;
+    P[q] = dp[(int64_t)a * KN + l];
+    GU[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
+  }
+  __syncthreads();
+  for (int q = tid; q < k * k; q += nt) {
+    const int a = q / k, b = q - a * k;
+    const T* pa = P + a * N;
+    const double* gb = GU + b * N;
+    double v = 0.0;
+    for (int l = 0; l < N; ++l) v += (double)pa[l] * gb[l];
+    Ai[a * LD + b] = v + (a == b ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  gj_block(Ai, k, LD, f, perm, sc, fl, true);
+  if (fl[1]) {
+    if (tid == 0) atomicOr(status + w, FIRE_W_SINGULAR);
+    return;
+  }
+  // B[a][l] = sum_b (A^-1)[b][a] G_U[b][l]
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q - a * N;
+    double v = 0.0;
+    for (int b = 0; b < k; ++b) v += Ai[b * LD + a] * GU[b * N + l];
+    B[q] = v;
+  }
+  // commit the new Phi rows of this determinant and spin block
+  for (int q = tid; q < k * N; q += nt) {
+    const int a = q / N, l = q - a * N;
+    phi[(int64_t)(lst[a] - e0) * N + l] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
+  }
+  __syncthreads();
+  double* Gr = GU;                  // [WB_RB][N]
+  double* Z = GU + WB_RB * N;       // [WB_RB][k]
+  for (int m0 = 0; m0 < N; m0 += WB_RB) {
+    const int rows = N - m0 < WB_RB ? N - m0 : WB_RB;
+    for (int q = tid; q < rows * N; q += nt) Gr[q] = (double)G[(int64_t)m0 * N + q];
+    __syncthreads();
+    for (int q = tid; q < rows * k; q += nt) {
+      const int m = q / k, a = q - m * k;
+      const double* gm = Gr + m * N;
+      const T* pa = P + a * N;
+      double v = 0.0;
+      for (int l = 0; l < N; ++l) v += gm[l] * (double)pa[l];
+      Z[q] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < rows * N; q += nt) {
+      const int m = q / N, l = q - m * N;
+      double v = Gr[q];
+      for (int a = 0; a < k; ++a) v -= Z[m * k + a] * B[a * N + l];
+      G[(int64_t)m0 * N + q] = (TI)v;
+    }
+    __syncthreads();
+  }
+}
+
 // Woodbury update of G for accepted walkers, in two kernels:
 //   k_woodbury_prep (per walker, determinant, spin block): A, A^-1 and
 //     B = A^-T G_U (k x N, into the workspace), and the commit of Phi rows;
@@ -606,14 +707,14 @@ __global__ __launch_bounds__(256) void k_woodbury_prep(const Dims D, int W, int 
                                                        const int* __restrict__ off, const int* __restrict__ acc,
                                                        const T* __restrict__ dphi, const T* __restrict__ oseg,
                                                        double* __restrict__ Bbuf, char* __restrict__ state,
-                                                       StateRec S, int32_t* status) {
+                                                       StateRec S, int32_t* status, int kmin) {
   extern __shared__ double lds[];
   __shared__ int perm[128];
   __shared__ double sc[2];
   __shared__ int fl[2];
   const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
   const int k = ucnt[2 * w + s];
-  if (!acc[w] || k == 0) return;
+  if (!acc[w] || k == 0 || k < kmin) return;
   const int N = D.nsig(s);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int LD = k + 1;
@@ -653,7 +754,7 @@ __global__ __launch_bounds__(256) void k_woodbury_rows(const Dims D, int W, int 
                                                        const int* __restrict__ off, const int* __restrict__ acc,
                                                        const T* __restrict__ dphi, const double* __restrict__ Bbuf,
                                                        char* __restrict__ state, StateRec S,
-                                                       const int32_t* __restrict__ status) {
+                                                       const int32_t* __restrict__ status, int kmin) {
   extern __shared__ double lds[];
   const int N = D.nsig(s);
   const int nrb = (N + WB_RB - 1) / WB_RB;
@@ -661,7 +762,7 @@ __global__ __launch_bounds__(256) void k_woodbury_rows(const Dims D, int W, int 
   const int det = (blockIdx.x / nrb) % D.K;
   const int w = blockIdx.x / (nrb * D.K);
   const int k = ucnt[2 * w + s];
-  if (!acc[w] || k == 0 || (status[w] & FIRE_W_SINGULAR)) return;
+  if (!acc[w] || k == 0 || k < kmin || (status[w] & FIRE_W_SINGULAR)) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int q0 = off[s * (W + 1) + w];
   const int KN = D.K * N;
@@ -934,31 +1035,50 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
   for (int s = 0; s < 2; ++s) {
     const int N = D.nsig(s);
     if (N == 0) continue;
+    // update sets up to KS: one fused workgroup per (walker, determinant)
+    const size_t lfu = wb_fused_lds(N, (int)h->tsize);
+    if (h->isize == 8) {
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lfu));
+      hipLaunchKernelGGL((k_woodbury<T, double>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+    } else {
+      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lfu));
+      hipLaunchKernelGGL((k_woodbury<T, float>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+    }
+    CHECK(hipGetLastError());
+    if (L.capS[s] <= KS) continue;
+    // larger update sets (rare): two kernels through a B buffer
     const size_t lds = detA_lds(L.capS[s]);
     double* Bbuf = (double*)(ws + L.bbuf[s]);
     const int nrb = (N + WB_RB - 1) / WB_RB;
+    const int kmin = KS + 1;
     if (h->isize == 8) {
       hipLaunchKernelGGL((k_woodbury_prep<T, double>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
                          (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
                          (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), Bbuf, state,
-                         S, status);
+                         S, status, kmin);
       CHECK(hipGetLastError());
       CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)wb_rows_lds(N)));
       hipLaunchKernelGGL((k_woodbury_rows<T, double>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
                          (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
-                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status);
+                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status, kmin);
     } else {
       hipLaunchKernelGGL((k_woodbury_prep<T, float>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
                          (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
                          (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), Bbuf, state,
-                         S, status);
+                         S, status, kmin);
       CHECK(hipGetLastError());
       CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)wb_rows_lds(N)));
       hipLaunchKernelGGL((k_woodbury_rows<T, float>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
                          (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
-                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status);
+                         (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status, kmin);
     }
     CHECK(hipGetLastError());
   }
