@@ -111,7 +111,8 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     ph = {k: v / steps for k, v in ph.items()}
     e_np = last_e.cpu().numpy()
     out = dict(phases_ms=ph, ms_per_step=sum(ph.values()), acceptance=acc_rate, have_grad=have_grad,
-               e_loc_mean=float(np.nanmean(e_np)), e_loc_nan=int(np.isnan(e_np).sum()))
+               e_loc_mean=float(np.nanmean(e_np)), e_loc_median=float(np.nanmedian(e_np)),
+               e_loc_nan=int(np.isnan(e_np).sum()))
     out["local_energies_per_s"] = W / (ph["local_energy"] / 1e3)
     out["walker_steps_per_s"] = W * n / (ph["sweep"] / 1e3)
     out["walkers_per_s"] = W / (out["ms_per_step"] / 1e3)

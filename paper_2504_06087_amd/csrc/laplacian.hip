@@ -61,6 +61,10 @@ LapLayout lap_layout(const fire_handle* h, int W) {
   }
   L.gd = take(Wl * D.K * n * 3 * 8);
   L.hd = take(Wl * D.K * n * 8);
+  L.tcap = D.cap_nbr + 1;
+  L.memb = take(Wl * n * 2 * L.tcap * 4);
+  L.mslot = take(Wl * n * 2 * L.tcap * 4);
+  L.mcnt = take(Wl * n * 2 * 4);
   L.total = o;
   return L;
 }
@@ -372,100 +376,154 @@ __global__ void k_phi_jet(const Dims D, int s, int Wc, const int32_t* __restrict
 // with M_ik = sum_l d_{n,x}Phi_il G_kl (G = Phi^-T), per spin block, plus the
 // Laplacian row term sum_l LapPhi_nl G_nl of electron n itself.
 // ---------------------------------------------------------------------------
-template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, const int16_t* __restrict__ nidx,
-                                                 const int32_t* __restrict__ ncnt, const int* __restrict__ joff,
-                                                 const T* __restrict__ dphi0, const T* __restrict__ dphi1,
-                                                 const char* __restrict__ state, StateRec S,
-                                                 double* __restrict__ gd, double* __restrict__ hd) {
-  extern __shared__ double lds[];
-  __shared__ int mem[2][130], slot[2][130], cntS[2], tmpi[130], tmps[130];
-  __shared__ double red[16];
-  const int K = D.K, n = D.n;
-  const int wl = blockIdx.x / (n * K);
-  const int nn = (blockIdx.x / K) % n;
-  const int det = blockIdx.x % K;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t en = (int64_t)wl * n + nn;
+typedef double d4v_ __attribute__((ext_vector_type(4)));
+
+// Members of T_n = {n} u N_n per spin block, with the slot of n in each
+// member's own tangent list (0 for n itself).  One wave per (walker, n);
+// members whose list does not hold n (cannot happen for a symmetric
+// neighbour relation) are dropped.
+__global__ __launch_bounds__(256) void k_lap_members(const Dims D, int Wc, const int16_t* __restrict__ nidx,
+                                                     const int32_t* __restrict__ ncnt, int tcap,
+                                                     int* __restrict__ memb, int* __restrict__ mslot,
+                                                     int* __restrict__ mcnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t en = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int n = D.n;
+  if (en >= (int64_t)Wc * n) return;
+  const int wl = (int)(en / n), nn = (int)(en % n);
   const int cn = ncnt[2 * en] + ncnt[2 * en + 1];
-  // members of T_n = {n} u N_n with the slot of n in each member's own list
-  for (int t = tid; t <= cn; t += nt) {
-    const int i = t == 0 ? nn : nidx[en * D.cap_nbr + t - 1];
-    int sl = 0;
-    if (i != nn) {
-      const int64_t ei = (int64_t)wl * n + i;
-      const int ci = ncnt[2 * ei] + ncnt[2 * ei + 1];
-      sl = -1;
-      for (int p = 0; p < ci; ++p)
-        if (nidx[ei * D.cap_nbr + p] == nn) { sl = 1 + p; break; }
+  int c[2] = {0, 0};
+  for (int t0 = 0; t0 <= cn; t0 += 64) {
+    const int t = t0 + lane;
+    int i = -1, sl = -1;
+    if (t <= cn) {
+      i = t == 0 ? nn : nidx[en * D.cap_nbr + t - 1];
+      if (i == nn) {
+        sl = 0;
+      } else {
+        const int64_t ei = (int64_t)wl * n + i;
+        const int ci = ncnt[2 * ei] + ncnt[2 * ei + 1];
+        for (int p = 0; p < ci; ++p)
+          if (nidx[ei * D.cap_nbr + p] == nn) { sl = 1 + p; break; }
+      }
     }
-    tmpi[t] = i;
-    tmps[t] = sl;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int c0 = 0, c1 = 0;
-    for (int t = 0; t <= cn; ++t) {
-      if (tmps[t] < 0) continue;
-      const int i = tmpi[t];
-      if (i < D.nu) { mem[0][c0] = i; slot[0][c0] = tmps[t]; ++c0; }
-      else { mem[1][c1] = i; slot[1][c1] = tmps[t]; ++c1; }
+    const bool ok = sl >= 0;
+    const bool up = i >= 0 && i < D.nu;
+    const uint64_t m0 = __ballot(ok && up), m1 = __ballot(ok && !up);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (ok) {
+      const int sp = up ? 0 : 1;
+      const int pos = c[sp] + __popcll((sp == 0 ? m0 : m1) & below);
+      memb[(en * 2 + sp) * tcap + pos] = i;
+      mslot[(en * 2 + sp) * tcap + pos] = sl;
     }
-    cntS[0] = c0;
-    cntS[1] = c1;
+    c[0] += __popcll(m0);
+    c[1] += __popcll(m1);
   }
-  __syncthreads();
+  if (lane == 0) {
+    mcnt[2 * en] = c[0];
+    mcnt[2 * en + 1] = c[1];
+  }
+}
+
+// log-det contraction per (walker, electron n, determinant), one wave each
+// (Methods, efficient Laplacian, eqs. forward_lap_det_M and logdet_lowrank):
+//   grad_{n,x} l_d = tr M_x,   hess_n = sum_x sum_{a,b in T_n} (M_x)_ab (M_x)_ba,
+// with (M_x)_ab = sum_l d_{n,x}Phi_{a l} G_{b l} (G = Phi^-T) per spin block,
+// plus the Laplacian row term sum_l LapPhi_nl G_nl of electron n itself.
+// Both M_x = D G^T and M_x^T = G D^T are formed tile by tile on 16x16x4 f64
+// MFMA with the same output layout, so sum_ab M_ab M_ba is a lane-wise
+// product of the two accumulators.  Rows past |T_n| are zero.
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, const int* __restrict__ memb,
+                                                 const int* __restrict__ mslot, const int* __restrict__ mcnt,
+                                                 int tcap, const int32_t* __restrict__ ncnt,
+                                                 const int* __restrict__ joff, const T* __restrict__ dphi0,
+                                                 const T* __restrict__ dphi1, const char* __restrict__ state,
+                                                 StateRec S, double* __restrict__ gd, double* __restrict__ hd) {
+  const int K = D.K, n = D.n;
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= (int64_t)Wc * n * K) return;
+  const int det = (int)(item % K);
+  const int64_t en = item / K;
+  const int wl = (int)(en / n), nn = (int)(en % n);
+  const int r16 = lane & 15, kq = lane >> 4;
   const char* rec = state + (int64_t)(w0 + wl) * S.stride;
   double gx[3] = {0, 0, 0}, hs = 0, lapt = 0;
   for (int s = 0; s < 2; ++s) {
     const int N = D.nsig(s), KN = K * N, e0 = s == 0 ? 0 : D.nu;
-    const int t = cntS[s];
+    const int t = mcnt[2 * en + s];
     if (t == 0 || N == 0) continue;
     const T* dphi = s == 0 ? dphi0 : dphi1;
     const TI* G = (const TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
-    double* Gs = lds;              // [t][N]
-    double* Ds = Gs + t * N;       // [t][N]
-    double* Ms = Ds + t * N;       // [t][t]
-    for (int q = tid; q < t * N; q += nt) Gs[q] = (double)G[(int64_t)(mem[s][q / N] - e0) * N + q % N];
+    const int* mem = memb + (en * 2 + s) * tcap;
+    const int* slt = mslot + (en * 2 + s) * tcap;
     // Laplacian-row term of electron n itself
     if ((nn < D.nu ? 0 : 1) == s) {
+      const int cn = ncnt[2 * en] + ncnt[2 * en + 1];
       const int64_t lr = joff[en] + 3 * (1 + cn);
       double v = 0;
-      for (int l = tid; l < N; l += nt) v += (double)dphi[lr * KN + det * N + l] * (double)G[(int64_t)(nn - e0) * N + l];
+      for (int l = lane; l < N; l += 64)
+        v += (double)dphi[lr * KN + det * N + l] * (double)G[(int64_t)(nn - e0) * N + l];
       lapt += v;
     }
+    const int KT = (t + 15) / 16;
     for (int x = 0; x < 3; ++x) {
-      __syncthreads();
-      for (int q = tid; q < t * N; q += nt) {
-        const int a = q / N, l = q % N;
-        const int64_t ei = (int64_t)wl * n + mem[s][a];
-        Ds[q] = (double)dphi[(joff[ei] + 3 * slot[s][a] + x) * KN + det * N + l];
-      }
-      __syncthreads();
-      for (int q = tid; q < t * t; q += nt) {
-        const int a = q / t, b = q % t;
-        double v = 0;
-        for (int l = 0; l < N; ++l) v += Ds[a * N + l] * Gs[b * N + l];
-        Ms[q] = v;
-      }
-      __syncthreads();
-      for (int q = tid; q < t * t; q += nt) {
-        const int a = q / t, b = q % t;
-        hs += Ms[a * t + b] * Ms[b * t + a];
-        if (a == b) gx[x] += Ms[q];
+      for (int tx = 0; tx < KT; ++tx) {
+        // row of this lane in tile tx: G row and jet row of member a
+        const int a = 16 * tx + r16;
+        const bool oka = a < t;
+        const int ua = oka ? mem[a] : e0;
+        const int64_t ra = oka ? ((int64_t)joff[(int64_t)wl * n + ua] + 3 * slt[a] + x) * KN + det * N : 0;
+        const TI* ga = G + (int64_t)(ua - e0) * N;
+        for (int ty = 0; ty < KT; ++ty) {
+          const int b = 16 * ty + r16;
+          const bool okb = b < t;
+          const int ub = okb ? mem[b] : e0;
+          const int64_t rb = okb ? ((int64_t)joff[(int64_t)wl * n + ub] + 3 * slt[b] + x) * KN + det * N : 0;
+          const TI* gb = G + (int64_t)(ub - e0) * N;
+          d4v_ m1 = {0.0, 0.0, 0.0, 0.0}, m2 = {0.0, 0.0, 0.0, 0.0};
+          constexpr int CH = 8;
+          for (int cb = 0; cb < N; cb += 4 * CH) {
+            double dx[CH], gyv[CH], gxv[CH], dyv[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+              const int col = cb + 4 * u + kq;
+              const bool cin = col < N;
+              dx[u] = (oka && cin) ? (double)dphi[ra + col] : 0.0;
+              gxv[u] = (oka && cin) ? (double)ga[col] : 0.0;
+              gyv[u] = (okb && cin) ? (double)gb[col] : 0.0;
+              dyv[u] = (okb && cin) ? (double)dphi[rb + col] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+              if (cb + 4 * u >= N) break;
+              m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(dx[u], gyv[u], m1, 0, 0, 0);
+              m2 = __builtin_amdgcn_mfma_f64_16x16x4f64(gxv[u], dyv[u], m2, 0, 0, 0);
+            }
+          }
+          // output layout: register i of lane l holds row 4 i + l/16, column l%16
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            hs += m1[i] * m2[i];
+            if (tx == ty && 4 * i + kq == r16) gx[x] += m1[i];
+          }
+        }
       }
     }
-    __syncthreads();
   }
-  const double g0 = block_sum<double>(gx[0], red);
-  const double g1 = block_sum<double>(gx[1], red);
-  const double g2 = block_sum<double>(gx[2], red);
-  const double hh = block_sum<double>(hs, red);
-  const double lt = block_sum<double>(lapt, red);
-  if (tid == 0) {
+  for (int o = 32; o > 0; o >>= 1) {
+    gx[0] += __shfl_xor(gx[0], o, 64);
+    gx[1] += __shfl_xor(gx[1], o, 64);
+    gx[2] += __shfl_xor(gx[2], o, 64);
+    hs += __shfl_xor(hs, o, 64);
+    lapt += __shfl_xor(lapt, o, 64);
+  }
+  if (lane == 0) {
     double* o = gd + (((int64_t)wl * K + det) * n + nn) * 3;
-    o[0] = g0; o[1] = g1; o[2] = g2;
-    hd[((int64_t)wl * K + det) * n + nn] = lt - hh;
+    o[0] = gx[0]; o[1] = gx[1]; o[2] = gx[2];
+    hd[((int64_t)wl * K + det) * n + nn] = lapt - hs;
   }
 }
 
@@ -663,24 +721,23 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
   }
   // determinant contraction and kinetic energy
   {
-    int tmax = D.cap_nbr + 1;
-    int Nmax = D.nu > D.nd ? D.nu : D.nd;
-    size_t lds = ((size_t)2 * tmax * Nmax + (size_t)tmax * tmax) * sizeof(double);
     double* gd = (double*)(ws + L.gd);
     double* hd = (double*)(ws + L.hd);
-    if (h->isize == 8) {
-      CHECK(hipFuncSetAttribute((const void*)k_det_lap<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_det_lap<T, double>), dim3((unsigned)(rows * D.K)), dim3(256), lds, st, D, Wc, w0,
-                         (const int16_t*)nidx, (const int32_t*)ncnt, (const int*)joff, (const T*)dph[0],
-                         (const T*)dph[1], (const char*)state, S, gd, hd);
-    } else {
-      CHECK(hipFuncSetAttribute((const void*)k_det_lap<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-      hipLaunchKernelGGL((k_det_lap<T, float>), dim3((unsigned)(rows * D.K)), dim3(256), lds, st, D, Wc, w0,
-                         (const int16_t*)nidx, (const int32_t*)ncnt, (const int*)joff, (const T*)dph[0],
-                         (const T*)dph[1], (const char*)state, S, gd, hd);
-    }
+    int* memb = (int*)(ws + L.memb);
+    int* mslot = (int*)(ws + L.mslot);
+    int* mcnt = (int*)(ws + L.mcnt);
+    hipLaunchKernelGGL(k_lap_members, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, D, Wc,
+                       (const int16_t*)nidx, (const int32_t*)ncnt, L.tcap, memb, mslot, mcnt);
+    CHECK(hipGetLastError());
+    const unsigned nblk = (unsigned)((rows * D.K + 3) / 4);
+    if (h->isize == 8)
+      hipLaunchKernelGGL((k_det_lap<T, double>), dim3(nblk), dim3(256), 0, st, D, Wc, w0, (const int*)memb,
+                         (const int*)mslot, (const int*)mcnt, L.tcap, (const int32_t*)ncnt, (const int*)joff,
+                         (const T*)dph[0], (const T*)dph[1], (const char*)state, S, gd, hd);
+    else
+      hipLaunchKernelGGL((k_det_lap<T, float>), dim3(nblk), dim3(256), 0, st, D, Wc, w0, (const int*)memb,
+                         (const int*)mslot, (const int*)mcnt, L.tcap, (const int32_t*)ncnt, (const int*)joff,
+                         (const T*)dph[0], (const T*)dph[1], (const char*)state, S, gd, hd);
     CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_kinetic, dim3(Wc), dim3(256), 0, st, D, Wc, w0, (const char*)state, S, (const double*)gd,
                        (const double*)hd, kin, grad);
@@ -689,12 +746,9 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
   return hipSuccess;
 }
 
-size_t lap_lds_needed(const fire_handle* h) {
-  const Dims& D = h->D;
-  int tmax = D.cap_nbr + 1;
-  int Nmax = D.nu > D.nd ? D.nu : D.nd;
-  return ((size_t)2 * tmax * Nmax + (size_t)tmax * tmax) * sizeof(double);
-}
+// dynamic LDS of the Laplacian kernels (the determinant contraction runs in
+// registers on MFMA tiles and needs none)
+size_t lap_lds_needed(const fire_handle* h) { return 0; }
 
 template <typename T>
 static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char* state, char* ws,

@@ -9,6 +9,8 @@ struct LapLayout {
   int64_t rowcap[2];
   size_t nidx, ncnt, joff, jtot, yj, ugj, h0j, projj, hval, zval, basisj;
   size_t jetA[2], jetB[2], envj[2], oval[2], dphi[2], gd, hd;
+  int tcap;                      // capacity of the T_n member lists per spin
+  size_t memb, mslot, mcnt;
   size_t total;
 };
 LapLayout lap_layout(const fire_handle* h, int W);

@@ -49,8 +49,10 @@ def test_h4_fp64_local_energy(lib):
     assert np.abs(g - go.numpy()).max() <= 1e-9
 
 
-@pytest.mark.parametrize("cutoff", [5.0, 1e-9])
+@pytest.mark.parametrize("cutoff", [5.0, 1e-9, 20.0])
 def test_polyene_fp64_local_energy(lib, cutoff):
+    """c = 20 bohr puts every same-spin electron in T_n (31 members: two
+    16-row MFMA tiles in the determinant contraction)."""
     log(f"case: narrow C12H14 fp64 E_L W=3 c={cutoff}")
     s, m, p, R = small_polyene(3, cutoff=cutoff)
     F, O, state, ws = setup_custom(s, m, p, R, "fp64")
