@@ -176,13 +176,13 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   Dims D{};
   D.nu = sys->n_up; D.nd = sys->n_dn; D.n = D.nu + D.nd; D.M = sys->n_nuc;
   D.NT = md->n_nuc_types; D.d = md->width; D.L = md->mlp_layers; D.K = md->n_det; D.E = md->n_env;
-  D.G = md->n_gauss; D.h1 = md->edge_h1; D.h2 = md->edge_h2; D.B = D.M * D.E;
+  D.B = D.M * D.E;
   D.cut = md->cutoff; D.cutn = md->cutoff_nuc; D.cap_nbr = md->cap_nbr; D.cap_upd = md->cap_upd;
   D.prec = md->precision;
   D.split = md->precision == FIRE_BF16_HYBRID ? md->bf16_split : 0;
   if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > 128 || D.nd > 128 || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
   if (D.d < 1 || D.d > 256 || D.L < 0 || D.L > 16 || D.K < 1 || D.K > 32 || D.E < 1) return FIRE_ERR_SHAPE;
-  if (D.G != kMaxG || D.h1 < 1 || D.h1 > kMaxH1 || D.h2 < 1 || D.h2 > kMaxH2) return FIRE_ERR_SHAPE;
+  if (md->n_gauss != kMaxG || md->edge_h1 != kMaxH1 || md->edge_h2 != kMaxH2) return FIRE_ERR_SHAPE;
   if (D.NT < 1 || !(D.cut > 0) || !(D.cutn > 0)) return FIRE_ERR_SHAPE;
   if (md->max_walkers < 1 || D.cap_nbr < 1 || D.cap_nbr > 32767 || D.cap_upd < 1) return FIRE_ERR_CAPACITY;
   for (int m = 0; m < D.M; ++m)

@@ -27,7 +27,10 @@ struct Dims {
   int M;              // nuclei
   int NT;             // rows of per-nucleus tables
   int d, L, K, E;     // width, MLP layers, determinants, envelopes per nucleus
-  int G, h1, h2;      // filter radial Gaussians and hidden widths
+  // filter radial Gaussians and hidden widths: fixed at the widths the
+  // method uses (32 Gaussians, edge MLP 16 -> 8), so every filter loop has
+  // compile-time bounds
+  static constexpr int G = kMaxG, h1 = kMaxH1, h2 = kMaxH2;
   int B;              // M * E envelope basis size
   double cut, cutn;   // c, c_n
   int cap_nbr, cap_upd;

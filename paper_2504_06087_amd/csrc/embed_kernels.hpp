@@ -56,23 +56,47 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
 template <typename T>
 FIRE_DEV void pair_features(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, const T* b2,
                             const T* sig, T cut, const Dims& D, T* out) {
+  // loops run to the compile-time maxima with guards, so that every weight
+  // load of a layer is issued before the first product needs it
   T r = sqrt(dx * dx + dy * dy + dz * dz);
   T e4[4] = {r, dx, dy, dz};
   T lo = log1p_over(r);
+#pragma unroll
   for (int k = 0; k < 4; ++k) out[k] = lo * e4[k];
-  T z1[kMaxH1];
-  for (int k = 0; k < D.h1; ++k) {
-    T a = b1[k];
-    for (int j = 0; j < 4; ++j) a += e4[j] * W1[j * D.h1 + k];
-    z1[k] = silu_(a);
+  T w1[4][kMaxH1], bb1[kMaxH1];
+#pragma unroll
+  for (int k = 0; k < kMaxH1; ++k) {
+    bb1[k] = k < D.h1 ? b1[k] : T(0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w1[j][k] = k < D.h1 ? W1[j * D.h1 + k] : T(0);
   }
-  for (int k = 0; k < D.h2; ++k) {
-    T a = b2[k];
-    for (int j = 0; j < D.h1; ++j) a += z1[j] * W2[j * D.h2 + k];
-    out[4 + k] = silu_(a);
+  T z1[kMaxH1];
+#pragma unroll
+  for (int k = 0; k < kMaxH1; ++k) {
+    T a = bb1[k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a += e4[j] * w1[j][k];
+    z1[k] = k < D.h1 ? silu_(a) : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxH2; ++k) {
+    if (k < D.h2) {
+      T w2[kMaxH1];
+#pragma unroll
+      for (int j = 0; j < kMaxH1; ++j) w2[j] = j < D.h1 ? W2[j * D.h2 + k] : T(0);
+      T a = b2[k];
+#pragma unroll
+      for (int j = 0; j < kMaxH1; ++j) a += z1[j] * w2[j];
+      out[4 + k] = silu_(a);
+    }
   }
   T fc = fcut_(r / cut);
-  for (int k = 0; k < D.G; ++k) out[12 + k] = fc * exp(-(sig[k] * sig[k]) * r * r);
+  T sg[kMaxG];
+#pragma unroll
+  for (int k = 0; k < kMaxG; ++k) sg[k] = k < D.G ? sig[k] : T(0);
+#pragma unroll
+  for (int k = 0; k < kMaxG; ++k)
+    if (k < D.G) out[12 + k] = fc * exp(-(sg[k] * sg[k]) * r * r);
   out[44] = fc;
 }
 constexpr int FEAT = 48;
@@ -89,6 +113,7 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
                                                   T* __restrict__ y_out, int epb) {
   const Dims& D = P.D;
   __shared__ T feat[MCH * FEAT];
+  __shared__ int ntp[MCH];
   __shared__ T red[16];
   const int c = threadIdx.x;
   const bool act = c < D.d;
@@ -108,20 +133,35 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
       __syncthreads();
       if (threadIdx.x < mc) {
         int m = m0 + threadIdx.x, t = P.ntype[m];
+        ntp[threadIdx.x] = t;
         pair_features<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
                          P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig,
                          (T)D.cutn, D, feat + threadIdx.x * FEAT);
       }
       __syncthreads();
       if (act) {
-        for (int k = 0; k < mc; ++k) {
-          const T* f = feat + k * FEAT;
-          if (f[44] == T(0)) continue;
-          T g1 = 0, g2 = 0;
-          for (int j = 0; j < D.h2; ++j) g1 += f[4 + j] * w3[j];
-          for (int j = 0; j < D.G; ++j) g2 += f[12 + j] * wenv[j];
-          T v = P.nuc_emb[P.ntype[m0 + k] * D.d + c] + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
-          s += g1 * g2 * v;
+        // nuclear embeddings of 16 nuclei are loaded together
+        constexpr int NG = 16;
+        for (int k0 = 0; k0 < mc; k0 += NG) {
+          T ne[NG];
+#pragma unroll
+          for (int u = 0; u < NG; ++u) ne[u] = k0 + u < mc ? P.nuc_emb[ntp[k0 + u] * D.d + c] : T(0);
+#pragma unroll
+          for (int u = 0; u < NG; ++u) {
+            const int k = k0 + u;
+            if (k >= mc) break;
+            const T* f = feat + k * FEAT;
+            if (f[44] == T(0)) continue;
+            T g1 = 0, g2 = 0;
+#pragma unroll
+            for (int j = 0; j < kMaxH2; ++j)
+              if (j < D.h2) g1 += f[4 + j] * w3[j];
+#pragma unroll
+            for (int j = 0; j < kMaxG; ++j)
+              if (j < D.G) g2 += f[12 + j] * wenv[j];
+            T v = ne[u] + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
+            s += g1 * g2 * v;
+          }
         }
       }
     }

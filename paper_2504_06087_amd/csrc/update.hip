@@ -216,12 +216,15 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
     const int a = (s == se) ? 0 : 1;
     const int cnt = ucnt[2 * j + s];
     const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
-    T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0;
+    T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0, be_old = 0, be_new = 0, ae_new = 0;
     if (act) {
       for (int k = 0; k < D.h2; ++k) w3[k] = P.ee_W3[(a * D.h2 + k) * D.d + c];
       for (int k = 0; k < D.G; ++k) wenv[k] = P.ee_Wenv[(a * D.G + k) * D.d + c];
       for (int k = 0; k < 4; ++k) we[k] = P.msg_We[(a * 4 + k) * D.d + c];
       bb = P.msg_b[a * D.d + c];
+      be_old = proj[((int64_t)e * 4 + 2 + a) * D.d + c];
+      be_new = pe_new[(2 + a) * D.d + c];
+      ae_new = pe_new[a * D.d + c];
     }
     T* hseg = s == 0 ? hseg0 : hseg1;
     T* mseg = s == 0 ? mseg0 : mseg1;
@@ -245,26 +248,46 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
       }
       __syncthreads();
       if (!act) continue;
-      for (int t = 0; t < tc; ++t) {
-        const int u = mem[t];
-        if (u == e) continue;
-        T mu = mold[(int64_t)u * D.d + c];
-        const T au = proj[((int64_t)u * 4 + a) * D.d + c];
-        for (int kind = 0; kind < 3; ++kind) {
-          const T* f = feat + (3 * t + kind) * FEAT;
-          if (f[44] == T(0)) continue;
-          T g1 = 0, g2 = 0;
-          for (int q = 0; q < D.h2; ++q) g1 += f[4 + q] * w3[q];
-          for (int q = 0; q < D.G; ++q) g2 += f[12 + q] * wenv[q];
-          const T ef = f[0] * we[0] + f[1] * we[1] + f[2] * we[2] + f[3] * we[3] + bb;
-          if (kind == 0) mu -= g1 * g2 * silu_(au + proj[((int64_t)e * 4 + 2 + a) * D.d + c] + ef);
-          else if (kind == 1) mu += g1 * g2 * silu_(au + pe_new[(2 + a) * D.d + c] + ef);
-          else acc_e += g1 * g2 * silu_(pe_new[a * D.d + c] + proj[((int64_t)u * 4 + 2 + a) * D.d + c] + ef);
+      // per-member cached values of 8 members are loaded together
+      constexpr int MG = 8;
+      for (int tg = 0; tg < tc; tg += MG) {
+        T mo[MG], au_[MG], bu_[MG], h0u[MG];
+#pragma unroll
+        for (int v = 0; v < MG; ++v) {
+          const int u = tg + v < tc ? mem[tg + v] : e;
+          mo[v] = mold[(int64_t)u * D.d + c];
+          au_[v] = proj[((int64_t)u * 4 + a) * D.d + c];
+          bu_[v] = proj[((int64_t)u * 4 + 2 + a) * D.d + c];
+          h0u[v] = h0[(int64_t)u * D.d + c];
         }
-        const int64_t q = q0 + t0 + t;
-        hseg[q * D.d + c] = h0[(int64_t)u * D.d + c] + mu;
-        mseg[q * D.d + c] = mu;
-        if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = u; }
+#pragma unroll
+        for (int v = 0; v < MG; ++v) {
+          const int t = tg + v;
+          if (t >= tc) break;
+          const int u = mem[t];
+          if (u == e) continue;
+          T mu = mo[v];
+          const T au = au_[v];
+          for (int kind = 0; kind < 3; ++kind) {
+            const T* f = feat + (3 * t + kind) * FEAT;
+            if (f[44] == T(0)) continue;
+            T g1 = 0, g2 = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxH2; ++q)
+              if (q < D.h2) g1 += f[4 + q] * w3[q];
+#pragma unroll
+            for (int q = 0; q < kMaxG; ++q)
+              if (q < D.G) g2 += f[12 + q] * wenv[q];
+            const T ef = f[0] * we[0] + f[1] * we[1] + f[2] * we[2] + f[3] * we[3] + bb;
+            if (kind == 0) mu -= g1 * g2 * silu_(au + be_old + ef);
+            else if (kind == 1) mu += g1 * g2 * silu_(au + be_new + ef);
+            else acc_e += g1 * g2 * silu_(ae_new + bu_[v] + ef);
+          }
+          const int64_t q = q0 + t0 + t;
+          hseg[q * D.d + c] = h0u[v] + mu;
+          mseg[q * D.d + c] = mu;
+          if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = u; }
+        }
       }
     }
   }
