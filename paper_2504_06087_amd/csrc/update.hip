@@ -435,32 +435,43 @@ FIRE_DEV double readlane_f64(double x, int l) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// log|det A| and its sign of a k x k matrix (k <= 32) held one row per lane
-// (lane r holds row r, columns in registers).  Gaussian elimination with
-// partial pivoting that never moves rows: the pivot of column p is the
+// max over lanes 0..31 of a 32-bit key, wave-uniform result: DPP row
+// shifts give each row's maximum in its lane 15, a row broadcast combines
+// rows 0 and 1 in lane 31
+FIRE_DEV uint32_t lanes32_max(uint32_t key) {
+  uint32_t m = key;
+  m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x111, 0xf, 0xf, false));   // row_shr:1
+  m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x112, 0xf, 0xf, false));   // row_shr:2
+  m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x114, 0xf, 0xf, false));   // row_shr:4
+  m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x118, 0xf, 0xf, false));   // row_shr:8
+  m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, 31);
+}
+
+// log|det A| and its sign of a k x k matrix (k <= KMAX <= 32) held one row
+// per lane (lane r holds row r, columns in registers).  Gaussian elimination
+// with partial pivoting that never moves rows: the pivot of column p is the
 // largest |A_rp| among the rows not yet used (ties to the lower row), its row
 // is broadcast with readlane, and the sign of the row permutation is counted
-// as inversions.  Every register index is a compile-time constant.
+// as inversions.  The product of the pivots is carried as a mantissa and a
+// binary exponent, so one logarithm is taken at the end.  Every register
+// index is a compile-time constant.
+template <int KMAX>
 FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, bool& sing) {
   const int lane = threadIdx.x & 63;
   uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
-  int inv = 0;
+  int inv = 0, ex = 0;
+  double mant = 1.0;
   sgn = 1.0;
-  logd = 0.0;
   sing = false;
 #pragma unroll
-  for (int p = 0; p < 32; ++p) {
+  for (int p = 0; p < KMAX; ++p) {
     if (p < k && !sing) {
       // pivot key: |A_rp| in float with the low 5 bits replaced by 31 - r
       const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
       const float av = (float)fabs(row[p]);
-      uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
-#pragma unroll
-      for (int o = 16; o > 0; o >>= 1) {
-        const uint32_t ok = (uint32_t)__shfl_xor((int)key, o, 64);
-        key = ok > key ? ok : key;
-      }
-      const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)key);
+      const uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
+      const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)lanes32_max(key));
       const int idx = 31 - (int)(best & 31u);
       const double pv = readlane_f64(row[p], idx);
       if ((best & ~31u) == 0u || !(fabs(pv) > 0.0)) {
@@ -468,19 +479,31 @@ FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, b
       } else {
         unused &= ~(1u << idx);
         inv += __popc(unused & ((1u << idx) - 1u));
-        logd += log(fabs(pv));
+        int e2;
+        mant *= frexp(fabs(pv), &e2);
+        ex += e2;
+        int e3;
+        mant = frexp(mant, &e3);
+        ex += e3;
         if (pv < 0) sgn = -sgn;
         const bool live = lane < 32 && ((unused >> (lane & 31)) & 1u);
         const double f = live ? row[p] / pv : 0.0;
 #pragma unroll
-        for (int c = p + 1; c < 32; ++c)
+        for (int c = p + 1; c < KMAX; ++c)
           if (c < k) row[c] -= f * readlane_f64(row[c], idx);
       }
     }
   }
+  logd = log(mant) + (double)ex * 0.69314718055994530942;
   if (inv & 1) sgn = -sgn;
 }
 
+// det A = det(I + dPhi_U G_U^T) with one wave per (job, determinant) item:
+// the product on 16x16x4 f64 MFMA tiles (|U_s| <= 32), then wave_lu_det.
+// Items are ordered (job group, determinant, job in group) so that the
+// quadrature points of one electron-atom pair, which share most G rows,
+// run side by side.  With `fused`, dPhi = o' env - Phi is formed on the fly
+// from the projections, cached envelopes and Phi (no dPhi pass).
 template <typename T, typename TI>
 __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                    const int* __restrict__ uidx, int capmax,
@@ -570,7 +593,10 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
   for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;
   double sg, ld;
   bool sing;
-  wave_lu_det(row, k, sg, ld, sing);
+  if (k <= 16)
+    wave_lu_det<16>(row, k, sg, ld, sing);
+  else
+    wave_lu_det<32>(row, k, sg, ld, sing);
   if (lane == 0) {
     if (sing) { out[0] = 0.0; out[1] = -INFINITY; }
     else { out[0] = sg; out[1] = ld; }
