@@ -62,7 +62,8 @@ static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeo
 static size_t wb_rows_lds(int N) { return (size_t)(2 * KS * N + WB_RB * N + WB_RB * KS + 8) * sizeof(double); }
 // k_woodbury: G_U/row block, B, A, f in FP64 and dPhi_U in the elementwise type
 static size_t wb_fused_lds(int N, int tsize) {
-  return (size_t)(2 * KS * N + KS * (KS + 1) + KS) * sizeof(double) + (size_t)KS * N * tsize + 16;
+  const size_t gu = (size_t)KS * N > 4 * 16 * 33 ? (size_t)KS * N : 4 * 16 * 33;
+  return (gu + (size_t)KS * N + KS * (KS + 1) + KS) * sizeof(double) + (size_t)KS * N * tsize + 16;
 }
 
 bool update_fits(const fire_handle* h) {
@@ -675,7 +676,7 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
   // LDS: GU [KS][N] (later the G row block and Z), B [KS][N], A [KS][KS+1],
   // f [KS], P [KS][N] in T
   double* GU = lds;
-  double* B = GU + KS * N;
+  double* B = GU + (KS * N > 4 * 16 * 33 ? KS * N : 4 * 16 * 33);
   double* Ai = B + KS * N;
   double* f = Ai + KS * (KS + 1);
   T* P = (T*)(f + KS);
@@ -720,28 +721,70 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     phi[(int64_t)(lst[a] - e0) * N + l] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
   }
   __syncthreads();
-  double* Gr = GU;                  // [WB_RB][N]
-  double* Z = GU + WB_RB * N;       // [WB_RB][k]
-  for (int m0 = 0; m0 < N; m0 += WB_RB) {
-    const int rows = N - m0 < WB_RB ? N - m0 : WB_RB;
-    for (int q = tid; q < rows * N; q += nt) Gr[q] = (double)G[(int64_t)m0 * N + q];
-    __syncthreads();
-    for (int q = tid; q < rows * k; q += nt) {
-      const int m = q / k, a = q - m * k;
-      const double* gm = Gr + m * N;
-      const T* pa = P + a * N;
-      double v = 0.0;
-      for (int l = 0; l < N; ++l) v += gm[l] * (double)pa[l];
-      Z[q] = v;
+  // G -= Z B in 16-row blocks, one wave per block of rows, on 16x16x4 f64
+  // MFMA tiles: Z = G_rows dPhi_U^T (K = N), then each 16x16 tile of G is
+  // loaded as the accumulator and Z B subtracted (K = |U_s|).  f64 MFMA
+  // layouts: A lane (r, q) holds A[r][q], B lane (r, q) holds B[q][r], the
+  // output register i of lane (r, q) holds C[4 i + q][r].
+  const int lane = tid & 63, wave = tid >> 6, r16 = lane & 15, kq = lane >> 4;
+  const int KT = k > 16 ? 2 : 1;
+  double* Zs = GU + wave * (16 * 33);   // this wave's Z tile [16][16 KT]
+  for (int ch = wave; ch * 16 < N; ch += 4) {
+    const int m0 = ch * 16;
+    const int mrow = m0 + r16;
+    d4v_ z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
+    for (int cb = 0; cb < N; cb += 32) {
+      double ga[8], pa0[8], pa1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int col = cb + 4 * u + kq;
+        const bool cin = col < N;
+        ga[u] = (cin && mrow < N) ? (double)G[(int64_t)mrow * N + col] : 0.0;
+        pa0[u] = (cin && r16 < k) ? (double)P[r16 * N + col] : 0.0;
+        pa1[u] = (cin && 16 + r16 < k) ? (double)P[(16 + r16) * N + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (cb + 4 * u >= N) break;
+        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa0[u], z0, 0, 0, 0);
+        if (KT > 1) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa1[u], z1, 0, 0, 0);
+      }
     }
-    __syncthreads();
-    for (int q = tid; q < rows * N; q += nt) {
-      const int m = q / N, l = q - m * N;
-      double v = Gr[q];
-      for (int a = 0; a < k; ++a) v -= Z[m * k + a] * B[a * N + l];
-      G[(int64_t)m0 * N + q] = (TI)v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Zs[(4 * i + kq) * 33 + r16] = z0[i];
+      Zs[(4 * i + kq) * 33 + 16 + r16] = KT > 1 ? z1[i] : 0.0;
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    double za[8];
+#pragma unroll
+    for (int s4 = 0; s4 < 8; ++s4) za[s4] = -Zs[r16 * 33 + 4 * s4 + kq];
+    for (int c0 = 0; c0 < N; c0 += 16) {
+      const int col = c0 + r16;
+      d4v_ acc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + 4 * i + kq;
+        acc[i] = (r < N && col < N) ? (double)G[(int64_t)r * N + col] : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 8; ++s4) {
+        if (s4 >= 4 * KT) break;
+        const int a = 4 * s4 + kq;
+        const double bv = (a < k && col < N) ? B[a * N + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za[s4], bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = m0 + 4 * i + kq;
+        if (r < N && col < N) G[(int64_t)r * N + col] = (TI)acc[i];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
 }
 
