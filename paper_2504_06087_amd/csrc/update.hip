@@ -61,9 +61,9 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
 static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
 static size_t wb_rows_lds(int N) { return (size_t)(2 * KS * N + WB_RB * N + WB_RB * KS + 8) * sizeof(double); }
 // k_woodbury: G_U/row block, B, A, f in FP64 and dPhi_U in the elementwise type
-static size_t wb_fused_lds(int N, int tsize) {
-  const size_t gu = (size_t)KS * N > 4 * 16 * 33 ? (size_t)KS * N : 4 * 16 * 33;
-  return (gu + (size_t)KS * N + KS * (KS + 1) + KS) * sizeof(double) + (size_t)KS * N * tsize + 16;
+static size_t wb_fused_lds(int N, int tsize, int ksm = KS) {
+  const size_t gu = (size_t)ksm * N > 4 * 16 * 33 ? (size_t)ksm * N : 4 * 16 * 33;
+  return (gu + (size_t)ksm * N + ksm * (ksm + 1) + ksm) * sizeof(double) + (size_t)ksm * N * tsize + 16;
 }
 
 bool update_fits(const fire_handle* h) {
@@ -657,29 +657,30 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
 //   B = A^-T G_U (kept in LDS), commit the new Phi rows, then stream G in
 //   blocks of WB_RB rows: Z = G_blk dPhi_U^T, G_blk -= Z B.
 // Larger update sets use k_woodbury_prep + k_woodbury_rows.
-template <typename T, typename TI>
+template <typename T, typename TI, int KSM>
 __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx, int capmax,
                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
                                                   const int* __restrict__ acc, const T* __restrict__ dphi,
                                                   const T* __restrict__ oseg, char* __restrict__ state, StateRec S,
                                                   int32_t* status) {
   extern __shared__ double lds[];
-  __shared__ int perm[KS];
+  __shared__ int perm[KSM];
   __shared__ double sc[2];
   __shared__ int fl[2];
   const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
   const int k = ucnt[2 * w + s];
-  if (!acc[w] || k == 0 || k > KS) return;
+  // this instance takes update sets of (KSM/2, KSM] rows (KSM = 16: 1..16)
+  if (!acc[w] || k == 0 || k > KSM || (KSM > 16 && k <= 16)) return;
   const int N = D.nsig(s);
   const int tid = threadIdx.x, nt = blockDim.x;
   const int LD = k + 1;
-  // LDS: GU [KS][N] (later the G row block and Z), B [KS][N], A [KS][KS+1],
-  // f [KS], P [KS][N] in T
+  // LDS: GU [KSM][N] (later the per-wave Z tiles), B [KSM][N],
+  // A [KSM][KSM+1], f [KSM], P [KSM][N] in T
   double* GU = lds;
-  double* B = GU + (KS * N > 4 * 16 * 33 ? KS * N : 4 * 16 * 33);
-  double* Ai = B + KS * N;
-  double* f = Ai + KS * (KS + 1);
-  T* P = (T*)(f + KS);
+  double* B = GU + (KSM * N > 4 * 16 * 33 ? KSM * N : 4 * 16 * 33);
+  double* Ai = B + KSM * N;
+  double* f = Ai + KSM * (KSM + 1);
+  T* P = (T*)(f + KSM);
   const int q0 = off[s * (W + 1) + w];
   const int e0 = s == 0 ? 0 : D.nu;
   const int* lst = uidx + ((int64_t)w * 2 + s) * capmax;
@@ -694,26 +695,128 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     GU[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
   }
   __syncthreads();
-  for (int q = tid; q < k * k; q += nt) {
-    const int a = q / k, b = q - a * k;
-    const T* pa = P + a * N;
-    const double* gb = GU + b * N;
-    double v = 0.0;
-    for (int l = 0; l < N; ++l) v += (double)pa[l] * gb[l];
-    Ai[a * LD + b] = v + (a == b ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  gj_block(Ai, k, LD, f, perm, sc, fl, true);
-  if (fl[1]) {
-    if (tid == 0) atomicOr(status + w, FIRE_W_SINGULAR);
-    return;
-  }
-  // B[a][l] = sum_b (A^-1)[b][a] G_U[b][l]
-  for (int q = tid; q < k * N; q += nt) {
-    const int a = q / N, l = q - a * N;
-    double v = 0.0;
-    for (int b = 0; b < k; ++b) v += Ai[b * LD + a] * GU[b * N + l];
-    B[q] = v;
+  {
+    // wave 0 forms A on MFMA, inverts it in registers and forms B on MFMA;
+    // the other waves wait at the barrier below
+    constexpr int NT = KSM / 16;          // 16-row tiles of A
+    constexpr int LA = KSM + 1;           // row stride of A in LDS
+    if (tid < 64) {
+      const int lane = tid, r16 = lane & 15, kq = lane >> 4;
+      // A = I + P G_U^T (rows and columns past k zero)
+      d4v_ am[NT][NT];
+#pragma unroll
+      for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y) am[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
+      for (int c0 = 0; c0 < N; c0 += 4) {
+        const int col = c0 + kq;
+        double pv[NT], gv[NT];
+#pragma unroll
+        for (int x = 0; x < NT; ++x) {
+          const int r = 16 * x + r16;
+          const bool ok = r < k && col < N;
+          pv[x] = ok ? (double)P[r * N + col] : 0.0;
+          gv[x] = ok ? GU[r * N + col] : 0.0;
+        }
+#pragma unroll
+        for (int x = 0; x < NT; ++x)
+#pragma unroll
+          for (int y = 0; y < NT; ++y) am[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(pv[x], gv[y], am[x][y], 0, 0, 0);
+      }
+#pragma unroll
+      for (int x = 0; x < NT; ++x)
+#pragma unroll
+        for (int y = 0; y < NT; ++y)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Ai[(16 * x + 4 * i + kq) * LA + 16 * y + r16] = am[x][y][i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // Gauss-Jordan on [A | I], lane r holds row r; pivots chosen among the
+      // unused rows by magnitude (no row moves): afterwards the right half of
+      // the pivot row of column p is row p of A^-1
+      double row[2 * KSM];
+#pragma unroll
+      for (int c = 0; c < KSM; ++c) {
+        row[c] = (lane < k && c < k) ? Ai[lane * LA + c] + (c == lane ? 1.0 : 0.0) : 0.0;
+        row[KSM + c] = (lane < k && c == lane) ? 1.0 : 0.0;
+      }
+      uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+      int pivrow[KSM];
+      bool sing = false;
+#pragma unroll
+      for (int p = 0; p < KSM; ++p) {
+        pivrow[p] = 0;
+        if (p < k && !sing) {
+          const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
+          const float av = (float)fabs(row[p]);
+          const uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
+          const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)lanes32_max(key));
+          const int idx = 31 - (int)(best & 31u);
+          const double pv = readlane_f64(row[p], idx);
+          if ((best & ~31u) == 0u || !(fabs(pv) > 0.0)) {
+            sing = true;
+          } else {
+            unused &= ~(1u << idx);
+            pivrow[p] = idx;
+            const double ip = 1.0 / pv;
+            const double fr = lane == idx ? 0.0 : row[p] * ip;
+#pragma unroll
+            for (int c = 0; c < 2 * KSM; ++c) {
+              const double pc = readlane_f64(row[c], idx);
+              row[c] = lane == idx ? row[c] * ip : row[c] - fr * pc;
+            }
+          }
+        }
+      }
+      if (sing) {
+        if (lane == 0) { fl[1] = 1; atomicOr(status + w, FIRE_W_SINGULAR); }
+      } else {
+        if (lane == 0) fl[1] = 0;
+        // A^-1 row p = right half of lane pivrow[p]; stored transposed
+#pragma unroll
+        for (int p = 0; p < KSM; ++p)
+          if (p < k && lane == pivrow[p])
+#pragma unroll
+            for (int c = 0; c < KSM; ++c) Ai[c * LA + p] = c < k ? row[KSM + c] : 0.0;   // Ai = (A^-1)^T
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if (!sing) {
+        // B = (A^-1)^T G_U, 16 columns of N per tile, K = |U_s|
+        double at[NT][KSM / 4];
+#pragma unroll
+        for (int x = 0; x < NT; ++x)
+#pragma unroll
+          for (int s4 = 0; s4 < KSM / 4; ++s4) {
+            const int b = 4 * s4 + kq;
+            at[x][s4] = b < k ? Ai[(16 * x + r16) * LA + b] : 0.0;
+          }
+        for (int c0 = 0; c0 < N; c0 += 16) {
+          const int col = c0 + r16;
+          double gv[KSM / 4];
+#pragma unroll
+          for (int s4 = 0; s4 < KSM / 4; ++s4) {
+            const int b = 4 * s4 + kq;
+            gv[s4] = (b < k && col < N) ? GU[b * N + col] : 0.0;
+          }
+#pragma unroll
+          for (int x = 0; x < NT; ++x) {
+            d4v_ bm = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < KSM / 4; ++s4) bm = __builtin_amdgcn_mfma_f64_16x16x4f64(at[x][s4], gv[s4], bm, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int a = 16 * x + 4 * i + kq;
+              if (a < k && col < N) B[a * N + col] = bm[i];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (fl[1]) return;
   }
   // commit the new Phi rows of this determinant and spin block
   for (int q = tid; q < k * N; q += nt) {
@@ -761,25 +864,34 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     double za[8];
 #pragma unroll
     for (int s4 = 0; s4 < 8; ++s4) za[s4] = -Zs[r16 * 33 + 4 * s4 + kq];
-    for (int c0 = 0; c0 < N; c0 += 16) {
-      const int col = c0 + r16;
-      d4v_ acc;
+    // four 16-column tiles at a time: all their G loads are issued first
+    for (int cq = 0; cq < N; cq += 64) {
+      d4v_ accs[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = m0 + 4 * i + kq;
-        acc[i] = (r < N && col < N) ? (double)G[(int64_t)r * N + col] : 0.0;
+      for (int t = 0; t < 4; ++t) {
+        const int col = cq + 16 * t + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = m0 + 4 * i + kq;
+          accs[t][i] = (r < N && col < N) ? (double)G[(int64_t)r * N + col] : 0.0;
+        }
       }
 #pragma unroll
-      for (int s4 = 0; s4 < 8; ++s4) {
-        if (s4 >= 4 * KT) break;
-        const int a = 4 * s4 + kq;
-        const double bv = (a < k && col < N) ? B[a * N + col] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(za[s4], bv, acc, 0, 0, 0);
-      }
+      for (int t = 0; t < 4; ++t) {
+        const int col = cq + 16 * t + r16;
+        if (cq + 16 * t >= N) break;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = m0 + 4 * i + kq;
-        if (r < N && col < N) G[(int64_t)r * N + col] = (TI)acc[i];
+        for (int s4 = 0; s4 < 8; ++s4) {
+          if (s4 >= 4 * KT) break;
+          const int a = 4 * s4 + kq;
+          const double bv = (a < k && col < N) ? B[a * N + col] : 0.0;
+          accs[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(za[s4], bv, accs[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = m0 + 4 * i + kq;
+          if (r < N && col < N) G[(int64_t)r * N + col] = (TI)accs[t][i];
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1127,22 +1239,36 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
   for (int s = 0; s < 2; ++s) {
     const int N = D.nsig(s);
     if (N == 0) continue;
-    // update sets up to KS: one fused workgroup per (walker, determinant)
-    const size_t lfu = wb_fused_lds(N, (int)h->tsize);
-    if (h->isize == 8) {
-      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lfu));
-      hipLaunchKernelGGL((k_woodbury<T, double>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
-                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
-                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
-    } else {
-      CHECK(hipFuncSetAttribute((const void*)k_woodbury<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lfu));
-      hipLaunchKernelGGL((k_woodbury<T, float>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
-                         (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
-                         (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+    // update sets up to KS: one fused workgroup per (walker, determinant);
+    // sets of up to 16 rows and of 17..32 rows in two instances (LDS sized
+    // for each)
+    for (int ksm = 16; ksm <= KS; ksm += 16) {
+      if (ksm > 16 && L.capS[s] <= 16) break;
+      const size_t lfu = wb_fused_lds(N, (int)h->tsize, ksm);
+      const void* fn;
+      if (h->isize == 8)
+        fn = ksm == 16 ? (const void*)k_woodbury<T, double, 16> : (const void*)k_woodbury<T, double, KS>;
+      else
+        fn = ksm == 16 ? (const void*)k_woodbury<T, float, 16> : (const void*)k_woodbury<T, float, KS>;
+      CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lfu));
+      if (h->isize == 8 && ksm == 16)
+        hipLaunchKernelGGL((k_woodbury<T, double, 16>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                           (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                           (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+      else if (h->isize == 8)
+        hipLaunchKernelGGL((k_woodbury<T, double, KS>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                           (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                           (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+      else if (ksm == 16)
+        hipLaunchKernelGGL((k_woodbury<T, float, 16>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                           (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                           (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+      else
+        hipLaunchKernelGGL((k_woodbury<T, float, KS>), dim3(W * D.K), dim3(256), lfu, st, D, W, s,
+                           (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
+                           (const int*)acc, (const T*)(ws + L.dphi[s]), (const T*)(ws + L.oseg[s]), state, S, status);
+      CHECK(hipGetLastError());
     }
-    CHECK(hipGetLastError());
     if (L.capS[s] <= KS) continue;
     // larger update sets (rare): two kernels through a B buffer
     const size_t lds = detA_lds(L.capS[s]);
