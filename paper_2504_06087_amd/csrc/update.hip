@@ -499,12 +499,120 @@ FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, b
   if (inv & 1) sgn = -sgn;
 }
 
-// det A = det(I + dPhi_U G_U^T) with one wave per (job, determinant) item:
-// the product on 16x16x4 f64 MFMA tiles (|U_s| <= 32), then wave_lu_det.
-// Items are ordered (job group, determinant, job in group) so that the
-// quadrature points of one electron-atom pair, which share most G rows,
-// run side by side.  With `fused`, dPhi = o' env - Phi is formed on the fly
-// from the projections, cached envelopes and Phi (no dPhi pass).
+// log|det A| and sign of one k x k matrix (k <= 16) per 16-lane group: the
+// four groups of a wave factor four matrices at once.  Lane 16 q + r holds
+// row r of matrix q; kk is the size of this lane's matrix (0: no matrix).
+// Same pivoting as wave_lu_det (largest magnitude among unused rows, no row
+// moves, sign from the inversion count); the group maximum comes from DPP
+// row shifts (a DPP row is a 16-lane group), rows are broadcast with
+// ds_bpermute, which every lane executes.
+FIRE_DEV void group_lu_det16(double (&row)[16], int kk, double& sgn, double& logd, bool& sing) {
+  const int lane = threadIdx.x & 63, r = lane & 15, base = lane & ~15;
+  uint32_t unused = kk >= 16 ? 0xffffu : ((1u << kk) - 1u);
+  int inv = 0, ex = 0;
+  double mant = 1.0;
+  sgn = 1.0;
+  sing = false;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const bool act = p < kk && !sing;
+    const bool cand = act && ((unused >> r) & 1u);
+    const float av = (float)fabs(row[p]);
+    const uint32_t key = cand ? ((__float_as_uint(av) & ~15u) | (uint32_t)(15 - r)) : 0u;
+    uint32_t m = key;
+    m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x111, 0xf, 0xf, false));   // row_shr:1
+    m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x112, 0xf, 0xf, false));   // row_shr:2
+    m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x114, 0xf, 0xf, false));   // row_shr:4
+    m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x118, 0xf, 0xf, false));   // row_shr:8
+    const uint32_t best = (uint32_t)__shfl((int)m, base + 15, 64);
+    const int idx = 15 - (int)(best & 15u);
+    const double pv = __shfl(row[p], base + idx, 64);
+    const bool ok = act && (best & ~15u) != 0u && fabs(pv) > 0.0;
+    if (act && !ok) sing = true;
+    double f = 0.0;
+    if (ok) {
+      unused &= ~(1u << idx);
+      inv += __popc(unused & ((1u << idx) - 1u));
+      int e2;
+      mant *= frexp(fabs(pv), &e2);
+      ex += e2;
+      int e3;
+      mant = frexp(mant, &e3);
+      ex += e3;
+      if (pv < 0) sgn = -sgn;
+      if ((unused >> r) & 1u) f = row[p] / pv;
+    }
+#pragma unroll
+    for (int c = p + 1; c < 16; ++c) {
+      const double pc = __shfl(row[c], base + idx, 64);
+      row[c] -= f * pc;
+    }
+  }
+  logd = log(mant) + (double)ex * 0.69314718055994530942;
+  if (inv & 1) sgn = -sgn;
+}
+
+// The product dPhi_U G_U^T of one (job, determinant) item, 16 KT x 16 KT,
+// on 16x16x4 f64 MFMA tiles, into LDS (row stride ld; rows/columns past k
+// are zero).  Operands of 8 MFMA steps (32 orbital columns) are loaded
+// before any is used.
+template <typename T, typename TI, int KT>
+FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, int N, int e0, double* ab, int ld) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  int ua[KT];
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const int a = 16 * t + r16;
+    ua[t] = a < k ? lst[a] : e0;
+  }
+  d4v_ acc[KT][KT];
+#pragma unroll
+  for (int x = 0; x < KT; ++x)
+#pragma unroll
+    for (int y = 0; y < KT; ++y) acc[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
+  constexpr int CH = 8;
+  for (int cb = 0; cb < N; cb += 4 * CH) {
+    double af[CH][KT], bf[CH][KT];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int col = cb + 4 * u + kq;
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int a = 16 * t + r16;
+        const bool ok = a < k && col < N;
+        af[u][t] = ok ? dr.at(a, ua[t], col) : 0.0;
+        bf[u][t] = ok ? (double)G[(int64_t)(ua[t] - e0) * N + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (cb + 4 * u >= N) break;
+#pragma unroll
+      for (int x = 0; x < KT; ++x)
+#pragma unroll
+        for (int y = 0; y < KT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][x], bf[u][y], acc[x][y], 0, 0, 0);
+    }
+  }
+  // f64 16x16x4 output: register i of lane l holds row 4 i + l/16, column l%16
+#pragma unroll
+  for (int x = 0; x < KT; ++x)
+#pragma unroll
+    for (int y = 0; y < KT; ++y)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ab[(16 * x + 4 * i + kq) * ld + 16 * y + r16] = acc[x][y][i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// det A = det(I + dPhi_U G_U^T) for (job, determinant) items, four per
+// wave.  Items are ordered (job group, determinant, job in group) so that the
+// quadrature points of one electron-atom pair, which share most G rows, run
+// side by side.  Items with 16 < |U_s| <= 32 are done one at a time
+// (32 x 32 product, wave_lu_det); items with |U_s| <= 16 are formed one after
+// another and factored together, one per 16-lane group.  With `fused`,
+// dPhi = o' env - Phi is formed on the fly from the projections, cached
+// envelopes and Phi (no dPhi pass).  |U_s| > 32 is left to k_detA.
 template <typename T, typename TI>
 __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                    const int* __restrict__ uidx, int capmax,
@@ -513,6 +621,103 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
                                                    const T* __restrict__ envnew, int fused,
                                                    const char* __restrict__ state, StateRec S,
                                                    double* __restrict__ detA, int jg) {
+  __shared__ double abuf[4][4 * 16 * 17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t quad = (int64_t)blockIdx.x * 4 + wave;
+  const int ngroups = (W + jg - 1) / jg;
+  const int64_t total = (int64_t)ngroups * D.K * jg;
+  if (quad * 4 >= total) return;
+  const int N = D.nsig(s), KN = D.K * N;
+  const int e0 = s == 0 ? 0 : D.nu;
+  double* ab = abuf[wave];
+  int jq[4], dq[4], kqv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t item = quad * 4 + q;
+    jq[q] = -1;
+    dq[q] = 0;
+    kqv[q] = -1;
+    if (item < total) {
+      const int gq = (int)(item % jg);
+      const int det = (int)((item / jg) % D.K);
+      const int g = (int)(item / ((int64_t)jg * D.K));
+      const int j = g * jg + gq;
+      if (j < W) {
+        jq[q] = j;
+        dq[q] = det;
+        kqv[q] = ucnt[2 * j + s];
+      }
+    }
+  }
+  auto item_rows = [&](int q, const TI*& G, DPhiRows<T>& dr, const int*& lst) {
+    const int j = jq[q], det = dq[q];
+    const int w = jw ? jw[j] : j;
+    const int q0 = off[s * (W + 1) + j];
+    lst = uidx + ((int64_t)j * 2 + s) * capmax;
+    const char* rec = state + (int64_t)w * S.stride;
+    const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
+    G = (const TI*)(rec + S.inv) + boff;
+    dr = DPhiRows<T>{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
+                     (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
+  };
+  auto out_of = [&](int q) { return detA + (((int64_t)jq[q] * D.K + dq[q]) * 2 + s) * 2; };
+  // empty update sets here; 16 < |U_s| <= 32 in k_detA_mid
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (kqv[q] == 0 && lane == 0) {
+      double* out = out_of(q);
+      out[0] = 1.0;
+      out[1] = 0.0;
+    }
+  }
+  // the small ones together
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) any = any || (kqv[q] >= 1 && kqv[q] <= 16);
+  if (!any) return;
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int k = kqv[q];
+    if (k >= 1 && k <= 16) {
+      const TI* G;
+      DPhiRows<T> dr;
+      const int* lst;
+      item_rows(q, G, dr, lst);
+      form_A<T, TI, 1>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
+    }
+  }
+  const int gq = lane >> 4, r = lane & 15;
+  int kk = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (gq == q) kk = (kqv[q] >= 1 && kqv[q] <= 16) ? kqv[q] : 0;
+  double row[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    row[c] = (r < kk && c < kk) ? ab[gq * 16 * 17 + r * 17 + c] + (c == r ? 1.0 : 0.0) : 0.0;
+  double sg, ld;
+  bool sing;
+  group_lu_det16(row, kk, sg, ld, sing);
+  if (r == 0 && kk > 0) {
+    double* out = detA + (((int64_t)jq[0] * D.K + dq[0]) * 2 + s) * 2;
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+      if (gq == q) out = detA + (((int64_t)jq[q] * D.K + dq[q]) * 2 + s) * 2;
+    if (sing) { out[0] = 0.0; out[1] = -INFINITY; }
+    else { out[0] = sg; out[1] = ld; }
+  }
+}
+
+// det A for items with 16 < |U_s| <= 32, one per wave: 32 x 32 product on
+// MFMA tiles, then wave_lu_det.  Other items exit at once.
+template <typename T, typename TI>
+__global__ __launch_bounds__(256) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
+                                                  const int* __restrict__ uidx, int capmax,
+                                                  const int* __restrict__ ucnt, const int* __restrict__ off,
+                                                  const T* __restrict__ dphi, const T* __restrict__ oseg,
+                                                  const T* __restrict__ envnew, int fused,
+                                                  const char* __restrict__ state, StateRec S,
+                                                  double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][32 * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t item = (int64_t)blockIdx.x * 4 + wave;
@@ -524,12 +729,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
   const int j = g * jg + gq;
   if (j >= W) return;
   const int k = ucnt[2 * j + s];
-  double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
-  if (k == 0) {
-    if (lane == 0) { out[0] = 1.0; out[1] = 0.0; }
-    return;
-  }
-  if (k > 32) return;   // handled by k_detA
+  if (k <= 16 || k > 32) return;
   const int w = jw ? jw[j] : j;
   const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
@@ -540,65 +740,16 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
   const TI* G = (const TI*)(rec + S.inv) + boff;
   const DPhiRows<T> dr{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
                        (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
-  const int r16 = lane & 15, kq = lane >> 4;
-  const int KT = k > 16 ? 2 : 1;
-  int ua[2];
-  for (int t = 0; t < 2; ++t) {
-    const int a = 16 * t + r16;
-    ua[t] = a < k ? lst[a] : -1;
-  }
-  d4v_ acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
-  // operands of 8 MFMA steps (32 orbital columns) are loaded before any is
-  // used, so the loads of a chunk are in flight together
-  constexpr int CH = 8;
-  for (int cb = 0; cb < N; cb += 4 * CH) {
-    double af[CH][2], bf[CH][2];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int col = cb + 4 * u + kq;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int a = 16 * t + r16;
-        const bool ok = t < KT && a < k && col < N;
-        af[u][t] = ok ? dr.at(a, ua[t], col) : 0.0;
-        bf[u][t] = ok ? (double)G[(int64_t)(ua[t] - e0) * N + col] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      if (cb + 4 * u >= N) break;
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][0], bf[u][0], acc[0][0], 0, 0, 0);
-      if (KT > 1) {
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][0], bf[u][1], acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][1], bf[u][0], acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][1], bf[u][1], acc[1][1], 0, 0, 0);
-      }
-    }
-  }
-  // f64 16x16x4 output: register i of lane l holds row 4 i + l/16, column l%16
   double* ab = abuf[wave];
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-      if (x < KT && y < KT)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ab[(16 * x + 4 * i + kq) * 33 + 16 * y + r16] = acc[x][y][i];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  form_A<T, TI, 2>(dr, G, lst, k, N, e0, ab, 33);
   double row[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;
   double sg, ld;
   bool sing;
-  if (k <= 16)
-    wave_lu_det<16>(row, k, sg, ld, sing);
-  else
-    wave_lu_det<32>(row, k, sg, ld, sing);
+  wave_lu_det<32>(row, k, sg, ld, sing);
   if (lane == 0) {
+    double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
     if (sing) { out[0] = 0.0; out[1] = -INFINITY; }
     else { out[0] = sg; out[1] = ld; }
   }
@@ -1185,17 +1336,31 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     }
     const int jg = jb.group > 0 ? jb.group : 1;
     const int64_t items = (int64_t)((W + jg - 1) / jg) * jg * D.K;
+    const int64_t quads = (items + 3) / 4;
     if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
                          (double*)(ws + L.detA), jg);
     else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
                          (double*)(ws + L.detA), jg);
     CHECK(hipGetLastError());
+    if (L.capS[s] > 16) {
+      if (h->isize == 8)
+        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+                           s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                           (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
+                           S, (double*)(ws + L.detA), jg);
+      else
+        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+                           s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                           (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
+                           S, (double*)(ws + L.detA), jg);
+      CHECK(hipGetLastError());
+    }
     if (L.capS[s] > 32) {
       const size_t lds = detA_lds(L.capmax);
       const unsigned nblk = (unsigned)(((W + jg - 1) / jg) * D.K);
