@@ -27,6 +27,38 @@ sys.path.insert(0, ROOT)
 METRIC = "local energies/s + MCMC walker-steps/s @180 e⁻, BF16-hybrid vs FP32 plain"
 HBM_PEAK = 8.0e12
 PEAK = {"bf16": 2.5e15, "bf16x3": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_flake180_w4096.txt")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2504_06087_amd", "csrc", "gemm.hip")
+
+
+def measured_traffic():
+    """HBM bytes per split-bf16 GEMM launch from the committed counter
+    summary, or None when the GEMM source has changed since it was taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+        if kv.get("gemm_source_sha256") != src:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe():
+    import torch
+    n = 256 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_copy": n * 4, "copies": 3}))
 
 
 def parse():
@@ -41,6 +73,8 @@ def parse():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the uneven 16-system batch")
     ap.add_argument("--c5-walkers", type=int, default=512)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB three times (HBM counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -238,6 +272,9 @@ def cpu_baseline():
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (walkers shard across GPUs "
                                    "without communication inside a step, see the design notes)"}))
@@ -253,14 +290,26 @@ def main():
         torch.cuda.empty_cache()
         fp32 = run_precision("fp32", 0, W, a.steps, a.warmup, not a.no_grad, profile=False)
         print(f"# fp32: {json.dumps({k: v for k, v in fp32.items() if k != 'prof'})}", flush=True)
-    # roofline of the dominant kernel: the MFMA GEMM of the hybrid path
+    # roofline of the dominant kernel: the MFMA GEMM of the hybrid path.
+    # Algorithmic flops and bytes come from each launch's actual row count;
+    # the bound is HBM when the flops per byte fall below the ridge point.
     prof = hyb["prof"] or {}
     kind = max(prof, key=lambda k: prof[k][1]) if prof else "bf16x3"
-    la, ms, fl = prof.get(kind, (0, 0.0, 0.0))
-    achieved = fl / (ms / 1e3) if ms > 0 else 0.0
-    roof = {"bound": "mfma", "kernel": f"k_gemm<{kind}>", "achieved": achieved / 1e12, "peak": PEAK[kind] / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK[kind], "traffic": None,
-            "launches": la, "kernel_ms_per_step": ms / a.steps, "flops_per_step": fl / a.steps}
+    la, ms, fl, by = prof.get(kind, (0, 0.0, 0.0, 0.0))
+    sec = ms / 1e3
+    tflops = fl / sec / 1e12 if sec > 0 else 0.0
+    gbs = by / sec / 1e9 if sec > 0 else 0.0
+    hbm_bound = by > 0 and fl / by < PEAK[kind] / HBM_PEAK
+    traffic = measured_traffic() if kind == "bf16x3" else None
+    roof = {"bound": "hbm" if hbm_bound else "mfma", "kernel": f"k_gemm<{kind}>",
+            "achieved": gbs if hbm_bound else tflops, "peak": HBM_PEAK / 1e9 if hbm_bound else PEAK[kind] / 1e12,
+            "unit": "GB/s" if hbm_bound else "TFLOP/s",
+            "frac": (gbs * 1e9 / HBM_PEAK) if hbm_bound else (tflops * 1e12 / PEAK[kind]),
+            "traffic": traffic,
+            "launches": la, "kernel_ms_per_step": ms / a.steps, "mean_launch_us": 1e3 * ms / max(1, la),
+            "algorithmic_bytes_per_launch": by / max(1, la), "flops_per_launch": fl / max(1, la),
+            "achieved_tflops": tflops, "mfma_frac": tflops * 1e12 / PEAK[kind],
+            "achieved_gbs": gbs, "hbm_frac": gbs * 1e9 / HBM_PEAK}
     c5 = None
     if not a.no_c5:
         torch.cuda.empty_cache()

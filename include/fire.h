@@ -201,10 +201,15 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
  * bracketed by HIP events, and its actual row count is written (by the
  * kernel) into counters (device, int32 [capacity]).  fire_profile_end
  * synchronises the stream and returns, per GEMM kind (0 f64, 1 f32, 2 bf16,
- * 3 split bf16), the launch count, summed kernel time (ms) and algorithmic
- * flops 2*M*N*K (host arrays of 4).  Launches beyond capacity are not timed. */
+ * 3 split bf16), the launch count, summed kernel time (ms), algorithmic
+ * flops 2*M*N*K and algorithmic HBM bytes (M rows of A read and of C written,
+ * C also read when accumulating, the multiplier rows read, Bt read once;
+ * host arrays of 4).  Launches beyond capacity are not timed.
+ * Both calls also enqueue one empty kernel (k_profile_mark) on the stream, so
+ * that a kernel trace or counter run can cut out exactly the profiled work. */
 fire_status fire_profile_begin(fire_handle* h, hipStream_t stream, int32_t* counters, int capacity);
-fire_status fire_profile_end(fire_handle* h, hipStream_t stream, int64_t* launches, double* ms, double* flops);
+fire_status fire_profile_end(fire_handle* h, hipStream_t stream, int64_t* launches, double* ms, double* flops,
+                             double* bytes);
 
 /* ---------------------------------------------------------------------------
  * Uneven multi-system batches.  n_systems molecules with different electron

@@ -408,9 +408,10 @@ fire_status fire_profile_begin(fire_handle* h, hipStream_t stream, int32_t* coun
   return profile_begin(counters, capacity, stream) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
-fire_status fire_profile_end(fire_handle* h, hipStream_t s, int64_t* launches, double* ms, double* flops) {
-  if (!h || !launches || !ms || !flops) return FIRE_ERR_ARG;
-  return profile_end(s, launches, ms, flops) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+fire_status fire_profile_end(fire_handle* h, hipStream_t s, int64_t* launches, double* ms, double* flops,
+                             double* bytes) {
+  if (!h || !launches || !ms || !flops || !bytes) return FIRE_ERR_ARG;
+  return profile_end(s, launches, ms, flops, bytes) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
 fire_status fire_sync_status(fire_handle* h, hipStream_t s, const int32_t* status, int W, int32_t* any_flags) {

@@ -54,10 +54,12 @@ struct GemmProfiler {
   void* ev;           // std::vector of event pairs (opaque)
   int* kinds;
   int* nk;            // N*K per launch (host)
+  double* bpr;        // algorithmic HBM bytes per processed row (A row, C row(s))
+  double* bfix;       // algorithmic HBM bytes independent of the rows (Bt)
 };
 GemmProfiler& gemm_profiler();
 hipError_t profile_begin(int* counters, int capacity, hipStream_t s);
-hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flops);
+hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flops, double* bytes);
 
 // Launch on stream; kind fixes the element types:
 //   MMA_F64: A double, Bt double, C double

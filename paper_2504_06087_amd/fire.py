@@ -86,7 +86,7 @@ def load() -> ctypes.CDLL:
     lib.fire_sync_status.argtypes = [P, V, V, I, ctypes.POINTER(ctypes.c_int32)]
     lib.fire_profile_begin.argtypes = [P, V, V, I]
     lib.fire_profile_end.argtypes = [P, V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double)]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.fire_batch_create.argtypes = [ctypes.POINTER(FireSystemDesc), I, ctypes.POINTER(FireModelDesc),
                                       ctypes.POINTER(P)]
     lib.fire_batch_destroy.argtypes = [P]
@@ -296,13 +296,14 @@ class Fire:
         _check(load().fire_profile_begin(self.h, _stream(), _dp(self._prof_counters), capacity), "fire_profile_begin")
 
     def profile_end(self):
-        """{kind: (launches, ms, flops)} for the GEMM kinds f64, f32, bf16, bf16x3."""
+        """{kind: (launches, ms, flops, bytes)} for the GEMM kinds f64, f32, bf16, bf16x3."""
         la = (ctypes.c_int64 * 4)()
         ms = (ctypes.c_double * 4)()
         fl = (ctypes.c_double * 4)()
-        _check(load().fire_profile_end(self.h, _stream(), la, ms, fl), "fire_profile_end")
+        by = (ctypes.c_double * 4)()
+        _check(load().fire_profile_end(self.h, _stream(), la, ms, fl, by), "fire_profile_end")
         names = ["f64", "f32", "bf16", "bf16x3"]
-        return {names[k]: (int(la[k]), float(ms[k]), float(fl[k])) for k in range(4) if la[k]}
+        return {names[k]: (int(la[k]), float(ms[k]), float(fl[k]), float(by[k])) for k in range(4) if la[k]}
 
     # ------------------------------------------------------------------
     def state_view(self, state, W, which: str):
