@@ -264,6 +264,67 @@ FIRE_HOST_DEVICE int msg_part_size(const Dims& D) { return 2 * (filt_off(D).size
 // mbar gives Gammabar = mbar SiLU(pre), prebar = mbar Gamma SiLU'(pre);
 // abar_i += prebar, bbar_j += prebar (atomic), and the weight partials.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Reductions over channels for one chunk of up to 16 pairs (FP32):
+//   red[k][q]     = sum_c u1[k][c] W3[q][c]      (q < h2)
+//   red[k][8 + q] = sum_c u2[k][c] Wenv[q][c]    (q < G)
+// Each thread holds u1[k], u2[k] of its channel c; each wave multiplies its
+// 64 channels out on f32 16x16x4 MFMA (the u values are transposed through
+// LDS), the four wave partials are summed in LDS.  wb: this lane's B
+// operands, wb[s][t] = W_(16 t + l16)[64 wave + 4 s + l/16] (t = 0: W3 rows,
+// zero past h2; t = 1, 2: Wenv rows).
+// ---------------------------------------------------------------------------
+typedef float f4v_ __attribute__((ext_vector_type(4)));
+constexpr int RCH = 16;   // pairs per channel reduction
+
+// us: LDS [waves][2][RCH][64] floats, filled by the caller (chan_slot: this
+// thread's slots for u1 and u2 of pair k, zero past kc); wp: LDS
+// [waves][RCH][40] floats; red: LDS [RCH][40] (overwritten for k < kc).
+// Called by the whole block.
+FIRE_DEV float* chan_slot(float* us, int k, int which) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  return us + wave * 2 * RCH * 64 + (which * RCH + k) * 64 + lane;
+}
+FIRE_DEV void chan_reduce(int kc, const float* W3, const float* Wenv, int d, float* us, float* wp, float* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  float* mine = us + wave * 2 * RCH * 64;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  f4v_ r1 = {0.f, 0.f, 0.f, 0.f}, r2 = {0.f, 0.f, 0.f, 0.f}, r3 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int st = 0; st < 16; ++st) {
+    // A[row = pair l16][k = channel 4 st + lg], B[k = channel][col = output l16]
+    const int c = 64 * wave + 4 * st + lg;
+    const bool cin = c < d;
+    const float a1 = mine[l16 * 64 + 4 * st + lg];
+    const float a2 = mine[(RCH + l16) * 64 + 4 * st + lg];
+    const float b1 = (cin && l16 < kMaxH2) ? W3[l16 * d + c] : 0.f;
+    const float b2 = cin ? Wenv[l16 * d + c] : 0.f;
+    const float b3 = cin ? Wenv[(16 + l16) * d + c] : 0.f;
+    r1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, r1, 0, 0, 0);
+    r2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, r2, 0, 0, 0);
+    r3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b3, r3, 0, 0, 0);
+  }
+  // output register e of lane (l16, lg): row 4 lg + e, column l16
+  float* pw = wp + wave * RCH * 40;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * lg + e;
+    if (l16 < 8) pw[k * 40 + l16] = r1[e];
+    pw[k * 40 + 8 + l16] = r2[e];
+    pw[k * 40 + 24 + l16] = r3[e];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kc * 40; q += blockDim.x) {
+    float v = 0.f;
+    for (int w = 0; w < nw; ++w) v += wp[w * RCH * 40 + q];
+    red[q] = v;
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
                                                  const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
@@ -284,6 +345,8 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
   const bool act = c < D.d;
   const int n = D.n, d = D.d;
   for (int q = tid; q < 2 * astr; q += nt) acc[q] = T(0);
+  __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
+  __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
   T aW3[2][kMaxH2], aWenv[2][kMaxG], aWe[2][4], ab[2];
   for (int a = 0; a < 2; ++a) {
     for (int k = 0; k < kMaxH2; ++k) aW3[a][k] = 0;
@@ -324,9 +387,10 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
         }
         for (int q = tid; q < jc * 40; q += nt) red[q] = T(0);
         __syncthreads();
-        for (int k = 0; k < jc; ++k) {
+        auto pair_grads = [&](int k, T& u1, T& u2) {
           const T* f = feat + k * EFEAT;
-          T u1 = 0, u2 = 0;
+          u1 = 0;
+          u2 = 0;
           if (act && f[88] != T(0)) {
             T g1 = 0, g2 = 0;
             for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
@@ -347,14 +411,32 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
             for (int q = 0; q < D.h2; ++q) aW3[a][q] += u1 * f[48 + q];
             for (int q = 0; q < D.G; ++q) aWenv[a][q] += u2 * f[88] * f[56 + q];
           }
-          // per-pair reductions over channels: zbar2_q = sum_c u1 W3[q][c], chibar_q = sum_c u2 Wenv[q][c]
-          for (int q = 0; q < D.h2; ++q) {
-            T v = wave_sum(act ? u1 * w3[q] : T(0));
-            if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+        };
+        // per-pair reductions over channels: zbar2_q = sum_c u1 W3[q][c], chibar_q = sum_c u2 Wenv[q][c]
+        if constexpr (sizeof(T) == 4) {
+          for (int k0 = 0; k0 < jc; k0 += RCH) {
+            const int kc = jc - k0 < RCH ? jc - k0 : RCH;
+            for (int kk = 0; kk < RCH; ++kk) {
+              T u1 = 0, u2 = 0;
+              if (kk < kc) pair_grads(k0 + kk, u1, u2);
+              *chan_slot(red_us, kk, 0) = (float)u1;
+              *chan_slot(red_us, kk, 1) = (float)u2;
+            }
+            chan_reduce(kc, (const float*)(P.ee_W3 + a * D.h2 * d), (const float*)(P.ee_Wenv + a * D.G * d), d,
+                        red_us, red_wp, (float*)red + k0 * 40);
           }
-          for (int q = 0; q < D.G; ++q) {
-            T v = wave_sum(act ? u2 * wenv[q] : T(0));
-            if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+        } else {
+          for (int k = 0; k < jc; ++k) {
+            T u1, u2;
+            pair_grads(k, u1, u2);
+            for (int q = 0; q < D.h2; ++q) {
+              T v = wave_sum(act ? u1 * w3[q] : T(0));
+              if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+            }
+            for (int q = 0; q < D.G; ++q) {
+              T v = wave_sum(act ? u2 * wenv[q] : T(0));
+              if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+            }
           }
         }
         __syncthreads();
@@ -499,6 +581,9 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
     for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
     for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
   }
+  // FP32: B operands and LDS of the MFMA channel reductions
+  __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
+  __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
   for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
     const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
     const T sb = act ? sbar[e * D.d + c] : T(0);
@@ -511,9 +596,12 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
     }
     for (int q = tid; q < mc * 40; q += nt) red[q] = T(0);
     __syncthreads();
-    for (int k = 0; k < mc; ++k) {
+    // per pair: u1 = dL/dg1, u2 = dL/dg2 of this channel, and the weight
+    // gradients that stay per channel
+    auto pair_grads = [&](int k, T& u1, T& u2) {
       const T* f = feat + k * EFEAT;
-      T u1 = 0, u2 = 0;
+      u1 = 0;
+      u2 = 0;
       if (act && f[88] != T(0)) {
         T g1 = 0, g2 = 0;
         for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
@@ -528,13 +616,31 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
         for (int q = 0; q < D.h2; ++q) aW3[q] += u1 * f[48 + q];
         for (int q = 0; q < D.G; ++q) aWenv[q] += u2 * f[88] * f[56 + q];
       }
-      for (int q = 0; q < D.h2; ++q) {
-        T v = wave_sum(act ? u1 * w3[q] : T(0));
-        if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+    };
+    if constexpr (sizeof(T) == 4) {
+      // reductions over channels of 16 pairs at a time on MFMA
+      for (int k0 = 0; k0 < mc; k0 += RCH) {
+        const int kc = mc - k0 < RCH ? mc - k0 : RCH;
+        for (int kk = 0; kk < RCH; ++kk) {
+          T u1 = 0, u2 = 0;
+          if (kk < kc) pair_grads(k0 + kk, u1, u2);
+          *chan_slot(red_us, kk, 0) = (float)u1;
+          *chan_slot(red_us, kk, 1) = (float)u2;
+        }
+        chan_reduce(kc, (const float*)P.en_W3, (const float*)P.en_Wenv, D.d, red_us, red_wp, (float*)red + k0 * 40);
       }
-      for (int q = 0; q < D.G; ++q) {
-        T v = wave_sum(act ? u2 * wenv[q] : T(0));
-        if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+    } else {
+      for (int k = 0; k < mc; ++k) {
+        T u1, u2;
+        pair_grads(k, u1, u2);
+        for (int q = 0; q < D.h2; ++q) {
+          T v = wave_sum(act ? u1 * w3[q] : T(0));
+          if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
+        }
+        for (int q = 0; q < D.G; ++q) {
+          T v = wave_sum(act ? u2 * wenv[q] : T(0));
+          if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
+        }
       }
     }
     __syncthreads();

@@ -367,6 +367,15 @@ template <typename T> struct DPhiRows {
     const T en = u == e ? envnew[(int64_t)j * KN + det * N + l] : envc[(int64_t)iloc * N + l];
     return (double)(oseg[q] * en - phic[(int64_t)iloc * N + l]);
   }
+  // base pointers of row a (electron u) for branch-free element reads:
+  // x (dPhi, or o' when fused), y (envelope) and z (Phi)
+  FIRE_DEV void row_ptrs(int a, int u, const T*& x, const T*& y, const T*& z) const {
+    const int64_t q = (row0 + a) * KN + det * N;
+    const int iloc = u - e0;
+    x = (dphi ? dphi : oseg) + q;
+    y = u == e ? envnew + (int64_t)j * KN + det * N : envc + (int64_t)iloc * N;
+    z = phic + (int64_t)iloc * N;
+  }
 };
 
 // det A for update sets with |U_s| > 32 (rare; the wave kernel below takes
@@ -450,16 +459,19 @@ FIRE_DEV uint32_t lanes32_max(uint32_t key) {
 }
 
 // log|det A| and its sign of a k x k matrix (k <= KMAX <= 32) held one row
-// per lane (lane r holds row r, columns in registers).  Gaussian elimination
-// with partial pivoting that never moves rows: the pivot of column p is the
-// largest |A_rp| among the rows not yet used (ties to the lower row), its row
-// is broadcast with readlane, and the sign of the row permutation is counted
-// as inversions.  The product of the pivots is carried as a mantissa and a
-// binary exponent, so one logarithm is taken at the end.  Every register
-// index is a compile-time constant.
+// per lane (lane r holds row r, columns in registers; entries past k are
+// zero).  Gaussian elimination with partial pivoting that never moves rows:
+// the pivot of column p is the largest |A_rp| among the rows not yet used
+// (ties to the lower row), its row is broadcast with readlane, and the sign
+// of the row permutation is counted as inversions.  The product of the
+// pivots is carried as a mantissa and a binary exponent, so one logarithm is
+// taken at the end.  Every register index is a compile-time constant; k is
+// made wave-uniform so that the column guards are scalar branches over groups
+// of four columns (columns past k hold zeros and are updated harmlessly).
 template <int KMAX>
 FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, bool& sing) {
   const int lane = threadIdx.x & 63;
+  k = __builtin_amdgcn_readfirstlane(k);
   uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
   int inv = 0, ex = 0;
   double mant = 1.0;
@@ -490,8 +502,17 @@ FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, b
         const bool live = lane < 32 && ((unused >> (lane & 31)) & 1u);
         const double f = live ? row[p] / pv : 0.0;
 #pragma unroll
-        for (int c = p + 1; c < KMAX; ++c)
-          if (c < k) row[c] -= f * readlane_f64(row[c], idx);
+        for (int c0 = 0; c0 < KMAX; c0 += 4) {
+          if (c0 + 3 > p && c0 < k) {
+            double pr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (c0 + t > p) pr[t] = readlane_f64(row[c0 + t], idx);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (c0 + t > p) row[c0 + t] -= f * pr[t];
+          }
+        }
       }
     }
   }
@@ -554,16 +575,25 @@ FIRE_DEV void group_lu_det16(double (&row)[16], int kk, double& sgn, double& log
 
 // The product dPhi_U G_U^T of one (job, determinant) item, 16 KT x 16 KT,
 // on 16x16x4 f64 MFMA tiles, into LDS (row stride ld; rows/columns past k
-// are zero).  Operands of 8 MFMA steps (32 orbital columns) are loaded
-// before any is used.
-template <typename T, typename TI, int KT>
+// are zero).  Every element read is unconditional (rows past k read row 0,
+// columns past N read column N-1, and both are zeroed afterwards), so the
+// reads of 8 MFMA steps (32 orbital columns) are all in flight together.
+template <typename T, typename TI, int KT, bool FUSED>
 FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, int N, int e0, double* ab, int ld) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  int ua[KT];
+  const T* xr[KT];
+  const T* yr[KT];
+  const T* zr[KT];
+  const TI* gr[KT];
+  bool rok[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     const int a = 16 * t + r16;
-    ua[t] = a < k ? lst[a] : e0;
+    rok[t] = a < k;
+    const int aa = rok[t] ? a : 0;
+    const int u = lst[aa];
+    dr.row_ptrs(aa, u, xr[t], yr[t], zr[t]);
+    gr[t] = G + (int64_t)(u - e0) * N;
   }
   d4v_ acc[KT][KT];
 #pragma unroll
@@ -576,22 +606,26 @@ FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, 
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
       const int col = cb + 4 * u + kq;
+      const bool cok = col < N;
+      const int cc = cok ? col : N - 1;
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
-        const int a = 16 * t + r16;
-        const bool ok = a < k && col < N;
-        af[u][t] = ok ? dr.at(a, ua[t], col) : 0.0;
-        bf[u][t] = ok ? (double)G[(int64_t)(ua[t] - e0) * N + col] : 0.0;
+        const bool ok = rok[t] && cok;
+        double v;
+        if constexpr (FUSED) v = (double)(xr[t][cc] * yr[t][cc] - zr[t][cc]);
+        else v = (double)xr[t][cc];
+        const double g = (double)gr[t][cc];
+        af[u][t] = ok ? v : 0.0;
+        bf[u][t] = ok ? g : 0.0;
       }
     }
+    // steps past N multiply zeros; no early exit, so no read is held back
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      if (cb + 4 * u >= N) break;
+    for (int u = 0; u < CH; ++u)
 #pragma unroll
       for (int x = 0; x < KT; ++x)
 #pragma unroll
         for (int y = 0; y < KT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][x], bf[u][y], acc[x][y], 0, 0, 0);
-    }
   }
   // f64 16x16x4 output: register i of lane l holds row 4 i + l/16, column l%16
 #pragma unroll
@@ -683,7 +717,8 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
       DPhiRows<T> dr;
       const int* lst;
       item_rows(q, G, dr, lst);
-      form_A<T, TI, 1>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
+      if (fused) form_A<T, TI, 1, true>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
+      else form_A<T, TI, 1, false>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
     }
   }
   const int gq = lane >> 4, r = lane & 15;
@@ -741,7 +776,8 @@ __global__ __launch_bounds__(256) void k_detA_mid(const Dims D, int W, const int
   const DPhiRows<T> dr{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
                        (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
   double* ab = abuf[wave];
-  form_A<T, TI, 2>(dr, G, lst, k, N, e0, ab, 33);
+  if (fused) form_A<T, TI, 2, true>(dr, G, lst, k, N, e0, ab, 33);
+  else form_A<T, TI, 2, false>(dr, G, lst, k, N, e0, ab, 33);
   double row[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;
@@ -884,21 +920,26 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       // Gauss-Jordan on [A | I], lane r holds row r; pivots chosen among the
-      // unused rows by magnitude (no row moves): afterwards the right half of
-      // the pivot row of column p is row p of A^-1
+      // unused rows by magnitude (no row moves) and left unnormalised: step p
+      // subtracts (M_rp / M_ip) times pivot row i from every other row r.
+      // Left columns before p are unit columns by then and are skipped;
+      // columns past k are zero and skipped in groups of four (k is
+      // wave-uniform).  Afterwards row p of A^-1 is the right half of the
+      // pivot row of column p divided by its pivot.
       double row[2 * KSM];
 #pragma unroll
       for (int c = 0; c < KSM; ++c) {
         row[c] = (lane < k && c < k) ? Ai[lane * LA + c] + (c == lane ? 1.0 : 0.0) : 0.0;
         row[KSM + c] = (lane < k && c == lane) ? 1.0 : 0.0;
       }
-      uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
-      int pivrow[KSM];
+      const int ku = __builtin_amdgcn_readfirstlane(k);
+      uint32_t unused = ku >= 32 ? 0xffffffffu : ((1u << ku) - 1u);
+      int mycol = 0;
+      double mypv = 1.0;
       bool sing = false;
 #pragma unroll
       for (int p = 0; p < KSM; ++p) {
-        pivrow[p] = 0;
-        if (p < k && !sing) {
+        if (p < ku && !sing) {
           const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
           const float av = (float)fabs(row[p]);
           const uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
@@ -909,13 +950,33 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
             sing = true;
           } else {
             unused &= ~(1u << idx);
-            pivrow[p] = idx;
+            if (lane == idx) {
+              mypv = pv;
+              mycol = p;
+            }
             const double ip = 1.0 / pv;
-            const double fr = lane == idx ? 0.0 : row[p] * ip;
+            const double fr = (lane == idx || lane >= ku) ? 0.0 : row[p] * ip;
 #pragma unroll
-            for (int c = 0; c < 2 * KSM; ++c) {
-              const double pc = readlane_f64(row[c], idx);
-              row[c] = lane == idx ? row[c] * ip : row[c] - fr * pc;
+            for (int c0 = 0; c0 < KSM; c0 += 4) {
+              if (c0 + 3 > p && c0 < ku) {
+                double pr[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                  if (c0 + t > p) pr[t] = readlane_f64(row[c0 + t], idx);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                  if (c0 + t > p) row[c0 + t] -= fr * pr[t];
+              }
+            }
+#pragma unroll
+            for (int c0 = 0; c0 < KSM; c0 += 4) {
+              if (c0 < ku) {
+                double pr[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pr[t] = readlane_f64(row[KSM + c0 + t], idx);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) row[KSM + c0 + t] -= fr * pr[t];
+              }
             }
           }
         }
@@ -924,12 +985,12 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
         if (lane == 0) { fl[1] = 1; atomicOr(status + w, FIRE_W_SINGULAR); }
       } else {
         if (lane == 0) fl[1] = 0;
-        // A^-1 row p = right half of lane pivrow[p]; stored transposed
+        // A^-1 row p = right half of the pivot row of column p / its pivot;
+        // each pivot lane stores its row transposed (Ai = (A^-1)^T)
+        const double sc_row = 1.0 / mypv;
+        if (lane < ku)
 #pragma unroll
-        for (int p = 0; p < KSM; ++p)
-          if (p < k && lane == pivrow[p])
-#pragma unroll
-            for (int c = 0; c < KSM; ++c) Ai[c * LA + p] = c < k ? row[KSM + c] : 0.0;   // Ai = (A^-1)^T
+          for (int c = 0; c < KSM; ++c) Ai[c * LA + mycol] = c < ku ? row[KSM + c] * sc_row : 0.0;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
