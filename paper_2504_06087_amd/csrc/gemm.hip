@@ -9,6 +9,7 @@
 #include "gemm.hpp"
 
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -133,6 +134,16 @@ FIRE_DEV void gemm_epilogue(const GemmArgs& g, const Acc (&acc)[BM / 32][BN / 32
   }
 }
 
+// Tile order.  Workgroups are dealt to the eight XCDs round-robin by
+// workgroup index, so with x = bid % 8 and k = bid / 8 row tile
+// x + 8 (k / nct) and column tile k % nct: each row tile is an XCD's own
+// (its column tiles share the A rows in that XCD's L2), and the row tiles of
+// the first rows are spread over all XCDs, which keeps the chip balanced when
+// only a prefix of the row capacity is live (device row count).  The grid is
+// round_up(row tiles, 8) x column tiles.
+FIRE_DEV int tile_row(int bid, int nct) { return (bid & 7) + 8 * ((bid >> 3) / nct); }
+FIRE_DEV int tile_col(int bid, int nct) { return (bid >> 3) % nct; }
+
 template <int KIND, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
   using P = MK<KIND>;
@@ -159,11 +170,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
     g.C = (char*)g.C + (int64_t)blockIdx.y * g.c_split_stride * (int64_t)sizeof(typename P::TC);
   }
   const int Kl = kend - kbeg;
-  // XCD-aware remap: consecutive logical tiles on the same XCD share A rows in L2
-  const int nb = gridDim.x, per = nb / 8;
-  const int bid = blockIdx.x;
-  const int lid = (bid < per * 8) ? (bid % 8) * per + bid / 8 : bid;
-  const int rt = lid / nct, ct = lid % nct;
+  const int rt = tile_row(blockIdx.x, nct), ct = tile_col(blockIdx.x, nct);
   const int64_t row0 = (int64_t)rt * BM, col0 = (int64_t)ct * BN;
   if (g.Mdev) {
     int m = *g.Mdev;
@@ -373,10 +380,7 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
 
   const int tid = threadIdx.x;
   const int nct = (g.N + BN - 1) / BN;
-  const int nb = gridDim.x, per = nb / 8;
-  const int bid = blockIdx.x;
-  const int lid = (bid < per * 8) ? (bid % 8) * per + bid / 8 : bid;
-  const int rt = lid / nct, ct = lid % nct;
+  const int rt = tile_row(blockIdx.x, nct), ct = tile_col(blockIdx.x, nct);
   const int64_t row0 = (int64_t)rt * BM, col0 = (int64_t)ct * BN;
   if (g.Mdev) {
     int m = *g.Mdev;
@@ -688,7 +692,7 @@ template <int KIND> static bool fast_ok(const GemmArgs& g) {
 
 template <int KIND, int BM, int BN> static hipError_t launch_tile(const GemmArgs& g, hipStream_t s, int vecA,
                                                                   int vecB) {
-  const int64_t tiles = (int64_t)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  const int64_t tiles = (int64_t)(((g.M + BM - 1) / BM + 7) / 8 * 8) * ((g.N + BN - 1) / BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   if constexpr (KIND != MMA_F64) {
     if (fast_ok<KIND>(g)) {
@@ -781,6 +785,10 @@ template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
     const double eb = KIND == MMA_F64 ? 8.0 : (KIND == MMA_F32 ? 4.0 : (KIND == MMA_BF16 ? 2.0 : 4.0));
     pr.bpr[slot] = (double)g.K * ea + (double)g.N * ec * (1.0 + (g.aux ? 1.0 : 0.0) + (g.accumulate ? 1.0 : 0.0));
     pr.bfix[slot] = (double)g.N * (double)g.K * eb;
+    pr.shape[4 * slot] = g.M;
+    pr.shape[4 * slot + 1] = g.N;
+    pr.shape[4 * slot + 2] = g.K;
+    pr.shape[4 * slot + 3] = v;
     (void)hipEventRecord(evs[2 * slot], s);
   }
   hipError_t e = launch_variant<KIND>(v, g, s, vecA, vecB);
@@ -860,6 +868,7 @@ hipError_t profile_begin(int* counters, int capacity, hipStream_t s) {
     delete[] pr.nk;
     delete[] pr.bpr;
     delete[] pr.bfix;
+    delete[] pr.shape;
   }
   pr.ev = nullptr;
   pr.capacity = capacity;
@@ -874,6 +883,7 @@ hipError_t profile_begin(int* counters, int capacity, hipStream_t s) {
   pr.nk = new int[capacity];
   pr.bpr = new double[capacity];
   pr.bfix = new double[capacity];
+  pr.shape = new int[4 * (size_t)capacity];
   pr.on = true;
   return hipSuccess;
 }
@@ -888,15 +898,22 @@ hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flo
   int* rows = new int[pr.used > 0 ? pr.used : 1];
   if (pr.used > 0) e = hipMemcpy(rows, pr.counters, (size_t)pr.used * 4, hipMemcpyDeviceToHost);
   hipEvent_t* ev = (hipEvent_t*)pr.ev;
+  const char* logpath = getenv("FIRE_GEMM_LOG");
+  FILE* lf = logpath ? fopen(logpath, "a") : nullptr;
   for (int k = 0; k < pr.used && e == hipSuccess; ++k) {
     float t = 0;
     (void)hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]);
     const int kd = pr.kinds[k];
+    const double b = (double)rows[k] * pr.bpr[k] + pr.bfix[k];
     launches[kd] += 1;
     ms[kd] += t;
     flops[kd] += 2.0 * (double)rows[k] * (double)pr.nk[k];
-    bytes[kd] += (double)rows[k] * pr.bpr[k] + pr.bfix[k];
+    bytes[kd] += b;
+    if (lf)
+      fprintf(lf, "%d %d %d %d %d %d %.6f %.0f\n", kd, rows[k], pr.shape[4 * k], pr.shape[4 * k + 1],
+              pr.shape[4 * k + 2], pr.shape[4 * k + 3], t, b);
   }
+  if (lf) fclose(lf);
   delete[] rows;
   return e;
 }

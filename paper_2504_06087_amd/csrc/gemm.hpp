@@ -56,9 +56,13 @@ struct GemmProfiler {
   int* nk;            // N*K per launch (host)
   double* bpr;        // algorithmic HBM bytes per processed row (A row, C row(s))
   double* bfix;       // algorithmic HBM bytes independent of the rows (Bt)
+  int* shape;         // per launch: row capacity, N, K, tile variant (host)
 };
 GemmProfiler& gemm_profiler();
 hipError_t profile_begin(int* counters, int capacity, hipStream_t s);
+// profile_end: per-kind totals; with FIRE_GEMM_LOG set to a file path, one
+// line per launch (kind, rows processed, row capacity, N, K, variant, ms,
+// algorithmic bytes) is appended to that file.
 hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flops, double* bytes);
 
 // Launch on stream; kind fixes the element types:
