@@ -380,247 +380,253 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
 
   const int tid = threadIdx.x;
   const int nct = (g.N + BN - 1) / BN;
-  const int rt = tile_row(blockIdx.x, nct), ct = tile_col(blockIdx.x, nct);
-  const int64_t row0 = (int64_t)rt * BM, col0 = (int64_t)ct * BN;
   if (g.Mdev) {
     int m = *g.Mdev;
     if (m < g.M) g.M = m;
   }
   if (g.prof_rows && blockIdx.x == 0 && threadIdx.x == 0) *g.prof_rows = g.M;
-  if (row0 >= g.M) return;
   const int K = g.K;
-
-  const float* arow[CA];
-  int ak[CA], ar[CA];
-#pragma unroll
-  for (int t = 0; t < CA; ++t) {
-    const int q = tid + 256 * t;
-    ar[t] = q / (BK / 4);
-    ak[t] = (q % (BK / 4)) * 4;
-    int64_t r = row0 + ar[t];
-    if (r >= g.M) r = row0;
-    arow[t] = (const float*)g.A + r * g.amap.gstride;
-  }
-  const char* brow[CB];
-  const char* browl[CB];
-  int bk[CB], br[CB];
-  constexpr int BE = BF ? 2 : 4;             // bytes per Bt element
-#pragma unroll
-  for (int t = 0; t < CB; ++t) {
-    const int q = tid + 256 * t;
-    br[t] = q / (BK / BV);
-    bk[t] = (q % (BK / BV)) * BV;
-    int64_t c = col0 + br[t];
-    if (c >= g.N) c = col0;
-    brow[t] = (const char*)g.Bt + c * g.ldb * BE;
-    browl[t] = SPLIT ? (const char*)g.Bt_lo + c * g.ldb * BE : brow[t];
-  }
-
-  Acc acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
-
-  // one register stage of global loads
-  struct Regs {
-    float4 a[CA];
-    uint4 b[CB];
-    uint4 bl[SPLIT ? CB : 1];
-  };
-  auto gload = [&](Regs& R, int k0) {
+  // persistent: the grid (a multiple of 8) walks the tiles of the live rows
+  // in the XCD order of tile_row/tile_col, so a workgroup stays on its XCD's
+  // row tiles and the grid drains once the live rows are done
+  const int ntiles = ((g.M + BM - 1) / BM + 7) / 8 * 8 * nct;
+  auto one_tile = [&](const int64_t row0, const int64_t col0) {
+    const float* arow[CA];
+    int ak[CA], ar[CA];
 #pragma unroll
     for (int t = 0; t < CA; ++t) {
-      const int kk = k0 + ak[t];
-      const bool ok = kk < K;
-      float4 v = *reinterpret_cast<const float4*>(arow[t] + (ok ? kk : 0));
-      R.a[t] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int q = tid + 256 * t;
+      ar[t] = q / (BK / 4);
+      ak[t] = (q % (BK / 4)) * 4;
+      int64_t r = row0 + ar[t];
+      if (r >= g.M) r = row0;
+      arow[t] = (const float*)g.A + r * g.amap.gstride;
     }
+    const char* brow[CB];
+    const char* browl[CB];
+    int bk[CB], br[CB];
+    constexpr int BE = BF ? 2 : 4;             // bytes per Bt element
 #pragma unroll
     for (int t = 0; t < CB; ++t) {
-      const int kk = k0 + bk[t];
-      const bool ok = kk < K;
-      const int64_t off = (int64_t)(ok ? kk : 0) * BE;
-      uint4 v = *reinterpret_cast<const uint4*>(brow[t] + off);
-      R.b[t] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
-      if constexpr (SPLIT) {
-        uint4 w = *reinterpret_cast<const uint4*>(browl[t] + off);
-        R.bl[t] = ok ? w : make_uint4(0u, 0u, 0u, 0u);
-      }
+      const int q = tid + 256 * t;
+      br[t] = q / (BK / BV);
+      bk[t] = (q % (BK / BV)) * BV;
+      int64_t c = col0 + br[t];
+      if (c >= g.N) c = col0;
+      brow[t] = (const char*)g.Bt + c * g.ldb * BE;
+      browl[t] = SPLIT ? (const char*)g.Bt_lo + c * g.ldb * BE : brow[t];
     }
-  };
-  auto stage_ptrs = [&](int buf, TL*& As, TL*& Bs, TL*& Asl, TL*& Bsl) {
-    As = (TL*)(lds + buf * 0);
-    Bs = As + BM * LDK;
-    Asl = Bs + BN * LDK;
-    Bsl = Asl + (SPLIT ? BM * LDK : 0);
-  };
-  auto store = [&](const Regs& R, int buf) {
-    TL *As, *Bs, *Asl, *Bsl;
-    stage_ptrs(buf, As, Bs, Asl, Bsl);
-    if constexpr (BF) {
+
+    Acc acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][j][e] = 0;
+
+    // one register stage of global loads
+    struct Regs {
+      float4 a[CA];
+      uint4 b[CB];
+      uint4 bl[SPLIT ? CB : 1];
+    };
+    auto gload = [&](Regs& R, int k0) {
 #pragma unroll
       for (int t = 0; t < CA; ++t) {
-        const float4 x = R.a[t];
-        const bf4v h = {(__bf16)x.x, (__bf16)x.y, (__bf16)x.z, (__bf16)x.w};
-        *reinterpret_cast<bf4v*>(&As[ar[t] * LDK + ak[t]]) = h;
-        if constexpr (SPLIT) {
-          const bf4v l = {(__bf16)(x.x - (float)h[0]), (__bf16)(x.y - (float)h[1]), (__bf16)(x.z - (float)h[2]),
-                          (__bf16)(x.w - (float)h[3])};
-          *reinterpret_cast<bf4v*>(&Asl[ar[t] * LDK + ak[t]]) = l;
-        }
+        const int kk = k0 + ak[t];
+        const bool ok = kk < K;
+        float4 v = *reinterpret_cast<const float4*>(arow[t] + (ok ? kk : 0));
+        R.a[t] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int t = 0; t < CB; ++t) {
-        *reinterpret_cast<uint4*>(&Bs[br[t] * LDK + bk[t]]) = R.b[t];
-        if constexpr (SPLIT) *reinterpret_cast<uint4*>(&Bsl[br[t] * LDK + bk[t]]) = R.bl[t];
+        const int kk = k0 + bk[t];
+        const bool ok = kk < K;
+        const int64_t off = (int64_t)(ok ? kk : 0) * BE;
+        uint4 v = *reinterpret_cast<const uint4*>(brow[t] + off);
+        R.b[t] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (SPLIT) {
+          uint4 w = *reinterpret_cast<const uint4*>(browl[t] + off);
+          R.bl[t] = ok ? w : make_uint4(0u, 0u, 0u, 0u);
+        }
       }
-    } else {
+    };
+    auto stage_ptrs = [&](int buf, TL*& As, TL*& Bs, TL*& Asl, TL*& Bsl) {
+      As = (TL*)(lds + buf * 0);
+      Bs = As + BM * LDK;
+      Asl = Bs + BN * LDK;
+      Bsl = Asl + (SPLIT ? BM * LDK : 0);
+    };
+    auto store = [&](const Regs& R, int buf) {
+      TL *As, *Bs, *Asl, *Bsl;
+      stage_ptrs(buf, As, Bs, Asl, Bsl);
+      if constexpr (BF) {
 #pragma unroll
-      for (int t = 0; t < CA; ++t) *reinterpret_cast<float4*>(&As[ar[t] * LDK + ak[t]]) = R.a[t];
-#pragma unroll
-      for (int t = 0; t < CB; ++t) *reinterpret_cast<uint4*>(&Bs[br[t] * LDK + bk[t]]) = R.b[t];
-    }
-  };
-
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lg = lane >> 4, l16 = lane & 15;
-  auto compute = [&](int buf) {
-    TL *As, *Bs, *Asl, *Bsl;
-    stage_ptrs(buf, As, Bs, Asl, Bsl);
-    if constexpr (BF) {
-      bf16x8v af[TM], bfr[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        af[i] = *reinterpret_cast<const bf16x8v*>(&As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bfr[j] = *reinterpret_cast<const bf16x8v*>(&Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
-      if constexpr (SPLIT) {
-        bf16x8v afl[TM], bfl[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-          afl[i] = *reinterpret_cast<const bf16x8v*>(&Asl[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          bfl[j] = *reinterpret_cast<const bf16x8v*>(&Bsl[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+        for (int t = 0; t < CA; ++t) {
+          const float4 x = R.a[t];
+          const bf4v h = {(__bf16)x.x, (__bf16)x.y, (__bf16)x.z, (__bf16)x.w};
+          *reinterpret_cast<bf4v*>(&As[ar[t] * LDK + ak[t]]) = h;
+          if constexpr (SPLIT) {
+            const bf4v l = {(__bf16)(x.x - (float)h[0]), (__bf16)(x.y - (float)h[1]), (__bf16)(x.z - (float)h[2]),
+                            (__bf16)(x.w - (float)h[3])};
+            *reinterpret_cast<bf4v*>(&Asl[ar[t] * LDK + ak[t]]) = l;
           }
-      }
+        }
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int t = 0; t < CB; ++t) {
+          *reinterpret_cast<uint4*>(&Bs[br[t] * LDK + bk[t]]) = R.b[t];
+          if constexpr (SPLIT) *reinterpret_cast<uint4*>(&Bsl[br[t] * LDK + bk[t]]) = R.bl[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < CA; ++t) *reinterpret_cast<float4*>(&As[ar[t] * LDK + ak[t]]) = R.a[t];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) *reinterpret_cast<uint4*>(&Bs[br[t] * LDK + bk[t]]) = R.b[t];
+      }
+    };
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lg = lane >> 4, l16 = lane & 15;
+    auto compute = [&](int buf) {
+      TL *As, *Bs, *Asl, *Bsl;
+      stage_ptrs(buf, As, Bs, Asl, Bsl);
+      if constexpr (BF) {
+        bf16x8v af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          af[i] = *reinterpret_cast<const bf16x8v*>(&As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    } else {
-      float af[TM][8], bfr[TN][8];
+          bfr[j] = *reinterpret_cast<const bf16x8v*>(&Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
+        if constexpr (SPLIT) {
+          bf16x8v afl[TM], bfl[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const float* src = &As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg];
-        const float4 u0 = *reinterpret_cast<const float4*>(src), u1 = *reinterpret_cast<const float4*>(src + 4);
-        af[i][0] = u0.x; af[i][1] = u0.y; af[i][2] = u0.z; af[i][3] = u0.w;
-        af[i][4] = u1.x; af[i][5] = u1.y; af[i][6] = u1.z; af[i][7] = u1.w;
-      }
+          for (int i = 0; i < TM; ++i)
+            afl[i] = *reinterpret_cast<const bf16x8v*>(&Asl[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg]);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const float* src = &Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg];
-        const float4 u0 = *reinterpret_cast<const float4*>(src), u1 = *reinterpret_cast<const float4*>(src + 4);
-        bfr[j][0] = u0.x; bfr[j][1] = u0.y; bfr[j][2] = u0.z; bfr[j][3] = u0.w;
-        bfr[j][4] = u1.x; bfr[j][5] = u1.y; bfr[j][6] = u1.z; bfr[j][7] = u1.w;
-      }
+          for (int j = 0; j < TN; ++j)
+            bfl[j] = *reinterpret_cast<const bf16x8v*>(&Bsl[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg]);
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl[i], bfr[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfl[j], acc[i][j], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][e], bfr[j][e], acc[i][j], 0, 0, 0);
-    }
-  };
-
-  // Pipeline: the global loads of slice k+1 are in flight while slice k is
-  // multiplied out of LDS.
-  const int nk = (K + BK - 1) / BK;
-  Regs R;
-  if (nk > 0) gload(R, 0);
-  for (int kt = 0; kt < nk; ++kt) {
-    store(R, 0);
-    __syncthreads();
-    if (kt + 1 < nk) gload(R, (kt + 1) * BK);
-    compute(0);
-    __syncthreads();
-  }
-  if constexpr (!VEC) {
-    gemm_epilogue<KIND, BM, BN>(g, acc, row0, col0, wm, wn, lg, l16);
-    return;
-  }
-  // Epilogue through LDS for dense C/aux rows: one half of the tile (the
-  // waves of one wave row) at a time is written to LDS in the MFMA layout,
-  // then every thread applies bias/SiLU/aux/accumulate to 4 consecutive
-  // columns and stores them with one 16-byte store (rows written whole).
-  float* Cs = (float*)lds;
-  const float* bias = (const float*)g.bias;
-  const float* aux = (const float*)g.aux;
-  float* C = (float*)g.C;
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      } else {
+        float af[TM][8], bfr[TN][8];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (wm == h) {
+        for (int i = 0; i < TM; ++i) {
+          const float* src = &As[(wm * (BM / 2) + i * 16 + l16) * LDK + 8 * lg];
+          const float4 u0 = *reinterpret_cast<const float4*>(src), u1 = *reinterpret_cast<const float4*>(src + 4);
+          af[i][0] = u0.x; af[i][1] = u0.y; af[i][2] = u0.z; af[i][3] = u0.w;
+          af[i][4] = u1.x; af[i][5] = u1.y; af[i][6] = u1.z; af[i][7] = u1.w;
+        }
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < TN; ++j) {
+          const float* src = &Bs[(wn * (BN / 2) + j * 16 + l16) * LDK + 8 * lg];
+          const float4 u0 = *reinterpret_cast<const float4*>(src), u1 = *reinterpret_cast<const float4*>(src + 4);
+          bfr[j][0] = u0.x; bfr[j][1] = u0.y; bfr[j][2] = u0.z; bfr[j][3] = u0.w;
+          bfr[j][4] = u1.x; bfr[j][5] = u1.y; bfr[j][6] = u1.z; bfr[j][7] = u1.w;
+        }
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int e = 0; e < 8; ++e)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) Cs[(i * 16 + 4 * lg + e) * LDC + wn * (BN / 2) + j * 16 + l16] = acc[i][j][e];
-    }
-    __syncthreads();
-    constexpr int NV = (BM / 2) * (BN / 4);
-    constexpr int NQ = NV / 256;
-    constexpr int CH = NQ < 4 ? NQ : 4;
-    // per chunk of CH float4: all loads first (aux and C may alias as far as
-    // the compiler knows, so a load issued after a store would wait for it)
+          for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int u0 = 0; u0 < NQ; u0 += CH) {
-      float4 xv[CH], ov[CH];
-#pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int q = (u0 + u) * 256 + tid;
-        const int rr = q / (BN / 4), cc = (q % (BN / 4)) * 4;
-        const int64_t r = row0 + h * (BM / 2) + rr, c = col0 + cc;
-        const bool ok = r < g.M && c < g.N;
-        xv[u] = make_float4(1.f, 1.f, 1.f, 1.f);
-        ov[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (aux && ok) xv[u] = *reinterpret_cast<const float4*>(aux + r * g.xmap.gstride + c);
-        if (g.accumulate && ok) ov[u] = *reinterpret_cast<const float4*>(C + r * g.cmap.gstride + c);
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][e], bfr[j][e], acc[i][j], 0, 0, 0);
       }
+    };
+
+    // Pipeline: the global loads of slice k+1 are in flight while slice k is
+    // multiplied out of LDS.
+    const int nk = (K + BK - 1) / BK;
+    Regs R;
+    if (nk > 0) gload(R, 0);
+    for (int kt = 0; kt < nk; ++kt) {
+      store(R, 0);
+      __syncthreads();
+      if (kt + 1 < nk) gload(R, (kt + 1) * BK);
+      compute(0);
+      __syncthreads();
+    }
+    if constexpr (!VEC) {
+      gemm_epilogue<KIND, BM, BN>(g, acc, row0, col0, wm, wn, lg, l16);
+      return;
+    }
+    // Epilogue through LDS for dense C/aux rows: one half of the tile (the
+    // waves of one wave row) at a time is written to LDS in the MFMA layout,
+    // then every thread applies bias/SiLU/aux/accumulate to 4 consecutive
+    // columns and stores them with one 16-byte store (rows written whole).
+    float* Cs = (float*)lds;
+    const float* bias = (const float*)g.bias;
+    const float* aux = (const float*)g.aux;
+    float* C = (float*)g.C;
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int q = (u0 + u) * 256 + tid;
-        const int rr = q / (BN / 4), cc = (q % (BN / 4)) * 4;
-        const int64_t r = row0 + h * (BM / 2) + rr, c = col0 + cc;
-        if (r < g.M && c < g.N) {
-          float4 v = *reinterpret_cast<const float4*>(&Cs[rr * LDC + cc]);
-          if (bias && !(g.bias_period > 0 && (uint32_t)r % (uint32_t)g.bias_period)) {
-            const float4 b = *reinterpret_cast<const float4*>(bias + c);
-            v.x += b.x; v.y += b.y; v.z += b.z; v.w += b.w;
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Cs[(i * 16 + 4 * lg + e) * LDC + wn * (BN / 2) + j * 16 + l16] = acc[i][j][e];
+      }
+      __syncthreads();
+      constexpr int NV = (BM / 2) * (BN / 4);
+      constexpr int NQ = NV / 256;
+      constexpr int CH = NQ < 4 ? NQ : 4;
+      // per chunk of CH float4: all loads first (aux and C may alias as far as
+      // the compiler knows, so a load issued after a store would wait for it)
+#pragma unroll
+      for (int u0 = 0; u0 < NQ; u0 += CH) {
+        float4 xv[CH], ov[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int q = (u0 + u) * 256 + tid;
+          const int rr = q / (BN / 4), cc = (q % (BN / 4)) * 4;
+          const int64_t r = row0 + h * (BM / 2) + rr, c = col0 + cc;
+          const bool ok = r < g.M && c < g.N;
+          xv[u] = make_float4(1.f, 1.f, 1.f, 1.f);
+          ov[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (aux && ok) xv[u] = *reinterpret_cast<const float4*>(aux + r * g.xmap.gstride + c);
+          if (g.accumulate && ok) ov[u] = *reinterpret_cast<const float4*>(C + r * g.cmap.gstride + c);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int q = (u0 + u) * 256 + tid;
+          const int rr = q / (BN / 4), cc = (q % (BN / 4)) * 4;
+          const int64_t r = row0 + h * (BM / 2) + rr, c = col0 + cc;
+          if (r < g.M && c < g.N) {
+            float4 v = *reinterpret_cast<const float4*>(&Cs[rr * LDC + cc]);
+            if (bias && !(g.bias_period > 0 && (uint32_t)r % (uint32_t)g.bias_period)) {
+              const float4 b = *reinterpret_cast<const float4*>(bias + c);
+              v.x += b.x; v.y += b.y; v.z += b.z; v.w += b.w;
+            }
+            if (g.act == ACT_SILU) {
+              v.x = silu_(v.x); v.y = silu_(v.y); v.z = silu_(v.z); v.w = silu_(v.w);
+            }
+            v.x *= xv[u].x; v.y *= xv[u].y; v.z *= xv[u].z; v.w *= xv[u].w;
+            v.x += ov[u].x; v.y += ov[u].y; v.z += ov[u].z; v.w += ov[u].w;
+            *reinterpret_cast<float4*>(C + r * g.cmap.gstride + c) = v;
           }
-          if (g.act == ACT_SILU) {
-            v.x = silu_(v.x); v.y = silu_(v.y); v.z = silu_(v.z); v.w = silu_(v.w);
-          }
-          v.x *= xv[u].x; v.y *= xv[u].y; v.z *= xv[u].z; v.w *= xv[u].w;
-          v.x += ov[u].x; v.y += ov[u].y; v.z += ov[u].z; v.w += ov[u].w;
-          *reinterpret_cast<float4*>(C + r * g.cmap.gstride + c) = v;
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
+  };
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = (int64_t)tile_row(t, nct) * BM, col0 = (int64_t)tile_col(t, nct) * BN;
+    if (row0 < g.M) one_tile(row0, col0);
   }
 }
 
@@ -690,16 +696,39 @@ template <int KIND> static bool fast_ok(const GemmArgs& g) {
   return true;
 }
 
+// Workgroups of the persistent fast kernel that fit on the current device at
+// once (occupancy x compute units), rounded down to a multiple of 8; cached
+// per device.
+template <int KIND, int BM, int BN, bool VEC> static int resident_wgs() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cached[dev] > 0) return cached[dev];
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_fast<KIND, BM, BN, VEC>, 256, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  int n = per_cu * cus / 8 * 8;
+  cached[dev] = n < 8 ? 8 : n;
+  return cached[dev];
+}
+
 template <int KIND, int BM, int BN> static hipError_t launch_tile(const GemmArgs& g, hipStream_t s, int vecA,
                                                                   int vecB) {
   const int64_t tiles = (int64_t)(((g.M + BM - 1) / BM + 7) / 8 * 8) * ((g.N + BN - 1) / BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   if constexpr (KIND != MMA_F64) {
     if (fast_ok<KIND>(g)) {
-      if (vec_epi_ok(g))
-        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
-      else
-        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, false>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+      if (vec_epi_ok(g)) {
+        const int64_t r = resident_wgs<KIND, BM, BN, true>();
+        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, true>), dim3((unsigned)(tiles < r ? tiles : r)), dim3(256), 0,
+                           s, g);
+      } else {
+        const int64_t r = resident_wgs<KIND, BM, BN, false>();
+        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, false>), dim3((unsigned)(tiles < r ? tiles : r)), dim3(256), 0,
+                           s, g);
+      }
       return hipGetLastError();
     }
   }
