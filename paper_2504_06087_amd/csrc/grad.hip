@@ -216,31 +216,85 @@ FIRE_DEV void edge_forward(T dx, T dy, T dz, const T* W1, const T* b1, const T* 
   f[88] = fcut_(r / cut);
 }
 
-// Backward of one pair's filter given zbar2 (h2) and chibar (G): accumulates
-// into acc = [W1 (4 h1) | b1 (h1) | W2 (h1 h2) | b2 (h2) | sigma (G)] (LDS).
+// Backward of the filters of a chunk of pairs in two steps, so that no two
+// threads ever add into the same accumulator entry:
+//  edge_backward_terms (one thread per pair, f = its edge_forward values,
+//    zb2 = zbar2 (h2), chib = chibar (G)) writes the per-pair terms
+//    t = [pre2bar (h2) | pre1bar (h1) | d/dsigma terms (G)], zeros for a
+//    pair outside the cutoff;
+//  edge_param_sums (all threads, one accumulator entry each) adds their sums
+//    over the chunk into W2, b2, sigma and W1, b1 (shared, or per pair slot
+//    when each slot has its own first layer).
+constexpr int ET = kMaxH2 + kMaxH1 + kMaxG;   // per-pair terms
 template <typename T>
-FIRE_DEV void edge_backward(const T* f, const T* zb2, const T* chib, const T* W2, const T* sig, const Dims& D,
-                            T* accW1, T* accb1, T* accW2, T* accb2, T* accsig) {
+FIRE_DEV void edge_backward_terms(const T* f, const T* zb2, const T* chib, const T* W2, const T* sig, T* t) {
+  constexpr int h1 = kMaxH1, h2 = kMaxH2, G = kMaxG;
   const T r = f[0], fc = f[88];
-  for (int k = 0; k < D.G; ++k) atomicAdd(&accsig[k], chib[k] * fc * f[56 + k] * (T(-2) * sig[k] * r * r));
-  T pre2b[kMaxH2];
-  for (int k = 0; k < D.h2; ++k) {
-    T s, s1, s2;
-    silu3(f[40 + k], s, s1, s2);
-    pre2b[k] = zb2[k] * s1;
-    atomicAdd(&accb2[k], pre2b[k]);
+  if (fc == T(0)) {
+    for (int k = 0; k < ET; ++k) t[k] = T(0);
+    return;
   }
-  for (int j = 0; j < D.h1; ++j) {
+  for (int k = 0; k < G; ++k) t[h2 + h1 + k] = chib[k] * fc * f[56 + k] * (T(-2) * sig[k] * r * r);
+  T pre2b[h2];
+  for (int k = 0; k < h2; ++k) {
+    T sv, s1, s2;
+    silu3(f[40 + k], sv, s1, s2);
+    pre2b[k] = zb2[k] * s1;
+    t[k] = pre2b[k];
+  }
+  for (int j = 0; j < h1; ++j) {
     T z1b = 0;
-    for (int k = 0; k < D.h2; ++k) {
-      atomicAdd(&accW2[j * D.h2 + k], pre2b[k] * f[24 + j]);
-      z1b += pre2b[k] * W2[j * D.h2 + k];
+    for (int k = 0; k < h2; ++k) z1b += pre2b[k] * W2[j * h2 + k];
+    T sv, s1, s2;
+    silu3(f[8 + j], sv, s1, s2);
+    t[h2 + j] = z1b * s1;
+  }
+}
+
+template <typename T, bool W1SLOT>
+FIRE_DEV void edge_param_sums(const T* feat, const T* et, int np, T* accW1, T* accb1, T* accW2, T* accb2,
+                              T* accsig) {
+  constexpr int h1 = kMaxH1, h2 = kMaxH2, G = kMaxG;
+  constexpr int NW2 = h1 * h2, NSH = NW2 + h2 + G + (W1SLOT ? 0 : 5 * h1);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int q = tid; q < NSH; q += nt) {
+    T sum = 0;
+    if (q < NW2) {
+      const int j = q / h2, kk = q % h2;
+      for (int k = 0; k < np; ++k) sum += et[k * ET + kk] * feat[k * EFEAT + 24 + j];
+      accW2[q] += sum;
+    } else if (q < NW2 + h2) {
+      const int kk = q - NW2;
+      for (int k = 0; k < np; ++k) sum += et[k * ET + kk];
+      accb2[kk] += sum;
+    } else if (q < NW2 + h2 + G) {
+      const int g = q - NW2 - h2;
+      for (int k = 0; k < np; ++k) sum += et[k * ET + h2 + h1 + g];
+      accsig[g] += sum;
+    } else {
+      const int q3 = q - NW2 - h2 - G;
+      if (q3 < 4 * h1) {
+        const int i = q3 / h1, j = q3 % h1;
+        for (int k = 0; k < np; ++k) sum += et[k * ET + h2 + j] * feat[k * EFEAT + i];
+        accW1[q3] += sum;
+      } else {
+        const int j = q3 - 4 * h1;
+        for (int k = 0; k < np; ++k) sum += et[k * ET + h2 + j];
+        accb1[j] += sum;
+      }
     }
-    T s, s1, s2;
-    silu3(f[8 + j], s, s1, s2);
-    const T p1 = z1b * s1;
-    atomicAdd(&accb1[j], p1);
-    for (int i = 0; i < 4; ++i) atomicAdd(&accW1[i * D.h1 + j], p1 * f[i]);
+  }
+  if constexpr (W1SLOT) {
+    for (int q = tid; q < np * 5 * h1; q += nt) {
+      const int k = q / (5 * h1), r5 = q % (5 * h1);
+      if (r5 < 4 * h1) {
+        const int i = r5 / h1, j = r5 % h1;
+        accW1[k * 4 * h1 + r5] += et[k * ET + h2 + j] * feat[k * EFEAT + i];
+      } else {
+        const int j = r5 - 4 * h1;
+        accb1[k * h1 + j] += et[k * ET + h2 + j];
+      }
+    }
   }
 }
 
@@ -335,6 +389,7 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
   const FiltOff fo = filt_off(D);
   __shared__ T feat[ECH * EFEAT];
   __shared__ T red[ECH * 40];
+  __shared__ T eterm[ECH * ET];
   __shared__ int jn[ECH];
   extern __shared__ char dyn[];
   // LDS accumulators of the scalar filter parameters, per alpha:
@@ -387,7 +442,9 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
         }
         for (int q = tid; q < jc * 40; q += nt) red[q] = T(0);
         __syncthreads();
-        auto pair_grads = [&](int k, T& u1, T& u2) {
+        // pj: the neighbour's projection b_j of this channel (read ahead)
+        auto proj_j = [&](int k) { return ((const T*)(rec + S.proj))[((int64_t)jn[k] * 4 + 2 + a) * d + c]; };
+        auto pair_grads = [&](int k, T pj, T& u1, T& u2) {
           const T* f = feat + k * EFEAT;
           u1 = 0;
           u2 = 0;
@@ -397,8 +454,7 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
             for (int q = 0; q < D.G; ++q) g2 += f[88] * f[56 + q] * wenv[q];
             const T gam = g1 * g2;
             const int j = jn[k];
-            const T pre = ai + ((const T*)(rec + S.proj))[((int64_t)j * 4 + 2 + a) * d + c] + f[4] * we[0] +
-                          f[5] * we[1] + f[6] * we[2] + f[7] * we[3] + bb;
+            const T pre = ai + pj + f[4] * we[0] + f[5] * we[1] + f[6] * we[2] + f[7] * we[3] + bb;
             T sf, s1, s2;
             silu3(pre, sf, s1, s2);
             const T gb = mb * sf, pb = mb * gam * s1;
@@ -416,9 +472,11 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
         if constexpr (sizeof(T) == 4) {
           for (int k0 = 0; k0 < jc; k0 += RCH) {
             const int kc = jc - k0 < RCH ? jc - k0 : RCH;
+            T pjv[RCH];
+            for (int kk = 0; kk < RCH; ++kk) pjv[kk] = act ? proj_j(kk < kc ? k0 + kk : k0) : T(0);
             for (int kk = 0; kk < RCH; ++kk) {
               T u1 = 0, u2 = 0;
-              if (kk < kc) pair_grads(k0 + kk, u1, u2);
+              if (kk < kc) pair_grads(k0 + kk, pjv[kk], u1, u2);
               *chan_slot(red_us, kk, 0) = (float)u1;
               *chan_slot(red_us, kk, 1) = (float)u2;
             }
@@ -428,7 +486,7 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
         } else {
           for (int k = 0; k < jc; ++k) {
             T u1, u2;
-            pair_grads(k, u1, u2);
+            pair_grads(k, act ? proj_j(k) : T(0), u1, u2);
             for (int q = 0; q < D.h2; ++q) {
               T v = wave_sum(act ? u1 * w3[q] : T(0));
               if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
@@ -440,14 +498,14 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
           }
         }
         __syncthreads();
-        if (tid < jc && feat[tid * EFEAT + 88] != T(0)) {
-          const T* f = feat + tid * EFEAT;
-          T chib[kMaxG];
-          for (int q = 0; q < D.G; ++q) chib[q] = red[tid * 40 + 8 + q];
-          // chi = f_cut * exp(-sigma^2 r^2): only the exponents are parameters
+        // chi = f_cut * exp(-sigma^2 r^2): only the exponents are parameters
+        if (tid < jc)
+          edge_backward_terms<T>(feat + tid * EFEAT, red + tid * 40, red + tid * 40 + 8, P.ee_W2 + a * D.h1 * D.h2,
+                                 P.ee_sig + a * D.G, eterm + tid * ET);
+        __syncthreads();
+        {
           T* A = acc + a * astr;
-          edge_backward<T>(f, red + tid * 40, chib, P.ee_W2 + a * D.h1 * D.h2, P.ee_sig + a * D.G, D, A + fo.W1,
-                           A + fo.b1, A + fo.W2, A + fo.b2, A + fo.W3);
+          edge_param_sums<T, false>(feat, eterm, jc, A + fo.W1, A + fo.b1, A + fo.W2, A + fo.b2, A + fo.W3);
         }
       }
     }
@@ -560,6 +618,8 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
   const int mc = D.M - m0 < ENCH ? D.M - m0 : ENCH;
   __shared__ T feat[ENCH * EFEAT];
   __shared__ T red[ENCH * 40];
+  __shared__ T eterm[ENCH * ET];
+  __shared__ int ntk[ENCH];
   extern __shared__ char dyn[];
   T* nucb = (T*)dyn;                       // [ENCH][d]
   T* sW1 = nucb + ENCH * D.d;              // [ENCH][4 h1]
@@ -581,6 +641,11 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
     for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
     for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
   }
+  // nucleus types of this block column, and the embeddings of the first
+  // four types of this channel in registers
+  if (tid < mc) ntk[tid] = P.ntype[m0 + tid];
+  T nemb[4];
+  for (int t = 0; t < 4; ++t) nemb[t] = (act && t < D.NT) ? P.nuc_emb[t * D.d + c] : T(0);
   // FP32: B operands and LDS of the MFMA channel reductions
   __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
   __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
@@ -607,7 +672,10 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
         for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
         for (int q = 0; q < D.G; ++q) g2 += f[88] * f[56 + q] * wenv[q];
         const T gam = g1 * g2;
-        const T v = P.nuc_emb[P.ntype[m0 + k] * D.d + c] + f[4] * wn[0] + f[5] * wn[1] + f[6] * wn[2] + f[7] * wn[3];
+        const int tk = ntk[k];
+        const T ne = tk == 0 ? nemb[0] : tk == 1 ? nemb[1] : tk == 2 ? nemb[2] : tk == 3 ? nemb[3]
+                                                                               : P.nuc_emb[tk * D.d + c];
+        const T v = ne + f[4] * wn[0] + f[5] * wn[1] + f[6] * wn[2] + f[7] * wn[3];
         const T gb = sb * v, vb = sb * gam;
         nucb[k * D.d + c] += vb;
         for (int q = 0; q < 4; ++q) aWn[q] += vb * f[4 + q];
@@ -644,13 +712,11 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
       }
     }
     __syncthreads();
-    if (tid < mc && feat[tid * EFEAT + 88] != T(0)) {
-      const T* f = feat + tid * EFEAT;
-      T chib[kMaxG];
-      for (int q = 0; q < D.G; ++q) chib[q] = red[tid * 40 + 8 + q];
-      edge_backward<T>(f, red + tid * 40, chib, P.en_W2, P.en_sig, D, sW1 + tid * 4 * D.h1, sb1 + tid * D.h1, sW2,
-                       sb2, ssig);
-    }
+    if (tid < mc)
+      edge_backward_terms<T>(feat + tid * EFEAT, red + tid * 40, red + tid * 40 + 8, P.en_W2, P.en_sig,
+                             eterm + tid * ET);
+    __syncthreads();
+    edge_param_sums<T, true>(feat, eterm, mc, sW1, sb1, sW2, sb2, ssig);
   }
   __syncthreads();
   T* out = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * eo.size;
