@@ -367,6 +367,14 @@ template <typename T> struct DPhiRows {
     const T en = u == e ? envnew[(int64_t)j * KN + det * N + l] : envc[(int64_t)iloc * N + l];
     return (double)(oseg[q] * en - phic[(int64_t)iloc * N + l]);
   }
+  // every row start of this item is aligned for reads of two consecutive
+  // elements (N even and all block bases aligned)
+  template <typename TI> FIRE_DEV bool pair_aligned(const TI* G) const {
+    const uintptr_t m = 2 * sizeof(T) - 1, mg = 2 * sizeof(TI) - 1;
+    if ((N & 1) != 0 || ((uintptr_t)G & mg) != 0) return false;
+    if (dphi) return ((uintptr_t)dphi & m) == 0;
+    return (((uintptr_t)oseg | (uintptr_t)envnew | (uintptr_t)envc | (uintptr_t)phic) & m) == 0;
+  }
   // base pointers of row a (electron u) for branch-free element reads:
   // x (dPhi, or o' when fused), y (envelope) and z (Phi)
   FIRE_DEV void row_ptrs(int a, int u, const T*& x, const T*& y, const T*& z) const {
@@ -578,7 +586,10 @@ FIRE_DEV void group_lu_det16(double (&row)[16], int kk, double& sgn, double& log
 // are zero).  Every element read is unconditional (rows past k read row 0,
 // columns past N read column N-1, and both are zeroed afterwards), so the
 // reads of 8 MFMA steps (32 orbital columns) are all in flight together.
-template <typename T, typename TI, int KT, bool FUSED>
+template <typename X> struct alignas(2 * sizeof(X)) Two {
+  X a, b;
+};
+template <typename T, typename TI, int KT, bool FUSED, bool PAIR>
 FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, int N, int e0, double* ab, int ld) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
   const T* xr[KT];
@@ -603,20 +614,51 @@ FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, 
   constexpr int CH = 8;
   for (int cb = 0; cb < N; cb += 4 * CH) {
     double af[CH][KT], bf[CH][KT];
+    if constexpr (PAIR) {
+      // steps 2v and 2v + 1 of lane group kq take columns cb + 8 v + 2 kq
+      // and the one after it (N even, pairs aligned): one read per pair
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int col = cb + 4 * u + kq;
-      const bool cok = col < N;
-      const int cc = cok ? col : N - 1;
+      for (int v = 0; v < CH / 2; ++v) {
+        const int col = cb + 8 * v + 2 * kq;
+        const bool cok = col < N;
+        const int cc = cok ? col : N - 2;
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const bool ok = rok[t] && cok;
-        double v;
-        if constexpr (FUSED) v = (double)(xr[t][cc] * yr[t][cc] - zr[t][cc]);
-        else v = (double)xr[t][cc];
-        const double g = (double)gr[t][cc];
-        af[u][t] = ok ? v : 0.0;
-        bf[u][t] = ok ? g : 0.0;
+        for (int t = 0; t < KT; ++t) {
+          const bool ok = rok[t] && cok;
+          const Two<T> x = *reinterpret_cast<const Two<T>*>(xr[t] + cc);
+          double v0, v1;
+          if constexpr (FUSED) {
+            const Two<T> y = *reinterpret_cast<const Two<T>*>(yr[t] + cc);
+            const Two<T> z = *reinterpret_cast<const Two<T>*>(zr[t] + cc);
+            v0 = (double)(x.a * y.a - z.a);
+            v1 = (double)(x.b * y.b - z.b);
+          } else {
+            v0 = (double)x.a;
+            v1 = (double)x.b;
+          }
+          const Two<TI> g = *reinterpret_cast<const Two<TI>*>(gr[t] + cc);
+          af[2 * v][t] = ok ? v0 : 0.0;
+          af[2 * v + 1][t] = ok ? v1 : 0.0;
+          bf[2 * v][t] = ok ? (double)g.a : 0.0;
+          bf[2 * v + 1][t] = ok ? (double)g.b : 0.0;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int col = cb + 4 * u + kq;
+        const bool cok = col < N;
+        const int cc = cok ? col : N - 1;
+#pragma unroll
+        for (int t = 0; t < KT; ++t) {
+          const bool ok = rok[t] && cok;
+          double v;
+          if constexpr (FUSED) v = (double)(xr[t][cc] * yr[t][cc] - zr[t][cc]);
+          else v = (double)xr[t][cc];
+          const double g = (double)gr[t][cc];
+          af[u][t] = ok ? v : 0.0;
+          bf[u][t] = ok ? g : 0.0;
+        }
       }
     }
     // steps past N multiply zeros; no early exit, so no read is held back
@@ -717,8 +759,14 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
       DPhiRows<T> dr;
       const int* lst;
       item_rows(q, G, dr, lst);
-      if (fused) form_A<T, TI, 1, true>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
-      else form_A<T, TI, 1, false>(dr, G, lst, k, N, e0, ab + q * 16 * 17, 17);
+      double* aq = ab + q * 16 * 17;
+      if (dr.pair_aligned(G)) {
+        if (fused) form_A<T, TI, 1, true, true>(dr, G, lst, k, N, e0, aq, 17);
+        else form_A<T, TI, 1, false, true>(dr, G, lst, k, N, e0, aq, 17);
+      } else {
+        if (fused) form_A<T, TI, 1, true, false>(dr, G, lst, k, N, e0, aq, 17);
+        else form_A<T, TI, 1, false, false>(dr, G, lst, k, N, e0, aq, 17);
+      }
     }
   }
   const int gq = lane >> 4, r = lane & 15;
@@ -746,7 +794,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
 // det A for items with 16 < |U_s| <= 32, one per wave: 32 x 32 product on
 // MFMA tiles, then wave_lu_det.  Other items exit at once.
 template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
+__global__ __launch_bounds__(256, 3) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                   const int* __restrict__ uidx, int capmax,
                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
@@ -776,8 +824,13 @@ __global__ __launch_bounds__(256) void k_detA_mid(const Dims D, int W, const int
   const DPhiRows<T> dr{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
                        (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
   double* ab = abuf[wave];
-  if (fused) form_A<T, TI, 2, true>(dr, G, lst, k, N, e0, ab, 33);
-  else form_A<T, TI, 2, false>(dr, G, lst, k, N, e0, ab, 33);
+  if (dr.pair_aligned(G)) {
+    if (fused) form_A<T, TI, 2, true, true>(dr, G, lst, k, N, e0, ab, 33);
+    else form_A<T, TI, 2, false, true>(dr, G, lst, k, N, e0, ab, 33);
+  } else {
+    if (fused) form_A<T, TI, 2, true, false>(dr, G, lst, k, N, e0, ab, 33);
+    else form_A<T, TI, 2, false, false>(dr, G, lst, k, N, e0, ab, 33);
+  }
   double row[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;

@@ -87,6 +87,36 @@ def test_polyene_ecp_fp64(lib):
     assert np.abs(parts[:, 4] - vo).max() <= 1e-9
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 5e-4)])
+def test_flake_ecp_even_orbital_blocks(lib, precision, tol):
+    """C4H4 flake, 20 electrons (10 + 10): even orbital blocks take the
+    paired-column reads of the determinant-lemma product, for the fused
+    o' env - Phi rows of the quadrature jobs.  Errors relative to
+    max(1, |V_NL|).  FP32 bound: FP32 orbital rows (rounding 6e-8) enter the
+    ratios amplified by the conditioning of random-init orbital matrices;
+    this geometry measures 6e-5, and 5e-4 leaves an 8x margin."""
+    log(f"case: C4H4 flake nonlocal ECP {precision} W=3 (N = 10 per spin)")
+    rng = np.random.default_rng(21)
+    R, sp = wl.grown_flake(20)
+    s = wl.make_system("C4H4", R, sp, pseudo_c=True, nonlocal_ecp=True, ecp_rng=rng)
+    m = wl.make_model(s, width=32, mlp_layers=2, n_det=2, n_env=2, cutoff=5.0, cutoff_nuc=20.0)
+    p = wl.init_params(s, m, rng)
+    Rw = wl.init_walkers(s, 3, rng)
+    assert s.n_up % 2 == 0 and s.n_dn % 2 == 0
+    F, O, state, ws = setup_custom(s, m, p, Rw, precision)
+    Q = wl.haar_rotations(3, np.random.default_rng(8))
+    Rd = dev(Rw)
+    F.eval_logpsi(Rd, state, ws)
+    v, st = F.ecp_nonlocal(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    vo = O.ecp_nonlocal(Rw, Q).numpy()
+    v = v.cpu().numpy()
+    err = (np.abs(v - vo) / np.maximum(1.0, np.abs(vo))).max()
+    log(f"V_NL gpu {v} oracle {vo} rel err {err:.2e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert err <= tol
+
+
 def test_polyene_fp32_local_energy_vs_gpu_fp64(lib):
     log("case: C12H14 full width fp32 vs fp64 E_L W=16")
     F32, O, s, m, p, R, st32, ws32 = setup(1, 16, "fp32")
