@@ -929,10 +929,27 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
   TI* G = (TI*)(rec + S.inv) + det * phi_per_det(D) + phi_block_off(D, s);
   T* phi = (T*)(rec + S.phi) + det * phi_per_det(D) + phi_block_off(D, s);
   const T* dp = dphi + (int64_t)q0 * KN + det * N;
-  for (int q = tid; q < k * N; q += nt) {
-    const int a = q / N, l = q - a * N;
-    P[q] = dp[(int64_t)a * KN + l];
-    GU[q] = (double)G[(int64_t)(lst[a] - e0) * N + l];
+  // staging reads four elements per thread at a time, all issued before the
+  // LDS writes (indices clamped into the k x N block, writes guarded)
+  const int kN = k * N;
+  for (int qs = tid; qs < kN; qs += 4 * nt) {
+    T pv[4];
+    TI gv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = qs + j * nt < kN ? qs + j * nt : kN - 1;
+      const int a = q / N, l = q - a * N;
+      pv[j] = dp[(int64_t)a * KN + l];
+      gv[j] = G[(int64_t)(lst[a] - e0) * N + l];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = qs + j * nt;
+      if (q < kN) {
+        P[q] = pv[j];
+        GU[q] = (double)gv[j];
+      }
+    }
   }
   __syncthreads();
   {
@@ -1083,10 +1100,24 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     __syncthreads();
     if (fl[1]) return;
   }
-  // commit the new Phi rows of this determinant and spin block
-  for (int q = tid; q < k * N; q += nt) {
-    const int a = q / N, l = q - a * N;
-    phi[(int64_t)(lst[a] - e0) * N + l] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
+  // commit the new Phi rows of this determinant and spin block (reads of
+  // four elements per thread issued together)
+  for (int qa = tid; qa < kN; qa += 4 * nt) {
+    T ov[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = qa + j * nt < kN ? qa + j * nt : kN - 1;
+      const int a = q / N, l = q - a * N;
+      ov[j] = oseg[(int64_t)(q0 + a) * KN + det * N + l];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = qa + j * nt;
+      if (q < kN) {
+        const int a = q / N, l = q - a * N;
+        phi[(int64_t)(lst[a] - e0) * N + l] = ov[j];
+      }
+    }
   }
   __syncthreads();
   // G -= Z B in 16-row blocks, one wave per block of rows, on 16x16x4 f64
