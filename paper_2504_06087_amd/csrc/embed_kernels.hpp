@@ -103,72 +103,119 @@ constexpr int FEAT = 48;
 
 // ---------------------------------------------------------------------------
 // a2 + a3 (first half): s_i = sum_m Gamma_m(e_im) * (nuc_emb_m + ebar_im W_n),
-// then y_i = LayerNorm(s_i).  Workgroup: one thread per channel, EPB electrons.
+// then y_i = LayerNorm(s_i).  Workgroup: one thread per channel, epb
+// electrons, ERB of them at a time: the pair features of ERB electrons x up
+// to MCH nuclei are formed together (one thread per pair), then every
+// channel sums the ERB rows.
 // ---------------------------------------------------------------------------
 constexpr int EPB = 8;
 constexpr int MCH = 64;
 
+// per-value sums over the workgroup (wave sums, then the waves in order)
+template <typename T, int NR> FIRE_DEV void block_sums(T (&v)[NR], T* red) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) v[r] = wave_sum(v[r]);
+  __syncthreads();
+  if (l == 0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[w * NR + r] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    T t = 0;
+    for (int k = 0; k < nw; ++k) t += red[k * NR + r];
+    v[r] = t;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __restrict__ R, int64_t nrows,
                                                   T* __restrict__ y_out, int epb) {
+  constexpr int ERB = sizeof(T) == 4 ? 4 : 2;   // electrons per pass (LDS: ERB x MCH pair features)
   const Dims& D = P.D;
-  __shared__ T feat[MCH * FEAT];
+  __shared__ T feat[ERB * MCH * FEAT];
   __shared__ int ntp[MCH];
-  __shared__ T red[16];
-  const int c = threadIdx.x;
+  __shared__ T red[4 * ERB];
+  const int c = threadIdx.x, nt = blockDim.x;
   const bool act = c < D.d;
-  T w3[kMaxH2], wenv[kMaxG], wn[4];
+  T w3[kMaxH2], wenv[kMaxG], wn[4], nemb[4];
   if (act) {
     for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
     for (int k = 0; k < D.G; ++k) wenv[k] = P.en_Wenv[k * D.d + c];
     for (int k = 0; k < 4; ++k) wn[k] = P.en_Wn[k * D.d + c];
   }
-  for (int el = 0; el < epb; ++el) {
-    int64_t e = (int64_t)blockIdx.x * epb + el;
-    if (e >= nrows) break;
-    const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
-    T s = 0;
+  // embeddings of the first four nucleus types of this channel
+  for (int t = 0; t < 4; ++t) nemb[t] = (act && t < D.NT) ? P.nuc_emb[t * D.d + c] : T(0);
+  const int64_t e_beg = (int64_t)blockIdx.x * epb;
+  const int64_t e_end = e_beg + epb < nrows ? e_beg + epb : nrows;
+  // electrons per pass: one pair per thread (the block has >= MCH threads)
+  const int mmax = D.M < MCH ? D.M : MCH;
+  const int rpp = nt / mmax < ERB ? (nt / mmax > 0 ? nt / mmax : 1) : ERB;
+  for (int64_t eb = e_beg; eb < e_end; eb += rpp) {
+    const int nr = e_end - eb < rpp ? (int)(e_end - eb) : rpp;
+    T s[ERB];
+#pragma unroll
+    for (int r = 0; r < ERB; ++r) s[r] = 0;
     for (int m0 = 0; m0 < D.M; m0 += MCH) {
-      int mc = D.M - m0 < MCH ? D.M - m0 : MCH;
+      const int mc = D.M - m0 < MCH ? D.M - m0 : MCH;
       __syncthreads();
-      if (threadIdx.x < mc) {
-        int m = m0 + threadIdx.x, t = P.ntype[m];
-        ntp[threadIdx.x] = t;
-        pair_features<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
-                         P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig,
-                         (T)D.cutn, D, feat + threadIdx.x * FEAT);
+      if (threadIdx.x < nr * mc) {
+        const int q = threadIdx.x, r = q / mc, k = q - r * mc;
+        const int64_t e = eb + r;
+        const int m = m0 + k, t = P.ntype[m];
+        if (r == 0) ntp[k] = t;
+        // the filter weights are re-read in every pass instead of being
+        // held in registers across the pass loop (an empty asm hides their
+        // loop invariance)
+        const T* W2p = P.en_W2;
+        const T* b2p = P.en_b2;
+        const T* sgp = P.en_sig;
+        asm volatile("" : "+s"(W2p), "+s"(b2p), "+s"(sgp));
+        pair_features<T>((T)(R[3 * e] - P.Rn[3 * m]), (T)(R[3 * e + 1] - P.Rn[3 * m + 1]),
+                         (T)(R[3 * e + 2] - P.Rn[3 * m + 2]), P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1,
+                         W2p, b2p, sgp, (T)D.cutn, D, feat + (r * MCH + k) * FEAT);
       }
       __syncthreads();
       if (act) {
-        // nuclear embeddings of 16 nuclei are loaded together
-        constexpr int NG = 16;
-        for (int k0 = 0; k0 < mc; k0 += NG) {
-          T ne[NG];
 #pragma unroll
-          for (int u = 0; u < NG; ++u) ne[u] = k0 + u < mc ? P.nuc_emb[ntp[k0 + u] * D.d + c] : T(0);
+        for (int r = 0; r < ERB; ++r) {
+          if (r < nr) {
+#pragma unroll 1
+            for (int k = 0; k < mc; ++k) {
+              const T* f = feat + (r * MCH + k) * FEAT;
+              if (f[44] == T(0)) continue;
+              const int tk = ntp[k];
+              const T ne = tk == 0 ? nemb[0] : tk == 1 ? nemb[1] : tk == 2 ? nemb[2] : tk == 3 ? nemb[3]
+                                                                                     : P.nuc_emb[tk * D.d + c];
+              T g1 = 0, g2 = 0;
 #pragma unroll
-          for (int u = 0; u < NG; ++u) {
-            const int k = k0 + u;
-            if (k >= mc) break;
-            const T* f = feat + k * FEAT;
-            if (f[44] == T(0)) continue;
-            T g1 = 0, g2 = 0;
+              for (int j = 0; j < kMaxH2; ++j) g1 += f[4 + j] * w3[j];
 #pragma unroll
-            for (int j = 0; j < kMaxH2; ++j)
-              if (j < D.h2) g1 += f[4 + j] * w3[j];
-#pragma unroll
-            for (int j = 0; j < kMaxG; ++j)
-              if (j < D.G) g2 += f[12 + j] * wenv[j];
-            T v = ne[u] + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
-            s += g1 * g2 * v;
+              for (int j = 0; j < kMaxG; ++j) g2 += f[12 + j] * wenv[j];
+              T v = ne + f[0] * wn[0] + f[1] * wn[1] + f[2] * wn[2] + f[3] * wn[3];
+              s[r] += g1 * g2 * v;
+            }
           }
         }
       }
     }
-    T mu = block_sum<T>(act ? s : T(0), red) / T(D.d);
-    T dv = act ? s - mu : T(0);
-    T var = block_sum<T>(dv * dv, red) / T(D.d);
-    if (act) y_out[e * D.d + c] = dv / sqrt(var + T(kLnEps)) * P.ln_g[c] + P.ln_b[c];
+    T mu[ERB], dv[ERB], var[ERB];
+#pragma unroll
+    for (int r = 0; r < ERB; ++r) mu[r] = act ? s[r] : T(0);
+    block_sums<T, ERB>(mu, red);
+#pragma unroll
+    for (int r = 0; r < ERB; ++r) {
+      mu[r] = mu[r] / T(D.d);
+      dv[r] = act ? s[r] - mu[r] : T(0);
+      var[r] = dv[r] * dv[r];
+    }
+    block_sums<T, ERB>(var, red);
+    if (act)
+#pragma unroll
+      for (int r = 0; r < ERB; ++r)
+        if (r < nr)
+          y_out[(eb + r) * D.d + c] = dv[r] / sqrt(var[r] / T(D.d) + T(kLnEps)) * P.ln_g[c] + P.ln_b[c];
   }
 }
 

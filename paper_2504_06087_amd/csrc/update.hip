@@ -1402,7 +1402,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
                      status);
   CHECK(hipGetLastError());
   // h0 and projections of the moved electron
-  const int epb = W >= 32768 ? 4 : 1;
+  const int epb = W >= 16384 ? 4 : (W >= 4096 ? 2 : 1);
   hipLaunchKernelGGL(k_en_embed<T>, dim3((W + epb - 1) / epb), dim3(blk), 0, st, P, (const double*)rnew,
                      (int64_t)W, y, epb);
   CHECK(hipGetLastError());
