@@ -120,6 +120,11 @@ FIRE_HOST_DEVICE float bf2f(bf16_t b) {
 // ---------------------------------------------------------------------------
 // Block reductions (blockDim.x a multiple of 64, <= 1024)
 // ---------------------------------------------------------------------------
+// two consecutive elements, read or written as one aligned access
+template <typename X> struct alignas(2 * sizeof(X)) Two {
+  X a, b;
+};
+
 template <typename T> FIRE_DEV T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

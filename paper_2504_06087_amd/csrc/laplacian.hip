@@ -469,6 +469,8 @@ __global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, c
       lapt += v;
     }
     const int KT = (t + 15) / 16;
+    const bool pair = (N & 1) == 0 && ((uintptr_t)dphi & (2 * sizeof(T) - 1)) == 0 &&
+                      ((uintptr_t)G & (2 * sizeof(TI) - 1)) == 0;
     for (int x = 0; x < 3; ++x) {
       for (int tx = 0; tx < KT; ++tx) {
         // row of this lane in tile tx: G row and jet row of member a
@@ -484,21 +486,52 @@ __global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, c
           const int64_t rb = okb ? ((int64_t)joff[(int64_t)wl * n + ub] + 3 * slt[b] + x) * KN + det * N : 0;
           const TI* gb = G + (int64_t)(ub - e0) * N;
           d4v_ m1 = {0.0, 0.0, 0.0, 0.0}, m2 = {0.0, 0.0, 0.0, 0.0};
+          // unconditional reads (rows past t read member row 0 of the
+          // segment and G row e0, columns past N read column N-1; values
+          // zeroed after), every MFMA step runs: the reads of a 32-column
+          // chunk are all in flight together
           constexpr int CH = 8;
           for (int cb = 0; cb < N; cb += 4 * CH) {
             double dx[CH], gyv[CH], gxv[CH], dyv[CH];
+            if (pair) {
+              // steps 2v, 2v + 1 of lane group kq: columns cb + 8 v + 2 kq and
+              // the next one (N even, rows aligned), one read per pair; the
+              // K order is permuted alike in all four operands
 #pragma unroll
-            for (int u = 0; u < CH; ++u) {
-              const int col = cb + 4 * u + kq;
-              const bool cin = col < N;
-              dx[u] = (oka && cin) ? (double)dphi[ra + col] : 0.0;
-              gxv[u] = (oka && cin) ? (double)ga[col] : 0.0;
-              gyv[u] = (okb && cin) ? (double)gb[col] : 0.0;
-              dyv[u] = (okb && cin) ? (double)dphi[rb + col] : 0.0;
+              for (int v = 0; v < CH / 2; ++v) {
+                const int col = cb + 8 * v + 2 * kq;
+                const bool cin = col < N;
+                const int cc = cin ? col : N - 2;
+                const Two<T> a0 = *reinterpret_cast<const Two<T>*>(dphi + ra + cc);
+                const Two<TI> a1 = *reinterpret_cast<const Two<TI>*>(ga + cc);
+                const Two<TI> a2 = *reinterpret_cast<const Two<TI>*>(gb + cc);
+                const Two<T> a3 = *reinterpret_cast<const Two<T>*>(dphi + rb + cc);
+                const bool ka = oka && cin, kb = okb && cin;
+                dx[2 * v] = ka ? (double)a0.a : 0.0;
+                dx[2 * v + 1] = ka ? (double)a0.b : 0.0;
+                gxv[2 * v] = ka ? (double)a1.a : 0.0;
+                gxv[2 * v + 1] = ka ? (double)a1.b : 0.0;
+                gyv[2 * v] = kb ? (double)a2.a : 0.0;
+                gyv[2 * v + 1] = kb ? (double)a2.b : 0.0;
+                dyv[2 * v] = kb ? (double)a3.a : 0.0;
+                dyv[2 * v + 1] = kb ? (double)a3.b : 0.0;
+              }
+            } else {
+#pragma unroll
+              for (int u = 0; u < CH; ++u) {
+                const int col = cb + 4 * u + kq;
+                const bool cin = col < N;
+                const int cc = cin ? col : N - 1;
+                const double v0 = (double)dphi[ra + cc], v1 = (double)ga[cc];
+                const double v2 = (double)gb[cc], v3 = (double)dphi[rb + cc];
+                dx[u] = (oka && cin) ? v0 : 0.0;
+                gxv[u] = (oka && cin) ? v1 : 0.0;
+                gyv[u] = (okb && cin) ? v2 : 0.0;
+                dyv[u] = (okb && cin) ? v3 : 0.0;
+              }
             }
 #pragma unroll
             for (int u = 0; u < CH; ++u) {
-              if (cb + 4 * u >= N) break;
               m1 = __builtin_amdgcn_mfma_f64_16x16x4f64(dx[u], gyv[u], m1, 0, 0, 0);
               m2 = __builtin_amdgcn_mfma_f64_16x16x4f64(gxv[u], dyv[u], m2, 0, 0, 0);
             }

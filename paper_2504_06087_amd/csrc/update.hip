@@ -586,9 +586,6 @@ FIRE_DEV void group_lu_det16(double (&row)[16], int kk, double& sgn, double& log
 // are zero).  Every element read is unconditional (rows past k read row 0,
 // columns past N read column N-1, and both are zeroed afterwards), so the
 // reads of 8 MFMA steps (32 orbital columns) are all in flight together.
-template <typename X> struct alignas(2 * sizeof(X)) Two {
-  X a, b;
-};
 template <typename T, typename TI, int KT, bool FUSED, bool PAIR>
 FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, int N, int e0, double* ab, int ld) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
