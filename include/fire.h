@@ -270,8 +270,12 @@ fire_status fire_graph_destroy(fire_graph* g);
  * 64x128, 64x64; one warm-up and one timed launch each, synchronising the
  * stream) and keeps the fastest; later launches of that shape use it, also
  * inside captured graphs.  Every tile shape sums K in the same order, so the
- * choice never changes results.  GEMMs that accumulate into their output
- * are not timed.  save/load write/read the choices as text. */
+ * choice never changes results.  GEMMs that accumulate into their output,
+ * and GEMMs whose live row count is a device value (the row capacity says
+ * little about the rows live at the first launch), are not timed and use
+ * 128x128.  A shape also records whether its rows are device-counted and
+ * whether its output rows are dense.  save/load write/read the choices as
+ * text, one line per shape: kind log2M N K split form variant. */
 fire_status fire_autotune(int on);
 fire_status fire_autotune_count(int* n_shapes);
 fire_status fire_autotune_clear(void);

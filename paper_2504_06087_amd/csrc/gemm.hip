@@ -643,21 +643,28 @@ GemmProfiler& gemm_profiler() {
 // 64 x 64 variant.  Every variant sums K in the same order (32-wide slices,
 // one MFMA chain per 16 x 16 sub-tile), so all produce bit-identical C.
 // While tuning is on, the first launch of each new shape (kind, log2 M, N, K,
-// split) on a stream that is not capturing times every variant on the real
+// split, form) on a stream that is not capturing times every variant on the real
 // operands and keeps the fastest; GEMMs that accumulate into C are not timed
-// (running them twice would add twice) and keep variant 0.
+// (running them twice would add twice) and keep variant 0, and so do GEMMs
+// whose live row count is a device value: their capacity (the key) says
+// little about the rows live at the first launch, and one timing taken at a
+// small live count would fix a small tile for every later launch.
 constexpr int kVariants = 4;
 static const int kTileM[kVariants] = {128, 128, 64, 64};
 static const int kTileN[kVariants] = {128, 64, 128, 64};
 
+// form: bit 0 a device row count, bit 1 the vector (dense-row) epilogue;
+// launches of one (kind, log2 M, N, K, split) that differ there behave
+// differently and keep separate choices
 struct TuneKey {
-  int kind, lgm, n, k, split;
+  int kind, lgm, n, k, split, form;
   bool operator<(const TuneKey& o) const {
     if (kind != o.kind) return kind < o.kind;
     if (lgm != o.lgm) return lgm < o.lgm;
     if (n != o.n) return n < o.n;
     if (k != o.k) return k < o.k;
-    return split < o.split;
+    if (split != o.split) return split < o.split;
+    return form < o.form;
   }
 };
 struct Tuner {
@@ -669,10 +676,12 @@ static Tuner& tuner() {
   static Tuner t;
   return t;
 }
+static bool vec_epi_ok(const GemmArgs& g);
 static TuneKey key_of(int kind, const GemmArgs& g) {
   int lg = 0;
   while ((1ll << lg) < (int64_t)g.M) ++lg;
-  return TuneKey{kind, lg, g.N, g.K, g.ksplit > 1 ? g.ksplit : 1};
+  const int form = (g.Mdev ? 1 : 0) | (vec_epi_ok(g) ? 2 : 0);
+  return TuneKey{kind, lg, g.N, g.K, g.ksplit > 1 ? g.ksplit : 1, form};
 }
 
 // C (and aux) rows dense with 16-byte aligned row starts and N % 4 == 0:
@@ -782,7 +791,7 @@ template <int KIND> static int pick_variant(const GemmArgs& g, hipStream_t s, in
     std::lock_guard<std::mutex> lk(t.mu);
     auto it = t.choice.find(key);
     if (it != t.choice.end()) return it->second;
-    if (!t.on || g.accumulate || g.prof_rows) return 0;
+    if (!t.on || g.accumulate || g.prof_rows || g.Mdev) return 0;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
@@ -844,16 +853,17 @@ void autotune_clear() {
   t.choice.clear();
 }
 
-// one line per shape: kind log2M N K split variant
+// one line per shape: kind log2M N K split form variant
 bool autotune_save(const char* path) {
   Tuner& t = tuner();
   std::lock_guard<std::mutex> lk(t.mu);
   FILE* f = fopen(path, "w");
   if (!f) return false;
-  fprintf(f, "# kind log2M N K split variant(0:128x128 1:128x64 2:64x128 3:64x64)\n");
+  fprintf(f, "# kind log2M N K split form(1: device rows, 2: vector epilogue) variant(0:128x128 1:128x64 "
+             "2:64x128 3:64x64)\n");
   for (auto& kv : t.choice)
-    fprintf(f, "%d %d %d %d %d %d\n", kv.first.kind, kv.first.lgm, kv.first.n, kv.first.k, kv.first.split,
-            kv.second);
+    fprintf(f, "%d %d %d %d %d %d %d\n", kv.first.kind, kv.first.lgm, kv.first.n, kv.first.k, kv.first.split,
+            kv.first.form, kv.second);
   return fclose(f) == 0;
 }
 
@@ -868,8 +878,8 @@ bool autotune_load(const char* path) {
     if (line[0] == '#' || line[0] == '\n') continue;
     TuneKey k{};
     int v = 0;
-    if (sscanf(line, "%d %d %d %d %d %d", &k.kind, &k.lgm, &k.n, &k.k, &k.split, &v) != 6 || v < 0 ||
-        v >= kVariants || k.kind < 0 || k.kind > 3) {
+    if (sscanf(line, "%d %d %d %d %d %d %d", &k.kind, &k.lgm, &k.n, &k.k, &k.split, &k.form, &v) != 7 || v < 0 ||
+        v >= kVariants || k.kind < 0 || k.kind > 3 || k.form < 0 || k.form > 3) {
       ok = false;
       break;
     }
