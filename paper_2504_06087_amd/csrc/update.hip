@@ -608,7 +608,7 @@ FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, 
   for (int x = 0; x < KT; ++x)
 #pragma unroll
     for (int y = 0; y < KT; ++y) acc[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
-  constexpr int CH = 8;
+  constexpr int CH = KT == 2 ? 4 : 8;     // MFMA steps per chunk of reads
   for (int cb = 0; cb < N; cb += 4 * CH) {
     double af[CH][KT], bf[CH][KT];
     if constexpr (PAIR) {
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
 // det A for items with 16 < |U_s| <= 32, one per wave: 32 x 32 product on
 // MFMA tiles, then wave_lu_det.  Other items exit at once.
 template <typename T, typename TI>
-__global__ __launch_bounds__(256, 3) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
+__global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                   const int* __restrict__ uidx, int capmax,
                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
