@@ -145,8 +145,10 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, in
                                                       int64_t cap0, int64_t cap1, const int* __restrict__ jw,
                                                       int32_t* __restrict__ status) {
   __shared__ int part[2][1024];
+  __shared__ int first_over[2];
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (W + nt - 1) / nt;
+  if (t < 2) first_over[t] = 0x7fffffff;
   const int b = t * per, e = b + per < W ? b + per : W;
   int s0 = 0, s1 = 0;
   for (int w = b; w < e; ++w) { s0 += ucnt[2 * w]; s1 += ucnt[2 * w + 1]; }
@@ -168,14 +170,23 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, in
       if (c0 + c1 > 0) atomicOr(status + (jw ? jw[w] : w), FIRE_W_UPD_OVERFLOW);
       ucnt[2 * w] = 0;
       ucnt[2 * w + 1] = 0;
+      // offsets only grow, so every later job overflows too: the rows in
+      // use end at the first dropped job's offsets
+      atomicMin(&first_over[0], a0);
+      atomicMin(&first_over[1], a1);
     }
     a0 += c0;
     a1 += c1;
   }
   __syncthreads();
+  // the row counts that later kernels read on the device (GEMM rows, dPhi
+  // rows) cover exactly the rows written: never the rows of a dropped job
   if (t < 2) {
+    int tot = off[t * (W + 1) + W];
+    if (tot > first_over[t]) tot = first_over[t];
     const int64_t cap = t == 0 ? cap0 : cap1;
-    if (off[t * (W + 1) + W] > cap) off[t * (W + 1) + W] = (int)cap;
+    if (tot > cap) tot = (int)cap;
+    off[t * (W + 1) + W] = tot;
   }
 }
 
@@ -400,7 +411,9 @@ __global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __
   extern __shared__ double lds[];
   __shared__ double sc[2];
   __shared__ int fl[2];
-  const int g = blockIdx.x / D.K, det = blockIdx.x % D.K;
+  // grid-stride over jobs, each checked once: the update sets of more than
+  // 32 rows this kernel takes are rare, so a small grid skips the rest
+  // cheaply; a job that has one gets all its determinants
   const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
   const int tid = threadIdx.x;
@@ -408,38 +421,38 @@ __global__ __launch_bounds__(256) void k_detA(const Dims D, int W, const int* __
   double* A = lds;                       // [capmax][capmax+1]
   double* f = A + capmax * (capmax + 1); // [capmax]
   int* pm = (int*)(f + capmax);
-  for (int jj = 0; jj < jg; ++jj) {
-    const int j = g * jg + jj;
-    if (j >= W) break;
-    const int w = jw ? jw[j] : j;
+  for (int j = blockIdx.x; j < W; j += gridDim.x) {
     const int k = ucnt[2 * j + s];
-    double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
-    if (k <= 32) continue;   // handled by k_detA_wave
-    const int LD = k + 1;
-    const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
-    const char* rec = state + (int64_t)w * S.stride;
-    const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
-    const TI* G = (const TI*)(rec + S.inv) + boff;
-    DPhiRows<T> dr{dphi, oseg, envnew, (const T*)(rec + S.env) + boff, (const T*)(rec + S.phi) + boff,
-                   (int64_t)off[s * (W + 1) + j], (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
-    for (int a = wave; a < k; a += nw) {
-      const int ua = lst[a];
-      const double x0 = lane < N ? dr.at(a, ua, lane) : 0.0;
-      const double x1 = lane + 64 < N ? dr.at(a, ua, lane + 64) : 0.0;
-      for (int b = 0; b < k; ++b) {
-        const TI* gb = G + (int64_t)(lst[b] - e0) * N;
-        double v = x0 * (lane < N ? (double)gb[lane] : 0.0) + x1 * (lane + 64 < N ? (double)gb[lane + 64] : 0.0);
-        v = wave_sum(v);
-        if (lane == 0) A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
+    if (k <= 32) continue;   // handled by k_detA_wave / k_detA_mid
+    const int w = jw ? jw[j] : j;
+    for (int det = 0; det < D.K; ++det) {
+      double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
+      const int LD = k + 1;
+      const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+      const char* rec = state + (int64_t)w * S.stride;
+      const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
+      const TI* G = (const TI*)(rec + S.inv) + boff;
+      DPhiRows<T> dr{dphi, oseg, envnew, (const T*)(rec + S.env) + boff, (const T*)(rec + S.phi) + boff,
+                     (int64_t)off[s * (W + 1) + j], (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
+      for (int a = wave; a < k; a += nw) {
+        const int ua = lst[a];
+        const double x0 = lane < N ? dr.at(a, ua, lane) : 0.0;
+        const double x1 = lane + 64 < N ? dr.at(a, ua, lane + 64) : 0.0;
+        for (int b = 0; b < k; ++b) {
+          const TI* gb = G + (int64_t)(lst[b] - e0) * N;
+          double v = x0 * (lane < N ? (double)gb[lane] : 0.0) + x1 * (lane + 64 < N ? (double)gb[lane + 64] : 0.0);
+          v = wave_sum(v);
+          if (lane == 0) A[a * LD + b] = v + (a == b ? 1.0 : 0.0);
+        }
       }
+      __syncthreads();
+      gj_block(A, k, LD, f, pm, sc, fl, false);
+      if (tid == 0) {
+        if (fl[1]) { out[0] = 0.0; out[1] = -INFINITY; }
+        else { out[0] = sc[0]; out[1] = sc[1]; }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    gj_block(A, k, LD, f, pm, sc, fl, false);
-    if (tid == 0) {
-      if (fl[1]) { out[0] = 0.0; out[1] = -INFINITY; }
-      else { out[0] = sc[0]; out[1] = sc[1]; }
-    }
-    __syncthreads();
   }
 }
 
@@ -1247,6 +1260,12 @@ __global__ __launch_bounds__(256) void k_woodbury_prep(const Dims D, int W, int 
 }
 
 template <typename T, typename TI>
+FIRE_DEV void woodbury_rows_item(const Dims& D, int W, int s, int rb, int det, int w, const int* __restrict__ ucnt,
+                                 const int* __restrict__ off, const int* __restrict__ acc,
+                                 const T* __restrict__ dphi, const double* __restrict__ Bbuf,
+                                 char* __restrict__ state, const StateRec& S, const int32_t* __restrict__ status,
+                                 int kmin, double* lds);
+template <typename T, typename TI>
 __global__ __launch_bounds__(256) void k_woodbury_rows(const Dims D, int W, int s, const int* __restrict__ ucnt,
                                                        const int* __restrict__ off, const int* __restrict__ acc,
                                                        const T* __restrict__ dphi, const double* __restrict__ Bbuf,
@@ -1255,9 +1274,27 @@ __global__ __launch_bounds__(256) void k_woodbury_rows(const Dims D, int W, int 
   extern __shared__ double lds[];
   const int N = D.nsig(s);
   const int nrb = (N + WB_RB - 1) / WB_RB;
-  const int rb = blockIdx.x % nrb;
-  const int det = (blockIdx.x / nrb) % D.K;
-  const int w = blockIdx.x / (nrb * D.K);
+  // grid-stride over walkers, each checked once: the large update sets
+  // this kernel takes are rare, so a small grid skips the rest cheaply;
+  // a walker that has one gets all its (determinant, row block) items
+  for (int w = blockIdx.x; w < W; w += gridDim.x) {
+    const int k = ucnt[2 * w + s];
+    if (!acc[w] || k == 0 || k < kmin || (status[w] & FIRE_W_SINGULAR)) continue;
+    for (int t = 0; t < D.K * nrb; ++t) {
+      __syncthreads();
+      woodbury_rows_item<T, TI>(D, W, s, t % nrb, t / nrb, w, ucnt, off, acc, dphi, Bbuf, state, S, status, kmin,
+                                lds);
+    }
+  }
+}
+
+template <typename T, typename TI>
+FIRE_DEV void woodbury_rows_item(const Dims& D, int W, int s, int rb, int det, int w, const int* __restrict__ ucnt,
+                                 const int* __restrict__ off, const int* __restrict__ acc,
+                                 const T* __restrict__ dphi, const double* __restrict__ Bbuf,
+                                 char* __restrict__ state, const StateRec& S, const int32_t* __restrict__ status,
+                                 int kmin, double* lds) {
+  const int N = D.nsig(s);
   const int k = ucnt[2 * w + s];
   if (!acc[w] || k == 0 || k < kmin || (status[w] & FIRE_W_SINGULAR)) return;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1505,7 +1542,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     }
     if (L.capS[s] > 32) {
       const size_t lds = detA_lds(L.capmax);
-      const unsigned nblk = (unsigned)(((W + jg - 1) / jg) * D.K);
+      const unsigned nblk = (unsigned)(W < 2048 ? W : 2048);
       const T* dp = fused ? nullptr : (const T*)(ws + L.dphi[s]);
       if (h->isize == 8) {
         CHECK(hipFuncSetAttribute((const void*)k_detA<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1582,6 +1619,7 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
     double* Bbuf = (double*)(ws + L.bbuf[s]);
     const int nrb = (N + WB_RB - 1) / WB_RB;
     const int kmin = KS + 1;
+    const unsigned wr_grid = (unsigned)(W < 2048 ? W : 2048);
     if (h->isize == 8) {
       hipLaunchKernelGGL((k_woodbury_prep<T, double>), dim3(W * D.K), dim3(256), lds, st, D, W, s,
                          (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off),
@@ -1590,7 +1628,7 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
       CHECK(hipGetLastError());
       CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)wb_rows_lds(N)));
-      hipLaunchKernelGGL((k_woodbury_rows<T, double>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
+      hipLaunchKernelGGL((k_woodbury_rows<T, double>), dim3(wr_grid), dim3(256), wb_rows_lds(N), st, D, W, s,
                          (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
                          (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status, kmin);
     } else {
@@ -1601,7 +1639,7 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
       CHECK(hipGetLastError());
       CHECK(hipFuncSetAttribute((const void*)k_woodbury_rows<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)wb_rows_lds(N)));
-      hipLaunchKernelGGL((k_woodbury_rows<T, float>), dim3(W * D.K * nrb), dim3(256), wb_rows_lds(N), st, D, W, s,
+      hipLaunchKernelGGL((k_woodbury_rows<T, float>), dim3(wr_grid), dim3(256), wb_rows_lds(N), st, D, W, s,
                          (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const int*)acc,
                          (const T*)(ws + L.dphi[s]), (const double*)Bbuf, state, S, (const int32_t*)status, kmin);
     }

@@ -103,3 +103,65 @@ def test_update_overflow_flag(lib):
     st = st.cpu().numpy()
     assert ((st & fire.W_UPD_OVERFLOW) != 0).all()
     assert np.isnan(lp.cpu().numpy()).all()
+
+
+def _flake72(scales, seed, ecp=False, cutoff=6.0):
+    """72 electrons (36 per spin), walkers contracted or stretched about the
+    centre by `scales`.  In a contracted walker every electron is within
+    c = 6 bohr of the moved one, so both spin blocks have |U_s| = 36 > 32
+    rows and take the large-set kernels (the workgroup det A, and the
+    two-kernel Woodbury update through a B buffer); the stretched walkers
+    keep the rows per job below the 32 the update segments reserve."""
+    from oracle import Oracle
+    from paper_2504_06087_amd import fire
+    rng = np.random.default_rng(seed)
+    R, sp = wl.grown_flake(72)
+    s = wl.make_system("flake72", R, sp, pseudo_c=True, nonlocal_ecp=ecp, ecp_rng=rng if ecp else None)
+    m = wl.make_model(s, width=32, mlp_layers=1, n_det=2, n_env=2, cutoff=cutoff, cutoff_nuc=20.0)
+    p = wl.init_params(s, m, rng)
+    W = len(scales)
+    Rw = wl.init_walkers(s, W, rng)
+    ctr = R.mean(axis=0)
+    for w, f in enumerate(scales):
+        Rw[w] = ctr + f * (Rw[w] - ctr)
+    F = fire.Fire(s, m, "fp64", max_walkers=W, cap_nbr=s.n_el - 1, cap_upd=s.n_el)
+    F.set_params(p)
+    state, ws = F.buffers(W)
+    return F, Oracle(s, m, p), s, Rw, state, ws, rng
+
+
+def test_large_update_sets_chain_matches_oracle(lib):
+    log("case: 72-electron flake fp64 mcmc W=4 (two contracted walkers: |U_s| = 36)")
+    F, O, s, R, state, ws, rng = _flake72([0.55, 0.55, 1.6, 1.6], 31)
+    xi, u = wl.mcmc_noise(1, s.n_el, 4, rng)
+    # the contracted walkers' first move has |U_s| > 32 in both spin blocks
+    d = np.linalg.norm(R[0] - R[0, 0], axis=1)
+    assert (d <= 6.0).sum() > 33
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    nacc, sg, lp, st = F.mcmc_sweep(Rd, state, ws, 1, 0.2, dev(xi), dev(u))
+    torch.cuda.synchronize()
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.2, xi, u)
+    log(f"accepts gpu {nacc.cpu().numpy()} oracle {no.numpy()}; |dlogpsi| {np.abs(lp.cpu().numpy() - lo.numpy()).max():.2e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(nacc.cpu().numpy(), no.numpy())
+    assert np.abs(Rd.cpu().numpy() - Ro.numpy()).max() <= 1e-12
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    dG, dP, dL = _fresh_vs_cached(F, Rd, state, ws, 4)
+    log(f"cached vs fresh after the sweep: G {dG:.1e}, Phi {dP:.1e}, log|psi| {dL:.1e}")
+    assert dG <= 1e-8 and dP <= 1e-11 and dL <= 1e-10
+
+
+def test_large_update_sets_ecp_matches_oracle(lib):
+    log("case: 72-electron flake fp64 nonlocal ECP W=2 (one contracted walker)")
+    F, O, s, R, state, ws, rng = _flake72([0.55, 1.6], 32, ecp=True)
+    Q = wl.haar_rotations(2, np.random.default_rng(8))
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    v, st = F.ecp_nonlocal(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    vo = O.ecp_nonlocal(R, Q).numpy()
+    v = v.cpu().numpy()
+    log(f"V_NL gpu {v} oracle {vo} err {np.abs(v - vo).max():.2e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.abs(v - vo).max() <= 1e-9
