@@ -32,11 +32,11 @@ template <> struct MK<MMA_F32> {
 };
 template <> struct MK<MMA_BF16> {
   using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
-  static constexpr int PAD = 8;
+  static constexpr int PAD = 16;
 };
 template <> struct MK<MMA_BF16X3> {
   using TA = float; using TB = bf16_t; using TC = float; using TL = bf16_t; using Acc = f4v;
-  static constexpr int PAD = 8;
+  static constexpr int PAD = 16;
 };
 
 // rows and columns are < 2^31: 32-bit quotients, 64-bit offsets
