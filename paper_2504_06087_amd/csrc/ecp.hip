@@ -197,9 +197,11 @@ struct EcpLayout {
 static EcpLayout ecp_layout(const fire_handle* h, int W) {
   EcpLayout L{};
   const Dims& D = h->D;
-  // jobs per chunk: about 12 jobs per electron and walker, at most 16384
+  // jobs per chunk: about 12 jobs per electron and walker, at most 32760
+  // (the update segments reserve 32 rows per job and spin; at 180 electrons
+  // and 16 determinants a chunk of 32760 jobs takes ~31 GB of workspace)
   int64_t want = (int64_t)W * 12;
-  L.Jc = (int)(want < 16380 ? (want > 264 ? want : 264) : 16380);   // a multiple of 12
+  L.Jc = (int)(want < 32760 ? (want > 264 ? want : 264) : 32760);   // a multiple of 12
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.cnt = take((size_t)D.n * W * 4);
