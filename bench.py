@@ -73,6 +73,11 @@ def parse():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the uneven 16-system batch")
     ap.add_argument("--c5-walkers", type=int, default=512)
+    ap.add_argument("--scaling", action="store_true",
+                    help="runtime-scaling sweep over cumulene chains instead of the step benchmark")
+    ap.add_argument("--scaling-carbons", type=str, default="4,8,16,24,32,44,63",
+                    help="chain lengths (carbons); 63 gives 256 electrons, 128 per spin, the largest supported")
+    ap.add_argument("--scaling-cutoff", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (HBM counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -234,6 +239,92 @@ def run_c5(split, W, steps, warmup):
     }
 
 
+def fit_exponent(n, t):
+    """eta of the least-squares power law t ~ n**eta (a line in log-log)."""
+    x, y = np.log(np.asarray(n, float)), np.log(np.asarray(t, float))
+    return float(np.polyfit(x, y, 1)[0])
+
+
+def paper_step_model(t_wf, t_upd, t_kin, n, n_sweeps=2, n_quad=4):
+    """Total time of one optimisation step composed from the measured update,
+    evaluation and kinetic times as in the paper's runtime study (Appendix,
+    runtime comparison): sampling T_wf + N_sweeps n T_upd, the pseudopotential
+    n N_quad T_upd and the spin operator n/2 T_upd, plus T_kin."""
+    return t_wf + n_sweeps * n * t_upd + t_kin + n * n_quad * t_upd + 0.5 * n * t_upd
+
+
+def run_scaling(carbons, W, split, cutoff):
+    """Runtime scaling on cumulenes H2C=(C=)kCH2 (Fig. 2a-c of the paper):
+    per chain length, the times of a full evaluation (T_wf), of one
+    single-electron update over all walkers (T_upd = sweep / n), of the
+    local energy without the nonlocal pseudopotential (T_kin = E_L call minus
+    the V_NL call), of the V_NL call, and of the gradient; fitted exponents
+    eta of T ~ n**eta."""
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    pts = []
+    for nc in carbons:
+        rng = np.random.default_rng(wl.BASE_SEED + 1000 + nc)
+        Rn, sp = wl.cumulene(nc)
+        s = wl.make_system(f"C{nc}H4", Rn, sp, pseudo_c=True, nonlocal_ecp=True, ecp_rng=rng, per_species=True)
+        m = wl.make_model(s, width=256, mlp_layers=3, n_det=16, n_env=8, cutoff=cutoff, cutoff_nuc=20.0)
+        p = wl.init_params(s, m, rng)
+        n = s.n_el
+        F = fire.Fire(s, m, "bf16", max_walkers=W, cap_nbr=48, cap_upd=64, refresh_every=50, bf16_split=split)
+        F.set_params(p)
+        state, ws = F.buffers(W)
+        R = torch.tensor(wl.init_walkers(s, W, rng), dtype=torch.float64, device="cuda")
+        Q = torch.tensor(wl.haar_rotations(W, rng), device="cuda")
+        xi, u = wl.mcmc_noise(3, n, W, rng)
+        xi, u = torch.tensor(xi, device="cuda"), torch.tensor(u, device="cuda")
+        coeff = torch.full((W,), 1.0 / W, dtype=torch.float64, device="cuda")
+        nacc = torch.zeros(W, dtype=torch.int32, device="cuda")
+        stream = torch.cuda.current_stream()
+        times = None
+        # pass 0: burn-in with the tile autotuner on; pass 1 timed
+        for it in range(2):
+            fire.autotune(it == 0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            ev[0].record(stream)
+            F.eval_logpsi(R, state, ws)
+            ev[1].record(stream)
+            F.mcmc_sweep(R, state, ws, 1, 0.2, xi[it:it + 1].contiguous(), u[it:it + 1].contiguous(), nacc)
+            ev[2].record(stream)
+            F.ecp_nonlocal(R, state, ws, Q)
+            ev[3].record(stream)
+            F.local_energy(R, state, ws, Q)
+            ev[4].record(stream)
+            F.grad_params(R, state, ws, coeff)
+            ev[5].record(stream)
+            torch.cuda.synchronize()
+            times = [ev[k].elapsed_time(ev[k + 1]) for k in range(5)]
+            print(f"# cumulene C{nc}H4 n={n} pass {it}: " + " ".join(f"{t:.1f}" for t in times) + " ms",
+                  file=sys.stderr, flush=True)
+        t_wf, t_sw, t_ecp, t_el, t_gr = times
+        t_upd = t_sw / n
+        t_kin = t_el - t_ecp
+        pts.append({"n_carbon": nc, "n_el": n, "t_wf_ms": t_wf, "t_upd_ms": t_upd, "t_sweep_ms": t_sw,
+                    "t_kin_ms": t_kin, "t_vnl_ms": t_ecp, "t_el_ms": t_el, "t_grad_ms": t_gr,
+                    "t_tot_model_ms": paper_step_model(t_wf, t_upd, t_kin, n),
+                    "t_step_measured_ms": t_wf + t_sw + t_el + t_gr})
+        del F, state, ws
+        torch.cuda.empty_cache()
+    fire.autotune(False)
+    ns = [q["n_el"] for q in pts]
+    fits = {}
+    for key in ("t_upd_ms", "t_kin_ms", "t_wf_ms", "t_tot_model_ms", "t_step_measured_ms"):
+        ts = [q[key] for q in pts]
+        fits[key] = {"all": fit_exponent(ns, ts)}
+        big = [(a, b) for a, b in zip(ns, ts) if a >= 100]
+        if len(big) >= 2:
+            fits[key]["n_el>=100"] = fit_exponent([a for a, _ in big], [b for _, b in big])
+    return {"metric": "cumulene runtime scaling (T ~ n_el^eta)", "walkers": W, "cutoff_bohr": cutoff,
+            "model": "width 256, 3 layers, 16 determinants, 8 envelopes, BF16-hybrid",
+            "points": pts, "eta": fits}
+
+
 def cpu_baseline():
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: one walker's forward pass, gradient, 12 of the 540 Hessian
@@ -282,6 +373,10 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     W = a.walkers
+    if a.scaling:
+        res = run_scaling([int(x) for x in a.scaling_carbons.split(",")], W, a.split, a.scaling_cutoff)
+        print(json.dumps(res), flush=True)
+        return
     hyb = run_precision("bf16", a.split, W, a.steps, a.warmup, not a.no_grad, profile=True)
     print(f"# hybrid: {json.dumps({k: v for k, v in hyb.items() if k != 'prof'})}", flush=True)
     print(f"# hybrid GEMM profile: {hyb['prof']}", flush=True)

@@ -6,7 +6,7 @@ assignments, initial walker positions, randomly initialised parameter arrays
 (by name and shape), pseudopotential tables, Metropolis noise and quadrature
 rotations.  Everything is deterministic given a config id and seed.
 
-The molecules of the paper (cumulenes, S22, acenes, the Fe-S complex) are not
+The molecules of the paper (S22, acenes, the Fe-S complex) are not
 available, so planar hydrocarbons of the same electron counts stand in for
 them:
 
@@ -14,6 +14,10 @@ them:
 * ``polyene`` zig-zag C12H14, 62 valence electrons
 * ``flake``   honeycomb C42H12 flake, 180 valence electrons
 * ``uneven``  16 systems (H chains and grown C/H flakes), 20..180 electrons
+
+The cumulene chains H2C=(C=)kCH2 of the runtime-scaling study are built from
+standard bond lengths and angles (``cumulene``), not from the paper's
+geometry files.
 
 Parameter names and shapes follow the ansatz of the paper's Methods section
 ("Wave function ansatz"): e-n filters and nuclear embeddings, GLU with
@@ -126,6 +130,38 @@ def polyene_c12h14(a: float = BOHR_CC, ch: float = BOHR_CH):
     R[:nC, :2] = C
     R[nC:, :2] = np.array(H)
     species = np.array([1] * nC + [0] * len(H), np.int32)
+    return R, species
+
+
+BOHR_CC_CUMULENE = 2.48   # cumulenic C=C, 1.31 angstrom
+BOHR_CH_SP2 = 2.04        # C-H on an sp2 carbon, 1.08 angstrom
+HCH_DEG = 118.0           # H-C-H angle of the terminal methylene groups
+
+
+def cumulene(n_carbon: int, a: float = BOHR_CC_CUMULENE, ch: float = BOHR_CH_SP2,
+             hch_deg: float = HCH_DEG):
+    """H2C=C=...=CH2 with n_carbon >= 2 carbons on the x axis, then 4 H.
+
+    The chain has n_carbon - 1 cumulated double bonds.  With an odd number of
+    them the two methylene groups lie in one plane (xy; ethylene,
+    butatriene), with an even number in perpendicular planes (xy and xz;
+    allene), as the alternating pi systems of the chain require.  Valence
+    electrons with a pseudo-carbon: 4 n_carbon + 4."""
+    if n_carbon < 2:
+        raise ValueError("a cumulene needs at least two carbons")
+    C = np.zeros((n_carbon, 3))
+    C[:, 0] = a * np.arange(n_carbon)
+    half = math.radians(hch_deg) / 2
+    far = C[-1]
+    planar = (n_carbon - 1) % 2 == 1
+    H = []
+    for sgn in (1.0, -1.0):
+        H.append(C[0] + ch * np.array([-math.cos(half), sgn * math.sin(half), 0.0]))
+    for sgn in (1.0, -1.0):
+        side = [0.0, sgn * math.sin(half), 0.0] if planar else [0.0, 0.0, sgn * math.sin(half)]
+        H.append(far + ch * np.array([math.cos(half), side[1], side[2]]))
+    R = np.concatenate([C, np.array(H)], axis=0)
+    species = np.array([1] * n_carbon + [0] * 4, np.int32)
     return R, species
 
 
