@@ -39,6 +39,13 @@ struct Dims {
   FIRE_HOST_DEVICE int nsig(int s) const { return s == 0 ? nu : nd; }
 };
 
+// Workgroups are dealt to the eight XCDs round-robin by index.  For a grid
+// that is a multiple of 8, logical block (b % 8) * (grid / 8) + b / 8 gives
+// each XCD one contiguous run of logical blocks, so consecutive blocks that
+// read the same rows share that XCD's L2.
+FIRE_DEV int64_t xcd_run(int64_t b, int64_t grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
+FIRE_HOST_DEVICE int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
+
 // Per-walker size in elements of Phi / Phi^-1 for all determinants.
 FIRE_HOST_DEVICE int64_t phi_per_det(const Dims& D) { return (int64_t)D.nu * D.nu + (int64_t)D.nd * D.nd; }
 FIRE_HOST_DEVICE int64_t phi_per_walker(const Dims& D) { return (int64_t)D.K * phi_per_det(D); }

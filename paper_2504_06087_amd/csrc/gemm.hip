@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 namespace fire {
@@ -79,6 +80,16 @@ template <typename TS> FIRE_DEV void load4(const TS* p, int k, int K, bool valid
   }
 }
 
+// SiLU of the GEMM epilogues.  f32: x / (1 + 2^(-x log2 e)) with the
+// hardware exp2 and reciprocal (about 1 ulp each) instead of the library exp
+// and an IEEE division, which cost as many instructions per element as the
+// whole K loop spends per element of C; every f32 tile and path uses this
+// same form, so variants stay bit-identical.  f64 keeps the library form.
+FIRE_DEV float silu_epi(float x) {
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
+}
+FIRE_DEV double silu_epi(double x) { return silu_(x); }
+
 // Epilogue: each lane holds column l16 of a 16x16 sub-tile; register e is
 // row 4*lg + e for the f32-accumulating MFMAs and row 4*e + lg for the f64 one
 // (measured lane layouts of v_mfma_f32_16x16x{4f32,32_bf16} and
@@ -126,7 +137,7 @@ FIRE_DEV void gemm_epilogue(const GemmArgs& g, const Acc (&acc)[BM / 32][BN / 32
       for (int e = 0; e < 4; ++e) {
         if (!rok[i][e]) continue;
         TC v = (TC)acc[i][j][e] + (rbias[i][e] ? bc : TC(0));
-        if (g.act == ACT_SILU) v = silu_(v);
+        if (g.act == ACT_SILU) v = silu_epi(v);
         v *= xv[i][e];
         v += ov[i][e];
         C[rco[i][e] + cco] = v;
@@ -359,7 +370,10 @@ typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 // clamped to a valid row/column and their results dropped; a K tail is
 // zero-filled by a select), and fp32 -> bf16 rounding uses the hardware
 // round-to-nearest-even conversion.  Same K order and tile layout as k_gemm.
-template <int KIND, int BM, int BN, bool VEC>
+// KF > 0 fixes K at compile time (a multiple of BK): the K loop unrolls,
+// every load of a tile addresses off one base register with immediate
+// offsets, and the K-tail selects drop out.
+template <int KIND, int BM, int BN, bool VEC, int KF = 0>
 __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
   static_assert(KIND != MMA_F64, "f64 uses k_gemm");
   using P = MK<KIND>;
@@ -385,7 +399,8 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
     if (m < g.M) g.M = m;
   }
   if (g.prof_rows && blockIdx.x == 0 && threadIdx.x == 0) *g.prof_rows = g.M;
-  const int K = g.K;
+  static_assert(KF % BK == 0, "a fixed K is a multiple of the K slice");
+  const int K = KF > 0 ? KF : g.K;
   // persistent: the grid (a multiple of 8) walks the tiles of the live rows
   // in the XCD order of tile_row/tile_col, so a workgroup stays on its XCD's
   // row tiles and the grid drains once the live rows are done
@@ -435,14 +450,14 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
 #pragma unroll
       for (int t = 0; t < CA; ++t) {
         const int kk = k0 + ak[t];
-        const bool ok = kk < K;
+        const bool ok = KF > 0 || kk < K;
         float4 v = *reinterpret_cast<const float4*>(arow[t] + (ok ? kk : 0));
         R.a[t] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int t = 0; t < CB; ++t) {
         const int kk = k0 + bk[t];
-        const bool ok = kk < K;
+        const bool ok = KF > 0 || kk < K;
         const int64_t off = (int64_t)(ok ? kk : 0) * BE;
         uint4 v = *reinterpret_cast<const uint4*>(brow[t] + off);
         R.b[t] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
@@ -549,15 +564,23 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
 
     // Pipeline: the global loads of slice k+1 are in flight while slice k is
     // multiplied out of LDS.
-    const int nk = (K + BK - 1) / BK;
     Regs R;
-    if (nk > 0) gload(R, 0);
-    for (int kt = 0; kt < nk; ++kt) {
+    auto slice = [&](int kt, int nk) {
       store(R, 0);
       __syncthreads();
       if (kt + 1 < nk) gload(R, (kt + 1) * BK);
       compute(0);
       __syncthreads();
+    };
+    if constexpr (KF > 0) {
+      constexpr int nk = KF / BK;
+      gload(R, 0);
+#pragma unroll
+      for (int kt = 0; kt < nk; ++kt) slice(kt, nk);
+    } else {
+      const int nk = (K + BK - 1) / BK;
+      if (nk > 0) gload(R, 0);
+      for (int kt = 0; kt < nk; ++kt) slice(kt, nk);
     }
     if constexpr (!VEC) {
       gemm_epilogue<KIND, BM, BN>(g, acc, row0, col0, wm, wn, lg, l16);
@@ -613,7 +636,7 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
               v.x += b.x; v.y += b.y; v.z += b.z; v.w += b.w;
             }
             if (g.act == ACT_SILU) {
-              v.x = silu_(v.x); v.y = silu_(v.y); v.z = silu_(v.z); v.w = silu_(v.w);
+              v.x = silu_epi(v.x); v.y = silu_epi(v.y); v.z = silu_epi(v.z); v.w = silu_epi(v.w);
             }
             v.x *= xv[u].x; v.y *= xv[u].y; v.z *= xv[u].z; v.w *= xv[u].w;
             v.x += ov[u].x; v.y += ov[u].y; v.z += ov[u].z; v.w += ov[u].w;
@@ -708,13 +731,13 @@ template <int KIND> static bool fast_ok(const GemmArgs& g) {
 // Workgroups of the persistent fast kernel that fit on the current device at
 // once (occupancy x compute units), rounded down to a multiple of 8; cached
 // per device.
-template <int KIND, int BM, int BN, bool VEC> static int resident_wgs() {
+template <int KIND, int BM, int BN, bool VEC, int KF> static int resident_wgs() {
   static int cached[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if (cached[dev] > 0) return cached[dev];
   int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_fast<KIND, BM, BN, VEC>, 256, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm_fast<KIND, BM, BN, VEC, KF>, 256, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
@@ -729,15 +752,27 @@ template <int KIND, int BM, int BN> static hipError_t launch_tile(const GemmArgs
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   if constexpr (KIND != MMA_F64) {
     if (fast_ok<KIND>(g)) {
-      if (vec_epi_ok(g)) {
-        const int64_t r = resident_wgs<KIND, BM, BN, true>();
-        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, true>), dim3((unsigned)(tiles < r ? tiles : r)), dim3(256), 0,
+      // K = 256 (the embedding width) is the contraction of nearly every
+      // split-bf16 launch: it takes the fixed-K kernel
+      auto go = [&](auto vec, auto kf) {
+        constexpr bool V = decltype(vec)::value;
+        constexpr int F = decltype(kf)::value;
+        const int64_t r = resident_wgs<KIND, BM, BN, V, F>();
+        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, V, F>), dim3((unsigned)(tiles < r ? tiles : r)), dim3(256), 0,
                            s, g);
-      } else {
-        const int64_t r = resident_wgs<KIND, BM, BN, false>();
-        hipLaunchKernelGGL((k_gemm_fast<KIND, BM, BN, false>), dim3((unsigned)(tiles < r ? tiles : r)), dim3(256), 0,
-                           s, g);
+      };
+      using K0 = std::integral_constant<int, 0>;
+      using K256 = std::integral_constant<int, 256>;
+      const bool vec = vec_epi_ok(g);
+      if constexpr (KIND == MMA_BF16X3) {
+        if (g.K == 256) {
+          if (vec) go(std::true_type{}, K256{});
+          else go(std::false_type{}, K256{});
+          return hipGetLastError();
+        }
       }
+      if (vec) go(std::true_type{}, K0{});
+      else go(std::false_type{}, K0{});
       return hipGetLastError();
     }
   }

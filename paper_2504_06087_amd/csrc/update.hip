@@ -709,7 +709,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
                                                    double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][4 * 16 * 17];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t quad = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t quad = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
   const int ngroups = (W + jg - 1) / jg;
   const int64_t total = (int64_t)ngroups * D.K * jg;
   if (quad * 4 >= total) return;
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const 
                                                   double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][32 * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t item = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
   const int ngroups = (W + jg - 1) / jg;
   if (item >= (int64_t)ngroups * D.K * jg) return;
   const int gq = (int)(item % jg);
@@ -962,12 +962,45 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     }
   }
   __syncthreads();
+  // Z = G_rows dPhi_U^T for the 16 rows from m0 (K = N) on f64 MFMA tiles;
+  // f64 MFMA layouts: A lane (r, q) holds A[r][q], B lane (r, q) holds
+  // B[q][r], the output register i of lane (r, q) holds C[4 i + q][r]
+  const int KT = k > 16 ? 2 : 1;
+  auto zrows = [&](int m0, d4v_& z0, d4v_& z1) {
+    const int lane = tid & 63, r16 = lane & 15, kq = lane >> 4;
+    const int mrow = m0 + r16;
+    z0 = d4v_{0.0, 0.0, 0.0, 0.0};
+    z1 = d4v_{0.0, 0.0, 0.0, 0.0};
+    for (int cb = 0; cb < N; cb += 32) {
+      double ga[8], pa0[8], pa1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int col = cb + 4 * u + kq;
+        const bool cin = col < N;
+        ga[u] = (cin && mrow < N) ? (double)G[(int64_t)mrow * N + col] : 0.0;
+        pa0[u] = (cin && r16 < k) ? (double)P[r16 * N + col] : 0.0;
+        pa1[u] = (cin && 16 + r16 < k) ? (double)P[(16 + r16) * N + col] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (cb + 4 * u >= N) break;
+        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa0[u], z0, 0, 0, 0);
+        if (KT > 1) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa1[u], z1, 0, 0, 0);
+      }
+    }
+  };
+  // Z of row chunk `wave` (waves 1..3), computed while wave 0 is busy below
+  d4v_ zp0 = {0.0, 0.0, 0.0, 0.0}, zp1 = {0.0, 0.0, 0.0, 0.0};
   {
     // wave 0 forms A on MFMA, inverts it in registers and forms B on MFMA;
-    // the other waves wait at the barrier below
+    // waves 1..3 form Z for their first row chunk, then all wait at the
+    // barrier below
     constexpr int NT = KSM / 16;          // 16-row tiles of A
     constexpr int LA = KSM + 1;           // row stride of A in LDS
-    if (tid < 64) {
+    if (tid >= 64) {
+      const int w3 = tid >> 6;
+      if (w3 * 16 < N) zrows(w3 * 16, zp0, zp1);
+    } else {
       const int lane = tid, r16 = lane & 15, kq = lane >> 4;
       // A = I + P G_U^T (rows and columns past k zero)
       d4v_ am[NT][NT];
@@ -1130,34 +1163,22 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
     }
   }
   __syncthreads();
-  // G -= Z B in 16-row blocks, one wave per block of rows, on 16x16x4 f64
-  // MFMA tiles: Z = G_rows dPhi_U^T (K = N), then each 16x16 tile of G is
-  // loaded as the accumulator and Z B subtracted (K = |U_s|).  f64 MFMA
-  // layouts: A lane (r, q) holds A[r][q], B lane (r, q) holds B[q][r], the
-  // output register i of lane (r, q) holds C[4 i + q][r].
+  // G -= Z B in 16-row chunks, one wave per chunk, on 16x16x4 f64 MFMA
+  // tiles: Z = G_rows dPhi_U^T (K = N), then each 16x16 tile of G is loaded
+  // as the accumulator and Z B subtracted (K = |U_s|).  Chunk c < 4 is wave
+  // c's (waves 1..3 already hold its Z); chunks from 4 on go to waves 1..3
+  // in turn, since wave 0 spent the precomputation on A and B.
   const int lane = tid & 63, wave = tid >> 6, r16 = lane & 15, kq = lane >> 4;
-  const int KT = k > 16 ? 2 : 1;
   double* Zs = GU + wave * (16 * 33);   // this wave's Z tile [16][16 KT]
-  for (int ch = wave; ch * 16 < N; ch += 4) {
+  const int nch = (N + 15) / 16;
+  for (int ch = wave; ch < nch; ch = ch < 4 ? (wave == 0 ? nch : wave + 3) : ch + 3) {
     const int m0 = ch * 16;
-    const int mrow = m0 + r16;
-    d4v_ z0 = {0.0, 0.0, 0.0, 0.0}, z1 = {0.0, 0.0, 0.0, 0.0};
-    for (int cb = 0; cb < N; cb += 32) {
-      double ga[8], pa0[8], pa1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int col = cb + 4 * u + kq;
-        const bool cin = col < N;
-        ga[u] = (cin && mrow < N) ? (double)G[(int64_t)mrow * N + col] : 0.0;
-        pa0[u] = (cin && r16 < k) ? (double)P[r16 * N + col] : 0.0;
-        pa1[u] = (cin && 16 + r16 < k) ? (double)P[(16 + r16) * N + col] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (cb + 4 * u >= N) break;
-        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa0[u], z0, 0, 0, 0);
-        if (KT > 1) z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u], pa1[u], z1, 0, 0, 0);
-      }
+    d4v_ z0, z1;
+    if (ch == wave && wave > 0) {
+      z0 = zp0;
+      z1 = zp1;
+    } else {
+      zrows(m0, z0, z1);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1516,25 +1537,26 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     const int jg = jb.group > 0 ? jb.group : 1;
     const int64_t items = (int64_t)((W + jg - 1) / jg) * jg * D.K;
     const int64_t quads = (items + 3) / 4;
+    // grids rounded to a multiple of 8 for the XCD-contiguous block order
     if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
                          (double*)(ws + L.detA), jg);
     else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
                          (double*)(ws + L.detA), jg);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
       if (h->isize == 8)
-        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
                            S, (double*)(ws + L.detA), jg);
       else
-        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
                            S, (double*)(ws + L.detA), jg);
