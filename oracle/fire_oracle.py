@@ -325,10 +325,34 @@ class Oracle:
     # ------------------------------------------------------------------
     # sampling and parameter gradients
     # ------------------------------------------------------------------
-    def mcmc_sweep(self, R, step, noise, unif):
-        """Systematic-scan Metropolis with Gaussian single-electron moves:
-        r'_e = r_e + step*xi; accept iff u < (psi'/psi)^2; full recompute for
-        every proposal.  noise [S][n][B][3], unif [S][n][B]."""
+    def gmm_log_density(self, r, tau):
+        """log rho_global(r) of the global single-electron jump (SI, improved
+        Monte Carlo sampling, eq. of rho_global): the charge-weighted mixture
+        rho(r) = sum_m Z_m N(r | R_m, tau^2 I) / sum_m Z_m of isotropic
+        Gaussians on the nuclei.  r [..., 3]."""
+        r = torch.as_tensor(r, dtype=DT)
+        d2 = ((r[..., None, :] - self.Rn) ** 2).sum(-1)                 # [..., M]
+        log_normal = -d2 / (2.0 * tau * tau) - 1.5 * math.log(2.0 * math.pi * tau * tau)
+        return torch.logsumexp(torch.log(self.Z) + log_normal, dim=-1) - torch.log(self.Z.sum())
+
+    def gmm_draw(self, pick, xi, tau):
+        """A draw from rho_global from explicit random numbers: component m
+        with probability Z_m / sum Z (the first m whose cumulative weight
+        exceeds the uniform pick), then R_m + tau xi.  pick [B], xi [B, 3]."""
+        pick = torch.as_tensor(pick, dtype=DT)
+        xi = torch.as_tensor(xi, dtype=DT)
+        cum = torch.cumsum(self.Z, 0) / self.Z.sum()
+        m = torch.searchsorted(cum, pick, right=True).clamp(max=self.Rn.shape[0] - 1)
+        return self.Rn[m] + tau * xi
+
+    def mcmc_sweep(self, R, step, noise, unif, kinds=None, pick=None, gstep=2.0):
+        """Systematic-scan Metropolis over the electrons with a full recompute
+        for every proposal (Methods, improved Monte Carlo sampling).  Sweep t
+        moves each electron locally, r'_e = r_e + step*xi, accepted iff
+        u < (psi'/psi)^2; with kinds[t] == 1 it instead jumps globally to a
+        draw of rho_global (gmm_draw, scale gstep), and the acceptance takes
+        the factor rho(r_e) / rho(r'_e) of the asymmetric proposal.
+        noise [S][n][B][3], unif and pick [S][n][B]."""
         R = torch.as_tensor(R, dtype=DT).clone()
         noise = torch.as_tensor(noise, dtype=DT)
         unif = torch.as_tensor(unif, dtype=DT)
@@ -336,11 +360,17 @@ class Oracle:
         s, l = self.log_psi(R)
         nacc = torch.zeros(R.shape[0], dtype=torch.long)
         for t in range(S):
+            jump = kinds is not None and int(kinds[t]) == 1
             for e in range(self.n):
                 Rp = R.clone()
-                Rp[:, e] = R[:, e] + step * noise[t, e]
+                if jump:
+                    Rp[:, e] = self.gmm_draw(pick[t, e], noise[t, e], gstep)
+                    log_q = self.gmm_log_density(R[:, e], gstep) - self.gmm_log_density(Rp[:, e], gstep)
+                else:
+                    Rp[:, e] = R[:, e] + step * noise[t, e]
+                    log_q = torch.zeros(R.shape[0], dtype=DT)
                 sp, lp = self.log_psi(Rp)
-                ratio2 = torch.exp(2.0 * (lp - l))
+                ratio2 = torch.exp(2.0 * (lp - l) + log_q)
                 acc = unif[t, e] < ratio2
                 R = torch.where(acc[:, None, None], Rp, R)
                 s = torch.where(acc, sp, s)

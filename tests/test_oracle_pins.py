@@ -494,3 +494,88 @@ def test_ecp_spherically_symmetric_wavefunction_gives_v0():
     ch0 = s.ecp[1][0]
     v0 = (ch0.a[None] * np.exp(-ch0.alpha[None] * r[:, None] ** 2)).sum(1)
     assert np.allclose(v, v0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# global single-electron jumps (SI, improved Monte Carlo sampling)
+# --------------------------------------------------------------------------
+def _gmm_oracle(name):
+    if name == "h2":
+        R, sp = wl.h_chain(2, spacing=1.4)
+        s = wl.make_system("H2", R, sp, pseudo_c=False)
+    else:
+        R, sp = wl.cumulene(2)
+        s = wl.make_system("C2H4", R, sp, pseudo_c=True)
+    m = wl.make_model(s, width=8, mlp_layers=1, n_det=1, n_env=1, cutoff=3.0, cutoff_nuc=20.0)
+    return Oracle(s, m, wl.init_params(s, m, np.random.default_rng(0))), s
+
+
+@pytest.mark.parametrize("name", ["h2", "c2h4"])
+def test_gmm_density_is_normalised(name):
+    """rho_global is a probability density: a 3D grid quadrature (spacing
+    0.25 bohr, spectrally accurate for Gaussians of width 2) integrates it
+    to 1."""
+    o, s = _gmm_oracle(name)
+    lo, hi = s.R_nuc.min(0) - 16.0, s.R_nuc.max(0) + 16.0
+    h = 0.25
+    axes = [torch.arange(lo[k], hi[k] + h / 2, h, dtype=DT) for k in range(3)]
+    tot = 0.0
+    for x in axes[0]:
+        Y, Z = torch.meshgrid(axes[1], axes[2], indexing="ij")
+        pts = torch.stack([torch.full_like(Y, float(x)), Y, Z], -1)
+        tot += float(torch.exp(o.gmm_log_density(pts, 2.0)).sum()) * h ** 3
+    assert abs(tot - 1.0) < 1e-6
+
+
+def test_gmm_density_single_nucleus_closed_form():
+    # one nucleus: rho is N(R, tau^2 I); at R it is (2 pi tau^2)^(-3/2)
+    s, m, p, _ = wl.hydrogen_atom(W=1, seed=0)
+    o = Oracle(s, m, p)
+    for tau in (0.5, 2.0, 3.0):
+        r = torch.tensor([[0.0, 0.0, 0.0], [1.0, -2.0, 0.5]], dtype=DT)
+        got = o.gmm_log_density(r, tau).numpy()
+        want = -1.5 * math.log(2 * math.pi * tau * tau) - np.array([0.0, 5.25]) / (2 * tau * tau)
+        assert np.allclose(got, want, atol=1e-14, rtol=0)
+
+
+def test_gmm_draw_component_weights():
+    """Component m is drawn with probability Z_m / sum Z: uniform picks on a
+    fine grid land on each nucleus in that proportion, and with xi = 0 the
+    draw is the nucleus itself."""
+    o, s = _gmm_oracle("c2h4")
+    K = 60000
+    pick = (torch.arange(K, dtype=DT) + 0.5) / K
+    r = o.gmm_draw(pick, torch.zeros(K, 3, dtype=DT), 2.0)
+    d = torch.cdist(r, torch.tensor(s.R_nuc, dtype=DT))
+    assert float(d.min(1).values.max()) == 0.0
+    counts = np.bincount(d.argmin(1).numpy(), minlength=len(s.Z)) / K
+    assert np.allclose(counts, s.Z / s.Z.sum(), atol=2.0 / K)
+    # xi moves the draw by tau xi
+    xi = torch.tensor([[0.3, -1.0, 2.0]], dtype=DT)
+    r1 = o.gmm_draw(torch.tensor([0.0], dtype=DT), xi, 2.0)
+    assert torch.allclose(r1[0], torch.tensor(s.R_nuc[0], dtype=DT) + 2.0 * xi[0], atol=0, rtol=0)
+
+
+def test_hydrogen_sampling_with_global_jumps():
+    """Only global jumps (an independence sampler from N(0, 4 I)) and
+    alternating local/global sweeps both sample |psi|^2 = exp(-2r)/pi:
+    <r> = 3/2.  Without the proposal factor the chain would instead sample
+    |psi|^2 rho (detailed balance of the uncorrected independence sampler),
+    whose mean radius is computed here and lies far outside the tolerance."""
+    s, m, p, R0 = wl.hydrogen_atom(W=512, seed=6)
+    o = Oracle(s, m, p)
+    r = np.linspace(0.0, 40.0, 400001)
+    wt = r ** 2 * np.exp(-2.0 * r - r ** 2 / 8.0)
+    biased = float((r * wt).sum() / wt.sum())
+    assert abs(biased - 1.5) > 0.2
+    for kinds in ([1] * 10, [0, 1] * 5):
+        rng = np.random.default_rng(12)
+        R = R0 * 0.5
+        rs = []
+        for blk in range(30):
+            xi, u = wl.mcmc_noise(10, 1, 512, rng)
+            pk = rng.uniform(size=u.shape)
+            R, _, _, _ = o.mcmc_sweep(R, 1.0, xi, u, kinds=kinds, pick=pk, gstep=2.0)
+            if blk >= 8:
+                rs.append(np.linalg.norm(R.numpy()[:, 0], axis=1).mean())
+        assert abs(np.mean(rs) - 1.5) < 0.03
