@@ -147,6 +147,23 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
             last_e = e
     prof = F.profile_end() if profile else None
     acc_rate = float((nacc - acc0).sum().item()) / (steps * W * n)
+    # one sweep of global single-electron jumps (charge-weighted Gaussian
+    # mixture over the nuclei, scale 2 bohr), after the timed steps
+    gmm = None
+    if profile:
+        rg = np.random.default_rng(17)
+        gxi = torch.tensor(rg.normal(size=(1, n, W, 3)), device="cuda")
+        gu = torch.tensor(rg.uniform(size=(1, n, W)), device="cuda")
+        gp = torch.tensor(wl.gmm_picks(1, n, W, rg), device="cuda")
+        g0 = nacc.clone()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        _, _, _, gst = F.mcmc_sweep_mixed(R, state, ws, [1], work.step, 2.0, gxi, gu, gp, nacc)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        gmm = {"ms": ev[0].elapsed_time(ev[1]), "acceptance": float((nacc - g0).sum().item()) / (W * n),
+               "walker_steps_per_s": W * n / (ev[0].elapsed_time(ev[1]) / 1e3),
+               "flagged_walkers": int((gst != 0).sum().item())}
     ph = {k: v / steps for k, v in ph.items()}
     e_np = last_e.cpu().numpy()
     out = dict(phases_ms=ph, ms_per_step=sum(ph.values()), acceptance=acc_rate, have_grad=have_grad,
@@ -156,6 +173,7 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     out["walker_steps_per_s"] = W * n / (ph["sweep"] / 1e3)
     out["walkers_per_s"] = W / (out["ms_per_step"] / 1e3)
     out["prof"] = prof
+    out["global_jump_sweep"] = gmm
     return out
 
 
@@ -423,6 +441,7 @@ def main():
         "walker_steps_per_s": hyb["walker_steps_per_s"],
         "local_energies_per_s_el_phase": hyb["local_energies_per_s"],
         "phases_ms": hyb["phases_ms"], "acceptance": hyb["acceptance"], "grad_included": hyb["have_grad"],
+        "global_jump_sweep": hyb.get("global_jump_sweep"),
         "fp32_plain": None if fp32 is None else {
             "value": fp32["walkers_per_s"], "ms_per_step": fp32["ms_per_step"], "phases_ms": fp32["phases_ms"],
             "walker_steps_per_s": fp32["walker_steps_per_s"],

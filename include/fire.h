@@ -173,6 +173,25 @@ fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void*
                             int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
                             hipStream_t stream);
 
+/* Sweeps that mix the local moves of fire_mcmc_sweep with global
+ * single-electron jumps (SI, improved Monte Carlo sampling: the
+ * charge-weighted Gaussian-mixture proposal over the nuclei and its
+ * acceptance factor).  kinds: host int32 [n_sweeps], 0 = a sweep of local
+ * moves r_e' = r_e + step*xi, 1 = a sweep of global jumps: component m is the
+ * first nucleus whose cumulative charge fraction sum_{m'<=m} Z_m'/sum Z
+ * exceeds pick[t][e][w], r_e' = R_m + global_step*xi, accepted iff
+ * u < (psi'/psi)^2 rho(r_e)/rho(r_e') with rho(r) = sum_m Z_m
+ * N(r | R_m, global_step^2 I)/sum Z (Z: the effective charges of the system
+ * description).  pick: device FP64 [S][n][W] uniforms in [0,1), may be NULL
+ * when no sweep is global; global_step > 0 then.  Every other argument,
+ * the update machinery and the refresh are those of fire_mcmc_sweep.
+ * FIRE_ERR_ARG for a kind other than 0/1 or a missing pick/scale. */
+fire_status fire_mcmc_sweep_mixed(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
+                                  double step, double global_step, const int32_t* kinds,
+                                  const double* noise, const double* unif, const double* pick,
+                                  int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
+                                  hipStream_t stream);
+
 /* Local energy E_L = -1/2 (Lap log|psi| + |grad log|psi||^2) + V_ee + V_en +
  * V_nn + V_NL (Methods, local energy and Hamiltonian) by the sparse forward
  * Laplacian (Methods, efficient Laplacian).  quad_rot [W][3][3] rotates the

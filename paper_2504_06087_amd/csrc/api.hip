@@ -371,8 +371,27 @@ fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void*
   fire_status st = check_call(h, W, R, state, ws, status);
   if (st != FIRE_OK) return st;
   if (n_sweeps < 0 || !noise || !unif || !n_accept || !(step >= 0)) return FIRE_ERR_ARG;
-  hipError_t e = mcmc_sweep_path(h, W, R, (char*)state, (char*)ws, n_sweeps, step, noise, unif, n_accept, logpsi,
-                                 sign, status, s);
+  hipError_t e = mcmc_sweep_path(h, W, R, (char*)state, (char*)ws, n_sweeps, step, 0.0, nullptr, noise, unif,
+                                 nullptr, n_accept, logpsi, sign, status, s);
+  return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+fire_status fire_mcmc_sweep_mixed(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
+                                  double step, double global_step, const int32_t* kinds, const double* noise,
+                                  const double* unif, const double* pick, int32_t* n_accept, double* logpsi,
+                                  double* sign, int32_t* status, hipStream_t s) {
+  fire_status st = check_call(h, W, R, state, ws, status);
+  if (st != FIRE_OK) return st;
+  if (n_sweeps < 0 || !noise || !unif || !n_accept || !(step >= 0) || (n_sweeps > 0 && !kinds))
+    return FIRE_ERR_ARG;
+  bool any_global = false;
+  for (int t = 0; t < n_sweeps; ++t) {
+    if (kinds[t] != 0 && kinds[t] != 1) return FIRE_ERR_ARG;
+    any_global = any_global || kinds[t] == 1;
+  }
+  if (any_global && (!pick || !(global_step > 0) || !isfinite(global_step))) return FIRE_ERR_ARG;
+  hipError_t e = mcmc_sweep_path(h, W, R, (char*)state, (char*)ws, n_sweeps, step, global_step, kinds, noise,
+                                 unif, pick, n_accept, logpsi, sign, status, s);
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 

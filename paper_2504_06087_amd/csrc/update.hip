@@ -29,6 +29,7 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
   const int64_t Wl = W;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.rnew = take(Wl * 3 * 8);
+  L.lqf = take(Wl * 8);
   L.uidx = take(Wl * 2 * L.capmax * 4);
   L.ucnt = take(Wl * 2 * 4);
   L.off = take((Wl + 1) * 2 * 4);
@@ -73,8 +74,28 @@ bool update_fits(const fire_handle* h) {
          wb_fused_lds(N, 8) <= 160 * 1024;
 }
 
+// log sum_m Z_m exp(-|r - R_m|^2 / (2 tau^2)): log rho_global(r) up to the
+// constant -log(sum Z) - 3/2 log(2 pi tau^2), which cancels in the ratio
+FIRE_DEV double gmm_log_unnorm(double x, double y, double z, const double* Rn, const double* Zn, int M,
+                               double inv2t2) {
+  double amax = -INFINITY;
+  for (int m = 0; m < M; ++m) {
+    const double dx = x - Rn[3 * m], dy = y - Rn[3 * m + 1], dz = z - Rn[3 * m + 2];
+    const double a = log(Zn[m]) - (dx * dx + dy * dy + dz * dz) * inv2t2;
+    amax = a > amax ? a : amax;
+  }
+  double sum = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const double dx = x - Rn[3 * m], dy = y - Rn[3 * m + 1], dz = z - Rn[3 * m + 2];
+    sum += exp(log(Zn[m]) - (dx * dx + dy * dy + dz * dz) * inv2t2 - amax);
+  }
+  return amax + log(sum);
+}
+
 // ---------------------------------------------------------------------------
-// propose: r_e' = r_e + step * xi and the update set, one wave per walker.
+// propose: r_e' = r_e + step * xi (local move) or a draw of the global
+// proposal rho_global (SI, improved Monte Carlo sampling), and the update
+// set, one wave per walker.
 // uidx[w][s][t]: spin-s members in ascending order, e first in its own list.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, Jobs jb, int n, int nu, int e,
@@ -94,6 +115,26 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
   double nx, ny, nz;
   if (jb.rexp) {
     nx = jb.rexp[3 * j]; ny = jb.rexp[3 * j + 1]; nz = jb.rexp[3 * j + 2];
+  } else if (jb.pick) {
+    // component: the first nucleus whose cumulative charge fraction exceeds
+    // the uniform pick; then R_m + gstep * xi
+    double tot = 0.0;
+    for (int m = 0; m < jb.M; ++m) tot += jb.Zn[m];
+    const double pk = jb.pick[j];
+    int mc = jb.M - 1;
+    double cum = 0.0;
+    for (int m = 0; m < jb.M; ++m) {
+      cum += jb.Zn[m];
+      if (cum / tot > pk) { mc = m; break; }
+    }
+    nx = jb.Rn[3 * mc] + jb.gstep * jb.xi[3 * j];
+    ny = jb.Rn[3 * mc + 1] + jb.gstep * jb.xi[3 * j + 1];
+    nz = jb.Rn[3 * mc + 2] + jb.gstep * jb.xi[3 * j + 2];
+    if (lane == 0 && jb.lqf) {
+      const double inv2t2 = 1.0 / (2.0 * jb.gstep * jb.gstep);
+      jb.lqf[j] = gmm_log_unnorm(ox, oy, oz, jb.Rn, jb.Zn, jb.M, inv2t2) -
+                  gmm_log_unnorm(nx, ny, nz, jb.Rn, jb.Zn, jb.M, inv2t2);
+    }
   } else {
     nx = ox + jb.step * jb.xi[3 * j]; ny = oy + jb.step * jb.xi[3 * j + 1]; nz = oz + jb.step * jb.xi[3 * j + 2];
   }
@@ -855,9 +896,11 @@ __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const 
 }
 
 // Acceptance: psi'/psi = sum_d s_d e^{l_d} prod_s det A_ds / sum_d s_d e^{l_d};
-// accept iff u < (psi'/psi)^2.  Updates the determinant logs and log|psi|.
+// accept iff u < (psi'/psi)^2, times rho(r_e)/rho(r_e') = e^lqf for a global
+// jump (lqf NULL for local moves).  Updates the determinant logs and log|psi|.
 __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, const double* __restrict__ rnew,
-                         const double* __restrict__ unif, char* __restrict__ state, StateRec S,
+                         const double* __restrict__ lqf, const double* __restrict__ unif,
+                         char* __restrict__ state, StateRec S,
                          const double* __restrict__ detA, int32_t* __restrict__ status, int* __restrict__ acc,
                          int32_t* __restrict__ n_accept) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -882,7 +925,7 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
   double lpn = 0.0;
   if (status[w] == 0 && tot != 0.0 && isfinite(tot) && isfinite(lmax)) {
     lpn = lmax + log(fabs(tot));
-    const double ratio2 = exp(2.0 * (lpn - lp));
+    const double ratio2 = exp(2.0 * (lpn - lp) + (lqf ? lqf[w] : 0.0));
     a = unif[w] < ratio2;
   }
   acc[w] = a;
@@ -1593,14 +1636,15 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
 }
 
 template <typename T>
-static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* R, const double* unif, char* state,
-                                    char* ws, int32_t* n_accept, int32_t* status, hipStream_t st) {
+static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* R, const double* unif, bool global,
+                                    char* state, char* ws, int32_t* n_accept, int32_t* status, hipStream_t st) {
   const Dims& D = h->D;
   const StateRec& S = h->st;
   const UpdLayout L = upd_layout(h, W);
   int* acc = (int*)(ws + L.acc);
   hipLaunchKernelGGL(k_accept, dim3((W + 127) / 128), dim3(128), 0, st, D, W, e, R, (const double*)(ws + L.rnew),
-                     unif, state, S, (const double*)(ws + L.detA), status, acc, n_accept);
+                     global ? (const double*)(ws + L.lqf) : (const double*)nullptr, unif, state, S,
+                     (const double*)(ws + L.detA), status, acc, n_accept);
   CHECK(hipGetLastError());
   for (int s = 0; s < 2; ++s) {
     const int N = D.nsig(s);
@@ -1676,8 +1720,9 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
 
 template <typename T>
 static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
-                             const double* noise, const double* unif, int32_t* n_accept, double* logpsi,
-                             double* sign, int32_t* status, hipStream_t st) {
+                             double gstep, const int32_t* kinds, const double* noise, const double* unif,
+                             const double* pick, int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
+                             hipStream_t st) {
   const Dims& D = h->D;
   Net<T> P = make_net<T>(h);
   CHECK(fill_i32(status, W, 0, st));
@@ -1689,9 +1734,18 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
       jb.woodbury = true;
       jb.xi = noise + ((int64_t)sw * D.n + e) * W * 3;
       jb.step = step;
+      const bool global = kinds && kinds[sw] == 1;
+      if (global) {
+        jb.pick = pick + ((int64_t)sw * D.n + e) * W;
+        jb.gstep = gstep;
+        jb.Rn = P.Rn;
+        jb.Zn = P.Zn;
+        jb.M = D.M;
+        jb.lqf = (double*)(ws + upd_layout(h, W).lqf);
+      }
       const double* u = unif + ((int64_t)sw * D.n + e) * W;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, ws, status, st));
-      CHECK(accept_and_commit<T>(h, W, e, R, u, state, ws, n_accept, status, st));
+      CHECK(accept_and_commit<T>(h, W, e, R, u, global, state, ws, n_accept, status, st));
     }
     if (refresh > 0 && (sw + 1) % refresh == 0) {
       // full re-evaluation of every cached quantity from the positions (FP64 LU)
@@ -1705,13 +1759,14 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
 }
 
 hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
-                           const double* noise, const double* unif, int32_t* n_accept, double* logpsi,
-                           double* sign, int32_t* status, hipStream_t s) {
+                           double gstep, const int32_t* kinds, const double* noise, const double* unif,
+                           const double* pick, int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
+                           hipStream_t s) {
   if (!update_fits(h)) return hipErrorInvalidValue;
-  return h->tsize == 8 ? sweep_impl<double>(h, W, R, state, ws, n_sweeps, step, noise, unif, n_accept, logpsi, sign,
-                                            status, s)
-                       : sweep_impl<float>(h, W, R, state, ws, n_sweeps, step, noise, unif, n_accept, logpsi, sign,
-                                           status, s);
+  return h->tsize == 8 ? sweep_impl<double>(h, W, R, state, ws, n_sweeps, step, gstep, kinds, noise, unif, pick,
+                                            n_accept, logpsi, sign, status, s)
+                       : sweep_impl<float>(h, W, R, state, ws, n_sweeps, step, gstep, kinds, noise, unif, pick,
+                                           n_accept, logpsi, sign, status, s);
 }
 
 template hipError_t propose_ratio<double>(const fire_handle*, const Net<double>&, const Jobs&, int,

@@ -22,12 +22,21 @@ struct Jobs {
   double step;
   bool woodbury;       // workspace laid out with the Woodbury buffers (Metropolis)
   int group;           // consecutive jobs sharing most of their update set (cache locality)
+  // global single-electron jumps (Metropolis only): with pick set, r_e' is a
+  // draw of the charge-weighted Gaussian mixture over the nuclei, R_m +
+  // gstep * xi, and log rho(r_e) - log rho(r_e') goes to lqf[j]
+  const double* pick;
+  double gstep;
+  const double* Rn;
+  const double* Zn;
+  int M;
+  double* lqf;
 };
 
 struct UpdLayout {
   int capS[2], capmax;
   int64_t rowcap[2];
-  size_t rnew, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
+  size_t rnew, lqf, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
   size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2], bbuf[2];
   size_t total;
 };

@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
 W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
 
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
-           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep",
+           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
     lib.fire_set_params.argtypes = [P, V, V, V]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
+    lib.fire_mcmc_sweep_mixed.argtypes = [P, I, V, V, V, I, D, D, ctypes.POINTER(ctypes.c_int32), V, V, V, V, V, V,
+                                          V, V]
     lib.fire_local_energy.argtypes = [P, I, V, V, V, V, V, V, V, V, V]
     lib.fire_ecp_nonlocal.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V]
@@ -263,6 +265,23 @@ class Fire:
         _check(load().fire_mcmc_sweep(self.h, W, _dp(R), _dp(state), _dp(ws), int(n_sweeps), float(step),
                                       _dp(noise), _dp(unif), _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status),
                                       _stream()), "fire_mcmc_sweep")
+        return n_accept, sign, logpsi, status
+
+    def mcmc_sweep_mixed(self, R, state, ws, kinds, step, global_step, noise, unif, pick, n_accept=None):
+        """Sweeps of local moves (kinds[t] = 0) and global single-electron
+        jumps (kinds[t] = 1); pick [S][n][W] uniforms (None if no sweep is
+        global)."""
+        W = R.shape[0]
+        if n_accept is None:
+            n_accept = torch.zeros(W, dtype=torch.int32, device=self.device)
+        sign = torch.empty(W, dtype=torch.float64, device=self.device)
+        logpsi = torch.empty_like(sign)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        k = (ctypes.c_int32 * len(kinds))(*[int(x) for x in kinds])
+        _check(load().fire_mcmc_sweep_mixed(self.h, W, _dp(R), _dp(state), _dp(ws), len(kinds), float(step),
+                                            float(global_step), k, _dp(noise), _dp(unif), _dp(pick),
+                                            _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status), _stream()),
+               "fire_mcmc_sweep_mixed")
         return n_accept, sign, logpsi, status
 
     def local_energy(self, R, state, ws, quad_rot=None, want_grad=False):

@@ -165,3 +165,72 @@ def test_large_update_sets_ecp_matches_oracle(lib):
     log(f"V_NL gpu {v} oracle {vo} err {np.abs(v - vo).max():.2e}")
     assert (st.cpu().numpy() == 0).all()
     assert np.abs(v - vo).max() <= 1e-9
+
+
+def _mixed_chain(cid, W, kinds, precision="fp64", gstep=2.0, seed=0, **kw):
+    F, O, s, m, p, R, state, ws = setup(cid, W, precision, **kw)
+    rng = np.random.default_rng(200 + cid + seed)
+    xi, u = wl.mcmc_noise(len(kinds), s.n_el, W, rng)
+    pk = wl.gmm_picks(len(kinds), s.n_el, W, rng)
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    nacc, sg, lp, st = F.mcmc_sweep_mixed(Rd, state, ws, kinds, 0.2, gstep, dev(xi), dev(u), dev(pk))
+    torch.cuda.synchronize()
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.2, xi, u, kinds=kinds, pick=pk, gstep=gstep)
+    return F, Rd, state, ws, nacc.cpu().numpy(), sg.cpu().numpy(), lp.cpu().numpy(), st.cpu().numpy(), \
+        Ro.numpy(), so.numpy(), lo.numpy(), no.numpy()
+
+
+@pytest.mark.parametrize("kinds", [[1] * 6, [0, 1, 1, 0, 1, 0]])
+def test_h4_global_jumps_match_oracle(lib, kinds):
+    log(f"case: H4 fp64 W=64 sweeps {kinds} (1 = global jumps from the nuclear Gaussian mixture)")
+    F, Rd, state, ws, na, sg, lp, st, Ro, so, lo, no = _mixed_chain(0, 64, kinds)
+    Rg = Rd.cpu().numpy()
+    log("acc", na.sum(), no.sum(), "max|dR|", np.abs(Rg - Ro).max(), "max|dlogpsi|", np.abs(lp - lo).max())
+    assert (st == 0).all()
+    assert np.array_equal(na, no)
+    assert np.abs(Rg - Ro).max() <= 1e-12
+    assert np.abs(lp - lo).max() <= 1e-10
+    assert np.array_equal(sg, so)
+    eg, ep, el = _fresh_vs_cached(F, Rd, state, ws, 64)
+    assert eg <= 1e-9 and ep <= 1e-12 and el <= 1e-10
+
+
+def test_polyene_global_jumps_match_oracle(lib):
+    """Global jumps land far from the old position: the update set is the
+    union of two separate neighbourhoods."""
+    log("case: C12H14 fp64 W=6 sweeps [1, 0] with global jumps")
+    n = 62
+    F, Rd, state, ws, na, sg, lp, st, Ro, so, lo, no = _mixed_chain(1, 6, [1, 0], refresh_every=0,
+                                                                     cap_upd=n, cap_nbr=n - 1)
+    Rg = Rd.cpu().numpy()
+    log("acc", na, no, "max|dR|", np.abs(Rg - Ro).max(), "max|dlogpsi|", np.abs(lp - lo).max())
+    assert (st == 0).all()
+    assert np.array_equal(na, no)
+    assert np.abs(Rg - Ro).max() <= 1e-12
+    assert np.abs(lp - lo).max() <= 1e-10
+    eg, ep, el = _fresh_vs_cached(F, Rd, state, ws, 6)
+    assert eg <= 1e-8 and ep <= 1e-11 and el <= 1e-10
+
+
+def test_mixed_sweep_argument_errors(lib):
+    from paper_2504_06087_amd import fire
+    F, O, s, m, p, R, state, ws = setup(0, 4, "fp64")
+    rng = np.random.default_rng(3)
+    xi, u = wl.mcmc_noise(2, s.n_el, 4, rng)
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    with pytest.raises(fire.FireError):
+        F.mcmc_sweep_mixed(Rd, state, ws, [0, 2], 0.2, 2.0, dev(xi), dev(u), dev(u))
+    with pytest.raises(fire.FireError):
+        F.mcmc_sweep_mixed(Rd, state, ws, [0, 1], 0.2, 2.0, dev(xi), dev(u), None)
+    with pytest.raises(fire.FireError):
+        F.mcmc_sweep_mixed(Rd, state, ws, [1, 1], 0.2, 0.0, dev(xi), dev(u), dev(u))
+    # all-local kinds need no picks and equal fire_mcmc_sweep
+    st2, ws2 = F.buffers(4)
+    R2 = Rd.clone()
+    F.eval_logpsi(R2, st2, ws2)
+    n1, _, l1, _ = F.mcmc_sweep_mixed(Rd, state, ws, [0, 0], 0.2, 0.0, dev(xi), dev(u), None)
+    n2, _, l2, _ = F.mcmc_sweep(R2, st2, ws2, 2, 0.2, dev(xi), dev(u))
+    torch.cuda.synchronize()
+    assert torch.equal(n1, n2) and torch.equal(l1, l2) and torch.equal(Rd, R2)

@@ -391,6 +391,11 @@ def mcmc_noise(n_sweeps: int, n_el: int, W: int, rng):
     return xi, u
 
 
+def gmm_picks(n_sweeps: int, n_el: int, W: int, rng):
+    """Uniforms [S][n][W] that choose the nucleus of each global jump."""
+    return rng.uniform(size=(n_sweeps, n_el, W))
+
+
 def haar_rotations(W: int, rng) -> np.ndarray:
     """Uniformly random rotation matrices [W][3][3] (QR of Gaussian matrices)."""
     A = rng.normal(size=(W, 3, 3))
