@@ -21,7 +21,8 @@ over orbitals; SiLU activations; a LLaMA-style GLU W_o[(LN(s)W_v+b_v) *
 SiLU(LN(s)W_g+b_g)] + b_o; filters 4 -> 16 -> 8 -> d with a 32-Gaussian radial
 part; the polynomial cutoff with p = 6; separate parallel/antiparallel
 message weights; no Jastrow factor (J = 1); semilocal l = 0, 1 pseudopotential
-channels with a 12-point icosahedral rule.
+channels with an equal-weight angular rule per species (12-point icosahedron
+unless the system names 4 or 6 points).
 
 The paper prints no worked example for this path, so no function here is
 compared with a printed number; every function is pinned instead by the
@@ -71,6 +72,27 @@ def _log1p_over(r):
     small = r < 1e-8
     rs = torch.where(small, torch.ones_like(r), r)
     return torch.where(small, 1.0 - 0.5 * r, torch.log1p(rs) / rs)
+
+
+def quadrature_directions(n_quad: int) -> torch.Tensor:
+    """Unit vectors of the equal-weight angular quadrature with n_quad points
+    (SI, effective core potential, N_quad per species): the vertices of the
+    tetrahedron (4), octahedron (6) or icosahedron (12), spherical designs of
+    strength 2, 3 and 5."""
+    if n_quad == 4:
+        v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) / math.sqrt(3.0)
+    elif n_quad == 6:
+        v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    elif n_quad == 12:
+        ph = (1.0 + math.sqrt(5.0)) / 2.0
+        v = []
+        for a in (1.0, -1.0):
+            for b in (ph, -ph):
+                v += [[0.0, a, b], [a, b, 0.0], [b, 0.0, a]]
+        v = np.array(v) / math.sqrt(1.0 + ph * ph)
+    else:
+        raise ValueError(f"no {n_quad}-point rule")
+    return torch.tensor(v, dtype=DT)
 
 
 class Oracle:
@@ -269,20 +291,21 @@ class Oracle:
 
     def ecp_nonlocal(self, R, Q=None):
         """Nonlocal pseudopotential: for every electron i and pseudo-atom I with
-        |r_i - R_I| < r_max, sum_l v_l(r)(2l+1) (1/12) sum_q P_l(cos) psi(r_i ->
-        R_I + r Q e_q)/psi, every ratio by full re-evaluation."""
-        from workloads import icosahedron_vertices
+        |r_i - R_I| < r_max, sum_l v_l(r)(2l+1) (1/N_q) sum_q P_l(cos)
+        psi(r_i -> R_I + r Q e_q)/psi, every ratio by full re-evaluation.  The
+        rule has N_q points per species (SI, effective core potential:
+        tetrahedron 4, octahedron 6, icosahedron 12; default 12)."""
         R = torch.as_tensor(R, dtype=DT)
         B, n = R.shape[:2]
         out = torch.zeros(B, dtype=DT)
         if not self.sys.ecp:
             return out
-        verts = torch.tensor(icosahedron_vertices(), dtype=DT)       # [12,3]
+        nq_of = getattr(self.sys, "ecp_nquad", {}) or {}
         Qs = torch.eye(3, dtype=DT)[None].expand(B, 3, 3) if Q is None else torch.as_tensor(Q, dtype=DT)
         s0, l0 = self.log_psi(R)
         rmax = self.sys.ecp_rmax
         for b in range(B):
-            pts = (Qs[b] @ verts.T).T                                 # rotated quadrature directions
+            rules = {nq: (Qs[b] @ quadrature_directions(nq).T).T for nq in (4, 6, 12)}   # rotated directions
             jobs = []
             for i in range(n):
                 for I in range(self.Rn.shape[0]):
@@ -296,15 +319,17 @@ class Oracle:
                     jobs.append((i, I, sp, r, v / r))
             if not jobs:
                 continue
-            Rq = R[b][None].repeat(len(jobs) * 12, 1, 1).clone()
+            nqs = [int(nq_of.get(sp, 12)) for (_, _, sp, _, _) in jobs]
+            first = np.concatenate([[0], np.cumsum(nqs)])
+            Rq = R[b][None].repeat(int(first[-1]), 1, 1).clone()
             for k, (i, I, sp, r, u) in enumerate(jobs):
-                Rq[12 * k:12 * k + 12, i] = self.Rn[I][None] + r * pts
+                Rq[first[k]:first[k + 1], i] = self.Rn[I][None] + r * rules[nqs[k]]
             sq, lq = self.log_psi(Rq)
             ratio = (sq * s0[b]) * torch.exp(lq - l0[b])
             tot = 0.0
             for k, (i, I, sp, r, u) in enumerate(jobs):
-                cos = pts @ u
-                rk = ratio[12 * k:12 * k + 12]
+                cos = rules[nqs[k]] @ u
+                rk = ratio[first[k]:first[k + 1]]
                 for ch in self.sys.ecp[sp]:
                     vl = float(np.sum(ch.a * np.exp(-ch.alpha * r * r)))
                     Pl = torch.ones_like(cos) if ch.l == 0 else cos

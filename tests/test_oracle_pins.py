@@ -479,13 +479,46 @@ def test_icosahedron_is_a_spherical_5_design():
             assert abs(Pl.mean() - (1.0 if l == 0 else 0.0)) < 1e-13
 
 
-def test_ecp_spherically_symmetric_wavefunction_gives_v0():
+@pytest.mark.parametrize("nq,strength", [(4, 2), (6, 3), (12, 5)])
+def test_quadrature_rules_are_spherical_designs(nq, strength):
+    """The N_q-point rules (tetrahedron, octahedron, icosahedron) average
+    P_l(e . e_q) to delta_l0 for every l up to their design strength and for
+    any direction e, and not beyond it (so each rule is the one named)."""
+    from numpy.polynomial import legendre
+    from oracle import quadrature_directions
+    v = quadrature_directions(nq).numpy()
+    assert v.shape == (nq, 3) and np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+    rng = np.random.default_rng(2)
+    worst_next = 0.0
+    for _ in range(6):
+        e = rng.normal(size=3)
+        e /= np.linalg.norm(e)
+        c = v @ e
+        for l in range(strength + 1):
+            Pl = legendre.legval(c, [0] * l + [1])
+            assert abs(Pl.mean() - (1.0 if l == 0 else 0.0)) < 1e-13
+        worst_next = max(worst_next, abs(legendre.legval(c, [0] * (strength + 1) + [1]).mean()))
+    assert worst_next > 1e-3
+
+
+def test_icosahedron_rule_matches_the_generated_vertices():
+    # two independent constructions of the 12-point set agree as point sets
+    from oracle import quadrature_directions
+    a = quadrature_directions(12).numpy()
+    b = wl.icosahedron_vertices()
+    d = np.linalg.norm(a[:, None] - b[None], axis=-1)
+    assert np.allclose(d.min(1), 0.0, atol=1e-14) and np.allclose(d.min(0), 0.0, atol=1e-14)
+
+
+@pytest.mark.parametrize("nq", [4, 6, 12])
+def test_ecp_spherically_symmetric_wavefunction_gives_v0(nq):
     """With psi = exp(-r) centred on the pseudo-atom every ratio is 1 and the
-    angular average of P_l vanishes for l = 1: V_NL = v_0(r)."""
+    angular average of P_l vanishes for l = 1 under each rule: V_NL = v_0(r)."""
     s, m, p, R = wl.hydrogen_atom(W=5, seed=9)
     rng = np.random.default_rng(3)
     s.species = np.ones(1, np.int32)
     s.ecp = wl._ecp_tables(rng)
+    s.ecp_nquad = {1: nq}
     R = R / np.linalg.norm(R, axis=-1, keepdims=True) * rng.uniform(0.2, 1.9, size=(5, 1, 1))
     o = Oracle(s, m, p)
     Q = wl.haar_rotations(5, rng)

@@ -71,6 +71,9 @@ class System:
     pp_width: np.ndarray       # [M] float64; 0 = bare Coulomb, w>0 -> -Z erf(r/w)/r
     ecp: Dict[int, List[EcpChannel]]  # species -> nonlocal channels
     ecp_rmax: float = 2.0
+    # species -> quadrature points of its nonlocal channels (4, 6 or 12;
+    # species not named use 12)
+    ecp_nquad: Dict[int, int] = dataclasses.field(default_factory=dict)
     elec_atom: Optional[np.ndarray] = None  # [n] atom index used to place electrons
 
     @property
