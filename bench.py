@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the uneven 16-system batch")
+    ap.add_argument("--no-rule4", action="store_true",
+                    help="skip the E_L phase timed with the 4-point pseudopotential rule on C")
     ap.add_argument("--c5-walkers", type=int, default=512)
     ap.add_argument("--scaling", action="store_true",
                     help="runtime-scaling sweep over cumulene chains instead of the step benchmark")
@@ -175,6 +177,38 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     out["prof"] = prof
     out["global_jump_sweep"] = gmm
     return out
+
+
+def run_el_rule(split, W, n_quad):
+    """The local-energy phase of the same workload with an n_quad-point
+    pseudopotential rule on C instead of the 12-point one (the paper's
+    per-species choice is 4 points for Li-Ne): one untimed and one timed
+    call after a full evaluation."""
+    import copy
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    work = wl.config(3, walkers=W)
+    s = copy.deepcopy(work.systems[0])
+    s.ecp_nquad = {1: n_quad}
+    F = fire.Fire(s, work.model, "bf16", max_walkers=W, cap_nbr=48, cap_upd=64, refresh_every=50,
+                  bf16_split=split)
+    F.set_params(work.params[0])
+    state, ws = F.buffers(W)
+    R = torch.tensor(work.R[0], dtype=torch.float64, device="cuda")
+    Q = torch.tensor(wl.haar_rotations(W, np.random.default_rng(7)), device="cuda")
+    F.eval_logpsi(R, state, ws)
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        F.local_energy(R, state, ws, Q)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    return {"n_quad_on_C": n_quad, "local_energy_ms": ms[-1], "local_energies_per_s_el_phase": W / (ms[-1] / 1e3)}
 
 
 def run_c5(split, W, steps, warmup):
@@ -398,6 +432,11 @@ def main():
     hyb = run_precision("bf16", a.split, W, a.steps, a.warmup, not a.no_grad, profile=True)
     print(f"# hybrid: {json.dumps({k: v for k, v in hyb.items() if k != 'prof'})}", flush=True)
     print(f"# hybrid GEMM profile: {hyb['prof']}", flush=True)
+    rule4 = None
+    if not a.no_rule4:
+        torch.cuda.empty_cache()
+        rule4 = run_el_rule(a.split, W, 4)
+        print(f"# E_L with the 4-point rule on C: {json.dumps(rule4)}", flush=True)
     fp32 = None
     if not a.no_fp32:
         torch.cuda.empty_cache()
@@ -442,6 +481,7 @@ def main():
         "local_energies_per_s_el_phase": hyb["local_energies_per_s"],
         "phases_ms": hyb["phases_ms"], "acceptance": hyb["acceptance"], "grad_included": hyb["have_grad"],
         "global_jump_sweep": hyb.get("global_jump_sweep"),
+        "local_energy_4point_rule": rule4,
         "fp32_plain": None if fp32 is None else {
             "value": fp32["walkers_per_s"], "ms_per_step": fp32["ms_per_step"], "phases_ms": fp32["phases_ms"],
             "walker_steps_per_s": fp32["walker_steps_per_s"],

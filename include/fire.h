@@ -71,6 +71,10 @@ typedef struct {
   int n_terms;         /* <= 4 */
   const double* a;     /* host [n_terms] */
   const double* alpha; /* host [n_terms] */
+  int n_quad;          /* angular quadrature points of this species (SI,
+                          effective core potential, N_quad per species):
+                          4 tetrahedron, 6 octahedron, 12 icosahedron, 0 = 12;
+                          every channel of one species gives the same value */
 } fire_ecp_channel;
 
 /* The molecule (Methods, Hamiltonian eq. hamiltonian).  Host arrays, copied. */

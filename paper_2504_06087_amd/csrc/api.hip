@@ -199,8 +199,12 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   for (int k = 0; k < sys->n_ecp; ++k) {
     const fire_ecp_channel& c = sys->ecp[k];
     if (c.n_terms < 1 || c.n_terms > 4 || c.l < 0 || c.l > 1 || !c.a || !c.alpha) { delete h; return FIRE_ERR_ARG; }
+    const int nq = c.n_quad == 0 ? 12 : c.n_quad;
+    bool clash = nq != 4 && nq != 6 && nq != 12;
+    for (const EcpChan& o : h->ecp) clash = clash || (o.species == c.species && o.nquad != nq);
+    if (clash) { delete h; return FIRE_ERR_ARG; }
     EcpChan e{};
-    e.species = c.species; e.l = c.l; e.nterms = c.n_terms;
+    e.species = c.species; e.l = c.l; e.nterms = c.n_terms; e.nquad = nq;
     for (int t = 0; t < c.n_terms; ++t) { e.a[t] = c.a[t]; e.alpha[t] = c.alpha[t]; }
     h->ecp.push_back(e);
   }

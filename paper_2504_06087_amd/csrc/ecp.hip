@@ -1,9 +1,10 @@
 // Nonlocal pseudopotential energy by angular quadrature of psi ratios
 // (Methods, effective core potential; low-rank wave-function updates):
 //   V_NL = sum_{i, I: |r_i - R_I| < r_max} sum_l v_l(r_iI) (2l+1)
-//          (1/12) sum_q P_l(rhat_iI . Q e_q) psi(r_i -> R_I + r_iI Q e_q) / psi
-// with the 12 icosahedron vertices e_q.  Every ratio is one single-electron
-// update (neighbour recompute + det A), never a full re-evaluation.
+//          (1/N_q) sum_q P_l(rhat_iI . Q e_q) psi(r_i -> R_I + r_iI Q e_q) / psi
+// with the N_q vertices e_q of the species' rule (4 tetrahedron, 6
+// octahedron, 12 icosahedron).  Every ratio is one single-electron update
+// (neighbour recompute + det A), never a full re-evaluation.
 #include <vector>
 
 #include "laplacian.hpp"
@@ -13,12 +14,12 @@ namespace fire {
 
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
-constexpr int NQ = 12;
+constexpr int NQ = 12;          // the largest rule
 constexpr int ECP_PMAX = 8;     // pseudo-atoms within r_max of one electron
 
 struct EcpTables {
   int nchan;
-  int species[8], l[8], nterms[8];
+  int species[8], l[8], nterms[8], nq[8];
   double a[8][4], alpha[8][4];
   double rmax;
 };
@@ -28,7 +29,7 @@ static EcpTables tables(const fire_handle* h) {
   t.nchan = (int)h->ecp.size() < 8 ? (int)h->ecp.size() : 8;
   for (int k = 0; k < t.nchan; ++k) {
     const EcpChan& c = h->ecp[k];
-    t.species[k] = c.species; t.l[k] = c.l; t.nterms[k] = c.nterms;
+    t.species[k] = c.species; t.l[k] = c.l; t.nterms[k] = c.nterms; t.nq[k] = c.nquad;
     for (int j = 0; j < 4; ++j) { t.a[k][j] = c.a[j]; t.alpha[k][j] = c.alpha[j]; }
   }
   t.rmax = h->ecp_rmax;
@@ -47,11 +48,29 @@ FIRE_DEV void ico_vertex(int q, double v[3]) {
   v[0] = t[0] * nrm; v[1] = t[1] * nrm; v[2] = t[2] * nrm;
 }
 
-FIRE_DEV bool is_ecp_species(const EcpTables& t, int sp) {
-  for (int k = 0; k < t.nchan; ++k)
-    if (t.species[k] == sp) return true;
-  return false;
+// tetrahedron (4) and octahedron (6) vertices
+FIRE_DEV void quad_vertex(int nq, int q, double v[3]) {
+  if (nq == 12) {
+    ico_vertex(q, v);
+  } else if (nq == 6) {
+    v[0] = v[1] = v[2] = 0.0;
+    v[q >> 1] = (q & 1) ? -1.0 : 1.0;
+  } else {
+    const double s = 0.57735026918962576451;   // 1/sqrt(3)
+    v[0] = s;
+    v[1] = (q == 1 || q == 3) ? -s : s;
+    v[2] = (q == 1 || q == 2) ? -s : s;
+    if (q >= 2) v[0] = -s;
+  }
 }
+
+// quadrature points of species sp (0: no nonlocal channel)
+FIRE_DEV int nq_of(const EcpTables& t, int sp) {
+  for (int k = 0; k < t.nchan; ++k)
+    if (t.species[k] == sp) return t.nq[k];
+  return 0;
+}
+FIRE_DEV bool is_ecp_species(const EcpTables& t, int sp) { return nq_of(t, sp) > 0; }
 
 // number of pseudo-atoms within r_max of electron e, per (e, w): cnt[e][w]
 __global__ void k_ecp_count(const Dims D, int W, const double* __restrict__ R, const double* __restrict__ Rn,
@@ -61,14 +80,19 @@ __global__ void k_ecp_count(const Dims D, int W, const double* __restrict__ R, c
   if (q >= (int64_t)W * D.n) return;
   const int w = (int)(q / D.n), e = (int)(q % D.n);
   const double* r = R + q * 3;
-  int c = 0;
+  // jobs of the first ECP_PMAX pseudo-atoms within r_max, N_q per atom
+  int c = 0, jobs = 0;
   for (int m = 0; m < D.M; ++m) {
-    if (!is_ecp_species(t, species[m])) continue;
+    const int nq = nq_of(t, species[m]);
+    if (nq == 0) continue;
     const double dx = r[0] - Rn[3 * m], dy = r[1] - Rn[3 * m + 1], dz = r[2] - Rn[3 * m + 2];
-    if (dx * dx + dy * dy + dz * dz < t.rmax * t.rmax) ++c;
+    if (dx * dx + dy * dy + dz * dz < t.rmax * t.rmax) {
+      if (c < ECP_PMAX) jobs += nq;
+      ++c;
+    }
   }
-  if (c > ECP_PMAX) { atomicOr(status + w, FIRE_W_UPD_OVERFLOW); c = ECP_PMAX; }
-  cnt[(int64_t)e * W + w] = NQ * c;
+  if (c > ECP_PMAX) atomicOr(status + w, FIRE_W_UPD_OVERFLOW);
+  cnt[(int64_t)e * W + w] = jobs;
 }
 
 // per electron e: exclusive scan over walkers of the job counts; tot[e]
@@ -111,14 +135,18 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const doub
     if (off[mid] <= jg) lo = mid; else hi = mid - 1;
   }
   const int w = lo;
-  const int loc = jg - off[w], p = loc / NQ, q = loc % NQ;
+  // the pseudo-atom and point of this job: walk the atoms within r_max in
+  // the order k_ecp_count counted them, N_q jobs each
+  int loc = jg - off[w];
   const double* r = R + ((int64_t)w * D.n + e) * 3;
-  int c = 0, I = -1;
-  for (int m = 0; m < D.M && I < 0; ++m) {
-    if (!is_ecp_species(t, species[m])) continue;
+  int c = 0, I = -1, q = 0, nqI = NQ;
+  for (int m = 0; m < D.M && I < 0 && c < ECP_PMAX; ++m) {
+    const int nq = nq_of(t, species[m]);
+    if (nq == 0) continue;
     const double dx = r[0] - Rn[3 * m], dy = r[1] - Rn[3 * m + 1], dz = r[2] - Rn[3 * m + 2];
     if (dx * dx + dy * dy + dz * dz < t.rmax * t.rmax) {
-      if (c == p) I = m;
+      if (loc < nq) { I = m; q = loc; nqI = nq; }
+      else loc -= nq;
       ++c;
     }
   }
@@ -131,7 +159,7 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const doub
   const double dx = r[0] - Rn[3 * I], dy = r[1] - Rn[3 * I + 1], dz = r[2] - Rn[3 * I + 2];
   const double rr = sqrt(dx * dx + dy * dy + dz * dz);
   double v[3], u[3];
-  ico_vertex(q, v);
+  quad_vertex(nqI, q, v);
   if (quad_rot) {
     const double* Q = quad_rot + (int64_t)w * 9;
     for (int k = 0; k < 3; ++k) u[k] = Q[3 * k] * v[0] + Q[3 * k + 1] * v[1] + Q[3 * k + 2] * v[2];
@@ -148,7 +176,7 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const doub
     double vl = 0.0;
     for (int m = 0; m < t.nterms[k]; ++m) vl += t.a[k][m] * exp(-t.alpha[k][m] * rr * rr);
     const double Pl = t.l[k] == 0 ? 1.0 : cs;
-    coef += vl * (2 * t.l[k] + 1) * Pl / NQ;
+    coef += vl * (2 * t.l[k] + 1) * Pl / nqI;
   }
   cf[j] = coef;
 }
@@ -258,7 +286,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       Jobs jb{};
       jb.J = J;
       jb.Jcap = L.Jc;
-      jb.group = NQ;
+      jb.group = tb.nq[0];   // the jobs of one (electron, pseudo-atom) pair are consecutive
       jb.jw = jw;
       jb.rexp = rexp;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, st));

@@ -20,7 +20,7 @@ struct ThetaEntry {
 };
 
 struct EcpChan {
-  int species, l, nterms;
+  int species, l, nterms, nquad;
   double a[4], alpha[4];
 };
 

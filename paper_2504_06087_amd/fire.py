@@ -32,7 +32,8 @@ EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params"
 
 class FireEcpChannel(ctypes.Structure):
     _fields_ = [("species", ctypes.c_int), ("l", ctypes.c_int), ("n_terms", ctypes.c_int),
-                ("a", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.POINTER(ctypes.c_double))]
+                ("a", ctypes.POINTER(ctypes.c_double)), ("alpha", ctypes.POINTER(ctypes.c_double)),
+                ("n_quad", ctypes.c_int)]
 
 
 class FireSystemDesc(ctypes.Structure):
@@ -150,9 +151,10 @@ def _system_desc(system, keep: list) -> FireSystemDesc:
             a = np.ascontiguousarray(ch.a, np.float64)
             al = np.ascontiguousarray(ch.alpha, np.float64)
             keep += [a, al]
+            nq = int(getattr(system, "ecp_nquad", {}).get(sp, 12))
             chans.append(FireEcpChannel(int(sp), int(ch.l), len(a),
                                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                        al.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+                                        al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nq))
     arr = (FireEcpChannel * max(1, len(chans)))(*chans)
     keep.append(arr)
     dp = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))

@@ -132,3 +132,34 @@ def test_polyene_fp32_local_energy_vs_gpu_fp64(lib):
     # to 1e-3 Ha, the worst walker to 5e-2 Ha
     assert np.median(err) <= 1e-3 and abs(np.mean(e32 - e64)) <= 1e-3
     assert err.max() <= 5e-2
+
+
+@pytest.mark.parametrize("nq", [4, 6])
+def test_polyene_ecp_per_species_rule(lib, nq):
+    """N_q-point rules per species (SI, effective core potential: 4 points
+    for Li-Ne, 6 for Na-Ar): V_NL against the oracle with the same rule."""
+    log(f"case: narrow C12H14 nonlocal ECP fp64 W=2, {nq}-point rule on C")
+    s, m, p, R = small_polyene(2, ecp=True, seed=11)
+    s.ecp_nquad = {1: nq}
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Q = wl.haar_rotations(2, np.random.default_rng(5))
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    v, st = F.ecp_nonlocal(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    vo = O.ecp_nonlocal(R, Q).numpy()
+    v = v.cpu().numpy()
+    log(f"V_NL gpu {v} oracle {vo} err {np.abs(v - vo).max():.2e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.abs(v - vo).max() <= 1e-9
+    # and the full local energy includes it
+    e, parts, g, st = _el(F, R, state, ws, Q=Q, grad=False)
+    assert np.abs(parts[:, 4] - vo).max() <= 1e-9
+
+
+def test_ecp_rule_validation(lib):
+    from paper_2504_06087_amd import fire
+    s, m, p, R = small_polyene(1, ecp=True, seed=11)
+    s.ecp_nquad = {1: 5}
+    with pytest.raises(fire.FireError):
+        fire.Fire(s, m, "fp64", max_walkers=1)
