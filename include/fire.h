@@ -206,8 +206,11 @@ fire_status fire_local_energy(fire_handle* h, int W, const double* R, void* stat
                               double* grad_logpsi, int32_t* status, hipStream_t stream);
 
 /* Nonlocal pseudopotential energy per walker (Methods, effective core
- * potential): for every electron within ecp_rmax of a pseudo-atom, a 12-point
- * icosahedral quadrature of psi ratios from single-electron low-rank updates. */
+ * potential): for every electron within ecp_rmax of a pseudo-atom, an
+ * equal-weight angular quadrature of psi ratios from single-electron low-rank
+ * updates, with the pseudo-atom species' n_quad points (4 tetrahedron, 6
+ * octahedron, 12 icosahedron), rotated by quad_rot[w] ([W][3][3], NULL:
+ * identity). */
 fire_status fire_ecp_nonlocal(fire_handle* h, int W, const double* R, void* state, void* ws,
                               const double* quad_rot, double* v_nl, int32_t* status,
                               hipStream_t stream);
