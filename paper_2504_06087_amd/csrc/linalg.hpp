@@ -11,6 +11,7 @@ namespace fire {
 // invert is set and the matrix is non-singular), sc[0] the sign and sc[1]
 // log|det A|, and fl[1] = 1 when a zero or non-finite pivot was met.
 // f: LDS scratch [N]; perm: LDS scratch [N]; sc: LDS [2]; fl: LDS [2].
+// The block size is a multiple of 128 (all callers launch 256 threads).
 FIRE_DEV void gj_block(double* A, int N, int LD, double* f, int* perm, double* sc, int* fl, bool invert) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) { sc[0] = 1.0; sc[1] = 0.0; fl[1] = 0; }
@@ -51,18 +52,25 @@ FIRE_DEV void gj_block(double* A, int N, int LD, double* f, int* perm, double* s
     }
     for (int i = tid; i < N; i += nt) f[i] = (i == k) ? 0.0 : A[i * LD + k] / piv;
     __syncthreads();
+    // thread t updates column c0 + t % 128 for c0 = 0, 128, ... and the
+    // rows t / 128, t / 128 + nt / 128, ...: the pivot-row element stays in a
+    // register and no index is divided (same update per element as a flat
+    // loop, so the same result)
+    const int tc = tid & 127, tr = tid >> 7, rs = nt >> 7;
     if (invert) {
-      for (int q = tid; q < N * N; q += nt) {
-        int i = q / N, j = q % N;
-        if (i == k) continue;
-        if (j == k) A[i * LD + j] = -f[i];
-        else A[i * LD + j] -= f[i] * A[k * LD + j];
+      for (int j = tc; j < N; j += 128) {
+        const double akj = A[k * LD + j];
+        for (int i = tr; i < N; i += rs) {
+          if (i == k) continue;
+          if (j == k) A[i * LD + j] = -f[i];
+          else A[i * LD + j] -= f[i] * akj;
+        }
       }
     } else {
       // determinant only: eliminate below the pivot
-      for (int q = tid; q < (N - k - 1) * (N - k - 1); q += nt) {
-        int i = k + 1 + q / (N - k - 1), j = k + 1 + q % (N - k - 1);
-        A[i * LD + j] -= f[i] * A[k * LD + j];
+      for (int j = k + 1 + tc; j < N; j += 128) {
+        const double akj = A[k * LD + j];
+        for (int i = k + 1 + tr; i < N; i += rs) A[i * LD + j] -= f[i] * akj;
       }
     }
     __syncthreads();
