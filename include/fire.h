@@ -139,13 +139,14 @@ fire_status fire_sizes(const fire_handle* h, int W, size_t* params_bytes, size_t
                        size_t* workspace_bytes);
 
 /* Byte offsets, within one walker's record of the state buffer, of the
- * cached intermediates: offsets[0..9] = h0 [n][d], projections [n][4][d]
+ * cached intermediates: offsets[0..10] = h0 [n][d], projections [n][4][d]
  * (a_par, a_anti, b_par, b_anti), messages m [n][d], Phi [K][(n_up^2 +
  * n_dn^2)] (per determinant the up block then the down block, row i =
  * electron, column l = orbital), envelopes (same shape as Phi), G = Phi^-T
  * (same shape: G[k][l] = (Phi^-1)[l][k], the derivative of log|det| by
- * Phi[k][l]), determinant signs [K][2] and log|det| [K][2] (FP64), log|psi|
- * and sign (FP64).  Arrays
+ * Phi[k][l]), determinant signs [K][2] and log|det| [K][2] (FP64),
+ * log|sum_d det_d| and its sign (FP64), and the log of the cusp Jastrow
+ * factor (FP64; log|psi| is the sum of the last two logs).  Arrays
  * other than the FP64 ones use the precision's elementwise type (FP64 for
  * FIRE_FP64, FP32 otherwise; Phi^-1 is FP64 except under FIRE_FP32).
  * *stride is the record size; walker w's record starts at w * stride. */

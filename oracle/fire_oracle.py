@@ -215,11 +215,28 @@ class Oracle:
         lmax = ld.max(1, keepdim=True).values
         tot = (sgn * torch.exp(ld - lmax)).sum(1)
         sign = torch.sign(tot)
-        logpsi = lmax[:, 0] + torch.log(torch.abs(tot))
+        logpsi = lmax[:, 0] + torch.log(torch.abs(tot)) + self.jastrow_cusp(R)
         return sign, logpsi, sgn, ld, phis
 
+    def jastrow_cusp(self, R):
+        """log of the cusp Jastrow factor (Methods, global electron
+        correlation): the sum over electron pairs i < j of w a^2 / (a + r_ij),
+        with (w, a) = (w_par, a_par) for equal spins and (w_anti, a_anti) for
+        opposite spins; theta entry jas_cusp = (w_par, a_par, w_anti, a_anti)."""
+        R = torch.as_tensor(R, dtype=DT)
+        if "jas_cusp" not in self.p or self.n < 2:
+            return torch.zeros(R.shape[0], dtype=DT)
+        q = self.p["jas_cusp"]
+        iu = torch.triu_indices(self.n, self.n, 1)
+        rij = torch.linalg.norm(R[:, iu[0]] - R[:, iu[1]], dim=-1)           # [B, pairs]
+        nu = self.sys.n_up
+        same = (iu[0] < nu) == (iu[1] < nu)
+        w = torch.where(same, q[0], q[2])
+        a = torch.where(same, q[1], q[3])
+        return (w * a * a / (a + rij)).sum(1)
+
     def log_psi(self, R):
-        """(sign, log|psi|) for walkers R [B,n,3], psi = sum_d det Phi_d (J = 1)."""
+        """(sign, log|psi|) for walkers R [B,n,3], psi = exp(J_cusp) sum_d det Phi_d."""
         R = torch.as_tensor(R, dtype=DT)
         s, l, *_ = self.log_psi_parts(R)
         return s, l

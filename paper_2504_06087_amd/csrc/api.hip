@@ -77,7 +77,7 @@ static void build_theta(fire_handle* h) {
       {"msg_Wa", {2, D.d, D.d}}, {"msg_Wb", {2, D.d, D.d}}, {"msg_We", {2, 4, D.d}}, {"msg_b", {2, D.d}},
       {"ee_W1", {2, 4, D.h1}}, {"ee_b1", {2, D.h1}}, {"ee_W2", {2, D.h1, D.h2}}, {"ee_b2", {2, D.h2}},
       {"ee_W3", {2, D.h2, D.d}}, {"ee_Wenv", {2, D.G, D.d}}, {"ee_sig", {2, D.G}},
-      {"mlp_W", {D.L, D.d, D.d}}, {"mlp_b", {D.L, D.d}},
+      {"mlp_W", {D.L, D.d, D.d}}, {"mlp_b", {D.L, D.d}}, {"jas_cusp", {4}},
       {"orb_W_up", {D.K, D.d, D.nu}}, {"orb_W_dn", {D.K, D.d, D.nd}},
       {"env_pi_up", {D.K, D.nu, D.M, D.E}}, {"env_pi_dn", {D.K, D.nd, D.M, D.E}}, {"env_sigma", {D.M, D.E}},
   };
@@ -133,6 +133,7 @@ static void build_layouts(fire_handle* h) {
   L.Rn = take((size_t)D.M * 3 * 8); L.Zn = take((size_t)D.M * 8); L.ppw = take((size_t)D.M * 8);
   L.ntype = take((size_t)D.M * 4);
   L.species = take((size_t)D.M * 4);
+  L.jas = take(4 * 8);
   L.total = o;
 
   StateRec& S = h->st;
@@ -148,6 +149,7 @@ static void build_layouts(fire_handle* h) {
   S.dlog = take((size_t)2 * D.K * 8);
   S.lpsi = take(8);
   S.spsi = take(8);
+  S.jas = take(8);
   S.stride = o;
 }
 
@@ -263,8 +265,8 @@ fire_status fire_sizes(const fire_handle* h, int W, size_t* params_bytes, size_t
 fire_status fire_state_layout(const fire_handle* h, size_t* offsets, size_t* stride) {
   if (!h || !offsets || !stride) return FIRE_ERR_ARG;
   const StateRec& S = h->st;
-  size_t o[10] = {S.h0, S.proj, S.m, S.phi, S.env, S.inv, S.dsign, S.dlog, S.lpsi, S.spsi};
-  for (int k = 0; k < 10; ++k) offsets[k] = o[k];
+  size_t o[11] = {S.h0, S.proj, S.m, S.phi, S.env, S.inv, S.dsign, S.dlog, S.lpsi, S.spsi, S.jas};
+  for (int k = 0; k < 11; ++k) offsets[k] = o[k];
   *stride = S.stride;
   return FIRE_OK;
 }
@@ -299,6 +301,7 @@ fire_status fire::set_params_split(fire_handle* h, const double* shared, const d
   DO(do_copy(T, b + L.b_vg, src("glu_bv"), plain(D.d), s));
   DO(do_copy(T, b + L.b_vg + (size_t)D.d * T, src("glu_bg"), plain(D.d), s));
   DO(cp(L.b_o, "glu_bo")); DO(cp(L.mlp_b, "mlp_b"));
+  DO(do_copy(8, b + L.jas, src("jas_cusp"), plain(4), s));
   // GEMM operands Bt[N][K] (and their low bf16 parts under the hybrid precision)
   const int64_t dd = (int64_t)D.d * D.d;
   const size_t LD = L.lo_delta;

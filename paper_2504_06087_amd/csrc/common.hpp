@@ -64,6 +64,21 @@ template <typename T> FIRE_DEV void silu3(T x, T& f, T& f1, T& f2) {
   f2 = s * (T(1) - s) * (T(2) + x * (T(1) - T(2) * s));
 }
 
+// Cusp Jastrow pair term (Methods, global electron correlation):
+// u(r) = w a^2 / (a + r) with (w, a) = q[0..1] for equal spins, q[2..3] for
+// opposite spins, and its first two derivatives in r.
+FIRE_DEV double jas_u(const double* q, bool same, double r) {
+  const double w = same ? q[0] : q[2], a = same ? q[1] : q[3];
+  return w * a * a / (a + r);
+}
+FIRE_DEV void jas_u3(const double* q, bool same, double r, double& u, double& u1, double& u2) {
+  const double w = same ? q[0] : q[2], a = same ? q[1] : q[3];
+  const double t = 1.0 / (a + r), c = w * a * a;
+  u = c * t;
+  u1 = -c * t * t;
+  u2 = 2.0 * c * t * t * t;
+}
+
 // u(x) = 1 - (p+1)(p+2)/2 x^p + p(p+2) x^(p+1) - p(p+1)/2 x^(p+2) for x < 1, else 0
 template <typename T> FIRE_DEV T fcut_(T x) {
   if (!(x < T(1))) return T(0);
@@ -164,6 +179,8 @@ template <typename T> struct Net {
   const T* env_sigma;
   // molecule
   const double *Rn, *Zn, *ppw;
+  // cusp Jastrow (w_par, a_par, w_anti, a_anti), FP64
+  const double* jas;
   const int* ntype;
   // packed GEMM weights (element type set by the precision)
   const void *Wvg_t, *Wo_t, *Wproj_t, *mlp_t, *orb_t0, *orb_t1, *pi0, *pi1;

@@ -182,10 +182,11 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const doub
 }
 
 // contribution of each job: coefficient * psi'/psi with
-// psi'/psi = sum_d w_d prod_s det A_ds,  w_d = s_d e^{l_d} / psi
+// psi'/psi = e^{dJ} sum_d w_d prod_s det A_ds,  w_d = s_d e^{l_d} / sum_d s_d e^{l_d}
+// (dJ: the job's change of log J_cusp)
 __global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__ jw, const double* __restrict__ cf,
-                            const double* __restrict__ detA, const char* __restrict__ state, StateRec S,
-                            double* __restrict__ contrib) {
+                            const double* __restrict__ detA, const double* __restrict__ dj,
+                            const char* __restrict__ state, StateRec S, double* __restrict__ contrib) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J) return;
   const int w = jw[j];
@@ -199,7 +200,7 @@ __global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__
     const double sg = ds[2 * k] * ds[2 * k + 1] * sp * dA[4 * k] * dA[4 * k + 2];
     if (sg != 0.0) r += sg * exp(dl[2 * k] + dl[2 * k + 1] - lp + dA[4 * k + 1] + dA[4 * k + 3]);
   }
-  contrib[j0 + j] = cf[j] * r;
+  contrib[j0 + j] = cf[j] * r * exp(dj[j]);
 }
 
 __global__ void k_ecp_reduce(int W, const int* __restrict__ off, const double* __restrict__ contrib,
@@ -291,7 +292,8 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       jb.rexp = rexp;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, st));
       hipLaunchKernelGGL(k_ecp_ratio, dim3((J + 255) / 256), dim3(256), 0, st, D, J, j0, (const int*)jw,
-                         (const double*)cf, (const double*)(uws + U.detA), (const char*)state, S, contrib);
+                         (const double*)cf, (const double*)(uws + U.detA), (const double*)(uws + U.dj),
+                         (const char*)state, S, contrib);
       CHECK(hipGetLastError());
     }
     if (Te > 0) {

@@ -150,9 +150,29 @@ __global__ __launch_bounds__(256) void k_gj_inverse(const char* __restrict__ sta
   }
 }
 
-// Signed log-sum-exp over determinants: log|psi| = l* + log|sum_d s_d e^(l_d - l*)|.
+// log J_cusp = sum_{i<j} u(r_ij) per walker (FP64), one workgroup per walker.
+__global__ __launch_bounds__(256) void k_jastrow(const Dims D, const double* __restrict__ R,
+                                                 const double* __restrict__ q, char* __restrict__ state,
+                                                 StateRec S) {
+  __shared__ double red[16];
+  const int w = blockIdx.x, n = D.n;
+  const double* Rw = R + (int64_t)w * n * 3;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t - i * n;
+    if (j <= i) continue;
+    const double dx = Rw[3 * i] - Rw[3 * j], dy = Rw[3 * i + 1] - Rw[3 * j + 1], dz = Rw[3 * i + 2] - Rw[3 * j + 2];
+    acc += jas_u(q, (i < D.nu) == (j < D.nu), sqrt(dx * dx + dy * dy + dz * dz));
+  }
+  const double tot = block_sum<double>(acc, red);
+  if (threadIdx.x == 0) *(double*)(state + (int64_t)w * S.stride + S.jas) = tot;
+}
+
+// Signed log-sum-exp over determinants: l* + log|sum_d s_d e^(l_d - l*)|
+// (cached); the returned log|psi| adds the cached log J_cusp.
 __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds, size_t off_dl, size_t off_lp,
-                            size_t off_sp, int W, int K, double* sign, double* logpsi, int32_t* status) {
+                            size_t off_sp, size_t off_jas, int W, int K, double* sign, double* logpsi,
+                            int32_t* status) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   char* rec = state + (int64_t)w * srec;
@@ -187,7 +207,7 @@ __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds
   }
   *(double*)(rec + off_lp) = lp;
   *(double*)(rec + off_sp) = sp;
-  if (logpsi) logpsi[w] = lp;
+  if (logpsi) logpsi[w] = lp + *(const double*)(rec + off_jas);
   if (sign) sign[w] = sp;
 }
 
@@ -304,8 +324,8 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
 }
 
 template <typename T>
-hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, double* logpsi, int32_t* status,
-                        hipStream_t s) {
+hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* state, double* sign, double* logpsi,
+                        int32_t* status, hipStream_t s) {
   const Dims& D = h->D;
   const StateRec& S = h->st;
   for (int sp = 0; sp < 2; ++sp) {
@@ -323,8 +343,11 @@ hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, 
                          S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
     CHECK(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_jastrow, dim3(W), dim3(256), 0, s, D, R, (const double*)((const char*)h->params + h->pl.jas),
+                     state, S);
+  CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_logsumexp, dim3((W + 127) / 128), dim3(128), 0, s, state, S.stride, S.dsign, S.dlog, S.lpsi,
-                     S.spsi, W, D.K, sign, logpsi, status);
+                     S.spsi, S.jas, W, D.K, sign, logpsi, status);
   return hipGetLastError();
 }
 
@@ -333,15 +356,17 @@ hipError_t forward(const fire_handle* h, int W, const double* R, char* state, ch
                    double* logpsi, int32_t* status, hipStream_t s) {
   Net<T> P = make_net<T>(h);
   CHECK(embed_and_orbitals<T>(h, P, W, R, state, ws, status, s));
-  return refresh_dets<T>(h, W, state, sign, logpsi, status, s);
+  return refresh_dets<T>(h, W, R, state, sign, logpsi, status, s);
 }
 
 template hipError_t forward<double>(const fire_handle*, int, const double*, char*, char*, double*, double*,
                                     int32_t*, hipStream_t);
 template hipError_t forward<float>(const fire_handle*, int, const double*, char*, char*, double*, double*,
                                    int32_t*, hipStream_t);
-template hipError_t refresh_dets<double>(const fire_handle*, int, char*, double*, double*, int32_t*, hipStream_t);
-template hipError_t refresh_dets<float>(const fire_handle*, int, char*, double*, double*, int32_t*, hipStream_t);
+template hipError_t refresh_dets<double>(const fire_handle*, int, const double*, char*, double*, double*, int32_t*,
+                                         hipStream_t);
+template hipError_t refresh_dets<float>(const fire_handle*, int, const double*, char*, double*, double*, int32_t*,
+                                        hipStream_t);
 template hipError_t embed_and_orbitals<double>(const fire_handle*, const Net<double>&, int, const double*, char*,
                                                char*, int32_t*, hipStream_t);
 template hipError_t embed_and_orbitals<float>(const fire_handle*, const Net<float>&, int, const double*, char*,

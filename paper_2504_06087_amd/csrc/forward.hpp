@@ -25,6 +25,7 @@ template <typename T> inline Net<T> make_net(const fire_handle* h) {
   P.b_vg = t(L.b_vg); P.b_o = t(L.b_o); P.mlp_b = t(L.mlp_b); P.env_sigma = t(L.env_sigma);
   P.Rn = (const double*)(b + L.Rn); P.Zn = (const double*)(b + L.Zn); P.ppw = (const double*)(b + L.ppw);
   P.ntype = (const int*)(b + L.ntype);
+  P.jas = (const double*)(b + L.jas);
   P.Wvg_t = b + L.Wvg_t; P.Wo_t = b + L.Wo_t; P.Wproj_t = b + L.Wproj_t; P.mlp_t = b + L.mlp_t;
   P.orb_t0 = b + L.orb_t0; P.orb_t1 = b + L.orb_t1; P.pi0 = b + L.pi0; P.pi1 = b + L.pi1;
   P.Wvg_n = b + L.Wvg_n; P.Wo_n = b + L.Wo_n; P.Wproj_n = b + L.Wproj_n; P.mlp_n = b + L.mlp_n;

@@ -1075,6 +1075,35 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
   return hipSuccess;
 }
 
+// Gradient of sum_w c_w log J_cusp,w by the Jastrow parameters q = (w_par,
+// a_par, w_anti, a_anti): for u = w a^2/(a + r), du/dw = a^2/(a + r) and
+// du/da = w a (a + 2r)/(a + r)^2, summed over the pairs of each walker; one
+// workgroup per walker adds c_w times its sums into g[0..3].
+__global__ __launch_bounds__(256) void k_jas_grad(const Dims D, int W, const double* __restrict__ R,
+                                                  const double* __restrict__ q, const double* __restrict__ coeff,
+                                                  const int32_t* __restrict__ status, double* __restrict__ g) {
+  __shared__ double red[16];
+  const int w = blockIdx.x, n = D.n;
+  if (status[w] != 0 || coeff[w] == 0.0) return;
+  const double* Rw = R + (int64_t)w * n * 3;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t - i * n;
+    if (j <= i) continue;
+    const double dx = Rw[3 * i] - Rw[3 * j], dy = Rw[3 * i + 1] - Rw[3 * j + 1], dz = Rw[3 * i + 2] - Rw[3 * j + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const int o = (i < D.nu) == (j < D.nu) ? 0 : 2;
+    const double wv = q[o], a = q[o + 1], t1 = 1.0 / (a + r);
+    s[o] += a * a * t1;
+    s[o + 1] += wv * a * (a + 2.0 * r) * t1 * t1;
+  }
+  for (int k = 0; k < 4; ++k) {
+    const double v = block_sum<double>(s[k], red);
+    if (threadIdx.x == 0 && v != 0.0) atomicAdd(g + k, coeff[w] * v);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff,
                             double* grad, int32_t* status, hipStream_t st) {
@@ -1087,7 +1116,9 @@ static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state,
     const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
     CHECK(grad_chunk<T>(h, P, w0, wc, R, state, ws, coeff, grad, status, st));
   }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, coeff, (const int32_t*)status,
+                     grad + theta_offset(h, "jas_cusp"));
+  return hipGetLastError();
 }
 
 hipError_t grad_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff, double* grad,

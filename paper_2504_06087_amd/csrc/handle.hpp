@@ -38,12 +38,16 @@ struct ParamsLayout {
   size_t lo_delta;
   // molecule
   size_t Rn, Zn, ppw, ntype, species;
+  // cusp Jastrow (w_par, a_par, w_anti, a_anti), FP64
+  size_t jas;
   size_t total;
 };
 
 // Per-walker record of cached intermediates (byte offsets within a record).
 struct StateRec {
-  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi;
+  // lpsi: log|sum_d det_d| (determinants only); jas: log J_cusp, so that
+  // log|psi| = lpsi + jas
+  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi, jas;
   size_t stride;
 };
 
@@ -83,7 +87,7 @@ hipError_t forward(const fire_handle* h, int W, const double* R, char* state, ch
 
 // Full re-evaluation of Phi^-1 and determinant logs from the cached Phi.
 template <typename T>
-hipError_t refresh_dets(const fire_handle* h, int W, char* state, double* sign, double* logpsi,
+hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* state, double* sign, double* logpsi,
                         int32_t* status, hipStream_t s);
 
 inline int gemm_kind(int prec) { return prec == FIRE_FP64 ? MMA_F64 : (prec == FIRE_FP32 ? MMA_F32 : MMA_BF16); }

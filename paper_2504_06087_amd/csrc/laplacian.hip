@@ -560,11 +560,16 @@ __global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, c
   }
 }
 
-// kinetic energy per walker: -1/2 Lap psi / psi = -1/2 sum_d w_d (Lap l_d + |grad l_d|^2)
-// with w_d = s_d e^{l_d} / psi; grad log|psi| = sum_d w_d grad l_d.
+// kinetic energy per walker: with psi = e^J D, D = sum_d s_d e^{l_d},
+// -1/2 Lap psi / psi = -1/2 [sum_d w_d (Lap l_d + |grad l_d|^2)
+//                           + Lap J + |grad J|^2 + 2 grad J . g],
+// w_d = s_d e^{l_d} / D, g = sum_d w_d grad l_d; grad log|psi| = g + grad J.
+// J = sum_{i<j} u(r_ij) (cusp Jastrow): grad_i J = sum_j u'(r_ij) (r_i - r_j)/r_ij,
+// Lap_i J = sum_j (u''(r_ij) + 2 u'(r_ij)/r_ij).
 __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, const char* __restrict__ state,
                                                  StateRec S, const double* __restrict__ gd,
-                                                 const double* __restrict__ hd, double* __restrict__ kin,
+                                                 const double* __restrict__ hd, const double* __restrict__ R,
+                                                 const double* __restrict__ jasq, double* __restrict__ kin,
                                                  double* __restrict__ grad) {
   __shared__ double red[16];
   __shared__ double wd[32];
@@ -577,6 +582,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
   const int K = D.K, n = D.n, tid = threadIdx.x;
   if (tid < K) wd[tid] = ds[2 * tid] * ds[2 * tid + 1] * sp * exp(dl[2 * tid] + dl[2 * tid + 1] - lp);
   __syncthreads();
+  const double* Rw = R + w * n * 3;
   double acc = 0;
   for (int q = tid; q < 3 * n; q += blockDim.x) {
     double g = 0;
@@ -585,10 +591,32 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
       g += wd[k] * v;
       acc += wd[k] * v * v;
     }
-    if (grad) grad[w * 3 * n + q] = g;
+    const int i = q / 3, c = q - 3 * i;
+    double gj = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = Rw[3 * i] - Rw[3 * j], dy = Rw[3 * i + 1] - Rw[3 * j + 1], dz = Rw[3 * i + 2] - Rw[3 * j + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double u, u1, u2;
+      jas_u3(jasq, (i < D.nu) == (j < D.nu), r, u, u1, u2);
+      gj += u1 * (Rw[3 * i + c] - Rw[3 * j + c]) / r;
+    }
+    acc += 2.0 * gj * g + gj * gj;
+    if (grad) grad[w * 3 * n + q] = g + gj;
   }
-  for (int q = tid; q < n; q += blockDim.x)
+  for (int q = tid; q < n; q += blockDim.x) {
     for (int k = 0; k < K; ++k) acc += wd[k] * hd[((int64_t)wl * K + k) * n + q];
+    double lj = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == q) continue;
+      const double dx = Rw[3 * q] - Rw[3 * j], dy = Rw[3 * q + 1] - Rw[3 * j + 1], dz = Rw[3 * q + 2] - Rw[3 * j + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double u, u1, u2;
+      jas_u3(jasq, (q < D.nu) == (j < D.nu), r, u, u1, u2);
+      lj += u2 + 2.0 * u1 / r;
+    }
+    acc += lj;
+  }
   const double tot = block_sum<double>(acc, red);
   if (tid == 0) kin[w] = -0.5 * tot;
 }
@@ -773,7 +801,7 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
                          (const T*)dph[0], (const T*)dph[1], (const char*)state, S, gd, hd);
     CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_kinetic, dim3(Wc), dim3(256), 0, st, D, Wc, w0, (const char*)state, S, (const double*)gd,
-                       (const double*)hd, kin, grad);
+                       (const double*)hd, R, P.jas, kin, grad);
     CHECK(hipGetLastError());
   }
   return hipSuccess;

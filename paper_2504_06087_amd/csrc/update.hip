@@ -30,6 +30,7 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.rnew = take(Wl * 3 * 8);
   L.lqf = take(Wl * 8);
+  L.dj = take(Wl * 8);
   L.uidx = take(Wl * 2 * L.capmax * 4);
   L.ucnt = take(Wl * 2 * 4);
   L.off = take((Wl + 1) * 2 * 4);
@@ -101,7 +102,8 @@ FIRE_DEV double gmm_log_unnorm(double x, double y, double z, const double* Rn, c
 __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, Jobs jb, int n, int nu, int e,
                                                  double cut2, int cap0, int cap1, int capmax,
                                                  double* __restrict__ rnew, int* __restrict__ uidx,
-                                                 int* __restrict__ ucnt, int32_t* status) {
+                                                 int* __restrict__ ucnt, const double* __restrict__ jasq,
+                                                 double* __restrict__ dj, int32_t* status) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= jb.J) return;
@@ -141,6 +143,20 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
   if (lane == 0) {
     rnew[3 * j] = nx; rnew[3 * j + 1] = ny; rnew[3 * j + 2] = nz;
     if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) atomicOr(status + w, FIRE_W_NONFINITE);
+  }
+  // change of log J_cusp: sum over i != e of u(|r_e' - r_i|) - u(|r_e - r_i|)
+  {
+    double d = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      if (i == e) continue;
+      const double ix = Rw[3 * i], iy = Rw[3 * i + 1], iz = Rw[3 * i + 2];
+      const bool same = (i < nu) == (e < nu);
+      const double rn = sqrt((nx - ix) * (nx - ix) + (ny - iy) * (ny - iy) + (nz - iz) * (nz - iz));
+      const double ro = sqrt((ox - ix) * (ox - ix) + (oy - iy) * (oy - iy) + (oz - iz) * (oz - iz));
+      d += jas_u(jasq, same, rn) - jas_u(jasq, same, ro);
+    }
+    d = wave_sum(d);
+    if (lane == 0) dj[j] = d;
   }
   const int se = e < nu ? 0 : 1;
   int cnt[2] = {0, 0};
@@ -899,7 +915,8 @@ __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const 
 // accept iff u < (psi'/psi)^2, times rho(r_e)/rho(r_e') = e^lqf for a global
 // jump (lqf NULL for local moves).  Updates the determinant logs and log|psi|.
 __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, const double* __restrict__ rnew,
-                         const double* __restrict__ lqf, const double* __restrict__ unif,
+                         const double* __restrict__ lqf, const double* __restrict__ dj,
+                         const double* __restrict__ unif,
                          char* __restrict__ state, StateRec S,
                          const double* __restrict__ detA, int32_t* __restrict__ status, int* __restrict__ acc,
                          int32_t* __restrict__ n_accept) {
@@ -925,7 +942,7 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
   double lpn = 0.0;
   if (status[w] == 0 && tot != 0.0 && isfinite(tot) && isfinite(lmax)) {
     lpn = lmax + log(fabs(tot));
-    const double ratio2 = exp(2.0 * (lpn - lp) + (lqf ? lqf[w] : 0.0));
+    const double ratio2 = exp(2.0 * (lpn - lp + dj[w]) + (lqf ? lqf[w] : 0.0));
     a = unif[w] < ratio2;
   }
   acc[w] = a;
@@ -937,6 +954,7 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
     }
   *(double*)(rec + S.lpsi) = lpn;
   *(double*)(rec + S.spsi) = tot > 0 ? 1.0 : -1.0;
+  *(double*)(rec + S.jas) += dj[w];
   R[((int64_t)w * D.n + e) * 3 + 0] = rnew[3 * w];
   R[((int64_t)w * D.n + e) * 3 + 1] = rnew[3 * w + 1];
   R[((int64_t)w * D.n + e) * 3 + 2] = rnew[3 * w + 2];
@@ -1458,7 +1476,7 @@ __global__ void k_final_outputs(const Dims D, int W, const char* __restrict__ st
   if (w >= W) return;
   const char* rec = state + (int64_t)w * S.stride;
   const bool bad = status[w] != 0;
-  if (logpsi) logpsi[w] = bad ? NAN : *(const double*)(rec + S.lpsi);
+  if (logpsi) logpsi[w] = bad ? NAN : *(const double*)(rec + S.lpsi) + *(const double*)(rec + S.jas);
   if (sign) sign[w] = bad ? 0.0 : *(const double*)(rec + S.spsi);
 }
 
@@ -1494,7 +1512,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   T* envnew = (T*)(ws + L.envnew);
 
   hipLaunchKernelGGL(k_propose, dim3((W + 3) / 4), dim3(256), 0, st, R, jb, D.n, D.nu, e, D.cut * D.cut,
-                     L.capS[0], L.capS[1], L.capmax, rnew, uidx, ucnt, status);
+                     L.capS[0], L.capS[1], L.capmax, rnew, uidx, ucnt, P.jas, (double*)(ws + L.dj), status);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off, L.rowcap[0], L.rowcap[1], jb.jw,
                      status);
@@ -1643,7 +1661,8 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
   const UpdLayout L = upd_layout(h, W);
   int* acc = (int*)(ws + L.acc);
   hipLaunchKernelGGL(k_accept, dim3((W + 127) / 128), dim3(128), 0, st, D, W, e, R, (const double*)(ws + L.rnew),
-                     global ? (const double*)(ws + L.lqf) : (const double*)nullptr, unif, state, S,
+                     global ? (const double*)(ws + L.lqf) : (const double*)nullptr, (const double*)(ws + L.dj),
+                     unif, state, S,
                      (const double*)(ws + L.detA), status, acc, n_accept);
   CHECK(hipGetLastError());
   for (int s = 0; s < 2; ++s) {
@@ -1750,7 +1769,7 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
     if (refresh > 0 && (sw + 1) % refresh == 0) {
       // full re-evaluation of every cached quantity from the positions (FP64 LU)
       CHECK(embed_and_orbitals<T>(h, P, W, R, state, ws, status, st));
-      CHECK(refresh_dets<T>(h, W, state, nullptr, nullptr, status, st));
+      CHECK(refresh_dets<T>(h, W, R, state, nullptr, nullptr, status, st));
     }
   }
   hipLaunchKernelGGL(k_final_outputs, dim3((W + 127) / 128), dim3(128), 0, st, D, W, (const char*)state, h->st,

@@ -36,7 +36,7 @@ struct Jobs {
 struct UpdLayout {
   int capS[2], capmax;
   int64_t rowcap[2];
-  size_t rnew, lqf, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
+  size_t rnew, lqf, dj, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
   size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2], bbuf[2];
   size_t total;
 };

@@ -200,7 +200,7 @@ class Fire:
         P = ctypes.c_int64(0)
         _check(lib.fire_num_params(self.h, ctypes.byref(P)), "fire_num_params")
         self.P = int(P.value)
-        offs = (ctypes.c_size_t * 10)()
+        offs = (ctypes.c_size_t * 11)()
         stride = ctypes.c_size_t(0)
         _check(lib.fire_state_layout(self.h, offs, ctypes.byref(stride)), "fire_state_layout")
         self.state_offsets = list(offs)
@@ -329,15 +329,15 @@ class Fire:
     # ------------------------------------------------------------------
     def state_view(self, state, W, which: str):
         """A typed view of one cached array for all W walkers (debug/tests)."""
-        names = ["h0", "proj", "m", "phi", "env", "inv", "dsign", "dlog", "lpsi", "spsi"]
+        names = ["h0", "proj", "m", "phi", "env", "inv", "dsign", "dlog", "lpsi", "spsi", "jas"]
         k = names.index(which)
         tsz = 8 if self.precision == "fp64" else 4
         isz = 4 if self.precision == "fp32" else 8
         n, d, K = self.n, self.model.width, self.model.n_det
         ppd = self.system.n_up ** 2 + self.system.n_dn ** 2
         count = {"h0": n * d, "proj": n * 4 * d, "m": n * d, "phi": K * ppd, "env": K * ppd, "inv": K * ppd,
-                 "dsign": 2 * K, "dlog": 2 * K, "lpsi": 1, "spsi": 1}[which]
-        esz = {"inv": isz, "dsign": 8, "dlog": 8, "lpsi": 8, "spsi": 8}.get(which, tsz)
+                 "dsign": 2 * K, "dlog": 2 * K, "lpsi": 1, "spsi": 1, "jas": 1}[which]
+        esz = {"inv": isz, "dsign": 8, "dlog": 8, "lpsi": 8, "spsi": 8, "jas": 8}.get(which, tsz)
         dt = torch.float64 if esz == 8 else torch.float32
         rec = state[:W * self.state_stride].view(W, self.state_stride)
         off = self.state_offsets[k]

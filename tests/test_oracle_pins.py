@@ -612,3 +612,58 @@ def test_hydrogen_sampling_with_global_jumps():
             if blk >= 8:
                 rs.append(np.linalg.norm(R.numpy()[:, 0], axis=1).mean())
         assert abs(np.mean(rs) - 1.5) < 0.03
+
+
+# --------------------------------------------------------------------------
+# cusp Jastrow factor (Methods, global electron correlation)
+# --------------------------------------------------------------------------
+def test_jastrow_cusp_closed_form_and_cusp_conditions():
+    """log psi gains sum_{i<j} w a^2/(a + r_ij) per spin class: checked on H4
+    against the pair sum written from the positions, and the slope at
+    coalescence is -w: with w_par = -1/4, w_anti = -1/2 the Kato cusp
+    conditions d(log psi)/dr = 1/4 (equal spins) and 1/2 (opposite spins)."""
+    s, m, p, R = _orc(0, W=3)
+    o0 = Oracle(s, m, copy.deepcopy(p))
+    q = np.array([-0.25, 0.7, -0.5, 1.3])
+    p1 = copy.deepcopy(p)
+    p1["jas_cusp"] = q.copy()
+    o1 = Oracle(s, m, p1)
+    _, l0 = o0.log_psi(R)
+    _, l1 = o1.log_psi(R)
+    spin = np.arange(s.n_el) >= s.n_up
+    want = np.zeros(R.shape[0])
+    for i in range(s.n_el):
+        for j in range(i + 1, s.n_el):
+            r = np.linalg.norm(R[:, i] - R[:, j], axis=1)
+            w, a = (q[0], q[1]) if spin[i] == spin[j] else (q[2], q[3])
+            want += w * a * a / (a + r)
+    assert np.allclose((l1 - l0).numpy(), want, atol=1e-12, rtol=0)
+    # slope of J along r_12 at coalescence for a lone pair: -w
+    Rh, sp = wl.h_chain(2, spacing=1.4)
+    for (nu, nd, slope) in ((2, 0, 0.25), (1, 1, 0.5)):
+        s2 = wl.make_system("H2", Rh, sp, pseudo_c=False, n_up=nu, n_dn=nd)
+        m2 = wl.make_model(s2, width=8, mlp_layers=1, n_det=1, n_env=1, cutoff=3.0, cutoff_nuc=20.0)
+        p2 = wl.init_params(s2, m2, np.random.default_rng(0))
+        p2["jas_cusp"] = np.array([-0.25, 0.8, -0.5, 1.2])
+        o2 = Oracle(s2, m2, p2)
+        hs = 1e-7
+        x = np.zeros((2, 2, 3))
+        x[:, 0] = [0.3, -0.2, 0.1]
+        x[0, 1] = x[0, 0] + [hs, 0.0, 0.0]
+        x[1, 1] = x[1, 0] + [2 * hs, 0.0, 0.0]
+        jv = o2.jastrow_cusp(x).numpy()
+        assert abs((jv[1] - jv[0]) / hs - slope) < 1e-5
+
+
+def test_jastrow_is_symmetric_and_zero_by_default():
+    s, m, p, R = _orc(0, W=2)
+    assert np.array_equal(p["jas_cusp"], [0.0, 1.0, 0.0, 1.0])
+    o = Oracle(s, m, p)
+    assert float(o.jastrow_cusp(R).abs().max()) == 0.0
+    p1 = copy.deepcopy(p)
+    p1["jas_cusp"] = np.array([-0.3, 0.9, -0.45, 1.1])
+    o1 = Oracle(s, m, p1)
+    Rs = R.copy()
+    Rs[:, [0, 1]] = Rs[:, [1, 0]]          # same-spin swap
+    Rs[:, [2, 3]] = Rs[:, [3, 2]]
+    assert torch.allclose(o1.jastrow_cusp(R), o1.jastrow_cusp(Rs), atol=1e-14, rtol=0)

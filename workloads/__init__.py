@@ -328,6 +328,8 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
         "ee_W3": (2, h2, d), "ee_Wenv": (2, G, d), "ee_sig": (2, G),
         # embedding MLP
         "mlp_W": (L, d, d), "mlp_b": (L, d),
+        # cusp Jastrow (w_par, a_par, w_anti, a_anti)
+        "jas_cusp": (4,),
         # orbitals and envelopes
         "orb_W_up": (K, d, nu), "orb_W_dn": (K, d, nd),
         "env_pi_up": (K, nu, M, E), "env_pi_dn": (K, nd, M, E),
@@ -354,6 +356,10 @@ def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
             p[name] = np.tile((1.0 + 7.0 * np.arange(G) / (G - 1)) / model.cutoff, (2, 1))
         elif name == "ln_g":
             p[name] = np.ones(shp)
+        elif name == "jas_cusp":
+            # J = 0 by default (the hot-path reading J = 1); (-1/4, a, -1/2, a)
+            # gives the electron-electron cusp conditions
+            p[name] = np.array([0.0, 1.0, 0.0, 1.0])
         elif name == "nuc_emb":
             p[name] = rng.normal(0.0, 1.0, size=shp)
         elif name.startswith("env_pi"):
@@ -506,11 +512,21 @@ def noise_for(work: Workload, n_sweeps: int, W: Optional[int] = None, system: in
     return mcmc_noise(n_sweeps, work.systems[system].n_el, W or work.walkers, rn)
 
 
-def fd_directions(work: Workload, n_dir: int = 32):
+def fd_directions(work: Workload, n_dir: int = 32, skip=("jas_cusp",)):
+    """Seeded unit directions in parameter space, zero on the entries named
+    in skip (drawn over the remaining entries only)."""
     rf = np.random.default_rng(work.seeds[STREAM_FD])
     shapes = param_shapes(work.systems[0], work.model)
-    P = sum(int(np.prod(s)) for s in shapes.values())
-    v = rf.normal(size=(n_dir, P))
+    sizes = [(k, int(np.prod(s))) for k, s in shapes.items()]
+    P = sum(n for _, n in sizes)
+    keep = np.ones(P, bool)
+    o = 0
+    for k, n in sizes:
+        if k in skip:
+            keep[o:o + n] = False
+        o += n
+    v = np.zeros((n_dir, P))
+    v[:, keep] = rf.normal(size=(n_dir, int(keep.sum())))
     return v / np.linalg.norm(v, axis=1, keepdims=True)
 
 
