@@ -583,6 +583,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
   if (tid < K) wd[tid] = ds[2 * tid] * ds[2 * tid + 1] * sp * exp(dl[2 * tid] + dl[2 * tid + 1] - lp);
   __syncthreads();
   const double* Rw = R + w * n * 3;
+  const bool jas_on = jasq[0] != 0.0 || jasq[2] != 0.0;   // J = 0 when both weights are
   double acc = 0;
   for (int q = tid; q < 3 * n; q += blockDim.x) {
     double g = 0;
@@ -593,7 +594,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
     }
     const int i = q / 3, c = q - 3 * i;
     double gj = 0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < (jas_on ? n : 0); ++j) {
       if (j == i) continue;
       const double dx = Rw[3 * i] - Rw[3 * j], dy = Rw[3 * i + 1] - Rw[3 * j + 1], dz = Rw[3 * i + 2] - Rw[3 * j + 2];
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
   for (int q = tid; q < n; q += blockDim.x) {
     for (int k = 0; k < K; ++k) acc += wd[k] * hd[((int64_t)wl * K + k) * n + q];
     double lj = 0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = 0; j < (jas_on ? n : 0); ++j) {
       if (j == q) continue;
       const double dx = Rw[3 * q] - Rw[3 * j], dy = Rw[3 * q + 1] - Rw[3 * j + 1], dz = Rw[3 * q + 2] - Rw[3 * j + 2];
       const double r = sqrt(dx * dx + dy * dy + dz * dz);

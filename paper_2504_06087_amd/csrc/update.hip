@@ -145,7 +145,10 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
     if (!isfinite(nx) || !isfinite(ny) || !isfinite(nz)) atomicOr(status + w, FIRE_W_NONFINITE);
   }
   // change of log J_cusp: sum over i != e of u(|r_e' - r_i|) - u(|r_e - r_i|)
-  {
+  // (zero without the factor: both weights zero)
+  if (jasq[0] == 0.0 && jasq[2] == 0.0) {
+    if (lane == 0) dj[j] = 0.0;
+  } else {
     double d = 0.0;
     for (int i = lane; i < n; i += 64) {
       if (i == e) continue;
