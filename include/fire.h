@@ -157,11 +157,14 @@ fire_status fire_state_layout(const fire_handle* h, size_t* offsets, size_t* str
  * unchanged for every later call on this handle. */
 fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t stream);
 
-/* log|psi| and its sign for W walkers (Methods, eq. wf with J = 1:
- * psi = sum_d det Phi_d^up det Phi_d^down), and the cached intermediates the
- * update, Laplacian and adjoint paths reuse (embeddings h0, projections,
- * messages, Phi, Phi^-1, per-determinant sign and log|det|) written to
- * state.  R: [W][n][3]; sign, logpsi: [W]; status: [W]. */
+/* log|psi| and its sign for W walkers (Methods, eq. wf with the cusp
+ * Jastrow factor as J: psi = exp(J_cusp) sum_d det Phi_d^up det Phi_d^down,
+ * J_cusp = sum_{i<j} w a^2/(a + r_ij) with theta entry jas_cusp = (w_par,
+ * a_par, w_anti, a_anti); J_cusp = 0 for zero weights), and the cached
+ * intermediates the update, Laplacian and adjoint paths reuse (embeddings
+ * h0, projections, messages, Phi, Phi^-1, per-determinant sign and log|det|,
+ * log J_cusp) written to state.  R: [W][n][3]; sign, logpsi: [W];
+ * status: [W]. */
 fire_status fire_eval_logpsi(fire_handle* h, int W, const double* R, void* state, void* ws,
                              double* sign, double* logpsi, int32_t* status, hipStream_t stream);
 

@@ -20,7 +20,8 @@ spin-block determinants; exp(-sigma |r - R|) envelopes with exponents shared
 over orbitals; SiLU activations; a LLaMA-style GLU W_o[(LN(s)W_v+b_v) *
 SiLU(LN(s)W_g+b_g)] + b_o; filters 4 -> 16 -> 8 -> d with a 32-Gaussian radial
 part; the polynomial cutoff with p = 6; separate parallel/antiparallel
-message weights; no Jastrow factor (J = 1); semilocal l = 0, 1 pseudopotential
+message weights; of the Jastrow terms only the cusp factor, exp of a pair sum
+with (w, a) per spin class (zero weights by default); semilocal l = 0, 1 pseudopotential
 channels with an equal-weight angular rule per species (12-point icosahedron
 unless the system names 4 or 6 points).
 

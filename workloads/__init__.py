@@ -357,7 +357,7 @@ def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
         elif name == "ln_g":
             p[name] = np.ones(shp)
         elif name == "jas_cusp":
-            # J = 0 by default (the hot-path reading J = 1); (-1/4, a, -1/2, a)
+            # zero weights by default: J_cusp = 1; (-1/4, a, -1/2, a)
             # gives the electron-electron cusp conditions
             p[name] = np.array([0.0, 1.0, 0.0, 1.0])
         elif name == "nuc_emb":
