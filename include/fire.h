@@ -194,6 +194,18 @@ fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void*
  * when no sweep is global; global_step > 0 then.  Every other argument,
  * the update machinery and the refresh are those of fire_mcmc_sweep.
  * FIRE_ERR_ARG for a kind other than 0/1 or a missing pick/scale. */
+/* Step-size adaptation of the local moves (Methods, improved Monte Carlo
+ * sampling: the proposal scale is adjusted on the fly towards a target
+ * acceptance ratio; 50 % in the paper's hyperparameters).  With the
+ * acceptance ratio a = accepted / proposed of the last sweeps,
+ * *new_step = step * exp(gain * (a - target)), limited to [step/2, 2 step]:
+ * a fixed point at a = target, larger steps when too many moves are
+ * accepted.  Host arithmetic only (no device work); FIRE_ERR_ARG for a
+ * non-positive step, proposed <= 0, accepted outside [0, proposed], a
+ * target outside (0, 1) or a negative gain. */
+fire_status fire_adapt_step(double step, int64_t accepted, int64_t proposed, double target, double gain,
+                            double* new_step);
+
 fire_status fire_mcmc_sweep_mixed(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
                                   double step, double global_step, const int32_t* kinds,
                                   const double* noise, const double* unif, const double* pick,

@@ -383,6 +383,18 @@ fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void*
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
+fire_status fire_adapt_step(double step, int64_t accepted, int64_t proposed, double target, double gain,
+                            double* new_step) {
+  if (!new_step || !(step > 0) || !isfinite(step) || proposed <= 0 || accepted < 0 || accepted > proposed ||
+      !(target > 0 && target < 1) || !(gain >= 0) || !isfinite(gain))
+    return FIRE_ERR_ARG;
+  const double a = (double)accepted / (double)proposed;
+  double f = exp(gain * (a - target));
+  f = f < 0.5 ? 0.5 : (f > 2.0 ? 2.0 : f);
+  *new_step = step * f;
+  return FIRE_OK;
+}
+
 fire_status fire_mcmc_sweep_mixed(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
                                   double step, double global_step, const int32_t* kinds, const double* noise,
                                   const double* unif, const double* pick, int32_t* n_accept, double* logpsi,

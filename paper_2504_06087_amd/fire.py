@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
 W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
 
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
-           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed",
+           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
     lib.fire_set_params.argtypes = [P, V, V, V]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
+    lib.fire_adapt_step.argtypes = [D, ctypes.c_int64, ctypes.c_int64, D, D, ctypes.POINTER(ctypes.c_double)]
     lib.fire_mcmc_sweep_mixed.argtypes = [P, I, V, V, V, I, D, D, ctypes.POINTER(ctypes.c_int32), V, V, V, V, V, V,
                                           V, V]
     lib.fire_local_energy.argtypes = [P, I, V, V, V, V, V, V, V, V, V]
@@ -119,6 +120,15 @@ def load() -> ctypes.CDLL:
 
 class FireError(RuntimeError):
     pass
+
+
+def adapt_step(step: float, accepted: int, proposed: int, target: float = 0.5, gain: float = 1.0) -> float:
+    """New local-move scale from the acceptance of the last sweeps
+    (fire_adapt_step)."""
+    out = ctypes.c_double()
+    _check(load().fire_adapt_step(float(step), int(accepted), int(proposed), float(target), float(gain),
+                                  ctypes.byref(out)), "fire_adapt_step")
+    return out.value
 
 
 def _check(code: int, what: str):

@@ -234,3 +234,28 @@ def test_mixed_sweep_argument_errors(lib):
     n2, _, l2, _ = F.mcmc_sweep(R2, st2, ws2, 2, 0.2, dev(xi), dev(u))
     torch.cuda.synchronize()
     assert torch.equal(n1, n2) and torch.equal(l1, l2) and torch.equal(Rd, R2)
+
+
+def test_step_adaptation_reaches_half_acceptance(lib):
+    """Sweeps one at a time with fire_adapt_step between them: the
+    acceptance of the last sweeps settles near the 50 % target."""
+    from paper_2504_06087_amd import fire
+    log("case: H4 fp64 W=256, 40 sweeps with step adaptation towards 50 %")
+    F, O, s, m, p, R, state, ws = setup(0, 256, "fp64")
+    rng = np.random.default_rng(77)
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    step, rates = 0.05, []
+    nacc = torch.zeros(256, dtype=torch.int32, device="cuda")
+    for t in range(40):
+        xi, u = wl.mcmc_noise(1, s.n_el, 256, rng)
+        before = int(nacc.sum())
+        _, _, _, st = F.mcmc_sweep(Rd, state, ws, 1, step, dev(xi), dev(u), nacc)
+        torch.cuda.synchronize()
+        acc = int(nacc.sum()) - before
+        rates.append(acc / (256 * s.n_el))
+        step = fire.adapt_step(step, acc, 256 * s.n_el, 0.5, 1.0)
+    assert (st.cpu().numpy() == 0).all()
+    late = float(np.mean(rates[-10:]))
+    log(f"first rate {rates[0]:.2f}, last ten {late:.3f}, final step {step:.3f}")
+    assert rates[0] > 0.8 and abs(late - 0.5) < 0.06
