@@ -3,6 +3,8 @@
 // message-passing step, the embedding MLP, envelopes and orbitals, FP64
 // Gauss-Jordan inversion with partial pivoting and the signed log-sum-exp
 // over determinants.
+#include <type_traits>
+
 #include "forward.hpp"
 #include "linalg.hpp"
 #include "embed_kernels.hpp"
@@ -101,40 +103,140 @@ __global__ __launch_bounds__(256) void k_msg(Net<T> P, const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// a7: in-place Gauss-Jordan inversion with partial (row) pivoting in FP64.
-// One workgroup per (walker, determinant) block of one spin.  Produces
-// Phi^-1 (TI), the sign and log|det| of the block.  det and inverse come
-// from the same elimination.
+// a7: in-place Gauss-Jordan inversion with partial (row) pivoting in FP64,
+// one workgroup per (walker, determinant) block of one spin: Phi^-1 (stored
+// as G = Phi^-T in TI), the sign and log|det| of the block from the same
+// elimination.
 // ---------------------------------------------------------------------------
-constexpr int LU_MAXN = 128;
-
-template <typename TP, typename TI>
-__global__ __launch_bounds__(256) void k_gj_inverse(const char* __restrict__ state_in, char* __restrict__ state_out,
-                                                    size_t srec, size_t off_phi, size_t off_inv, size_t off_ds,
-                                                    size_t off_dl, Dims D, int spin, int32_t* status) {
-  extern __shared__ double lds[];
+// a7 with the block in registers: the N x N block (N <= 16 NB) is spread
+// over a 16 x 16 grid of threads, thread (ty, tx) holding rows ty + 16 a and
+// columns tx + 16 b (a, b < NB).  The elimination is gj_block's (partial
+// pivoting by row swaps, multipliers by division, the inverse formed in
+// place, columns permuted back at the end); per step only the pivot column,
+// the pivot row and the row it swaps with pass through LDS, and every
+// element update is a register FMA.
+template <typename TP, typename TI, int NB>
+__global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__ state_in, char* __restrict__ state_out,
+                                                        size_t srec, size_t off_phi, size_t off_inv, size_t off_ds,
+                                                        size_t off_dl, Dims D, int spin, int32_t* status) {
+  __shared__ double prow[16 * NB], krow[16 * NB], pcol[16 * NB];
+  __shared__ double cbest[16];
+  __shared__ int cidx[16], perm[16 * NB], icol[16 * NB];
+  __shared__ int pvt;
   const int N = spin == 0 ? D.nu : D.nd;
-  const int LD = N + 1;
-  double* A = lds;                 // [N][LD]
-  double* f = lds + N * LD;        // [N]
-  __shared__ int perm[LU_MAXN];
-  __shared__ double sc[2];
-  __shared__ int fl[2];
   const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
   const int64_t boff = det * phi_per_det(D) + phi_block_off(D, spin);
   const TP* phi = (const TP*)(state_in + (int64_t)w * srec + off_phi) + boff;
   TI* inv = (TI*)(state_out + (int64_t)w * srec + off_inv) + boff;
   double* dsign = (double*)(state_out + (int64_t)w * srec + off_ds);
   double* dlog = (double*)(state_out + (int64_t)w * srec + off_dl);
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   if (N == 0) {
     if (tid == 0) { dsign[det * 2 + spin] = 1.0; dlog[det * 2 + spin] = 0.0; }
     return;
   }
-  for (int q = tid; q < N * N; q += nt) A[(q / N) * LD + q % N] = (double)phi[q];
-  __syncthreads();
-  gj_block(A, N, LD, f, perm, sc, fl, true);
-  if (fl[1]) {
+  double A[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ty + 16 * a, j = tx + 16 * b;
+      A[a][b] = (i < N && j < N) ? (double)phi[(int64_t)i * N + j] : 0.0;
+    }
+  double lsum = 0.0, sgn = 1.0;
+  bool sing = false;
+  for (int k = 0; k < N; ++k) {
+    const int kb = k >> 4, k16 = k & 15;
+    // column k of my rows (meaningful for tx == k16)
+    double ck[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      double c = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) c = b == kb ? A[a][b] : c;
+      ck[a] = c;
+    }
+    if (tx == k16) {
+      double best = -1.0;
+      int bi = k;
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int i = ty + 16 * a;
+        const double v = fabs(ck[a]);
+        if (i >= k && i < N && v > best) { best = v; bi = i; }
+      }
+      cbest[ty] = best;
+      cidx[ty] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int t = 0; t < 16; ++t)
+        if (cbest[t] > best || (cbest[t] == best && cidx[t] < bi)) { best = cbest[t]; bi = cidx[t]; }
+      pvt = bi;
+      perm[k] = bi;
+    }
+    __syncthreads();
+    const int p = pvt;
+    const int pb = p >> 4, p16 = p & 15;
+    // the old rows k and p, and column k after the swap
+    if (ty == k16 || ty == p16) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = tx + 16 * b;
+        double rk = 0.0, rp = 0.0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          rk = a == kb ? A[a][b] : rk;
+          rp = a == pb ? A[a][b] : rp;
+        }
+        if (j < N) {
+          if (ty == k16) krow[j] = rk;
+          if (ty == p16) prow[j] = rp;
+        }
+      }
+    }
+    if (tx == k16) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const int i = ty + 16 * a;
+        if (i < N) pcol[i == k ? p : (i == p ? k : i)] = ck[a];
+      }
+    }
+    __syncthreads();
+    const double piv = prow[k];
+    if (piv == 0.0 || !isfinite(piv)) { sing = true; break; }
+    if (tid == 0) {
+      lsum += log(fabs(piv));
+      sgn *= (piv < 0 ? -1.0 : 1.0) * (p != k ? -1.0 : 1.0);
+    }
+    double pj[NB], kj[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = tx + 16 * b;
+      pj[b] = j < N ? prow[j] : 0.0;
+      kj[b] = j < N ? krow[j] : 0.0;
+    }
+    const double ip = 1.0 / piv;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const int i = ty + 16 * a;
+      const bool isk = i == k, isp = i == p && p != k;
+      const double f = (isk || i >= N) ? 0.0 : pcol[i] / piv;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = tx + 16 * b;
+        const double old = isk ? pj[b] : (isp ? kj[b] : A[a][b]);
+        double v;
+        if (isk) v = j == k ? ip : old / piv;
+        else v = j == k ? -f : old - f * pj[b];
+        A[a][b] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (sing) {
     if (tid == 0) {
       atomicOr(status + w, FIRE_W_SINGULAR);
       dsign[det * 2 + spin] = 0.0;
@@ -142,12 +244,29 @@ __global__ __launch_bounds__(256) void k_gj_inverse(const char* __restrict__ sta
     }
     return;
   }
-  // store G = Phi^-T: G[k][l] = (Phi^-1)[l][k]
-  for (int q = tid; q < N * N; q += nt) inv[q] = (TI)A[(q % N) * LD + q / N];
+  // columns permuted back: after undoing the swaps in reverse order, column
+  // c holds column col[c] of A; G[c][l] = (Phi^-1)[l][c] = A[l][col[c]]
   if (tid == 0) {
-    dsign[det * 2 + spin] = sc[0];
-    dlog[det * 2 + spin] = sc[1];
+    for (int c = 0; c < N; ++c) icol[c] = c;   // col[] built in place
+    for (int k = N - 1; k >= 0; --k) {
+      const int q = perm[k];
+      const int t = icol[k];
+      icol[k] = icol[q];
+      icol[q] = t;
+    }
+    // invert: icol holds col[]; turn it into its inverse in perm[]
+    for (int c = 0; c < N; ++c) perm[icol[c]] = c;
+    dsign[det * 2 + spin] = sgn;
+    dlog[det * 2 + spin] = lsum;
   }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int l = ty + 16 * a, m = tx + 16 * b;
+      if (l < N && m < N) inv[(int64_t)perm[m] * N + l] = (TI)A[a][b];
+    }
 }
 
 // log J_cusp = sum_{i<j} u(r_ij) per walker (FP64), one workgroup per walker.
@@ -330,17 +449,27 @@ hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* stat
   const StateRec& S = h->st;
   for (int sp = 0; sp < 2; ++sp) {
     const int N = D.nsig(sp);
-    size_t lds = ((size_t)N * (N + 1) + N) * sizeof(double);
-    CHECK(hipFuncSetAttribute((const void*)k_gj_inverse<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-    CHECK(hipFuncSetAttribute((const void*)k_gj_inverse<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-    if (h->isize == 8)
-      hipLaunchKernelGGL((k_gj_inverse<T, double>), dim3(W * D.K), dim3(256), lds, s, state, state, S.stride,
-                         S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
-    else
-      hipLaunchKernelGGL((k_gj_inverse<T, float>), dim3(W * D.K), dim3(256), lds, s, state, state, S.stride,
-                         S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
+    const int nb = (N + 15) / 16;
+    const dim3 g((unsigned)(W * D.K)), blk(256);
+    auto go = [&](auto nbc) {
+      constexpr int NBC = decltype(nbc)::value;
+      if (h->isize == 8)
+        hipLaunchKernelGGL((k_gj_inverse_reg<T, double, NBC>), g, blk, 0, s, state, state, S.stride, S.phi, S.inv,
+                           S.dsign, S.dlog, D, sp, status);
+      else
+        hipLaunchKernelGGL((k_gj_inverse_reg<T, float, NBC>), g, blk, 0, s, state, state, S.stride, S.phi, S.inv,
+                           S.dsign, S.dlog, D, sp, status);
+    };
+    switch (nb) {
+      case 0: case 1: go(std::integral_constant<int, 1>{}); break;
+      case 2: go(std::integral_constant<int, 2>{}); break;
+      case 3: go(std::integral_constant<int, 3>{}); break;
+      case 4: go(std::integral_constant<int, 4>{}); break;
+      case 5: go(std::integral_constant<int, 5>{}); break;
+      case 6: go(std::integral_constant<int, 6>{}); break;
+      case 7: go(std::integral_constant<int, 7>{}); break;
+      default: go(std::integral_constant<int, 8>{}); break;
+    }
     CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_jastrow, dim3(W), dim3(256), 0, s, D, R, (const double*)((const char*)h->params + h->pl.jas),
