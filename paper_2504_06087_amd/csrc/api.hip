@@ -224,6 +224,12 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
 }
 
 fire_status fire_destroy(fire_handle* h) {
+  if (h && h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h && h->side_fork) (void)hipEventDestroy(h->side_fork);
+  if (h && h->side_join) (void)hipEventDestroy(h->side_join);
   delete h;
   return FIRE_OK;
 }

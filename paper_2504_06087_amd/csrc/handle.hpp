@@ -68,6 +68,11 @@ struct fire_handle {
   void* params;                 // device params buffer (set by fire_set_params)
   size_t lap_budget;            // workspace bytes the Laplacian's walker chunks may use
   const double* theta_dev;      // theta passed to fire_set_params
+  // second stream of the local energy: the kinetic energy runs on it beside
+  // the pseudopotential on the caller's stream (created on first use, default
+  // priority), with the events that order it against the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
 };
 
 namespace fire {

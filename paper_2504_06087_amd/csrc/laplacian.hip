@@ -16,6 +16,8 @@
 #include "embed_kernels.hpp"
 #include "jets.hpp"
 
+#include <mutex>
+
 namespace fire {
 
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
@@ -812,6 +814,11 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
 // registers on MFMA tiles and needs none)
 size_t lap_lds_needed(const fire_handle* h) { return 0; }
 
+static std::mutex& side_mutex() {
+  static std::mutex m;
+  return m;
+}
+
 template <typename T>
 static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char* state, char* ws,
                                     const double* quad_rot, double* e_loc, double* parts, double* grad,
@@ -819,21 +826,43 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
   const Dims& D = h->D;
   Net<T> P = make_net<T>(h);
   const LapLayout L = lap_layout(h, W);
-  // per-walker results first, then one region shared by the Laplacian chunks
-  // and (afterwards) the pseudopotential jobs
+  // per-walker results first, then the region of the Laplacian chunks, then
+  // that of the pseudopotential jobs
   double* kin = (double*)ws;
   double* pot = kin + align_up((size_t)W * 8) / 8;
   double* vnl = pot + align_up((size_t)W * 3 * 8) / 8;
   char* region = (char*)(vnl + align_up((size_t)W * 8) / 8);
+  char* region_ecp = region + align_up(L.total);
   CHECK(fill_i32(status, W, 0, st));
+  const bool has_ecp = !h->ecp.empty();
+  // With a pseudopotential, the kinetic energy and the potential run on the
+  // handle's second stream, beside the quadrature jobs on the caller's stream:
+  // the two read the same state, write disjoint outputs and workspace regions,
+  // and meet only in the status flags (atomic OR).  The fork (record on st,
+  // wait on the side stream) is atomic under a lock, so concurrent calls
+  // cannot swap their fork points; a later record of the join event lies
+  // later on the serial side stream, so waiting on it is never too early.
+  hipStream_t ks = st;
+  if (has_ecp) {
+    std::lock_guard<std::mutex> lock(side_mutex());
+    if (!h->side) CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    if (!h->side_fork) CHECK(hipEventCreateWithFlags(&h->side_fork, hipEventDisableTiming));
+    if (!h->side_join) CHECK(hipEventCreateWithFlags(&h->side_join, hipEventDisableTiming));
+    CHECK(hipEventRecord(h->side_fork, st));
+    CHECK(hipStreamWaitEvent(h->side, h->side_fork, 0));
+    ks = h->side;
+  }
   for (int w0 = 0; w0 < W; w0 += L.Wc) {
     const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
-    CHECK(kinetic_chunk<T>(h, P, w0, wc, R, state, region, kin, grad, status, st));
+    CHECK(kinetic_chunk<T>(h, P, w0, wc, R, state, region, kin, grad, status, ks));
   }
-  hipLaunchKernelGGL(k_potential, dim3(W), dim3(256), 0, st, D, W, R, P.Rn, P.Zn, P.ppw, pot);
+  hipLaunchKernelGGL(k_potential, dim3(W), dim3(256), 0, ks, D, W, R, P.Rn, P.Zn, P.ppw, pot);
   CHECK(hipGetLastError());
-  bool has_ecp = !h->ecp.empty();
-  if (has_ecp) CHECK(ecp_into(h, W, R, state, region, quad_rot, vnl, status, st));
+  if (has_ecp) {
+    CHECK(hipEventRecord(h->side_join, ks));
+    CHECK(ecp_into(h, W, R, state, region_ecp, quad_rot, vnl, status, st));
+    CHECK(hipStreamWaitEvent(st, h->side_join, 0));
+  }
   hipLaunchKernelGGL(k_local_energy_sum, dim3((W + 127) / 128), dim3(128), 0, st, W, (const double*)kin,
                      (const double*)pot, has_ecp ? (const double*)vnl : nullptr, (const int32_t*)status, e_loc, parts);
   return hipGetLastError();
@@ -841,8 +870,8 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
 
 size_t lap_ws_bytes(const fire_handle* h, int W) {
   const LapLayout L = lap_layout(h, W);
-  const size_t reg = L.total > ecp_ws_bytes(h, W) ? L.total : ecp_ws_bytes(h, W);
-  return align_up((size_t)W * 8) + align_up((size_t)W * 3 * 8) + align_up((size_t)W * 8) + align_up(reg);
+  const size_t reg = align_up(L.total) + align_up(ecp_ws_bytes(h, W));
+  return align_up((size_t)W * 8) + align_up((size_t)W * 3 * 8) + align_up((size_t)W * 8) + reg;
 }
 
 hipError_t local_energy_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,
