@@ -228,6 +228,11 @@ fire_status fire_destroy(fire_handle* h) {
     (void)hipStreamSynchronize(h->side);
     (void)hipStreamDestroy(h->side);
   }
+  if (h && h->side_ecp) {
+    (void)hipStreamSynchronize(h->side_ecp);
+    (void)hipStreamDestroy(h->side_ecp);
+  }
+  if (h && h->side_ecp_join) (void)hipEventDestroy(h->side_ecp_join);
   if (h && h->side_fork) (void)hipEventDestroy(h->side_fork);
   if (h && h->side_join) (void)hipEventDestroy(h->side_join);
   delete h;

@@ -5,6 +5,7 @@
 // with the N_q vertices e_q of the species' rule (4 tetrahedron, 6
 // octahedron, 12 icosahedron).  Every ratio is one single-electron update
 // (neighbour recompute + det A), never a full re-evaluation.
+#include <mutex>
 #include <vector>
 
 #include "laplacian.hpp"
@@ -217,32 +218,52 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
   if (i < n) p[i] = v;
 }
 
+std::mutex& handle_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+__global__ void k_add_f64(double* p, const double* q, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] += q[i];
+}
+
+// Shared job counts, then two lanes of job buffers: electrons alternate
+// between the lanes, which run on two streams.
 struct EcpLayout {
   int Jc;
-  size_t cnt, off, tot, jw, rexp, cf, contrib, upd;
+  size_t cnt, off, tot;
+  size_t lane[2];                                  // lane bases
+  size_t jw, rexp, cf, contrib, vnl, upd;          // offsets within a lane
   size_t total;
 };
 
 static EcpLayout ecp_layout(const fire_handle* h, int W) {
   EcpLayout L{};
   const Dims& D = h->D;
-  // jobs per chunk: about 12 jobs per electron and walker, at most 32760
-  // (the update segments reserve 32 rows per job and spin; at 180 electrons
-  // and 16 determinants a chunk of 32760 jobs takes ~31 GB of workspace)
+  // jobs per chunk and lane: about 12 jobs per electron and walker, at most
+  // 16380, a multiple of 4, 6 and 12 (the update segments reserve 32 rows per
+  // job and spin; at 180 electrons and 16 determinants a lane of 16380 jobs
+  // takes ~15 GB of workspace)
   int64_t want = (int64_t)W * 12;
-  L.Jc = (int)(want < 32760 ? (want > 264 ? want : 264) : 32760);   // a multiple of 12
+  L.Jc = (int)(want < 16380 ? (want > 264 ? want : 264) : 16380);
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.cnt = take((size_t)D.n * W * 4);
   L.off = take((size_t)D.n * (W + 1) * 4);
   L.tot = take((size_t)D.n * 4);
-  L.jw = take((size_t)L.Jc * 4);
-  L.rexp = take((size_t)L.Jc * 3 * 8);
-  L.cf = take((size_t)L.Jc * 8);
-  L.contrib = take((size_t)W * ECP_PMAX * NQ * 8);
-  L.upd = o;
-  o += upd_layout(h, L.Jc, false).total;
-  L.total = align_up(o);
+  size_t q = 0;
+  auto ltake = [&](size_t b) { size_t r = q; q = align_up(q + b); return r; };
+  L.jw = ltake((size_t)L.Jc * 4);
+  L.rexp = ltake((size_t)L.Jc * 3 * 8);
+  L.cf = ltake((size_t)L.Jc * 8);
+  L.contrib = ltake((size_t)W * ECP_PMAX * NQ * 8);
+  L.vnl = ltake((size_t)W * 8);
+  L.upd = q;
+  q = align_up(q + upd_layout(h, L.Jc, false).total);
+  L.lane[0] = o;
+  L.lane[1] = o + q;
+  L.total = align_up(o + 2 * q);
   return L;
 }
 
@@ -260,14 +281,15 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   int* cnt = (int*)(ws + L.cnt);
   int* off = (int*)(ws + L.off);
   int* tot = (int*)(ws + L.tot);
-  int* jw = (int*)(ws + L.jw);
-  double* rexp = (double*)(ws + L.rexp);
-  double* cf = (double*)(ws + L.cf);
-  double* contrib = (double*)(ws + L.contrib);
-  char* uws = ws + L.upd;
   const int* sp_dev = (const int*)((const char*)h->params + h->pl.species);
-  hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, st, vnl, (int64_t)W, 0.0);
-  CHECK(hipGetLastError());
+  // lane 0 accumulates into vnl on the caller's stream, lane 1 into its own
+  // sum on the handle's pseudopotential stream; both are cleared here, before
+  // the host waits on st, so lane 1 needs no event to start after them
+  double* vl[2] = {vnl, (double*)(ws + L.lane[1] + L.vnl)};
+  for (int l = 0; l < 2; ++l) {
+    hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, st, vl[l], (int64_t)W, 0.0);
+    CHECK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_ecp_count, dim3((unsigned)(((int64_t)W * D.n + 255) / 256)), dim3(256), 0, st, D, W, R, P.Rn,
                      sp_dev, tb, cnt, status);
   CHECK(hipGetLastError());
@@ -276,12 +298,28 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   std::vector<int> htot(D.n);
   CHECK(hipMemcpyAsync(htot.data(), tot, (size_t)D.n * 4, hipMemcpyDeviceToHost, st));
   CHECK(hipStreamSynchronize(st));
+  hipStream_t ls[2] = {st, st};
+  {
+    std::lock_guard<std::mutex> lock(handle_mutex());
+    if (!h->side_ecp) CHECK(hipStreamCreateWithFlags(&h->side_ecp, hipStreamNonBlocking));
+    if (!h->side_ecp_join) CHECK(hipEventCreateWithFlags(&h->side_ecp_join, hipEventDisableTiming));
+    ls[1] = h->side_ecp;
+  }
   for (int e = 0; e < D.n; ++e) {
     const int Te = htot[e];
+    if (Te == 0) continue;
+    const int ln = e & 1;
+    hipStream_t ss = ls[ln];
+    char* lb = ws + L.lane[ln];
+    int* jw = (int*)(lb + L.jw);
+    double* rexp = (double*)(lb + L.rexp);
+    double* cf = (double*)(lb + L.cf);
+    double* contrib = (double*)(lb + L.contrib);
+    char* uws = lb + L.upd;
     const int* offe = off + (int64_t)e * (W + 1);
     for (int j0 = 0; j0 < Te; j0 += L.Jc) {
       const int J = Te - j0 < L.Jc ? Te - j0 : L.Jc;
-      hipLaunchKernelGGL(k_ecp_jobs, dim3((J + 255) / 256), dim3(256), 0, st, D, W, e, j0, J, R, P.Rn, sp_dev, tb,
+      hipLaunchKernelGGL(k_ecp_jobs, dim3((J + 255) / 256), dim3(256), 0, ss, D, W, e, j0, J, R, P.Rn, sp_dev, tb,
                          quad_rot, offe, jw, rexp, cf);
       CHECK(hipGetLastError());
       Jobs jb{};
@@ -290,18 +328,21 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       jb.group = tb.nq[0];   // the jobs of one (electron, pseudo-atom) pair are consecutive
       jb.jw = jw;
       jb.rexp = rexp;
-      CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, st));
-      hipLaunchKernelGGL(k_ecp_ratio, dim3((J + 255) / 256), dim3(256), 0, st, D, J, j0, (const int*)jw,
+      CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, ss));
+      hipLaunchKernelGGL(k_ecp_ratio, dim3((J + 255) / 256), dim3(256), 0, ss, D, J, j0, (const int*)jw,
                          (const double*)cf, (const double*)(uws + U.detA), (const double*)(uws + U.dj),
                          (const char*)state, S, contrib);
       CHECK(hipGetLastError());
     }
-    if (Te > 0) {
-      hipLaunchKernelGGL(k_ecp_reduce, dim3((W + 255) / 256), dim3(256), 0, st, W, offe, (const double*)contrib, vnl);
-      CHECK(hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_ecp_reduce, dim3((W + 255) / 256), dim3(256), 0, ss, W, offe, (const double*)contrib, vl[ln]);
+    CHECK(hipGetLastError());
   }
-  return hipSuccess;
+  // join lane 1 (a later record of the join event lies later on the serial
+  // lane-1 stream, so the wait is never too early) and add its sum
+  CHECK(hipEventRecord(h->side_ecp_join, ls[1]));
+  CHECK(hipStreamWaitEvent(st, h->side_ecp_join, 0));
+  hipLaunchKernelGGL(k_add_f64, dim3((W + 255) / 256), dim3(256), 0, st, vnl, (const double*)vl[1], (int64_t)W);
+  return hipGetLastError();
 }
 
 hipError_t ecp_into(const fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,

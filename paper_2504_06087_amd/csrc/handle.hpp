@@ -1,5 +1,6 @@
 // Internal handle, packed-parameter layout, state and workspace layouts.
 #pragma once
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,10 @@ struct fire_handle {
   // priority), with the events that order it against the caller's stream
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
+  // second stream of the pseudopotential (every other electron's quadrature
+  // jobs) and its join event; created on first use under handle_mutex()
+  mutable hipStream_t side_ecp = nullptr;
+  mutable hipEvent_t side_ecp_join = nullptr;
 };
 
 namespace fire {
@@ -110,6 +115,10 @@ inline hipError_t gemm_site(const fire_handle* h, int site, GemmArgs g, hipStrea
   }
   return gemm(kind, g, s);
 }
+
+// Guards the lazy creation of the handles' side streams and the fork of
+// the local energy onto them.
+std::mutex& handle_mutex();
 
 static inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

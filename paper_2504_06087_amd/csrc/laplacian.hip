@@ -814,11 +814,6 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
 // registers on MFMA tiles and needs none)
 size_t lap_lds_needed(const fire_handle* h) { return 0; }
 
-static std::mutex& side_mutex() {
-  static std::mutex m;
-  return m;
-}
-
 template <typename T>
 static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char* state, char* ws,
                                     const double* quad_rot, double* e_loc, double* parts, double* grad,
@@ -844,7 +839,7 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
   // later on the serial side stream, so waiting on it is never too early.
   hipStream_t ks = st;
   if (has_ecp) {
-    std::lock_guard<std::mutex> lock(side_mutex());
+    std::lock_guard<std::mutex> lock(handle_mutex());
     if (!h->side) CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     if (!h->side_fork) CHECK(hipEventCreateWithFlags(&h->side_fork, hipEventDisableTiming));
     if (!h->side_join) CHECK(hipEventCreateWithFlags(&h->side_join, hipEventDisableTiming));
