@@ -380,7 +380,7 @@ FIRE_DEV void chan_reduce(int kc, const float* W3, const float* Wenv, int d, flo
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
+__global__ __launch_bounds__(256, 2) void k_msg_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
                                                  const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
                                                  const char* __restrict__ state, StateRec S,
                                                  const T* __restrict__ mbar, T* __restrict__ projbar,
@@ -399,16 +399,16 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
   const int c = threadIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const bool act = c < D.d;
   const int n = D.n, d = D.d;
-  for (int q = tid; q < 2 * astr; q += nt) acc[q] = T(0);
+  for (int q = tid; q < astr; q += nt) acc[q] = T(0);
   __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
   __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
-  T aW3[2][kMaxH2], aWenv[2][kMaxG], aWe[2][4], ab[2];
-  for (int a = 0; a < 2; ++a) {
-    for (int k = 0; k < kMaxH2; ++k) aW3[a][k] = 0;
-    for (int k = 0; k < kMaxG; ++k) aWenv[a][k] = 0;
-    for (int k = 0; k < 4; ++k) aWe[a][k] = 0;
-    ab[a] = 0;
-  }
+  // one pair class per launch row of blocks: a = blockIdx.y (par, anti), which
+  // halves the live accumulators and so doubles the resident waves
+  const int a = blockIdx.y;
+  T aW3[kMaxH2], aWenv[kMaxG], aWe[4], ab = 0;
+  for (int k = 0; k < kMaxH2; ++k) aW3[k] = 0;
+  for (int k = 0; k < kMaxG; ++k) aWenv[k] = 0;
+  for (int k = 0; k < 4; ++k) aWe[k] = 0;
   __syncthreads();
   for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
     const int64_t wl = e / n;
@@ -419,8 +419,8 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
     const double rx = Rw[3 * i], ry = Rw[3 * i + 1], rz = Rw[3 * i + 2];
     const T mb = act ? mbar[e * d + c] : T(0);
     const int c0 = ncnt[2 * e], c1 = ncnt[2 * e + 1];
-    T abar[2] = {0, 0};
-    for (int a = 0; a < 2; ++a) {
+    T abar = 0;
+    {
       const int na = a == 0 ? c0 : c1, sbase = a == 0 ? 0 : c0;
       T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0, ai = 0;
       if (act) {
@@ -458,14 +458,14 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
             T sf, s1, s2;
             silu3(pre, sf, s1, s2);
             const T gb = mb * sf, pb = mb * gam * s1;
-            abar[a] += pb;
+            abar += pb;
             atomicAdd(&projbar[((wl * n + j) * 4 + 2 + a) * d + c], pb);
-            for (int q = 0; q < 4; ++q) aWe[a][q] += pb * f[4 + q];
-            ab[a] += pb;
+            for (int q = 0; q < 4; ++q) aWe[q] += pb * f[4 + q];
+            ab += pb;
             u1 = gb * g2;
             u2 = gb * g1;
-            for (int q = 0; q < D.h2; ++q) aW3[a][q] += u1 * f[48 + q];
-            for (int q = 0; q < D.G; ++q) aWenv[a][q] += u2 * f[88] * f[56 + q];
+            for (int q = 0; q < D.h2; ++q) aW3[q] += u1 * f[48 + q];
+            for (int q = 0; q < D.G; ++q) aWenv[q] += u2 * f[88] * f[56 + q];
           }
         };
         // per-pair reductions over channels: zbar2_q = sum_c u1 W3[q][c], chibar_q = sum_c u2 Wenv[q][c]
@@ -504,28 +504,25 @@ __global__ __launch_bounds__(256) void k_msg_bwd(Net<T> P, const double* __restr
                                  P.ee_sig + a * D.G, eterm + tid * ET);
         __syncthreads();
         {
-          T* A = acc + a * astr;
+          T* A = acc;
           edge_param_sums<T, false>(feat, eterm, jc, A + fo.W1, A + fo.b1, A + fo.W2, A + fo.b2, A + fo.W3);
         }
       }
     }
-    if (act) {
-      projbar[(e * 4 + 0) * d + c] += abar[0];
-      projbar[(e * 4 + 1) * d + c] += abar[1];
-    }
+    if (act) projbar[(e * 4 + a) * d + c] += abar;
   }
   __syncthreads();
   T* out = part + (int64_t)blockIdx.x * msg_part_size(D);
-  for (int a = 0; a < 2; ++a) {
+  {
     T* o = out + a * (fo.size + 5 * D.d);
     if (act) {
-      for (int q = 0; q < D.h2; ++q) o[fo.W3 + q * d + c] = aW3[a][q];
-      for (int q = 0; q < D.G; ++q) o[fo.Wenv + q * d + c] = aWenv[a][q];
-      for (int q = 0; q < 4; ++q) o[fo.size + q * d + c] = aWe[a][q];
-      o[fo.size + 4 * d + c] = ab[a];
+      for (int q = 0; q < D.h2; ++q) o[fo.W3 + q * d + c] = aW3[q];
+      for (int q = 0; q < D.G; ++q) o[fo.Wenv + q * d + c] = aWenv[q];
+      for (int q = 0; q < 4; ++q) o[fo.size + q * d + c] = aWe[q];
+      o[fo.size + 4 * d + c] = ab;
     }
-    for (int q = tid; q < fo.W3; q += nt) o[q] = acc[a * astr + q];
-    for (int q = tid; q < D.G; q += nt) o[fo.sig + q] = acc[a * astr + fo.W3 + q];
+    for (int q = tid; q < fo.W3; q += nt) o[q] = acc[q];
+    for (int q = tid; q < D.G; q += nt) o[fo.sig + q] = acc[fo.W3 + q];
   }
 }
 
@@ -977,10 +974,10 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
                      T(0));
   CHECK(hipGetLastError());
   const FiltOff fo = filt_off(D);
-  const size_t msg_lds = (size_t)2 * (fo.W3 + D.G) * sizeof(T);
+  const size_t msg_lds = (size_t)(fo.W3 + D.G) * sizeof(T);
   CHECK(hipFuncSetAttribute((const void*)k_msg_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)msg_lds));
   const int nb_msg = rows < GBLK ? (int)rows : GBLK;
-  hipLaunchKernelGGL(k_msg_bwd<T>, dim3(nb_msg), dim3(blk), msg_lds, st, P, Rc, rows, w0, (const int16_t*)nidx,
+  hipLaunchKernelGGL(k_msg_bwd<T>, dim3(nb_msg, 2), dim3(blk), msg_lds, st, P, Rc, rows, w0, (const int16_t*)nidx,
                      (const int32_t*)ncnt, (const char*)state, S, (const T*)hb_cur, projbar, epart);
   CHECK(hipGetLastError());
   {
