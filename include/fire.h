@@ -157,6 +157,18 @@ fire_status fire_state_layout(const fire_handle* h, size_t* offsets, size_t* str
  * unchanged for every later call on this handle. */
 fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t stream);
 
+/* Stream overlap inside fire_local_energy (off by default).  With on != 0 the
+ * kinetic energy (Methods, forward Laplacian) runs on a second stream of the
+ * handle beside the nonlocal pseudopotential, whose electrons alternate
+ * between the caller's stream and a third one; both join the caller's stream
+ * before the call's last kernel.  Results equal the serial schedule up to the
+ * order in which the two pseudopotential lane sums are added.  The streams
+ * have the default priority and live until fire_destroy.  Overlapped kernels
+ * share the chip, so per-kernel timings under it are not standalone rates.
+ * Not for calls under graph capture (the pseudopotential path cannot be
+ * captured either way).  Errors: FIRE_ERR_ARG for a null handle. */
+fire_status fire_set_overlap(fire_handle* h, int on);
+
 /* log|psi| and its sign for W walkers (Methods, eq. wf with the cusp
  * Jastrow factor as J: psi = exp(J_cusp) sum_d det Phi_d^up det Phi_d^down,
  * J_cusp = sum_{i<j} w a^2/(a + r_ij) with theta entry jas_cusp = (w_par,

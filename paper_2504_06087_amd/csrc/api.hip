@@ -360,6 +360,12 @@ fire_status fire::set_params_split(fire_handle* h, const double* shared, const d
 
 extern "C" {
 
+fire_status fire_set_overlap(fire_handle* h, int on) {
+  if (!h) return FIRE_ERR_ARG;
+  h->overlap = on != 0;
+  return FIRE_OK;
+}
+
 fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t s) {
   if (!h || !theta || !params_buf) return FIRE_ERR_ARG;
   return fire::set_params_split(h, theta, theta + th(h, "orb_W_up").offset, params_buf, s);

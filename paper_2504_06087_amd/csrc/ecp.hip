@@ -228,8 +228,10 @@ __global__ void k_add_f64(double* p, const double* q, int64_t n) {
   if (i < n) p[i] += q[i];
 }
 
-// Shared job counts, then two lanes of job buffers: electrons alternate
-// between the lanes, which run on two streams.
+// Shared job counts, then one or two lanes of job buffers.  With overlap on,
+// electrons alternate between two lanes, which run on two streams; otherwise
+// one lane of twice the chunk takes them all on the caller's stream.  Both
+// layouts take about the same bytes; the workspace holds the larger.
 struct EcpLayout {
   int Jc;
   size_t cnt, off, tot;
@@ -238,15 +240,16 @@ struct EcpLayout {
   size_t total;
 };
 
-static EcpLayout ecp_layout(const fire_handle* h, int W) {
+static EcpLayout ecp_layout(const fire_handle* h, int W, int lanes) {
   EcpLayout L{};
   const Dims& D = h->D;
   // jobs per chunk and lane: about 12 jobs per electron and walker, at most
-  // 16380, a multiple of 4, 6 and 12 (the update segments reserve 32 rows per
-  // job and spin; at 180 electrons and 16 determinants a lane of 16380 jobs
-  // takes ~15 GB of workspace)
+  // 32760 / lanes, a multiple of 4, 6 and 12 (the update segments reserve 32
+  // rows per job and spin; at 180 electrons and 16 determinants 32760 jobs
+  // take ~31 GB of workspace)
+  const int64_t cap = 32760 / lanes;
   int64_t want = (int64_t)W * 12;
-  L.Jc = (int)(want < 16380 ? (want > 264 ? want : 264) : 16380);
+  L.Jc = (int)(want < cap ? (want > 264 ? want : 264) : cap);
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.cnt = take((size_t)D.n * W * 4);
@@ -262,12 +265,16 @@ static EcpLayout ecp_layout(const fire_handle* h, int W) {
   L.upd = q;
   q = align_up(q + upd_layout(h, L.Jc, false).total);
   L.lane[0] = o;
-  L.lane[1] = o + q;
-  L.total = align_up(o + 2 * q);
+  L.lane[1] = o + (lanes == 2 ? q : 0);
+  L.total = align_up(o + lanes * q);
   return L;
 }
 
-size_t ecp_ws_bytes(const fire_handle* h, int W) { return h->ecp.empty() ? 0 : ecp_layout(h, W).total; }
+size_t ecp_ws_bytes(const fire_handle* h, int W) {
+  if (h->ecp.empty()) return 0;
+  const size_t a = ecp_layout(h, W, 1).total, b = ecp_layout(h, W, 2).total;
+  return a > b ? a : b;
+}
 
 template <typename T>
 static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* state, char* ws,
@@ -275,7 +282,8 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   const Dims& D = h->D;
   const StateRec& S = h->st;
   Net<T> P = make_net<T>(h);
-  const EcpLayout L = ecp_layout(h, W);
+  const int lanes = h->overlap ? 2 : 1;
+  const EcpLayout L = ecp_layout(h, W, lanes);
   const EcpTables tb = tables(h);
   const UpdLayout U = upd_layout(h, L.Jc, false);
   int* cnt = (int*)(ws + L.cnt);
@@ -286,7 +294,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   // sum on the handle's pseudopotential stream; both are cleared here, before
   // the host waits on st, so lane 1 needs no event to start after them
   double* vl[2] = {vnl, (double*)(ws + L.lane[1] + L.vnl)};
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < lanes; ++l) {
     hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, st, vl[l], (int64_t)W, 0.0);
     CHECK(hipGetLastError());
   }
@@ -299,7 +307,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   CHECK(hipMemcpyAsync(htot.data(), tot, (size_t)D.n * 4, hipMemcpyDeviceToHost, st));
   CHECK(hipStreamSynchronize(st));
   hipStream_t ls[2] = {st, st};
-  {
+  if (lanes == 2) {
     std::lock_guard<std::mutex> lock(handle_mutex());
     if (!h->side_ecp) CHECK(hipStreamCreateWithFlags(&h->side_ecp, hipStreamNonBlocking));
     if (!h->side_ecp_join) CHECK(hipEventCreateWithFlags(&h->side_ecp_join, hipEventDisableTiming));
@@ -308,7 +316,7 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   for (int e = 0; e < D.n; ++e) {
     const int Te = htot[e];
     if (Te == 0) continue;
-    const int ln = e & 1;
+    const int ln = lanes == 2 ? (e & 1) : 0;
     hipStream_t ss = ls[ln];
     char* lb = ws + L.lane[ln];
     int* jw = (int*)(lb + L.jw);
@@ -339,9 +347,11 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   }
   // join lane 1 (a later record of the join event lies later on the serial
   // lane-1 stream, so the wait is never too early) and add its sum
-  CHECK(hipEventRecord(h->side_ecp_join, ls[1]));
-  CHECK(hipStreamWaitEvent(st, h->side_ecp_join, 0));
-  hipLaunchKernelGGL(k_add_f64, dim3((W + 255) / 256), dim3(256), 0, st, vnl, (const double*)vl[1], (int64_t)W);
+  if (lanes == 2) {
+    CHECK(hipEventRecord(h->side_ecp_join, ls[1]));
+    CHECK(hipStreamWaitEvent(st, h->side_ecp_join, 0));
+    hipLaunchKernelGGL(k_add_f64, dim3((W + 255) / 256), dim3(256), 0, st, vnl, (const double*)vl[1], (int64_t)W);
+  }
   return hipGetLastError();
 }
 

@@ -72,6 +72,7 @@ struct fire_handle {
   // second stream of the local energy: the kinetic energy runs on it beside
   // the pseudopotential on the caller's stream (created on first use, default
   // priority), with the events that order it against the caller's stream
+  bool overlap = false;         // fire_set_overlap
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
   // second stream of the pseudopotential (every other electron's quadrature

@@ -830,15 +830,17 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
   char* region_ecp = region + align_up(L.total);
   CHECK(fill_i32(status, W, 0, st));
   const bool has_ecp = !h->ecp.empty();
-  // With a pseudopotential, the kinetic energy and the potential run on the
-  // handle's second stream, beside the quadrature jobs on the caller's stream:
+  // With a pseudopotential and overlap on, the kinetic energy and the
+  // potential run on the handle's second stream, beside the quadrature jobs
+  // on the caller's stream:
   // the two read the same state, write disjoint outputs and workspace regions,
   // and meet only in the status flags (atomic OR).  The fork (record on st,
   // wait on the side stream) is atomic under a lock, so concurrent calls
   // cannot swap their fork points; a later record of the join event lies
   // later on the serial side stream, so waiting on it is never too early.
   hipStream_t ks = st;
-  if (has_ecp) {
+  const bool fork = has_ecp && h->overlap;
+  if (fork) {
     std::lock_guard<std::mutex> lock(handle_mutex());
     if (!h->side) CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     if (!h->side_fork) CHECK(hipEventCreateWithFlags(&h->side_fork, hipEventDisableTiming));
@@ -853,11 +855,9 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
   }
   hipLaunchKernelGGL(k_potential, dim3(W), dim3(256), 0, ks, D, W, R, P.Rn, P.Zn, P.ppw, pot);
   CHECK(hipGetLastError());
-  if (has_ecp) {
-    CHECK(hipEventRecord(h->side_join, ks));
-    CHECK(ecp_into(h, W, R, state, region_ecp, quad_rot, vnl, status, st));
-    CHECK(hipStreamWaitEvent(st, h->side_join, 0));
-  }
+  if (fork) CHECK(hipEventRecord(h->side_join, ks));
+  if (has_ecp) CHECK(ecp_into(h, W, R, state, region_ecp, quad_rot, vnl, status, st));
+  if (fork) CHECK(hipStreamWaitEvent(st, h->side_join, 0));
   hipLaunchKernelGGL(k_local_energy_sum, dim3((W + 127) / 128), dim3(128), 0, st, W, (const double*)kin,
                      (const double*)pot, has_ecp ? (const double*)vnl : nullptr, (const int32_t*)status, e_loc, parts);
   return hipGetLastError();

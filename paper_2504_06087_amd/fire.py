@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
 W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
 
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
-           "fire_state_layout", "fire_set_params", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
+           "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_size_t)]
     lib.fire_state_layout.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.fire_set_params.argtypes = [P, V, V, V]
+    lib.fire_set_overlap.argtypes = [P, I]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
     lib.fire_adapt_step.argtypes = [D, ctypes.c_int64, ctypes.c_int64, D, D, ctypes.POINTER(ctypes.c_double)]
@@ -244,6 +245,10 @@ class Fire:
         p, s, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
         _check(load().fire_sizes(self.h, int(W), ctypes.byref(p), ctypes.byref(s), ctypes.byref(w)), "fire_sizes")
         return p.value, s.value, w.value
+
+    def set_overlap(self, on: bool):
+        """Stream overlap inside local_energy (fire_set_overlap; off by default)."""
+        _check(load().fire_set_overlap(self.h, int(bool(on))), "fire_set_overlap")
 
     def set_params(self, params):
         theta = params if isinstance(params, torch.Tensor) else _f64(self.flatten(params), self.device)

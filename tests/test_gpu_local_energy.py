@@ -163,3 +163,29 @@ def test_ecp_rule_validation(lib):
     s.ecp_nquad = {1: 5}
     with pytest.raises(fire.FireError):
         fire.Fire(s, m, "fp64", max_walkers=1)
+
+
+def test_polyene_ecp_stream_overlap(lib):
+    """fire_set_overlap: the kinetic energy beside the pseudopotential, whose
+    electrons alternate between two streams.  The local energy, its parts and
+    grad log|psi| equal the serial schedule (the lane sums of V_NL are added
+    in another order: 1e-12 relative) and the oracle, on two calls in a row
+    and after switching back."""
+    log("case: narrow C12H14 with nonlocal ECP fp64 W=3, stream overlap on/off")
+    s, m, p, R = small_polyene(3, ecp=True, seed=12)
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Q = wl.haar_rotations(3, np.random.default_rng(6))
+    e0, parts0, g0, st0 = _el(F, R, state, ws, Q=Q)
+    F.set_overlap(True)
+    runs = [_el(F, R, state, ws, Q=Q) for _ in range(2)]
+    F.set_overlap(False)
+    runs.append(_el(F, R, state, ws, Q=Q))
+    eo = O.local_energy(R, Q, chunk=32)[0].numpy()
+    for e, parts, g, st in runs:
+        assert (st == 0).all()
+        scale = np.maximum(1.0, np.abs(e0))
+        log(f"E_L {e} serial {e0} oracle {eo}")
+        assert (np.abs(e - e0) / scale).max() <= 1e-12
+        assert (np.abs(parts - parts0) / np.maximum(1.0, np.abs(parts0))).max() <= 1e-12
+        assert np.abs(g - g0).max() <= 1e-12 * max(1.0, np.abs(g0).max())
+        assert (np.abs(e - eo) / scale).max() <= 1e-7
