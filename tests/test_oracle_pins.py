@@ -529,6 +529,58 @@ def test_ecp_spherically_symmetric_wavefunction_gives_v0(nq):
     assert np.allclose(v, v0, atol=1e-12)
 
 
+@pytest.mark.parametrize("nq", [4, 6, 12])
+@pytest.mark.parametrize("orient", ["along", "against"])
+def test_ecp_p_type_wavefunction_gives_v1(nq, orient):
+    """A p-type one-electron psi = (u . d) g(|d|) about the pseudo-atom, d =
+    r - R_I, has quadrature ratios (u . q)/(u . dhat) with q the rotated rule
+    direction.  Every rule of design strength >= 2 averages q q^T to I/3, so
+    the l = 1 channel gives 3 (1/N_q) sum_q (dhat . q)(u . q)/(u . dhat) = 1
+    and the l = 0 channel (1/N_q) sum_q (u . q)/(u . dhat) = 0: V_NL = v_1(r)
+    exactly (the addition theorem for l = 1).  The case u . dhat < 0 makes
+    every ratio's sign matter, and the Haar rotations Q make the Legendre
+    argument depend on the rotated direction: a dropped (2l+1), P_1 taken on
+    the unrotated rule or an unsigned ratio each break the equality."""
+    s, m, p, R = wl.hydrogen_atom(W=6, seed=11)
+    rng = np.random.default_rng(5)
+    s.species = np.ones(1, np.int32)
+    s.ecp = wl._ecp_tables(rng)
+    s.ecp_nquad = {1: nq}
+    dhat = rng.normal(size=(6, 3))
+    dhat /= np.linalg.norm(dhat, axis=1, keepdims=True)
+    r = rng.uniform(0.2, 1.9, size=6)
+    R = (s.R_nuc[0][None] + dhat * r[:, None])[:, None, :]
+    u = rng.normal(size=3)
+    # choose the sign of u per case so that u . dhat has one sign on every walker
+    dots = dhat @ u
+    keep = np.abs(dots) > 0.2
+    R, dhat, r, dots = R[keep], dhat[keep], r[keep], dots[keep]
+    sgn = 1.0 if orient == "along" else -1.0
+    R = R.copy()
+    dhat = dhat * (np.sign(dots) * sgn)[:, None]
+    R[:, 0] = s.R_nuc[0][None] + dhat * r[:, None]
+    assert (np.sign(dhat @ u) == sgn).all()
+    o = Oracle(s, m, p)
+    Rn = torch.tensor(s.R_nuc[0])
+    ut = torch.tensor(u)
+
+    def p_type(X):
+        X = torch.as_tensor(X, dtype=DT)
+        d = X[:, 0] - Rn
+        val = (d @ ut) * torch.exp(-0.7 * (d * d).sum(-1))
+        return torch.sign(val), torch.log(val.abs())
+    o.log_psi = p_type
+    Q = wl.haar_rotations(len(R), rng)
+    v = o.ecp_nonlocal(R, Q).numpy()
+    ch1 = [c for c in s.ecp[1] if c.l == 1][0]
+    v1 = (ch1.a[None] * np.exp(-ch1.alpha[None] * r[:, None] ** 2)).sum(1)
+    assert np.allclose(v, v1, atol=1e-12, rtol=1e-12)
+    # the test is not degenerate: the l = 1 value differs from v_0 and from 0
+    ch0 = [c for c in s.ecp[1] if c.l == 0][0]
+    v0 = (ch0.a[None] * np.exp(-ch0.alpha[None] * r[:, None] ** 2)).sum(1)
+    assert np.abs(v1 - v0).min() > 1e-3 and np.abs(v1).min() > 1e-3
+
+
 # --------------------------------------------------------------------------
 # global single-electron jumps (SI, improved Monte Carlo sampling)
 # --------------------------------------------------------------------------
