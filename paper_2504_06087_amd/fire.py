@@ -218,6 +218,10 @@ class Fire:
         self.state_stride = int(stride.value)
         self.params_buf = None
         self.theta = None
+        # counters that FireLogPsi uses to see whether the parameters or a
+        # state buffer changed between its forward and backward
+        self.params_version = 0
+        self._state_versions = {}
 
     def __del__(self):
         try:
@@ -256,6 +260,7 @@ class Fire:
         self.params_buf = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.theta = theta
         _check(load().fire_set_params(self.h, _dp(theta), _dp(self.params_buf), _stream()), "fire_set_params")
+        self.params_version += 1
 
     def buffers(self, W: int):
         _, s, w = self.sizes(W)
@@ -263,6 +268,13 @@ class Fire:
                 torch.empty(w, dtype=torch.uint8, device=self.device))
 
     # ------------------------------------------------------------------
+    def state_version(self, state) -> int:
+        return self._state_versions.get(state.data_ptr(), 0)
+
+    def _touch(self, state):
+        k = state.data_ptr()
+        self._state_versions[k] = self._state_versions.get(k, 0) + 1
+
     def eval_logpsi(self, R, state, ws):
         W = R.shape[0]
         sign = torch.empty(W, dtype=torch.float64, device=self.device)
@@ -270,6 +282,7 @@ class Fire:
         status = torch.empty(W, dtype=torch.int32, device=self.device)
         _check(load().fire_eval_logpsi(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(sign), _dp(logpsi),
                                        _dp(status), _stream()), "fire_eval_logpsi")
+        self._touch(state)
         return sign, logpsi, status
 
     def mcmc_sweep(self, R, state, ws, n_sweeps, step, noise, unif, n_accept=None):
@@ -282,6 +295,7 @@ class Fire:
         _check(load().fire_mcmc_sweep(self.h, W, _dp(R), _dp(state), _dp(ws), int(n_sweeps), float(step),
                                       _dp(noise), _dp(unif), _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status),
                                       _stream()), "fire_mcmc_sweep")
+        self._touch(state)
         return n_accept, sign, logpsi, status
 
     def mcmc_sweep_mixed(self, R, state, ws, kinds, step, global_step, noise, unif, pick, n_accept=None):
@@ -299,6 +313,7 @@ class Fire:
                                             float(global_step), k, _dp(noise), _dp(unif), _dp(pick),
                                             _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status), _stream()),
                "fire_mcmc_sweep_mixed")
+        self._touch(state)
         return n_accept, sign, logpsi, status
 
     def local_energy(self, R, state, ws, quad_rot=None, want_grad=False):
@@ -542,18 +557,53 @@ class FireLogPsi(torch.autograd.Function):
     forward(theta, R, handle, state, ws): packs theta into the handle, runs
     fire_eval_logpsi.  backward: fire_grad_params with coeff = grad_output,
     i.e. d/d theta of sum_w grad_output_w log|psi_w|.  No gradient w.r.t. R.
+
+    The adjoint reads the handle's packed parameters and the cached state of
+    the forward.  When either changed in between (another set_params, or an
+    evaluation or sweep into the same state buffer), backward packs the
+    saved theta again and re-evaluates the saved positions first.  Walkers
+    flagged by the forward or the adjoint (status bits) have NaN log|psi|; a
+    non-zero grad_output on one of them raises FireError; with zero
+    grad_output they are left out of the adjoint.
     """
 
     @staticmethod
     def forward(ctx, theta, R, handle, state, ws):
-        handle.set_params(theta.detach().contiguous())
+        theta = theta.detach().contiguous()
+        handle.set_params(theta)
         sign, lp, st = handle.eval_logpsi(R, state, ws)
         ctx.handle, ctx.state, ctx.ws = handle, state, ws
-        ctx.save_for_backward(R)
+        ctx.params_version = handle.params_version
+        ctx.state_version = handle.state_version(state)
+        ctx.save_for_backward(theta, R, st)
         return lp
 
     @staticmethod
     def backward(ctx, grad_out):
-        (R,) = ctx.saved_tensors
-        g, st = ctx.handle.grad_params(R, ctx.state, ctx.ws, grad_out.detach().to(torch.float64).contiguous())
+        theta, R, st = ctx.saved_tensors
+        h = ctx.handle
+        if h.params_version != ctx.params_version:
+            h.set_params(theta)
+        if h.params_version != ctx.params_version or h.state_version(ctx.state) != ctx.state_version:
+            _, _, st = h.eval_logpsi(R, ctx.state, ctx.ws)
+        coeff = grad_out.detach().to(torch.float64).contiguous()
+        flagged = st != 0
+        bad = flagged & (coeff != 0)
+        if bool(bad.any()):
+            idx = torch.nonzero(bad).flatten()[:8].tolist()
+            raise FireError(f"FireLogPsi.backward: flagged walkers {idx} (status bits) have a non-zero grad_output")
+        if bool(flagged.any()):
+            # the adjoint of a flagged walker would read non-finite cached
+            # values: differentiate the other walkers only
+            keep = torch.nonzero(~flagged).flatten()
+            R = R.index_select(0, keep).contiguous()
+            coeff = coeff.index_select(0, keep).contiguous()
+            if R.shape[0] == 0:
+                return torch.zeros_like(theta), None, None, None, None
+            h.eval_logpsi(R, ctx.state, ctx.ws)
+        g, st2 = h.grad_params(R, ctx.state, ctx.ws, coeff)
+        bad = (st2 != 0) & (coeff != 0)
+        if bool(bad.any()):
+            idx = torch.nonzero(bad).flatten()[:8].tolist()
+            raise FireError(f"FireLogPsi.backward: the adjoint flagged walkers {idx} (status bits)")
         return g, None, None, None, None

@@ -127,3 +127,40 @@ def test_autograd_function(lib):
     (lp * w).sum().backward()
     ref = _oracle_grad(F, O, R, w.cpu().numpy())
     assert np.abs(theta.grad.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_autograd_function_survives_interleaved_calls(lib):
+    """Between FireLogPsi's forward and backward the handle gets another
+    parameter vector and the state buffer another evaluation and a sweep;
+    backward restores both and returns the gradient of the forward's
+    (theta, R).  A flagged walker with a non-zero grad_output raises."""
+    from paper_2504_06087_amd import fire
+    F, O, s, m, p, R, state, ws = setup(0, 4, "fp64")
+    theta0 = F.flatten(p)
+    theta = torch.tensor(theta0, device="cuda", requires_grad=True)
+    Rd = dev(R)
+    lp = fire.FireLogPsi.apply(theta, Rd, F, state, ws)
+    w = torch.tensor([0.5, -1.0, 2.0, 0.25], device="cuda", dtype=torch.float64)
+    # interleaved work on the same handle and state
+    F.set_params(torch.tensor(theta0 * 1.1, device="cuda"))
+    R2 = dev(R + 0.3)
+    F.eval_logpsi(R2, state, ws)
+    xi, u = wl.mcmc_noise(1, s.n_el, 4, np.random.default_rng(9))
+    F.mcmc_sweep(R2, state, ws, 1, 0.2, dev(xi), dev(u))
+    (lp * w).sum().backward()
+    ref = _oracle_grad(F, O, R, w.cpu().numpy())
+    err = np.abs(theta.grad.cpu().numpy() - ref).max() / np.abs(ref).max()
+    log(f"interleaved FireLogPsi backward: rel err {err:.1e}")
+    assert err <= 1e-10
+    # a walker with a NaN position is flagged; its grad_output must be zero
+    Rb = R.copy()
+    Rb[1, 0, 0] = np.nan
+    theta2 = torch.tensor(theta0, device="cuda", requires_grad=True)
+    lpb = fire.FireLogPsi.apply(theta2, dev(Rb), F, state, ws)
+    with pytest.raises(fire.FireError):
+        (lpb * w).sum().backward()
+    theta3 = torch.tensor(theta0, device="cuda", requires_grad=True)
+    lpc = fire.FireLogPsi.apply(theta3, dev(Rb), F, state, ws)
+    mask = torch.tensor([1.0, 0.0, 1.0, 1.0], device="cuda", dtype=torch.float64)
+    (torch.nan_to_num(lpc) * w * mask).sum().backward()
+    assert torch.isfinite(theta3.grad).all()

@@ -1,9 +1,16 @@
 """The BF16/FP64 hybrid against FP64 on the 180-electron flake (the
 benchmark's molecule and network), per result: log|psi|, E_L and the energy
 gradient sum_w c_w grad log|psi_w| with c_w = (E_L,w - mean E_L)/W.  The FP64
-path itself matches the oracle (other tests); this one states how far the
-hybrid is from it on random-init networks, whose badly conditioned orbital
-matrices amplify every rounding (the bounds are loose on purpose)."""
+path itself matches the oracle at this size (sampled walkers in the full-size
+test) and at this network (the benchmark-network tests); here it is the
+reference the hybrid's error is stated against, on 256 walkers.
+
+Random-init orbital matrices at 180 electrons are badly conditioned: the
+first-order amplifier sum_kl |G_kl Phi_kl| of a relative perturbation of Phi
+into log|det| has a median of ~4500 over these walkers and reaches ~2e5.  The
+hybrid's log|psi| error is held to that amplifier times the split-bf16
+rounding; the stated E_L tolerance (1e-3 Ha on the batch mean, the reading of
+the tolerance this build takes) is asserted and reported as missed."""
 import numpy as np
 import pytest
 import torch
@@ -13,8 +20,10 @@ from gpu_common import dev, log
 
 pytestmark = pytest.mark.gpu
 
+W = 256
 
-def _run(precision, work, W, Q):
+
+def _run(precision, work, Q, amp=False):
     from paper_2504_06087_amd import fire
     kw = dict(cap_nbr=48, cap_upd=64)
     if precision == "bf16":
@@ -24,31 +33,75 @@ def _run(precision, work, W, Q):
     state, ws = F.buffers(W)
     Rd = dev(work.R[0])
     _, lp, st = F.eval_logpsi(Rd, state, ws)
-    e, _, _, st2 = F.local_energy(Rd, state, ws, dev(Q))
+    e, parts, _, st2 = F.local_energy(Rd, state, ws, dev(Q))
     torch.cuda.synchronize()
-    return F, Rd, state, ws, lp.cpu().numpy(), e.cpu().numpy(), st.cpu().numpy() | st2.cpu().numpy()
+    out = dict(F=F, R=Rd, state=state, ws=ws, lp=lp.cpu().numpy(), e=e.cpu().numpy(), parts=parts.cpu().numpy(),
+               st=st.cpu().numpy() | st2.cpu().numpy())
+    if amp:
+        s, K = work.systems[0], work.model.n_det
+        nu2 = s.n_up ** 2
+        G = F.state_view(state, W, "inv").view(W, K, -1)
+        P = F.state_view(state, W, "phi").view(W, K, -1)
+        a = (G[:, :, :nu2] * P[:, :, :nu2]).abs().sum(-1) + (G[:, :, nu2:] * P[:, :, nu2:]).abs().sum(-1)
+        wts = torch.softmax(F.state_view(state, W, "dlog").view(W, K, 2).sum(-1), 1)
+        out["amp"] = (a * wts).sum(1).cpu().numpy()
+    return out
 
 
-def test_flake_hybrid_vs_fp64_per_result(lib):
-    W = 16
+@pytest.fixture(scope="module")
+def flake_runs():
     work = wl.config(3, walkers=W)
     Q = wl.haar_rotations(W, np.random.default_rng(7))
-    log("case: C42H12, 16 walkers: BF16 hybrid vs FP64 for log|psi|, E_L and the energy gradient")
-    F64, R64, s64, w64, lp64, e64, st64 = _run("fp64", work, W, Q)
-    Fh, Rh, sh, wh, lph, eh, sth = _run("bf16", work, W, Q)
-    assert (st64 == 0).all() and (sth == 0).all()
-    dl = np.abs(lph - lp64)
-    de = np.abs(eh - e64)
-    coeff = (e64 - e64.mean()) / W
-    g64, _ = F64.grad_params(R64, s64, w64, dev(coeff))
-    gh, _ = Fh.grad_params(Rh, sh, wh, dev(coeff))
+    log(f"case: C42H12, {W} walkers: FP64, BF16 hybrid and FP32 plain E_L")
+    r64 = _run("fp64", work, Q, amp=True)
+    rh = _run("bf16", work, Q)
+    r32 = _run("fp32", work, Q)
+    return work, r64, rh, r32
+
+
+def _stats(tag, d):
+    a = np.abs(d)
+    return (f"{tag}: |dE| median {np.median(a):.2e}, p90 {np.quantile(a, 0.9):.2e}, p99 {np.quantile(a, 0.99):.2e}, "
+            f"max {a.max():.2e} Ha; batch-mean difference {d.mean():+.2e} Ha")
+
+
+def test_flake_hybrid_vs_fp64_per_result(lib, flake_runs):
+    work, r64, rh, r32 = flake_runs
+    assert (r64["st"] == 0).all() and (rh["st"] == 0).all() and (r32["st"] == 0).all()
+    amp = r64["amp"]
+    dl = np.abs(rh["lp"] - r64["lp"])
+    de = rh["e"] - r64["e"]
+    log(f"amplifier median {np.median(amp):.0f}, max {amp.max():.0f}; hybrid log|psi| error median "
+        f"{np.median(dl):.1e}, max {dl.max():.1e} (|log psi| ~ {np.abs(r64['lp']).mean():.0f})")
+    log(_stats("hybrid E_L", de))
+    for k, name in ((0, "kinetic"), (4, "V_NL")):
+        d = rh["parts"][:, k] - r64["parts"][:, k]
+        log(_stats(f"hybrid {name}", d))
+    log(_stats("FP32-plain E_L", r32["e"] - r64["e"]))
+    # log|psi|: split-bf16 products carry ~2^-17 relative error; 2^-14 times
+    # the amplifier leaves 8x headroom on every walker
+    assert (dl <= 2.0 ** -14 * amp).all()
+    assert np.isfinite(rh["e"]).all()
+    # the energy gradient of the hybrid against the FP64 one on the same walkers
+    coeff = dev((r64["e"] - r64["e"].mean()) / W)
+    g64, _ = r64["F"].grad_params(r64["R"], r64["state"], r64["ws"], coeff)
+    gh, _ = rh["F"].grad_params(rh["R"], rh["state"], rh["ws"], coeff)
     torch.cuda.synchronize()
     g64, gh = g64.cpu().numpy(), gh.cpu().numpy()
     rel = np.linalg.norm(gh - g64) / np.linalg.norm(g64)
     cos = float(gh @ g64 / (np.linalg.norm(gh) * np.linalg.norm(g64)))
-    log(f"log|psi|: median {np.median(dl):.1e}, max {dl.max():.1e} (|log psi| ~ {np.abs(lp64).mean():.0f}); "
-        f"E_L: median {np.median(de):.2e} Ha, max {de.max():.2e} Ha (|E_L| ~ {np.abs(e64).mean():.0f}); "
-        f"gradient: |g_h - g|/|g| {rel:.2e}, cosine {cos:.6f}")
-    assert np.median(dl) <= 1e-2
-    assert np.isfinite(eh).all() and np.median(de) <= 1.0
-    assert cos >= 0.9
+    log(f"energy gradient: |g_h - g|/|g| {rel:.2e}, cosine {cos:.6f}")
+    assert cos >= 0.99
+
+
+@pytest.mark.xfail(strict=False, reason="misses: the batch-mean E_L of the split-bf16 hybrid differs from FP64 by "
+                   "+3.5e1 Ha over 256 walkers (median per-walker 3.4e-2 Ha, max 9.9e3 Ha); FP32-plain differs by "
+                   "-3.4 Ha; the badly conditioned random-init orbital matrices amplify every rounding")
+def test_flake_hybrid_local_energy_tolerance(lib, flake_runs):
+    """The stated E_L tolerance of the hybrid path, read on the batch mean
+    over the benchmark walkers: |mean E_L(hybrid) - mean E_L(FP64)| <= 1e-3
+    Ha."""
+    work, r64, rh, r32 = flake_runs
+    d = rh["e"] - r64["e"]
+    log(_stats("hybrid E_L", d))
+    assert abs(d.mean()) <= 1e-3
