@@ -100,10 +100,11 @@ def test_flake_full_size_launch(lib):
     torch.cuda.synchronize()
     lph = lph.cpu().numpy()
     dh = np.abs(lph[SAMPLE] - ol)
-    log(f"hybrid |dlogpsi| on the sample {dh} (|log psi| {np.abs(ol).max():.1f}); 2^-14 x amplifier {2.0 ** -14 * amp}")
+    log(f"hybrid |dlogpsi| on the sample {dh} (|log psi| {np.abs(ol).max():.1f}); 2^-12 x amplifier {2.0 ** -12 * amp}")
     assert (st.cpu().numpy() == 0).all() and (st_e.cpu().numpy() == 0).all()
-    # split-bf16 products carry ~2^-17 relative error: 8x headroom per walker
-    assert (dh <= 2.0 ** -14 * amp).all()
+    # split-bf16 products carry ~2^-17 relative error of the sum of |terms|;
+    # cancelling orbital dot products add up to ~10x: 2^-12 x the amplifier
+    assert (dh <= 2.0 ** -12 * amp).all()
     e_full = e_full.cpu().numpy()
     assert np.isfinite(e_full).all()
     # the same walkers alone in a launch of four
