@@ -180,6 +180,24 @@ fire_status fire_set_overlap(fire_handle* h, int on);
 fire_status fire_eval_logpsi(fire_handle* h, int W, const double* R, void* state, void* ws,
                              double* sign, double* logpsi, int32_t* status, hipStream_t stream);
 
+/* fire_eval_logpsi without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same computation, kernels and outputs as
+ * fire_eval_logpsi, with its workspace taken from a file-scope device array
+ * of FIRE_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The caller still owns R, state, sign, logpsi and
+ * status.  The call allocates nothing.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (different streams, or
+ * threads) race and must be ordered by the caller.  Errors: as
+ * fire_eval_logpsi; FIRE_ERR_CAPACITY when the evaluation of W walkers needs
+ * more than FIRE_NOALLOC_SCRATCH_BYTES of workspace (about 1.25 MB per walker
+ * at 180 electrons, width 256 and 432 envelope functions in the BF16 hybrid:
+ * up to 53 walkers; 4 electrons at width 32: over 10 000); FIRE_ERR_HIP when
+ * the array's device address cannot be looked up. */
+#define FIRE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fire_status fire_eval_logpsi_noalloc(fire_handle* h, int W, const double* R, void* state, double* sign,
+                                     double* logpsi, int32_t* status, hipStream_t stream);
+
 /* n_sweeps systematic-scan Metropolis sweeps with Gaussian single-electron
  * moves r_e' = r_e + step*xi (Methods, improved Monte Carlo sampling), each
  * proposal evaluated by neighbour recompute and the matrix-determinant lemma

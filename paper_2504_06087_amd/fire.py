@@ -21,7 +21,8 @@ PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
 W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
 
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
-           "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
+           "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_eval_logpsi_noalloc",
+           "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
@@ -81,6 +82,7 @@ def load() -> ctypes.CDLL:
     lib.fire_set_params.argtypes = [P, V, V, V]
     lib.fire_set_overlap.argtypes = [P, I]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
+    lib.fire_eval_logpsi_noalloc.argtypes = [P, I, V, V, V, V, V, V]
     lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
     lib.fire_adapt_step.argtypes = [D, ctypes.c_int64, ctypes.c_int64, D, D, ctypes.POINTER(ctypes.c_double)]
     lib.fire_mcmc_sweep_mixed.argtypes = [P, I, V, V, V, I, D, D, ctypes.POINTER(ctypes.c_int32), V, V, V, V, V, V,
@@ -282,6 +284,18 @@ class Fire:
         status = torch.empty(W, dtype=torch.int32, device=self.device)
         _check(load().fire_eval_logpsi(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(sign), _dp(logpsi),
                                        _dp(status), _stream()), "fire_eval_logpsi")
+        self._touch(state)
+        return sign, logpsi, status
+
+    def eval_logpsi_noalloc(self, R, state):
+        """fire_eval_logpsi_noalloc: the evaluation with the library's own
+        per-GPU scratch array as workspace (allocation-free)."""
+        W = R.shape[0]
+        sign = torch.empty(W, dtype=torch.float64, device=self.device)
+        logpsi = torch.empty_like(sign)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_eval_logpsi_noalloc(self.h, W, _dp(R), _dp(state), _dp(sign), _dp(logpsi), _dp(status),
+                                               _stream()), "fire_eval_logpsi_noalloc")
         self._touch(state)
         return sign, logpsi, status
 
