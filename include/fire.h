@@ -13,10 +13,10 @@
  *  - All tensor pointers are DEVICE pointers owned by the caller unless a
  *    comment says "host".  All work is enqueued on the caller's hipStream_t
  *    and no call allocates device memory.  No compute call synchronises the
- *    stream, with one exception: on a system with nonlocal pseudopotential
- *    channels, fire_local_energy and fire_ecp_nonlocal read the per-electron
- *    quadrature job counts back to the host once per call (one stream
- *    synchronisation) to size their launches.
+ *    stream or reads a device value back to the host, so every compute call
+ *    can be captured into a HIP graph.  (The pseudopotential quadrature sizes
+ *    its launches from a bound on its job counts fixed by the geometry and
+ *    reads the live counts on the device.)
  *  - Positions are FP64 [W][n][3], electrons 0..n_up-1 spin up, the rest down.
  *  - Errors the host can see (bad pointer, shape, precision, W > max_walkers)
  *    are returned immediately as a negative fire_status and nothing is
@@ -160,13 +160,15 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
 /* Stream overlap inside fire_local_energy (off by default).  With on != 0 the
  * kinetic energy (Methods, forward Laplacian) runs on a second stream of the
  * handle beside the nonlocal pseudopotential, whose electrons alternate
- * between the caller's stream and a third one; both join the caller's stream
- * before the call's last kernel.  Results equal the serial schedule up to the
- * order in which the two pseudopotential lane sums are added.  The streams
- * have the default priority and live until fire_destroy.  Overlapped kernels
- * share the chip, so per-kernel timings under it are not standalone rates.
- * Not for calls under graph capture (the pseudopotential path cannot be
- * captured either way).  Errors: FIRE_ERR_ARG for a null handle. */
+ * between the caller's stream and a third one; both fork from and join the
+ * caller's stream within the call.  Results equal the serial schedule up to
+ * the order in which the two pseudopotential lane sums are added.  The first
+ * call with on != 0 creates the streams (default priority) and their events,
+ * which live until fire_destroy; compute calls never create or change them.
+ * Overlapped kernels share the chip, so per-kernel timings under it are not
+ * standalone rates, and the GEMM autotuner does not time shapes inside an
+ * overlapped call.  Errors: FIRE_ERR_ARG for a null handle, FIRE_ERR_HIP when
+ * a stream or event cannot be created. */
 fire_status fire_set_overlap(fire_handle* h, int on);
 
 /* log|psi| and its sign for W walkers (Methods, eq. wf with the cusp
@@ -201,15 +203,22 @@ fire_status fire_eval_logpsi_noalloc(fire_handle* h, int W, const double* R, voi
 /* n_sweeps systematic-scan Metropolis sweeps with Gaussian single-electron
  * moves r_e' = r_e + step*xi (Methods, improved Monte Carlo sampling), each
  * proposal evaluated by neighbour recompute and the matrix-determinant lemma
- * (Methods, low-rank wave-function updates); accepted moves update Phi^-1 by
- * the Woodbury identity.  State is refreshed by a full evaluation every
- * refresh_every sweeps.  noise [S][n][W][3] and unif [S][n][W] are explicit
- * random numbers (both non-NULL).  R is updated in place; n_accept [W] is
- * incremented; logpsi/sign [W] receive the final values. */
+ * (Methods, low-rank wave-function updates), accepted iff u < (psi'/psi)^2;
+ * accepted moves update Phi^-1 by the Woodbury identity.  State is refreshed
+ * by a full evaluation every refresh_every sweeps.  Random numbers: explicit
+ * noise [S][n][W][3] (xi) and unif [S][n][W] (u), or both NULL: then sweep t
+ * draws them on the device from the counter-based generator Philox4x32-10
+ * (Salmon et al., SC'11) with key seed and counter (w, e + 2^16 b, lo32(c),
+ * hi32(c)), c = counter + t, b = 0, 1, 2 (three blocks per proposal; 53-bit
+ * uniforms from pairs of words, xi by Box-Muller from blocks 0 and 1, u from
+ * block 2); a caller advances counter by n_sweeps between calls.  seed and
+ * counter are ignored with explicit numbers.  R is updated in place;
+ * n_accept [W] is incremented; logpsi/sign [W] receive the final values.
+ * FIRE_ERR_ARG when exactly one of noise and unif is NULL. */
 fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps,
-                            double step, const double* noise, const double* unif,
-                            int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
-                            hipStream_t stream);
+                            double step, const double* noise, const double* unif, uint64_t seed,
+                            uint64_t counter, int32_t* n_accept, double* logpsi, double* sign,
+                            int32_t* status, hipStream_t stream);
 
 /* Sweeps that mix the local moves of fire_mcmc_sweep with global
  * single-electron jumps (SI, improved Monte Carlo sampling: the
@@ -326,9 +335,7 @@ fire_status fire_batch_step(fire_batch* b, const int* W, double* R, void* state,
                             double step, const double* noise, const double* unif, int32_t* n_accept,
                             double* e_loc, double* grad, int32_t* status, hipStream_t stream);
 /* Capture fire_batch_step with these exact arguments into a HIP graph (the
- * buffers are bound into it: a replay reads their contents at launch time).
- * Refused (FIRE_ERR_ARG) when a system has nonlocal pseudopotential channels,
- * whose launches are sized on the host. */
+ * buffers are bound into it: a replay reads their contents at launch time). */
 fire_status fire_batch_graph_create(fire_batch* b, const int* W, double* R, void* state, void* ws, int n_sweeps,
                                     double step, const double* noise, const double* unif, int32_t* n_accept,
                                     double* e_loc, double* grad, int32_t* status, fire_graph** out);

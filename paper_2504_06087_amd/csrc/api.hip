@@ -2,6 +2,8 @@
 // and the entry points.  All device work runs in the other translation units.
 #include <string.h>
 
+#include <mutex>
+
 #include <string>
 #include <vector>
 
@@ -171,6 +173,48 @@ const char* fire_status_string(fire_status s) {
   return "unknown status";
 }
 
+// Largest number of pseudo-atoms whose r_max-balls share a point.  Atoms
+// whose balls share a point are pairwise closer than 2 r_max, so the largest
+// clique of the graph "closer than 2 r_max" bounds it (a branch-and-bound
+// search; the graphs are sparse).
+static int clique_max(const std::vector<std::vector<char>>& adj, const std::vector<int>& cand, int size, int best) {
+  if (cand.empty()) return size > best ? size : best;
+  for (size_t a = 0; a < cand.size(); ++a) {
+    if (size + (int)(cand.size() - a) <= best) break;
+    std::vector<int> next;
+    for (size_t b = a + 1; b < cand.size(); ++b)
+      if (adj[cand[a]][cand[b]]) next.push_back(cand[b]);
+    best = clique_max(adj, next, size + 1, best);
+  }
+  return best;
+}
+
+static int ecp_atoms_bound(const fire_handle* h) {
+  std::vector<int> at;
+  for (int m = 0; m < h->D.M; ++m)
+    for (const EcpChan& c : h->ecp)
+      if (c.species == h->species[m]) { at.push_back(m); break; }
+  const int na = (int)at.size();
+  if (na == 0) return 0;
+  const double lim = 4.0 * h->ecp_rmax * h->ecp_rmax;
+  std::vector<std::vector<char>> adj(na, std::vector<char>(na, 0));
+  for (int a = 0; a < na; ++a)
+    for (int b = 0; b < na; ++b) {
+      const double* p = &h->Rn[3 * at[a]];
+      const double* q = &h->Rn[3 * at[b]];
+      const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+      adj[a][b] = a != b && dx * dx + dy * dy + dz * dz < lim;
+    }
+  int best = 1;
+  for (int a = 0; a < na; ++a) {
+    std::vector<int> nb;
+    for (int b = a + 1; b < na; ++b)
+      if (adj[a][b]) nb.push_back(b);
+    best = clique_max(adj, nb, 1, best);
+  }
+  return best;
+}
+
 fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, fire_handle** out) {
   if (!sys || !md || !out || !sys->R_nuc || !sys->Z || !sys->species || !sys->nuc_type || !sys->pp_width)
     return FIRE_ERR_ARG;
@@ -211,6 +255,7 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
     h->ecp.push_back(e);
   }
   h->ecp_rmax = sys->ecp_rmax;
+  h->ecp_pmax = ecp_atoms_bound(h);
   h->tsize = D.prec == FIRE_FP64 ? 8 : 4;
   h->gsize = D.prec == FIRE_FP64 ? 8 : (D.prec == FIRE_FP32 ? 4 : 2);
   h->isize = D.prec == FIRE_FP32 ? 4 : 8;
@@ -233,6 +278,7 @@ fire_status fire_destroy(fire_handle* h) {
     (void)hipStreamDestroy(h->side_ecp);
   }
   if (h && h->side_ecp_join) (void)hipEventDestroy(h->side_ecp_join);
+  if (h && h->side_ecp_fork) (void)hipEventDestroy(h->side_ecp_fork);
   if (h && h->side_fork) (void)hipEventDestroy(h->side_fork);
   if (h && h->side_join) (void)hipEventDestroy(h->side_join);
   delete h;
@@ -362,6 +408,17 @@ extern "C" {
 
 fire_status fire_set_overlap(fire_handle* h, int on) {
   if (!h) return FIRE_ERR_ARG;
+  if (on) {
+    // the streams and events of the overlapped schedule, created once here
+    // (default priority) so that compute calls never change the handle
+    std::lock_guard<std::mutex> lock(fire::handle_mutex());
+    bool ok = true;
+    if (!h->side) ok = ok && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
+    if (!h->side_ecp) ok = ok && hipStreamCreateWithFlags(&h->side_ecp, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t* ev : {&h->side_fork, &h->side_join, &h->side_ecp_fork, &h->side_ecp_join})
+      if (!*ev) ok = ok && hipEventCreateWithFlags(ev, hipEventDisableTiming) == hipSuccess;
+    if (!ok) return FIRE_ERR_HIP;
+  }
   h->overlap = on != 0;
   return FIRE_OK;
 }
@@ -390,13 +447,13 @@ fire_status fire_eval_logpsi(fire_handle* h, int W, const double* R, void* state
 }
 
 fire_status fire_mcmc_sweep(fire_handle* h, int W, double* R, void* state, void* ws, int n_sweeps, double step,
-                            const double* noise, const double* unif, int32_t* n_accept, double* logpsi,
-                            double* sign, int32_t* status, hipStream_t s) {
+                            const double* noise, const double* unif, uint64_t seed, uint64_t counter,
+                            int32_t* n_accept, double* logpsi, double* sign, int32_t* status, hipStream_t s) {
   fire_status st = check_call(h, W, R, state, ws, status);
   if (st != FIRE_OK) return st;
-  if (n_sweeps < 0 || !noise || !unif || !n_accept || !(step >= 0)) return FIRE_ERR_ARG;
+  if (n_sweeps < 0 || (!noise) != (!unif) || !n_accept || !(step >= 0)) return FIRE_ERR_ARG;
   hipError_t e = mcmc_sweep_path(h, W, R, (char*)state, (char*)ws, n_sweeps, step, 0.0, nullptr, noise, unif,
-                                 nullptr, n_accept, logpsi, sign, status, s);
+                                 nullptr, seed, counter, n_accept, logpsi, sign, status, s);
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
@@ -427,7 +484,7 @@ fire_status fire_mcmc_sweep_mixed(fire_handle* h, int W, double* R, void* state,
   }
   if (any_global && (!pick || !(global_step > 0) || !isfinite(global_step))) return FIRE_ERR_ARG;
   hipError_t e = mcmc_sweep_path(h, W, R, (char*)state, (char*)ws, n_sweeps, step, global_step, kinds, noise,
-                                 unif, pick, n_accept, logpsi, sign, status, s);
+                                 unif, pick, 0, 0, n_accept, logpsi, sign, status, s);
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 

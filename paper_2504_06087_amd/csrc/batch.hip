@@ -21,7 +21,6 @@ struct fire_batch {
   std::vector<int64_t> P_sys;      // full theta size of each system
   std::vector<int64_t> priv_off;   // offset of system s's private block in the batch theta
   int64_t P_total = 0;
-  bool any_ecp = false;
   int n_branch = 0;
   std::vector<hipStream_t> streams;
   hipStream_t capture = nullptr;
@@ -206,7 +205,7 @@ static fire_status enqueue_system(fire_batch* b, int s, const SysOff& o, const S
   fire_status r = fire_eval_logpsi(h, W, R, state, ws, sign, lpsi, s0, st);
   if (r != FIRE_OK) return r;
   if (a.n_sweeps > 0) {
-    r = fire_mcmc_sweep(h, W, R, state, ws, a.n_sweeps, a.step, a.noise + o.noise0, a.unif + o.unif0,
+    r = fire_mcmc_sweep(h, W, R, state, ws, a.n_sweeps, a.step, a.noise + o.noise0, a.unif + o.unif0, 0, 0,
                         a.n_accept + o.walker0, lpsi, sign, s1, st);
     if (r != FIRE_OK) return r;
   } else if (fill_i32(s1, W, 0, st) != hipSuccess) {
@@ -280,7 +279,6 @@ fire_status fire_batch_create(const fire_system_desc* systems, int n_systems, co
     h->lap_budget = (size_t)12 << 30;   // per branch at most one system's Laplacian chunk is live
     b->sys.push_back(h);
     b->n_el.push_back(n);
-    if (!h->ecp.empty()) b->any_ecp = true;
   }
   if (r == FIRE_OK) {
     // every entry before the orbital block is shared and must agree in shape
@@ -383,7 +381,6 @@ fire_status fire_batch_graph_create(fire_batch* b, const int* W, double* R, void
   if (!out) return FIRE_ERR_ARG;
   if (!b || !W || !R || !state || !ws || !e_loc || !grad || !status || n_sweeps < 0) return FIRE_ERR_ARG;
   if (n_sweeps > 0 && (!noise || !unif || !n_accept)) return FIRE_ERR_ARG;
-  if (b->any_ecp) return FIRE_ERR_ARG;   // the quadrature path sizes its launches on the host
   for (fire_handle* h : b->sys)
     if (!h->params) return FIRE_ERR_STATE;
   StepArgs a{W, R, (char*)state, (char*)ws, n_sweeps, step, noise, unif, n_accept, e_loc, grad, status};

@@ -121,13 +121,26 @@ __global__ __launch_bounds__(1024) void k_ecp_scan(int W, const int* __restrict_
   for (int w = b; w < en; ++w) { o[w] = a; a += c[w]; }
 }
 
-// jobs [j0, j0 + J) of electron e: walker, new position and quadrature weight
-__global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const double* __restrict__ R,
+// jobs [j0, j0 + Jc) of electron e: walker, new position and quadrature
+// weight.  The chunk's live job count min(max(tot_e - j0, 0), Jc) comes from
+// the device total tot_e and is written to *jdev for the kernels that follow;
+// jobs beyond it are inactive (walker 0, weight 0).
+__global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int Jc, const int* __restrict__ tot_e,
+                           int* __restrict__ jdev, const double* __restrict__ R,
                            const double* __restrict__ Rn, const int* __restrict__ species, EcpTables t,
                            const double* __restrict__ quad_rot, const int* __restrict__ off, int* __restrict__ jw,
                            double* __restrict__ rexp, double* __restrict__ cf) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+  if (j >= Jc) return;
+  int J = *tot_e - j0;
+  J = J < 0 ? 0 : (J > Jc ? Jc : J);
+  if (j == 0) *jdev = J;
+  if (j >= J) {
+    jw[j] = 0;
+    rexp[3 * j] = R[3 * e]; rexp[3 * j + 1] = R[3 * e + 1]; rexp[3 * j + 2] = R[3 * e + 2];
+    cf[j] = 0.0;
+    return;
+  }
   const int jg = j0 + j;
   // walker: last w with off[w] <= jg
   int lo = 0, hi = W - 1;
@@ -185,11 +198,12 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int J, const doub
 // contribution of each job: coefficient * psi'/psi with
 // psi'/psi = e^{dJ} sum_d w_d prod_s det A_ds,  w_d = s_d e^{l_d} / sum_d s_d e^{l_d}
 // (dJ: the job's change of log J_cusp)
-__global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__ jw, const double* __restrict__ cf,
-                            const double* __restrict__ detA, const double* __restrict__ dj,
-                            const char* __restrict__ state, StateRec S, double* __restrict__ contrib) {
+__global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__ jdev, const int* __restrict__ jw,
+                            const double* __restrict__ cf, const double* __restrict__ detA,
+                            const double* __restrict__ dj, const char* __restrict__ state, StateRec S,
+                            double* __restrict__ contrib) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+  if (j >= J || j >= *jdev) return;
   const int w = jw[j];
   const char* rec = state + (int64_t)w * S.stride;
   const double* ds = (const double*)(rec + S.dsign);
@@ -236,7 +250,7 @@ struct EcpLayout {
   int Jc;
   size_t cnt, off, tot;
   size_t lane[2];                                  // lane bases
-  size_t jw, rexp, cf, contrib, vnl, upd;          // offsets within a lane
+  size_t jw, rexp, cf, contrib, vnl, jdev, upd;    // offsets within a lane
   size_t total;
 };
 
@@ -262,6 +276,7 @@ static EcpLayout ecp_layout(const fire_handle* h, int W, int lanes) {
   L.cf = ltake((size_t)L.Jc * 8);
   L.contrib = ltake((size_t)W * ECP_PMAX * NQ * 8);
   L.vnl = ltake((size_t)W * 8);
+  L.jdev = ltake(4);
   L.upd = q;
   q = align_up(q + upd_layout(h, L.Jc, false).total);
   L.lane[0] = o;
@@ -276,13 +291,27 @@ size_t ecp_ws_bytes(const fire_handle* h, int W) {
   return a > b ? a : b;
 }
 
+// Chunks per electron.  An electron is within r_max of at most ecp_pmax
+// pseudo-atoms (a bound fixed by the geometry at handle creation), so it has
+// at most W * ecp_pmax * (largest rule) jobs; the chunk loop covers that
+// bound and each chunk reads its live job count on the device, so no count
+// is read back to the host.
+static int ecp_chunks(const fire_handle* h, int W, int Jc) {
+  int nqmax = 0;
+  for (const EcpChan& c : h->ecp) nqmax = c.nquad > nqmax ? c.nquad : nqmax;
+  const int pm = h->ecp_pmax < ECP_PMAX ? h->ecp_pmax : ECP_PMAX;
+  const int64_t bound = (int64_t)W * pm * nqmax;
+  return (int)((bound + Jc - 1) / Jc);
+}
+
 template <typename T>
 static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* state, char* ws,
                            const double* quad_rot, double* vnl, int32_t* status, hipStream_t st) {
   const Dims& D = h->D;
   const StateRec& S = h->st;
   Net<T> P = make_net<T>(h);
-  const int lanes = h->overlap ? 2 : 1;
+  const int lanes = (h->overlap && h->side_ecp) ? 2 : 1;
+  AutotuneHold hold(lanes == 2);
   const EcpLayout L = ecp_layout(h, W, lanes);
   const EcpTables tb = tables(h);
   const UpdLayout U = upd_layout(h, L.Jc, false);
@@ -291,8 +320,8 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   int* tot = (int*)(ws + L.tot);
   const int* sp_dev = (const int*)((const char*)h->params + h->pl.species);
   // lane 0 accumulates into vnl on the caller's stream, lane 1 into its own
-  // sum on the handle's pseudopotential stream; both are cleared here, before
-  // the host waits on st, so lane 1 needs no event to start after them
+  // sum on the handle's pseudopotential stream, which starts after the
+  // counts (fork event)
   double* vl[2] = {vnl, (double*)(ws + L.lane[1] + L.vnl)};
   for (int l = 0; l < lanes; ++l) {
     hipLaunchKernelGGL(k_fill_f64, dim3((W + 255) / 256), dim3(256), 0, st, vl[l], (int64_t)W, 0.0);
@@ -303,19 +332,17 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_ecp_scan, dim3(D.n), dim3(1024), 0, st, W, (const int*)cnt, off, tot);
   CHECK(hipGetLastError());
-  std::vector<int> htot(D.n);
-  CHECK(hipMemcpyAsync(htot.data(), tot, (size_t)D.n * 4, hipMemcpyDeviceToHost, st));
-  CHECK(hipStreamSynchronize(st));
   hipStream_t ls[2] = {st, st};
   if (lanes == 2) {
+    // record and wait as one step, so that concurrent calls on other streams
+    // cannot move the fork point
     std::lock_guard<std::mutex> lock(handle_mutex());
-    if (!h->side_ecp) CHECK(hipStreamCreateWithFlags(&h->side_ecp, hipStreamNonBlocking));
-    if (!h->side_ecp_join) CHECK(hipEventCreateWithFlags(&h->side_ecp_join, hipEventDisableTiming));
+    CHECK(hipEventRecord(h->side_ecp_fork, st));
+    CHECK(hipStreamWaitEvent(h->side_ecp, h->side_ecp_fork, 0));
     ls[1] = h->side_ecp;
   }
+  const int nch = ecp_chunks(h, W, L.Jc);
   for (int e = 0; e < D.n; ++e) {
-    const int Te = htot[e];
-    if (Te == 0) continue;
     const int ln = lanes == 2 ? (e & 1) : 0;
     hipStream_t ss = ls[ln];
     char* lb = ws + L.lane[ln];
@@ -323,23 +350,25 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
     double* rexp = (double*)(lb + L.rexp);
     double* cf = (double*)(lb + L.cf);
     double* contrib = (double*)(lb + L.contrib);
+    int* jdev = (int*)(lb + L.jdev);
     char* uws = lb + L.upd;
     const int* offe = off + (int64_t)e * (W + 1);
-    for (int j0 = 0; j0 < Te; j0 += L.Jc) {
-      const int J = Te - j0 < L.Jc ? Te - j0 : L.Jc;
-      hipLaunchKernelGGL(k_ecp_jobs, dim3((J + 255) / 256), dim3(256), 0, ss, D, W, e, j0, J, R, P.Rn, sp_dev, tb,
-                         quad_rot, offe, jw, rexp, cf);
+    for (int c = 0; c < nch; ++c) {
+      const int j0 = c * L.Jc;
+      hipLaunchKernelGGL(k_ecp_jobs, dim3((L.Jc + 255) / 256), dim3(256), 0, ss, D, W, e, j0, L.Jc,
+                         (const int*)(tot + e), jdev, R, P.Rn, sp_dev, tb, quad_rot, offe, jw, rexp, cf);
       CHECK(hipGetLastError());
       Jobs jb{};
-      jb.J = J;
+      jb.J = L.Jc;
       jb.Jcap = L.Jc;
+      jb.Jdev = jdev;
       jb.group = tb.nq[0];   // the jobs of one (electron, pseudo-atom) pair are consecutive
       jb.jw = jw;
       jb.rexp = rexp;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, ss));
-      hipLaunchKernelGGL(k_ecp_ratio, dim3((J + 255) / 256), dim3(256), 0, ss, D, J, j0, (const int*)jw,
-                         (const double*)cf, (const double*)(uws + U.detA), (const double*)(uws + U.dj),
-                         (const char*)state, S, contrib);
+      hipLaunchKernelGGL(k_ecp_ratio, dim3((L.Jc + 255) / 256), dim3(256), 0, ss, D, L.Jc, j0, (const int*)jdev,
+                         (const int*)jw, (const double*)cf, (const double*)(uws + U.detA),
+                         (const double*)(uws + U.dj), (const char*)state, S, contrib);
       CHECK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_ecp_reduce, dim3((W + 255) / 256), dim3(256), 0, ss, W, offe, (const double*)contrib, vl[ln]);

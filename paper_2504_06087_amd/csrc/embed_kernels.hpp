@@ -131,7 +131,9 @@ template <typename T, int NR> FIRE_DEV void block_sums(T (&v)[NR], T* red) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __restrict__ R, int64_t nrows,
-                                                  T* __restrict__ y_out, int epb) {
+                                                  T* __restrict__ y_out, int epb, const int* __restrict__ nrows_dev) {
+  // rows at or beyond a device row count (when given) are inactive
+  if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
   constexpr int ERB = sizeof(T) == 4 ? 4 : 2;   // electrons per pass (LDS: ERB x MCH pair features)
   const Dims& D = P.D;
   __shared__ T feat[ERB * MCH * FEAT];
@@ -221,7 +223,9 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
 
 // GLU gate: t = u * SiLU(g) with [u | g] the two halves of each row of ug.
 template <typename T>
-__global__ void k_glu(const T* __restrict__ ug, T* __restrict__ out, int64_t nrows, int d) {
+__global__ void k_glu(const T* __restrict__ ug, T* __restrict__ out, int64_t nrows, int d,
+                      const int* __restrict__ nrows_dev) {
+  if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nrows * d) return;
   int64_t r = i / d;
@@ -232,8 +236,10 @@ __global__ void k_glu(const T* __restrict__ ug, T* __restrict__ out, int64_t nro
 
 // Envelope basis exp(-sigma_me |r_i - R_m|), row e = (w, i), column m*E + k.
 template <typename T>
-__global__ void k_env_basis(Net<T> P, const double* __restrict__ R, int64_t nrows, T* __restrict__ out) {
+__global__ void k_env_basis(Net<T> P, const double* __restrict__ R, int64_t nrows, T* __restrict__ out,
+                            const int* __restrict__ nrows_dev) {
   const Dims& D = P.D;
+  if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
   int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= nrows * D.B) return;
   int64_t e = q / D.B;

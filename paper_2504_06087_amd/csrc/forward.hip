@@ -370,7 +370,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
 
   hipLaunchKernelGGL(k_nbr, dim3(W), dim3(256), 0, s, R, W, D.n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt, status);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y, EPB);
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y, EPB, (const int*)nullptr);
   CHECK(hipGetLastError());
   // GLU: [u | g] = y [W_v | W_g] + [b_v | b_g];  t = u * SiLU(g);  h0 = t W_o + b_o
   {
@@ -380,7 +380,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.M = (int)rows; g.N = 2 * D.d; g.K = D.d; g.act = ACT_NONE;
     CHECK(gemm_site(h, SITE_EMB, g, s));
   }
-  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * D.d + 255) / 256)), dim3(256), 0, s, ug, y, rows, D.d);
+  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * D.d + 255) / 256)), dim3(256), 0, s, ug, y, rows, D.d, (const int*)nullptr);
   CHECK(hipGetLastError());
   {
     GemmArgs g{};
@@ -413,7 +413,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     T* t = hin; hin = hout; hout = t;
   }
   // envelopes and orbitals per spin block
-  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, s, P, R, rows, basis);
+  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, s, P, R, rows, basis, (const int*)nullptr);
   CHECK(hipGetLastError());
   for (int sp = 0; sp < 2; ++sp) {
     const int N = D.nsig(sp), e0 = sp == 0 ? 0 : D.nu;

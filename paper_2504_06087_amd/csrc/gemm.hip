@@ -694,6 +694,7 @@ struct Tuner {
   std::mutex mu;
   std::map<TuneKey, int> choice;
   bool on = false;
+  int held = 0;   // > 0 while an overlapped call enqueues: no timing then
 };
 static Tuner& tuner() {
   static Tuner t;
@@ -826,7 +827,7 @@ template <int KIND> static int pick_variant(const GemmArgs& g, hipStream_t s, in
     std::lock_guard<std::mutex> lk(t.mu);
     auto it = t.choice.find(key);
     if (it != t.choice.end()) return it->second;
-    if (!t.on || g.accumulate || g.prof_rows || g.Mdev) return 0;
+    if (!t.on || t.held > 0 || g.accumulate || g.prof_rows || g.Mdev) return 0;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
@@ -867,6 +868,12 @@ template <int KIND> static hipError_t launch(GemmArgs g, hipStream_t s) {
   hipError_t e = launch_variant<KIND>(v, g, s, vecA, vecB);
   if (prof) (void)hipEventRecord(evs[2 * slot + 1], s);
   return e;
+}
+
+void autotune_hold(int delta) {
+  Tuner& t = tuner();
+  std::lock_guard<std::mutex> lk(t.mu);
+  t.held += delta;
 }
 
 hipError_t autotune_set(int on) {

@@ -74,7 +74,15 @@ hipError_t profile_end(hipStream_t s, int64_t* launches, double* ms, double* flo
 hipError_t gemm(int kind, const GemmArgs& g, hipStream_t s);
 
 // Tile autotuner (process-wide): on/off, number of tuned shapes, clear,
-// save/load of the choices as text.
+// save/load of the choices as text.  autotune_hold(+1 / -1) brackets work
+// whose GEMMs share the chip with other streams (overlapped calls): no shape
+// is timed while a hold is active, so no contended timing is kept.
+void autotune_hold(int delta);
+struct AutotuneHold {
+  bool on;
+  explicit AutotuneHold(bool o) : on(o) { if (on) autotune_hold(1); }
+  ~AutotuneHold() { if (on) autotune_hold(-1); }
+};
 hipError_t autotune_set(int on);
 int autotune_count();
 void autotune_clear();

@@ -874,7 +874,7 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
   hipLaunchKernelGGL(k_nbr, dim3(Wc), dim3(256), 0, st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
                      status + w0);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, st, P, Rc, rows, y, EPB);
+  hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, st, P, Rc, rows, y, EPB, (const int*)nullptr);
   CHECK(hipGetLastError());
   {
     GemmArgs g{};
@@ -882,7 +882,7 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
     g.C = ug; g.cmap = rows_dense(2 * d); g.ccol = cols_dense(); g.M = (int)rows; g.N = 2 * d; g.K = d;
     CHECK(gemm_site(h, SITE_EMB, g, st));
   }
-  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, (const T*)ug, tt, rows, d);
+  hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, (const T*)ug, tt, rows, d, (const int*)nullptr);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_h1_from_state<T>, dim3((unsigned)((rows * d + 255) / 256)), dim3(256), 0, st, D, Wc, w0,
                      (const char*)state, S, hk);
@@ -898,7 +898,7 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
     CHECK(hipGetLastError());
   }
   const T* hL = hk + (int64_t)D.L * rows * d;
-  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, st, P, Rc, rows, basis);
+  hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, st, P, Rc, rows, basis, (const int*)nullptr);
   CHECK(hipGetLastError());
 
   // ---- orbitals and envelopes backward

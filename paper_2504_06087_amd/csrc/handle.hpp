@@ -69,16 +69,19 @@ struct fire_handle {
   void* params;                 // device params buffer (set by fire_set_params)
   size_t lap_budget;            // workspace bytes the Laplacian's walker chunks may use
   const double* theta_dev;      // theta passed to fire_set_params
+  // most pseudo-atoms within ecp_rmax of any one point (from the geometry)
+  int ecp_pmax = 0;
   // second stream of the local energy: the kinetic energy runs on it beside
-  // the pseudopotential on the caller's stream (created on first use, default
-  // priority), with the events that order it against the caller's stream
+  // the pseudopotential on the caller's stream (default priority), with the
+  // events that order it against the caller's stream; and a third stream
+  // that takes every other electron's quadrature jobs, with its fork and join
+  // events.  All are created by fire_set_overlap and live until
+  // fire_destroy; compute calls never create or change them.
   bool overlap = false;         // fire_set_overlap
   hipStream_t side = nullptr;
   hipEvent_t side_fork = nullptr, side_join = nullptr;
-  // second stream of the pseudopotential (every other electron's quadrature
-  // jobs) and its join event; created on first use under handle_mutex()
-  mutable hipStream_t side_ecp = nullptr;
-  mutable hipEvent_t side_ecp_join = nullptr;
+  hipStream_t side_ecp = nullptr;
+  hipEvent_t side_ecp_fork = nullptr, side_ecp_join = nullptr;
 };
 
 namespace fire {

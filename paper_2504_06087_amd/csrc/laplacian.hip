@@ -839,12 +839,10 @@ static hipError_t local_energy_impl(fire_handle* h, int W, const double* R, char
   // cannot swap their fork points; a later record of the join event lies
   // later on the serial side stream, so waiting on it is never too early.
   hipStream_t ks = st;
-  const bool fork = has_ecp && h->overlap;
+  const bool fork = has_ecp && h->overlap && h->side;
+  AutotuneHold hold(fork);
   if (fork) {
     std::lock_guard<std::mutex> lock(handle_mutex());
-    if (!h->side) CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-    if (!h->side_fork) CHECK(hipEventCreateWithFlags(&h->side_fork, hipEventDisableTiming));
-    if (!h->side_join) CHECK(hipEventCreateWithFlags(&h->side_join, hipEventDisableTiming));
     CHECK(hipEventRecord(h->side_fork, st));
     CHECK(hipStreamWaitEvent(h->side, h->side_fork, 0));
     ks = h->side;

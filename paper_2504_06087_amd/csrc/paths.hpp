@@ -8,10 +8,14 @@ size_t workspace_bytes_for(const fire_handle* h, int W);
 
 // kinds (host [n_sweeps], NULL: all local): 1 marks a sweep of global jumps,
 // which read pick [S][n][W] and the scale gstep
+// noise == NULL: each sweep draws its numbers from the counter-based
+// generator (key seed, counter base counter + sweep index)
 hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
                            double gstep, const int32_t* kinds, const double* noise, const double* unif,
-                           const double* pick, int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
-                           hipStream_t s);
+                           const double* pick, uint64_t seed, uint64_t counter, int32_t* n_accept, double* logpsi,
+                           double* sign, int32_t* status, hipStream_t s);
+size_t rng_ws_offset(const fire_handle* h, int W);
+size_t rng_ws_bytes(const fire_handle* h, int W);
 hipError_t local_energy_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,
                              double* e_loc, double* parts, double* grad_logpsi, int32_t* status, hipStream_t s);
 hipError_t ecp_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* quad_rot,

@@ -10,6 +10,7 @@
 // update G by the Woodbury identity in one read-modify-write pass:
 //   G' = G - (G dPhi_U^T) A^-T G_U.
 #include "update.hpp"
+#include "rng.hpp"
 
 #include "embed_kernels.hpp"
 #include "linalg.hpp"
@@ -766,11 +767,13 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
                                                    const T* __restrict__ dphi, const T* __restrict__ oseg,
                                                    const T* __restrict__ envnew, int fused,
                                                    const char* __restrict__ state, StateRec S,
-                                                   double* __restrict__ detA, int jg) {
+                                                   double* __restrict__ detA, int jg, const int* __restrict__ Jdev) {
   __shared__ double abuf[4][4 * 16 * 17];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t quad = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
-  const int ngroups = (W + jg - 1) / jg;
+  // jobs at or beyond a device job count (when given) are inactive
+  const int Wact = Jdev && *Jdev < W ? *Jdev : W;
+  const int ngroups = (Wact + jg - 1) / jg;
   const int64_t total = (int64_t)ngroups * D.K * jg;
   if (quad * 4 >= total) return;
   const int N = D.nsig(s), KN = D.K * N;
@@ -788,7 +791,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
       const int det = (int)((item / jg) % D.K);
       const int g = (int)(item / ((int64_t)jg * D.K));
       const int j = g * jg + gq;
-      if (j < W) {
+      if (j < Wact) {
         jq[q] = j;
         dq[q] = det;
         kqv[q] = ucnt[2 * j + s];
@@ -870,17 +873,18 @@ __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const 
                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
                                                   const T* __restrict__ envnew, int fused,
                                                   const char* __restrict__ state, StateRec S,
-                                                  double* __restrict__ detA, int jg) {
+                                                  double* __restrict__ detA, int jg, const int* __restrict__ Jdev) {
   __shared__ double abuf[4][32 * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t item = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
-  const int ngroups = (W + jg - 1) / jg;
+  const int Wact = Jdev && *Jdev < W ? *Jdev : W;
+  const int ngroups = (Wact + jg - 1) / jg;
   if (item >= (int64_t)ngroups * D.K * jg) return;
   const int gq = (int)(item % jg);
   const int det = (int)((item / jg) % D.K);
   const int g = (int)(item / ((int64_t)jg * D.K));
   const int j = g * jg + gq;
-  if (j >= W) return;
+  if (j >= Wact) return;
   const int k = ucnt[2 * j + s];
   if (k <= 16 || k > 32) return;
   const int w = jw ? jw[j] : j;
@@ -1523,25 +1527,28 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   // h0 and projections of the moved electron
   const int epb = W >= 16384 ? 4 : (W >= 4096 ? 2 : 1);
   hipLaunchKernelGGL(k_en_embed<T>, dim3((W + epb - 1) / epb), dim3(blk), 0, st, P, (const double*)rnew,
-                     (int64_t)W, y, epb);
+                     (int64_t)W, y, epb, jb.Jdev);
   CHECK(hipGetLastError());
   {
     GemmArgs g{};
     g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wvg_t; g.ldb = D.d; g.bias = P.b_vg;
     g.C = ug; g.cmap = rows_dense(2 * D.d); g.ccol = cols_dense(); g.M = W; g.N = 2 * D.d; g.K = D.d;
+    g.Mdev = jb.Jdev;
     CHECK(gemm_site(h, SITE_EMB, g, st));
   }
   hipLaunchKernelGGL(k_glu<T>, dim3((unsigned)(((int64_t)W * D.d + 255) / 256)), dim3(256), 0, st, ug, y,
-                     (int64_t)W, D.d);
+                     (int64_t)W, D.d, jb.Jdev);
   CHECK(hipGetLastError());
   {
     GemmArgs g{};
     g.A = y; g.amap = rows_dense(D.d); g.Bt = P.Wo_t; g.ldb = D.d; g.bias = P.b_o;
     g.C = h0new; g.cmap = rows_dense(D.d); g.ccol = cols_dense(); g.M = W; g.N = D.d; g.K = D.d;
+    g.Mdev = jb.Jdev;
     CHECK(gemm_site(h, SITE_EMB, g, st));
     GemmArgs p{};
     p.A = h0new; p.amap = rows_dense(D.d); p.Bt = P.Wproj_t; p.ldb = D.d;
     p.C = projnew; p.cmap = rows_dense(4 * D.d); p.ccol = cols_dense(); p.M = W; p.N = 4 * D.d; p.K = D.d;
+    p.Mdev = jb.Jdev;
     CHECK(gemm_site(h, SITE_EMB, p, st));
   }
   T* hs[2][2];
@@ -1559,13 +1566,14 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   CHECK(hipGetLastError());
   // envelopes of the moved electron at r_e'
   hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)(((int64_t)W * D.B + 255) / 256)), dim3(256), 0, st, P,
-                     (const double*)rnew, (int64_t)W, basis);
+                     (const double*)rnew, (int64_t)W, basis, jb.Jdev);
   CHECK(hipGetLastError());
   {
     const int N = D.nsig(se);
     GemmArgs g{};
     g.A = basis; g.amap = rows_dense(D.B); g.Bt = se == 0 ? P.pi0 : P.pi1; g.ldb = D.B;
     g.C = envnew; g.cmap = rows_dense((int64_t)D.K * N); g.ccol = cols_dense(); g.M = W; g.N = D.K * N; g.K = D.B;
+    g.Mdev = jb.Jdev;
     CHECK(gemm_site(h, SITE_ORB, g, st));
   }
   for (int s = 0; s < 2; ++s) {
@@ -1606,24 +1614,24 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
       hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg);
+                         (double*)(ws + L.detA), jg, jb.Jdev);
     else
       hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg);
+                         (double*)(ws + L.detA), jg, jb.Jdev);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
       if (h->isize == 8)
         hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg);
+                           S, (double*)(ws + L.detA), jg, jb.Jdev);
       else
         hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg);
+                           S, (double*)(ws + L.detA), jg, jb.Jdev);
       CHECK(hipGetLastError());
     }
     if (L.capS[s] > 32) {
@@ -1740,21 +1748,55 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
   return hipGetLastError();
 }
 
+// The random numbers of one sweep from the counter-based generator:
+// xi [n][W][3] and u [n][W] for sweep counter c.
+__global__ void k_sweep_randoms(int n, int W, uint64_t seed, uint64_t c, double* __restrict__ xi,
+                                double* __restrict__ u) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * W) return;
+  const int e = (int)(q / W), w = (int)(q % W);
+  double x[3], a;
+  proposal_randoms(seed, c, e, w, x, a);
+  xi[3 * q] = x[0];
+  xi[3 * q + 1] = x[1];
+  xi[3 * q + 2] = x[2];
+  u[q] = a;
+}
+
+// Workspace of the generated random numbers of one sweep: after the regions
+// of the update and of the periodic full re-evaluation, which share the start
+// of the workspace.
+size_t rng_ws_offset(const fire_handle* h, int W) {
+  const size_t a = upd_layout(h, W).total, b = ws_forward(h, W).total;
+  return align_up(a > b ? a : b);
+}
+size_t rng_ws_bytes(const fire_handle* h, int W) { return align_up((size_t)h->D.n * W * 4 * sizeof(double)); }
+
 template <typename T>
 static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
                              double gstep, const int32_t* kinds, const double* noise, const double* unif,
-                             const double* pick, int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
-                             hipStream_t st) {
+                             const double* pick, uint64_t seed, uint64_t counter, int32_t* n_accept,
+                             double* logpsi, double* sign, int32_t* status, hipStream_t st) {
   const Dims& D = h->D;
   Net<T> P = make_net<T>(h);
   CHECK(fill_i32(status, W, 0, st));
   const int refresh = h->model.refresh_every;
+  // without explicit random numbers each sweep draws its own into the
+  // workspace (counter base + sweep index)
+  const bool gen = noise == nullptr;
+  double* gxi = (double*)(ws + rng_ws_offset(h, W));
+  double* gu = gxi + (int64_t)D.n * W * 3;
   for (int sw = 0; sw < n_sweeps; ++sw) {
+    if (gen) {
+      hipLaunchKernelGGL(k_sweep_randoms, dim3((unsigned)(((int64_t)D.n * W + 255) / 256)), dim3(256), 0, st, D.n, W,
+                         seed, counter + (uint64_t)sw, gxi, gu);
+      CHECK(hipGetLastError());
+    }
     for (int e = 0; e < D.n; ++e) {
       Jobs jb{};
       jb.J = W;
       jb.woodbury = true;
-      jb.xi = noise + ((int64_t)sw * D.n + e) * W * 3;
+      jb.xi = gen ? gxi + (int64_t)e * W * 3 : noise + ((int64_t)sw * D.n + e) * W * 3;
       jb.step = step;
       const bool global = kinds && kinds[sw] == 1;
       if (global) {
@@ -1765,7 +1807,7 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
         jb.M = D.M;
         jb.lqf = (double*)(ws + upd_layout(h, W).lqf);
       }
-      const double* u = unif + ((int64_t)sw * D.n + e) * W;
+      const double* u = gen ? gu + (int64_t)e * W : unif + ((int64_t)sw * D.n + e) * W;
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, ws, status, st));
       CHECK(accept_and_commit<T>(h, W, e, R, u, global, state, ws, n_accept, status, st));
     }
@@ -1782,13 +1824,13 @@ static hipError_t sweep_impl(fire_handle* h, int W, double* R, char* state, char
 
 hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* ws, int n_sweeps, double step,
                            double gstep, const int32_t* kinds, const double* noise, const double* unif,
-                           const double* pick, int32_t* n_accept, double* logpsi, double* sign, int32_t* status,
-                           hipStream_t s) {
+                           const double* pick, uint64_t seed, uint64_t counter, int32_t* n_accept, double* logpsi,
+                           double* sign, int32_t* status, hipStream_t s) {
   if (!update_fits(h)) return hipErrorInvalidValue;
   return h->tsize == 8 ? sweep_impl<double>(h, W, R, state, ws, n_sweeps, step, gstep, kinds, noise, unif, pick,
-                                            n_accept, logpsi, sign, status, s)
+                                            seed, counter, n_accept, logpsi, sign, status, s)
                        : sweep_impl<float>(h, W, R, state, ws, n_sweeps, step, gstep, kinds, noise, unif, pick,
-                                           n_accept, logpsi, sign, status, s);
+                                           seed, counter, n_accept, logpsi, sign, status, s);
 }
 
 template hipError_t propose_ratio<double>(const fire_handle*, const Net<double>&, const Jobs&, int,

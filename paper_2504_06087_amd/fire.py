@@ -83,7 +83,7 @@ def load() -> ctypes.CDLL:
     lib.fire_set_overlap.argtypes = [P, I]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_eval_logpsi_noalloc.argtypes = [P, I, V, V, V, V, V, V]
-    lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, V, V, V, V, V]
+    lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, ctypes.c_uint64, ctypes.c_uint64, V, V, V, V, V]
     lib.fire_adapt_step.argtypes = [D, ctypes.c_int64, ctypes.c_int64, D, D, ctypes.POINTER(ctypes.c_double)]
     lib.fire_mcmc_sweep_mixed.argtypes = [P, I, V, V, V, I, D, D, ctypes.POINTER(ctypes.c_int32), V, V, V, V, V, V,
                                           V, V]
@@ -299,7 +299,10 @@ class Fire:
         self._touch(state)
         return sign, logpsi, status
 
-    def mcmc_sweep(self, R, state, ws, n_sweeps, step, noise, unif, n_accept=None):
+    def mcmc_sweep(self, R, state, ws, n_sweeps, step, noise=None, unif=None, n_accept=None, seed: int = 0,
+                   counter: int = 0):
+        """Metropolis sweeps; with noise and unif None the library draws the
+        random numbers itself (Philox4x32-10, key seed, counter base counter)."""
         W = R.shape[0]
         if n_accept is None:
             n_accept = torch.zeros(W, dtype=torch.int32, device=self.device)
@@ -307,8 +310,8 @@ class Fire:
         logpsi = torch.empty_like(sign)
         status = torch.empty(W, dtype=torch.int32, device=self.device)
         _check(load().fire_mcmc_sweep(self.h, W, _dp(R), _dp(state), _dp(ws), int(n_sweeps), float(step),
-                                      _dp(noise), _dp(unif), _dp(n_accept), _dp(logpsi), _dp(sign), _dp(status),
-                                      _stream()), "fire_mcmc_sweep")
+                                      _dp(noise), _dp(unif), int(seed), int(counter), _dp(n_accept), _dp(logpsi),
+                                      _dp(sign), _dp(status), _stream()), "fire_mcmc_sweep")
         self._touch(state)
         return n_accept, sign, logpsi, status
 

@@ -259,3 +259,44 @@ def test_step_adaptation_reaches_half_acceptance(lib):
     late = float(np.mean(rates[-10:]))
     log(f"first rate {rates[0]:.2f}, last ten {late:.3f}, final step {step:.3f}")
     assert rates[0] > 0.8 and abs(late - 0.5) < 0.06
+
+
+def test_counter_based_rng_chain_matches_oracle(lib):
+    """fire_mcmc_sweep with no explicit random numbers draws them from
+    Philox4x32-10 on the device; the oracle's chain driven by the host
+    implementation of the same generator (written separately from its
+    published definition) makes the same accept decisions and reaches the
+    same positions.  Two calls in a row advance the counter base; explicit
+    numbers equal to the generated ones give the same chain; passing
+    only one of noise and unif is refused."""
+    from oracle.philox import sweep_randoms
+    from paper_2504_06087_amd import fire
+    log("case: H4 fp64 W=16, counter-based random numbers, 2 + 1 sweeps")
+    F, O, s, m, p, R, state, ws = setup(0, 16, "fp64")
+    n, W, seed, c0 = s.n_el, 16, 0x1234abcd9876, 41
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    nacc = torch.zeros(W, dtype=torch.int32, device="cuda")
+    F.mcmc_sweep(Rd, state, ws, 2, 0.2, None, None, nacc, seed=seed, counter=c0)
+    _, _, lp, st = F.mcmc_sweep(Rd, state, ws, 1, 0.2, None, None, nacc, seed=seed, counter=c0 + 2)
+    torch.cuda.synchronize()
+    draws = [sweep_randoms(seed, c0, t, n, W) for t in range(3)]
+    xi = np.stack([d[0] for d in draws])
+    u = np.stack([d[1] for d in draws])
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.2, xi, u)
+    dR = np.abs(Rd.cpu().numpy() - Ro.numpy()).max()
+    log(f"accepts {int(nacc.sum())} (oracle {int(no.sum())}), max |dR| {dR:.1e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(nacc.cpu().numpy(), no.numpy())
+    assert dR <= 1e-12
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    # the host's numbers passed explicitly give the same chain (the two
+    # generators' logarithms and sines may differ in the last bit)
+    R2 = dev(R)
+    F.eval_logpsi(R2, state, ws)
+    n2 = torch.zeros(W, dtype=torch.int32, device="cuda")
+    F.mcmc_sweep(R2, state, ws, 3, 0.2, dev(xi), dev(u), n2)
+    torch.cuda.synchronize()
+    assert torch.equal(n2, nacc) and float((R2 - Rd).abs().max()) <= 1e-13
+    with pytest.raises(fire.FireError):
+        F.mcmc_sweep(R2, state, ws, 1, 0.2, dev(xi), None, n2)

@@ -719,3 +719,40 @@ def test_jastrow_is_symmetric_and_zero_by_default():
     Rs[:, [0, 1]] = Rs[:, [1, 0]]          # same-spin swap
     Rs[:, [2, 3]] = Rs[:, [3, 2]]
     assert torch.allclose(o1.jastrow_cusp(R), o1.jastrow_cusp(Rs), atol=1e-14, rtol=0)
+
+
+# --------------------------------------------------------------------------
+# the counter-based generator of the sampler's own random numbers
+# --------------------------------------------------------------------------
+def test_philox_known_answer_vectors():
+    """Philox4x32-10 reproduces the published known-answer vectors."""
+    import os
+    from oracle.philox import philox4x32_10
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_sweep_randoms_distribution():
+    """The Metropolis draws: uniforms inside (0, 1) with mean 1/2 and
+    variance 1/12, normals with mean 0, variance 1 and kurtosis 3 (within
+    five standard errors over 2^17 draws); different sweeps, electrons and
+    walkers give different numbers."""
+    from oracle.philox import sweep_randoms
+    xi, u = sweep_randoms(12345, 7, 0, 128, 1024)
+    assert xi.shape == (128, 1024, 3) and u.shape == (128, 1024)
+    assert (u > 0).all() and (u < 1).all()
+    N = u.size
+    assert abs(u.mean() - 0.5) < 5 * np.sqrt(1 / 12 / N)
+    assert abs(u.var() - 1 / 12) < 5 * np.sqrt(1 / 180 / N)
+    z = xi.reshape(-1)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / z.size)
+    assert abs((z ** 4).mean() - 3.0) < 5 * np.sqrt(96.0 / z.size)
+    xi2, u2 = sweep_randoms(12345, 7, 1, 128, 1024)
+    assert not np.any(u2 == u)
+    assert len(np.unique(u)) == u.size
