@@ -5,32 +5,148 @@
 namespace fire {
 
 // ---------------------------------------------------------------------------
-// a1: neighbour lists.  One workgroup per walker; electron i lists every
-// j != i with |r_i - r_j| <= c, same-spin first, then opposite spin.
+// a1: neighbour lists through a cell list.  One workgroup per walker (n <=
+// 256): the walker's electrons are binned into a grid over their bounding
+// box whose cells are at least c wide along every axis (at most 12 per axis),
+// so every pair within c lies in the same or an adjacent cell; electron i
+// then tests only the members of its 27 surrounding cells.  The hits are
+// kept as a bit set over electron indices and emitted in ascending index,
+// same-spin first, then opposite spin: the same lists, in the same order, as
+// a test of every pair.
 // ---------------------------------------------------------------------------
+constexpr int kNbrCellsPerAxis = 12;
+constexpr int kNbrCells = kNbrCellsPerAxis * kNbrCellsPerAxis * kNbrCellsPerAxis;
+
 static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
                                              double cut2, int cap, int16_t* __restrict__ idx,
                                              int32_t* __restrict__ cnt, int32_t* status) {
   __shared__ double pos[256 * 3];
-  int w = blockIdx.x;
+  __shared__ int cell_of[256];
+  __shared__ int cstart[kNbrCells + 1];
+  __shared__ int cfill[kNbrCells];
+  __shared__ unsigned char members[256];
+  __shared__ double red[2][3][4];
+  __shared__ double box_lo[3], box_h[3];
+  __shared__ int box_g[3];
+  const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* Rw = R + (int64_t)w * n * 3;
-  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) pos[t] = Rw[t];
+  for (int t = tid; t < 3 * n; t += blockDim.x) pos[t] = Rw[t];
+  for (int t = tid; t < kNbrCells; t += blockDim.x) cfill[t] = 0;
   __syncthreads();
-  int i = threadIdx.x;
-  if (i >= n) return;
-  double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-  if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) atomicOr(status + w, FIRE_W_NONFINITE);
-  int16_t* out = idx + ((int64_t)w * n + i) * cap;
-  int si = i < nu ? 0 : 1;
+  const bool mine = tid < n;
+  double xi = 0, yi = 0, zi = 0;
+  bool fin = false;
+  if (mine) {
+    xi = pos[3 * tid]; yi = pos[3 * tid + 1]; zi = pos[3 * tid + 2];
+    fin = isfinite(xi) && isfinite(yi) && isfinite(zi);
+    if (!fin) atomicOr(status + w, FIRE_W_NONFINITE);
+  }
+  // bounding box of the finite positions
+  double lo[3] = {fin ? xi : INFINITY, fin ? yi : INFINITY, fin ? zi : INFINITY};
+  double hi[3] = {fin ? xi : -INFINITY, fin ? yi : -INFINITY, fin ? zi : -INFINITY};
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[k] = fmin(lo[k], __shfl_xor(lo[k], o, 64));
+      hi[k] = fmax(hi[k], __shfl_xor(hi[k], o, 64));
+    }
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) { red[0][k][wave] = lo[k]; red[1][k][wave] = hi[k]; }
+  __syncthreads();
+  if (tid < 3) {
+    double l = INFINITY, h = -INFINITY;
+    for (int v = 0; v < (int)(blockDim.x >> 6); ++v) { l = fmin(l, red[0][tid][v]); h = fmax(h, red[1][tid][v]); }
+    const double c = sqrt(cut2);
+    int g = 1;
+    double ext = h - l;
+    if (!(ext > 0) || !isfinite(ext)) { ext = 0; l = isfinite(l) ? l : 0.0; }
+    if (c > 0 && c < 1e300 && ext > 0) {
+      const double q = ceil(ext / c);
+      g = q < 1 ? 1 : (q > kNbrCellsPerAxis ? kNbrCellsPerAxis : (int)q);
+    }
+    // cells at least c wide, g of them covering the extent
+    const double hw = fmax(c, ext / g);
+    box_lo[tid] = l;
+    box_h[tid] = hw > 0 && isfinite(hw) ? hw : 1.0;
+    box_g[tid] = g;
+  }
+  __syncthreads();
+  const int gx = box_g[0], gy = box_g[1], gz = box_g[2];
+  int cx = 0, cy = 0, cz = 0;
+  if (mine) {
+    if (fin) {
+      cx = (int)((xi - box_lo[0]) / box_h[0]); cx = cx < 0 ? 0 : (cx >= gx ? gx - 1 : cx);
+      cy = (int)((yi - box_lo[1]) / box_h[1]); cy = cy < 0 ? 0 : (cy >= gy ? gy - 1 : cy);
+      cz = (int)((zi - box_lo[2]) / box_h[2]); cz = cz < 0 ? 0 : (cz >= gz ? gz - 1 : cz);
+    }
+    const int cidx = (cz * gy + cy) * gx + cx;
+    cell_of[tid] = cidx;
+    atomicAdd(&cfill[cidx], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the cell counts (wave 0; at most 1728 cells)
+  const int ncell = gx * gy * gz;
+  if (wave == 0) {
+    const int per = (ncell + 63) / 64;
+    const int b0 = lane * per, b1 = b0 + per < ncell ? b0 + per : ncell;
+    int sacc = 0;
+    for (int t = b0; t < b1; ++t) sacc += cfill[t];
+    int incl = sacc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    int run = incl - sacc;
+    for (int t = b0; t < b1; ++t) { cstart[t] = run; run += cfill[t]; cfill[t] = 0; }
+    if (lane == 63) cstart[ncell] = incl;
+  }
+  __syncthreads();
+  if (mine) {
+    const int cidx = cell_of[tid];
+    members[cstart[cidx] + atomicAdd(&cfill[cidx], 1)] = (unsigned char)tid;
+  }
+  __syncthreads();
+  if (!mine) return;
+  uint64_t hit[4] = {0, 0, 0, 0};
+  if (fin) {
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int z = cz + dz;
+      if (z < 0 || z >= gz) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int y = cy + dy;
+        if (y < 0 || y >= gy) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = cx + dx;
+          if (x < 0 || x >= gx) continue;
+          const int cc = (z * gy + y) * gx + x;
+          for (int t = cstart[cc]; t < cstart[cc + 1]; ++t) {
+            const int j = members[t];
+            if (j == tid) continue;
+            const double ddx = xi - pos[3 * j], ddy = yi - pos[3 * j + 1], ddz = zi - pos[3 * j + 2];
+            if (ddx * ddx + ddy * ddy + ddz * ddz <= cut2) hit[j >> 6] |= 1ull << (j & 63);
+          }
+        }
+      }
+    }
+  }
+  // emit: same spin class first, then the other, ascending index
+  int16_t* out = idx + ((int64_t)w * n + tid) * cap;
+  const int si = tid < nu ? 0 : 1;
   int c[2] = {0, 0};
   int k = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < n; ++j) {
-      if (j == i) continue;
-      int sj = j < nu ? 0 : 1;
-      if ((sj == si) != (pass == 0)) continue;
-      double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
-      if (dx * dx + dy * dy + dz * dz <= cut2) {
+    const bool up = (pass == 0) == (si == 0);        // this pass lists spin-up electrons
+    const int j0 = up ? 0 : nu, j1 = up ? nu : n;
+    for (int q = 0; q < 4; ++q) {
+      uint64_t m = hit[q];
+      const int base = 64 * q;
+      // keep the bits of [j0, j1)
+      if (base + 64 <= j0 || base >= j1) continue;
+      if (j0 > base) m &= ~0ull << (j0 - base);
+      if (j1 < base + 64) m &= (j1 - base) >= 64 ? ~0ull : ((1ull << (j1 - base)) - 1);
+      while (m) {
+        const int j = base + __builtin_ctzll(m);
+        m &= m - 1;
         if (k < cap) out[k] = (int16_t)j;
         ++k;
         ++c[pass];
@@ -42,8 +158,8 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
     c[0] = c[0] < cap ? c[0] : cap;
     c[1] = cap - c[0] < c[1] ? cap - c[0] : c[1];
   }
-  cnt[((int64_t)w * n + i) * 2 + 0] = c[0];
-  cnt[((int64_t)w * n + i) * 2 + 1] = c[1];
+  cnt[((int64_t)w * n + tid) * 2 + 0] = c[0];
+  cnt[((int64_t)w * n + tid) * 2 + 1] = c[1];
 }
 
 // ---------------------------------------------------------------------------
