@@ -563,7 +563,10 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
     };
 
     // Pipeline: the global loads of slice k+1 are in flight while slice k is
-    // multiplied out of LDS.
+    // multiplied out of LDS.  With K fixed, two register stages alternate:
+    // the loads of slice k+2 are issued as slice k is stored, so two slices
+    // of MFMA work cover their latency (the K loop unrolls, so each slice's
+    // stage is known at compile time).
     Regs R;
     auto slice = [&](int kt, int nk) {
       store(R, 0);
@@ -574,9 +577,18 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
     };
     if constexpr (KF > 0) {
       constexpr int nk = KF / BK;
+      Regs R2;
       gload(R, 0);
+      if (nk > 1) gload(R2, BK);
 #pragma unroll
-      for (int kt = 0; kt < nk; ++kt) slice(kt, nk);
+      for (int kt = 0; kt < nk; ++kt) {
+        Regs& Rk = (kt & 1) ? R2 : R;
+        store(Rk, 0);
+        __syncthreads();
+        if (kt + 2 < nk) gload(Rk, (kt + 2) * BK);
+        compute(0);
+        __syncthreads();
+      }
     } else {
       const int nk = (K + BK - 1) / BK;
       if (nk > 0) gload(R, 0);
