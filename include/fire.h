@@ -272,10 +272,36 @@ fire_status fire_ecp_nonlocal(fire_handle* h, int W, const double* R, void* stat
 
 /* grad[P] = sum_w coeff[w] d log|psi_w| / d theta (Methods, energy gradient
  * with coeff_w = (E_L,w - mean E_L)/W), by a hand-written adjoint with
- * per-layer recomputation.  grad is overwritten. */
+ * per-layer recomputation.  grad is overwritten.  per_walker (optional,
+ * device FP64 [W][P], NULL to skip): row w receives d log|psi_w| / d theta,
+ * the per-walker gradients the natural-gradient step needs (Methods,
+ * variational Monte Carlo, eq. spring); grad is then the coeff-weighted sum of
+ * the rows.  The per-walker mode runs the adjoint one walker at a time. */
 fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state, void* ws,
-                             const double* coeff, double* grad, int32_t* status,
+                             const double* coeff, double* grad, double* per_walker, int32_t* status,
                              hipStream_t stream);
+
+/* One natural-gradient parameter update (Methods, variational Monte Carlo,
+ * eq. spring, with momentum; SI, non-hermitian operator gradients in
+ * Spring, eq. aux_spring):
+ *   delta = Obar^T (Obar Obar^T + lambda I)^-1 (eps + eps~ - eta Obar delta_prev)
+ *           + eta delta_prev + (delta_tilde - Obar^T eps~)
+ * with Obar the per-walker gradients O (device FP64 [W][P], row w =
+ * d log|psi_w| / d theta, e.g. from fire_grad_params' per_walker) centred over
+ * the walkers, eps = e_loc (device [W]) centred, and, when delta_tilde
+ * (device [P], a gradient not of the form Obar^T v) is given, eps~ = (Obar
+ * Obar^T + lambda_pinv I)^-1 Obar delta_tilde, the damped pseudo-inverse that
+ * splits delta_tilde into its part in the span of the rows of Obar (added to
+ * eps) and the rest (added to delta).  delta_prev (device [P]) may be NULL
+ * (zero).  The W x W Gram matrix is one FP64 MFMA GEMM over the parameters;
+ * the damped systems are solved by a blocked FP64 Cholesky factorisation.
+ * ws: the handle's workspace (fire_sizes covers it).  info (device int32):
+ * 0, or 1 when a damped Gram matrix was not positive definite.  Errors:
+ * FIRE_ERR_ARG for null pointers, W < 2, lambda <= 0 or (with delta_tilde)
+ * lambda_pinv <= 0; FIRE_ERR_CAPACITY for W above max_walkers or 8192. */
+fire_status fire_spring_step(fire_handle* h, int W, const double* O, const double* e_loc, double lambda,
+                             double eta, const double* delta_prev, const double* delta_tilde,
+                             double lambda_pinv, double* delta, void* ws, int32_t* info, hipStream_t stream);
 
 /* Kernel timing for roofline reports.  Between fire_profile_begin and
  * fire_profile_end every MFMA GEMM launched on `stream` by this handle is

@@ -444,3 +444,44 @@ def energy_gradient(orc: Oracle, R, e_loc):
     e = torch.as_tensor(e_loc, dtype=DT)
     W = e.shape[0]
     return orc.grad_params(R, (e - e.mean()) / W)
+
+
+def per_walker_gradients(orc: Oracle, R, names):
+    """O [W][P]: row w is d log|psi_w| / d theta, flattened in the order of
+    names (one reverse pass per walker)."""
+    R = torch.as_tensor(R, dtype=DT)
+    W = R.shape[0]
+    rows = []
+    for w in range(W):
+        c = torch.zeros(W, dtype=DT)
+        c[w] = 1.0
+        g = orc.grad_params(R, c)
+        rows.append(torch.cat([g[k].reshape(-1) for k in names]))
+    return torch.stack(rows).numpy()
+
+
+def spring_step(O, e, lam, eta, delta_prev=None, delta_tilde=None, lam_pinv=None):
+    """The natural-gradient update with momentum (Methods, variational Monte
+    Carlo, eq. spring): with Obar the walker-centred per-walker gradients
+    (rows = walkers) and eps the centred local energies,
+      delta = Obar^T (Obar Obar^T + lam I)^-1 (eps - Obar eta delta_prev) + eta delta_prev.
+    With an extra gradient delta_tilde (SI, non-hermitian operator gradients
+    in Spring, eq. aux_spring), its part in the span of the rows of Obar,
+    Obar^T eps~ with eps~ = (Obar Obar^T + lam_pinv I)^-1 Obar delta_tilde (the
+    damped pseudo-inverse), joins eps, and the rest is added to delta."""
+    O = np.asarray(O, np.float64)
+    e = np.asarray(e, np.float64)
+    W, P = O.shape
+    Ob = O - O.mean(0, keepdims=True)
+    eps = e - e.mean()
+    dprev = np.zeros(P) if delta_prev is None else np.asarray(delta_prev, np.float64)
+    K = Ob @ Ob.T
+    rhs = eps - Ob @ (eta * dprev)
+    out = eta * dprev
+    if delta_tilde is not None:
+        dt = np.asarray(delta_tilde, np.float64)
+        eps_t = np.linalg.solve(K + lam_pinv * np.eye(W), Ob @ dt)
+        rhs = rhs + eps_t
+        out = out + dt - Ob.T @ eps_t
+    x = np.linalg.solve(K + lam * np.eye(W), rhs)
+    return Ob.T @ x + out

@@ -507,11 +507,23 @@ fire_status fire_ecp_nonlocal(fire_handle* h, int W, const double* R, void* stat
 }
 
 fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state, void* ws, const double* coeff,
-                             double* grad, int32_t* status, hipStream_t s) {
+                             double* grad, double* per_walker, int32_t* status, hipStream_t s) {
   fire_status st = check_call(h, W, R, state, ws, status);
   if (st != FIRE_OK) return st;
   if (!coeff || !grad) return FIRE_ERR_ARG;
-  hipError_t e = grad_path(h, W, R, (char*)state, (char*)ws, coeff, grad, status, s);
+  hipError_t e = grad_path(h, W, R, (char*)state, (char*)ws, coeff, grad, per_walker, status, s);
+  return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+fire_status fire_spring_step(fire_handle* h, int W, const double* O, const double* e_loc, double lambda, double eta,
+                             const double* delta_prev, const double* delta_tilde, double lambda_pinv, double* delta,
+                             void* ws, int32_t* info, hipStream_t s) {
+  if (!h || !O || !e_loc || !delta || !ws || !info || W < 2) return FIRE_ERR_ARG;
+  if (!(lambda > 0) || !isfinite(lambda) || !isfinite(eta)) return FIRE_ERR_ARG;
+  if (delta_tilde && (!(lambda_pinv > 0) || !isfinite(lambda_pinv))) return FIRE_ERR_ARG;
+  if (W > h->model.max_walkers || spring_ws_bytes(h->P, W) == 0) return FIRE_ERR_CAPACITY;
+  hipError_t e = spring_step(h->P, W, O, e_loc, lambda, eta, delta_prev, delta_tilde, lambda_pinv, delta, (char*)ws,
+                             info, s);
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 

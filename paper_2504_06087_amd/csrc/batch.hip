@@ -215,7 +215,7 @@ static fire_status enqueue_system(fire_batch* b, int s, const SysOff& o, const S
   if (r != FIRE_OK) return r;
   hipLaunchKernelGGL(k_energy_coeff, dim3(1), dim3(256), 0, st, (const double*)e, W, coeff);
   if (hipGetLastError() != hipSuccess) return FIRE_ERR_HIP;
-  r = fire_grad_params(h, W, R, state, ws, coeff, (double*)(wb + o.gtmp), s3, st);
+  r = fire_grad_params(h, W, R, state, ws, coeff, (double*)(wb + o.gtmp), nullptr, s3, st);
   if (r != FIRE_OK) return r;
   hipLaunchKernelGGL(k_or_status, dim3((W + 255) / 256), dim3(256), 0, st, W, (const int32_t*)s0,
                      (const int32_t*)s1, (const int32_t*)s2, (const int32_t*)s3, a.status + o.walker0);

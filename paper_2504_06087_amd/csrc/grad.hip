@@ -801,7 +801,8 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   return L;
 }
 
-size_t grad_ws_bytes(const fire_handle* h, int W) { return grad_layout(h, W).total; }
+// the per-walker mode keeps a vector of ones (coefficients) after the layout
+size_t grad_ws_bytes(const fire_handle* h, int W) { return grad_layout(h, W).total + align_up((size_t)W * 8); }
 
 // weight gradient C[a][b] = sum_r X[r][a] Y[r][b] (rows through maps), into grad
 template <typename T>
@@ -1078,10 +1079,13 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
 // workgroup per walker adds c_w times its sums into g[0..3].
 __global__ __launch_bounds__(256) void k_jas_grad(const Dims D, int W, const double* __restrict__ R,
                                                   const double* __restrict__ q, const double* __restrict__ coeff,
-                                                  const int32_t* __restrict__ status, double* __restrict__ g) {
+                                                  const int32_t* __restrict__ status, double* __restrict__ g,
+                                                  int64_t gstride) {
   __shared__ double red[16];
   const int w = blockIdx.x, n = D.n;
   if (status[w] != 0 || coeff[w] == 0.0) return;
+  // gstride > 0: walker w's sums go to its own row g + w gstride
+  if (gstride > 0) g += (int64_t)w * gstride;
   const double* Rw = R + (int64_t)w * n * 3;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
@@ -1101,29 +1105,61 @@ __global__ __launch_bounds__(256) void k_jas_grad(const Dims D, int W, const dou
   }
 }
 
+// grad[p] = sum_w coeff[w] O[w][p] over the per-walker gradients
+__global__ void k_weighted_rows(int64_t P, int W, const double* __restrict__ O, const double* __restrict__ coeff,
+                                double* __restrict__ grad) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s = 0.0;
+  for (int w = 0; w < W; ++w) s += coeff[w] * O[(int64_t)w * P + p];
+  grad[p] = s;
+}
+
 template <typename T>
 static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff,
-                            double* grad, int32_t* status, hipStream_t st) {
+                            double* grad, double* per_walker, int32_t* status, hipStream_t st) {
   Net<T> P = make_net<T>(h);
   const GradLayout L = grad_layout(h, W);
   CHECK(fill_i32(status, W, 0, st));
-  hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((h->P + 255) / 256)), dim3(256), 0, st, grad, (int64_t)h->P, 0.0);
-  CHECK(hipGetLastError());
-  for (int w0 = 0; w0 < W; w0 += L.Wc) {
-    const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
-    CHECK(grad_chunk<T>(h, P, w0, wc, R, state, ws, coeff, grad, status, st));
+  if (!per_walker) {
+    hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((h->P + 255) / 256)), dim3(256), 0, st, grad, (int64_t)h->P,
+                       0.0);
+    CHECK(hipGetLastError());
+    for (int w0 = 0; w0 < W; w0 += L.Wc) {
+      const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
+      CHECK(grad_chunk<T>(h, P, w0, wc, R, state, ws, coeff, grad, status, st));
+    }
+    hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, coeff, (const int32_t*)status,
+                       grad + theta_offset(h, "jas_cusp"), (int64_t)0);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, coeff, (const int32_t*)status,
-                     grad + theta_offset(h, "jas_cusp"));
+  // Per-walker gradients O[w] = d log|psi_w| / d theta: the same adjoint run
+  // one walker at a time (coefficient 1) into that walker's row, then
+  // grad = sum_w coeff_w O[w].  One-walker chunks keep every reduction of the
+  // batched adjoint unchanged; the cost is launch-bound (about 70 launches
+  // per walker).
+  double* ones = (double*)(ws + L.total);
+  hipLaunchKernelGGL(k_fill<double>, dim3((W + 255) / 256), dim3(256), 0, st, ones, (int64_t)W, 1.0);
+  CHECK(hipGetLastError());
+  const int64_t WP = (int64_t)W * h->P;
+  hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)((WP + 255) / 256)), dim3(256), 0, st, per_walker, WP, 0.0);
+  CHECK(hipGetLastError());
+  for (int w = 0; w < W; ++w)
+    CHECK(grad_chunk<T>(h, P, w, 1, R, state, ws, ones, per_walker + (int64_t)w * h->P, status, st));
+  hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, (const double*)ones,
+                     (const int32_t*)status, per_walker + theta_offset(h, "jas_cusp"), (int64_t)h->P);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_weighted_rows, dim3((unsigned)((h->P + 255) / 256)), dim3(256), 0, st, (int64_t)h->P, W,
+                     (const double*)per_walker, coeff, grad);
   return hipGetLastError();
 }
 
 hipError_t grad_path(fire_handle* h, int W, const double* R, char* state, char* ws, const double* coeff, double* grad,
-                     int32_t* status, hipStream_t s) {
+                     double* per_walker, int32_t* status, hipStream_t s) {
   const Dims& D = h->D;
   if (D.M > 4096 || D.d > 256) return hipErrorInvalidValue;
-  return h->tsize == 8 ? grad_impl<double>(h, W, R, state, ws, coeff, grad, status, s)
-                       : grad_impl<float>(h, W, R, state, ws, coeff, grad, status, s);
+  return h->tsize == 8 ? grad_impl<double>(h, W, R, state, ws, coeff, grad, per_walker, status, s)
+                       : grad_impl<float>(h, W, R, state, ws, coeff, grad, per_walker, status, s);
 }
 
 }  // namespace fire

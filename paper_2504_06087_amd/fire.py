@@ -23,7 +23,7 @@ W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
            "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_eval_logpsi_noalloc",
            "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
-           "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_sync_status",
+           "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_spring_step", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
            "fire_batch_sizes", "fire_batch_set_params", "fire_batch_step", "fire_batch_graph_create",
@@ -89,7 +89,8 @@ def load() -> ctypes.CDLL:
                                           V, V]
     lib.fire_local_energy.argtypes = [P, I, V, V, V, V, V, V, V, V, V]
     lib.fire_ecp_nonlocal.argtypes = [P, I, V, V, V, V, V, V, V]
-    lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V]
+    lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V, V]
+    lib.fire_spring_step.argtypes = [P, I, V, V, D, D, V, V, D, V, V, V, V]
     lib.fire_sync_status.argtypes = [P, V, V, I, ctypes.POINTER(ctypes.c_int32)]
     lib.fire_profile_begin.argtypes = [P, V, V, I]
     lib.fire_profile_end.argtypes = [P, V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -351,13 +352,26 @@ class Fire:
                                         _dp(status), _stream()), "fire_ecp_nonlocal")
         return v, status
 
-    def grad_params(self, R, state, ws, coeff):
+    def grad_params(self, R, state, ws, coeff, per_walker=None):
+        """sum_w coeff_w d log|psi_w|/d theta; with per_walker (a [W][P] FP64
+        tensor) also every walker's gradient."""
         W = R.shape[0]
         g = torch.empty(self.P, dtype=torch.float64, device=self.device)
         status = torch.empty(W, dtype=torch.int32, device=self.device)
-        _check(load().fire_grad_params(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(coeff), _dp(g), _dp(status),
-                                       _stream()), "fire_grad_params")
+        _check(load().fire_grad_params(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(coeff), _dp(g), _dp(per_walker),
+                                       _dp(status), _stream()), "fire_grad_params")
         return g, status
+
+    def spring_step(self, O, e_loc, ws, lam, eta, delta_prev=None, delta_tilde=None, lam_pinv=0.0):
+        """fire_spring_step: the natural-gradient update from per-walker
+        gradients O [W][P] and local energies; returns (delta [P], info)."""
+        W = O.shape[0]
+        delta = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        info = torch.empty(1, dtype=torch.int32, device=self.device)
+        _check(load().fire_spring_step(self.h, W, _dp(O), _dp(e_loc), float(lam), float(eta), _dp(delta_prev),
+                                       _dp(delta_tilde), float(lam_pinv), _dp(delta), _dp(ws), _dp(info), _stream()),
+               "fire_spring_step")
+        return delta, info
 
     def profile_begin(self, capacity: int = 200000):
         self._prof_counters = torch.zeros(capacity, dtype=torch.int32, device=self.device)

@@ -756,3 +756,70 @@ def test_sweep_randoms_distribution():
     xi2, u2 = sweep_randoms(12345, 7, 1, 128, 1024)
     assert not np.any(u2 == u)
     assert len(np.unique(u)) == u.size
+
+
+# --------------------------------------------------------------------------
+# the natural-gradient step (Methods, variational Monte Carlo, eq. spring;
+# SI, non-hermitian operator gradients in Spring, eq. aux_spring)
+# --------------------------------------------------------------------------
+def _spring_data(W=12, P=30, seed=0):
+    rng = np.random.default_rng(seed)
+    O = rng.normal(size=(W, P)) + 0.3 * rng.normal(size=P)
+    e = rng.normal(size=W) * 2.0 - 5.0
+    dprev = rng.normal(size=P) * 0.1
+    return O, e, dprev
+
+
+def test_spring_is_the_damped_least_squares_minimiser():
+    """delta minimises |Obar delta - eps|^2 + lam |delta - eta delta_prev|^2:
+    it equals the P x P normal-equation solution (Obar^T Obar + lam I)^-1
+    (Obar^T eps + lam eta delta_prev), and the objective's gradient vanishes
+    there (Obar, eps centred over the walkers)."""
+    from oracle import spring_step
+    O, e, dprev = _spring_data()
+    lam, eta = 0.05, 0.9
+    d = spring_step(O, e, lam, eta, dprev)
+    Ob = O - O.mean(0)
+    eps = e - e.mean()
+    P = O.shape[1]
+    ref = np.linalg.solve(Ob.T @ Ob + lam * np.eye(P), Ob.T @ eps + lam * eta * dprev)
+    assert np.allclose(d, ref, rtol=1e-10, atol=1e-12)
+    grad = Ob.T @ (Ob @ d - eps) + lam * (d - eta * dprev)
+    assert np.abs(grad).max() < 1e-10 * max(1.0, np.abs(Ob.T @ eps).max())
+
+
+def test_spring_interpolates_as_damping_vanishes():
+    """With W - 1 <= P the centred Gram matrix has full rank on the centred
+    vectors, so as lam -> 0 the update reproduces the centred energies:
+    Obar delta -> eps (momentum off)."""
+    from oracle import spring_step
+    O, e, _ = _spring_data(W=10, P=40, seed=1)
+    d = spring_step(O, e, 1e-10, 0.0)
+    Ob = O - O.mean(0)
+    assert np.abs(Ob @ d - (e - e.mean())).max() < 1e-6
+
+
+def test_spring_extra_gradient_split():
+    """An extra gradient in the span of the rows of Obar is carried entirely
+    through eps (its out-of-span rest vanishes), one orthogonal to every row
+    passes through unchanged, and without one the update is eq. spring."""
+    from oracle import spring_step
+    O, e, dprev = _spring_data(W=8, P=25, seed=2)
+    lam, eta = 1e-2, 0.99
+    Ob = O - O.mean(0)
+    base = spring_step(O, e, lam, eta, dprev)
+    # orthogonal to every row of Obar: eps~ = 0
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=O.shape[1])
+    Q, _ = np.linalg.qr(Ob.T)
+    v_out = v - Q @ (Q.T @ v)
+    d_out = spring_step(O, e, lam, eta, dprev, delta_tilde=v_out, lam_pinv=1e-12)
+    assert np.allclose(d_out, base + v_out, atol=1e-10)
+    # in the span: delta~ = Obar^T a; then the rest vanishes and eps~ = the
+    # centred a (the pseudo-inverse solution on the range)
+    a = rng.normal(size=O.shape[0])
+    v_in = Ob.T @ a
+    d_in = spring_step(O, e, lam, eta, dprev, delta_tilde=v_in, lam_pinv=1e-12)
+    a_c = a - a.mean()
+    x = np.linalg.solve(Ob @ Ob.T + lam * np.eye(O.shape[0]), (e - e.mean()) + a_c - Ob @ (eta * dprev))
+    assert np.allclose(d_in, Ob.T @ x + eta * dprev, atol=1e-8)
