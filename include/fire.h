@@ -281,6 +281,22 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
                              const double* coeff, double* grad, double* per_walker, int32_t* status,
                              hipStream_t stream);
 
+/* Two-electron swap ratios of the S+ spin penalty (SI, low-rank updates in
+ * S+ operator): for the spin-down electron beta (n_up <= beta < n) and every
+ * spin-up electron a, ratios[w][a] = psi(pi_{a,beta} r_w) / psi(r_w), the
+ * wave function with the positions of a and beta exchanged over the cached
+ * one, and r_beta[w] = 1 - sum_a ratios[w][a], the per-walker estimator R_beta
+ * whose square gives <S+ psi|S+ psi> = n_down/(n_up + 1) E[R_beta^2].  Each
+ * ratio is one low-rank update: the embeddings of the two positions keep
+ * their nuclear part, the pairs of a third electron with either position
+ * change class, and the determinants change in the rows of {a, beta} and the
+ * electrons within c of either position (a rank-|U| update per spin block
+ * through the matrix-determinant lemma).  ratios: device [W][n_up]; r_beta:
+ * [W].  state must hold the evaluation at R.  Errors: FIRE_ERR_ARG for null
+ * pointers, no spin-up electron or beta outside the spin-down range. */
+fire_status fire_splus_ratios(fire_handle* h, int W, const double* R, void* state, void* ws, int beta,
+                              double* ratios, double* r_beta, int32_t* status, hipStream_t stream);
+
 /* One natural-gradient parameter update (Methods, variational Monte Carlo,
  * eq. spring, with momentum; SI, non-hermitian operator gradients in
  * Spring, eq. aux_spring):

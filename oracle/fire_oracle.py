@@ -365,6 +365,22 @@ class Oracle:
         parts = torch.cat([kin[:, None], V, vnl[:, None]], 1)
         return parts.sum(1), parts
 
+    def splus_ratios(self, R, beta):
+        """The S+ spin-penalty estimator (SI, low-rank updates in S+
+        operator): for the spin-down electron beta and every spin-up electron
+        a, psi(pi_{a,beta} r)/psi(r) with the positions of a and beta
+        exchanged (a full re-evaluation), and R_beta = 1 - sum_a of them.
+        Returns (ratios [B, n_up], R_beta [B])."""
+        R = torch.as_tensor(R, dtype=DT)
+        s0, l0 = self.log_psi(R)
+        out = torch.zeros(R.shape[0], self.n_up, dtype=DT)
+        for a in range(self.n_up):
+            Rs = R.clone()
+            Rs[:, [a, beta]] = R[:, [beta, a]]
+            s1, l1 = self.log_psi(Rs)
+            out[:, a] = s1 * s0 * torch.exp(l1 - l0)
+        return out, 1.0 - out.sum(1)
+
     # ------------------------------------------------------------------
     # sampling and parameter gradients
     # ------------------------------------------------------------------

@@ -515,6 +515,15 @@ fire_status fire_grad_params(fire_handle* h, int W, const double* R, void* state
   return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
+fire_status fire_splus_ratios(fire_handle* h, int W, const double* R, void* state, void* ws, int beta,
+                              double* ratios, double* r_beta, int32_t* status, hipStream_t s) {
+  fire_status st = check_call(h, W, R, state, ws, status);
+  if (st != FIRE_OK) return st;
+  if (!ratios || !r_beta || h->D.nu < 1 || beta < h->D.nu || beta >= h->D.n) return FIRE_ERR_ARG;
+  hipError_t e = splus_path(h, W, R, (char*)state, (char*)ws, beta, ratios, r_beta, status, s);
+  return e == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
 fire_status fire_spring_step(fire_handle* h, int W, const double* O, const double* e_loc, double lambda, double eta,
                              const double* delta_prev, const double* delta_tilde, double lambda_pinv, double* delta,
                              void* ws, int32_t* info, hipStream_t s) {

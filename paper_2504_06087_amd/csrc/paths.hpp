@@ -15,6 +15,10 @@ hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* 
                            const double* pick, uint64_t seed, uint64_t counter, int32_t* n_accept, double* logpsi,
                            double* sign, int32_t* status, hipStream_t s);
 size_t rng_ws_offset(const fire_handle* h, int W);
+// two-electron swap ratios of the S+ estimator (update.hip)
+size_t swap_ws_bytes(const fire_handle* h, int W);
+hipError_t splus_path(fire_handle* h, int W, const double* R, char* state, char* ws, int eb, double* ratios,
+                      double* rb, int32_t* status, hipStream_t s);
 // the natural-gradient step (spring.hip); 0 bytes when W exceeds its limit
 size_t spring_ws_bytes(int64_t P, int W);
 hipError_t spring_step(int64_t P, int W, const double* O, const double* e_loc, double lambda, double eta,

@@ -1833,6 +1833,389 @@ hipError_t mcmc_sweep_path(fire_handle* h, int W, double* R, char* state, char* 
                                            seed, counter, n_accept, logpsi, sign, status, s);
 }
 
+// ---------------------------------------------------------------------------
+// Two-electron swaps for the S+ estimator (SI, low-rank updates in S+
+// operator): psi(pi_ab r) / psi(r) for the exchange of the positions of an
+// up electron a and a down electron b, one job per walker.  After the swap
+// the position r_a carries a down electron and r_b an up one: the nuclear
+// part of every embedding is unchanged (h0 is a function of the position, so
+// the slot of a takes the cached h0 and projections of b and vice versa), the
+// electron pairs that change class are those between a third electron and
+// either position, and the determinants change in the rows of
+// U = {a, b} u N(r_a) u N(r_b) only: a rank-|U_s| update per spin block,
+// with a first in the up list and b first in the down list.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_swap_propose(const double* __restrict__ R, int W, int n, int nu, int ea,
+                                                      int eb, double cut2, int cap0, int cap1, int capmax,
+                                                      double* __restrict__ ra, double* __restrict__ rb,
+                                                      int* __restrict__ uidx, int* __restrict__ ucnt,
+                                                      const double* __restrict__ jasq, double* __restrict__ dj,
+                                                      int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= W) return;
+  const double* Rw = R + (int64_t)j * n * 3;
+  const double ax = Rw[3 * ea], ay = Rw[3 * ea + 1], az = Rw[3 * ea + 2];
+  const double bx = Rw[3 * eb], by = Rw[3 * eb + 1], bz = Rw[3 * eb + 2];
+  if (lane == 0) {
+    // new positions: the slot of a (up) at r_b, the slot of b (down) at r_a
+    ra[3 * j] = bx; ra[3 * j + 1] = by; ra[3 * j + 2] = bz;
+    rb[3 * j] = ax; rb[3 * j + 1] = ay; rb[3 * j + 2] = az;
+  }
+  // change of log J_cusp: the pairs of a third electron i with either position
+  if (jasq[0] == 0.0 && jasq[2] == 0.0) {
+    if (lane == 0) dj[j] = 0.0;
+  } else {
+    double d = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      if (i == ea || i == eb) continue;
+      const double ix = Rw[3 * i], iy = Rw[3 * i + 1], iz = Rw[3 * i + 2];
+      const bool up = i < nu;
+      const double rA = sqrt((ax - ix) * (ax - ix) + (ay - iy) * (ay - iy) + (az - iz) * (az - iz));
+      const double rB = sqrt((bx - ix) * (bx - ix) + (by - iy) * (by - iy) + (bz - iz) * (bz - iz));
+      d += jas_u(jasq, up, rB) + jas_u(jasq, !up, rA) - jas_u(jasq, up, rA) - jas_u(jasq, !up, rB);
+    }
+    d = wave_sum(d);
+    if (lane == 0) dj[j] = d;
+  }
+  int cnt[2] = {1, 1};
+  int* u0 = uidx + (int64_t)j * 2 * capmax;
+  if (lane == 0) { u0[0] = ea; u0[capmax] = eb; }
+  const int cap[2] = {cap0, cap1};
+  bool over = false;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    bool in = false;
+    if (i < n && i != ea && i != eb) {
+      const double x = Rw[3 * i], y = Rw[3 * i + 1], z = Rw[3 * i + 2];
+      const double d0 = (x - ax) * (x - ax) + (y - ay) * (y - ay) + (z - az) * (z - az);
+      const double d1 = (x - bx) * (x - bx) + (y - by) * (y - by) + (z - bz) * (z - bz);
+      in = d0 <= cut2 || d1 <= cut2;
+    }
+    const int si = i < nu ? 0 : 1;
+    const uint64_t m = __ballot(in);
+    const uint64_t mup = __ballot(in && si == 0);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int pos = si == 0 ? __popcll(mup & below) : __popcll((m & ~mup) & below);
+    if (in) {
+      const int t = cnt[si] + pos;
+      if (t < cap[si]) u0[si * capmax + t] = i;
+    }
+    cnt[0] += __popcll(mup);
+    cnt[1] += __popcll(m & ~mup);
+  }
+  for (int s = 0; s < 2; ++s)
+    if (cnt[s] > cap[s]) { over = true; cnt[s] = cap[s]; }
+  if (lane == 0) {
+    ucnt[2 * j] = cnt[0];
+    ucnt[2 * j + 1] = cnt[1];
+    if (over) atomicOr(status + j, FIRE_W_UPD_OVERFLOW);
+  }
+}
+
+// Messages after the swap, one workgroup per job, one thread per channel.
+// For a member u of either list: the edges to the two positions change
+// class, m_u += sum_{p in {r_a, r_b}} [msg^new(u, p) - msg^old(u, p)] with
+// msg^c(u, p) = Gamma^c(r_u - p) * SiLU(a^c_u + b^c_p + e(r_u - p) W_e^c + b^c)
+// and b_p the projection of the embedding at p.  The two moved slots get
+// their full message: the slot of a (up, at r_b) sums msg over every member
+// and the other moved slot, the slot of b (down, at r_a) likewise.
+template <typename T>
+__global__ __launch_bounds__(256) void k_msg_swap(Net<T> P, int W, int ea, int eb, const double* __restrict__ R,
+                                                  const int* __restrict__ uidx, int capmax,
+                                                  const int* __restrict__ ucnt, const int* __restrict__ off,
+                                                  const char* __restrict__ state, StateRec S, T* hseg0, T* hseg1,
+                                                  T* mseg0, T* mseg1, int* rinfo0, int* rinfo1) {
+  const Dims& D = P.D;
+  constexpr int MPC = 10;               // members per chunk (6 pair feature sets each)
+  constexpr int NS = 6;
+  __shared__ T feat[NS * MPC * FEAT];
+  __shared__ T fab[2 * FEAT];
+  __shared__ int mem[MPC];
+  const int j = blockIdx.x;
+  if (ucnt[2 * j] + ucnt[2 * j + 1] == 0) return;   // dropped job
+  const int c = threadIdx.x;
+  const bool act = c < D.d;
+  const int n = D.n, d = D.d;
+  const char* rec = state + (int64_t)j * S.stride;
+  const T* h0 = (const T*)(rec + S.h0);
+  const T* proj = (const T*)(rec + S.proj);
+  const T* mold = (const T*)(rec + S.m);
+  const double* Rw = R + (int64_t)j * n * 3;
+  const double ax = Rw[3 * ea], ay = Rw[3 * ea + 1], az = Rw[3 * ea + 2];
+  const double bx = Rw[3 * eb], by = Rw[3 * eb + 1], bz = Rw[3 * eb + 2];
+  // per-channel weights of both pair classes
+  T w3[2][kMaxH2], wenv[2][kMaxG], we[2][4], bb[2];
+  for (int a = 0; a < 2; ++a) {
+    for (int k = 0; k < kMaxH2; ++k) w3[a][k] = (act && k < D.h2) ? P.ee_W3[(a * D.h2 + k) * d + c] : T(0);
+    for (int k = 0; k < kMaxG; ++k) wenv[a][k] = (act && k < D.G) ? P.ee_Wenv[(a * D.G + k) * d + c] : T(0);
+    for (int k = 0; k < 4; ++k) we[a][k] = act ? P.msg_We[(a * 4 + k) * d + c] : T(0);
+    bb[a] = act ? P.msg_b[a * d + c] : T(0);
+  }
+  auto edge = [&](const T* f, int a, T av, T bv) -> T {
+    if (f[44] == T(0)) return T(0);
+    T g1 = 0, g2 = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxH2; ++q) g1 += f[4 + q] * w3[a][q];
+#pragma unroll
+    for (int q = 0; q < kMaxG; ++q) g2 += f[12 + q] * wenv[a][q];
+    const T ef = f[0] * we[a][0] + f[1] * we[a][1] + f[2] * we[a][2] + f[3] * we[a][3] + bb[a];
+    return g1 * g2 * silu_(av + bv + ef);
+  };
+  auto feats = [&](double dx, double dy, double dz, int a, T* out) {
+    pair_features<T>((T)dx, (T)dy, (T)dz, P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2,
+                     P.ee_b2 + a * D.h2, P.ee_sig + a * D.G, (T)D.cut, D, out);
+  };
+  // the pair of the two moved slots (opposite spins before and after)
+  if (threadIdx.x == 0) feats(bx - ax, by - ay, bz - az, 1, fab);          // slot a at r_b <- slot b at r_a
+  else if (threadIdx.x == 1) feats(ax - bx, ay - by, az - bz, 1, fab + FEAT);   // slot b at r_a <- slot a at r_b
+  T acc_a = 0, acc_b = 0;
+  const T pa_a0 = act ? proj[((int64_t)ea * 4 + 0) * d + c] : T(0), pa_a1 = act ? proj[((int64_t)ea * 4 + 1) * d + c] : T(0);
+  const T pa_b0 = act ? proj[((int64_t)ea * 4 + 2) * d + c] : T(0), pa_b1 = act ? proj[((int64_t)ea * 4 + 3) * d + c] : T(0);
+  const T pb_a0 = act ? proj[((int64_t)eb * 4 + 0) * d + c] : T(0), pb_a1 = act ? proj[((int64_t)eb * 4 + 1) * d + c] : T(0);
+  const T pb_b0 = act ? proj[((int64_t)eb * 4 + 2) * d + c] : T(0), pb_b1 = act ? proj[((int64_t)eb * 4 + 3) * d + c] : T(0);
+  __syncthreads();
+  if (act) {
+    acc_a += edge(fab, 1, pb_a1, pa_b1);          // receiver at r_b with a-proj of r_b, sender at r_a
+    acc_b += edge(fab + FEAT, 1, pa_a1, pb_b1);
+  }
+  for (int s = 0; s < 2; ++s) {
+    const int cnt = ucnt[2 * j + s];
+    const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+    T* hseg = s == 0 ? hseg0 : hseg1;
+    T* mseg = s == 0 ? mseg0 : mseg1;
+    int* rinfo = s == 0 ? rinfo0 : rinfo1;
+    const int q0 = off[s * (W + 1) + j];
+    // class of an edge between a member of block s and an up / down electron
+    const int c_up = s == 0 ? 0 : 1, c_dn = 1 - c_up;
+    for (int t0 = 1; t0 < cnt; t0 += MPC) {   // t = 0 is the moved slot
+      const int tc = cnt - t0 < MPC ? cnt - t0 : MPC;
+      __syncthreads();
+      if (threadIdx.x < NS * tc) {
+        const int t = threadIdx.x / NS, kind = threadIdx.x % NS;
+        const int u = lst[t0 + t];
+        if (kind == 0) mem[t] = u;
+        const double ux = Rw[3 * u], uy = Rw[3 * u + 1], uz = Rw[3 * u + 2];
+        T* out = feat + (NS * t + kind) * FEAT;
+        // 0, 1: (u <- r_a) in class 0 / 1;  2, 3: (u <- r_b) in class 0 / 1
+        // 4: (slot a at r_b <- u), class c_up;  5: (slot b at r_a <- u), class c_dn
+        if (kind < 2) feats(ux - ax, uy - ay, uz - az, kind, out);
+        else if (kind < 4) feats(ux - bx, uy - by, uz - bz, kind - 2, out);
+        else if (kind == 4) feats(bx - ux, by - uy, bz - uz, c_up, out);
+        else feats(ax - ux, ay - uy, az - uz, c_dn, out);
+      }
+      __syncthreads();
+      if (!act) continue;
+      for (int t = 0; t < tc; ++t) {
+        const int u = mem[t];
+        const T* f = feat + NS * t * FEAT;
+        const T au[2] = {proj[((int64_t)u * 4 + 0) * d + c], proj[((int64_t)u * 4 + 1) * d + c]};
+        const T bu[2] = {proj[((int64_t)u * 4 + 2) * d + c], proj[((int64_t)u * 4 + 3) * d + c]};
+        // at r_a: old class c_up (an up electron there), new class c_dn; b-proj of r_a
+        const T pa_b[2] = {pa_b0, pa_b1}, pb_b[2] = {pb_b0, pb_b1};
+        T dm = edge(f + c_dn * FEAT, c_dn, au[c_dn], pa_b[c_dn]) - edge(f + c_up * FEAT, c_up, au[c_up], pa_b[c_up]);
+        // at r_b: old class c_dn, new class c_up; b-proj of r_b
+        dm += edge(f + (2 + c_up) * FEAT, c_up, au[c_up], pb_b[c_up]) -
+              edge(f + (2 + c_dn) * FEAT, c_dn, au[c_dn], pb_b[c_dn]);
+        // the moved slots receive from u
+        const T pb_a[2] = {pb_a0, pb_a1}, pa_a[2] = {pa_a0, pa_a1};
+        acc_a += edge(f + 4 * FEAT, c_up, pb_a[c_up], bu[c_up]);
+        acc_b += edge(f + 5 * FEAT, c_dn, pa_a[c_dn], bu[c_dn]);
+        const T mu = mold[(int64_t)u * d + c] + dm;
+        const int64_t q = q0 + t0 + t;
+        hseg[q * d + c] = h0[(int64_t)u * d + c] + mu;
+        mseg[q * d + c] = mu;
+        if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = u; }
+      }
+    }
+  }
+  if (act) {
+    // slot a (up list, first) carries the embedding of position r_b
+    const int64_t qa = off[j], qb = off[(W + 1) + j];
+    hseg0[qa * d + c] = h0[(int64_t)eb * d + c] + acc_a;
+    mseg0[qa * d + c] = acc_a;
+    hseg1[qb * d + c] = h0[(int64_t)ea * d + c] + acc_b;
+    mseg1[qb * d + c] = acc_b;
+    if (c == 0) {
+      rinfo0[2 * qa] = j; rinfo0[2 * qa + 1] = ea;
+      rinfo1[2 * qb] = j; rinfo1[2 * qb + 1] = eb;
+    }
+  }
+}
+
+// ratio[w][a] = e^{dJ} sum_d w_d prod_s det A_ds with w_d the determinant's
+// share of the sum (as a pseudopotential ratio, one job per walker)
+__global__ void k_swap_ratio(const Dims D, int W, int ea, const double* __restrict__ detA,
+                             const double* __restrict__ dj, const char* __restrict__ state, StateRec S,
+                             const int32_t* __restrict__ status, double* __restrict__ ratios) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= W) return;
+  const char* rec = state + (int64_t)j * S.stride;
+  const double* ds = (const double*)(rec + S.dsign);
+  const double* dl = (const double*)(rec + S.dlog);
+  const double lp = *(const double*)(rec + S.lpsi), sp = *(const double*)(rec + S.spsi);
+  const double* dA = detA + (int64_t)j * D.K * 4;
+  double r = 0.0;
+  for (int k = 0; k < D.K; ++k) {
+    const double sg = ds[2 * k] * ds[2 * k + 1] * sp * dA[4 * k] * dA[4 * k + 2];
+    if (sg != 0.0) r += sg * exp(dl[2 * k] + dl[2 * k + 1] - lp + dA[4 * k + 1] + dA[4 * k + 3]);
+  }
+  ratios[(int64_t)j * D.nu + ea] = status[j] ? NAN : r * exp(dj[j]);
+}
+
+// R_b[w] = 1 - sum_a ratio[w][a]
+__global__ void k_splus_rb(int W, int nu, const double* __restrict__ ratios, double* __restrict__ rb) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  double s = 0.0;
+  for (int a = 0; a < nu; ++a) s += ratios[(int64_t)w * nu + a];
+  rb[w] = 1.0 - s;
+}
+
+// workspace of a swap batch: the update layout without the Woodbury buffer,
+// then the second moved position and the second envelope row
+size_t swap_ws_bytes(const fire_handle* h, int W) {
+  const UpdLayout L = upd_layout(h, W, false);
+  return L.total + align_up((size_t)W * 24) + align_up((size_t)W * h->D.K * (h->D.nd > 0 ? h->D.nd : 1) * h->tsize);
+}
+
+template <typename T>
+static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int ea, int eb, const double* R,
+                             char* state, char* ws, int32_t* status, double* ratios, hipStream_t st) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  const UpdLayout L = upd_layout(h, W, false);
+  const int blk = D.d <= 64 ? 64 : (D.d + 63) / 64 * 64;
+  double* ra = (double*)(ws + L.rnew);
+  double* rb = (double*)(ws + L.total);
+  T* env1 = (T*)(ws + L.total + align_up((size_t)W * 24));
+  int* uidx = (int*)(ws + L.uidx);
+  int* ucnt = (int*)(ws + L.ucnt);
+  int* off = (int*)(ws + L.off);
+  T* basis = (T*)(ws + L.basis);
+  T* env0 = (T*)(ws + L.envnew);
+  hipLaunchKernelGGL(k_swap_propose, dim3((W + 3) / 4), dim3(256), 0, st, R, W, D.n, D.nu, ea, eb, D.cut * D.cut,
+                     L.capS[0], L.capS[1], L.capmax, ra, rb, uidx, ucnt, P.jas, (double*)(ws + L.dj), status);
+  CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off, L.rowcap[0], L.rowcap[1],
+                     (const int*)nullptr, status);
+  CHECK(hipGetLastError());
+  T* hs[2][2];
+  T* ms[2];
+  int* ri[2];
+  for (int s = 0; s < 2; ++s) {
+    hs[s][0] = (T*)(ws + L.hseg[s][0]);
+    hs[s][1] = (T*)(ws + L.hseg[s][1]);
+    ms[s] = (T*)(ws + L.mseg[s]);
+    ri[s] = (int*)(ws + L.rowinfo[s]);
+  }
+  hipLaunchKernelGGL(k_msg_swap<T>, dim3(W), dim3(blk), 0, st, P, W, ea, eb, R, (const int*)uidx, L.capmax,
+                     (const int*)ucnt, (const int*)off, (const char*)state, S, hs[0][0], hs[1][0], ms[0], ms[1], ri[0],
+                     ri[1]);
+  CHECK(hipGetLastError());
+  // envelopes of the two moved slots at their new positions
+  const T* envs[2] = {env0, env1};
+  for (int s = 0; s < 2; ++s) {
+    const int N = D.nsig(s);
+    hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)(((int64_t)W * D.B + 255) / 256)), dim3(256), 0, st, P,
+                       (const double*)(s == 0 ? ra : rb), (int64_t)W, basis, (const int*)nullptr);
+    CHECK(hipGetLastError());
+    GemmArgs g{};
+    g.A = basis; g.amap = rows_dense(D.B); g.Bt = s == 0 ? P.pi0 : P.pi1; g.ldb = D.B;
+    g.C = (void*)envs[s]; g.cmap = rows_dense((int64_t)D.K * N); g.ccol = cols_dense(); g.M = W; g.N = D.K * N;
+    g.K = D.B;
+    CHECK(gemm_site(h, SITE_ORB, g, st));
+  }
+  for (int s = 0; s < 2; ++s) {
+    const int N = D.nsig(s);
+    const int e_s = s == 0 ? ea : eb;
+    const int* Mdev = off + s * (W + 1) + W;
+    const int rows = (int)L.rowcap[s];
+    T* hin = hs[s][0];
+    T* hout = hs[s][1];
+    for (int k = 0; k < D.L; ++k) {
+      GemmArgs g{};
+      g.A = hin; g.amap = rows_dense(D.d);
+      g.Bt = (const char*)P.mlp_t + (size_t)k * D.d * D.d * h->gsize; g.ldb = D.d;
+      g.bias = P.mlp_b + (int64_t)k * D.d; g.C = hout; g.cmap = rows_dense(D.d); g.ccol = cols_dense();
+      g.M = rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU; g.Mdev = Mdev;
+      CHECK(gemm_site(h, SITE_EMB, g, st));
+      T* t = hin; hin = hout; hout = t;
+    }
+    T* oseg = (T*)(ws + L.oseg[s]);
+    GemmArgs o{};
+    o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
+    o.C = oseg; o.cmap = rows_dense((int64_t)D.K * N); o.ccol = cols_dense();
+    o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
+    CHECK(gemm_site(h, SITE_ORB, o, st));
+    const int64_t items = (int64_t)W * D.K;
+    const int64_t quads = (items + 3) / 4;
+    if (h->isize == 8)
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W,
+                         (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
+                         (double*)(ws + L.detA), 1, (const int*)nullptr);
+    else
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W,
+                         (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
+                         (double*)(ws + L.detA), 1, (const int*)nullptr);
+    CHECK(hipGetLastError());
+    if (L.capS[s] > 16) {
+      if (h->isize == 8)
+        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W,
+                           (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
+                           (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
+                           (double*)(ws + L.detA), 1, (const int*)nullptr);
+      else
+        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W,
+                           (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
+                           (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
+                           (double*)(ws + L.detA), 1, (const int*)nullptr);
+      CHECK(hipGetLastError());
+    }
+    if (L.capS[s] > 32) {
+      const size_t lds = detA_lds(L.capmax);
+      const unsigned nblk = (unsigned)(W < 2048 ? W : 2048);
+      if (h->isize == 8) {
+        CHECK(hipFuncSetAttribute((const void*)k_detA<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+        hipLaunchKernelGGL((k_detA<T, double>), dim3(nblk), dim3(256), lds, st, D, W, (const int*)nullptr, s, e_s,
+                           (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off, (const T*)nullptr,
+                           (const T*)oseg, envs[s], (const char*)state, S, (double*)(ws + L.detA), 1);
+      } else {
+        CHECK(hipFuncSetAttribute((const void*)k_detA<T, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+        hipLaunchKernelGGL((k_detA<T, float>), dim3(nblk), dim3(256), lds, st, D, W, (const int*)nullptr, s, e_s,
+                           (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off, (const T*)nullptr,
+                           (const T*)oseg, envs[s], (const char*)state, S, (double*)(ws + L.detA), 1);
+      }
+      CHECK(hipGetLastError());
+    }
+  }
+  hipLaunchKernelGGL(k_swap_ratio, dim3((W + 127) / 128), dim3(128), 0, st, D, W, ea, (const double*)(ws + L.detA),
+                     (const double*)(ws + L.dj), (const char*)state, S, (const int32_t*)status, ratios);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t splus_impl(fire_handle* h, int W, const double* R, char* state, char* ws, int eb, double* ratios,
+                             double* rb, int32_t* status, hipStream_t st) {
+  const Dims& D = h->D;
+  Net<T> P = make_net<T>(h);
+  CHECK(fill_i32(status, W, 0, st));
+  for (int ea = 0; ea < D.nu; ++ea) CHECK(swap_ratio<T>(h, P, W, ea, eb, R, state, ws, status, ratios, st));
+  hipLaunchKernelGGL(k_splus_rb, dim3((W + 127) / 128), dim3(128), 0, st, W, D.nu, (const double*)ratios, rb);
+  return hipGetLastError();
+}
+
+hipError_t splus_path(fire_handle* h, int W, const double* R, char* state, char* ws, int eb, double* ratios,
+                      double* rb, int32_t* status, hipStream_t s) {
+  if (!update_fits(h)) return hipErrorInvalidValue;
+  return h->tsize == 8 ? splus_impl<double>(h, W, R, state, ws, eb, ratios, rb, status, s)
+                       : splus_impl<float>(h, W, R, state, ws, eb, ratios, rb, status, s);
+}
+
 template hipError_t propose_ratio<double>(const fire_handle*, const Net<double>&, const Jobs&, int,
                                           const double*, char*, char*, int32_t*, hipStream_t);
 template hipError_t propose_ratio<float>(const fire_handle*, const Net<float>&, const Jobs&, int, const double*,

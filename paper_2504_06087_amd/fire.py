@@ -23,7 +23,7 @@ W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
            "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_eval_logpsi_noalloc",
            "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
-           "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_spring_step", "fire_sync_status",
+           "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_spring_step", "fire_splus_ratios", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
            "fire_batch_create", "fire_batch_destroy", "fire_batch_num_params", "fire_batch_system",
            "fire_batch_sizes", "fire_batch_set_params", "fire_batch_step", "fire_batch_graph_create",
@@ -91,6 +91,7 @@ def load() -> ctypes.CDLL:
     lib.fire_ecp_nonlocal.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_grad_params.argtypes = [P, I, V, V, V, V, V, V, V, V]
     lib.fire_spring_step.argtypes = [P, I, V, V, D, D, V, V, D, V, V, V, V]
+    lib.fire_splus_ratios.argtypes = [P, I, V, V, V, I, V, V, V, V]
     lib.fire_sync_status.argtypes = [P, V, V, I, ctypes.POINTER(ctypes.c_int32)]
     lib.fire_profile_begin.argtypes = [P, V, V, I]
     lib.fire_profile_end.argtypes = [P, V, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -361,6 +362,17 @@ class Fire:
         _check(load().fire_grad_params(self.h, W, _dp(R), _dp(state), _dp(ws), _dp(coeff), _dp(g), _dp(per_walker),
                                        _dp(status), _stream()), "fire_grad_params")
         return g, status
+
+    def splus_ratios(self, R, state, ws, beta: int):
+        """fire_splus_ratios: psi(pi_{a,beta} r)/psi(r) for every spin-up a,
+        and R_beta = 1 - sum_a; returns (ratios [W][n_up], r_beta [W], status)."""
+        W = R.shape[0]
+        ratios = torch.empty(W, self.system.n_up, dtype=torch.float64, device=self.device)
+        rb = torch.empty(W, dtype=torch.float64, device=self.device)
+        status = torch.empty(W, dtype=torch.int32, device=self.device)
+        _check(load().fire_splus_ratios(self.h, W, _dp(R), _dp(state), _dp(ws), int(beta), _dp(ratios), _dp(rb),
+                                        _dp(status), _stream()), "fire_splus_ratios")
+        return ratios, rb, status
 
     def spring_step(self, O, e_loc, ws, lam, eta, delta_prev=None, delta_tilde=None, lam_pinv=0.0):
         """fire_spring_step: the natural-gradient update from per-walker

@@ -823,3 +823,55 @@ def test_spring_extra_gradient_split():
     a_c = a - a.mean()
     x = np.linalg.solve(Ob @ Ob.T + lam * np.eye(O.shape[0]), (e - e.mean()) + a_c - Ob @ (eta * dprev))
     assert np.allclose(d_in, Ob.T @ x + eta * dprev, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# S+ spin penalty (SI, low-rank updates in S+ operator)
+# --------------------------------------------------------------------------
+def _closed_shell_h4(W=6, seed=4, n_det=2):
+    """H4 (2 up, 2 down) with the zeroed network (every embedding the same
+    constant) and the same orbital weights and envelopes in both spin blocks:
+    every determinant is a closed-shell product D(phi; r_up) D(phi; r_down)
+    of one set of spatial orbitals."""
+    w = wl.config(0, walkers=W)
+    s, m, p, R = w.systems[0], w.model, w.params[0], w.R[0]
+    m.n_det = n_det
+    rng = np.random.default_rng(seed)
+    p = wl.init_params(s, m, rng)
+    wl.zero_network(p)
+    p["orb_W_dn"] = p["orb_W_up"].copy()
+    p["env_pi_dn"] = p["env_pi_up"].copy()
+    return s, m, p, R
+
+
+def test_splus_estimator_vanishes_for_closed_shell_products():
+    """For a sum of closed-shell products, each factor built from one set of
+    spatial orbitals for both spins, sum_a psi(pi_{a,beta} r)/psi(r) = 1 at
+    every configuration (expanding the swapped determinants by their rows:
+    sum_a sum_k phi_k(r_beta) (Phi_up^-1)_ka phi_l(r_a) (Phi_dn^-1)_lb
+    collapses through Phi_up^-1 Phi_up = I to (Phi_dn Phi_dn^-1)_bb = 1), so
+    R_beta = 0: the singlet has no S+ component.  With different orbitals in
+    the two blocks it does not vanish."""
+    s, m, p, R = _closed_shell_h4()
+    o = Oracle(s, m, p)
+    for beta in (2, 3):
+        ratios, rb = o.splus_ratios(R, beta)
+        assert np.abs(rb.numpy()).max() < 1e-10
+        assert np.abs(ratios.numpy()).max() > 1e-3     # the ratios themselves are not trivial
+    p2 = dict(p)
+    p2["env_pi_dn"] = p["env_pi_dn"] + 0.5 * np.random.default_rng(8).normal(size=p["env_pi_dn"].shape)
+    _, rb2 = Oracle(s, m, p2).splus_ratios(R, 2)
+    assert np.abs(rb2.numpy()).min() > 1e-6
+
+
+def test_splus_swap_is_an_involution():
+    """Swapping twice restores the configuration: the ratio at the swapped
+    walkers is the reciprocal of the ratio at the original ones."""
+    w = wl.config(0, walkers=5)
+    o = Oracle(w.systems[0], w.model, w.params[0])
+    R = w.R[0]
+    r1, _ = o.splus_ratios(R, 2)
+    Rs = R.copy()
+    Rs[:, [0, 2]] = R[:, [2, 0]]
+    r2, _ = o.splus_ratios(Rs, 2)
+    assert np.allclose(r1[:, 0].numpy() * r2[:, 0].numpy(), 1.0, rtol=1e-12)
