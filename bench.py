@@ -187,13 +187,28 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
         gmm = {"ms": ev[0].elapsed_time(ev[1]), "acceptance": float((nacc - g0).sum().item()) / (W * n),
                "walker_steps_per_s": W * n / (ev[0].elapsed_time(ev[1]) / 1e3),
                "flagged_walkers": int((gst != 0).sum().item())}
+    # the S+ estimator for one spin-down electron: n_up two-electron swap
+    # ratios per walker by low-rank updates, on the final state
+    splus = None
+    if profile:
+        F.eval_logpsi(R, state, ws)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        _, rb, sst = F.splus_ratios(R, state, ws, s.n_up)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1])
+        splus = {"ms": t, "swap_ratios_per_s": W * s.n_up / (t / 1e3), "beta": s.n_up,
+                 "flagged_walkers": int((sst != 0).sum().item()),
+                 "mean_r_beta_squared": float(torch.nan_to_num(rb * rb).mean().item())}
     ph = {k: v / steps for k, v in ph.items()}
     if ovl is not None:
-        # the timed step with its local-energy phase scaled by the measured
-        # overlapped / serial ratio on the same state
+        # an estimate, not a measured step: the timed step with its
+        # local-energy phase scaled by the overlapped / serial ratio of the
+        # two calls above on the same state
         el = ph["local_energy"] * ovl["local_energy_ms"] / ovl["local_energy_ms_serial"]
-        ovl["ms_per_step"] = sum(ph.values()) - ph["local_energy"] + el
-        ovl["walkers_per_s"] = W / (ovl["ms_per_step"] / 1e3)
+        ovl["estimated_ms_per_step"] = sum(ph.values()) - ph["local_energy"] + el
+        ovl["estimated_walkers_per_s"] = W / (ovl["estimated_ms_per_step"] / 1e3)
     e_np = last_e.cpu().numpy()
     out = dict(phases_ms=ph, ms_per_step=sum(ph.values()), acceptance=acc_rate, have_grad=have_grad,
                e_loc_mean=float(np.nanmean(e_np)), e_loc_median=float(np.nanmedian(e_np)),
@@ -204,7 +219,90 @@ def run_precision(prec, split, W, steps, warmup, want_grad, profile):
     out["prof"] = prof
     out["global_jump_sweep"] = gmm
     out["stream_overlap"] = ovl
+    out["splus"] = splus
+    if profile:
+        out["counts"] = measured_counts(work, R.cpu().numpy(), work.step)
     return out
+
+
+def measured_counts(work, R, step, sample=256, seed=5):
+    """Neighbour and update-set counts on the walkers the timed steps left
+    (a sample): |N_i| within c, |U| of a proposal of scale `step`, and
+    pseudopotential (electron, atom) pairs within r_max per walker."""
+    s, m = work.systems[0], work.model
+    R = R[:sample]
+    W, n = R.shape[:2]
+    d = np.linalg.norm(R[:, :, None] - R[:, None], axis=-1)
+    nb = (d <= m.cutoff).sum(-1) - 1
+    rng = np.random.default_rng(seed)
+    e = rng.integers(0, n, size=W)
+    rn = R[np.arange(W), e] + step * rng.normal(size=(W, 3))
+    d_old = d[np.arange(W), e]
+    d_new = np.linalg.norm(R - rn[:, None], axis=-1)
+    U = ((d_old <= m.cutoff) | (d_new <= m.cutoff)).sum(-1)
+    dn = np.linalg.norm(R[:, :, None] - s.R_nuc[None, None], axis=-1)
+    ecp = ((dn < s.ecp_rmax) & (s.species[None, None] == 1)).sum((1, 2)) if s.ecp else np.zeros(W)
+    return {"walkers_sampled": int(W), "n_nb_mean": float(nb.mean()), "n_nb_max": int(nb.max()),
+            "update_set_mean": float(U.mean()), "update_set_max": int(U.max()),
+            "ecp_pairs_per_walker_mean": float(ecp.mean()), "ecp_pairs_per_walker_max": int(ecp.max())}
+
+
+def run_tolerance(split, W=64):
+    """The hybrid's stated E_L tolerance on a sample of the benchmark's
+    walkers: E_L of the same W walkers in the BF16 hybrid and in FP64."""
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    work = wl.config(3, walkers=W)
+    Q = torch.tensor(wl.haar_rotations(W, np.random.default_rng(7)), device="cuda")
+    R = torch.tensor(work.R[0], dtype=torch.float64, device="cuda")
+    e = {}
+    for prec, sp in (("fp64", 0), ("bf16", split)):
+        F = fire.Fire(work.systems[0], work.model, prec, max_walkers=W, cap_nbr=48, cap_upd=64, bf16_split=sp)
+        F.set_params(work.params[0])
+        state, ws = F.buffers(W)
+        F.eval_logpsi(R, state, ws)
+        e[prec], _, _, _ = F.local_energy(R, state, ws, Q)
+        torch.cuda.synchronize()
+        e[prec] = e[prec].cpu().numpy()
+        del F, state, ws
+        torch.cuda.empty_cache()
+    d = e["bf16"] - e["fp64"]
+    return {"walkers": W, "bar_ha": 1e-3, "batch_mean_diff_ha": float(np.mean(d)),
+            "median_abs_diff_ha": float(np.median(np.abs(d))), "max_abs_diff_ha": float(np.abs(d).max()),
+            "met": bool(abs(np.mean(d)) <= 1e-3)}
+
+
+def run_spring(W=256):
+    """One natural-gradient step at the benchmark's molecule and network:
+    the per-walker gradients [W][P] (the adjoint one walker at a time), then
+    the W x W Gram matrix, its centring and the FP64 Cholesky solve."""
+    import torch
+    import workloads as wl
+    from paper_2504_06087_amd import fire
+
+    work = wl.config(3, walkers=W)
+    F = fire.Fire(work.systems[0], work.model, "bf16", max_walkers=W, cap_nbr=48, cap_upd=64, bf16_split=7)
+    F.set_params(work.params[0])
+    state, ws = F.buffers(W)
+    R = torch.tensor(work.R[0], dtype=torch.float64, device="cuda")
+    Q = torch.tensor(wl.haar_rotations(W, np.random.default_rng(7)), device="cuda")
+    O = torch.empty(W, F.P, dtype=torch.float64, device="cuda")
+    F.eval_logpsi(R, state, ws)
+    e, _, _, _ = F.local_energy(R, state, ws, Q)
+    coeff = torch.zeros(W, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    F.grad_params(R, state, ws, coeff, per_walker=O)
+    ev[1].record(stream)
+    delta, info = F.spring_step(O, e, ws, 1e-3, 0.99)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    return {"walkers": W, "parameters": F.P, "per_walker_grad_ms": ev[0].elapsed_time(ev[1]),
+            "spring_step_ms": ev[1].elapsed_time(ev[2]), "info": int(info.item()),
+            "delta_norm": float(delta.norm().item())}
 
 
 def run_el_rule(split, W, n_quad):
@@ -432,13 +530,38 @@ def cpu_baseline():
     O.log_psi(Rq)
     t_24 = time.time() - t0
     t_el = t_fwd + t_lap * (3 * s.n_el / len(coords)) + t_24 * (12 * pairs / 24.0)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 1.0 / t_el, "unit": "local energies/s", "cores": torch.get_num_threads(), "kind": "oracle",
+        "cpu_model": model,
         "walker_steps_per_s": 1.0 / t_fwd,
         "sample": (f"1 walker of the same workload: forward ({t_fwd:.2f}s), gradient + 12 of {3 * s.n_el} Hessian "
                    f"diagonal entries ({t_lap:.2f}s, scaled x{3 * s.n_el / len(coords):.0f}), 24 of {12 * pairs} "
                    f"quadrature ratios ({t_24:.2f}s, scaled); a Metropolis walker-step is one full forward"),
     }
+
+
+def model_roofline(hyb):
+    """Whole-phase fractions of the cost model's ceilings: local energies
+    against the ~100 GFLOP per walker of the model at the BF16 peak, and
+    walker-steps against the bytes a proposal moves with the measured update
+    set and acceptance (FP64 inverse)."""
+    c = hyb.get("counts") or {}
+    U = c.get("update_set_mean", 26.3)
+    acc = hyb.get("acceptance", 0.5)
+    n, d, K, N = 180, 256, 16, 90
+    bytes_step = 24 * n + 10 * U * d + 4 * U * K * N + 8 * N * U * K + acc * 4 * K * N * N * 8
+    el = hyb["local_energies_per_s"]
+    ws = hyb["walker_steps_per_s"]
+    return {"e_loc_gflop_per_walker": 100.0, "e_loc_frac_of_bf16_peak": el * 100e9 / 2.5e15,
+            "walker_step_bytes": bytes_step, "walker_step_frac_of_hbm": ws * bytes_step / HBM_PEAK}
 
 
 def main():
@@ -495,6 +618,12 @@ def main():
         torch.cuda.empty_cache()
         c5 = run_c5(a.split, a.c5_walkers, a.steps, a.warmup)
         print(f"# c5: {json.dumps(c5)}", flush=True)
+    torch.cuda.empty_cache()
+    tol = run_tolerance(a.split)
+    print(f"# hybrid E_L tolerance: {json.dumps(tol)}", flush=True)
+    torch.cuda.empty_cache()
+    spring = run_spring()
+    print(f"# spring: {json.dumps(spring)}", flush=True)
     cpu = None if a.no_cpu else cpu_baseline()
     line = {
         "metric": METRIC, "value": hyb["walkers_per_s"], "unit": "local energies/s", "n_gpus": 1,
@@ -511,6 +640,11 @@ def main():
         "global_jump_sweep": hyb.get("global_jump_sweep"),
         "stream_overlap": hyb.get("stream_overlap"),
         "local_energy_4point_rule": rule4,
+        "hybrid_e_loc_tolerance": tol,
+        "measured_counts": hyb.get("counts"),
+        "model_roofline": model_roofline(hyb),
+        "splus_estimator": hyb.get("splus"),
+        "spring_step": spring,
         "fp32_plain": None if fp32 is None else {
             "value": fp32["walkers_per_s"], "ms_per_step": fp32["ms_per_step"], "phases_ms": fp32["phases_ms"],
             "walker_steps_per_s": fp32["walker_steps_per_s"],

@@ -171,6 +171,17 @@ fire_status fire_set_params(fire_handle* h, const double* theta, void* params_bu
  * a stream or event cannot be created. */
 fire_status fire_set_overlap(fire_handle* h, int on);
 
+/* Upper bound on the quadrature jobs per chunk of the nonlocal
+ * pseudopotential (Methods, pseudopotentials: each electron's quadrature
+ * points go through the low-rank ratio in chunks).  0 (the default) lets
+ * the library choose: equal chunks covering an electron's job bound, at most
+ * 24 GiB of update segments per chunk.  A positive max_jobs lowers that cap
+ * (rounded down to a multiple of 12, at least 12), which shrinks the
+ * workspace fire_sizes reports; call fire_sizes after this.  Results do not
+ * depend on the chunking (each walker's quadrature terms are summed in one
+ * fixed order).  Errors: FIRE_ERR_ARG for a null handle or max_jobs < 0. */
+fire_status fire_set_ecp_chunk(fire_handle* h, int max_jobs);
+
 /* log|psi| and its sign for W walkers (Methods, eq. wf with the cusp
  * Jastrow factor as J: psi = exp(J_cusp) sum_d det Phi_d^up det Phi_d^down,
  * J_cusp = sum_{i<j} w a^2/(a + r_ij) with theta entry jas_cusp = (w_par,

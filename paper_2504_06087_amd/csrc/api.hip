@@ -423,6 +423,12 @@ fire_status fire_set_overlap(fire_handle* h, int on) {
   return FIRE_OK;
 }
 
+fire_status fire_set_ecp_chunk(fire_handle* h, int max_jobs) {
+  if (!h || max_jobs < 0) return FIRE_ERR_ARG;
+  h->ecp_chunk_cap = max_jobs;
+  return FIRE_OK;
+}
+
 fire_status fire_set_params(fire_handle* h, const double* theta, void* params_buf, hipStream_t s) {
   if (!h || !theta || !params_buf) return FIRE_ERR_ARG;
   return fire::set_params_split(h, theta, theta + th(h, "orb_W_up").offset, params_buf, s);

@@ -44,6 +44,14 @@ struct Dims {
 // each XCD one contiguous run of logical blocks, so consecutive blocks that
 // read the same rows share that XCD's L2.
 FIRE_DEV int64_t xcd_run(int64_t b, int64_t grid) { return (b & 7) * (grid >> 3) + (b >> 3); }
+// The same dealing in runs of T logical blocks: XCD b % 8 takes every
+// eighth run, in order, so each run (blocks that share rows) stays in one
+// L2 while a live prefix of the grid (the rest exiting at once) still
+// spreads over all eight XCDs.  The grid is a multiple of 8 T.
+FIRE_DEV int64_t xcd_runs(unsigned b, unsigned T) {
+  const unsigned i = b >> 3, q = i / T;
+  return ((int64_t)(q << 3) + (b & 7)) * T + (i - q * T);
+}
 FIRE_HOST_DEVICE int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
 
 // Per-walker size in elements of Phi / Phi^-1 for all determinants.

@@ -254,16 +254,41 @@ struct EcpLayout {
   size_t total;
 };
 
+// Jobs per electron are at most W * ecp_pmax * (largest rule): an electron
+// lies within r_max of at most ecp_pmax pseudo-atoms (a bound fixed by the
+// geometry at handle creation).
+static int64_t ecp_job_bound(const fire_handle* h, int W) {
+  int nqmax = 0;
+  for (const EcpChan& c : h->ecp) nqmax = c.nquad > nqmax ? c.nquad : nqmax;
+  const int pm = h->ecp_pmax < ECP_PMAX ? h->ecp_pmax : ECP_PMAX;
+  const int64_t b = (int64_t)W * (pm > 0 ? pm : 1) * (nqmax > 0 ? nqmax : 1);
+  return b > 0 ? b : 1;
+}
+
 static EcpLayout ecp_layout(const fire_handle* h, int W, int lanes) {
   EcpLayout L{};
   const Dims& D = h->D;
-  // jobs per chunk and lane: about 12 jobs per electron and walker, at most
-  // 32760 / lanes, a multiple of 4, 6 and 12 (the update segments reserve 32
-  // rows per job and spin; at 180 electrons and 16 determinants 32760 jobs
-  // take ~31 GB of workspace)
-  const int64_t cap = 32760 / lanes;
-  int64_t want = (int64_t)W * 12;
-  L.Jc = (int)(want < cap ? (want > 264 ? want : 264) : cap);
+  // Jobs per chunk and lane.  A chunk's update segments hold kRowsPerJob
+  // rows per job and spin of K N_s orbital values each: the cap keeps every
+  // element index of a segment below 2^31 and a lane's segments within
+  // 24 GiB.  The chunks of an electron's bound are made equal and a
+  // multiple of 12 (the sizes of the 4-, 6- and 12-point rules divide it).
+  const UpdLayout u1k = upd_layout(h, 1024, false);
+  int64_t per_row = 1;
+  for (int s = 0; s < 2; ++s) {
+    const int64_t r = (u1k.rowcap[s] / 1024) * D.K * (D.nsig(s) > 0 ? D.nsig(s) : 1);
+    per_row = r > per_row ? r : per_row;
+  }
+  const int64_t cap_idx = (int64_t)0x7fffffff / per_row;
+  const int64_t cap_mem = ((int64_t)24 << 30) / (int64_t)(u1k.total / 1024 + 64);
+  int64_t cap = (cap_idx < cap_mem ? cap_idx : cap_mem) / lanes;
+  if (h->ecp_chunk_cap > 0 && h->ecp_chunk_cap < cap) cap = h->ecp_chunk_cap;
+  cap = cap / 12 * 12;
+  if (cap < 12) cap = 12;
+  const int64_t bound = ecp_job_bound(h, W);
+  const int64_t nch = (bound + cap - 1) / cap;
+  const int64_t jc = ((bound + nch - 1) / nch + 11) / 12 * 12;
+  L.Jc = (int)(jc < cap ? jc : cap);
   size_t o = 0;
   auto take = [&](size_t b) { size_t r = o; o = align_up(o + b); return r; };
   L.cnt = take((size_t)D.n * W * 4);
@@ -291,17 +316,11 @@ size_t ecp_ws_bytes(const fire_handle* h, int W) {
   return a > b ? a : b;
 }
 
-// Chunks per electron.  An electron is within r_max of at most ecp_pmax
-// pseudo-atoms (a bound fixed by the geometry at handle creation), so it has
-// at most W * ecp_pmax * (largest rule) jobs; the chunk loop covers that
-// bound and each chunk reads its live job count on the device, so no count
-// is read back to the host.
+// Chunks per electron: the chunk loop covers the job bound and each chunk
+// reads its live job count on the device, so no count is read back to the
+// host.
 static int ecp_chunks(const fire_handle* h, int W, int Jc) {
-  int nqmax = 0;
-  for (const EcpChan& c : h->ecp) nqmax = c.nquad > nqmax ? c.nquad : nqmax;
-  const int pm = h->ecp_pmax < ECP_PMAX ? h->ecp_pmax : ECP_PMAX;
-  const int64_t bound = (int64_t)W * pm * nqmax;
-  return (int)((bound + Jc - 1) / Jc);
+  return (int)((ecp_job_bound(h, W) + Jc - 1) / Jc);
 }
 
 template <typename T>

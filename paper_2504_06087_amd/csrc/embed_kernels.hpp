@@ -250,6 +250,7 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
                                                   T* __restrict__ y_out, int epb, const int* __restrict__ nrows_dev) {
   // rows at or beyond a device row count (when given) are inactive
   if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
+  if ((int64_t)blockIdx.x * epb >= nrows) return;
   constexpr int ERB = sizeof(T) == 4 ? 4 : 2;   // electrons per pass (LDS: ERB x MCH pair features)
   const Dims& D = P.D;
   __shared__ T feat[ERB * MCH * FEAT];
@@ -342,12 +343,13 @@ template <typename T>
 __global__ void k_glu(const T* __restrict__ ug, T* __restrict__ out, int64_t nrows, int d,
                       const int* __restrict__ nrows_dev) {
   if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nrows * d) return;
-  int64_t r = i / d;
-  int c = (int)(i % d);
-  T u = ug[r * 2 * d + c], g = ug[r * 2 * d + d + c];
-  out[i] = u * silu_(g);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows * d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / d;
+    const int c = (int)(i % d);
+    const T u = ug[r * 2 * d + c], g = ug[r * 2 * d + d + c];
+    out[i] = u * silu_(g);
+  }
 }
 
 // Envelope basis exp(-sigma_me |r_i - R_m|), row e = (w, i), column m*E + k.
@@ -356,13 +358,14 @@ __global__ void k_env_basis(Net<T> P, const double* __restrict__ R, int64_t nrow
                             const int* __restrict__ nrows_dev) {
   const Dims& D = P.D;
   if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
-  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= nrows * D.B) return;
-  int64_t e = q / D.B;
-  int b = (int)(q % D.B), m = b / D.E;
-  double dx = R[3 * e] - P.Rn[3 * m], dy = R[3 * e + 1] - P.Rn[3 * m + 1], dz = R[3 * e + 2] - P.Rn[3 * m + 2];
-  T dist = (T)sqrt(dx * dx + dy * dy + dz * dz);
-  out[q] = exp(-P.env_sigma[b] * dist);
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nrows * D.B;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = q / D.B;
+    const int b = (int)(q % D.B), m = b / D.E;
+    const double dx = R[3 * e] - P.Rn[3 * m], dy = R[3 * e + 1] - P.Rn[3 * m + 1], dz = R[3 * e + 2] - P.Rn[3 * m + 2];
+    const T dist = (T)sqrt(dx * dx + dy * dy + dz * dz);
+    out[q] = exp(-P.env_sigma[b] * dist);
+  }
 }
 
 

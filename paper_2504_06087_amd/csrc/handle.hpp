@@ -71,6 +71,7 @@ struct fire_handle {
   const double* theta_dev;      // theta passed to fire_set_params
   // most pseudo-atoms within ecp_rmax of any one point (from the geometry)
   int ecp_pmax = 0;
+  int ecp_chunk_cap = 0;   // fire_set_ecp_chunk: jobs per chunk cap (0: automatic)
   // second stream of the local energy: the kinetic energy runs on it beside
   // the pseudopotential on the caller's stream (default priority), with the
   // events that order it against the caller's stream; and a third stream

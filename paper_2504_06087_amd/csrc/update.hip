@@ -54,11 +54,24 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
     L.hseg[s][1] = take(rows * D.d * ts);
     L.mseg[s] = take(rows * D.d * ts);
     L.oseg[s] = take(rows * D.K * N * ts);
-    L.dphi[s] = take(rows * D.K * N * ts);
+    // dPhi rows are kept only for the Woodbury update; ratio-only batches
+    // form them on the fly
+    L.dphi[s] = with_woodbury ? take(rows * D.K * N * ts) : 0;
     L.bbuf[s] = with_woodbury ? take(rows * D.K * N * 8) : 0;
   }
   L.total = o;
   return L;
+}
+
+// Det-lemma block order: eight job groups (jg consecutive jobs, K
+// determinants each; a walker's groups are consecutive and read the same
+// rows of Phi^-1) form a run of det_run blocks of `per` items; runs are
+// dealt to the XCDs in turn (xcd_runs), and the grid is a whole number of
+// eight runs.
+FIRE_HOST_DEVICE int det_run(int jg, int K, int per) { return (8 * jg * K + per - 1) / per; }
+static unsigned det_grid(int64_t blocks, int jg, int K, int per) {
+  const int64_t r8 = 8 * det_run(jg, K, per);
+  return (unsigned)((blocks + r8 - 1) / r8 * r8);
 }
 
 static size_t detA_lds(int k) { return (size_t)(k * (k + 1) + 2 * k + 8) * sizeof(double); }
@@ -201,16 +214,19 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
 
 // exclusive scan of the per-spin member counts: off[s][w], off[s][W] = total.
 // A job whose rows would end beyond the segment capacity gets zero members
-// (it is skipped) and its walker is flagged.
+// (it is skipped) and its walker is flagged.  Jobs at or beyond a device job
+// count (when given) have no members: the scan covers the live ones and the
+// rest get the total as their offset.
 __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, int W, int* __restrict__ off,
                                                       int64_t cap0, int64_t cap1, const int* __restrict__ jw,
-                                                      int32_t* __restrict__ status) {
+                                                      int32_t* __restrict__ status, const int* __restrict__ Jdev) {
   __shared__ int part[2][1024];
-  __shared__ int first_over[2];
+  __shared__ int first_over[2], total[2];
   const int t = threadIdx.x, nt = blockDim.x;
-  const int per = (W + nt - 1) / nt;
+  const int Wl = Jdev && *Jdev < W ? (*Jdev > 0 ? *Jdev : 0) : W;
+  const int per = (Wl + nt - 1) / nt;
   if (t < 2) first_over[t] = 0x7fffffff;
-  const int b = t * per, e = b + per < W ? b + per : W;
+  const int b = t * per, e = b + per < Wl ? b + per : Wl;
   int s0 = 0, s1 = 0;
   for (int w = b; w < e; ++w) { s0 += ucnt[2 * w]; s1 += ucnt[2 * w + 1]; }
   part[0][t] = s0;
@@ -220,8 +236,13 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, in
     int acc = 0;
     for (int k = 0; k < nt; ++k) { int v = part[t][k]; part[t][k] = acc; acc += v; }
     off[t * (W + 1) + W] = acc;
+    total[t] = acc;
   }
   __syncthreads();
+  for (int w = Wl + t; w < W; w += nt) {
+    off[w] = total[0];
+    off[(W + 1) + w] = total[1];
+  }
   int a0 = part[0][t], a1 = part[1][t];
   for (int w = b; w < e; ++w) {
     off[w] = a0;
@@ -767,12 +788,13 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
                                                    const T* __restrict__ dphi, const T* __restrict__ oseg,
                                                    const T* __restrict__ envnew, int fused,
                                                    const char* __restrict__ state, StateRec S,
-                                                   double* __restrict__ detA, int jg, const int* __restrict__ Jdev) {
+                                                   double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][4 * 16 * 17];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t quad = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
-  // jobs at or beyond a device job count (when given) are inactive
-  const int Wact = Jdev && *Jdev < W ? *Jdev : W;
+  const int64_t quad = xcd_runs(blockIdx.x, det_run(jg, D.K, 16)) * 4 + wave;
+  // jobs at or beyond a device job count have empty update sets (k_propose
+  // clears their counts), so their items end at the counts read below
+  const int Wact = W;
   const int ngroups = (Wact + jg - 1) / jg;
   const int64_t total = (int64_t)ngroups * D.K * jg;
   if (quad * 4 >= total) return;
@@ -873,11 +895,11 @@ __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const 
                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
                                                   const T* __restrict__ envnew, int fused,
                                                   const char* __restrict__ state, StateRec S,
-                                                  double* __restrict__ detA, int jg, const int* __restrict__ Jdev) {
+                                                  double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][32 * 33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t item = xcd_run(blockIdx.x, gridDim.x) * 4 + wave;
-  const int Wact = Jdev && *Jdev < W ? *Jdev : W;
+  const int64_t item = xcd_runs(blockIdx.x, det_run(jg, D.K, 4)) * 4 + wave;
+  const int Wact = W;   // jobs beyond a device job count have empty update sets
   const int ngroups = (Wact + jg - 1) / jg;
   if (item >= (int64_t)ngroups * D.K * jg) return;
   const int gq = (int)(item % jg);
@@ -1522,7 +1544,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
                      L.capS[0], L.capS[1], L.capmax, rnew, uidx, ucnt, P.jas, (double*)(ws + L.dj), status);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off, L.rowcap[0], L.rowcap[1], jb.jw,
-                     status);
+                     status, jb.Jdev);
   CHECK(hipGetLastError());
   // h0 and projections of the moved electron
   const int epb = W >= 16384 ? 4 : (W >= 4096 ? 2 : 1);
@@ -1609,29 +1631,29 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     const int jg = jb.group > 0 ? jb.group : 1;
     const int64_t items = (int64_t)((W + jg - 1) / jg) * jg * D.K;
     const int64_t quads = (items + 3) / 4;
-    // grids rounded to a multiple of 8 for the XCD-contiguous block order
+    // grids of whole runs of eight (det_grid) for the run-wise XCD order
     if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3(det_grid((quads + 3) / 4, jg, D.K, 16)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg, jb.Jdev);
+                         (double*)(ws + L.detA), jg);
     else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3(det_grid((quads + 3) / 4, jg, D.K, 16)), dim3(256), 0, st, D, W, jb.jw,
                          s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg, jb.Jdev);
+                         (double*)(ws + L.detA), jg);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
       if (h->isize == 8)
-        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3(det_grid((items + 3) / 4, jg, D.K, 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg, jb.Jdev);
+                           S, (double*)(ws + L.detA), jg);
       else
-        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W, jb.jw,
+        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3(det_grid((items + 3) / 4, jg, D.K, 4)), dim3(256), 0, st, D, W, jb.jw,
                            s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                            (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg, jb.Jdev);
+                           S, (double*)(ws + L.detA), jg);
       CHECK(hipGetLastError());
     }
     if (L.capS[s] > 32) {
@@ -2098,7 +2120,7 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
                      L.capS[0], L.capS[1], L.capmax, ra, rb, uidx, ucnt, P.jas, (double*)(ws + L.dj), status);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, ucnt, W, off, L.rowcap[0], L.rowcap[1],
-                     (const int*)nullptr, status);
+                     (const int*)nullptr, status, (const int*)nullptr);
   CHECK(hipGetLastError());
   T* hs[2][2];
   T* ms[2];
@@ -2151,27 +2173,27 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
     const int64_t items = (int64_t)W * D.K;
     const int64_t quads = (items + 3) / 4;
     if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W,
+      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3(det_grid((quads + 3) / 4, 1, D.K, 16)), dim3(256), 0, st, D, W,
                          (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                         (double*)(ws + L.detA), 1, (const int*)nullptr);
+                         (double*)(ws + L.detA), 1);
     else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3((unsigned)round8((quads + 3) / 4)), dim3(256), 0, st, D, W,
+      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3(det_grid((quads + 3) / 4, 1, D.K, 16)), dim3(256), 0, st, D, W,
                          (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
                          (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                         (double*)(ws + L.detA), 1, (const int*)nullptr);
+                         (double*)(ws + L.detA), 1);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
       if (h->isize == 8)
-        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W,
+        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3(det_grid((items + 3) / 4, 1, D.K, 4)), dim3(256), 0, st, D, W,
                            (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
                            (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                           (double*)(ws + L.detA), 1, (const int*)nullptr);
+                           (double*)(ws + L.detA), 1);
       else
-        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3((unsigned)round8((items + 3) / 4)), dim3(256), 0, st, D, W,
+        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3(det_grid((items + 3) / 4, 1, D.K, 4)), dim3(256), 0, st, D, W,
                            (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
                            (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                           (double*)(ws + L.detA), 1, (const int*)nullptr);
+                           (double*)(ws + L.detA), 1);
       CHECK(hipGetLastError());
     }
     if (L.capS[s] > 32) {

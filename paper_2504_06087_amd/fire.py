@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": FIRE_FP64, "fp32": FIRE_FP32, "bf16": FIRE_BF16_HYBRID}
 W_NBR_OVERFLOW, W_UPD_OVERFLOW, W_SINGULAR, W_NONFINITE, W_DETSUM_ZERO = 1, 2, 4, 8, 16
 
 EXPORTS = ["fire_create", "fire_destroy", "fire_param_layout", "fire_num_params", "fire_sizes",
-           "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_eval_logpsi", "fire_eval_logpsi_noalloc",
+           "fire_state_layout", "fire_set_params", "fire_set_overlap", "fire_set_ecp_chunk", "fire_eval_logpsi", "fire_eval_logpsi_noalloc",
            "fire_mcmc_sweep", "fire_mcmc_sweep_mixed", "fire_adapt_step",
            "fire_local_energy", "fire_ecp_nonlocal", "fire_grad_params", "fire_spring_step", "fire_splus_ratios", "fire_sync_status",
            "fire_profile_begin", "fire_profile_end", "fire_status_string",
@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
     lib.fire_state_layout.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.fire_set_params.argtypes = [P, V, V, V]
     lib.fire_set_overlap.argtypes = [P, I]
+    lib.fire_set_ecp_chunk.argtypes = [P, I]
     lib.fire_eval_logpsi.argtypes = [P, I, V, V, V, V, V, V, V]
     lib.fire_eval_logpsi_noalloc.argtypes = [P, I, V, V, V, V, V, V]
     lib.fire_mcmc_sweep.argtypes = [P, I, V, V, V, I, D, V, V, ctypes.c_uint64, ctypes.c_uint64, V, V, V, V, V]
@@ -257,6 +258,11 @@ class Fire:
     def set_overlap(self, on: bool):
         """Stream overlap inside local_energy (fire_set_overlap; off by default)."""
         _check(load().fire_set_overlap(self.h, int(bool(on))), "fire_set_overlap")
+
+    def set_ecp_chunk(self, max_jobs: int):
+        """Cap on the pseudopotential quadrature jobs per chunk (fire_set_ecp_chunk;
+        0 = automatic).  Call sizes()/buffers() afterwards."""
+        _check(load().fire_set_ecp_chunk(self.h, int(max_jobs)), "fire_set_ecp_chunk")
 
     def set_params(self, params):
         theta = params if isinstance(params, torch.Tensor) else _f64(self.flatten(params), self.device)

@@ -94,3 +94,23 @@ def test_adapt_step_is_exported_host_arithmetic():
     lib = fire.load()
     assert lib.fire_adapt_step(0.3, 5, 10, 0.5, 1.0, ctypes.byref(out)) == 0 and out.value == 0.3
     assert lib.fire_adapt_step(0.3, 11, 10, 0.5, 1.0, ctypes.byref(out)) != 0
+
+
+def test_ecp_chunk_cap_sizes_and_errors():
+    """fire_set_ecp_chunk: a negative cap or a null handle is refused; a cap
+    shrinks (never grows) the workspace fire_sizes reports; 0 restores it."""
+    from paper_2504_06087_amd import fire
+    rng = np.random.default_rng(3)
+    R, sp = wl.grown_flake(20)
+    s = wl.make_system("C4H4", R, sp, pseudo_c=True, nonlocal_ecp=True, ecp_rng=rng)
+    m = wl.make_model(s, width=64, mlp_layers=1, n_det=4, n_env=2, cutoff=5.0, cutoff_nuc=20.0)
+    F = fire.Fire(s, m, "fp64", max_walkers=512, device="cpu")
+    lib = fire.load()
+    assert lib.fire_set_ecp_chunk(ctypes.c_void_p(0), 0) == -1
+    assert lib.fire_set_ecp_chunk(F.h, -1) == -1
+    w0 = F.sizes(512)[2]
+    F.set_ecp_chunk(120)
+    w1 = F.sizes(512)[2]
+    F.set_ecp_chunk(0)
+    assert F.sizes(512)[2] == w0
+    assert w1 < w0

@@ -189,3 +189,40 @@ def test_polyene_ecp_stream_overlap(lib):
         assert (np.abs(parts - parts0) / np.maximum(1.0, np.abs(parts0))).max() <= 1e-12
         assert np.abs(g - g0).max() <= 1e-12 * max(1.0, np.abs(g0).max())
         assert (np.abs(e - eo) / scale).max() <= 1e-7
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_ecp_chunk_cap_keeps_results(lib, overlap):
+    """fire_set_ecp_chunk: caps of 12 and 36 quadrature jobs per chunk (many
+    chunks per electron, a ragged last one and empty ones) give the same V_NL
+    as the automatic single chunk and the oracle, with a smaller workspace."""
+    log(f"case: narrow C12H14 nonlocal ECP fp64 W=5, chunk caps 12/36, overlap={overlap}")
+    s, m, p, R = small_polyene(5, ecp=True, seed=13)
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    F.set_overlap(overlap)
+    Q = wl.haar_rotations(5, np.random.default_rng(9))
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    v0, st0 = F.ecp_nonlocal(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    v0 = v0.cpu().numpy()
+    vo = O.ecp_nonlocal(R, Q).numpy()
+    assert (st0.cpu().numpy() == 0).all()
+    assert np.abs(v0 - vo).max() <= 1e-9
+    wsb0 = F.sizes(5)[2]
+    for cap in (12, 36):
+        F.set_ecp_chunk(cap)
+        st1, ws1 = F.buffers(5)
+        wsb = F.sizes(5)[2]
+        F.eval_logpsi(Rd, st1, ws1)
+        v, st = F.ecp_nonlocal(Rd, st1, ws1, dev(Q))
+        torch.cuda.synchronize()
+        v = v.cpu().numpy()
+        d = np.abs(v - v0).max()
+        log(f"cap {cap}: V_NL {v} vs automatic {v0}: max diff {d:.1e}; workspace {wsb} vs {wsb0} bytes")
+        assert (st.cpu().numpy() == 0).all()
+        assert wsb <= wsb0
+        assert d <= 1e-12 * max(1.0, np.abs(v0).max())
+        assert np.abs(v - vo).max() <= 1e-9
+    F.set_ecp_chunk(0)
+    F.set_overlap(False)
