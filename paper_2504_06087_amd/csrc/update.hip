@@ -460,14 +460,6 @@ template <typename T> struct DPhiRows {
     const T en = u == e ? envnew[(int64_t)j * KN + det * N + l] : envc[(int64_t)iloc * N + l];
     return (double)(oseg[q] * en - phic[(int64_t)iloc * N + l]);
   }
-  // every row start of this item is aligned for reads of two consecutive
-  // elements (N even and all block bases aligned)
-  template <typename TI> FIRE_DEV bool pair_aligned(const TI* G) const {
-    const uintptr_t m = 2 * sizeof(T) - 1, mg = 2 * sizeof(TI) - 1;
-    if ((N & 1) != 0 || ((uintptr_t)G & mg) != 0) return false;
-    if (dphi) return ((uintptr_t)dphi & m) == 0;
-    return (((uintptr_t)oseg | (uintptr_t)envnew | (uintptr_t)envc | (uintptr_t)phic) & m) == 0;
-  }
   // base pointers of row a (electron u) for branch-free element reads:
   // x (dPhi, or o' when fused), y (envelope) and z (Phi)
   FIRE_DEV void row_ptrs(int a, int u, const T*& x, const T*& y, const T*& z) const {
@@ -561,38 +553,62 @@ FIRE_DEV uint32_t lanes32_max(uint32_t key) {
   return (uint32_t)__builtin_amdgcn_readlane((int)m, 31);
 }
 
-// log|det A| and its sign of a k x k matrix (k <= KMAX <= 32) held one row
-// per lane (lane r holds row r, columns in registers; entries past k are
-// zero).  Gaussian elimination with partial pivoting that never moves rows:
-// the pivot of column p is the largest |A_rp| among the rows not yet used
-// (ties to the lower row), its row is broadcast with readlane, and the sign
-// of the row permutation is counted as inversions.  The product of the
+// Orders this wave's LDS accesses: everything before it is complete, as
+// seen by every lane of the wave, before anything after it.
+FIRE_DEV void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// log|det A| and its sign of two matrices, one per half wave: lane 32 h + r
+// holds row r of matrix h (columns in registers; rows and columns past the
+// half's size kh <= 32 are zero).  Gaussian elimination with partial
+// pivoting that never moves rows: the pivot of column p is the largest
+// |A_rp| among the rows not yet used (ties to the lower row); the sign of
+// the row permutation is counted as inversions, and the product of the
 // pivots is carried as a mantissa and a binary exponent, so one logarithm is
-// taken at the end.  Every register index is a compile-time constant; k is
-// made wave-uniform so that the column guards are scalar branches over groups
-// of four columns (columns past k hold zeros and are updated harmlessly).
-template <int KMAX>
-FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, bool& sing) {
-  const int lane = threadIdx.x & 63;
-  k = __builtin_amdgcn_readfirstlane(k);
-  uint32_t unused = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+// taken at the end.  The pivot lane of each half stores its row (from
+// column p on) in LDS (piv: 64 doubles of this wave) and every lane of the
+// half reads it back as a broadcast, so one instruction stream eliminates
+// both matrices.  Every register index is a compile-time constant; the
+// column guards are scalar, from the larger of the two sizes.
+FIRE_DEV void halves_lu_det32(double (&row)[32], int kh, double* piv, double& sgn, double& logd, bool& sing) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, r = lane & 31;
+  const int kmax = __builtin_amdgcn_readfirstlane(max(__builtin_amdgcn_readlane(kh, 0), __builtin_amdgcn_readlane(kh, 32)));
+  uint32_t unused = kh >= 32 ? 0xffffffffu : ((1u << kh) - 1u);
   int inv = 0, ex = 0;
   double mant = 1.0;
   sgn = 1.0;
   sing = false;
+  double* prow = piv + 32 * h;
 #pragma unroll
-  for (int p = 0; p < KMAX; ++p) {
-    if (p < k && !sing) {
-      // pivot key: |A_rp| in float with the low 5 bits replaced by 31 - r
-      const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
+  for (int p = 0; p < 32; ++p) {
+    if (p < kmax) {
+      const bool act = p < kh && !sing;
+      const bool cand = act && ((unused >> r) & 1u);
       const float av = (float)fabs(row[p]);
-      const uint32_t key = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - lane)) : 0u;
-      const uint32_t best = (uint32_t)__builtin_amdgcn_readfirstlane((int)lanes32_max(key));
+      uint32_t m = cand ? ((__float_as_uint(av) & ~31u) | (uint32_t)(31 - r)) : 0u;
+      m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x111, 0xf, 0xf, false));   // row_shr:1
+      m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x112, 0xf, 0xf, false));   // row_shr:2
+      m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x114, 0xf, 0xf, false));   // row_shr:4
+      m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x118, 0xf, 0xf, false));   // row_shr:8
+      m = max(m, (uint32_t)__builtin_amdgcn_update_dpp((int)m, (int)m, 0x142, 0xa, 0xf, false));   // row_bcast:15
+      const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)m, 31);
+      const uint32_t b1 = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+      const uint32_t best = h ? b1 : b0;
       const int idx = 31 - (int)(best & 31u);
-      const double pv = readlane_f64(row[p], idx);
-      if ((best & ~31u) == 0u || !(fabs(pv) > 0.0)) {
-        sing = true;
-      } else {
+      if (act && r == idx) {
+#pragma unroll
+        for (int c0 = p & ~1; c0 < 32; c0 += 2)
+          if (c0 < kmax) *reinterpret_cast<double2*>(prow + c0) = make_double2(row[c0], row[c0 + 1]);
+      }
+      wave_lds_order();
+      const double pv = prow[p];
+      const bool ok = act && (best & ~31u) != 0u && fabs(pv) > 0.0;
+      if (act && !ok) sing = true;
+      double f = 0.0;
+      if (ok) {
         unused &= ~(1u << idx);
         inv += __popc(unused & ((1u << idx) - 1u));
         int e2;
@@ -602,21 +618,17 @@ FIRE_DEV void wave_lu_det(double (&row)[32], int k, double& sgn, double& logd, b
         mant = frexp(mant, &e3);
         ex += e3;
         if (pv < 0) sgn = -sgn;
-        const bool live = lane < 32 && ((unused >> (lane & 31)) & 1u);
-        const double f = live ? row[p] / pv : 0.0;
+        if ((unused >> r) & 1u) f = row[p] / pv;
+      }
 #pragma unroll
-        for (int c0 = 0; c0 < KMAX; c0 += 4) {
-          if (c0 + 3 > p && c0 < k) {
-            double pr[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (c0 + t > p) pr[t] = readlane_f64(row[c0 + t], idx);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (c0 + t > p) row[c0 + t] -= f * pr[t];
-          }
+      for (int c0 = p & ~1; c0 < 32; c0 += 2) {
+        if (c0 < kmax) {
+          const double2 q = *reinterpret_cast<const double2*>(prow + c0);
+          if (c0 > p) row[c0] -= f * q.x;
+          if (c0 + 1 > p) row[c0 + 1] -= f * q.y;
         }
       }
+      wave_lds_order();
     }
   }
   logd = log(mant) + (double)ex * 0.69314718055994530942;
@@ -677,90 +689,94 @@ FIRE_DEV void group_lu_det16(double (&row)[16], int kk, double& sgn, double& log
 }
 
 // The product dPhi_U G_U^T of one (job, determinant) item, 16 KT x 16 KT,
-// on 16x16x4 f64 MFMA tiles, into LDS (row stride ld; rows/columns past k
-// are zero).  Every element read is unconditional (rows past k read row 0,
-// columns past N read column N-1, and both are zeroed afterwards), so the
-// reads of 8 MFMA steps (32 orbital columns) are all in flight together.
+// on 16x16x4 f64 MFMA tiles, into LDS (row stride ld).  Only entries with
+// both indices below k are meaningful: rows past k read row 0 (their
+// entries are never used by the callers), so the loads need no guards.
+// The orbital index runs in chunks of 4 CH columns (CH MFMA steps whose
+// reads are all in flight together); each lane's row pointers carry its
+// column within a chunk, so the full chunks read at constant offsets, and
+// only the last, partial chunk clamps its columns and zeroes those past N.
 template <typename T, typename TI, int KT, bool FUSED, bool PAIR>
 FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, int N, int e0, double* ab, int ld) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  // lane group kq: PAIR steps 2v, 2v + 1 take columns 8 v + 2 kq and the one
+  // after it (N even, pairs aligned); otherwise step u takes column 4 u + kq
+  const int lo = PAIR ? 2 * kq : kq;
   const T* xr[KT];
   const T* yr[KT];
   const T* zr[KT];
   const TI* gr[KT];
-  bool rok[KT];
 #pragma unroll
   for (int t = 0; t < KT; ++t) {
     const int a = 16 * t + r16;
-    rok[t] = a < k;
-    const int aa = rok[t] ? a : 0;
+    const int aa = a < k ? a : 0;
     const int u = lst[aa];
     dr.row_ptrs(aa, u, xr[t], yr[t], zr[t]);
-    gr[t] = G + (int64_t)(u - e0) * N;
+    xr[t] += lo;
+    yr[t] += lo;
+    zr[t] += lo;
+    gr[t] = G + (int64_t)(u - e0) * N + lo;
   }
   d4v_ acc[KT][KT];
 #pragma unroll
   for (int x = 0; x < KT; ++x)
 #pragma unroll
     for (int y = 0; y < KT; ++y) acc[x][y] = d4v_{0.0, 0.0, 0.0, 0.0};
-  constexpr int CH = KT == 2 ? 4 : 8;     // MFMA steps per chunk of reads
-  for (int cb = 0; cb < N; cb += 4 * CH) {
+  constexpr int CH = KT == 2 ? 4 : 8;
+  constexpr int CW = 4 * CH;
+  auto chunk = [&](int cb, bool tail) {
     double af[CH][KT], bf[CH][KT];
     if constexpr (PAIR) {
-      // steps 2v and 2v + 1 of lane group kq take columns cb + 8 v + 2 kq
-      // and the one after it (N even, pairs aligned): one read per pair
 #pragma unroll
       for (int v = 0; v < CH / 2; ++v) {
-        const int col = cb + 8 * v + 2 * kq;
-        const bool cok = col < N;
-        const int cc = cok ? col : N - 2;
+        const bool cok = !tail || cb + 8 * v + lo < N;
+        const int o = cok ? cb + 8 * v : N - 2 - lo;
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
-          const bool ok = rok[t] && cok;
-          const Two<T> x = *reinterpret_cast<const Two<T>*>(xr[t] + cc);
+          const Two<T> x = *reinterpret_cast<const Two<T>*>(xr[t] + o);
           double v0, v1;
           if constexpr (FUSED) {
-            const Two<T> y = *reinterpret_cast<const Two<T>*>(yr[t] + cc);
-            const Two<T> z = *reinterpret_cast<const Two<T>*>(zr[t] + cc);
+            const Two<T> y = *reinterpret_cast<const Two<T>*>(yr[t] + o);
+            const Two<T> z = *reinterpret_cast<const Two<T>*>(zr[t] + o);
             v0 = (double)(x.a * y.a - z.a);
             v1 = (double)(x.b * y.b - z.b);
           } else {
             v0 = (double)x.a;
             v1 = (double)x.b;
           }
-          const Two<TI> g = *reinterpret_cast<const Two<TI>*>(gr[t] + cc);
-          af[2 * v][t] = ok ? v0 : 0.0;
-          af[2 * v + 1][t] = ok ? v1 : 0.0;
-          bf[2 * v][t] = ok ? (double)g.a : 0.0;
-          bf[2 * v + 1][t] = ok ? (double)g.b : 0.0;
+          const Two<TI> g = *reinterpret_cast<const Two<TI>*>(gr[t] + o);
+          af[2 * v][t] = cok ? v0 : 0.0;
+          af[2 * v + 1][t] = cok ? v1 : 0.0;
+          bf[2 * v][t] = (double)g.a;
+          bf[2 * v + 1][t] = (double)g.b;
         }
       }
     } else {
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        const int col = cb + 4 * u + kq;
-        const bool cok = col < N;
-        const int cc = cok ? col : N - 1;
+        const bool cok = !tail || cb + 4 * u + lo < N;
+        const int o = cok ? cb + 4 * u : N - 1 - lo;
 #pragma unroll
         for (int t = 0; t < KT; ++t) {
-          const bool ok = rok[t] && cok;
           double v;
-          if constexpr (FUSED) v = (double)(xr[t][cc] * yr[t][cc] - zr[t][cc]);
-          else v = (double)xr[t][cc];
-          const double g = (double)gr[t][cc];
-          af[u][t] = ok ? v : 0.0;
-          bf[u][t] = ok ? g : 0.0;
+          if constexpr (FUSED) v = (double)(xr[t][o] * yr[t][o] - zr[t][o]);
+          else v = (double)xr[t][o];
+          af[u][t] = cok ? v : 0.0;
+          bf[u][t] = (double)gr[t][o];
         }
       }
     }
-    // steps past N multiply zeros; no early exit, so no read is held back
 #pragma unroll
     for (int u = 0; u < CH; ++u)
 #pragma unroll
       for (int x = 0; x < KT; ++x)
 #pragma unroll
         for (int y = 0; y < KT; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u][x], bf[u][y], acc[x][y], 0, 0, 0);
-  }
+  };
+  const int nfull = N / CW;
+#pragma unroll 1
+  for (int c = 0; c < nfull; ++c) chunk(c * CW, false);
+  if (nfull * CW < N) chunk(nfull * CW, true);
   // f64 16x16x4 output: register i of lane l holds row 4 i + l/16, column l%16
 #pragma unroll
   for (int x = 0; x < KT; ++x)
@@ -773,50 +789,49 @@ FIRE_DEV void form_A(const DPhiRows<T>& dr, const TI* G, const int* lst, int k, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// det A = det(I + dPhi_U G_U^T) for (job, determinant) items, four per
-// wave.  Items are ordered (job group, determinant, job in group) so that the
-// quadrature points of one electron-atom pair, which share most G rows, run
-// side by side.  Items with 16 < |U_s| <= 32 are done one at a time
-// (32 x 32 product, wave_lu_det); items with |U_s| <= 16 are formed one after
-// another and factored together, one per 16-lane group.  With `fused`,
+// det A = det(I + dPhi_U G_U^T) for (job, determinant) items with
+// |U_s| <= 16, four per wave, formed one after another and factored
+// together, one per 16-lane group.  Items are ordered (job group,
+// determinant, job in group) so that the quadrature points of one
+// electron-atom pair, which share most G rows, run side by side.  With FUSED,
 // dPhi = o' env - Phi is formed on the fly from the projections, cached
-// envelopes and Phi (no dPhi pass).  |U_s| > 32 is left to k_detA.
-template <typename T, typename TI>
+// envelopes and Phi (no dPhi pass); PAIR (chosen on the host) reads two
+// consecutive orbital columns at once.  16 < |U_s| <= 32 is left to
+// k_detA_mid, |U_s| > 32 to k_detA.  Jobs at or beyond a device job count
+// have empty update sets (k_propose clears their counts).
+template <typename T, typename TI, bool FUSED, bool PAIR>
 __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                    const int* __restrict__ uidx, int capmax,
                                                    const int* __restrict__ ucnt, const int* __restrict__ off,
                                                    const T* __restrict__ dphi, const T* __restrict__ oseg,
-                                                   const T* __restrict__ envnew, int fused,
+                                                   const T* __restrict__ envnew,
                                                    const char* __restrict__ state, StateRec S,
                                                    double* __restrict__ detA, int jg) {
   __shared__ double abuf[4][4 * 16 * 17];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t quad = xcd_runs(blockIdx.x, det_run(jg, D.K, 16)) * 4 + wave;
-  // jobs at or beyond a device job count have empty update sets (k_propose
-  // clears their counts), so their items end at the counts read below
-  const int Wact = W;
-  const int ngroups = (Wact + jg - 1) / jg;
-  const int64_t total = (int64_t)ngroups * D.K * jg;
-  if (quad * 4 >= total) return;
+  // item counts stay below 2^31: 32-bit index arithmetic
+  const unsigned quad = (unsigned)xcd_runs(blockIdx.x, det_run(jg, D.K, 16)) * 4u + (unsigned)wave;
+  const unsigned ujg = (unsigned)jg, uK = (unsigned)D.K;
+  const unsigned total = ((unsigned)W + ujg - 1u) / ujg * ujg * uK;
+  if (quad * 4u >= total) return;
   const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
   double* ab = abuf[wave];
   int jq[4], dq[4], kqv[4];
+  // (group, determinant, job in group) of the quad's first item, then stepped
+  {
+    unsigned ig = (quad * 4u) % ujg, rest = (quad * 4u) / ujg;
+    unsigned id = rest % uK, g = rest / uK;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t item = quad * 4 + q;
-    jq[q] = -1;
-    dq[q] = 0;
-    kqv[q] = -1;
-    if (item < total) {
-      const int gq = (int)(item % jg);
-      const int det = (int)((item / jg) % D.K);
-      const int g = (int)(item / ((int64_t)jg * D.K));
-      const int j = g * jg + gq;
-      if (j < Wact) {
-        jq[q] = j;
-        dq[q] = det;
-        kqv[q] = ucnt[2 * j + s];
+    for (int q = 0; q < 4; ++q) {
+      const unsigned j = g * ujg + ig;
+      const bool live = quad * 4u + (unsigned)q < total && j < (unsigned)W;
+      jq[q] = live ? (int)j : -1;
+      dq[q] = (int)id;
+      kqv[q] = live ? ucnt[2 * j + s] : -1;
+      if (++ig == ujg) {
+        ig = 0;
+        if (++id == uK) { id = 0; ++g; }
       }
     }
   }
@@ -828,7 +843,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
     const char* rec = state + (int64_t)w * S.stride;
     const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
     G = (const TI*)(rec + S.inv) + boff;
-    dr = DPhiRows<T>{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
+    dr = DPhiRows<T>{FUSED ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
                      (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
   };
   auto out_of = [&](int q) { return detA + (((int64_t)jq[q] * D.K + dq[q]) * 2 + s) * 2; };
@@ -855,13 +870,7 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
       const int* lst;
       item_rows(q, G, dr, lst);
       double* aq = ab + q * 16 * 17;
-      if (dr.pair_aligned(G)) {
-        if (fused) form_A<T, TI, 1, true, true>(dr, G, lst, k, N, e0, aq, 17);
-        else form_A<T, TI, 1, false, true>(dr, G, lst, k, N, e0, aq, 17);
-      } else {
-        if (fused) form_A<T, TI, 1, true, false>(dr, G, lst, k, N, e0, aq, 17);
-        else form_A<T, TI, 1, false, false>(dr, G, lst, k, N, e0, aq, 17);
-      }
+      form_A<T, TI, 1, FUSED, PAIR>(dr, G, lst, k, N, e0, aq, 17);
     }
   }
   const int gq = lane >> 4, r = lane & 15;
@@ -886,58 +895,91 @@ __global__ __launch_bounds__(256) void k_detA_wave(const Dims D, int W, const in
   }
 }
 
-// det A for items with 16 < |U_s| <= 32, one per wave: 32 x 32 product on
-// MFMA tiles, then wave_lu_det.  Other items exit at once.
-template <typename T, typename TI>
+// det A for items with 16 < |U_s| <= 32: each wave forms one 32 x 32
+// product on MFMA tiles into its LDS buffer; then waves 0 and 2 of the
+// block factor two matrices each (their own and the next wave's, one per
+// half wave; halves_lu_det32).  Items are ordered (job, determinant), so
+// the four waves of a block take four determinants of one job (K >= 4) and
+// the jobs of a quadrature group (which share most rows of Phi^-1) follow
+// one another.  Items of other sizes skip the work; every wave reaches the
+// block barrier.
+template <typename T, typename TI, bool FUSED, bool PAIR>
 __global__ __launch_bounds__(256, 4) void k_detA_mid(const Dims D, int W, const int* __restrict__ jw, int s, int e,
                                                   const int* __restrict__ uidx, int capmax,
                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
                                                   const T* __restrict__ dphi, const T* __restrict__ oseg,
-                                                  const T* __restrict__ envnew, int fused,
+                                                  const T* __restrict__ envnew,
                                                   const char* __restrict__ state, StateRec S,
                                                   double* __restrict__ detA, int jg) {
-  __shared__ double abuf[4][32 * 33];
+  __shared__ __align__(16) double abuf[4][32 * 33];
+  __shared__ int kb[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t item = xcd_runs(blockIdx.x, det_run(jg, D.K, 4)) * 4 + wave;
-  const int Wact = W;   // jobs beyond a device job count have empty update sets
-  const int ngroups = (Wact + jg - 1) / jg;
-  if (item >= (int64_t)ngroups * D.K * jg) return;
-  const int gq = (int)(item % jg);
-  const int det = (int)((item / jg) % D.K);
-  const int g = (int)(item / ((int64_t)jg * D.K));
-  const int j = g * jg + gq;
-  if (j >= Wact) return;
-  const int k = ucnt[2 * j + s];
-  if (k <= 16 || k > 32) return;
-  const int w = jw ? jw[j] : j;
+  // item counts stay below 2^31: 32-bit index arithmetic
+  const unsigned item = (unsigned)xcd_runs(blockIdx.x, det_run(jg, D.K, 4)) * 4u + (unsigned)wave;
+  const int j = (int)(item / (unsigned)D.K), det = (int)(item % (unsigned)D.K);
+  int k = item < (unsigned)W * (unsigned)D.K ? ucnt[2 * j + s] : 0;
+  k = (k > 16 && k <= 32) ? k : 0;
+  if (lane == 0) kb[wave] = k;
   const int N = D.nsig(s), KN = D.K * N;
   const int e0 = s == 0 ? 0 : D.nu;
-  const int q0 = off[s * (W + 1) + j];
-  const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
-  const char* rec = state + (int64_t)w * S.stride;
-  const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
-  const TI* G = (const TI*)(rec + S.inv) + boff;
-  const DPhiRows<T> dr{fused ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
-                       (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
   double* ab = abuf[wave];
-  if (dr.pair_aligned(G)) {
-    if (fused) form_A<T, TI, 2, true, true>(dr, G, lst, k, N, e0, ab, 33);
-    else form_A<T, TI, 2, false, true>(dr, G, lst, k, N, e0, ab, 33);
-  } else {
-    if (fused) form_A<T, TI, 2, true, false>(dr, G, lst, k, N, e0, ab, 33);
-    else form_A<T, TI, 2, false, false>(dr, G, lst, k, N, e0, ab, 33);
+  if (k > 0) {
+    const int w = jw ? jw[j] : j;
+    const int q0 = off[s * (W + 1) + j];
+    const int* lst = uidx + ((int64_t)j * 2 + s) * capmax;
+    const char* rec = state + (int64_t)w * S.stride;
+    const int64_t boff = det * phi_per_det(D) + phi_block_off(D, s);
+    const TI* G = (const TI*)(rec + S.inv) + boff;
+    const DPhiRows<T> dr{FUSED ? nullptr : dphi, oseg, envnew, (const T*)(rec + S.env) + boff,
+                         (const T*)(rec + S.phi) + boff, (int64_t)q0, (int64_t)KN, (int64_t)det, (int64_t)N, e, e0, j};
+    form_A<T, TI, 2, FUSED, PAIR>(dr, G, lst, k, N, e0, ab, 33);
   }
+  __syncthreads();
+  if (wave & 1) return;
+  const int h = lane >> 5, r = lane & 31;
+  const int kh = kb[wave + h];
+  if (__builtin_amdgcn_readfirstlane(kb[wave] | kb[wave + 1]) == 0) return;
+  const double* src = abuf[wave + h];
   double row[32];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) row[c] = (lane < k && c < k) ? ab[lane * 33 + c] + (c == lane ? 1.0 : 0.0) : 0.0;
+  for (int c = 0; c < 32; ++c) row[c] = (r < kh && c < kh) ? src[r * 33 + c] + (c == r ? 1.0 : 0.0) : 0.0;
+  wave_lds_order();
   double sg, ld;
   bool sing;
-  wave_lu_det<32>(row, k, sg, ld, sing);
-  if (lane == 0) {
-    double* out = detA + (((int64_t)j * D.K + det) * 2 + s) * 2;
+  halves_lu_det32(row, kh, ab, sg, ld, sing);
+  if (r == 0 && kh > 0) {
+    // item (j, det) at j K + det; the paired wave's item is the next one
+    double* out = detA + ((int64_t)(item + h) * 2 + s) * 2;
     if (sing) { out[0] = 0.0; out[1] = -INFINITY; }
     else { out[0] = sg; out[1] = ld; }
   }
+}
+
+// The det-lemma kernels by their flags (the signature does not depend on
+// the inverse type TI).
+template <typename T>
+using DetAKernel = void (*)(const Dims, int, const int*, int, int, const int*, int, const int*, const int*,
+                            const T*, const T*, const T*, const char*, StateRec, double*, int);
+template <typename T, typename TI, bool F, bool P> static DetAKernel<T> detA_pick(bool mid) {
+  return mid ? k_detA_mid<T, TI, F, P> : k_detA_wave<T, TI, F, P>;
+}
+template <typename T, typename TI> static DetAKernel<T> detA_pick(bool mid, bool fused, bool pair) {
+  if (fused) return pair ? detA_pick<T, TI, true, true>(mid) : detA_pick<T, TI, true, false>(mid);
+  return pair ? detA_pick<T, TI, false, true>(mid) : detA_pick<T, TI, false, false>(mid);
+}
+template <typename T> static DetAKernel<T> detA_kernel(const fire_handle* h, bool mid, bool fused, bool pair) {
+  return h->isize == 8 ? detA_pick<T, double>(mid, fused, pair) : detA_pick<T, float>(mid, fused, pair);
+}
+// Two-column reads in the det-lemma products need every row of the Phi,
+// envelope, inverse, projection and dPhi blocks to start at an even element
+// offset of a 16-byte aligned base: both spin blocks even (the blocks of one
+// determinant then have even sizes) and the state record, its fields and the
+// workspace 16-byte aligned.
+static bool detA_pair(const fire_handle* h, const void* state, const void* ws) {
+  const Dims& D = h->D;
+  const StateRec& S = h->st;
+  return D.nu % 2 == 0 && D.nd % 2 == 0 && (S.stride | S.inv | S.env | S.phi) % 16 == 0 &&
+         (uintptr_t)state % 16 == 0 && (uintptr_t)ws % 16 == 0;
 }
 
 // Acceptance: psi'/psi = sum_d s_d e^{l_d} prod_s det A_ds / sum_d s_d e^{l_d};
@@ -1632,28 +1674,17 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     const int64_t items = (int64_t)((W + jg - 1) / jg) * jg * D.K;
     const int64_t quads = (items + 3) / 4;
     // grids of whole runs of eight (det_grid) for the run-wise XCD order
-    if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3(det_grid((quads + 3) / 4, jg, D.K, 16)), dim3(256), 0, st, D, W, jb.jw,
-                         s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg);
-    else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3(det_grid((quads + 3) / 4, jg, D.K, 16)), dim3(256), 0, st, D, W, jb.jw,
-                         s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state, S,
-                         (double*)(ws + L.detA), jg);
+    const bool pair = detA_pair(h, state, ws);
+    hipLaunchKernelGGL(detA_kernel<T>(h, false, fused, pair), dim3(det_grid((quads + 3) / 4, jg, D.K, 16)), dim3(256),
+                       0, st, D, W, jb.jw, s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                       (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, (const char*)state, S,
+                       (double*)(ws + L.detA), jg);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
-      if (h->isize == 8)
-        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3(det_grid((items + 3) / 4, jg, D.K, 4)), dim3(256), 0, st, D, W, jb.jw,
-                           s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                           (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg);
-      else
-        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3(det_grid((items + 3) / 4, jg, D.K, 4)), dim3(256), 0, st, D, W, jb.jw,
-                           s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                           (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, fused, (const char*)state,
-                           S, (double*)(ws + L.detA), jg);
+      hipLaunchKernelGGL(detA_kernel<T>(h, true, fused, pair), dim3(det_grid((items + 3) / 4, jg, D.K, 4)), dim3(256),
+                         0, st, D, W, jb.jw, s, e, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
+                         (const T*)(ws + L.dphi[s]), (const T*)oseg, (const T*)envnew, (const char*)state, S,
+                         (double*)(ws + L.detA), jg);
       CHECK(hipGetLastError());
     }
     if (L.capS[s] > 32) {
@@ -2172,28 +2203,17 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
     CHECK(gemm_site(h, SITE_ORB, o, st));
     const int64_t items = (int64_t)W * D.K;
     const int64_t quads = (items + 3) / 4;
-    if (h->isize == 8)
-      hipLaunchKernelGGL((k_detA_wave<T, double>), dim3(det_grid((quads + 3) / 4, 1, D.K, 16)), dim3(256), 0, st, D, W,
-                         (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                         (double*)(ws + L.detA), 1);
-    else
-      hipLaunchKernelGGL((k_detA_wave<T, float>), dim3(det_grid((quads + 3) / 4, 1, D.K, 16)), dim3(256), 0, st, D, W,
-                         (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt, (const int*)off,
-                         (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                         (double*)(ws + L.detA), 1);
+    const bool pair = detA_pair(h, state, ws);
+    hipLaunchKernelGGL(detA_kernel<T>(h, false, true, pair), dim3(det_grid((quads + 3) / 4, 1, D.K, 16)), dim3(256), 0,
+                       st, D, W, (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
+                       (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], (const char*)state, S,
+                       (double*)(ws + L.detA), 1);
     CHECK(hipGetLastError());
     if (L.capS[s] > 16) {
-      if (h->isize == 8)
-        hipLaunchKernelGGL((k_detA_mid<T, double>), dim3(det_grid((items + 3) / 4, 1, D.K, 4)), dim3(256), 0, st, D, W,
-                           (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
-                           (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                           (double*)(ws + L.detA), 1);
-      else
-        hipLaunchKernelGGL((k_detA_mid<T, float>), dim3(det_grid((items + 3) / 4, 1, D.K, 4)), dim3(256), 0, st, D, W,
-                           (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
-                           (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], 1, (const char*)state, S,
-                           (double*)(ws + L.detA), 1);
+      hipLaunchKernelGGL(detA_kernel<T>(h, true, true, pair), dim3(det_grid((items + 3) / 4, 1, D.K, 4)), dim3(256), 0,
+                         st, D, W, (const int*)nullptr, s, e_s, (const int*)uidx, L.capmax, (const int*)ucnt,
+                         (const int*)off, (const T*)nullptr, (const T*)oseg, envs[s], (const char*)state, S,
+                         (double*)(ws + L.detA), 1);
       CHECK(hipGetLastError());
     }
     if (L.capS[s] > 32) {

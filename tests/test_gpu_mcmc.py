@@ -105,7 +105,7 @@ def test_update_overflow_flag(lib):
     assert np.isnan(lp.cpu().numpy()).all()
 
 
-def _flake72(scales, seed, ecp=False, cutoff=6.0):
+def _flake72(scales, seed, ecp=False, cutoff=6.0, n_det=2):
     """72 electrons (36 per spin), walkers contracted or stretched about the
     centre by `scales`.  In a contracted walker every electron is within
     c = 6 bohr of the moved one, so both spin blocks have |U_s| = 36 > 32
@@ -117,7 +117,7 @@ def _flake72(scales, seed, ecp=False, cutoff=6.0):
     rng = np.random.default_rng(seed)
     R, sp = wl.grown_flake(72)
     s = wl.make_system("flake72", R, sp, pseudo_c=True, nonlocal_ecp=ecp, ecp_rng=rng if ecp else None)
-    m = wl.make_model(s, width=32, mlp_layers=1, n_det=2, n_env=2, cutoff=cutoff, cutoff_nuc=20.0)
+    m = wl.make_model(s, width=32, mlp_layers=1, n_det=n_det, n_env=2, cutoff=cutoff, cutoff_nuc=20.0)
     p = wl.init_params(s, m, rng)
     W = len(scales)
     Rw = wl.init_walkers(s, W, rng)
@@ -165,6 +165,45 @@ def test_large_update_sets_ecp_matches_oracle(lib):
     log(f"V_NL gpu {v} oracle {vo} err {np.abs(v - vo).max():.2e}")
     assert (st.cpu().numpy() == 0).all()
     assert np.abs(v - vo).max() <= 1e-9
+
+
+def _same_spin_counts(s, R, cutoff):
+    """|{e} u N(r_e)| per spin block of e, for every walker and electron."""
+    d = np.linalg.norm(R[:, :, None, :] - R[:, None, :, :], axis=-1)
+    up = np.arange(s.n_el) < s.n_up
+    same = up[:, None] == up[None, :]
+    return ((d <= cutoff) & same[None]).sum(axis=2)
+
+
+def test_mid_update_sets_odd_determinants_match_oracle(lib):
+    """Update sets of 17 to 32 rows per spin block (the paired-LU kernel),
+    with three determinants, so that a wave pair or a block of four
+    determinant items straddles two jobs: a Metropolis sweep and the nonlocal
+    quadrature against the oracle."""
+    log("case: 72-electron flake fp64, K = 3, |U_s| in (16, 32]: sweep and V_NL, W=3")
+    F, O, s, R, state, ws, rng = _flake72([0.7, 0.8, 0.9], 33, ecp=True, cutoff=5.0, n_det=3)
+    cnt = _same_spin_counts(s, R, 5.0)
+    frac = ((cnt > 16) & (cnt <= 32)).mean()
+    log(f"fraction of electrons with 16 < |{{e}} u N(r_e)| <= 32 in their spin block: {frac:.2f}")
+    assert frac >= 0.3
+    Q = wl.haar_rotations(3, np.random.default_rng(12))
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    v, st = F.ecp_nonlocal(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    vo = O.ecp_nonlocal(R, Q).numpy()
+    log(f"V_NL gpu {v.cpu().numpy()} oracle {vo}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.abs(v.cpu().numpy() - vo).max() <= 1e-9
+    xi, u = wl.mcmc_noise(1, s.n_el, 3, rng)
+    nacc, sg, lp, st = F.mcmc_sweep(Rd, state, ws, 1, 0.2, dev(xi), dev(u))
+    torch.cuda.synchronize()
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.2, xi, u)
+    log(f"accepts gpu {nacc.cpu().numpy()} oracle {no.numpy()}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(nacc.cpu().numpy(), no.numpy())
+    assert np.abs(Rd.cpu().numpy() - Ro.numpy()).max() <= 1e-12
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
 
 
 def _mixed_chain(cid, W, kinds, precision="fp64", gstep=2.0, seed=0, **kw):
