@@ -387,12 +387,16 @@ fire_status fire_batch_set_params(fire_batch* b, const double* theta, void* para
 fire_status fire_batch_step(fire_batch* b, const int* W, double* R, void* state, void* ws, int n_sweeps,
                             double step, const double* noise, const double* unif, int32_t* n_accept,
                             double* e_loc, double* grad, int32_t* status, hipStream_t stream);
-/* Capture fire_batch_step with these exact arguments into a HIP graph (the
- * buffers are bound into it: a replay reads their contents at launch time). */
+/* Capture fire_batch_step with these exact arguments into HIP graphs, one
+ * per internal stream branch (the buffers are bound into them: a replay reads
+ * their contents at launch time).  The graph object refers to the batch's
+ * streams and is valid while the batch lives. */
 fire_status fire_batch_graph_create(fire_batch* b, const int* W, double* R, void* state, void* ws, int n_sweeps,
                                     double step, const double* noise, const double* unif, int32_t* n_accept,
                                     double* e_loc, double* grad, int32_t* status, fire_graph** out);
-/* Replay the whole captured step as one launch on `stream`. */
+/* Replay the whole captured step with one call: the branch graphs run on the
+ * batch's streams, forked from and joined back to `stream`, then the gradient
+ * combine runs on `stream`.  Replays of one batch must not overlap. */
 fire_status fire_graph_launch(fire_graph* g, hipStream_t stream);
 fire_status fire_graph_destroy(fire_graph* g);
 

@@ -2,8 +2,8 @@
 // counts advanced together, one step = full evaluation, Metropolis sweeps,
 // local energy, energy-gradient coefficients and the parameter gradient, for
 // every system, enqueued as one fork/join DAG over a few streams and
-// optionally captured once into a HIP graph that replays the whole step as a
-// single launch.  The embedding parameters (filters, per-species nuclear
+// optionally captured once into HIP graphs (one per stream branch) that
+// replay the whole step with one call.  The embedding parameters (filters, per-species nuclear
 // tables, GLU, messages, MLP) are shared by all systems; orbital weights and
 // envelopes are per system (Methods, wave function ansatz: the embedding
 // network is molecule-agnostic, the orbital layer depends on the molecule).
@@ -23,15 +23,10 @@ struct fire_batch {
   int64_t P_total = 0;
   int n_branch = 0;
   std::vector<hipStream_t> streams;
-  hipStream_t capture = nullptr;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
 };
 
-struct fire_graph {
-  hipGraph_t g = nullptr;
-  hipGraphExec_t x = nullptr;
-};
 
 namespace fire {
 
@@ -156,6 +151,24 @@ struct BatchGrad {
   int64_t priv_off[kMaxSystems + 1];
 };
 
+}  // namespace fire
+
+// A captured batch step: one graph per stream branch (its systems in order),
+// replayed on the batch's branch streams, then the gradient combine.  A graph
+// with parallel branches is replayed one branch after another by the
+// runtime, so the branches are captured and launched separately.
+struct fire_graph {
+  fire_batch* b = nullptr;
+  std::vector<hipGraph_t> g;
+  std::vector<hipGraphExec_t> x;
+  std::vector<int> branch;      // stream branch of graph k
+  fire::BatchGrad tail{};
+  int64_t P_total = 0;
+  double* grad = nullptr;
+};
+
+namespace fire {
+
 // batch gradient: shared entries summed over systems in system order,
 // private entries copied from their system
 __global__ void k_batch_grad(BatchGrad a, int64_t P_total, double* __restrict__ out) {
@@ -222,26 +235,13 @@ static fire_status enqueue_system(fire_batch* b, int s, const SysOff& o, const S
   return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
 }
 
-static fire_status enqueue_step(fire_batch* b, const StepArgs& a, hipStream_t origin) {
+static fire_status check_sizes(const fire_batch* b, const StepArgs& a) {
   for (int s = 0; s < b->n; ++s)
     if (a.W[s] < 1 || a.W[s] > b->sys[s]->model.max_walkers) return FIRE_ERR_CAPACITY;
-  const std::vector<SysOff> off = batch_offsets(b, a.W, a.n_sweeps, nullptr, nullptr, nullptr);
-  std::vector<int> order;
-  const std::vector<int> br = schedule(b, a.W, &order);
-  if (hipEventRecord(b->fork, origin) != hipSuccess) return FIRE_ERR_HIP;
-  for (int k = 0; k < b->n_branch; ++k)
-    if (hipStreamWaitEvent(b->streams[k], b->fork, 0) != hipSuccess) return FIRE_ERR_HIP;
-  fire_status r = FIRE_OK;
-  for (int s : order) {
-    r = enqueue_system(b, s, off[s], a, b->streams[br[s]]);
-    if (r != FIRE_OK) break;
-  }
-  // always join, so that a capture in progress stays well formed
-  for (int k = 0; k < b->n_branch; ++k) {
-    if (hipEventRecord(b->join[k], b->streams[k]) != hipSuccess) return FIRE_ERR_HIP;
-    if (hipStreamWaitEvent(origin, b->join[k], 0) != hipSuccess) return FIRE_ERR_HIP;
-  }
-  if (r != FIRE_OK) return r;
+  return FIRE_OK;
+}
+
+static BatchGrad grad_args(const fire_batch* b, const std::vector<SysOff>& off, const StepArgs& a) {
   BatchGrad g{};
   g.n = b->n;
   g.P_shared = b->P_shared;
@@ -250,9 +250,67 @@ static fire_status enqueue_step(fire_batch* b, const StepArgs& a, hipStream_t or
     g.priv_off[s] = b->priv_off[s];
   }
   g.priv_off[b->n] = b->P_total;
-  hipLaunchKernelGGL(k_batch_grad, dim3((unsigned)((b->P_total + 255) / 256)), dim3(256), 0, origin, g, b->P_total,
-                     a.grad);
+  return g;
+}
+
+static fire_status enqueue_combine(const fire_batch* b, const BatchGrad& g, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_grad, dim3((unsigned)((b->P_total + 255) / 256)), dim3(256), 0, st, g, b->P_total, grad);
   return hipGetLastError() == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+}
+
+static fire_status enqueue_step(fire_batch* b, const StepArgs& a, hipStream_t origin) {
+  fire_status r = check_sizes(b, a);
+  if (r != FIRE_OK) return r;
+  const std::vector<SysOff> off = batch_offsets(b, a.W, a.n_sweeps, nullptr, nullptr, nullptr);
+  std::vector<int> order;
+  const std::vector<int> br = schedule(b, a.W, &order);
+  if (hipEventRecord(b->fork, origin) != hipSuccess) return FIRE_ERR_HIP;
+  for (int k = 0; k < b->n_branch; ++k)
+    if (hipStreamWaitEvent(b->streams[k], b->fork, 0) != hipSuccess) return FIRE_ERR_HIP;
+  for (int s : order) {
+    r = enqueue_system(b, s, off[s], a, b->streams[br[s]]);
+    if (r != FIRE_OK) break;
+  }
+  // always join, so that the streams stay ordered after an error
+  for (int k = 0; k < b->n_branch; ++k) {
+    if (hipEventRecord(b->join[k], b->streams[k]) != hipSuccess) return FIRE_ERR_HIP;
+    if (hipStreamWaitEvent(origin, b->join[k], 0) != hipSuccess) return FIRE_ERR_HIP;
+  }
+  if (r != FIRE_OK) return r;
+  return enqueue_combine(b, grad_args(b, off, a), a.grad, origin);
+}
+
+static void graph_free(fire_graph* G) {
+  for (hipGraphExec_t x : G->x)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipGraph_t g : G->g)
+    if (g) (void)hipGraphDestroy(g);
+  delete G;
+}
+
+// Capture branch k's systems (in schedule order) on its own stream.
+static fire_status capture_branch(fire_batch* b, int k, const std::vector<int>& order, const std::vector<int>& br,
+                                  const std::vector<SysOff>& off, const StepArgs& a, fire_graph* G) {
+  hipStream_t st = b->streams[k];
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return FIRE_ERR_HIP;
+  fire_status r = FIRE_OK;
+  for (int s : order)
+    if (br[s] == k && r == FIRE_OK) r = enqueue_system(b, s, off[s], a, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (r != FIRE_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return r != FIRE_OK ? r : FIRE_ERR_HIP;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return FIRE_ERR_HIP;
+  }
+  G->g.push_back(g);
+  G->x.push_back(x);
+  G->branch.push_back(k);
+  return FIRE_OK;
 }
 
 }  // namespace fire
@@ -307,9 +365,7 @@ fire_status fire_batch_create(const fire_system_desc* systems, int n_systems, co
       if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { r = FIRE_ERR_HIP; break; }
       b->join.push_back(ev);
     }
-    if (r == FIRE_OK && (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
-                         hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess))
-      r = FIRE_ERR_HIP;
+    if (r == FIRE_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) r = FIRE_ERR_HIP;
   }
   if (r != FIRE_OK) {
     fire_batch_destroy(b);
@@ -324,7 +380,6 @@ fire_status fire_batch_destroy(fire_batch* b) {
   for (fire_handle* h : b->sys) fire_destroy(h);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
-  if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return FIRE_OK;
@@ -384,36 +439,43 @@ fire_status fire_batch_graph_create(fire_batch* b, const int* W, double* R, void
   for (fire_handle* h : b->sys)
     if (!h->params) return FIRE_ERR_STATE;
   StepArgs a{W, R, (char*)state, (char*)ws, n_sweeps, step, noise, unif, n_accept, e_loc, grad, status};
-  if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed) != hipSuccess) return FIRE_ERR_HIP;
-  const fire_status r = enqueue_step(b, a, b->capture);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(b->capture, &g);
-  if (r != FIRE_OK || e != hipSuccess || !g) {
-    if (g) (void)hipGraphDestroy(g);
-    return r != FIRE_OK ? r : FIRE_ERR_HIP;
-  }
-  hipGraphExec_t x = nullptr;
-  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(g);
-    return FIRE_ERR_HIP;
-  }
+  fire_status r = check_sizes(b, a);
+  if (r != FIRE_OK) return r;
+  const std::vector<SysOff> off = batch_offsets(b, a.W, a.n_sweeps, nullptr, nullptr, nullptr);
+  std::vector<int> order;
+  const std::vector<int> br = schedule(b, a.W, &order);
   fire_graph* G = new fire_graph();
-  G->g = g;
-  G->x = x;
+  G->b = b;
+  for (int k = 0; k < b->n_branch && r == FIRE_OK; ++k) r = capture_branch(b, k, order, br, off, a, G);
+  if (r != FIRE_OK) {
+    graph_free(G);
+    return r;
+  }
+  G->tail = grad_args(b, off, a);
+  G->grad = grad;
   *out = G;
   return FIRE_OK;
 }
 
 fire_status fire_graph_launch(fire_graph* g, hipStream_t stream) {
-  if (!g || !g->x) return FIRE_ERR_ARG;
-  return hipGraphLaunch(g->x, stream) == hipSuccess ? FIRE_OK : FIRE_ERR_HIP;
+  if (!g || !g->b || g->x.empty()) return FIRE_ERR_ARG;
+  fire_batch* b = g->b;
+  if (hipEventRecord(b->fork, stream) != hipSuccess) return FIRE_ERR_HIP;
+  fire_status r = FIRE_OK;
+  for (size_t k = 0; k < g->x.size(); ++k) {
+    hipStream_t st = b->streams[g->branch[k]];
+    if (hipStreamWaitEvent(st, b->fork, 0) != hipSuccess || hipGraphLaunch(g->x[k], st) != hipSuccess) r = FIRE_ERR_HIP;
+    if (hipEventRecord(b->join[g->branch[k]], st) != hipSuccess ||
+        hipStreamWaitEvent(stream, b->join[g->branch[k]], 0) != hipSuccess)
+      return FIRE_ERR_HIP;
+  }
+  if (r != FIRE_OK) return r;
+  return enqueue_combine(b, g->tail, g->grad, stream);
 }
 
 fire_status fire_graph_destroy(fire_graph* g) {
   if (!g) return FIRE_ERR_ARG;
-  if (g->x) (void)hipGraphExecDestroy(g->x);
-  if (g->g) (void)hipGraphDestroy(g->g);
-  delete g;
+  graph_free(g);
   return FIRE_OK;
 }
 

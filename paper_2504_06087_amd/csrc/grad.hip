@@ -331,6 +331,31 @@ FIRE_HOST_DEVICE int msg_part_size(const Dims& D) { return 2 * (filt_off(D).size
 typedef float f4v_ __attribute__((ext_vector_type(4)));
 constexpr int RCH = 16;   // pairs per channel reduction
 
+// One pair's channel sums on the FP64 path: out[q] = sum_c u1_c W3[q][c]
+// (q < h2) and out[8 + q] = sum_c u2_c Wenv[q][c] (q < G).  Each wave's sums
+// go to its row of w4 ([waves][40]); then one thread per output adds the
+// waves in order, so the sums do not depend on scheduling.  Every thread of
+// the block calls it.
+template <typename T>
+FIRE_DEV void pair_sums_waves(T u1, T u2, const T* w3, const T* wenv, bool act, int h2, int G, T* w4, T* out) {
+  const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int q = 0; q < h2; ++q) {
+    const T v = wave_sum(act ? u1 * w3[q] : T(0));
+    if ((tid & 63) == 0) w4[wave * 40 + q] = v;
+  }
+  for (int q = 0; q < G; ++q) {
+    const T v = wave_sum(act ? u2 * wenv[q] : T(0));
+    if ((tid & 63) == 0) w4[wave * 40 + 8 + q] = v;
+  }
+  __syncthreads();
+  if (tid < 40 && (tid < h2 || (tid >= 8 && tid < 8 + G))) {
+    T v = 0;
+    for (int x = 0; x < nw; ++x) v += w4[x * 40 + tid];
+    out[tid] = v;
+  }
+  __syncthreads();
+}
+
 // us: LDS [waves][2][RCH][64] floats, filled by the caller (chan_slot: this
 // thread's slots for u1 and u2 of pair k, zero past kc); wp: LDS
 // [waves][RCH][40] floats; red: LDS [RCH][40] (overwritten for k < kc).
@@ -379,6 +404,75 @@ FIRE_DEV void chan_reduce(int kc, const float* W3, const float* Wenv, int d, flo
   __syncthreads();
 }
 
+// The sender side of the message backward: for row j and pair class a,
+// the gradient of its projection b_j (slot 2 + a) collects, over the
+// receivers i with j in N(i), pb_ij = mbar_i gamma_ij silu'(a_i + b_j +
+// f_ij We + b), with gamma_ij and f_ij the filter and edge features of
+// r_i - r_j.  The neighbour relation is symmetric, so the receivers are the
+// class-a entries of j's own list, summed in list order: the result does not
+// depend on scheduling (the receiver side, k_msg_bwd, writes slot a only).
+template <typename T>
+__global__ __launch_bounds__(256) void k_projbar_gather(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
+                                                        const int16_t* __restrict__ nidx,
+                                                        const int32_t* __restrict__ ncnt,
+                                                        const char* __restrict__ state, StateRec S,
+                                                        const T* __restrict__ mbar, T* __restrict__ projbar) {
+  const Dims& D = P.D;
+  __shared__ T feat[ECH * EFEAT];
+  __shared__ int jn[ECH];
+  const int c = threadIdx.x, tid = threadIdx.x;
+  const bool act = c < D.d;
+  const int n = D.n, d = D.d;
+  const int a = blockIdx.y;
+  T w3[kMaxH2], wenv[kMaxG], we[4], bb = 0;
+  if (act) {
+    for (int k = 0; k < D.h2; ++k) w3[k] = P.ee_W3[(a * D.h2 + k) * d + c];
+    for (int k = 0; k < D.G; ++k) wenv[k] = P.ee_Wenv[(a * D.G + k) * d + c];
+    for (int k = 0; k < 4; ++k) we[k] = P.msg_We[(a * 4 + k) * d + c];
+    bb = P.msg_b[a * d + c];
+  }
+  for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
+    const int64_t wl = e / n;
+    const int jrow = (int)(e % n);
+    const char* rec = state + (w0 + wl) * S.stride;
+    const T* proj = (const T*)(rec + S.proj);
+    const double* Rw = R + wl * n * 3;
+    const double rx = Rw[3 * jrow], ry = Rw[3 * jrow + 1], rz = Rw[3 * jrow + 2];
+    const T bj = act ? proj[((int64_t)jrow * 4 + 2 + a) * d + c] : T(0);
+    const int c0 = ncnt[2 * e], c1 = ncnt[2 * e + 1];
+    const int na = a == 0 ? c0 : c1, sbase = a == 0 ? 0 : c0;
+    T sum = 0;
+    for (int i0 = 0; i0 < na; i0 += ECH) {
+      const int ic = na - i0 < ECH ? na - i0 : ECH;
+      __syncthreads();
+      if (tid < ic) {
+        const int i = nidx[e * D.cap_nbr + sbase + i0 + tid];
+        jn[tid] = i;
+        edge_forward<T>((T)(Rw[3 * i] - rx), (T)(Rw[3 * i + 1] - ry), (T)(Rw[3 * i + 2] - rz),
+                        P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2,
+                        P.ee_sig + a * D.G, (T)D.cut, D, feat + tid * EFEAT);
+      }
+      __syncthreads();
+      if (act) {
+        for (int k = 0; k < ic; ++k) {
+          const T* f = feat + k * EFEAT;
+          if (f[88] == T(0)) continue;
+          const int i = jn[k];
+          T g1 = 0, g2 = 0;
+          for (int q = 0; q < D.h2; ++q) g1 += f[48 + q] * w3[q];
+          for (int q = 0; q < D.G; ++q) g2 += f[88] * f[56 + q] * wenv[q];
+          const T ai = proj[((int64_t)i * 4 + a) * d + c];
+          const T pre = ai + bj + f[4] * we[0] + f[5] * we[1] + f[6] * we[2] + f[7] * we[3] + bb;
+          T sf, s1, s2;
+          silu3(pre, sf, s1, s2);
+          sum += mbar[(wl * n + i) * d + c] * (g1 * g2) * s1;
+        }
+      }
+    }
+    if (act) projbar[(e * 4 + 2 + a) * d + c] += sum;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_msg_bwd(Net<T> P, const double* __restrict__ R, int64_t nrows, int w0,
                                                  const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
@@ -402,6 +496,7 @@ __global__ __launch_bounds__(256, 2) void k_msg_bwd(Net<T> P, const double* __re
   for (int q = tid; q < astr; q += nt) acc[q] = T(0);
   __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
   __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
+  __shared__ T red4[sizeof(T) == 8 ? 4 * 40 : 1];
   // one pair class per launch row of blocks: a = blockIdx.y (par, anti), which
   // halves the live accumulators and so doubles the resident waves
   const int a = blockIdx.y;
@@ -459,7 +554,6 @@ __global__ __launch_bounds__(256, 2) void k_msg_bwd(Net<T> P, const double* __re
             silu3(pre, sf, s1, s2);
             const T gb = mb * sf, pb = mb * gam * s1;
             abar += pb;
-            atomicAdd(&projbar[((wl * n + j) * 4 + 2 + a) * d + c], pb);
             for (int q = 0; q < 4; ++q) aWe[q] += pb * f[4 + q];
             ab += pb;
             u1 = gb * g2;
@@ -487,14 +581,7 @@ __global__ __launch_bounds__(256, 2) void k_msg_bwd(Net<T> P, const double* __re
           for (int k = 0; k < jc; ++k) {
             T u1, u2;
             pair_grads(k, act ? proj_j(k) : T(0), u1, u2);
-            for (int q = 0; q < D.h2; ++q) {
-              T v = wave_sum(act ? u1 * w3[q] : T(0));
-              if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
-            }
-            for (int q = 0; q < D.G; ++q) {
-              T v = wave_sum(act ? u2 * wenv[q] : T(0));
-              if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
-            }
+            pair_sums_waves(u1, u2, w3, wenv, act, D.h2, D.G, red4, red + k * 40);
           }
         }
         __syncthreads();
@@ -646,6 +733,7 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
   // FP32: B operands and LDS of the MFMA channel reductions
   __shared__ float red_us[sizeof(T) == 4 ? 4 * 2 * RCH * 64 : 1];
   __shared__ float red_wp[sizeof(T) == 4 ? 4 * RCH * 40 : 1];
+  __shared__ T red4[sizeof(T) == 8 ? 4 * 40 : 1];
   for (int64_t e = blockIdx.x; e < nrows; e += gridDim.x) {
     const double rx = R[3 * e], ry = R[3 * e + 1], rz = R[3 * e + 2];
     const T sb = act ? sbar[e * D.d + c] : T(0);
@@ -698,14 +786,7 @@ __global__ __launch_bounds__(256) void k_en_bwd(Net<T> P, const double* __restri
       for (int k = 0; k < mc; ++k) {
         T u1, u2;
         pair_grads(k, u1, u2);
-        for (int q = 0; q < D.h2; ++q) {
-          T v = wave_sum(act ? u1 * w3[q] : T(0));
-          if ((tid & 63) == 0) atomicAdd(&red[k * 40 + q], v);
-        }
-        for (int q = 0; q < D.G; ++q) {
-          T v = wave_sum(act ? u2 * wenv[q] : T(0));
-          if ((tid & 63) == 0) atomicAdd(&red[k * 40 + 8 + q], v);
-        }
+        pair_sums_waves(u1, u2, w3, wenv, act, D.h2, D.G, red4, red + k * 40);
       }
     }
     __syncthreads();
@@ -802,7 +883,11 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
 }
 
 // the per-walker mode keeps a vector of ones (coefficients) after the layout
-size_t grad_ws_bytes(const fire_handle* h, int W) { return grad_layout(h, W).total + align_up((size_t)W * 8); }
+// after the adjoint's layout: W doubles (unit coefficients of the per-walker
+// mode), then the cusp Jastrow's per-walker sums [W][4]
+size_t grad_ws_bytes(const fire_handle* h, int W) {
+  return grad_layout(h, W).total + align_up((size_t)W * 8) + align_up((size_t)W * 4 * 8);
+}
 
 // weight gradient C[a][b] = sum_r X[r][a] Y[r][b] (rows through maps), into grad
 template <typename T>
@@ -981,6 +1066,9 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
   hipLaunchKernelGGL(k_msg_bwd<T>, dim3(nb_msg, 2), dim3(blk), msg_lds, st, P, Rc, rows, w0, (const int16_t*)nidx,
                      (const int32_t*)ncnt, (const char*)state, S, (const T*)hb_cur, projbar, epart);
   CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_projbar_gather<T>, dim3(nb_msg, 2), dim3(blk), 0, st, P, Rc, rows, w0, (const int16_t*)nidx,
+                     (const int32_t*)ncnt, (const char*)state, S, (const T*)hb_cur, projbar);
+  CHECK(hipGetLastError());
   {
     const int ps = msg_part_size(D);
     for (int a = 0; a < 2; ++a) {
@@ -1076,15 +1164,19 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
 // Gradient of sum_w c_w log J_cusp,w by the Jastrow parameters q = (w_par,
 // a_par, w_anti, a_anti): for u = w a^2/(a + r), du/dw = a^2/(a + r) and
 // du/da = w a (a + 2r)/(a + r)^2, summed over the pairs of each walker; one
-// workgroup per walker adds c_w times its sums into g[0..3].
+// workgroup per walker writes c_w times its sums to part[w][0..3] (zeros for a
+// flagged walker), which k_jas_sum adds into g in walker order; with
+// gstride > 0 the sums go to walker w's own row g + w gstride instead.
 __global__ __launch_bounds__(256) void k_jas_grad(const Dims D, int W, const double* __restrict__ R,
                                                   const double* __restrict__ q, const double* __restrict__ coeff,
                                                   const int32_t* __restrict__ status, double* __restrict__ g,
-                                                  int64_t gstride) {
+                                                  int64_t gstride, double* __restrict__ part) {
   __shared__ double red[16];
   const int w = blockIdx.x, n = D.n;
-  if (status[w] != 0 || coeff[w] == 0.0) return;
-  // gstride > 0: walker w's sums go to its own row g + w gstride
+  if (status[w] != 0 || coeff[w] == 0.0) {
+    if (part && threadIdx.x < 4) part[4 * w + threadIdx.x] = 0.0;
+    return;
+  }
   if (gstride > 0) g += (int64_t)w * gstride;
   const double* Rw = R + (int64_t)w * n * 3;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1100,7 +1192,23 @@ __global__ __launch_bounds__(256) void k_jas_grad(const Dims D, int W, const dou
   }
   for (int k = 0; k < 4; ++k) {
     const double v = block_sum<double>(s[k], red);
-    if (threadIdx.x == 0 && v != 0.0) atomicAdd(g + k, coeff[w] * v);
+    if (threadIdx.x == 0) {
+      if (part) part[4 * w + k] = coeff[w] * v;
+      else g[k] += coeff[w] * v;
+    }
+    __syncthreads();
+  }
+}
+
+// g[k] += sum_w part[w][k], each thread over a fixed stride of walkers and
+// the block sum in a fixed order (the result does not depend on scheduling)
+__global__ __launch_bounds__(256) void k_jas_sum(int W, const double* __restrict__ part, double* __restrict__ g) {
+  __shared__ double red[16];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int w = threadIdx.x; w < W; w += blockDim.x) s += part[4 * w + k];
+    s = block_sum<double>(s, red);
+    if (threadIdx.x == 0) g[k] += s;
     __syncthreads();
   }
 }
@@ -1129,8 +1237,12 @@ static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state,
       const int wc = W - w0 < L.Wc ? W - w0 : L.Wc;
       CHECK(grad_chunk<T>(h, P, w0, wc, R, state, ws, coeff, grad, status, st));
     }
+    double* jpart = (double*)(ws + L.total + align_up((size_t)W * 8));
     hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, coeff, (const int32_t*)status,
-                       grad + theta_offset(h, "jas_cusp"), (int64_t)0);
+                       grad + theta_offset(h, "jas_cusp"), (int64_t)0, jpart);
+    CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_jas_sum, dim3(1), dim3(256), 0, st, W, (const double*)jpart,
+                       grad + theta_offset(h, "jas_cusp"));
     return hipGetLastError();
   }
   // Per-walker gradients O[w] = d log|psi_w| / d theta: the same adjoint run
@@ -1147,7 +1259,8 @@ static hipError_t grad_impl(fire_handle* h, int W, const double* R, char* state,
   for (int w = 0; w < W; ++w)
     CHECK(grad_chunk<T>(h, P, w, 1, R, state, ws, ones, per_walker + (int64_t)w * h->P, status, st));
   hipLaunchKernelGGL(k_jas_grad, dim3(W), dim3(256), 0, st, h->D, W, R, P.jas, (const double*)ones,
-                     (const int32_t*)status, per_walker + theta_offset(h, "jas_cusp"), (int64_t)h->P);
+                     (const int32_t*)status, per_walker + theta_offset(h, "jas_cusp"), (int64_t)h->P,
+                     (double*)nullptr);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_weighted_rows, dim3((unsigned)((h->P + 255) / 256)), dim3(256), 0, st, (int64_t)h->P, W,
                      (const double*)per_walker, coeff, grad);

@@ -164,3 +164,23 @@ def test_autograd_function_survives_interleaved_calls(lib):
     mask = torch.tensor([1.0, 0.0, 1.0, 1.0], device="cuda", dtype=torch.float64)
     (torch.nan_to_num(lpc) * w * mask).sum().backward()
     assert torch.isfinite(theta3.grad).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_gradient_is_deterministic(lib, precision):
+    """Every reduction of the adjoint has a fixed order (the sender side of
+    the message backward gathers over its own neighbour list, the cusp
+    Jastrow sums walkers in order): two calls give the same bits."""
+    log(f"case: narrow C12H14 {precision} W=6, two gradient calls bit for bit")
+    s, m, p, R = small_polyene(6, seed=21)
+    p["jas_cusp"] = np.array([-0.25, 0.8, -0.5, 1.2])
+    F, O, state, ws = setup_custom(s, m, p, R, precision)
+    coeff = np.random.default_rng(4).normal(size=6)
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    g1, _ = F.grad_params(Rd, state, ws, dev(coeff))
+    g1 = g1.clone()
+    g2, st = F.grad_params(Rd, state, ws, dev(coeff))
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    assert torch.equal(g1, g2)
