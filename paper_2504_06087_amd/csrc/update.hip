@@ -378,8 +378,8 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
             else acc_e += g1 * g2 * silu_(ae_new + bu_[v] + ef);
           }
           const int64_t q = q0 + t0 + t;
-          hseg[q * D.d + c] = h0u[v] + mu;
-          mseg[q * D.d + c] = mu;
+          __builtin_nontemporal_store(h0u[v] + mu, hseg + (int64_t)q * D.d + c);
+          __builtin_nontemporal_store(mu, mseg + (int64_t)q * D.d + c);
           if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = u; }
         }
       }
@@ -390,8 +390,8 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
     T* mseg = se == 0 ? mseg0 : mseg1;
     int* rinfo = se == 0 ? rinfo0 : rinfo1;
     const int64_t q = off[se * (W + 1) + j];   // e is first in its list
-    hseg[q * D.d + c] = h0new[(int64_t)j * D.d + c] + acc_e;
-    mseg[q * D.d + c] = acc_e;
+    __builtin_nontemporal_store(h0new[(int64_t)j * D.d + c] + acc_e, hseg + (int64_t)q * D.d + c);
+    __builtin_nontemporal_store(acc_e, mseg + (int64_t)q * D.d + c);
     if (c == 0) { rinfo[2 * q] = j; rinfo[2 * q + 1] = e; }
   }
 }
