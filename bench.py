@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--c5-walkers", type=int, default=512)
     ap.add_argument("--scaling", action="store_true",
                     help="runtime-scaling sweep over cumulene chains instead of the step benchmark")
-    ap.add_argument("--scaling-carbons", type=str, default="4,8,16,24,32,44,63",
+    ap.add_argument("--scaling-carbons", type=str, default="4,8,16,24,32,44,63,80,95",
                     help="chain lengths (carbons); 63 gives 256 electrons, 128 per spin, the largest supported")
     ap.add_argument("--scaling-cutoff", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",

@@ -124,7 +124,7 @@ typedef struct {
 
 /* Create/destroy a handle.  Copies the host arrays.  Returns FIRE_ERR_SHAPE
  * outside the dimensions the kernels support (width <= 256, n_up, n_dn <=
- * 128, n_gauss == 32, edge MLP widths exactly 16 and 8, K <= 32, L <= 16). */
+ * 192, n_gauss == 32, edge MLP widths exactly 16 and 8, K <= 32, L <= 16). */
 fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* model, fire_handle** out);
 fire_status fire_destroy(fire_handle* h);
 

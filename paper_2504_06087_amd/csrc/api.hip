@@ -226,7 +226,7 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   D.cut = md->cutoff; D.cutn = md->cutoff_nuc; D.cap_nbr = md->cap_nbr; D.cap_upd = md->cap_upd;
   D.prec = md->precision;
   D.split = md->precision == FIRE_BF16_HYBRID ? md->bf16_split : 0;
-  if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > 128 || D.nd > 128 || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
+  if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > kMaxPerSpin || D.nd > kMaxPerSpin || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
   if (D.d < 1 || D.d > 256 || D.L < 0 || D.L > 16 || D.K < 1 || D.K > 32 || D.E < 1) return FIRE_ERR_SHAPE;
   if (md->n_gauss != kMaxG || md->edge_h1 != kMaxH1 || md->edge_h2 != kMaxH2) return FIRE_ERR_SHAPE;
   if (D.NT < 1 || !(D.cut > 0) || !(D.cutn > 0)) return FIRE_ERR_SHAPE;

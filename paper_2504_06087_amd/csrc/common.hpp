@@ -16,6 +16,7 @@ namespace fire {
 constexpr int kFcutP = 6;          // exponent p of the polynomial cutoff
 constexpr double kLnEps = 1e-5;    // LayerNorm epsilon
 constexpr int kMaxG = 32;          // radial Gaussians per filter
+constexpr int kMaxPerSpin = 192;   // electrons per spin block (register inversion, Woodbury LDS)
 constexpr int kMaxH1 = 16;         // filter hidden widths
 constexpr int kMaxH2 = 8;
 

@@ -5,8 +5,8 @@
 namespace fire {
 
 // ---------------------------------------------------------------------------
-// a1: neighbour lists through a cell list.  One workgroup per walker (n <=
-// 256): the walker's electrons are binned into a grid over their bounding
+// a1: neighbour lists through a cell list.  One workgroup per walker, one
+// thread per electron (NMAX = 256 or 512 threads, n <= NMAX): the walker's electrons are binned into a grid over their bounding
 // box whose cells are at least c wide along every axis (at most 12 per axis),
 // so every pair within c lies in the same or an adjacent cell; electron i
 // then tests only the members of its 27 surrounding cells.  The hits are
@@ -17,15 +17,17 @@ namespace fire {
 constexpr int kNbrCellsPerAxis = 12;
 constexpr int kNbrCells = kNbrCellsPerAxis * kNbrCellsPerAxis * kNbrCellsPerAxis;
 
-static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
-                                             double cut2, int cap, int16_t* __restrict__ idx,
-                                             int32_t* __restrict__ cnt, int32_t* status) {
-  __shared__ double pos[256 * 3];
-  __shared__ int cell_of[256];
+template <int NMAX>
+__global__ __launch_bounds__(NMAX) void k_nbr(const double* __restrict__ R, int W, int n, int nu,
+                                              double cut2, int cap, int16_t* __restrict__ idx,
+                                              int32_t* __restrict__ cnt, int32_t* status) {
+  constexpr int NW = NMAX / 64;   // waves; also 64-bit words of the hit set
+  __shared__ double pos[NMAX * 3];
+  __shared__ int cell_of[NMAX];
   __shared__ int cstart[kNbrCells + 1];
   __shared__ int cfill[kNbrCells];
-  __shared__ unsigned char members[256];
-  __shared__ double red[2][3][4];
+  __shared__ int16_t members[NMAX];
+  __shared__ double red[2][3][NW];
   __shared__ double box_lo[3], box_h[3];
   __shared__ int box_g[3];
   const int w = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -103,11 +105,13 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
   __syncthreads();
   if (mine) {
     const int cidx = cell_of[tid];
-    members[cstart[cidx] + atomicAdd(&cfill[cidx], 1)] = (unsigned char)tid;
+    members[cstart[cidx] + atomicAdd(&cfill[cidx], 1)] = (int16_t)tid;
   }
   __syncthreads();
   if (!mine) return;
-  uint64_t hit[4] = {0, 0, 0, 0};
+  uint64_t hit[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) hit[q] = 0;
   if (fin) {
     for (int dz = -1; dz <= 1; ++dz) {
       const int z = cz + dz;
@@ -123,7 +127,11 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
             const int j = members[t];
             if (j == tid) continue;
             const double ddx = xi - pos[3 * j], ddy = yi - pos[3 * j + 1], ddz = zi - pos[3 * j + 2];
-            if (ddx * ddx + ddy * ddy + ddz * ddz <= cut2) hit[j >> 6] |= 1ull << (j & 63);
+            if (ddx * ddx + ddy * ddy + ddz * ddz <= cut2) {
+#pragma unroll
+              for (int q = 0; q < NW; ++q)
+                if (q == (j >> 6)) hit[q] |= 1ull << (j & 63);
+            }
           }
         }
       }
@@ -137,7 +145,7 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
   for (int pass = 0; pass < 2; ++pass) {
     const bool up = (pass == 0) == (si == 0);        // this pass lists spin-up electrons
     const int j0 = up ? 0 : nu, j1 = up ? nu : n;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NW; ++q) {
       uint64_t m = hit[q];
       const int base = 64 * q;
       // keep the bits of [j0, j1)
@@ -160,6 +168,15 @@ static __global__ __launch_bounds__(256) void k_nbr(const double* __restrict__ R
   }
   cnt[((int64_t)w * n + tid) * 2 + 0] = c[0];
   cnt[((int64_t)w * n + tid) * 2 + 1] = c[1];
+}
+
+// One thread per electron: 256 threads up to 256 electrons, 512 up to 512.
+inline void launch_nbr(dim3 grid, hipStream_t st, const double* R, int W, int n, int nu, double cut2, int cap,
+                       int16_t* idx, int32_t* cnt, int32_t* status) {
+  if (n <= 256)
+    hipLaunchKernelGGL(k_nbr<256>, grid, dim3(256), 0, st, R, W, n, nu, cut2, cap, idx, cnt, status);
+  else
+    hipLaunchKernelGGL(k_nbr<512>, grid, dim3(512), 0, st, R, W, n, nu, cut2, cap, idx, cnt, status);
 }
 
 // ---------------------------------------------------------------------------

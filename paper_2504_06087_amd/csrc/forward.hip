@@ -108,20 +108,20 @@ __global__ __launch_bounds__(256) void k_msg(Net<T> P, const double* __restrict_
 // as G = Phi^-T in TI), the sign and log|det| of the block from the same
 // elimination.
 // ---------------------------------------------------------------------------
-// a7 with the block in registers: the N x N block (N <= 16 NB) is spread
-// over a 16 x 16 grid of threads, thread (ty, tx) holding rows ty + 16 a and
-// columns tx + 16 b (a, b < NB).  The elimination is gj_block's (partial
+// a7 with the block in registers: the N x N block (N <= TG NB) is spread
+// over a TG x TG grid of threads (TG = 16, or 32 for blocks past 128 rows),
+// thread (ty, tx) holding rows ty + TG a and columns tx + TG b (a, b < NB).  The elimination is gj_block's (partial
 // pivoting by row swaps, multipliers by division, the inverse formed in
 // place, columns permuted back at the end); per step only the pivot column,
 // the pivot row and the row it swaps with pass through LDS, and every
 // element update is a register FMA.
-template <typename TP, typename TI, int NB>
-__global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__ state_in, char* __restrict__ state_out,
+template <typename TP, typename TI, int NB, int TG>
+__global__ __launch_bounds__(TG * TG) void k_gj_inverse_reg(const char* __restrict__ state_in, char* __restrict__ state_out,
                                                         size_t srec, size_t off_phi, size_t off_inv, size_t off_ds,
                                                         size_t off_dl, Dims D, int spin, int32_t* status) {
-  __shared__ double prow[16 * NB], krow[16 * NB], pcol[16 * NB];
-  __shared__ double cbest[16];
-  __shared__ int cidx[16], perm[16 * NB], icol[16 * NB];
+  __shared__ double prow[TG * NB], krow[TG * NB], pcol[TG * NB];
+  __shared__ double cbest[TG];
+  __shared__ int cidx[TG], perm[TG * NB], icol[TG * NB];
   __shared__ int pvt;
   const int N = spin == 0 ? D.nu : D.nd;
   const int w = blockIdx.x / D.K, det = blockIdx.x % D.K;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
   TI* inv = (TI*)(state_out + (int64_t)w * srec + off_inv) + boff;
   double* dsign = (double*)(state_out + (int64_t)w * srec + off_ds);
   double* dlog = (double*)(state_out + (int64_t)w * srec + off_dl);
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG;
   if (N == 0) {
     if (tid == 0) { dsign[det * 2 + spin] = 1.0; dlog[det * 2 + spin] = 0.0; }
     return;
@@ -140,14 +140,14 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int i = ty + 16 * a, j = tx + 16 * b;
+      const int i = ty + TG * a, j = tx + TG * b;
       A[a][b] = (i < N && j < N) ? (double)phi[(int64_t)i * N + j] : 0.0;
     }
   double lsum = 0.0, sgn = 1.0;
   bool sing = false;
   for (int k = 0; k < N; ++k) {
-    const int kb = k >> 4, k16 = k & 15;
-    // column k of my rows (meaningful for tx == k16)
+    const int kb = k / TG, kt = k % TG;
+    // column k of my rows (meaningful for tx == kt)
     double ck[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
@@ -156,12 +156,12 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
       for (int b = 0; b < NB; ++b) c = b == kb ? A[a][b] : c;
       ck[a] = c;
     }
-    if (tx == k16) {
+    if (tx == kt) {
       double best = -1.0;
       int bi = k;
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
-        const int i = ty + 16 * a;
+        const int i = ty + TG * a;
         const double v = fabs(ck[a]);
         if (i >= k && i < N && v > best) { best = v; bi = i; }
       }
@@ -172,19 +172,19 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
     if (tid == 0) {
       double best = -1.0;
       int bi = k;
-      for (int t = 0; t < 16; ++t)
+      for (int t = 0; t < TG; ++t)
         if (cbest[t] > best || (cbest[t] == best && cidx[t] < bi)) { best = cbest[t]; bi = cidx[t]; }
       pvt = bi;
       perm[k] = bi;
     }
     __syncthreads();
     const int p = pvt;
-    const int pb = p >> 4, p16 = p & 15;
+    const int pb = p / TG, pt = p % TG;
     // the old rows k and p, and column k after the swap
-    if (ty == k16 || ty == p16) {
+    if (ty == kt || ty == pt) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int j = tx + 16 * b;
+        const int j = tx + TG * b;
         double rk = 0.0, rp = 0.0;
 #pragma unroll
         for (int a = 0; a < NB; ++a) {
@@ -192,15 +192,15 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
           rp = a == pb ? A[a][b] : rp;
         }
         if (j < N) {
-          if (ty == k16) krow[j] = rk;
-          if (ty == p16) prow[j] = rp;
+          if (ty == kt) krow[j] = rk;
+          if (ty == pt) prow[j] = rp;
         }
       }
     }
-    if (tx == k16) {
+    if (tx == kt) {
 #pragma unroll
       for (int a = 0; a < NB; ++a) {
-        const int i = ty + 16 * a;
+        const int i = ty + TG * a;
         if (i < N) pcol[i == k ? p : (i == p ? k : i)] = ck[a];
       }
     }
@@ -214,19 +214,19 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
     double pj[NB], kj[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int j = tx + 16 * b;
+      const int j = tx + TG * b;
       pj[b] = j < N ? prow[j] : 0.0;
       kj[b] = j < N ? krow[j] : 0.0;
     }
     const double ip = 1.0 / piv;
 #pragma unroll
     for (int a = 0; a < NB; ++a) {
-      const int i = ty + 16 * a;
+      const int i = ty + TG * a;
       const bool isk = i == k, isp = i == p && p != k;
       const double f = (isk || i >= N) ? 0.0 : pcol[i] / piv;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int j = tx + 16 * b;
+        const int j = tx + TG * b;
         const double old = isk ? pj[b] : (isp ? kj[b] : A[a][b]);
         double v;
         if (isk) v = j == k ? ip : old / piv;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_gj_inverse_reg(const char* __restrict__
   for (int a = 0; a < NB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int l = ty + 16 * a, m = tx + 16 * b;
+      const int l = ty + TG * a, m = tx + TG * b;
       if (l < N && m < N) inv[(int64_t)perm[m] * N + l] = (TI)A[a][b];
     }
 }
@@ -368,7 +368,7 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
   T* basis = (T*)(ws + L.basis);
   const int64_t srecT = S.stride / sizeof(T);   // record stride in T elements
 
-  hipLaunchKernelGGL(k_nbr, dim3(W), dim3(256), 0, s, R, W, D.n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt, status);
+  launch_nbr(dim3(W), s, R, W, D.n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt, status);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, s, P, R, rows, y, EPB, (const int*)nullptr);
   CHECK(hipGetLastError());
@@ -449,26 +449,36 @@ hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* stat
   const StateRec& S = h->st;
   for (int sp = 0; sp < 2; ++sp) {
     const int N = D.nsig(sp);
-    const int nb = (N + 15) / 16;
-    const dim3 g((unsigned)(W * D.K)), blk(256);
-    auto go = [&](auto nbc) {
-      constexpr int NBC = decltype(nbc)::value;
+    // up to 128 rows: a 16 x 16 thread grid (up to 64 values per thread);
+    // up to 192: 32 x 32 (up to 36 values per thread: a 1024-thread
+    // workgroup holds 128 registers per lane)
+    const int nb = N <= 128 ? (N + 15) / 16 : (N + 31) / 32;
+    const dim3 g((unsigned)(W * D.K));
+    auto go = [&](auto nbc, auto tgc) {
+      constexpr int NBC = decltype(nbc)::value, TGC = decltype(tgc)::value;
       if (h->isize == 8)
-        hipLaunchKernelGGL((k_gj_inverse_reg<T, double, NBC>), g, blk, 0, s, state, state, S.stride, S.phi, S.inv,
-                           S.dsign, S.dlog, D, sp, status);
+        hipLaunchKernelGGL((k_gj_inverse_reg<T, double, NBC, TGC>), g, dim3(TGC * TGC), 0, s, state, state, S.stride,
+                           S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
       else
-        hipLaunchKernelGGL((k_gj_inverse_reg<T, float, NBC>), g, blk, 0, s, state, state, S.stride, S.phi, S.inv,
-                           S.dsign, S.dlog, D, sp, status);
+        hipLaunchKernelGGL((k_gj_inverse_reg<T, float, NBC, TGC>), g, dim3(TGC * TGC), 0, s, state, state, S.stride,
+                           S.phi, S.inv, S.dsign, S.dlog, D, sp, status);
     };
-    switch (nb) {
-      case 0: case 1: go(std::integral_constant<int, 1>{}); break;
-      case 2: go(std::integral_constant<int, 2>{}); break;
-      case 3: go(std::integral_constant<int, 3>{}); break;
-      case 4: go(std::integral_constant<int, 4>{}); break;
-      case 5: go(std::integral_constant<int, 5>{}); break;
-      case 6: go(std::integral_constant<int, 6>{}); break;
-      case 7: go(std::integral_constant<int, 7>{}); break;
-      default: go(std::integral_constant<int, 8>{}); break;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    if (N <= 128) {
+      switch (nb) {
+        case 0: case 1: go(std::integral_constant<int, 1>{}, I16{}); break;
+        case 2: go(std::integral_constant<int, 2>{}, I16{}); break;
+        case 3: go(std::integral_constant<int, 3>{}, I16{}); break;
+        case 4: go(std::integral_constant<int, 4>{}, I16{}); break;
+        case 5: go(std::integral_constant<int, 5>{}, I16{}); break;
+        case 6: go(std::integral_constant<int, 6>{}, I16{}); break;
+        case 7: go(std::integral_constant<int, 7>{}, I16{}); break;
+        default: go(std::integral_constant<int, 8>{}, I16{}); break;
+      }
+    } else {
+      if (nb <= 5) go(std::integral_constant<int, 5>{}, I32{});
+      else go(std::integral_constant<int, 6>{}, I32{});
     }
     CHECK(hipGetLastError());
   }

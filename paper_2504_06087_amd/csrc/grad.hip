@@ -957,8 +957,8 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
   const RowMap h0map{n, srecT, d}, projmap{n, srecT, 4 * d};
 
   // ---- forward recompute of node activations
-  hipLaunchKernelGGL(k_nbr, dim3(Wc), dim3(256), 0, st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
-                     status + w0);
+  launch_nbr(dim3(Wc), st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
+             status + w0);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_en_embed<T>, dim3((unsigned)((rows + EPB - 1) / EPB)), dim3(blk), 0, st, P, Rc, rows, y, EPB, (const int*)nullptr);
   CHECK(hipGetLastError());

@@ -701,8 +701,8 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
   T* jA[2] = {(T*)(ws + L.jetA[0]), (T*)(ws + L.jetA[1])};
   T* jB[2] = {(T*)(ws + L.jetB[0]), (T*)(ws + L.jetB[1])};
 
-  hipLaunchKernelGGL(k_nbr, dim3(Wc), dim3(256), 0, st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
-                     status + w0);
+  launch_nbr(dim3(Wc), st, Rc, Wc, n, D.nu, D.cut * D.cut, D.cap_nbr, nidx, ncnt,
+             status + w0);
   CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_jet_offsets, dim3(1), dim3(1024), 0, st, Wc, n, D.nu, (const int32_t*)ncnt, joff, jtot);
   CHECK(hipGetLastError());
