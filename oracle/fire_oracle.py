@@ -20,8 +20,11 @@ spin-block determinants; exp(-sigma |r - R|) envelopes with exponents shared
 over orbitals; SiLU activations; a LLaMA-style GLU W_o[(LN(s)W_v+b_v) *
 SiLU(LN(s)W_g+b_g)] + b_o; filters 4 -> 16 -> 8 -> d with a 32-Gaussian radial
 part; the polynomial cutoff with p = 6; separate parallel/antiparallel
-message weights; of the Jastrow terms only the cusp factor, exp of a pair sum
-with (w, a) per spin class (zero weights by default); semilocal l = 0, 1 pseudopotential
+message weights; of the Jastrow terms the cusp factor, exp of a pair sum
+with (w, a) per spin class (zero weights by default), and optionally the
+per-electron MLP factor exp(sum_i MLP_1(h_i)) sum_i MLP_2(h_i) over the final
+embeddings, each MLP two SiLU hidden layers and a scalar linear readout, the
+factors multiplying (their logs add); semilocal l = 0, 1 pseudopotential
 channels with an equal-weight angular rule per species (12-point icosahedron
 unless the system names 4 or 6 points).
 
@@ -217,6 +220,10 @@ class Oracle:
         tot = (sgn * torch.exp(ld - lmax)).sum(1)
         sign = torch.sign(tot)
         logpsi = lmax[:, 0] + torch.log(torch.abs(tot)) + self.jastrow_cusp(R)
+        if "jmlp_W1" in self.p:
+            lj, sj = self.jastrow_mlp(h)
+            logpsi = logpsi + lj
+            sign = sign * sj
         return sign, logpsi, sgn, ld, phis
 
     def jastrow_cusp(self, R):
@@ -236,8 +243,30 @@ class Oracle:
         a = torch.where(same, q[1], q[3])
         return (w * a * a / (a + rij)).sum(1)
 
+    def jastrow_mlp_terms(self, h):
+        """The two per-electron readouts of the MLP Jastrow (Methods, global
+        electron correlation): MLP_k(h_i) = w3_k . SiLU(SiLU(h_i W1_k + b1_k)
+        W2_k + b2_k) + b3_k for k = 1 (log part) and 2 (node part), over the
+        final embeddings h [B,n,d]: returns [B,n,2]."""
+        p = self.p
+        out = []
+        for k in (0, 1):
+            z = silu(h @ p["jmlp_W1"][k] + p["jmlp_b1"][k])
+            z = silu(z @ p["jmlp_W2"][k] + p["jmlp_b2"][k])
+            out.append(z @ p["jmlp_w3"][k] + p["jmlp_b3"][k])
+        return torch.stack(out, -1)
+
+    def jastrow_mlp(self, h):
+        """(log|J_MLP|, sign J_MLP) with J_MLP = exp(sum_i MLP_1(h_i)) *
+        sum_i MLP_2(h_i) (Methods, global electron correlation; the three
+        Jastrow terms multiply, their logs add)."""
+        t = self.jastrow_mlp_terms(h)
+        s1, s2 = t[..., 0].sum(1), t[..., 1].sum(1)
+        return s1 + torch.log(torch.abs(s2)), torch.sign(s2)
+
     def log_psi(self, R):
-        """(sign, log|psi|) for walkers R [B,n,3], psi = exp(J_cusp) sum_d det Phi_d."""
+        """(sign, log|psi|) for walkers R [B,n,3], psi = exp(J_cusp) J_MLP sum_d det Phi_d
+        (J_MLP = 1 unless the parameters hold its weights)."""
         R = torch.as_tensor(R, dtype=DT)
         s, l, *_ = self.log_psi_parts(R)
         return s, l

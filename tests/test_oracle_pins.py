@@ -722,6 +722,140 @@ def test_jastrow_is_symmetric_and_zero_by_default():
 
 
 # --------------------------------------------------------------------------
+# MLP Jastrow (Methods, global electron correlation: exp(sum_i MLP_1(h_i))
+# times sum_i MLP_2(h_i) over the final embeddings)
+# --------------------------------------------------------------------------
+def _silu_np(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def _jmlp_h4(W=3, Hj=8, seed=11):
+    s, m, p, R = _orc(0, W=W)
+    m.jas_mlp_width = Hj
+    p = wl.init_params(s, m, np.random.default_rng(seed))
+    m0 = copy.deepcopy(m)
+    m0.jas_mlp_width = 0
+    p0 = {k: v for k, v in p.items() if not k.startswith("jmlp_")}
+    return s, m, p, m0, p0, R
+
+
+def test_jastrow_mlp_constant_readouts_closed_form():
+    """With W1 = W2 = 0 every readout is the constant c_k = w3_k . SiLU(b2_k)
+    + b3_k, so log|psi| gains n c_1 + log|n c_2| and the sign takes
+    sign(c_2), for either sign of c_2."""
+    s, m, p, m0, p0, R = _jmlp_h4()
+    s0, l0 = Oracle(s, m0, p0).log_psi(R)
+    q = copy.deepcopy(p)
+    q["jmlp_W1"][:] = 0.0
+    q["jmlp_W2"][:] = 0.0
+    q["jmlp_b2"] = np.random.default_rng(3).normal(size=q["jmlp_b2"].shape)
+    n = s.n_el
+    for b3 in ([0.3, 0.2], [-0.1, -0.9]):
+        q["jmlp_b3"] = np.array(b3)
+        c = [float(np.dot(q["jmlp_w3"][k], _silu_np(q["jmlp_b2"][k]))) + b3[k] for k in (0, 1)]
+        s1, l1 = Oracle(s, m, q).log_psi(R)
+        assert np.allclose((l1 - l0).numpy(), n * c[0] + math.log(abs(n * c[1])), atol=1e-12, rtol=0)
+        assert np.array_equal(s1.numpy(), s0.numpy() * np.sign(c[1]))
+
+
+def test_jastrow_mlp_single_path_hand_computed():
+    """One live path per readout: W1_k = v_k e_0^T (a column of the [d][Hj]
+    matrix), W2_k = a_k e_0 e_1^T (hidden unit 0 feeds unit 1), so MLP_k(h) =
+    w3_k[1] SiLU(a_k SiLU(h . v_k + b1_k[0]) + b2_k[1]) + sum_{c != 1}
+    w3_k[c] SiLU(b2_k[c]) + b3_k, summed over the final embeddings h_i; a
+    transposed layer, swapped readouts or a dropped log fail it."""
+    s, m, p, m0, p0, R = _jmlp_h4(W=4)
+    rng = np.random.default_rng(8)
+    q = copy.deepcopy(p)
+    d, Hj = m.width, m.jas_mlp_width
+    v = rng.normal(size=(2, d)) / math.sqrt(d)
+    a = np.array([1.3, -0.8])
+    q["jmlp_W1"] = np.zeros((2, d, Hj))
+    q["jmlp_W2"] = np.zeros((2, Hj, Hj))
+    for k in (0, 1):
+        q["jmlp_W1"][k, :, 0] = v[k]
+        q["jmlp_W2"][k, 0, 1] = a[k]
+    q["jmlp_b1"] = rng.normal(size=(2, Hj))
+    q["jmlp_b2"] = rng.normal(size=(2, Hj))
+    q["jmlp_b3"] = np.array([0.2, 0.5])
+    o = Oracle(s, m, q)
+    h = o.embed(torch.as_tensor(R))["h"].numpy()                # [B, n, d]
+    S = []
+    for k in (0, 1):
+        w3, b1, b2 = q["jmlp_w3"][k], q["jmlp_b1"][k], q["jmlp_b2"][k]
+        live = w3[1] * _silu_np(a[k] * _silu_np(h @ v[k] + b1[0]) + b2[1])
+        dead = float(np.dot(w3, _silu_np(b2))) - w3[1] * _silu_np(b2[1])
+        S.append((live + dead + q["jmlp_b3"][k]).sum(1))
+    _, l0 = Oracle(s, m0, p0).log_psi(R)
+    s1, l1 = o.log_psi(R)
+    assert np.allclose((l1 - l0).numpy(), S[0] + np.log(np.abs(S[1])), atol=1e-12, rtol=0)
+    s0, _ = Oracle(s, m0, p0).log_psi(R)
+    assert np.array_equal(s1.numpy(), s0.numpy() * np.sign(S[1]))
+
+
+def test_jastrow_mlp_is_symmetric_under_same_spin_swaps():
+    """The factor is symmetric, so log|psi| keeps its value and the sign
+    flips under a same-spin exchange, as without it."""
+    s, m, p, m0, p0, R = _jmlp_h4()
+    o = Oracle(s, m, p)
+    Rs = R.copy()
+    Rs[:, [0, 1]] = Rs[:, [1, 0]]
+    sa, la = o.log_psi(R)
+    sb, lb = o.log_psi(Rs)
+    assert torch.allclose(la, lb, atol=1e-12, rtol=0)
+    assert torch.equal(sa, -sb)
+
+
+def test_jastrow_mlp_gradient_and_laplacian_vs_finite_differences():
+    """grad and Lap of log|psi| with the MLP Jastrow (autodiff in the oracle)
+    against fourth-order central differences of log|psi| itself."""
+    s, m, p, m0, p0, R = _jmlp_h4(W=2)
+    o = Oracle(s, m, p)
+    g, lap = o.grad_lap(R)
+    h = 1e-3
+    for w in range(2):
+        x0 = R[w].copy()
+        f = lambda x: float(o.log_psi(x[None])[1][0])
+        l0 = f(x0)
+        fd_lap, fd_g = 0.0, np.zeros_like(x0)
+        for i in range(s.n_el):
+            for k in range(3):
+                vals = {}
+                for st in (-2, -1, 1, 2):
+                    x = x0.copy()
+                    x[i, k] += st * h
+                    vals[st] = f(x)
+                fd_g[i, k] = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * h)
+                fd_lap += (-vals[2] + 16 * vals[1] - 30 * l0 + 16 * vals[-1] - vals[-2]) / (12 * h * h)
+        assert np.allclose(g[w].numpy(), fd_g, atol=1e-7 * max(1.0, np.abs(fd_g).max()))
+        # fourth-order differences: relative error ~1e-7 at |Lap| of several hundred
+        assert abs(float(lap[w]) - fd_lap) < 1e-6 * max(1.0, abs(fd_lap))
+
+
+def test_jastrow_mlp_theta_gradient_vs_finite_differences():
+    s, m, p, m0, p0, R = _jmlp_h4(W=3)
+    o = Oracle(s, m, p)
+    coeff = np.array([0.7, -1.3, 0.4])
+    g = o.grad_params(R, coeff)
+    names = [k for k in p if k.startswith("jmlp_")] + ["mlp_W", "glu_Wo"]
+    rng = np.random.default_rng(6)
+    for _ in range(4):
+        dirs = {k: rng.normal(size=p[k].shape) for k in names}
+        nrm = math.sqrt(sum((v ** 2).sum() for v in dirs.values()))
+        dirs = {k: v / nrm for k, v in dirs.items()}
+        hh = 1e-5
+
+        def val(t):
+            q = dict(p)
+            for k in names:
+                q[k] = p[k] + t * dirs[k]
+            return float((Oracle(s, m, q).log_psi(R)[1].numpy() * coeff).sum())
+        fd = (8 * (val(hh) - val(-hh)) - (val(2 * hh) - val(-2 * hh))) / (12 * hh)
+        an = sum(float((g[k].numpy() * dirs[k]).sum()) for k in names)
+        assert abs(fd - an) < 1e-8 * max(1.0, abs(an))
+
+
+# --------------------------------------------------------------------------
 # the counter-based generator of the sampler's own random numbers
 # --------------------------------------------------------------------------
 def test_philox_known_answer_vectors():

@@ -98,6 +98,7 @@ class Model:
     cutoff_nuc: float = 20.0
     n_nuc_types: int = 0        # rows of per-nucleus tables
     env_sigma_fixed: Optional[float] = None  # C1: a single exp(-|r-R|)
+    jas_mlp_width: int = 0      # hidden width of the per-electron MLP Jastrow (0: off)
 
 
 # ----------------------------------------------------------------------------
@@ -312,6 +313,12 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
     T = model.n_nuc_types or system.n_nuc
     M, K, E, L = system.n_nuc, model.n_det, model.n_env, model.mlp_layers
     nu, nd = system.n_up, system.n_dn
+    Hj = model.jas_mlp_width
+    jm = {} if Hj <= 0 else {
+        # per-electron MLP Jastrow: index 0 MLP_1 (log part), 1 MLP_2 (node part)
+        "jmlp_W1": (2, d, Hj), "jmlp_b1": (2, Hj), "jmlp_W2": (2, Hj, Hj), "jmlp_b2": (2, Hj),
+        "jmlp_w3": (2, Hj), "jmlp_b3": (2,),
+    }
     return {
         # electron-nucleus filter Gamma_m and nuclear embeddings
         "en_W1": (T, 4, h1), "en_b1": (T, h1),
@@ -330,6 +337,7 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
         "mlp_W": (L, d, d), "mlp_b": (L, d),
         # cusp Jastrow (w_par, a_par, w_anti, a_anti)
         "jas_cusp": (4,),
+        **jm,
         # orbitals and envelopes
         "orb_W_up": (K, d, nu), "orb_W_dn": (K, d, nd),
         "env_pi_up": (K, nu, M, E), "env_pi_dn": (K, nd, M, E),
@@ -340,7 +348,8 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
 def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
     """Matrices N(0, 1/fan_in), biases 0, LayerNorm (1, 0), nuclear
     embeddings N(0,1), envelope weights N(0, 1/(M*N_env)), envelope exponents
-    linspace(0.5, 3), Gaussian filter widths (1 + 7k/(G-1))/cutoff."""
+    linspace(0.5, 3), Gaussian filter widths (1 + 7k/(G-1))/cutoff; the MLP
+    Jastrow's readout vectors N(0, 1/width) and readout biases (0, 1)."""
     shapes = param_shapes(system, model)
     p: Dict[str, np.ndarray] = {}
     G = model.n_gauss
@@ -360,6 +369,14 @@ def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
             # zero weights by default: J_cusp = 1; (-1/4, a, -1/2, a)
             # gives the electron-electron cusp conditions
             p[name] = np.array([0.0, 1.0, 0.0, 1.0])
+        elif name == "jmlp_w3":
+            p[name] = rng.normal(0.0, 1.0 / math.sqrt(shp[-1]), size=shp)
+        elif name == "jmlp_b3":
+            # MLP_1 bias 0; MLP_2 bias 1, so that sum_i MLP_2(h_i) starts near
+            # n, away from its zero set
+            p[name] = np.array([0.0, 1.0])
+        elif name == "jmlp_b2":
+            p[name] = np.zeros(shp)
         elif name == "nuc_emb":
             p[name] = rng.normal(0.0, 1.0, size=shp)
         elif name.startswith("env_pi"):
