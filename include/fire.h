@@ -111,6 +111,16 @@ typedef struct {
                          split into bf16 high + low parts (three MFMA products,
                          FP32 accumulation): bit 0 embedding/MLP rows, bit 1
                          orbital/envelope rows, bit 2 Laplacian tangent rows */
+  int jas_mlp_width;  /* per-electron MLP Jastrow (Methods, global electron
+                         correlation): J_MLP = exp(sum_i MLP_1(h_i)) *
+                         sum_i MLP_2(h_i) over the final embeddings h_i, each
+                         MLP two SiLU hidden layers of this width and a scalar
+                         linear readout; the factor multiplies the cusp factor.
+                         0: off; else a multiple of 8, at most width.  Adds the
+                         theta entries jmlp_W1 [2][d][w], jmlp_b1 [2][w],
+                         jmlp_W2 [2][w][w], jmlp_b2 [2][w], jmlp_w3 [2][w],
+                         jmlp_b3 [2] after jas_cusp (index 0: MLP_1, 1: MLP_2).
+                         sum_i MLP_2(h_i) = 0 makes psi = 0 (FIRE_W_DETSUM_ZERO). */
 } fire_model_desc;
 
 typedef struct fire_handle fire_handle;

@@ -83,6 +83,17 @@ static void build_theta(fire_handle* h) {
       {"orb_W_up", {D.K, D.d, D.nu}}, {"orb_W_dn", {D.K, D.d, D.nd}},
       {"env_pi_up", {D.K, D.nu, D.M, D.E}}, {"env_pi_dn", {D.K, D.nd, D.M, D.E}}, {"env_sigma", {D.M, D.E}},
   };
+  if (D.Hj > 0) {
+    // MLP Jastrow entries follow the cusp Jastrow (before the per-system
+    // orbital block)
+    size_t at = 0;
+    while (at < e.size() && e[at].first != "jas_cusp") ++at;
+    const int w = D.Hj;
+    std::vector<std::pair<std::string, std::vector<int>>> jm = {
+        {"jmlp_W1", {2, D.d, w}}, {"jmlp_b1", {2, w}}, {"jmlp_W2", {2, w, w}},
+        {"jmlp_b2", {2, w}},      {"jmlp_w3", {2, w}}, {"jmlp_b3", {2}}};
+    e.insert(e.begin() + (at + 1), jm.begin(), jm.end());
+  }
   int64_t off = 0;
   h->theta.clear();
   for (auto& x : e) {
@@ -124,6 +135,8 @@ static void build_layouts(fire_handle* h) {
   L.Wproj_n = take((size_t)4 * D.d * D.d * G); L.mlp_n = take((size_t)D.L * D.d * D.d * G);
   L.orb_n0 = take((size_t)D.K * D.nu * D.d * G); L.orb_n1 = take((size_t)D.K * D.nd * D.d * G);
   L.pi_n0 = take((size_t)D.K * D.nu * D.B * G); L.pi_n1 = take((size_t)D.K * D.nd * D.B * G);
+  L.jm_W1t = take((size_t)2 * D.Hj * D.d * G); L.jm_W2t = take((size_t)2 * D.Hj * D.Hj * G);
+  L.jm_W1n = take((size_t)2 * D.Hj * D.d * G); L.jm_W2n = take((size_t)2 * D.Hj * D.Hj * G);
   if (D.prec == FIRE_BF16_HYBRID) {
     const size_t region = o - L.Wvg_t;
     L.lo_delta = region;
@@ -136,6 +149,8 @@ static void build_layouts(fire_handle* h) {
   L.ntype = take((size_t)D.M * 4);
   L.species = take((size_t)D.M * 4);
   L.jas = take(4 * 8);
+  L.jm_b1 = take((size_t)2 * D.Hj * T); L.jm_b2 = take((size_t)2 * D.Hj * T);
+  L.jm_w3 = take((size_t)2 * D.Hj * T); L.jm_b3 = take(2 * T);
   L.total = o;
 
   StateRec& S = h->st;
@@ -152,6 +167,8 @@ static void build_layouts(fire_handle* h) {
   S.lpsi = take(8);
   S.spsi = take(8);
   S.jas = take(8);
+  S.jme = take(D.Hj > 0 ? (size_t)D.n * 2 * 8 : 0);
+  S.jms = take(D.Hj > 0 ? 2 * 8 : 0);
   S.stride = o;
 }
 
@@ -226,6 +243,8 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   D.cut = md->cutoff; D.cutn = md->cutoff_nuc; D.cap_nbr = md->cap_nbr; D.cap_upd = md->cap_upd;
   D.prec = md->precision;
   D.split = md->precision == FIRE_BF16_HYBRID ? md->bf16_split : 0;
+  D.Hj = md->jas_mlp_width;
+  if (D.Hj < 0 || (D.Hj > 0 && (D.Hj % 8 != 0 || D.Hj > md->width))) return FIRE_ERR_SHAPE;
   if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > kMaxPerSpin || D.nd > kMaxPerSpin || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
   if (D.d < 1 || D.d > 256 || D.L < 0 || D.L > 16 || D.K < 1 || D.K > 32 || D.E < 1) return FIRE_ERR_SHAPE;
   if (md->n_gauss != kMaxG || md->edge_h1 != kMaxH1 || md->edge_h2 != kMaxH2) return FIRE_ERR_SHAPE;
@@ -359,6 +378,17 @@ fire_status fire::set_params_split(fire_handle* h, const double* shared, const d
   DO(do_copy(T, b + L.b_vg + (size_t)D.d * T, src("glu_bg"), plain(D.d), s));
   DO(cp(L.b_o, "glu_bo")); DO(cp(L.mlp_b, "mlp_b"));
   DO(do_copy(8, b + L.jas, src("jas_cusp"), plain(4), s));
+  if (D.Hj > 0) {
+    const int w = D.Hj;
+    const size_t LD0 = L.lo_delta;
+    DO(cp(L.jm_b1, "jmlp_b1")); DO(cp(L.jm_b2, "jmlp_b2")); DO(cp(L.jm_w3, "jmlp_w3")); DO(cp(L.jm_b3, "jmlp_b3"));
+    // W1t[k w + c][i] = W1[k][i][c]; W2t[k][c][i] = W2[k][i][c]
+    DO(do_copy(G, b + L.jm_W1t, src("jmlp_W1"), transposed(2, D.d, w), s, LD0));
+    DO(do_copy(G, b + L.jm_W2t, src("jmlp_W2"), transposed(2, w, w), s, LD0));
+    // adjoint: W1n[k][i][c] = W1[k][i][c], W2n[k][i][c] = W2[k][i][c]
+    DO(do_copy(G, b + L.jm_W1n, src("jmlp_W1"), plain((int64_t)2 * D.d * w), s, LD0));
+    DO(do_copy(G, b + L.jm_W2n, src("jmlp_W2"), plain((int64_t)2 * w * w), s, LD0));
+  }
   // GEMM operands Bt[N][K] (and their low bf16 parts under the hybrid precision)
   const int64_t dd = (int64_t)D.d * D.d;
   const size_t LD = L.lo_delta;

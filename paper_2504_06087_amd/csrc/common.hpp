@@ -37,6 +37,7 @@ struct Dims {
   int cap_nbr, cap_upd;
   int prec;
   int split;          // GEMM sites using split bf16 operands (hybrid precision)
+  int Hj;             // hidden width of the MLP Jastrow (0: off)
   FIRE_HOST_DEVICE int nsig(int s) const { return s == 0 ? nu : nd; }
 };
 
@@ -195,6 +196,11 @@ template <typename T> struct Net {
   const void *Wvg_t, *Wo_t, *Wproj_t, *mlp_t, *orb_t0, *orb_t1, *pi0, *pi1;
   // the same GEMM weights in the adjoint orientation (Bt = W)
   const void *Wvg_n, *Wo_n, *Wproj_n, *mlp_n, *orb_n0, *orb_n1, *pi_n0, *pi_n1;
+  // MLP Jastrow (D.Hj > 0): biases b1 [2 Hj], b2 [2 Hj], readouts w3 [2][Hj]
+  // and b3 [2] in T; GEMM operands W1t [2 Hj][d] (both first layers),
+  // W2t [2][Hj][Hj], and W1n [2][d][Hj], W2n [2][Hj][Hj] for the adjoint
+  const T *jm_b1, *jm_b2, *jm_w3, *jm_b3;
+  const void *jm_W1t, *jm_W2t, *jm_W1n, *jm_W2n;
 };
 
 // ---------------------------------------------------------------------------

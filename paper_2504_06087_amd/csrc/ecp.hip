@@ -197,11 +197,12 @@ __global__ void k_ecp_jobs(const Dims D, int W, int e, int j0, int Jc, const int
 
 // contribution of each job: coefficient * psi'/psi with
 // psi'/psi = e^{dJ} sum_d w_d prod_s det A_ds,  w_d = s_d e^{l_d} / sum_d s_d e^{l_d}
-// (dJ: the job's change of log J_cusp)
+// (dJ: the job's change of the Jastrow log magnitude; jsg, when set, the
+// sign change of the MLP Jastrow's node factor)
 __global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__ jdev, const int* __restrict__ jw,
                             const double* __restrict__ cf, const double* __restrict__ detA,
-                            const double* __restrict__ dj, const char* __restrict__ state, StateRec S,
-                            double* __restrict__ contrib) {
+                            const double* __restrict__ dj, const double* __restrict__ jsg,
+                            const char* __restrict__ state, StateRec S, double* __restrict__ contrib) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= J || j >= *jdev) return;
   const int w = jw[j];
@@ -215,7 +216,7 @@ __global__ void k_ecp_ratio(const Dims D, int J, int j0, const int* __restrict__
     const double sg = ds[2 * k] * ds[2 * k + 1] * sp * dA[4 * k] * dA[4 * k + 2];
     if (sg != 0.0) r += sg * exp(dl[2 * k] + dl[2 * k + 1] - lp + dA[4 * k + 1] + dA[4 * k + 3]);
   }
-  contrib[j0 + j] = cf[j] * r * exp(dj[j]);
+  contrib[j0 + j] = cf[j] * r * exp(dj[j]) * (jsg ? jsg[j] : 1.0);
 }
 
 __global__ void k_ecp_reduce(int W, const int* __restrict__ off, const double* __restrict__ contrib,
@@ -387,7 +388,9 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       CHECK(propose_ratio<T>(h, P, jb, e, R, state, uws, status, ss));
       hipLaunchKernelGGL(k_ecp_ratio, dim3((L.Jc + 255) / 256), dim3(256), 0, ss, D, L.Jc, j0, (const int*)jdev,
                          (const int*)jw, (const double*)cf, (const double*)(uws + U.detA),
-                         (const double*)(uws + U.dj), (const char*)state, S, contrib);
+                         (const double*)(uws + U.dj),
+                         h->D.Hj > 0 ? (const double*)(uws + U.jsg) : (const double*)nullptr, (const char*)state,
+                         S, contrib);
       CHECK(hipGetLastError());
     }
     hipLaunchKernelGGL(k_ecp_reduce, dim3((W + 255) / 256), dim3(256), 0, ss, W, offe, (const double*)contrib, vl[ln]);

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "forward.hpp"
+#include "jastrow.hpp"
 #include "linalg.hpp"
 #include "embed_kernels.hpp"
 
@@ -288,10 +289,11 @@ __global__ __launch_bounds__(256) void k_jastrow(const Dims D, const double* __r
 }
 
 // Signed log-sum-exp over determinants: l* + log|sum_d s_d e^(l_d - l*)|
-// (cached); the returned log|psi| adds the cached log J_cusp.
+// (cached); the returned log|psi| adds the cached Jastrow log magnitude, and
+// with the MLP Jastrow (jm) the sign takes sign(S_2).
 __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds, size_t off_dl, size_t off_lp,
                             size_t off_sp, size_t off_jas, int W, int K, double* sign, double* logpsi,
-                            int32_t* status) {
+                            int32_t* status, bool jm, size_t off_jms) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   char* rec = state + (int64_t)w * srec;
@@ -327,7 +329,7 @@ __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds
   *(double*)(rec + off_lp) = lp;
   *(double*)(rec + off_sp) = sp;
   if (logpsi) logpsi[w] = lp + *(const double*)(rec + off_jas);
-  if (sign) sign[w] = sp;
+  if (sign) sign[w] = jm && ((const double*)(rec + off_jms))[1] < 0.0 ? -sp : sp;
 }
 
 // ---------------------------------------------------------------------------
@@ -345,6 +347,8 @@ WsLayout ws_forward(const fire_handle* h, int W) {
   L.hA = o;      o = align_up(o + rows * D.d * ts);
   L.hB = o;      o = align_up(o + rows * D.d * ts);
   L.basis = o;   o = align_up(o + rows * D.B * ts);
+  L.jrow = o;    o = align_up(o + (D.Hj > 0 ? rows * 2 * 8 : 0));
+  L.jscr = o;    o = align_up(o + jm_rows_ws(h, rows));
   L.total = o;
   return L;
 }
@@ -411,6 +415,12 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     g.M = (int)rows; g.N = D.d; g.K = D.d; g.act = ACT_SILU;
     CHECK(gemm_site(h, SITE_EMB, g, s));
     T* t = hin; hin = hout; hout = t;
+  }
+  // MLP Jastrow readouts of the final embeddings and their sums
+  if (D.Hj > 0) {
+    double* jrow = (double*)(ws + L.jrow);
+    CHECK(jm_rows<T>(h, P, hin, (int)rows, nullptr, ws + L.jscr, jrow, s));
+    CHECK(jm_store(h, W, jrow, state, s));
   }
   // envelopes and orbitals per spin block
   hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, s, P, R, rows, basis, (const int*)nullptr);
@@ -485,8 +495,9 @@ hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* stat
   hipLaunchKernelGGL(k_jastrow, dim3(W), dim3(256), 0, s, D, R, (const double*)((const char*)h->params + h->pl.jas),
                      state, S);
   CHECK(hipGetLastError());
+  CHECK(jm_total(h, W, state, status, s));
   hipLaunchKernelGGL(k_logsumexp, dim3((W + 127) / 128), dim3(128), 0, s, state, S.stride, S.dsign, S.dlog, S.lpsi,
-                     S.spsi, S.jas, W, D.K, sign, logpsi, status);
+                     S.spsi, S.jas, W, D.K, sign, logpsi, status, D.Hj > 0, S.jms);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ template <typename T> inline Net<T> make_net(const fire_handle* h) {
   P.orb_t0 = b + L.orb_t0; P.orb_t1 = b + L.orb_t1; P.pi0 = b + L.pi0; P.pi1 = b + L.pi1;
   P.Wvg_n = b + L.Wvg_n; P.Wo_n = b + L.Wo_n; P.Wproj_n = b + L.Wproj_n; P.mlp_n = b + L.mlp_n;
   P.orb_n0 = b + L.orb_n0; P.orb_n1 = b + L.orb_n1; P.pi_n0 = b + L.pi_n0; P.pi_n1 = b + L.pi_n1;
+  P.jm_b1 = t(L.jm_b1); P.jm_b2 = t(L.jm_b2); P.jm_w3 = t(L.jm_w3); P.jm_b3 = t(L.jm_b3);
+  P.jm_W1t = b + L.jm_W1t; P.jm_W2t = b + L.jm_W2t; P.jm_W1n = b + L.jm_W1n; P.jm_W2n = b + L.jm_W2n;
   return P;
 }
 

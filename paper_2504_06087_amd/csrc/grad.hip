@@ -149,6 +149,31 @@ __global__ void k_orb_bar(const Dims D, int s, int Wc, int w0, const char* __res
   o[q] = pb * o[q];
 }
 
+// MLP Jastrow readout k (0: S_1, 1: S_2) of row r = (w, i): its adjoint
+// g = c_w (k = 0) or c_w / S_2,w (k = 1); then a2bar = g w3 SiLU'(a2), the
+// readout-weight terms g z2 and g itself (bias)
+template <typename T>
+__global__ void k_jm_readout_bar(int64_t rows, int n, int w0, int Hj, int k, const char* __restrict__ state,
+                                 StateRec S, const double* __restrict__ coeff, const T* __restrict__ w3,
+                                 const T* __restrict__ a2, const T* z2, T* __restrict__ a2bar, T* gz2,
+                                 T* __restrict__ gcol) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= rows * Hj) return;
+  const int64_t r = q / Hj;
+  const int c = (int)(q % Hj);
+  const int64_t w = w0 + r / n;
+  double g = coeff[w];
+  if (k == 1) {
+    const double s2 = ((const double*)(state + w * S.stride + S.jms))[1];
+    g = s2 != 0.0 && isfinite(s2) ? g / s2 : 0.0;
+  }
+  T f, f1, f2;
+  silu3(a2[q], f, f1, f2);
+  a2bar[q] = (T)(g * (double)w3[c] * (double)f1);
+  gz2[q] = (T)(g * (double)z2[q]);
+  if (c == 0) gcol[r] = (T)g;
+}
+
 // ubar = tbar * SiLU(g), gbar = tbar * u * SiLU'(g)
 template <typename T>
 __global__ void k_glu_bar(const T* __restrict__ ug, const T* __restrict__ tbar, T* __restrict__ ugbar, int64_t nrows,
@@ -827,6 +852,7 @@ struct GradLayout {
   int Wc;
   size_t nidx, ncnt, y, ug, t, hk, zk, basis, o[2], obar[2], hbar, hbar2, zbar, h0bar, projbar, tbar, ugbar;
   size_t ybar, sbar, bbar, trA, trB, split, epart;
+  size_t jm[7];   // MLP Jastrow: a1, z1, a2, z2, a2bar, z1bar/a1bar [rows][Hj]; readout bars [rows]
   size_t total;
 };
 
@@ -840,7 +866,8 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   if (KNmax > widest) widest = KNmax;
   if (D.B > widest) widest = D.B;
   const size_t per_walker = (size_t)D.n * ts *
-                            ((size_t)20 * D.d + 2 * (size_t)D.L * D.d + 2 * (size_t)D.B + 3 * (size_t)KNmax + 2 * widest);
+                            ((size_t)20 * D.d + 2 * (size_t)D.L * D.d + 2 * (size_t)D.B + 3 * (size_t)KNmax + 2 * widest +
+                             (D.Hj > 0 ? (size_t)6 * D.Hj + 1 : 0));
   const size_t budget = (size_t)24 << 30;
   int wc = (int)(budget / per_walker);
   if (wc < 1) wc = 1;
@@ -878,6 +905,7 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   const size_t ep = (size_t)GBLK * ((size_t)msg_part_size(D) > (size_t)2 * D.d ? (size_t)msg_part_size(D) : 2 * D.d);
   const size_t enp = (size_t)GBLK * ((D.M + ENCH - 1) / ENCH) * en_off(D).size;
   L.epart = take((ep > enp ? ep : enp) * ts);
+  for (int k = 0; k < 7; ++k) L.jm[k] = D.Hj > 0 ? take(R * (k < 6 ? D.Hj : 1) * ts) : 0;
   L.total = o;
   return L;
 }
@@ -1034,6 +1062,61 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
     hipLaunchKernelGGL(k_reduce_splits<T>, dim3((D.B + 255) / 256), dim3(256), 0, st, (const T*)part, GNS, 1, D.B,
                        grad, th("env_sigma"), (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
     CHECK(hipGetLastError());
+  }
+  // ---- MLP Jastrow backward: hbar += sum_k a1bar_k W1_k^T, with the
+  // weight gradients of both readout MLPs
+  if (D.Hj > 0) {
+    const int Hj = D.Hj;
+    T* a1 = (T*)(ws + L.jm[0]);
+    T* z1 = (T*)(ws + L.jm[1]);
+    T* a2 = (T*)(ws + L.jm[2]);
+    T* z2 = (T*)(ws + L.jm[3]);
+    T* a2b = (T*)(ws + L.jm[4]);
+    T* z1b = (T*)(ws + L.jm[5]);
+    T* gcol = (T*)(ws + L.jm[6]);
+    const int64_t nq = rows * Hj;
+    const unsigned gq = (unsigned)((nq + 255) / 256);
+    for (int k = 0; k < 2; ++k) {
+      const char* W1k = (const char*)P.jm_W1t + (size_t)k * Hj * d * h->gsize;
+      const char* W2k = (const char*)P.jm_W2t + (size_t)k * Hj * Hj * h->gsize;
+      GemmArgs g1{};
+      g1.A = hL; g1.amap = rows_dense(d); g1.Bt = W1k; g1.ldb = d; g1.bias = P.jm_b1 + (int64_t)k * Hj;
+      g1.C = a1; g1.cmap = rows_dense(Hj); g1.ccol = cols_dense(); g1.M = (int)rows; g1.N = Hj; g1.K = d;
+      CHECK(gemm_site(h, SITE_EMB, g1, st));
+      hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, z1, nq);
+      CHECK(hipGetLastError());
+      GemmArgs g2{};
+      g2.A = z1; g2.amap = rows_dense(Hj); g2.Bt = W2k; g2.ldb = Hj; g2.bias = P.jm_b2 + (int64_t)k * Hj;
+      g2.C = a2; g2.cmap = rows_dense(Hj); g2.ccol = cols_dense(); g2.M = (int)rows; g2.N = Hj; g2.K = Hj;
+      CHECK(gemm_site(h, SITE_EMB, g2, st));
+      hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a2, z2, nq);
+      CHECK(hipGetLastError());
+      // z2 is not needed after this: it takes the readout-weight terms g z2
+      hipLaunchKernelGGL(k_jm_readout_bar<T>, dim3(gq), dim3(256), 0, st, rows, n, w0, Hj, k, (const char*)state, S,
+                         coeff, P.jm_w3 + (int64_t)k * Hj, (const T*)a2, (const T*)z2, a2b, z2, gcol);
+      CHECK(hipGetLastError());
+      CHECK(bgrad<T>(L, ws, z2, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_w3") + (int64_t)k * Hj, st));
+      CHECK(bgrad<T>(L, ws, gcol, rows_dense(1), (int)rows, 1, grad, th("jmlp_b3") + k, st));
+      CHECK(wgrad<T>(h, L, ws, z1, rows_dense(Hj), (int)rows, Hj, a2b, rows_dense(Hj), Hj, grad,
+                     th("jmlp_W2") + (int64_t)k * Hj * Hj, Hj, (int64_t)1 << 40, 0, 1, st));
+      CHECK(bgrad<T>(L, ws, a2b, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_b2") + (int64_t)k * Hj, st));
+      // z1bar = a2bar W2_k^T, then a1bar = z1bar SiLU'(a1) (into a2, free now)
+      GemmArgs b2{};
+      b2.A = a2b; b2.amap = rows_dense(Hj); b2.Bt = (const char*)P.jm_W2n + (size_t)k * Hj * Hj * h->gsize;
+      b2.ldb = Hj; b2.C = z1b; b2.cmap = rows_dense(Hj); b2.ccol = cols_dense(); b2.M = (int)rows; b2.N = Hj;
+      b2.K = Hj;
+      CHECK(gemm_site(h, SITE_GRAD, b2, st));
+      hipLaunchKernelGGL(k_silu_bar<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, (const T*)z1b, a2, nq);
+      CHECK(hipGetLastError());
+      CHECK(wgrad<T>(h, L, ws, hL, rows_dense(d), (int)rows, d, a2, rows_dense(Hj), Hj, grad,
+                     th("jmlp_W1") + (int64_t)k * d * Hj, Hj, (int64_t)1 << 40, 0, 1, st));
+      CHECK(bgrad<T>(L, ws, a2, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_b1") + (int64_t)k * Hj, st));
+      GemmArgs b1{};
+      b1.A = a2; b1.amap = rows_dense(Hj); b1.Bt = (const char*)P.jm_W1n + (size_t)k * d * Hj * h->gsize;
+      b1.ldb = Hj; b1.C = hbar; b1.cmap = rows_dense(d); b1.ccol = cols_dense(); b1.M = (int)rows; b1.N = d;
+      b1.K = Hj; b1.accumulate = 1;
+      CHECK(gemm_site(h, SITE_GRAD, b1, st));
+    }
   }
   // ---- MLP backward
   T* hb_cur = hbar;

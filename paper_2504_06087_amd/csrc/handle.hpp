@@ -35,6 +35,9 @@ struct ParamsLayout {
   size_t Wvg_t, Wo_t, Wproj_t, mlp_t, orb_t0, orb_t1, pi0, pi1;
   // GEMM operands in the adjoint orientation (B = W^T): Bt = W, type G
   size_t Wvg_n, Wo_n, Wproj_n, mlp_n, orb_n0, orb_n1, pi_n0, pi_n1;
+  // MLP Jastrow: small arrays in T, GEMM operands in G (inside the region
+  // that has low bf16 parts)
+  size_t jm_b1, jm_b2, jm_w3, jm_b3, jm_W1t, jm_W2t, jm_W1n, jm_W2n;
   // low bf16 parts of every GEMM operand above live at (offset + lo_delta)
   size_t lo_delta;
   // molecule
@@ -46,9 +49,12 @@ struct ParamsLayout {
 
 // Per-walker record of cached intermediates (byte offsets within a record).
 struct StateRec {
-  // lpsi: log|sum_d det_d| (determinants only); jas: log J_cusp, so that
-  // log|psi| = lpsi + jas
-  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi, jas;
+  // lpsi: log|sum_d det_d| (determinants only); jas: log of the Jastrow
+  // magnitude, log J_cusp + log|J_MLP|, so that log|psi| = lpsi + jas.
+  // With the MLP Jastrow: jme [n][2] per-electron readouts MLP_1(h_i),
+  // MLP_2(h_i) and jms [2] their sums S_1, S_2 (FP64); sign(psi) =
+  // spsi * sign(S_2)
+  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi, jas, jme, jms;
   size_t stride;
 };
 
@@ -90,6 +96,7 @@ namespace fire {
 // Workspace regions for a batch of W walkers (byte offsets).
 struct WsLayout {
   size_t nbr_idx, nbr_cnt, y, ug, hA, hB, basis;
+  size_t jrow, jscr;   // MLP Jastrow readouts [W n][2] (FP64) and their scratch
   size_t total;
 };
 WsLayout ws_forward(const fire_handle* h, int W);

@@ -12,6 +12,7 @@
 // logdet_lowrank):  d_{nx} log det = sum_i M_ii,  Lap log det =
 //   sum_il LapPhi_il Phi^-1_li - sum_{n,x} sum_{i,k in T_n} M_ik M_ki.
 #include "laplacian.hpp"
+#include "jastrow.hpp"
 
 #include "embed_kernels.hpp"
 #include "jets.hpp"
@@ -31,7 +32,10 @@ LapLayout lap_layout(const fire_handle* h, int W) {
   const size_t ts = h->tsize;
   const int nmax = D.nu > D.nd ? D.nu : D.nd;
   const size_t per_walker = (size_t)D.n * jet_rows_max(D) * ((size_t)2 * D.d + (size_t)D.K * nmax) * ts +
-                            (size_t)D.n * 5 * ((size_t)8 * D.d + D.B + (size_t)D.K * nmax) * ts;
+                            (size_t)D.n * 5 * ((size_t)8 * D.d + D.B + (size_t)D.K * nmax) * ts +
+                            (D.Hj > 0 ? (size_t)D.n * jet_rows_max(D) * (2 * D.Hj * ts + 16) +
+                                            (size_t)D.n * (2 * D.Hj * ts + 24)
+                                      : 0);
   const size_t budget = h->lap_budget;
   int wc = (int)(budget / (per_walker > 0 ? per_walker : 1));
   if (wc < 1) wc = 1;
@@ -67,6 +71,16 @@ LapLayout lap_layout(const fire_handle* h, int W) {
   L.memb = take(Wl * n * 2 * L.tcap * 4);
   L.mslot = take(Wl * n * 2 * L.tcap * 4);
   L.mcnt = take(Wl * n * 2 * 4);
+  if (D.Hj > 0) {
+    L.jzv = take(2 * Wl * n * D.Hj * ts);
+    for (int s = 0; s < 2; ++s) {
+      L.jjx[s] = take(L.rowcap[s] * D.Hj * ts);
+      L.jjy[s] = take(L.rowcap[s] * D.Hj * ts);
+      L.jjt[s] = take(L.rowcap[s] * 2 * 8);
+    }
+    L.jgJ = take(Wl * n * 3 * 8);
+    L.jlap = take(Wl * 8);
+  }
   L.total = o;
   return L;
 }
@@ -571,7 +585,8 @@ __global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, c
 __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, const char* __restrict__ state,
                                                  StateRec S, const double* __restrict__ gd,
                                                  const double* __restrict__ hd, const double* __restrict__ R,
-                                                 const double* __restrict__ jasq, double* __restrict__ kin,
+                                                 const double* __restrict__ jasq, const double* __restrict__ gJ,
+                                                 const double* __restrict__ lapJ, double* __restrict__ kin,
                                                  double* __restrict__ grad) {
   __shared__ double red[16];
   __shared__ double wd[32];
@@ -604,6 +619,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
       jas_u3(jasq, (i < D.nu) == (j < D.nu), r, u, u1, u2);
       gj += u1 * (Rw[3 * i + c] - Rw[3 * j + c]) / r;
     }
+    if (gJ) gj += gJ[(int64_t)wl * 3 * n + q];
     acc += 2.0 * gj * g + gj * gj;
     if (grad) grad[w * 3 * n + q] = g + gj;
   }
@@ -620,6 +636,7 @@ __global__ __launch_bounds__(256) void k_kinetic(const Dims D, int Wc, int w0, c
     }
     acc += lj;
   }
+  if (lapJ && tid == 0) acc += lapJ[wl];
   const double tot = block_sum<double>(acc, red);
   if (tid == 0) kin[w] = -0.5 * tot;
 }
@@ -803,8 +820,27 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
                          (const int*)mslot, (const int*)mcnt, L.tcap, (const int32_t*)ncnt, (const int*)joff,
                          (const T*)dph[0], (const T*)dph[1], (const char*)state, S, gd, hd);
     CHECK(hipGetLastError());
+    // MLP Jastrow: its gradient and Laplacian from the jets of h_i (jin
+    // and the member lists are still intact; jout is free)
+    double* gJ = nullptr;
+    double* lapJ = nullptr;
+    if (D.Hj > 0) {
+      JmJetArgs a{};
+      a.Wc = Wc; a.w0 = w0; a.rowcap[0] = L.rowcap[0]; a.rowcap[1] = L.rowcap[1];
+      a.ncnt = ncnt; a.joff = joff; a.jtot = jtot; a.memb = memb; a.mslot = mslot; a.mcnt = mcnt; a.tcap = L.tcap;
+      a.hval = hval; a.jin[0] = jin[0]; a.jin[1] = jin[1]; a.zv = ws + L.jzv;
+      for (int s = 0; s < 2; ++s) {
+        a.jx[s] = ws + L.jjx[s];
+        a.jy[s] = ws + L.jjy[s];
+        a.jt[s] = (double*)(ws + L.jjt[s]);
+      }
+      gJ = (double*)(ws + L.jgJ);
+      lapJ = (double*)(ws + L.jlap);
+      a.gJ = gJ; a.lapJ = lapJ;
+      CHECK(jm_kinetic<T>(h, P, a, (const char*)state, st));
+    }
     hipLaunchKernelGGL(k_kinetic, dim3(Wc), dim3(256), 0, st, D, Wc, w0, (const char*)state, S, (const double*)gd,
-                       (const double*)hd, R, P.jas, kin, grad);
+                       (const double*)hd, R, P.jas, (const double*)gJ, (const double*)lapJ, kin, grad);
     CHECK(hipGetLastError());
   }
   return hipSuccess;

@@ -11,6 +11,9 @@ struct LapLayout {
   size_t jetA[2], jetB[2], envj[2], oval[2], dphi[2], gd, hd;
   int tcap;                      // capacity of the T_n member lists per spin
   size_t memb, mslot, mcnt;
+  // MLP Jastrow jets (D.Hj > 0): values [2][rows][Hj], jet rows [rowcap][Hj]
+  // twice per spin, readout rows [rowcap][2] (FP64), grad [Wc][n][3], Lap [Wc]
+  size_t jzv, jjx[2], jjy[2], jjt[2], jgJ, jlap;
   size_t total;
 };
 LapLayout lap_layout(const fire_handle* h, int W);

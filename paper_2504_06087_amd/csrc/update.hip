@@ -10,6 +10,7 @@
 // update G by the Woodbury identity in one read-modify-write pass:
 //   G' = G - (G dPhi_U^T) A^-T G_U.
 #include "update.hpp"
+#include "jastrow.hpp"
 #include "rng.hpp"
 
 #include "embed_kernels.hpp"
@@ -58,6 +59,12 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
     // form them on the fly
     L.dphi[s] = with_woodbury ? take(rows * D.K * N * ts) : 0;
     L.bbuf[s] = with_woodbury ? take(rows * D.K * N * 8) : 0;
+    L.jnew[s] = D.Hj > 0 ? take(rows * 2 * 8) : 0;
+  }
+  if (D.Hj > 0) {
+    L.jsum = take(Wl * 2 * 8);
+    L.jsg = take(Wl * 8);
+    L.jscr = take(jm_rows_ws(h, L.rowcap[0] > L.rowcap[1] ? L.rowcap[0] : L.rowcap[1]));
   }
   L.total = o;
   return L;
@@ -1548,7 +1555,8 @@ __global__ void k_final_outputs(const Dims D, int W, const char* __restrict__ st
   const char* rec = state + (int64_t)w * S.stride;
   const bool bad = status[w] != 0;
   if (logpsi) logpsi[w] = bad ? NAN : *(const double*)(rec + S.lpsi) + *(const double*)(rec + S.jas);
-  if (sign) sign[w] = bad ? 0.0 : *(const double*)(rec + S.spsi);
+  const double sp = *(const double*)(rec + S.spsi);
+  if (sign) sign[w] = bad ? 0.0 : (D.Hj > 0 && ((const double*)(rec + S.jms))[1] < 0.0 ? -sp : sp);
 }
 
 __global__ void k_unit_detA(int nwd, int s, double* detA) {
@@ -1656,6 +1664,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
       CHECK(gemm_site(h, SITE_EMB, g, st));
       T* t = hin; hin = hout; hout = t;
     }
+    if (D.Hj > 0) CHECK(jm_rows<T>(h, P, hin, rows, Mdev, ws + L.jscr, (double*)(ws + L.jnew[s]), st));
     T* oseg = (T*)(ws + L.oseg[s]);
     GemmArgs o{};
     o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
@@ -1714,6 +1723,10 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
                          (double*)(ws + L.detA));
       CHECK(hipGetLastError());
     }
+  // the change of log|J_MLP| joins the cusp factor's change in dj
+  CHECK(jm_delta(h, W, jb.jw, uidx, L.capmax, ucnt, off, (const double*)(ws + L.jnew[0]),
+                 (const double*)(ws + L.jnew[1]), state, (double*)(ws + L.dj), (double*)(ws + L.jsg),
+                 (double*)(ws + L.jsum), st));
   return hipSuccess;
 }
 
@@ -1798,7 +1811,10 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
                      L.capmax, (const int*)(ws + L.ucnt), (const int*)(ws + L.off), (const T*)(ws + L.h0new),
                      (const T*)(ws + L.projnew), (const T*)(ws + L.mseg[0]), (const T*)(ws + L.mseg[1]),
                      (const T*)(ws + L.envnew), state, S);
-  return hipGetLastError();
+  CHECK(hipGetLastError());
+  return jm_commit(h, W, acc, (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt),
+                   (const int*)(ws + L.off), (const double*)(ws + L.jnew[0]), (const double*)(ws + L.jnew[1]),
+                   (const double*)(ws + L.jsum), state, st);
 }
 
 // The random numbers of one sweep from the counter-based generator:
@@ -2099,8 +2115,9 @@ __global__ __launch_bounds__(256) void k_msg_swap(Net<T> P, int W, int ea, int e
 // ratio[w][a] = e^{dJ} sum_d w_d prod_s det A_ds with w_d the determinant's
 // share of the sum (as a pseudopotential ratio, one job per walker)
 __global__ void k_swap_ratio(const Dims D, int W, int ea, const double* __restrict__ detA,
-                             const double* __restrict__ dj, const char* __restrict__ state, StateRec S,
-                             const int32_t* __restrict__ status, double* __restrict__ ratios) {
+                             const double* __restrict__ dj, const double* __restrict__ jsg,
+                             const char* __restrict__ state, StateRec S, const int32_t* __restrict__ status,
+                             double* __restrict__ ratios) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= W) return;
   const char* rec = state + (int64_t)j * S.stride;
@@ -2113,7 +2130,7 @@ __global__ void k_swap_ratio(const Dims D, int W, int ea, const double* __restri
     const double sg = ds[2 * k] * ds[2 * k + 1] * sp * dA[4 * k] * dA[4 * k + 2];
     if (sg != 0.0) r += sg * exp(dl[2 * k] + dl[2 * k + 1] - lp + dA[4 * k + 1] + dA[4 * k + 3]);
   }
-  ratios[(int64_t)j * D.nu + ea] = status[j] ? NAN : r * exp(dj[j]);
+  ratios[(int64_t)j * D.nu + ea] = status[j] ? NAN : r * exp(dj[j]) * (jsg ? jsg[j] : 1.0);
 }
 
 // R_b[w] = 1 - sum_a ratio[w][a]
@@ -2195,6 +2212,7 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
       CHECK(gemm_site(h, SITE_EMB, g, st));
       T* t = hin; hin = hout; hout = t;
     }
+    if (D.Hj > 0) CHECK(jm_rows<T>(h, P, hin, rows, Mdev, ws + L.jscr, (double*)(ws + L.jnew[s]), st));
     T* oseg = (T*)(ws + L.oseg[s]);
     GemmArgs o{};
     o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
@@ -2235,8 +2253,12 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
       CHECK(hipGetLastError());
     }
   }
+  CHECK(jm_delta(h, W, (const int*)nullptr, uidx, L.capmax, ucnt, off, (const double*)(ws + L.jnew[0]),
+                 (const double*)(ws + L.jnew[1]), state, (double*)(ws + L.dj), (double*)(ws + L.jsg),
+                 (double*)(ws + L.jsum), st));
   hipLaunchKernelGGL(k_swap_ratio, dim3((W + 127) / 128), dim3(128), 0, st, D, W, ea, (const double*)(ws + L.detA),
-                     (const double*)(ws + L.dj), (const char*)state, S, (const int32_t*)status, ratios);
+                     (const double*)(ws + L.dj), D.Hj > 0 ? (const double*)(ws + L.jsg) : (const double*)nullptr,
+                     (const char*)state, S, (const int32_t*)status, ratios);
   return hipGetLastError();
 }
 

@@ -38,6 +38,9 @@ struct UpdLayout {
   int64_t rowcap[2];
   size_t rnew, lqf, dj, uidx, ucnt, off, acc, detA, y, ug, h0new, projnew, basis, envnew;
   size_t rowinfo[2], hseg[2][2], mseg[2], oseg[2], dphi[2], bbuf[2];
+  // MLP Jastrow (D.Hj > 0): new readouts of the update rows [rowcap[s]][2],
+  // per-job new sums [J][2] and sign changes [J] (FP64), readout scratch
+  size_t jnew[2], jsum, jsg, jscr;
   size_t total;
 };
 // Workspace of J jobs.  Each spin segment holds J * min(capS, kRowsPerJob)

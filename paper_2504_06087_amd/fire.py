@@ -51,7 +51,7 @@ class FireModelDesc(ctypes.Structure):
                 ("edge_h2", ctypes.c_int), ("n_nuc_types", ctypes.c_int), ("cutoff", ctypes.c_double),
                 ("cutoff_nuc", ctypes.c_double), ("precision", ctypes.c_int), ("max_walkers", ctypes.c_int),
                 ("cap_nbr", ctypes.c_int), ("cap_upd", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("bf16_split", ctypes.c_int)]
+                ("bf16_split", ctypes.c_int), ("jas_mlp_width", ctypes.c_int)]
 
 
 class FireParamEntry(ctypes.Structure):
@@ -207,7 +207,8 @@ class Fire:
         md = FireModelDesc(model.width, model.mlp_layers, model.n_det, model.n_env, model.n_gauss,
                            int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
                            float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], int(max_walkers),
-                           self.cap_nbr, self.cap_upd, int(refresh_every), int(bf16_split))
+                           self.cap_nbr, self.cap_upd, int(refresh_every), int(bf16_split),
+                           int(getattr(model, "jas_mlp_width", 0)))
         self.max_walkers = max_walkers
         hd = ctypes.c_void_p()
         _check(lib.fire_create(ctypes.byref(sd), ctypes.byref(md), ctypes.byref(hd)), "fire_create")
@@ -447,7 +448,8 @@ class FireBatch:
         md = FireModelDesc(model.width, model.mlp_layers, model.n_det, model.n_env, model.n_gauss,
                            int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
                            float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], max(self.W),
-                           int(cap_nbr), int(cap_upd), int(refresh_every), int(bf16_split))
+                           int(cap_nbr), int(cap_upd), int(refresh_every), int(bf16_split),
+                           int(getattr(model, "jas_mlp_width", 0)))
         b = ctypes.c_void_p()
         _check(lib.fire_batch_create(descs, len(self.systems), ctypes.byref(md), ctypes.byref(b)),
                "fire_batch_create")

@@ -73,6 +73,28 @@ def test_create_rejects_unsupported_shapes():
         fire.Fire(w.systems[0], m, "fp64", max_walkers=8, device="cpu")
 
 
+def test_mlp_jastrow_layout_and_width_checks():
+    """The MLP Jastrow's theta entries follow jas_cusp in the generator's
+    order; a width that is not a multiple of 8 or exceeds the embedding
+    width is refused at handle creation."""
+    import copy
+    from paper_2504_06087_amd import fire
+    w = wl.config(0, walkers=2)
+    m = copy.deepcopy(w.model)
+    m.jas_mlp_width = 16
+    F = fire.Fire(w.systems[0], m, "fp64", max_walkers=2, device="cpu")
+    shapes = wl.param_shapes(w.systems[0], m)
+    names = [x[0] for x in F.layout]
+    assert names == list(shapes.keys())
+    k = names.index("jas_cusp")
+    assert names[k + 1:k + 7] == ["jmlp_W1", "jmlp_b1", "jmlp_W2", "jmlp_b2", "jmlp_w3", "jmlp_b3"]
+    assert all(tuple(x[2]) == tuple(shapes[x[0]]) for x in F.layout)
+    for bad in (12, 64, -8):
+        m.jas_mlp_width = bad
+        with pytest.raises(fire.FireError):
+            fire.Fire(w.systems[0], m, "fp64", max_walkers=2, device="cpu")
+
+
 @pytest.mark.parametrize("nq,ok", [(4, True), (6, True), (12, True), (5, False), (8, False)])
 def test_create_checks_the_quadrature_size(nq, ok):
     """fire_ecp_channel.n_quad names the pseudopotential rule of a species:
