@@ -23,8 +23,10 @@ part; the polynomial cutoff with p = 6; separate parallel/antiparallel
 message weights; of the Jastrow terms the cusp factor, exp of a pair sum
 with (w, a) per spin class (zero weights by default), and optionally the
 per-electron MLP factor exp(sum_i MLP_1(h_i)) sum_i MLP_2(h_i) over the final
-embeddings, each MLP two SiLU hidden layers and a scalar linear readout, the
-factors multiplying (their logs add); semilocal l = 0, 1 pseudopotential
+embeddings and the attention factor exp(MLP_1(V)) MLP_2(V) over register
+embeddings V (softmax over the electrons of h_i . q_r weighting h_i W^V_r),
+each MLP two SiLU hidden layers and a scalar linear readout, the factors
+multiplying (their logs add); semilocal l = 0, 1 pseudopotential
 channels with an equal-weight angular rule per species (12-point icosahedron
 unless the system names 4 or 6 points).
 
@@ -224,6 +226,10 @@ class Oracle:
             lj, sj = self.jastrow_mlp(h)
             logpsi = logpsi + lj
             sign = sign * sj
+        if "jatt_q" in self.p:
+            la, sa = self.jastrow_att(h)
+            logpsi = logpsi + la
+            sign = sign * sa
         return sign, logpsi, sgn, ld, phis
 
     def jastrow_cusp(self, R):
@@ -264,9 +270,35 @@ class Oracle:
         s1, s2 = t[..., 0].sum(1), t[..., 1].sum(1)
         return s1 + torch.log(torch.abs(s2)), torch.sign(s2)
 
+    def jastrow_att_registers(self, h):
+        """Register embeddings of the attention Jastrow (Methods, global
+        electron correlation): for register r, the softmax over the electrons
+        of the logits h_i . q_r weights the values h_i W^V_r; returns
+        V = Concat_r v_r [B, N_reg d_reg]."""
+        p = self.p
+        logits = torch.einsum("bnd,rd->bnr", h, p["jatt_q"])
+        w = torch.softmax(logits, dim=1)                           # over electrons
+        vals = torch.einsum("bnd,rde->bnre", h, p["jatt_Wv"])
+        v = torch.einsum("bnr,bnre->bre", w, vals)
+        return v.reshape(h.shape[0], -1)
+
+    def jastrow_att(self, h):
+        """(log|J_att|, sign J_att) with J_att = exp(MLP_1(V)) MLP_2(V) over the
+        register embeddings V, each MLP two SiLU hidden layers and a scalar
+        linear readout."""
+        p = self.p
+        V = self.jastrow_att_registers(h)
+        out = []
+        for k in (0, 1):
+            z = silu(V @ p["jatt_W1"][k] + p["jatt_b1"][k])
+            z = silu(z @ p["jatt_W2"][k] + p["jatt_b2"][k])
+            out.append(z @ p["jatt_w3"][k] + p["jatt_b3"][k])
+        return out[0] + torch.log(torch.abs(out[1])), torch.sign(out[1])
+
     def log_psi(self, R):
-        """(sign, log|psi|) for walkers R [B,n,3], psi = exp(J_cusp) J_MLP sum_d det Phi_d
-        (J_MLP = 1 unless the parameters hold its weights)."""
+        """(sign, log|psi|) for walkers R [B,n,3], psi = exp(J_cusp) J_MLP J_att
+        sum_d det Phi_d (J_MLP, J_att = 1 unless the parameters hold their
+        weights)."""
         R = torch.as_tensor(R, dtype=DT)
         s, l, *_ = self.log_psi_parts(R)
         return s, l

@@ -856,6 +856,164 @@ def test_jastrow_mlp_theta_gradient_vs_finite_differences():
 
 
 # --------------------------------------------------------------------------
+# attention Jastrow (Methods, global electron correlation: cross attention of
+# register queries over the electron embeddings, exp(MLP_1(V)) MLP_2(V))
+# --------------------------------------------------------------------------
+def _jatt_h4(W=3, regs=4, dr=4, Ha=8, seed=12):
+    s, m, p, R = _orc(0, W=W)
+    m.jas_att_regs, m.jas_att_dim, m.jas_att_width = regs, dr, Ha
+    p = wl.init_params(s, m, np.random.default_rng(seed))
+    m0 = copy.deepcopy(m)
+    m0.jas_att_regs = 0
+    p0 = {k: v for k, v in p.items() if not k.startswith("jatt_")}
+    return s, m, p, m0, p0, R
+
+
+def _single_path_readout(q, rng, width, Ha):
+    """Readouts with one live path each (as in the MLP Jastrow pin): returns
+    the live directions v_k and gains a_k."""
+    v = rng.normal(size=(2, width)) / math.sqrt(width)
+    a = np.array([1.1, -0.7])
+    q["jatt_W1"] = np.zeros((2, width, Ha))
+    q["jatt_W2"] = np.zeros((2, Ha, Ha))
+    for k in (0, 1):
+        q["jatt_W1"][k, :, 0] = v[k]
+        q["jatt_W2"][k, 0, 1] = a[k]
+    q["jatt_b1"] = rng.normal(size=(2, Ha))
+    q["jatt_b2"] = rng.normal(size=(2, Ha))
+    q["jatt_b3"] = np.array([0.3, -0.6])
+    return v, a
+
+
+def _readout_np(q, V, v, a):
+    out = []
+    for k in (0, 1):
+        w3, b1, b2 = q["jatt_w3"][k], q["jatt_b1"][k], q["jatt_b2"][k]
+        live = w3[1] * _silu_np(a[k] * _silu_np(V @ v[k] + b1[0]) + b2[1])
+        dead = float(np.dot(w3, _silu_np(b2))) - w3[1] * _silu_np(b2[1])
+        out.append(live + dead + q["jatt_b3"][k])
+    return out
+
+
+def test_jastrow_att_uniform_attention_closed_form():
+    """Zero queries make every softmax uniform: v_r = mean_i h_i W^V_r, and
+    with single-path readouts log|J_att| = MLP_1(V) + log|MLP_2(V)| follows
+    by hand; the register order (r-major concatenation) and the value-map
+    orientation are fixed by it."""
+    s, m, p, m0, p0, R = _jatt_h4(W=4)
+    rng = np.random.default_rng(4)
+    q = copy.deepcopy(p)
+    q["jatt_q"][:] = 0.0
+    regs, dr = m.jas_att_regs, m.jas_att_dim
+    v, a = _single_path_readout(q, rng, regs * dr, m.jas_att_width)
+    o = Oracle(s, m, q)
+    h = o.embed(torch.as_tensor(R))["h"].numpy()
+    V = np.concatenate([h.mean(1) @ q["jatt_Wv"][r] for r in range(regs)], axis=1)
+    o1, o2 = _readout_np(q, V, v, a)
+    _, l0 = Oracle(s, m0, p0).log_psi(R)
+    s0, _ = Oracle(s, m0, p0).log_psi(R)
+    s1, l1 = o.log_psi(R)
+    assert np.allclose((l1 - l0).numpy(), o1 + np.log(np.abs(o2)), atol=1e-12, rtol=0)
+    assert np.array_equal(s1.numpy(), s0.numpy() * np.sign(o2))
+
+
+def test_jastrow_att_sharp_attention_limit():
+    """Queries scaled by a large factor make each softmax pick the electron
+    with the largest logit h_i . q_r: v_r -> h_{i*} W^V_r."""
+    s, m, p, m0, p0, R = _jatt_h4(W=4)
+    rng = np.random.default_rng(9)
+    q = copy.deepcopy(p)
+    regs, dr = m.jas_att_regs, m.jas_att_dim
+    v, a = _single_path_readout(q, rng, regs * dr, m.jas_att_width)
+    q["jatt_q"] = q["jatt_q"] * 1.0e4
+    o = Oracle(s, m, q)
+    h = o.embed(torch.as_tensor(R))["h"].numpy()
+    lg = np.einsum("bnd,rd->bnr", h, q["jatt_q"])
+    srt = np.sort(lg, axis=1)
+    assert (srt[:, -1] - srt[:, -2]).min() > 40.0        # the runner-up weight is below e^-40
+    top = lg.argmax(1)                                     # [B, regs]
+    V = np.concatenate([h[np.arange(h.shape[0]), top[:, r]] @ q["jatt_Wv"][r] for r in range(regs)], axis=1)
+    Vo = o.jastrow_att_registers(torch.as_tensor(h)).numpy()
+    assert np.allclose(Vo, V, atol=1e-12, rtol=0)
+    o1, o2 = _readout_np(q, V, v, a)
+    _, l0 = Oracle(s, m0, p0).log_psi(R)
+    _, l1 = o.log_psi(R)
+    assert np.allclose((l1 - l0).numpy(), o1 + np.log(np.abs(o2)), atol=1e-10, rtol=0)
+
+
+def test_jastrow_att_weak_attention_slope():
+    """At queries lambda q the register embedding's slope at lambda = 0 is
+    the covariance over the electrons of the logit h_i . q_r and the value
+    h_i W^V_r (the first-order expansion of the softmax about uniform
+    weights): dv_r/dlambda = mean_i (l_ri - mean l_r) u_ri."""
+    s, m, p, m0, p0, R = _jatt_h4(W=3)
+    o = Oracle(s, m, p)
+    h = o.embed(torch.as_tensor(R))["h"]
+    qhat = p["jatt_q"].copy()
+    regs = m.jas_att_regs
+    lam = 1e-4
+    Vs = []
+    for t in (lam, -lam):
+        o.p["jatt_q"] = torch.as_tensor(t * qhat)
+        Vs.append(o.jastrow_att_registers(h).numpy())
+    slope = (Vs[0] - Vs[1]) / (2 * lam)
+    hn = h.numpy()
+    want = []
+    for r in range(regs):
+        lg = hn @ qhat[r]                                   # [B, n]
+        u = hn @ p["jatt_Wv"][r]                            # [B, n, dr]
+        want.append(((lg - lg.mean(1, keepdims=True))[..., None] * u).mean(1))
+    want = np.concatenate(want, axis=1)
+    assert np.abs(slope - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
+
+
+def test_jastrow_att_gradient_and_laplacian_vs_finite_differences():
+    s, m, p, m0, p0, R = _jatt_h4(W=2)
+    o = Oracle(s, m, p)
+    g, lap = o.grad_lap(R)
+    h = 1e-3
+    for w in range(2):
+        x0 = R[w].copy()
+        f = lambda x: float(o.log_psi(x[None])[1][0])
+        l0 = f(x0)
+        fd_lap, fd_g = 0.0, np.zeros_like(x0)
+        for i in range(s.n_el):
+            for k in range(3):
+                vals = {}
+                for st in (-2, -1, 1, 2):
+                    x = x0.copy()
+                    x[i, k] += st * h
+                    vals[st] = f(x)
+                fd_g[i, k] = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * h)
+                fd_lap += (-vals[2] + 16 * vals[1] - 30 * l0 + 16 * vals[-1] - vals[-2]) / (12 * h * h)
+        assert np.allclose(g[w].numpy(), fd_g, atol=1e-7 * max(1.0, np.abs(fd_g).max()))
+        assert abs(float(lap[w]) - fd_lap) < 1e-6 * max(1.0, abs(fd_lap))
+
+
+def test_jastrow_att_theta_gradient_vs_finite_differences():
+    s, m, p, m0, p0, R = _jatt_h4(W=3)
+    o = Oracle(s, m, p)
+    coeff = np.array([0.7, -1.3, 0.4])
+    g = o.grad_params(R, coeff)
+    names = [k for k in p if k.startswith("jatt_")] + ["mlp_W"]
+    rng = np.random.default_rng(6)
+    for _ in range(4):
+        dirs = {k: rng.normal(size=p[k].shape) for k in names}
+        nrm = math.sqrt(sum((v ** 2).sum() for v in dirs.values()))
+        dirs = {k: v / nrm for k, v in dirs.items()}
+        hh = 1e-5
+
+        def val(t):
+            q = dict(p)
+            for k in names:
+                q[k] = p[k] + t * dirs[k]
+            return float((Oracle(s, m, q).log_psi(R)[1].numpy() * coeff).sum())
+        fd = (8 * (val(hh) - val(-hh)) - (val(2 * hh) - val(-2 * hh))) / (12 * hh)
+        an = sum(float((g[k].numpy() * dirs[k]).sum()) for k in names)
+        assert abs(fd - an) < 1e-8 * max(1.0, abs(an))
+
+
+# --------------------------------------------------------------------------
 # the counter-based generator of the sampler's own random numbers
 # --------------------------------------------------------------------------
 def test_philox_known_answer_vectors():

@@ -99,6 +99,9 @@ class Model:
     n_nuc_types: int = 0        # rows of per-nucleus tables
     env_sigma_fixed: Optional[float] = None  # C1: a single exp(-|r-R|)
     jas_mlp_width: int = 0      # hidden width of the per-electron MLP Jastrow (0: off)
+    jas_att_regs: int = 0       # registers of the attention Jastrow (0: off)
+    jas_att_dim: int = 16       # register dimension d_reg
+    jas_att_width: int = 0      # hidden width of its readout MLPs
 
 
 # ----------------------------------------------------------------------------
@@ -319,6 +322,13 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
         "jmlp_W1": (2, d, Hj), "jmlp_b1": (2, Hj), "jmlp_W2": (2, Hj, Hj), "jmlp_b2": (2, Hj),
         "jmlp_w3": (2, Hj), "jmlp_b3": (2,),
     }
+    Ra, dr, Ha = model.jas_att_regs, model.jas_att_dim, model.jas_att_width
+    ja = {} if Ra <= 0 else {
+        # attention Jastrow: queries, value maps, readouts 0 (log part), 1 (node part)
+        "jatt_q": (Ra, d), "jatt_Wv": (Ra, d, dr),
+        "jatt_W1": (2, Ra * dr, Ha), "jatt_b1": (2, Ha), "jatt_W2": (2, Ha, Ha), "jatt_b2": (2, Ha),
+        "jatt_w3": (2, Ha), "jatt_b3": (2,),
+    }
     return {
         # electron-nucleus filter Gamma_m and nuclear embeddings
         "en_W1": (T, 4, h1), "en_b1": (T, h1),
@@ -338,6 +348,7 @@ def param_shapes(system: System, model: Model) -> Dict[str, tuple]:
         # cusp Jastrow (w_par, a_par, w_anti, a_anti)
         "jas_cusp": (4,),
         **jm,
+        **ja,
         # orbitals and envelopes
         "orb_W_up": (K, d, nu), "orb_W_dn": (K, d, nd),
         "env_pi_up": (K, nu, M, E), "env_pi_dn": (K, nd, M, E),
@@ -349,7 +360,8 @@ def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
     """Matrices N(0, 1/fan_in), biases 0, LayerNorm (1, 0), nuclear
     embeddings N(0,1), envelope weights N(0, 1/(M*N_env)), envelope exponents
     linspace(0.5, 3), Gaussian filter widths (1 + 7k/(G-1))/cutoff; the MLP
-    Jastrow's readout vectors N(0, 1/width) and readout biases (0, 1)."""
+    and attention Jastrows' readout vectors N(0, 1/width) and readout biases
+    (0, 1); attention queries N(0, 1/d)."""
     shapes = param_shapes(system, model)
     p: Dict[str, np.ndarray] = {}
     G = model.n_gauss
@@ -369,13 +381,13 @@ def init_params(system: System, model: Model, rng) -> Dict[str, np.ndarray]:
             # zero weights by default: J_cusp = 1; (-1/4, a, -1/2, a)
             # gives the electron-electron cusp conditions
             p[name] = np.array([0.0, 1.0, 0.0, 1.0])
-        elif name == "jmlp_w3":
+        elif name in ("jmlp_w3", "jatt_w3", "jatt_q"):
             p[name] = rng.normal(0.0, 1.0 / math.sqrt(shp[-1]), size=shp)
-        elif name == "jmlp_b3":
+        elif name in ("jmlp_b3", "jatt_b3"):
             # MLP_1 bias 0; MLP_2 bias 1, so that sum_i MLP_2(h_i) starts near
             # n, away from its zero set
             p[name] = np.array([0.0, 1.0])
-        elif name == "jmlp_b2":
+        elif name in ("jmlp_b2", "jatt_b2"):
             p[name] = np.zeros(shp)
         elif name == "nuc_emb":
             p[name] = rng.normal(0.0, 1.0, size=shp)
