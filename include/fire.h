@@ -121,6 +121,20 @@ typedef struct {
                          jmlp_W2 [2][w][w], jmlp_b2 [2][w], jmlp_w3 [2][w],
                          jmlp_b3 [2] after jas_cusp (index 0: MLP_1, 1: MLP_2).
                          sum_i MLP_2(h_i) = 0 makes psi = 0 (FIRE_W_DETSUM_ZERO). */
+  int jas_att_regs;   /* attention-register Jastrow (Methods, global electron
+                         correlation): N_reg registers; for register r the
+                         softmax over the electrons of h_i . q_r weights the
+                         values h_i W^V_r (d_reg wide), V = Concat_r v_r, and
+                         J_att = exp(MLP_1(V)) MLP_2(V), each readout MLP two
+                         SiLU hidden layers of jas_att_width and a scalar
+                         linear readout.  0: off; else <= 64.  Adds theta
+                         entries jatt_q [N_reg][d], jatt_Wv [N_reg][d][d_reg],
+                         jatt_W1 [2][N_reg d_reg][w], jatt_b1 [2][w],
+                         jatt_W2 [2][w][w], jatt_b2 [2][w], jatt_w3 [2][w],
+                         jatt_b3 [2] after the MLP Jastrow's.  MLP_2(V) = 0
+                         makes psi = 0 (FIRE_W_DETSUM_ZERO). */
+  int jas_att_dim;    /* d_reg (<= 64; N_reg d_reg a multiple of 8, <= 1024) */
+  int jas_att_width;  /* readout width w: a multiple of 8, 8..256 */
 } fire_model_desc;
 
 typedef struct fire_handle fire_handle;

@@ -94,6 +94,18 @@ static void build_theta(fire_handle* h) {
         {"jmlp_b2", {2, w}},      {"jmlp_w3", {2, w}}, {"jmlp_b3", {2}}};
     e.insert(e.begin() + (at + 1), jm.begin(), jm.end());
   }
+  if (D.Ra > 0) {
+    // attention Jastrow entries follow the MLP Jastrow's (or the cusp's)
+    size_t at = 0;
+    const char* after = D.Hj > 0 ? "jmlp_b3" : "jas_cusp";
+    while (at < e.size() && e[at].first != after) ++at;
+    const int w = D.Ha;
+    std::vector<std::pair<std::string, std::vector<int>>> ja = {
+        {"jatt_q", {D.Ra, D.d}},        {"jatt_Wv", {D.Ra, D.d, D.dr}}, {"jatt_W1", {2, D.NV(), w}},
+        {"jatt_b1", {2, w}},             {"jatt_W2", {2, w, w}},         {"jatt_b2", {2, w}},
+        {"jatt_w3", {2, w}},             {"jatt_b3", {2}}};
+    e.insert(e.begin() + (at + 1), ja.begin(), ja.end());
+  }
   int64_t off = 0;
   h->theta.clear();
   for (auto& x : e) {
@@ -137,6 +149,9 @@ static void build_layouts(fire_handle* h) {
   L.pi_n0 = take((size_t)D.K * D.nu * D.B * G); L.pi_n1 = take((size_t)D.K * D.nd * D.B * G);
   L.jm_W1t = take((size_t)2 * D.Hj * D.d * G); L.jm_W2t = take((size_t)2 * D.Hj * D.Hj * G);
   L.jm_W1n = take((size_t)2 * D.Hj * D.d * G); L.jm_W2n = take((size_t)2 * D.Hj * D.Hj * G);
+  L.ja_Pt = take((size_t)D.NA() * D.d * G); L.ja_Pn = take((size_t)D.NA() * D.d * G);
+  L.ja_W1t = take((size_t)2 * D.Ha * D.NV() * G); L.ja_W2t = take((size_t)2 * D.Ha * D.Ha * G);
+  L.ja_W1n = take((size_t)2 * D.Ha * D.NV() * G); L.ja_W2n = take((size_t)2 * D.Ha * D.Ha * G);
   if (D.prec == FIRE_BF16_HYBRID) {
     const size_t region = o - L.Wvg_t;
     L.lo_delta = region;
@@ -151,6 +166,8 @@ static void build_layouts(fire_handle* h) {
   L.jas = take(4 * 8);
   L.jm_b1 = take((size_t)2 * D.Hj * T); L.jm_b2 = take((size_t)2 * D.Hj * T);
   L.jm_w3 = take((size_t)2 * D.Hj * T); L.jm_b3 = take(2 * T);
+  L.ja_b1 = take((size_t)2 * D.Ha * T); L.ja_b2 = take((size_t)2 * D.Ha * T);
+  L.ja_w3 = take((size_t)2 * D.Ha * T); L.ja_b3 = take(2 * T);
   L.total = o;
 
   StateRec& S = h->st;
@@ -169,6 +186,8 @@ static void build_layouts(fire_handle* h) {
   S.jas = take(8);
   S.jme = take(D.Hj > 0 ? (size_t)D.n * 2 * 8 : 0);
   S.jms = take(D.Hj > 0 ? 2 * 8 : 0);
+  S.jae = take(D.Ra > 0 ? (size_t)D.n * D.NA() * T : 0);
+  S.jat = take(D.Ra > 0 ? (size_t)(2 * D.Ra + D.NV() + 2) * 8 : 0);
   S.stride = o;
 }
 
@@ -245,6 +264,13 @@ fire_status fire_create(const fire_system_desc* sys, const fire_model_desc* md, 
   D.split = md->precision == FIRE_BF16_HYBRID ? md->bf16_split : 0;
   D.Hj = md->jas_mlp_width;
   if (D.Hj < 0 || (D.Hj > 0 && (D.Hj % 8 != 0 || D.Hj > md->width))) return FIRE_ERR_SHAPE;
+  D.Ra = md->jas_att_regs;
+  D.dr = D.Ra > 0 ? md->jas_att_dim : 0;
+  D.Ha = D.Ra > 0 ? md->jas_att_width : 0;
+  if (D.Ra < 0 || D.Ra > 64) return FIRE_ERR_SHAPE;
+  if (D.Ra > 0 && (D.dr < 1 || D.dr > 64 || D.NV() % 8 != 0 || D.NV() > 1024 || D.Ha < 8 || D.Ha > 256 ||
+                   D.Ha % 8 != 0))
+    return FIRE_ERR_SHAPE;
   if (D.nu < 0 || D.nd < 0 || D.n < 1 || D.nu > kMaxPerSpin || D.nd > kMaxPerSpin || D.M < 1 || D.M > 4096) return FIRE_ERR_SHAPE;
   if (D.d < 1 || D.d > 256 || D.L < 0 || D.L > 16 || D.K < 1 || D.K > 32 || D.E < 1) return FIRE_ERR_SHAPE;
   if (md->n_gauss != kMaxG || md->edge_h1 != kMaxH1 || md->edge_h2 != kMaxH2) return FIRE_ERR_SHAPE;
@@ -388,6 +414,22 @@ fire_status fire::set_params_split(fire_handle* h, const double* shared, const d
     // adjoint: W1n[k][i][c] = W1[k][i][c], W2n[k][i][c] = W2[k][i][c]
     DO(do_copy(G, b + L.jm_W1n, src("jmlp_W1"), plain((int64_t)2 * D.d * w), s, LD0));
     DO(do_copy(G, b + L.jm_W2n, src("jmlp_W2"), plain((int64_t)2 * w * w), s, LD0));
+  }
+  if (D.Ra > 0) {
+    const int w = D.Ha, NA = D.NA(), NV = D.NV();
+    const size_t LD0 = L.lo_delta;
+    DO(cp(L.ja_b1, "jatt_b1")); DO(cp(L.ja_b2, "jatt_b2")); DO(cp(L.ja_w3, "jatt_w3")); DO(cp(L.ja_b3, "jatt_b3"));
+    // Pt[r][c] = q[r][c];  Pt[Ra + r dr + e][c] = Wv[r][c][e]
+    DO(do_copy(G, b + L.ja_Pt, src("jatt_q"), plain((int64_t)D.Ra * D.d), s, LD0));
+    DO(do_copy(G, b + L.ja_Pt + (size_t)D.Ra * D.d * G, src("jatt_Wv"), transposed(D.Ra, D.d, D.dr), s, LD0));
+    // Pn[c][r] = q[r][c];  Pn[c][Ra + r dr + e] = Wv[r][c][e]
+    DO(do_copy(G, b + L.ja_Pn, src("jatt_q"), Copy{1, D.Ra, D.d, 0, D.d, 1, 0, 1, NA}, s, LD0));
+    DO(do_copy(G, b + L.ja_Pn + (size_t)D.Ra * G, src("jatt_Wv"),
+               Copy{D.Ra, D.d, D.dr, (int64_t)D.d * D.dr, D.dr, 1, D.dr, NA, 1}, s, LD0));
+    DO(do_copy(G, b + L.ja_W1t, src("jatt_W1"), transposed(2, NV, w), s, LD0));
+    DO(do_copy(G, b + L.ja_W2t, src("jatt_W2"), transposed(2, w, w), s, LD0));
+    DO(do_copy(G, b + L.ja_W1n, src("jatt_W1"), plain((int64_t)2 * NV * w), s, LD0));
+    DO(do_copy(G, b + L.ja_W2n, src("jatt_W2"), plain((int64_t)2 * w * w), s, LD0));
   }
   // GEMM operands Bt[N][K] (and their low bf16 parts under the hybrid precision)
   const int64_t dd = (int64_t)D.d * D.d;

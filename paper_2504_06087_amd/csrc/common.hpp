@@ -38,6 +38,9 @@ struct Dims {
   int prec;
   int split;          // GEMM sites using split bf16 operands (hybrid precision)
   int Hj;             // hidden width of the MLP Jastrow (0: off)
+  int Ra, dr, Ha;     // attention Jastrow: registers (0: off), register width, readout width
+  FIRE_HOST_DEVICE int NV() const { return Ra * dr; }          // register embedding width
+  FIRE_HOST_DEVICE int NA() const { return Ra * (1 + dr); }    // logits + values per electron
   FIRE_HOST_DEVICE int nsig(int s) const { return s == 0 ? nu : nd; }
 };
 
@@ -201,6 +204,11 @@ template <typename T> struct Net {
   // W2t [2][Hj][Hj], and W1n [2][d][Hj], W2n [2][Hj][Hj] for the adjoint
   const T *jm_b1, *jm_b2, *jm_w3, *jm_b3;
   const void *jm_W1t, *jm_W2t, *jm_W1n, *jm_W2n;
+  // attention Jastrow (D.Ra > 0): projection Pt [NA][d] (queries, then the
+  // value maps r-major) and Pn [d][NA] for the adjoint; readout MLPs over V
+  // as for the MLP Jastrow (input width NV, hidden Ha)
+  const T *ja_b1, *ja_b2, *ja_w3, *ja_b3;
+  const void *ja_Pt, *ja_Pn, *ja_W1t, *ja_W2t, *ja_W1n, *ja_W2n;
 };
 
 // ---------------------------------------------------------------------------

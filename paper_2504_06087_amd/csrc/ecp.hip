@@ -389,7 +389,8 @@ static hipError_t ecp_impl(const fire_handle* h, int W, const double* R, char* s
       hipLaunchKernelGGL(k_ecp_ratio, dim3((L.Jc + 255) / 256), dim3(256), 0, ss, D, L.Jc, j0, (const int*)jdev,
                          (const int*)jw, (const double*)cf, (const double*)(uws + U.detA),
                          (const double*)(uws + U.dj),
-                         h->D.Hj > 0 ? (const double*)(uws + U.jsg) : (const double*)nullptr, (const char*)state,
+                         h->D.Hj > 0 || h->D.Ra > 0 ? (const double*)(uws + U.jsg) : (const double*)nullptr,
+                         (const char*)state,
                          S, contrib);
       CHECK(hipGetLastError());
     }

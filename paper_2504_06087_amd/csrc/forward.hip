@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_jastrow(const Dims D, const double* __r
 // with the MLP Jastrow (jm) the sign takes sign(S_2).
 __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds, size_t off_dl, size_t off_lp,
                             size_t off_sp, size_t off_jas, int W, int K, double* sign, double* logpsi,
-                            int32_t* status, bool jm, size_t off_jms) {
+                            int32_t* status, bool jm, size_t off_jms, bool ja, size_t off_ja_node) {
   int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
   char* rec = state + (int64_t)w * srec;
@@ -329,7 +329,9 @@ __global__ void k_logsumexp(char* __restrict__ state, size_t srec, size_t off_ds
   *(double*)(rec + off_lp) = lp;
   *(double*)(rec + off_sp) = sp;
   if (logpsi) logpsi[w] = lp + *(const double*)(rec + off_jas);
-  if (sign) sign[w] = jm && ((const double*)(rec + off_jms))[1] < 0.0 ? -sp : sp;
+  double sg = jm && ((const double*)(rec + off_jms))[1] < 0.0 ? -sp : sp;
+  if (ja && *(const double*)(rec + off_ja_node) < 0.0) sg = -sg;
+  if (sign) sign[w] = sg;
 }
 
 // ---------------------------------------------------------------------------
@@ -349,6 +351,7 @@ WsLayout ws_forward(const fire_handle* h, int W) {
   L.basis = o;   o = align_up(o + rows * D.B * ts);
   L.jrow = o;    o = align_up(o + (D.Hj > 0 ? rows * 2 * 8 : 0));
   L.jscr = o;    o = align_up(o + jm_rows_ws(h, rows));
+  L.ascr = o;    o = align_up(o + ja_eval_ws(h, W));
   L.total = o;
   return L;
 }
@@ -422,6 +425,8 @@ hipError_t embed_and_orbitals(const fire_handle* h, const Net<T>& P, int W, cons
     CHECK(jm_rows<T>(h, P, hin, (int)rows, nullptr, ws + L.jscr, jrow, s));
     CHECK(jm_store(h, W, jrow, state, s));
   }
+  // attention Jastrow: projections, softmax sums, registers and readouts
+  if (D.Ra > 0) CHECK(ja_eval<T>(h, P, W, hin, state, ws + L.ascr, s));
   // envelopes and orbitals per spin block
   hipLaunchKernelGGL(k_env_basis<T>, dim3((unsigned)((rows * D.B + 255) / 256)), dim3(256), 0, s, P, R, rows, basis, (const int*)nullptr);
   CHECK(hipGetLastError());
@@ -496,8 +501,10 @@ hipError_t refresh_dets(const fire_handle* h, int W, const double* R, char* stat
                      state, S);
   CHECK(hipGetLastError());
   CHECK(jm_total(h, W, state, status, s));
+  CHECK(ja_total(h, W, state, status, s));
   hipLaunchKernelGGL(k_logsumexp, dim3((W + 127) / 128), dim3(128), 0, s, state, S.stride, S.dsign, S.dlog, S.lpsi,
-                     S.spsi, S.jas, W, D.K, sign, logpsi, status, D.Hj > 0, S.jms);
+                     S.spsi, S.jas, W, D.K, sign, logpsi, status, D.Hj > 0, S.jms, D.Ra > 0,
+                     S.jat + (size_t)(2 * D.Ra + D.NV() + 1) * 8);
   return hipGetLastError();
 }
 

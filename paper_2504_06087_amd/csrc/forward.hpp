@@ -32,6 +32,9 @@ template <typename T> inline Net<T> make_net(const fire_handle* h) {
   P.orb_n0 = b + L.orb_n0; P.orb_n1 = b + L.orb_n1; P.pi_n0 = b + L.pi_n0; P.pi_n1 = b + L.pi_n1;
   P.jm_b1 = t(L.jm_b1); P.jm_b2 = t(L.jm_b2); P.jm_w3 = t(L.jm_w3); P.jm_b3 = t(L.jm_b3);
   P.jm_W1t = b + L.jm_W1t; P.jm_W2t = b + L.jm_W2t; P.jm_W1n = b + L.jm_W1n; P.jm_W2n = b + L.jm_W2n;
+  P.ja_b1 = t(L.ja_b1); P.ja_b2 = t(L.ja_b2); P.ja_w3 = t(L.ja_w3); P.ja_b3 = t(L.ja_b3);
+  P.ja_Pt = b + L.ja_Pt; P.ja_Pn = b + L.ja_Pn; P.ja_W1t = b + L.ja_W1t; P.ja_W2t = b + L.ja_W2t;
+  P.ja_W1n = b + L.ja_W1n; P.ja_W2n = b + L.ja_W2n;
   return P;
 }
 

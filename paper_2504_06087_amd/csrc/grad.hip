@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "embed_kernels.hpp"
+#include "jastrow.hpp"
 
 namespace fire {
 
@@ -149,22 +150,23 @@ __global__ void k_orb_bar(const Dims D, int s, int Wc, int w0, const char* __res
   o[q] = pb * o[q];
 }
 
-// MLP Jastrow readout k (0: S_1, 1: S_2) of row r = (w, i): its adjoint
-// g = c_w (k = 0) or c_w / S_2,w (k = 1); then a2bar = g w3 SiLU'(a2), the
-// readout-weight terms g z2 and g itself (bias)
+// Jastrow readout k (0: log part, 1: node part) of row r of walker
+// w = w0 + r / per: its adjoint g = c_w (k = 0) or c_w / node_w (k = 1, the
+// node factor's value, FP64 at byte node_off of the record); then
+// a2bar = g w3 SiLU'(a2), the readout-weight terms g z2 and g itself (bias)
 template <typename T>
-__global__ void k_jm_readout_bar(int64_t rows, int n, int w0, int Hj, int k, const char* __restrict__ state,
-                                 StateRec S, const double* __restrict__ coeff, const T* __restrict__ w3,
-                                 const T* __restrict__ a2, const T* z2, T* __restrict__ a2bar, T* gz2,
-                                 T* __restrict__ gcol) {
+__global__ void k_jm_readout_bar(int64_t rows, int per, int w0, int Hj, int k, const char* __restrict__ state,
+                                 size_t stride, size_t node_off, const double* __restrict__ coeff,
+                                 const T* __restrict__ w3, const T* __restrict__ a2, const T* z2,
+                                 T* __restrict__ a2bar, T* gz2, T* __restrict__ gcol) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= rows * Hj) return;
   const int64_t r = q / Hj;
   const int c = (int)(q % Hj);
-  const int64_t w = w0 + r / n;
+  const int64_t w = w0 + r / per;
   double g = coeff[w];
   if (k == 1) {
-    const double s2 = ((const double*)(state + w * S.stride + S.jms))[1];
+    const double s2 = *(const double*)(state + w * stride + node_off);
     g = s2 != 0.0 && isfinite(s2) ? g / s2 : 0.0;
   }
   T f, f1, f2;
@@ -172,6 +174,51 @@ __global__ void k_jm_readout_bar(int64_t rows, int n, int w0, int Hj, int k, con
   a2bar[q] = (T)(g * (double)w3[c] * (double)f1);
   gz2[q] = (T)(g * (double)z2[q]);
   if (c == 0) gcol[r] = (T)g;
+}
+
+// attention Jastrow: register embeddings V = N / Z of walkers w0 + [0, Wc)
+template <typename T>
+__global__ void k_ja_vrows(const Dims D, int Wc, int w0, const char* __restrict__ state, StateRec S,
+                           T* __restrict__ V) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int NV = D.NV();
+  if (q >= (int64_t)Wc * NV) return;
+  const int64_t wl = q / NV;
+  const int c = (int)(q % NV);
+  const double* jt = (const double*)(state + (w0 + wl) * S.stride + S.jat);
+  V[q] = (T)(jt[2 * D.Ra + c] / jt[D.Ra + c / D.dr]);
+}
+
+// attention Jastrow adjoint per row (w, i): with p_ri = e^{l_ri - m_r} / Z_r,
+//   ubar_ric = Vbar_rc p_ri,  lbar_ri = p_ri sum_c Vbar_rc (u_ric - V_rc)
+template <typename T>
+__global__ __launch_bounds__(256) void k_ja_bar(const Dims D, int w0, const char* __restrict__ state, StateRec S,
+                                                const T* __restrict__ Vbar, T* __restrict__ abar) {
+  const int64_t row = blockIdx.x;
+  const int n = D.n, NA = D.NA(), NV = D.NV(), Ra = D.Ra, dr = D.dr;
+  const int64_t wl = row / n;
+  const int i = (int)(row % n);
+  const char* rec = state + (w0 + wl) * S.stride;
+  const T* a = (const T*)(rec + S.jae) + (int64_t)i * NA;
+  const double* jt = (const double*)(rec + S.jat);
+  const T* vb = Vbar + wl * NV;
+  for (int c = threadIdx.x; c < NA; c += blockDim.x) {
+    const int r = c < Ra ? c : (c - Ra) / dr;
+    const double Z = jt[Ra + r];
+    const double p = exp((double)a[r] - jt[r]) / Z;
+    double v;
+    if (c < Ra) {
+      double acc = 0.0;
+      for (int e = 0; e < dr; ++e) {
+        const int cc = r * dr + e;
+        acc += (double)vb[cc] * ((double)a[Ra + cc] - jt[2 * Ra + cc] / Z);
+      }
+      v = p * acc;
+    } else {
+      v = (double)vb[c - Ra] * p;
+    }
+    abar[row * NA + c] = (T)v;
+  }
 }
 
 // ubar = tbar * SiLU(g), gbar = tbar * u * SiLU'(g)
@@ -853,6 +900,7 @@ struct GradLayout {
   size_t nidx, ncnt, y, ug, t, hk, zk, basis, o[2], obar[2], hbar, hbar2, zbar, h0bar, projbar, tbar, ugbar;
   size_t ybar, sbar, bbar, trA, trB, split, epart;
   size_t jm[7];   // MLP Jastrow: a1, z1, a2, z2, a2bar, z1bar/a1bar [rows][Hj]; readout bars [rows]
+  size_t ja[10];  // attention Jastrow: V, Vbar [Wc][NV], abar [rows][NA], readout scratch as jm over Wc rows
   size_t total;
 };
 
@@ -865,9 +913,11 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   int widest = 4 * D.d;
   if (KNmax > widest) widest = KNmax;
   if (D.B > widest) widest = D.B;
+  if (D.NA() > widest) widest = D.NA();
+  if (D.Ha > widest) widest = D.Ha;
   const size_t per_walker = (size_t)D.n * ts *
                             ((size_t)20 * D.d + 2 * (size_t)D.L * D.d + 2 * (size_t)D.B + 3 * (size_t)KNmax + 2 * widest +
-                             (D.Hj > 0 ? (size_t)6 * D.Hj + 1 : 0));
+                             (D.Hj > 0 ? (size_t)6 * D.Hj + 1 : 0) + (D.Ra > 0 ? (size_t)D.NA() + 8 * D.Ha : 0));
   const size_t budget = (size_t)24 << 30;
   int wc = (int)(budget / per_walker);
   if (wc < 1) wc = 1;
@@ -906,6 +956,12 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   const size_t enp = (size_t)GBLK * ((D.M + ENCH - 1) / ENCH) * en_off(D).size;
   L.epart = take((ep > enp ? ep : enp) * ts);
   for (int k = 0; k < 7; ++k) L.jm[k] = D.Hj > 0 ? take(R * (k < 6 ? D.Hj : 1) * ts) : 0;
+  if (D.Ra > 0) {
+    L.ja[0] = take((size_t)wc * D.NV() * ts);
+    L.ja[1] = take((size_t)wc * D.NV() * ts);
+    L.ja[2] = take(R * D.NA() * ts);
+    for (int k = 0; k < 7; ++k) L.ja[3 + k] = take((size_t)wc * (k < 6 ? D.Ha : 1) * ts);
+  }
   L.total = o;
   return L;
 }
@@ -948,6 +1004,65 @@ static hipError_t bgrad(const GradLayout& L, char* ws, const T* X, RowMap xm, in
   hipLaunchKernelGGL(k_reduce_splits<T>, dim3((C + 255) / 256), dim3(256), 0, st, (const T*)part, GNS, 1, C, grad,
                      base, (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
   return hipGetLastError();
+}
+
+// Backward of a pair of Jastrow readout MLPs over rows X [M][Q.in] (per rows
+// per walker, walkers from w0): weight gradients into grad under the theta
+// names prefix + W1, b1, W2, b2, w3, b3, and Xbar = sum_k a1bar_k W1_k^T
+// (added to Xbar when accumulate).  buf: seven scratch arrays, six of [M][H]
+// and one of [M] (T).
+template <typename T>
+static hipError_t readout_backward(const fire_handle* h, const GradLayout& L, char* ws, const Readout<T>& Q,
+                                   const T* X, int M, int per, int w0, const char* state, size_t node_off,
+                                   const double* coeff, const char* prefix, T* const* buf, T* Xbar, bool accumulate,
+                                   double* grad, hipStream_t st) {
+  const int H = Q.H, in = Q.in;
+  T *a1 = buf[0], *z1 = buf[1], *a2 = buf[2], *z2 = buf[3], *a2b = buf[4], *z1b = buf[5], *gcol = buf[6];
+  auto th = [&](const char* nm) { return theta_offset(h, (std::string(prefix) + nm).c_str()); };
+  const int64_t nq = (int64_t)M * H;
+  const unsigned gq = (unsigned)((nq + 255) / 256);
+  for (int k = 0; k < 2; ++k) {
+    const char* W1k = (const char*)Q.W1t + (size_t)k * H * in * h->gsize;
+    const char* W2k = (const char*)Q.W2t + (size_t)k * H * H * h->gsize;
+    GemmArgs g1{};
+    g1.A = X; g1.amap = rows_dense(in); g1.Bt = W1k; g1.ldb = in; g1.bias = Q.b1 + (int64_t)k * H;
+    g1.C = a1; g1.cmap = rows_dense(H); g1.ccol = cols_dense(); g1.M = M; g1.N = H; g1.K = in;
+    CHECK(gemm_site(h, SITE_EMB, g1, st));
+    hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, z1, nq);
+    CHECK(hipGetLastError());
+    GemmArgs g2{};
+    g2.A = z1; g2.amap = rows_dense(H); g2.Bt = W2k; g2.ldb = H; g2.bias = Q.b2 + (int64_t)k * H;
+    g2.C = a2; g2.cmap = rows_dense(H); g2.ccol = cols_dense(); g2.M = M; g2.N = H; g2.K = H;
+    CHECK(gemm_site(h, SITE_EMB, g2, st));
+    hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a2, z2, nq);
+    CHECK(hipGetLastError());
+    // z2 is not needed after this: it takes the readout-weight terms g z2
+    hipLaunchKernelGGL(k_jm_readout_bar<T>, dim3(gq), dim3(256), 0, st, (int64_t)M, per, w0, H, k, state,
+                       h->st.stride, node_off, coeff, Q.w3 + (int64_t)k * H, (const T*)a2, (const T*)z2, a2b, z2,
+                       gcol);
+    CHECK(hipGetLastError());
+    CHECK(bgrad<T>(L, ws, z2, rows_dense(H), M, H, grad, th("w3") + (int64_t)k * H, st));
+    CHECK(bgrad<T>(L, ws, gcol, rows_dense(1), M, 1, grad, th("b3") + k, st));
+    CHECK(wgrad<T>(h, L, ws, z1, rows_dense(H), M, H, a2b, rows_dense(H), H, grad, th("W2") + (int64_t)k * H * H, H,
+                   (int64_t)1 << 40, 0, 1, st));
+    CHECK(bgrad<T>(L, ws, a2b, rows_dense(H), M, H, grad, th("b2") + (int64_t)k * H, st));
+    // z1bar = a2bar W2_k^T, then a1bar = z1bar SiLU'(a1) (into a2, free now)
+    GemmArgs b2{};
+    b2.A = a2b; b2.amap = rows_dense(H); b2.Bt = (const char*)Q.W2n + (size_t)k * H * H * h->gsize;
+    b2.ldb = H; b2.C = z1b; b2.cmap = rows_dense(H); b2.ccol = cols_dense(); b2.M = M; b2.N = H; b2.K = H;
+    CHECK(gemm_site(h, SITE_GRAD, b2, st));
+    hipLaunchKernelGGL(k_silu_bar<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, (const T*)z1b, a2, nq);
+    CHECK(hipGetLastError());
+    CHECK(wgrad<T>(h, L, ws, X, rows_dense(in), M, in, a2, rows_dense(H), H, grad, th("W1") + (int64_t)k * in * H, H,
+                   (int64_t)1 << 40, 0, 1, st));
+    CHECK(bgrad<T>(L, ws, a2, rows_dense(H), M, H, grad, th("b1") + (int64_t)k * H, st));
+    GemmArgs b1{};
+    b1.A = a2; b1.amap = rows_dense(H); b1.Bt = (const char*)Q.W1n + (size_t)k * in * H * h->gsize;
+    b1.ldb = H; b1.C = Xbar; b1.cmap = rows_dense(in); b1.ccol = cols_dense(); b1.M = M; b1.N = in;
+    b1.K = H; b1.accumulate = accumulate || k == 1;
+    CHECK(gemm_site(h, SITE_GRAD, b1, st));
+  }
+  return hipSuccess;
 }
 
 template <typename T>
@@ -1063,60 +1178,39 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
                        grad, th("env_sigma"), (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
     CHECK(hipGetLastError());
   }
-  // ---- MLP Jastrow backward: hbar += sum_k a1bar_k W1_k^T, with the
-  // weight gradients of both readout MLPs
-  if (D.Hj > 0) {
-    const int Hj = D.Hj;
-    T* a1 = (T*)(ws + L.jm[0]);
-    T* z1 = (T*)(ws + L.jm[1]);
-    T* a2 = (T*)(ws + L.jm[2]);
-    T* z2 = (T*)(ws + L.jm[3]);
-    T* a2b = (T*)(ws + L.jm[4]);
-    T* z1b = (T*)(ws + L.jm[5]);
-    T* gcol = (T*)(ws + L.jm[6]);
-    const int64_t nq = rows * Hj;
-    const unsigned gq = (unsigned)((nq + 255) / 256);
-    for (int k = 0; k < 2; ++k) {
-      const char* W1k = (const char*)P.jm_W1t + (size_t)k * Hj * d * h->gsize;
-      const char* W2k = (const char*)P.jm_W2t + (size_t)k * Hj * Hj * h->gsize;
-      GemmArgs g1{};
-      g1.A = hL; g1.amap = rows_dense(d); g1.Bt = W1k; g1.ldb = d; g1.bias = P.jm_b1 + (int64_t)k * Hj;
-      g1.C = a1; g1.cmap = rows_dense(Hj); g1.ccol = cols_dense(); g1.M = (int)rows; g1.N = Hj; g1.K = d;
-      CHECK(gemm_site(h, SITE_EMB, g1, st));
-      hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, z1, nq);
-      CHECK(hipGetLastError());
-      GemmArgs g2{};
-      g2.A = z1; g2.amap = rows_dense(Hj); g2.Bt = W2k; g2.ldb = Hj; g2.bias = P.jm_b2 + (int64_t)k * Hj;
-      g2.C = a2; g2.cmap = rows_dense(Hj); g2.ccol = cols_dense(); g2.M = (int)rows; g2.N = Hj; g2.K = Hj;
-      CHECK(gemm_site(h, SITE_EMB, g2, st));
-      hipLaunchKernelGGL(k_silu_inplace<T>, dim3(gq), dim3(256), 0, st, (const T*)a2, z2, nq);
-      CHECK(hipGetLastError());
-      // z2 is not needed after this: it takes the readout-weight terms g z2
-      hipLaunchKernelGGL(k_jm_readout_bar<T>, dim3(gq), dim3(256), 0, st, rows, n, w0, Hj, k, (const char*)state, S,
-                         coeff, P.jm_w3 + (int64_t)k * Hj, (const T*)a2, (const T*)z2, a2b, z2, gcol);
-      CHECK(hipGetLastError());
-      CHECK(bgrad<T>(L, ws, z2, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_w3") + (int64_t)k * Hj, st));
-      CHECK(bgrad<T>(L, ws, gcol, rows_dense(1), (int)rows, 1, grad, th("jmlp_b3") + k, st));
-      CHECK(wgrad<T>(h, L, ws, z1, rows_dense(Hj), (int)rows, Hj, a2b, rows_dense(Hj), Hj, grad,
-                     th("jmlp_W2") + (int64_t)k * Hj * Hj, Hj, (int64_t)1 << 40, 0, 1, st));
-      CHECK(bgrad<T>(L, ws, a2b, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_b2") + (int64_t)k * Hj, st));
-      // z1bar = a2bar W2_k^T, then a1bar = z1bar SiLU'(a1) (into a2, free now)
-      GemmArgs b2{};
-      b2.A = a2b; b2.amap = rows_dense(Hj); b2.Bt = (const char*)P.jm_W2n + (size_t)k * Hj * Hj * h->gsize;
-      b2.ldb = Hj; b2.C = z1b; b2.cmap = rows_dense(Hj); b2.ccol = cols_dense(); b2.M = (int)rows; b2.N = Hj;
-      b2.K = Hj;
-      CHECK(gemm_site(h, SITE_GRAD, b2, st));
-      hipLaunchKernelGGL(k_silu_bar<T>, dim3(gq), dim3(256), 0, st, (const T*)a1, (const T*)z1b, a2, nq);
-      CHECK(hipGetLastError());
-      CHECK(wgrad<T>(h, L, ws, hL, rows_dense(d), (int)rows, d, a2, rows_dense(Hj), Hj, grad,
-                     th("jmlp_W1") + (int64_t)k * d * Hj, Hj, (int64_t)1 << 40, 0, 1, st));
-      CHECK(bgrad<T>(L, ws, a2, rows_dense(Hj), (int)rows, Hj, grad, th("jmlp_b1") + (int64_t)k * Hj, st));
-      GemmArgs b1{};
-      b1.A = a2; b1.amap = rows_dense(Hj); b1.Bt = (const char*)P.jm_W1n + (size_t)k * d * Hj * h->gsize;
-      b1.ldb = Hj; b1.C = hbar; b1.cmap = rows_dense(d); b1.ccol = cols_dense(); b1.M = (int)rows; b1.N = d;
-      b1.K = Hj; b1.accumulate = 1;
-      CHECK(gemm_site(h, SITE_GRAD, b1, st));
-    }
+  // ---- Jastrow readouts backward: the MLP Jastrow over the final
+  // embeddings (hbar += its input adjoint), then the attention Jastrow over
+  // the register embeddings and its softmax (hbar += abar Pn)
+  T* jb[7];
+  for (int k = 0; k < 7; ++k) jb[k] = (T*)(ws + L.jm[k]);
+  if (D.Hj > 0)
+    CHECK(readout_backward<T>(h, L, ws, jm_readout<T>(h, P), hL, (int)rows, n, w0, state, S.jms + 8, coeff, "jmlp_",
+                              jb, hbar, true, grad, st));
+  if (D.Ra > 0) {
+    const int NV = D.NV(), NA = D.NA();
+    T* V = (T*)(ws + L.ja[0]);
+    T* Vbar = (T*)(ws + L.ja[1]);
+    T* abar = (T*)(ws + L.ja[2]);
+    T* rb[7];
+    for (int k = 0; k < 7; ++k) rb[k] = (T*)(ws + L.ja[3 + k]);
+    hipLaunchKernelGGL(k_ja_vrows<T>, dim3((unsigned)(((int64_t)Wc * NV + 255) / 256)), dim3(256), 0, st, D, Wc, w0,
+                       (const char*)state, S, V);
+    CHECK(hipGetLastError());
+    CHECK(readout_backward<T>(h, L, ws, ja_readout<T>(h, P), V, Wc, 1, w0, state,
+                              S.jat + (size_t)(2 * D.Ra + NV + 1) * 8, coeff, "jatt_", rb, Vbar, false, grad, st));
+    hipLaunchKernelGGL(k_ja_bar<T>, dim3((unsigned)rows), dim3(256), 0, st, D, w0, (const char*)state, S,
+                       (const T*)Vbar, abar);
+    CHECK(hipGetLastError());
+    // q[r][c] += sum_rows h[c] lbar[r];  Wv[r][c][e] += sum_rows h[c] ubar[r dr + e]
+    CHECK(wgrad<T>(h, L, ws, hL, rows_dense(d), (int)rows, d, abar, rows_dense(NA), D.Ra, grad, th("jatt_q"), 1,
+                   (int64_t)1 << 40, 0, d, st));
+    CHECK(wgrad<T>(h, L, ws, hL, rows_dense(d), (int)rows, d, abar + D.Ra, rows_dense(NA), NV, grad, th("jatt_Wv"),
+                   D.dr, D.dr, (int64_t)d * D.dr, 1, st));
+    GemmArgs b1{};
+    b1.A = abar; b1.amap = rows_dense(NA); b1.Bt = P.ja_Pn; b1.ldb = NA;
+    b1.C = hbar; b1.cmap = rows_dense(d); b1.ccol = cols_dense(); b1.M = (int)rows; b1.N = d; b1.K = NA;
+    b1.accumulate = 1;
+    CHECK(gemm_site(h, SITE_GRAD, b1, st));
   }
   // ---- MLP backward
   T* hb_cur = hbar;

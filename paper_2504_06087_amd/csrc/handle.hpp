@@ -38,6 +38,8 @@ struct ParamsLayout {
   // MLP Jastrow: small arrays in T, GEMM operands in G (inside the region
   // that has low bf16 parts)
   size_t jm_b1, jm_b2, jm_w3, jm_b3, jm_W1t, jm_W2t, jm_W1n, jm_W2n;
+  // attention Jastrow: small arrays in T, GEMM operands in G
+  size_t ja_b1, ja_b2, ja_w3, ja_b3, ja_Pt, ja_Pn, ja_W1t, ja_W2t, ja_W1n, ja_W2n;
   // low bf16 parts of every GEMM operand above live at (offset + lo_delta)
   size_t lo_delta;
   // molecule
@@ -53,8 +55,12 @@ struct StateRec {
   // magnitude, log J_cusp + log|J_MLP|, so that log|psi| = lpsi + jas.
   // With the MLP Jastrow: jme [n][2] per-electron readouts MLP_1(h_i),
   // MLP_2(h_i) and jms [2] their sums S_1, S_2 (FP64); sign(psi) =
-  // spsi * sign(S_2)
-  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi, jas, jme, jms;
+  // spsi * sign(S_2).  With the attention Jastrow: jae [n][NA] per-electron
+  // logits h_i . q_r and values h_i W^V_r (T), and jat (FP64): the logit
+  // shifts m [N_reg], the softmax sums Z [N_reg] = sum_i e^{l_ri - m_r} and
+  // N [NV] = sum_i e^{l_ri - m_r} u_ri, and the readouts o [2] = MLP_1(V),
+  // MLP_2(V); sign(psi) also takes sign(o_2)
+  size_t h0, proj, m, phi, env, inv, dsign, dlog, lpsi, spsi, jas, jme, jms, jae, jat;
   size_t stride;
 };
 
@@ -97,6 +103,7 @@ namespace fire {
 struct WsLayout {
   size_t nbr_idx, nbr_cnt, y, ug, hA, hB, basis;
   size_t jrow, jscr;   // MLP Jastrow readouts [W n][2] (FP64) and their scratch
+  size_t ascr;         // attention Jastrow: registers, readouts and their scratch
   size_t total;
 };
 WsLayout ws_forward(const fire_handle* h, int W);

@@ -35,6 +35,10 @@ LapLayout lap_layout(const fire_handle* h, int W) {
                             (size_t)D.n * 5 * ((size_t)8 * D.d + D.B + (size_t)D.K * nmax) * ts +
                             (D.Hj > 0 ? (size_t)D.n * jet_rows_max(D) * (2 * D.Hj * ts + 16) +
                                             (size_t)D.n * (2 * D.Hj * ts + 24)
+                                      : 0) +
+                            (D.Ra > 0 ? (size_t)D.n * jet_rows_max(D) * D.NA() * ts +
+                                            (size_t)(3 * D.n + 2) * ((size_t)(D.NV() + 2 * D.Ha) * ts + 16) +
+                                            (size_t)4 * D.n * D.Ra * 8 + (size_t)D.n * 24
                                       : 0);
   const size_t budget = h->lap_budget;
   int wc = (int)(budget / (per_walker > 0 ? per_walker : 1));
@@ -78,9 +82,12 @@ LapLayout lap_layout(const fire_handle* h, int W) {
       L.jjy[s] = take(L.rowcap[s] * D.Hj * ts);
       L.jjt[s] = take(L.rowcap[s] * 2 * 8);
     }
+  }
+  if (D.Hj > 0 || D.Ra > 0) {
     L.jgJ = take(Wl * n * 3 * 8);
     L.jlap = take(Wl * 8);
   }
+  if (D.Ra > 0) L.jak = take(ja_kin_ws(h, wc, L.rowcap));
   L.total = o;
   return L;
 }
@@ -824,20 +831,24 @@ static hipError_t kinetic_chunk(const fire_handle* h, const Net<T>& P, int w0, i
     // and the member lists are still intact; jout is free)
     double* gJ = nullptr;
     double* lapJ = nullptr;
-    if (D.Hj > 0) {
+    if (D.Hj > 0 || D.Ra > 0) {
       JmJetArgs a{};
       a.Wc = Wc; a.w0 = w0; a.rowcap[0] = L.rowcap[0]; a.rowcap[1] = L.rowcap[1];
       a.ncnt = ncnt; a.joff = joff; a.jtot = jtot; a.memb = memb; a.mslot = mslot; a.mcnt = mcnt; a.tcap = L.tcap;
-      a.hval = hval; a.jin[0] = jin[0]; a.jin[1] = jin[1]; a.zv = ws + L.jzv;
-      for (int s = 0; s < 2; ++s) {
-        a.jx[s] = ws + L.jjx[s];
-        a.jy[s] = ws + L.jjy[s];
-        a.jt[s] = (double*)(ws + L.jjt[s]);
+      a.hval = hval; a.jin[0] = jin[0]; a.jin[1] = jin[1];
+      if (D.Hj > 0) {
+        a.zv = ws + L.jzv;
+        for (int s = 0; s < 2; ++s) {
+          a.jx[s] = ws + L.jjx[s];
+          a.jy[s] = ws + L.jjy[s];
+          a.jt[s] = (double*)(ws + L.jjt[s]);
+        }
       }
       gJ = (double*)(ws + L.jgJ);
       lapJ = (double*)(ws + L.jlap);
       a.gJ = gJ; a.lapJ = lapJ;
-      CHECK(jm_kinetic<T>(h, P, a, (const char*)state, st));
+      if (D.Hj > 0) CHECK(jm_kinetic<T>(h, P, a, (const char*)state, st));
+      if (D.Ra > 0) CHECK(ja_kinetic<T>(h, P, a, (const char*)state, ws + L.jak, D.Hj == 0, st));
     }
     hipLaunchKernelGGL(k_kinetic, dim3(Wc), dim3(256), 0, st, D, Wc, w0, (const char*)state, S, (const double*)gd,
                        (const double*)hd, R, P.jas, (const double*)gJ, (const double*)lapJ, kin, grad);

@@ -14,6 +14,7 @@ struct LapLayout {
   // MLP Jastrow jets (D.Hj > 0): values [2][rows][Hj], jet rows [rowcap][Hj]
   // twice per spin, readout rows [rowcap][2] (FP64), grad [Wc][n][3], Lap [Wc]
   size_t jzv, jjx[2], jjy[2], jjt[2], jgJ, jlap;
+  size_t jak;   // attention Jastrow jets (scratch of ja_kinetic)
   size_t total;
 };
 LapLayout lap_layout(const fire_handle* h, int W);

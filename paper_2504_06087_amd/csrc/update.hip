@@ -63,8 +63,12 @@ UpdLayout upd_layout(const fire_handle* h, int W, bool with_woodbury) {
   }
   if (D.Hj > 0) {
     L.jsum = take(Wl * 2 * 8);
-    L.jsg = take(Wl * 8);
     L.jscr = take(jm_rows_ws(h, L.rowcap[0] > L.rowcap[1] ? L.rowcap[0] : L.rowcap[1]));
+  }
+  if (D.Hj > 0 || D.Ra > 0) L.jsg = take(Wl * 8);
+  if (D.Ra > 0) {
+    for (int s = 0; s < 2; ++s) L.anew[s] = take(L.rowcap[s] * D.NA() * ts);
+    L.ja = take(ja_update_ws(h, W));
   }
   L.total = o;
   return L;
@@ -1555,8 +1559,10 @@ __global__ void k_final_outputs(const Dims D, int W, const char* __restrict__ st
   const char* rec = state + (int64_t)w * S.stride;
   const bool bad = status[w] != 0;
   if (logpsi) logpsi[w] = bad ? NAN : *(const double*)(rec + S.lpsi) + *(const double*)(rec + S.jas);
-  const double sp = *(const double*)(rec + S.spsi);
-  if (sign) sign[w] = bad ? 0.0 : (D.Hj > 0 && ((const double*)(rec + S.jms))[1] < 0.0 ? -sp : sp);
+  double sp = *(const double*)(rec + S.spsi);
+  if (D.Hj > 0 && ((const double*)(rec + S.jms))[1] < 0.0) sp = -sp;
+  if (D.Ra > 0 && ((const double*)(rec + S.jat))[2 * D.Ra + D.NV() + 1] < 0.0) sp = -sp;
+  if (sign) sign[w] = bad ? 0.0 : sp;
 }
 
 __global__ void k_unit_detA(int nwd, int s, double* detA) {
@@ -1665,6 +1671,13 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
       T* t = hin; hin = hout; hout = t;
     }
     if (D.Hj > 0) CHECK(jm_rows<T>(h, P, hin, rows, Mdev, ws + L.jscr, (double*)(ws + L.jnew[s]), st));
+    if (D.Ra > 0) {
+      GemmArgs ga{};
+      ga.A = hin; ga.amap = rows_dense(D.d); ga.Bt = P.ja_Pt; ga.ldb = D.d;
+      ga.C = ws + L.anew[s]; ga.cmap = rows_dense(D.NA()); ga.ccol = cols_dense(); ga.M = rows; ga.N = D.NA();
+      ga.K = D.d; ga.Mdev = Mdev;
+      CHECK(gemm_site(h, SITE_EMB, ga, st));
+    }
     T* oseg = (T*)(ws + L.oseg[s]);
     GemmArgs o{};
     o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
@@ -1727,6 +1740,9 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   CHECK(jm_delta(h, W, jb.jw, uidx, L.capmax, ucnt, off, (const double*)(ws + L.jnew[0]),
                  (const double*)(ws + L.jnew[1]), state, (double*)(ws + L.dj), (double*)(ws + L.jsg),
                  (double*)(ws + L.jsum), st));
+  CHECK(ja_delta<T>(h, P, W, jb.jw, jb.Jdev, uidx, L.capmax, ucnt, off, (const T*)(ws + L.anew[0]),
+                    (const T*)(ws + L.anew[1]), state, ws + L.ja, (double*)(ws + L.dj), (double*)(ws + L.jsg),
+                    D.Hj == 0, st));
   return hipSuccess;
 }
 
@@ -1812,9 +1828,12 @@ static hipError_t accept_and_commit(const fire_handle* h, int W, int e, double* 
                      (const T*)(ws + L.projnew), (const T*)(ws + L.mseg[0]), (const T*)(ws + L.mseg[1]),
                      (const T*)(ws + L.envnew), state, S);
   CHECK(hipGetLastError());
-  return jm_commit(h, W, acc, (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt),
-                   (const int*)(ws + L.off), (const double*)(ws + L.jnew[0]), (const double*)(ws + L.jnew[1]),
-                   (const double*)(ws + L.jsum), state, st);
+  CHECK(jm_commit(h, W, acc, (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt),
+                  (const int*)(ws + L.off), (const double*)(ws + L.jnew[0]), (const double*)(ws + L.jnew[1]),
+                  (const double*)(ws + L.jsum), state, st));
+  return ja_commit<T>(h, W, acc, (const int*)(ws + L.uidx), L.capmax, (const int*)(ws + L.ucnt),
+                      (const int*)(ws + L.off), (const T*)(ws + L.anew[0]), (const T*)(ws + L.anew[1]), ws + L.ja,
+                      state, st);
 }
 
 // The random numbers of one sweep from the counter-based generator:
@@ -2213,6 +2232,13 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
       T* t = hin; hin = hout; hout = t;
     }
     if (D.Hj > 0) CHECK(jm_rows<T>(h, P, hin, rows, Mdev, ws + L.jscr, (double*)(ws + L.jnew[s]), st));
+    if (D.Ra > 0) {
+      GemmArgs ga{};
+      ga.A = hin; ga.amap = rows_dense(D.d); ga.Bt = P.ja_Pt; ga.ldb = D.d;
+      ga.C = ws + L.anew[s]; ga.cmap = rows_dense(D.NA()); ga.ccol = cols_dense(); ga.M = rows; ga.N = D.NA();
+      ga.K = D.d; ga.Mdev = Mdev;
+      CHECK(gemm_site(h, SITE_EMB, ga, st));
+    }
     T* oseg = (T*)(ws + L.oseg[s]);
     GemmArgs o{};
     o.A = hin; o.amap = rows_dense(D.d); o.Bt = s == 0 ? P.orb_t0 : P.orb_t1; o.ldb = D.d;
@@ -2256,8 +2282,12 @@ static hipError_t swap_ratio(const fire_handle* h, const Net<T>& P, int W, int e
   CHECK(jm_delta(h, W, (const int*)nullptr, uidx, L.capmax, ucnt, off, (const double*)(ws + L.jnew[0]),
                  (const double*)(ws + L.jnew[1]), state, (double*)(ws + L.dj), (double*)(ws + L.jsg),
                  (double*)(ws + L.jsum), st));
+  CHECK(ja_delta<T>(h, P, W, (const int*)nullptr, (const int*)nullptr, uidx, L.capmax, ucnt, off,
+                    (const T*)(ws + L.anew[0]), (const T*)(ws + L.anew[1]), state, ws + L.ja, (double*)(ws + L.dj),
+                    (double*)(ws + L.jsg), D.Hj == 0, st));
   hipLaunchKernelGGL(k_swap_ratio, dim3((W + 127) / 128), dim3(128), 0, st, D, W, ea, (const double*)(ws + L.detA),
-                     (const double*)(ws + L.dj), D.Hj > 0 ? (const double*)(ws + L.jsg) : (const double*)nullptr,
+                     (const double*)(ws + L.dj),
+                     D.Hj > 0 || D.Ra > 0 ? (const double*)(ws + L.jsg) : (const double*)nullptr,
                      (const char*)state, S, (const int32_t*)status, ratios);
   return hipGetLastError();
 }

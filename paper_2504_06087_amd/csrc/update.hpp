@@ -41,6 +41,9 @@ struct UpdLayout {
   // MLP Jastrow (D.Hj > 0): new readouts of the update rows [rowcap[s]][2],
   // per-job new sums [J][2] and sign changes [J] (FP64), readout scratch
   size_t jnew[2], jsum, jsg, jscr;
+  // attention Jastrow (D.Ra > 0): projections of the new update rows
+  // [rowcap[s]][NA] (T) and the per-job sums, registers and readouts
+  size_t anew[2], ja;
   size_t total;
 };
 // Workspace of J jobs.  Each spin segment holds J * min(capS, kRowsPerJob)

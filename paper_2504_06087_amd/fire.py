@@ -51,7 +51,8 @@ class FireModelDesc(ctypes.Structure):
                 ("edge_h2", ctypes.c_int), ("n_nuc_types", ctypes.c_int), ("cutoff", ctypes.c_double),
                 ("cutoff_nuc", ctypes.c_double), ("precision", ctypes.c_int), ("max_walkers", ctypes.c_int),
                 ("cap_nbr", ctypes.c_int), ("cap_upd", ctypes.c_int), ("refresh_every", ctypes.c_int),
-                ("bf16_split", ctypes.c_int), ("jas_mlp_width", ctypes.c_int)]
+                ("bf16_split", ctypes.c_int), ("jas_mlp_width", ctypes.c_int), ("jas_att_regs", ctypes.c_int),
+                ("jas_att_dim", ctypes.c_int), ("jas_att_width", ctypes.c_int)]
 
 
 class FireParamEntry(ctypes.Structure):
@@ -188,6 +189,13 @@ def _param_layout(h):
     return [(e.name.decode(), int(e.offset), tuple(e.shape[:e.ndim])) for e in ents]
 
 
+def _jastrow_fields(model):
+    """(jas_mlp_width, jas_att_regs, jas_att_dim, jas_att_width) of a model."""
+    regs = int(getattr(model, "jas_att_regs", 0))
+    return (int(getattr(model, "jas_mlp_width", 0)), regs, int(getattr(model, "jas_att_dim", 0)) if regs else 0,
+            int(getattr(model, "jas_att_width", 0)) if regs else 0)
+
+
 class Fire:
     """One handle of libfire for one molecule and one parameter set."""
 
@@ -208,7 +216,7 @@ class Fire:
                            int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
                            float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], int(max_walkers),
                            self.cap_nbr, self.cap_upd, int(refresh_every), int(bf16_split),
-                           int(getattr(model, "jas_mlp_width", 0)))
+                           *_jastrow_fields(model))
         self.max_walkers = max_walkers
         hd = ctypes.c_void_p()
         _check(lib.fire_create(ctypes.byref(sd), ctypes.byref(md), ctypes.byref(hd)), "fire_create")
@@ -449,7 +457,7 @@ class FireBatch:
                            int(model.edge_hidden[0]), int(model.edge_hidden[1]), int(model.n_nuc_types),
                            float(model.cutoff), float(model.cutoff_nuc), PRECISIONS[precision], max(self.W),
                            int(cap_nbr), int(cap_upd), int(refresh_every), int(bf16_split),
-                           int(getattr(model, "jas_mlp_width", 0)))
+                           *_jastrow_fields(model))
         b = ctypes.c_void_p()
         _check(lib.fire_batch_create(descs, len(self.systems), ctypes.byref(md), ctypes.byref(b)),
                "fire_batch_create")

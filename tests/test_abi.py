@@ -95,6 +95,30 @@ def test_mlp_jastrow_layout_and_width_checks():
             fire.Fire(w.systems[0], m, "fp64", max_walkers=2, device="cpu")
 
 
+def test_att_jastrow_layout_and_shape_checks():
+    """The attention Jastrow's theta entries follow the MLP Jastrow's in the
+    generator's order; unsupported register counts, widths and readout
+    widths are refused at handle creation."""
+    import copy
+    from paper_2504_06087_amd import fire
+    w = wl.config(0, walkers=2)
+    m = copy.deepcopy(w.model)
+    m.jas_mlp_width = 16
+    m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 4, 4, 16
+    F = fire.Fire(w.systems[0], m, "fp64", max_walkers=2, device="cpu")
+    shapes = wl.param_shapes(w.systems[0], m)
+    names = [x[0] for x in F.layout]
+    assert names == list(shapes.keys())
+    k = names.index("jmlp_b3")
+    assert names[k + 1:k + 9] == ["jatt_q", "jatt_Wv", "jatt_W1", "jatt_b1", "jatt_W2", "jatt_b2", "jatt_w3",
+                                  "jatt_b3"]
+    assert all(tuple(x[2]) == tuple(shapes[x[0]]) for x in F.layout)
+    for regs, dim, width in ((65, 4, 16), (4, 3, 16), (4, 4, 12), (4, 4, 264), (4, 0, 16)):
+        m.jas_att_regs, m.jas_att_dim, m.jas_att_width = regs, dim, width
+        with pytest.raises(fire.FireError):
+            fire.Fire(w.systems[0], m, "fp64", max_walkers=2, device="cpu")
+
+
 @pytest.mark.parametrize("nq,ok", [(4, True), (6, True), (12, True), (5, False), (8, False)])
 def test_create_checks_the_quadrature_size(nq, ok):
     """fire_ecp_channel.n_quad names the pseudopotential rule of a species:

@@ -1,0 +1,141 @@
+"""GPU parity with the attention-register Jastrow factor (Methods, global
+electron correlation: registers v_r = softmax_i(h_i . q_r)^T (h_i W^V_r) and
+J_att = exp(MLP_1(V)) MLP_2(V)), alone and beside the MLP Jastrow, against
+the FP64 oracle: log|psi| and its sign, the Metropolis chain (the update
+rows change the cached softmax sums), cached against fresh sums, the local
+energy (dense tangents of the registers through the readout MLPs), the
+nonlocal pseudopotential ratios, the S+ swap ratios and the parameter
+gradient including the queries, value maps and readouts."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from gpu_common import dev, log, setup_custom, small_polyene
+
+pytestmark = pytest.mark.gpu
+
+
+def _h4(W, b3_node, with_mlp, seed=23):
+    w = wl.config(0, walkers=W)
+    s, m, R = w.systems[0], copy.deepcopy(w.model), w.R[0].copy()
+    m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 4, 4, 16
+    m.jas_mlp_width = 16 if with_mlp else 0
+    p = wl.init_params(s, m, np.random.default_rng(seed))
+    p["jatt_b3"] = np.array([0.2, b3_node])
+    return s, m, p, R
+
+
+@pytest.mark.parametrize("b3_node,with_mlp", [(1.0, False), (-1.0, True)])
+def test_h4_att_jastrow_matches_oracle(lib, b3_node, with_mlp):
+    W = 32
+    log(f"case: H4 fp64 W={W} attention Jastrow (node bias {b3_node}, MLP Jastrow {with_mlp}): "
+        "log|psi|, 5 sweeps, E_L, gradient")
+    s, m, p, R = _h4(W, b3_node, with_mlp)
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Rd = dev(R)
+    sg, lp, st = F.eval_logpsi(Rd, state, ws)
+    torch.cuda.synchronize()
+    so, lo = O.log_psi(R)
+    log(f"log|psi| err {np.abs(lp.cpu().numpy() - lo.numpy()).max():.1e}; signs "
+        f"{sg.cpu().numpy()[:6]} vs {so.numpy()[:6]}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(sg.cpu().numpy(), so.numpy())
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    rng = np.random.default_rng(9)
+    xi, u = wl.mcmc_noise(5, s.n_el, W, rng)
+    nacc, sg, lp, st = F.mcmc_sweep(Rd, state, ws, 5, 0.2, dev(xi), dev(u))
+    torch.cuda.synchronize()
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.2, xi, u)
+    Rg = Rd.cpu().numpy()
+    log(f"chain: accepts {int(nacc.sum())} vs {int(no.sum())}, |dR| {np.abs(Rg - Ro.numpy()).max():.1e}, "
+        f"|dlogpsi| {np.abs(lp.cpu().numpy() - lo.numpy()).max():.1e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(nacc.cpu().numpy(), no.numpy())
+    assert np.abs(Rg - Ro.numpy()).max() <= 1e-12
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    assert np.array_equal(sg.cpu().numpy(), so.numpy())
+    J1 = F.state_view(state, W, "jas").clone()
+    st2, ws2 = F.buffers(W)
+    F.eval_logpsi(Rd, st2, ws2)
+    torch.cuda.synchronize()
+    dj = float((J1 - F.state_view(st2, W, "jas")).abs().max())
+    log(f"cached vs fresh Jastrow log: {dj:.1e}")
+    assert dj <= 1e-11
+    e, parts, g, st = F.local_energy(Rd, state, ws, None, want_grad=True)
+    torch.cuda.synchronize()
+    eo, po = O.local_energy(Rg)
+    go, _ = O.grad_lap(Rg)
+    err = (np.abs(e.cpu().numpy() - eo.numpy()) / np.maximum(1.0, np.abs(eo.numpy()))).max()
+    gerr = np.abs(g.cpu().numpy() - go.numpy()).max()
+    log(f"E_L rel err {err:.1e}; grad log|psi| err {gerr:.1e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert err <= 1e-8
+    assert gerr <= 1e-9
+    coeff = rng.normal(size=W)
+    gp, st = F.grad_params(Rd, state, ws, dev(coeff))
+    torch.cuda.synchronize()
+    ref = F.flatten({k: v.numpy() for k, v in O.grad_params(Rg, coeff).items()})
+    gp = gp.cpu().numpy()
+    for name, off, shp in F.layout:
+        if name.startswith("jatt_") or name.startswith("jmlp_"):
+            sz = int(np.prod(shp))
+            e_ = np.abs(gp[off:off + sz] - ref[off:off + sz]).max() / max(1e-300, np.abs(ref[off:off + sz]).max())
+            log(f"  {name}: rel err {e_:.1e}")
+            assert e_ <= 1e-10
+    rel = np.abs(gp - ref).max() / np.abs(ref).max()
+    log(f"whole gradient rel err {rel:.1e}")
+    assert rel <= 1e-10
+
+
+def test_polyene_ecp_att_jastrow_matches_oracle(lib):
+    log("case: narrow C12H14 fp64 W=2 with both neural Jastrows: log|psi|, V_NL, E_L, gradient")
+    s, m, p, R = small_polyene(2, ecp=True, seed=11)
+    m = copy.deepcopy(m)
+    m.jas_mlp_width = 16
+    m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 4, 4, 16
+    p = wl.init_params(s, m, np.random.default_rng(37))
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Q = wl.haar_rotations(2, np.random.default_rng(5))
+    Rd = dev(R)
+    sg, lp, _ = F.eval_logpsi(Rd, state, ws)
+    e, parts, _, st = F.local_energy(Rd, state, ws, dev(Q))
+    torch.cuda.synchronize()
+    so, lo = O.log_psi(R)
+    eo, po = O.local_energy(R, Q, chunk=32)
+    vnl_err = np.abs(parts.cpu().numpy()[:, 4] - po.numpy()[:, 4]).max()
+    kin_err = np.abs(parts.cpu().numpy()[:, 0] - po.numpy()[:, 0]).max() / max(1.0, np.abs(po.numpy()[:, 0]).max())
+    err = (np.abs(e.cpu().numpy() - eo.numpy()) / np.maximum(1.0, np.abs(eo.numpy()))).max()
+    log(f"log|psi| err {np.abs(lp.cpu().numpy() - lo.numpy()).max():.1e}; kinetic rel err {kin_err:.1e}; "
+        f"V_NL err {vnl_err:.1e}; E_L rel err {err:.1e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(sg.cpu().numpy(), so.numpy())
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    assert vnl_err <= 1e-9
+    assert err <= 1e-8
+    coeff = np.array([0.6, -1.1])
+    gp, st = F.grad_params(Rd, state, ws, dev(coeff))
+    torch.cuda.synchronize()
+    ref = F.flatten({k: v.numpy() for k, v in O.grad_params(R, coeff).items()})
+    rel = np.abs(gp.cpu().numpy() - ref).max() / np.abs(ref).max()
+    log(f"gradient rel err {rel:.1e}")
+    assert rel <= 1e-10
+
+
+def test_h4_att_jastrow_swap_ratios(lib):
+    log("case: H4 fp64 W=8 with the attention Jastrow: S+ swap ratios")
+    s, m, p, R = _h4(8, -1.0, False)
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    for beta in (2, 3):
+        r, rb, st = F.splus_ratios(Rd, state, ws, beta)
+        torch.cuda.synchronize()
+        ro, rbo = O.splus_ratios(R, beta)
+        err = np.abs(r.cpu().numpy() - ro.numpy()).max() / max(1.0, np.abs(ro.numpy()).max())
+        log(f"beta={beta}: ratio err {err:.1e}")
+        assert (st.cpu().numpy() == 0).all()
+        assert err <= 1e-10
+        assert np.abs(rb.cpu().numpy() - rbo.numpy()).max() <= 1e-9
