@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the uneven 16-system batch")
+    ap.add_argument("--jastrow", action="store_true",
+                    help="also time the hybrid step with the MLP and attention Jastrows at the paper's widths")
     ap.add_argument("--no-rule4", action="store_true",
                     help="skip the E_L phase timed with the 4-point pseudopotential rule on C")
     ap.add_argument("--c5-walkers", type=int, default=512)
@@ -85,13 +87,23 @@ def parse():
     return ap.parse_args()
 
 
-def run_precision(prec, split, W, steps, warmup, want_grad, profile):
+def run_precision(prec, split, W, steps, warmup, want_grad, profile, jastrow=False):
+    import copy
     import torch
     import workloads as wl
     from paper_2504_06087_amd import fire
 
     work = wl.config(3, walkers=W)
     s, m, p, R0 = work.systems[0], work.model, work.params[0], work.R[0]
+    if jastrow:
+        # the paper's Jastrow widths: per-electron MLP [256, 256], 16
+        # registers of width 16 with [256, 256] readouts; their weights
+        # drawn like the rest (the network's own weights unchanged)
+        m = copy.deepcopy(m)
+        m.jas_mlp_width, m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 256, 16, 16, 256
+        pj = wl.init_params(s, m, np.random.default_rng(41))
+        p = {k: (pj[k] if k.startswith(("jmlp_", "jatt_")) else v) for k, v in pj.items()}
+        p.update({k: v for k, v in work.params[0].items()})
     F = fire.Fire(s, m, prec, max_walkers=W, cap_nbr=48, cap_upd=64, refresh_every=50, bf16_split=split)
     F.set_params(p)
     state, ws = F.buffers(W)
@@ -583,6 +595,12 @@ def main():
     hyb = run_precision("bf16", a.split, W, a.steps, a.warmup, not a.no_grad, profile=True)
     print(f"# hybrid: {json.dumps({k: v for k, v in hyb.items() if k != 'prof'})}", flush=True)
     print(f"# hybrid GEMM profile: {hyb['prof']}", flush=True)
+    jas = None
+    if a.jastrow:
+        torch.cuda.empty_cache()
+        jas = run_precision("bf16", a.split, W, a.steps, a.warmup, not a.no_grad, profile=False, jastrow=True)
+        jas = {k: v for k, v in jas.items() if k not in ("prof", "counts")}
+        print(f"# hybrid with the MLP and attention Jastrows: {json.dumps(jas)}", flush=True)
     rule4 = None
     if not a.no_rule4:
         torch.cuda.empty_cache()
@@ -640,6 +658,7 @@ def main():
         "global_jump_sweep": hyb.get("global_jump_sweep"),
         "stream_overlap": hyb.get("stream_overlap"),
         "local_energy_4point_rule": rule4,
+        "step_with_neural_jastrows": jas,
         "hybrid_e_loc_tolerance": tol,
         "measured_counts": hyb.get("counts"),
         "model_roofline": model_roofline(hyb),
