@@ -20,14 +20,17 @@ pytestmark = pytest.mark.gpu
 STEP = 0.2
 
 
-def small_batch(W=(6, 4, 5), seed=11, width=32, layers=1, n_det=2):
+def small_batch(W=(6, 4, 5), seed=11, width=32, layers=1, n_det=2, jastrow=False):
     """Three systems of uneven size: H6 chain, a grown C4H4 flake (20
-    electrons), H9 chain (odd electron count)."""
+    electrons), H9 chain (odd electron count); with jastrow, the MLP and
+    attention Jastrows (shared like the embedding)."""
     rng = np.random.default_rng(seed)
     geoms = [wl.h_chain(6), wl.grown_flake(20), wl.h_chain(9)]
     systems = [wl.make_system(f"b{k}", R, sp, pseudo_c=True, per_species=True) for k, (R, sp) in enumerate(geoms)]
     m = wl.Model(width=width, mlp_layers=layers, n_det=n_det, n_env=2, cutoff=5.0, cutoff_nuc=20.0,
                  n_nuc_types=2)
+    if jastrow:
+        m.jas_mlp_width, m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 16, 4, 4, 16
     params = [wl.init_params(s, m, rng) for s in systems]
     shared, private = wl.batch_params(params)
     Rs = [wl.init_walkers(s, w, rng) for s, w in zip(systems, W)]
@@ -89,10 +92,11 @@ def test_batch_equals_each_system_alone(lib):
     assert ds <= 1e-10
 
 
-def test_batch_fp64_matches_oracle(lib):
+@pytest.mark.parametrize("jastrow", [False, True])
+def test_batch_fp64_matches_oracle(lib, jastrow):
     from oracle import Oracle
-    log("case: uneven batch fp64 vs oracle chain, E_L and summed gradient")
-    B, systems, m, shared, private, Rs, noise, R, xi, u, state, ws, nacc = _batch(lib, "fp64")
+    log(f"case: uneven batch fp64 vs oracle chain, E_L and summed gradient (neural Jastrows {jastrow})")
+    B, systems, m, shared, private, Rs, noise, R, xi, u, state, ws, nacc = _batch(lib, "fp64", jastrow=jastrow)
     e, g, st = B.step(R, state, ws, 1, STEP, xi, u, nacc)
     torch.cuda.synchronize()
     e_b = B.split_walkers(e)
