@@ -139,3 +139,37 @@ def test_h4_att_jastrow_swap_ratios(lib):
         assert (st.cpu().numpy() == 0).all()
         assert err <= 1e-10
         assert np.abs(rb.cpu().numpy() - rbo.numpy()).max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec,tol_lp,tol_e", [("fp32", 1e-4, 1e-3), ("bf16", 1e-2, 5e-2)])
+def test_h4_neural_jastrows_reduced_precision(lib, prec, tol_lp, tol_e):
+    """Both neural Jastrows in FP32 and in the BF16 hybrid (split-bf16 GEMMs
+    on every site): log|psi| after a sweep and E_L against the FP64 oracle,
+    within the precision's rounding (relative to max(1, |value|))."""
+    W = 16
+    log(f"case: H4 {prec} W={W} with both neural Jastrows: log|psi|, 2 sweeps, E_L")
+    s, m, p, R = _h4(W, 1.0, True)
+    F, O, state, ws = setup_custom(s, m, p, R, prec, **({"bf16_split": 7} if prec == "bf16" else {}))
+    Rd = dev(R)
+    sg, lp, st = F.eval_logpsi(Rd, state, ws)
+    torch.cuda.synchronize()
+    so, lo = O.log_psi(R)
+    elp = (np.abs(lp.cpu().numpy() - lo.numpy()) / np.maximum(1.0, np.abs(lo.numpy()))).max()
+    rng = np.random.default_rng(4)
+    xi, u = wl.mcmc_noise(2, s.n_el, W, rng)
+    F.mcmc_sweep(Rd, state, ws, 2, 0.2, dev(xi), dev(u))
+    e, parts, _, st2 = F.local_energy(Rd, state, ws, None)
+    torch.cuda.synchronize()
+    Rg = Rd.cpu().numpy()
+    eo, _ = O.local_energy(Rg)
+    _, lo2 = O.log_psi(Rg)
+    F2, _, s3, w3 = setup_custom(s, m, p, Rg, prec, **({"bf16_split": 7} if prec == "bf16" else {}))
+    _, lp2, _ = F2.eval_logpsi(dev(Rg), s3, w3)
+    torch.cuda.synchronize()
+    elp2 = (np.abs(lp2.cpu().numpy() - lo2.numpy()) / np.maximum(1.0, np.abs(lo2.numpy()))).max()
+    ee = (np.abs(e.cpu().numpy() - eo.numpy()) / np.maximum(1.0, np.abs(eo.numpy()))).max()
+    log(f"log|psi| rel err {elp:.1e} (after the sweeps {elp2:.1e}); E_L rel err {ee:.1e}")
+    assert (st.cpu().numpy() == 0).all() and (st2.cpu().numpy() == 0).all()
+    assert np.array_equal(sg.cpu().numpy(), so.numpy())
+    assert elp <= tol_lp and elp2 <= tol_lp
+    assert ee <= tol_e
