@@ -173,3 +173,25 @@ def test_h4_neural_jastrows_reduced_precision(lib, prec, tol_lp, tol_e):
     assert np.array_equal(sg.cpu().numpy(), so.numpy())
     assert elp <= tol_lp and elp2 <= tol_lp
     assert ee <= tol_e
+
+
+def test_h4_neural_jastrows_per_walker_gradients(lib):
+    """The per-walker gradients (the rows SPRING consumes) with both neural
+    Jastrows, against the oracle's one reverse pass per walker."""
+    from oracle import per_walker_gradients
+    W = 6
+    log(f"case: H4 fp64 W={W} with both neural Jastrows: per-walker gradients")
+    s, m, p, R = _h4(W, -1.0, True)
+    F, O_, state, ws = setup_custom(s, m, p, R, "fp64")
+    Rd = dev(R)
+    F.eval_logpsi(Rd, state, ws)
+    O = torch.empty(W, F.P, dtype=torch.float64, device="cuda")
+    coeff = np.random.default_rng(5).normal(size=W)
+    g, st = F.grad_params(Rd, state, ws, dev(coeff), per_walker=O)
+    torch.cuda.synchronize()
+    names = [x[0] for x in F.layout]
+    ref = per_walker_gradients(O_, R, names)
+    err = np.abs(O.cpu().numpy() - ref).max() / np.abs(ref).max()
+    log(f"per-walker rows: max |dO| / max |O| = {err:.1e}")
+    assert (st.cpu().numpy() == 0).all()
+    assert err <= 1e-10
