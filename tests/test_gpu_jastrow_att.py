@@ -195,3 +195,46 @@ def test_h4_neural_jastrows_per_walker_gradients(lib):
     log(f"per-walker rows: max |dO| / max |O| = {err:.1e}")
     assert (st.cpu().numpy() == 0).all()
     assert err <= 1e-10
+
+
+def test_single_electron_with_neural_jastrows(lib):
+    """Edge case: one electron (hydrogen, no spin-down block, no
+    neighbours): the softmax runs over a single electron and the jets have
+    only the electron's own rows; log|psi|, a sweep, E_L and the gradient
+    against the oracle."""
+    W = 8
+    log(f"case: hydrogen fp64 W={W} with both neural Jastrows")
+    s, m, p, R = wl.hydrogen_atom(W=W, seed=3)
+    m = copy.deepcopy(m)
+    m.jas_mlp_width = 8          # at most the embedding width (8)
+    m.jas_att_regs, m.jas_att_dim, m.jas_att_width = 2, 4, 8
+    p = wl.init_params(s, m, np.random.default_rng(17))
+    F, O, state, ws = setup_custom(s, m, p, R, "fp64")
+    Rd = dev(R)
+    sg, lp, st = F.eval_logpsi(Rd, state, ws)
+    torch.cuda.synchronize()
+    so, lo = O.log_psi(R)
+    assert (st.cpu().numpy() == 0).all()
+    assert np.array_equal(sg.cpu().numpy(), so.numpy())
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    rng = np.random.default_rng(2)
+    xi, u = wl.mcmc_noise(3, s.n_el, W, rng)
+    nacc, sg, lp, st = F.mcmc_sweep(Rd, state, ws, 3, 0.3, dev(xi), dev(u))
+    torch.cuda.synchronize()
+    Ro, so, lo, no = O.mcmc_sweep(R, 0.3, xi, u)
+    assert np.array_equal(nacc.cpu().numpy(), no.numpy())
+    assert np.abs(Rd.cpu().numpy() - Ro.numpy()).max() <= 1e-12
+    assert np.abs(lp.cpu().numpy() - lo.numpy()).max() <= 1e-10
+    Rg = Rd.cpu().numpy()
+    e, _, _, st = F.local_energy(Rd, state, ws, None)
+    coeff = rng.normal(size=W)
+    gp, st2 = F.grad_params(Rd, state, ws, dev(coeff))
+    torch.cuda.synchronize()
+    eo, _ = O.local_energy(Rg)
+    ref = F.flatten({k: v.numpy() for k, v in O.grad_params(Rg, coeff).items()})
+    ee = (np.abs(e.cpu().numpy() - eo.numpy()) / np.maximum(1.0, np.abs(eo.numpy()))).max()
+    eg = np.abs(gp.cpu().numpy() - ref).max() / np.abs(ref).max()
+    log(f"E_L rel err {ee:.1e}; gradient rel err {eg:.1e}")
+    assert (st.cpu().numpy() == 0).all() and (st2.cpu().numpy() == 0).all()
+    assert ee <= 1e-8
+    assert eg <= 1e-10
