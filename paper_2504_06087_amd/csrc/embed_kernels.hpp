@@ -234,6 +234,75 @@ FIRE_DEV void pair_features(T dx, T dy, T dz, const T* W1, const T* b1, const T*
 }
 constexpr int FEAT = 48;
 
+// The same features with the layer-2 and envelope weights of a filter staged
+// in LDS (stage_filter: W2 transposed, zero-padded to the compile-time
+// maxima) and every weight read where it is used: far fewer live registers
+// than pair_features, for kernels whose occupancy its preloaded weights would
+// limit.  W1 [4][h1] and b1 [h1] may sit in LDS or in global memory.  Same
+// products in the same order, so the results equal pair_features bit for bit.
+constexpr int FW_W1 = 0, FW_B1 = 4 * kMaxH1, FW_W2T = FW_B1 + kMaxH1, FW_B2 = FW_W2T + kMaxH1 * kMaxH2,
+              FW_SIG = FW_B2 + kMaxH2, FW_SIZE = FW_SIG + kMaxG;
+// fw[FW_W1..] = W1 [4][h1] and fw[FW_B1..] = b1 (compact, when W1 is given),
+// fw[FW_W2T + k kMaxH1 + j] = W2[j][k], then b2 and the envelope widths.
+template <typename T>
+FIRE_DEV void stage_filter(const T* W1, const T* b1, const T* W2, const T* b2, const T* sig, const Dims& D, T* fw,
+                           int tid, int nt) {
+  for (int q = tid; q < FW_SIZE; q += nt) {
+    T v = 0;
+    if (q < FW_B1) {
+      if (W1 && q < 4 * D.h1) v = W1[q];
+    } else if (q < FW_W2T) {
+      if (W1 && q - FW_B1 < D.h1) v = b1[q - FW_B1];
+    } else if (q < FW_B2) {
+      const int k = (q - FW_W2T) / kMaxH1, j = (q - FW_W2T) % kMaxH1;
+      if (k < D.h2 && j < D.h1) v = W2[j * D.h2 + k];
+    } else if (q < FW_SIG) {
+      if (q - FW_B2 < D.h2) v = b2[q - FW_B2];
+    } else {
+      if (q - FW_SIG < D.G) v = sig[q - FW_SIG];
+    }
+    fw[q] = v;
+  }
+}
+template <typename T>
+FIRE_DEV void pair_features_lds(T dx, T dy, T dz, const T* W1, const T* b1, const T* fw, T cut, const Dims& D,
+                                T* out) {
+  T r = sqrt(dx * dx + dy * dy + dz * dz);
+  T e4[4] = {r, dx, dy, dz};
+  T lo = log1p_over(r);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = lo * e4[k];
+  T z1[kMaxH1];
+#pragma unroll
+  for (int k = 0; k < kMaxH1; ++k) {
+    if (k < D.h1) {
+      T a = b1[k];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a += e4[j] * W1[j * D.h1 + k];
+      z1[k] = silu_(a);
+    } else {
+      z1[k] = T(0);
+    }
+  }
+#pragma unroll 2
+  for (int k = 0; k < kMaxH2; ++k) {
+    if (k < D.h2) {
+      const T* w2 = fw + FW_W2T + k * kMaxH1;
+      T a = fw[FW_B2 + k];
+#pragma unroll
+      for (int j = 0; j < kMaxH1; ++j) a += z1[j] * w2[j];
+      out[4 + k] = silu_(a);
+    }
+  }
+  T fc = fcut_(r / cut);
+#pragma unroll 4
+  for (int k = 0; k < kMaxG; ++k) {
+    const T sg = fw[FW_SIG + k];
+    if (k < D.G) out[12 + k] = fc * exp(-(sg * sg) * r * r);
+  }
+  out[44] = fc;
+}
+
 // ---------------------------------------------------------------------------
 // a2 + a3 (first half): s_i = sum_m Gamma_m(e_im) * (nuc_emb_m + ebar_im W_n),
 // then y_i = LayerNorm(s_i).  Workgroup: one thread per channel, epb
@@ -262,19 +331,34 @@ template <typename T, int NR> FIRE_DEV void block_sums(T (&v)[NR], T* red) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __restrict__ R, int64_t nrows,
-                                                  T* __restrict__ y_out, int epb, const int* __restrict__ nrows_dev) {
+// ERB electrons per pass (LDS: ERB x MCH pair features); launches of at most
+// two electrons per workgroup take ERB = 2.  The layer-1 weights of the first
+// EN_LDS_TYPES nucleus types are staged in LDS with the shared filter weights.
+constexpr int EN_LDS_TYPES = 8;
+template <typename T> constexpr int en_erb() { return sizeof(T) == 4 ? 4 : 2; }
+template <typename T, int ERB = en_erb<T>()>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_en_embed(Net<T> P, const double* __restrict__ R,
+                                                                        int64_t nrows, T* __restrict__ y_out, int epb,
+                                                                        const int* __restrict__ nrows_dev) {
   // rows at or beyond a device row count (when given) are inactive
   if (nrows_dev && *nrows_dev < nrows) nrows = *nrows_dev;
   if ((int64_t)blockIdx.x * epb >= nrows) return;
-  constexpr int ERB = sizeof(T) == 4 ? 4 : 2;   // electrons per pass (LDS: ERB x MCH pair features)
   const Dims& D = P.D;
   __shared__ T feat[ERB * MCH * FEAT];
   __shared__ int ntp[MCH];
   __shared__ T red[4 * ERB];
+  __shared__ T fw[FW_SIZE];
+  __shared__ T w1t[EN_LDS_TYPES * 5 * kMaxH1];   // per type: W1 [4][h1], then b1 [h1]
   const int c = threadIdx.x, nt = blockDim.x;
   const bool act = c < D.d;
+  stage_filter<T>(nullptr, nullptr, P.en_W2, P.en_b2, P.en_sig, D, fw, c, nt);
+  {
+    const int ntl = D.NT < EN_LDS_TYPES ? D.NT : EN_LDS_TYPES;
+    for (int q = c; q < ntl * 5 * D.h1; q += nt) {
+      const int t = q / (5 * D.h1), i = q - t * 5 * D.h1;
+      w1t[t * 5 * kMaxH1 + i] = i < 4 * D.h1 ? P.en_W1[t * 4 * D.h1 + i] : P.en_b1[t * D.h1 + i - 4 * D.h1];
+    }
+  }
   T w3[kMaxH2], wenv[kMaxG], wn[4], nemb[4];
   if (act) {
     for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
@@ -301,16 +385,11 @@ __global__ __launch_bounds__(256) void k_en_embed(Net<T> P, const double* __rest
         const int64_t e = eb + r;
         const int m = m0 + k, t = P.ntype[m];
         if (r == 0) ntp[k] = t;
-        // the filter weights are re-read in every pass instead of being
-        // held in registers across the pass loop (an empty asm hides their
-        // loop invariance)
-        const T* W2p = P.en_W2;
-        const T* b2p = P.en_b2;
-        const T* sgp = P.en_sig;
-        asm volatile("" : "+s"(W2p), "+s"(b2p), "+s"(sgp));
-        pair_features<T>((T)(R[3 * e] - P.Rn[3 * m]), (T)(R[3 * e + 1] - P.Rn[3 * m + 1]),
-                         (T)(R[3 * e + 2] - P.Rn[3 * m + 2]), P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1,
-                         W2p, b2p, sgp, (T)D.cutn, D, feat + (r * MCH + k) * FEAT);
+        const T* W1p = t < EN_LDS_TYPES ? w1t + t * 5 * kMaxH1 : P.en_W1 + t * 4 * D.h1;
+        const T* b1p = t < EN_LDS_TYPES ? w1t + t * 5 * kMaxH1 + 4 * D.h1 : P.en_b1 + t * D.h1;
+        pair_features_lds<T>((T)(R[3 * e] - P.Rn[3 * m]), (T)(R[3 * e + 1] - P.Rn[3 * m + 1]),
+                             (T)(R[3 * e + 2] - P.Rn[3 * m + 2]), W1p, b1p, fw, (T)D.cutn, D,
+                             feat + (r * MCH + k) * FEAT);
       }
       __syncthreads();
       if (act) {

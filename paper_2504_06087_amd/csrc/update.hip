@@ -290,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, in
 // h0 + m' and m' for every member at its compact row, and the row's (w, u).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* __restrict__ jw, int e,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_msg_update(Net<T> P, int W, const int* __restrict__ jw, int e,
                                                     const double* __restrict__ R,
                                                     const double* __restrict__ rnew, const int* __restrict__ uidx,
                                                     int capmax, const int* __restrict__ ucnt,
@@ -302,8 +302,12 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
   constexpr int MPC = 21;               // members per chunk (3 pair feature sets each)
   __shared__ T feat[3 * MPC * FEAT];
   __shared__ int mem[MPC];
+  __shared__ T fw[2 * FW_SIZE];   // filter weights of both pair classes
   const int j = blockIdx.x;
   if (ucnt[2 * j] + ucnt[2 * j + 1] == 0) return;   // inactive job
+  for (int a = 0; a < 2; ++a)
+    stage_filter<T>(P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2,
+                    P.ee_sig + a * D.G, D, fw + a * FW_SIZE, threadIdx.x, blockDim.x);
   const int w = jw ? jw[j] : j;
   const int c = threadIdx.x;
   const bool act = c < D.d;
@@ -347,9 +351,9 @@ __global__ __launch_bounds__(256) void k_msg_update(Net<T> P, int W, const int* 
         if (kind == 0) { dx = ux - ox; dy = uy - oy; dz = uz - oz; }        // (u, e) old
         else if (kind == 1) { dx = ux - nx; dy = uy - ny; dz = uz - nz; }   // (u, e) new
         else { dx = nx - ux; dy = ny - uy; dz = nz - uz; }                  // (e, u) new
-        pair_features<T>((T)dx, (T)dy, (T)dz, P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1,
-                         P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2, P.ee_sig + a * D.G, (T)D.cut, D,
-                         feat + threadIdx.x * FEAT);
+        const T* fa = fw + a * FW_SIZE;
+        pair_features_lds<T>((T)dx, (T)dy, (T)dz, fa + FW_W1, fa + FW_B1, fa, (T)D.cut, D,
+                             feat + threadIdx.x * FEAT);
       }
       __syncthreads();
       if (!act) continue;
@@ -1604,7 +1608,7 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
   CHECK(hipGetLastError());
   // h0 and projections of the moved electron
   const int epb = W >= 16384 ? 4 : (W >= 4096 ? 2 : 1);
-  hipLaunchKernelGGL(k_en_embed<T>, dim3((W + epb - 1) / epb), dim3(blk), 0, st, P, (const double*)rnew,
+  hipLaunchKernelGGL((k_en_embed<T, 2>), dim3((W + epb - 1) / epb), dim3(blk), 0, st, P, (const double*)rnew,
                      (int64_t)W, y, epb, jb.Jdev);
   CHECK(hipGetLastError());
   {
