@@ -1055,7 +1055,7 @@ __global__ void k_accept(const Dims D, int W, int e, double* __restrict__ R, con
 //   blocks of WB_RB rows: Z = G_blk dPhi_U^T, G_blk -= Z B.
 // Larger update sets use k_woodbury_prep + k_woodbury_rows.
 template <typename T, typename TI, int KSM>
-__global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx, int capmax,
+__global__ __launch_bounds__(256, KSM > 16 ? 3 : 5) void k_woodbury(const Dims D, int W, int s, const int* __restrict__ uidx, int capmax,
                                                   const int* __restrict__ ucnt, const int* __restrict__ off,
                                                   const int* __restrict__ acc, const T* __restrict__ dphi,
                                                   const T* __restrict__ oseg, char* __restrict__ state, StateRec S,
@@ -1179,26 +1179,26 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      // Gauss-Jordan on [A | I], lane r holds row r; pivots chosen among the
-      // unused rows by magnitude (no row moves) and left unnormalised: step p
-      // subtracts (M_rp / M_ip) times pivot row i from every other row r.
-      // Left columns before p are unit columns by then and are skipped;
-      // columns past k are zero and skipped in groups of four (k is
-      // wave-uniform).  Afterwards row p of A^-1 is the right half of the
-      // pivot row of column p divided by its pivot.
-      double row[2 * KSM];
+      // Gauss-Jordan inversion in place, lane r holds row r of A; pivots are
+      // chosen among the unused rows by magnitude (no row moves).  Step p
+      // with pivot row i: row i is divided by the pivot, its column p taking
+      // 1 / pivot, and every other row subtracts its column-p entry times the
+      // new row i, its column p taking minus that entry over the pivot.
+      // Columns past k are zero and skipped in groups of four (k is
+      // wave-uniform).  Afterwards the row that pivoted column p holds row p
+      // of A^-1 with its columns in pivot order: entry c is A^-1[p][piv[c]].
+      double row[KSM];
 #pragma unroll
-      for (int c = 0; c < KSM; ++c) {
+      for (int c = 0; c < KSM; ++c)
         row[c] = (lane < k && c < k) ? Ai[lane * LA + c] + (c == lane ? 1.0 : 0.0) : 0.0;
-        row[KSM + c] = (lane < k && c == lane) ? 1.0 : 0.0;
-      }
       const int ku = __builtin_amdgcn_readfirstlane(k);
       uint32_t unused = ku >= 32 ? 0xffffffffu : ((1u << ku) - 1u);
       int mycol = 0;
-      double mypv = 1.0;
+      int piv[KSM];
       bool sing = false;
 #pragma unroll
       for (int p = 0; p < KSM; ++p) {
+        piv[p] = 0;
         if (p < ku && !sing) {
           const bool cand = lane < 32 && ((unused >> (lane & 31)) & 1u);
           const float av = (float)fabs(row[p]);
@@ -1210,32 +1210,24 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
             sing = true;
           } else {
             unused &= ~(1u << idx);
-            if (lane == idx) {
-              mypv = pv;
-              mycol = p;
-            }
+            piv[p] = idx;
+            const bool me = lane == idx;
+            if (me) mycol = p;
             const double ip = 1.0 / pv;
-            const double fr = (lane == idx || lane >= ku) ? 0.0 : row[p] * ip;
+            if (me) {
 #pragma unroll
-            for (int c0 = 0; c0 < KSM; c0 += 4) {
-              if (c0 + 3 > p && c0 < ku) {
-                double pr[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                  if (c0 + t > p) pr[t] = readlane_f64(row[c0 + t], idx);
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-                  if (c0 + t > p) row[c0 + t] -= fr * pr[t];
-              }
+              for (int c = 0; c < KSM; ++c)
+                if ((c & ~3) < ku) row[c] = (c == p ? 1.0 : row[c]) * ip;
             }
+            const double fr = (me || lane >= ku) ? 0.0 : row[p];
 #pragma unroll
             for (int c0 = 0; c0 < KSM; c0 += 4) {
               if (c0 < ku) {
                 double pr[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) pr[t] = readlane_f64(row[KSM + c0 + t], idx);
+                for (int t = 0; t < 4; ++t) pr[t] = readlane_f64(row[c0 + t], idx);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) row[KSM + c0 + t] -= fr * pr[t];
+                for (int t = 0; t < 4; ++t) row[c0 + t] = ((c0 + t == p && !me) ? 0.0 : row[c0 + t]) - fr * pr[t];
               }
             }
           }
@@ -1245,12 +1237,14 @@ __global__ __launch_bounds__(256) void k_woodbury(const Dims D, int W, int s, co
         if (lane == 0) { fl[1] = 1; atomicOr(status + w, FIRE_W_SINGULAR); }
       } else {
         if (lane == 0) fl[1] = 0;
-        // A^-1 row p = right half of the pivot row of column p / its pivot;
-        // each pivot lane stores its row transposed (Ai = (A^-1)^T)
-        const double sc_row = 1.0 / mypv;
+        // each pivot lane stores its row of A^-1 transposed (Ai = (A^-1)^T),
+        // undoing the pivot order of the columns
         if (lane < ku)
 #pragma unroll
-          for (int c = 0; c < KSM; ++c) Ai[c * LA + mycol] = c < ku ? row[KSM + c] * sc_row : 0.0;
+          for (int c = 0; c < KSM; ++c) {
+            if (c < ku) Ai[piv[c] * LA + mycol] = row[c];
+            else Ai[c * LA + mycol] = 0.0;
+          }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
