@@ -412,30 +412,36 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 1) void k_msg_update(Net<
 }
 
 // Phi' rows = o' * env (cached env, or the moved electron's new env) and
-// dPhi = Phi' - Phi in the inverse's precision.  One thread per element.
+// dPhi = Phi' - Phi in the inverse's precision.  One workgroup per update row
+// (rows at or beyond the device row count exit), threads over its K N entries.
 template <typename T>
-__global__ void k_dphi(const Dims D, int s, int e, const int* __restrict__ jw, const int* __restrict__ rinfo,
-                       const int* __restrict__ Mdev,
-                       T* __restrict__ oseg, const char* __restrict__ state, StateRec S,
-                       const T* __restrict__ envnew, T* __restrict__ dphi) {
+__global__ __launch_bounds__(256) void k_dphi(const Dims D, int s, int e, const int* __restrict__ jw,
+                                              const int* __restrict__ rinfo, const int* __restrict__ Mdev,
+                                              T* __restrict__ oseg, const char* __restrict__ state, StateRec S,
+                                              const T* __restrict__ envnew, T* __restrict__ dphi) {
+  const int64_t r = blockIdx.x;
+  if (r >= *Mdev) return;
   const int N = D.nsig(s);
   const int KN = D.K * N;
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t rows = *Mdev;
-  if (q >= rows * KN) return;
-  const int64_t r = q / KN;
-  const int col = (int)(q % KN);
   const int j = rinfo[2 * r], u = rinfo[2 * r + 1];
   const int w = jw ? jw[j] : j;
-  const int det = col / N, l = col % N;
   const int iloc = s == 0 ? u : u - D.nu;
   const char* rec = state + (int64_t)w * S.stride;
-  const int64_t idx = det * phi_per_det(D) + phi_block_off(D, s) + (int64_t)iloc * N + l;
-  const T env = (u == e) ? envnew[(int64_t)j * KN + col] : ((const T*)(rec + S.env))[idx];
-  const T pn = oseg[q] * env;
-  const T po = ((const T*)(rec + S.phi))[idx];
-  oseg[q] = pn;
-  dphi[q] = pn - po;
+  const int64_t boff = phi_block_off(D, s) + (int64_t)iloc * N;
+  const T* envc = (const T*)(rec + S.env) + boff;
+  const T* phic = (const T*)(rec + S.phi) + boff;
+  const T* envn = envnew + (int64_t)j * KN;
+  const bool moved = u == e;
+  T* orow = oseg + r * KN;
+  T* drow = dphi + r * KN;
+  for (int col = threadIdx.x; col < KN; col += blockDim.x) {
+    const int det = col / N, l = col - det * N;
+    const int64_t idx = (int64_t)det * phi_per_det(D) + l;
+    const T env = moved ? envn[col] : envc[idx];
+    const T pn = orow[col] * env;
+    orow[col] = pn;
+    drow[col] = pn - phic[idx];
+  }
 }
 
 // A = I + dPhi_U G_U^T for one (job, determinant, spin block) into LDS:
@@ -1682,10 +1688,9 @@ hipError_t propose_ratio(const fire_handle* h, const Net<T>& P, const Jobs& jb, 
     o.C = oseg; o.cmap = rows_dense((int64_t)D.K * N); o.ccol = cols_dense();
     o.M = rows; o.N = D.K * N; o.K = D.d; o.Mdev = Mdev;
     CHECK(gemm_site(h, SITE_ORB, o, st));
-    const int64_t tot = (int64_t)rows * D.K * N;
     const int fused = jb.woodbury ? 0 : 1;   // Metropolis keeps dPhi for the Woodbury update
     if (!fused) {
-      hipLaunchKernelGGL((k_dphi<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, D, s, e, jb.jw,
+      hipLaunchKernelGGL((k_dphi<T>), dim3((unsigned)rows), dim3(256), 0, st, D, s, e, jb.jw,
                          (const int*)ri[s], Mdev, oseg, (const char*)state, S, (const T*)envnew,
                          (T*)(ws + L.dphi[s]));
       CHECK(hipGetLastError());
