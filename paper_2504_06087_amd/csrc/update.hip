@@ -231,21 +231,29 @@ __global__ __launch_bounds__(256) void k_propose(const double* __restrict__ R, J
 __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, int W, int* __restrict__ off,
                                                       int64_t cap0, int64_t cap1, const int* __restrict__ jw,
                                                       int32_t* __restrict__ status, const int* __restrict__ Jdev) {
-  __shared__ int part[2][1024];
+  __shared__ int wtot[2][16];
   __shared__ int first_over[2], total[2];
-  const int t = threadIdx.x, nt = blockDim.x;
+  const int t = threadIdx.x, nt = blockDim.x;   // nt = 1024: 16 full waves
+  const int lane = t & 63, wv = t >> 6, nw = nt >> 6;
   const int Wl = Jdev && *Jdev < W ? (*Jdev > 0 ? *Jdev : 0) : W;
   const int per = (Wl + nt - 1) / nt;
   if (t < 2) first_over[t] = 0x7fffffff;
   const int b = t * per, e = b + per < Wl ? b + per : Wl;
   int s0 = 0, s1 = 0;
   for (int w = b; w < e; ++w) { s0 += ucnt[2 * w]; s1 += ucnt[2 * w + 1]; }
-  part[0][t] = s0;
-  part[1][t] = s1;
+  // exclusive scan of the threads' sums: inclusive scans within each wave,
+  // then the wave totals in order
+  int i0 = s0, i1 = s1;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y0 = __shfl_up(i0, d), y1 = __shfl_up(i1, d);
+    if (lane >= d) { i0 += y0; i1 += y1; }
+  }
+  if (lane == 63) { wtot[0][wv] = i0; wtot[1][wv] = i1; }
   __syncthreads();
   if (t < 2) {
     int acc = 0;
-    for (int k = 0; k < nt; ++k) { int v = part[t][k]; part[t][k] = acc; acc += v; }
+    for (int k = 0; k < nw; ++k) { const int v = wtot[t][k]; wtot[t][k] = acc; acc += v; }
     off[t * (W + 1) + W] = acc;
     total[t] = acc;
   }
@@ -254,7 +262,7 @@ __global__ __launch_bounds__(1024) void k_scan_counts(int* __restrict__ ucnt, in
     off[w] = total[0];
     off[(W + 1) + w] = total[1];
   }
-  int a0 = part[0][t], a1 = part[1][t];
+  int a0 = wtot[0][wv] + i0 - s0, a1 = wtot[1][wv] + i1 - s1;
   for (int w = b; w < e; ++w) {
     off[w] = a0;
     off[(W + 1) + w] = a1;
