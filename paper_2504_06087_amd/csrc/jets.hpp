@@ -46,9 +46,11 @@ template <typename T> FIRE_DEV J3<T> jsilu(const J3<T>& x) {
 // Each jet occupies 5 consecutive T (v, gx, gy, gz, l); out[44*5] holds f_cut.
 constexpr int JFEAT = 44 * 5 + 4;
 
+// W2 entry (j, k) is read at W2[j s2j + k s2k]: (h2, 1) for the row-major
+// parameter, (1, kMaxH1) for a transposed copy staged in LDS.
 template <typename T>
-FIRE_DEV void pair_feature_jets(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, const T* b2, const T* sig,
-                                T cut, const Dims& D, T* out) {
+FIRE_DEV void pair_feature_jets(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, int s2j, int s2k,
+                                const T* b2, const T* sig, T cut, const Dims& D, T* out) {
   T r = sqrt(dx * dx + dy * dy + dz * dz);
   J3<T> rj;
   rj.v = r;
@@ -81,7 +83,7 @@ FIRE_DEV void pair_feature_jets(T dx, T dy, T dz, const T* W1, const T* b1, cons
   }
   for (int k = 0; k < D.h2; ++k) {
     J3<T> a = jconst(b2[k]);
-    for (int j = 0; j < D.h1; ++j) jaxpy(a, W2[j * D.h2 + k], z1[j]);
+    for (int j = 0; j < D.h1; ++j) jaxpy(a, W2[j * s2j + k * s2k], z1[j]);
     put(4 + k, jsilu(a));
   }
   fcut3(r / cut, f, f1, f2);
@@ -93,6 +95,12 @@ FIRE_DEV void pair_feature_jets(T dx, T dy, T dz, const T* W1, const T* b1, cons
     put(12 + k, jmul(fc, gk));
   }
   out[44 * 5] = f;
+}
+
+template <typename T>
+FIRE_DEV void pair_feature_jets(T dx, T dy, T dz, const T* W1, const T* b1, const T* W2, const T* b2, const T* sig,
+                                T cut, const Dims& D, T* out) {
+  pair_feature_jets<T>(dx, dy, dz, W1, b1, W2, D.h2, 1, b2, sig, cut, D, out);
 }
 
 template <typename T> FIRE_DEV J3<T> jload(const T* p) { return J3<T>{p[0], {p[1], p[2], p[3]}, p[4]}; }

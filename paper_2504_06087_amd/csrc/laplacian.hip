@@ -134,13 +134,25 @@ __global__ __launch_bounds__(1024) void k_jet_offsets(int Wc, int n, int nu, con
 constexpr int JCH = 32;   // pairs per LDS chunk
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_en_embed_jet(Net<T> P, const double* __restrict__ R, int64_t nrows,
-                                                      T* __restrict__ yj) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_en_embed_jet(Net<T> P, const double* __restrict__ R,
+                                                                            int64_t nrows, T* __restrict__ yj) {
   const Dims& D = P.D;
   __shared__ T feat[JCH * JFEAT];
   __shared__ T red[16];
+  // filter weights staged in LDS as in k_en_embed (shared part, then layer 1
+  // of the first EN_LDS_TYPES nucleus types)
+  __shared__ T fw[FW_SIZE];
+  __shared__ T w1t[EN_LDS_TYPES * 5 * kMaxH1];
   const int c = threadIdx.x;
   const bool act = c < D.d;
+  stage_filter<T>(nullptr, nullptr, P.en_W2, P.en_b2, P.en_sig, D, fw, c, blockDim.x);
+  {
+    const int ntl = D.NT < EN_LDS_TYPES ? D.NT : EN_LDS_TYPES;
+    for (int q = c; q < ntl * 5 * D.h1; q += blockDim.x) {
+      const int t = q / (5 * D.h1), i = q - t * 5 * D.h1;
+      w1t[t * 5 * kMaxH1 + i] = i < 4 * D.h1 ? P.en_W1[t * 4 * D.h1 + i] : P.en_b1[t * D.h1 + i - 4 * D.h1];
+    }
+  }
   T w3[kMaxH2], wenv[kMaxG], wn[4];
   if (act) {
     for (int k = 0; k < D.h2; ++k) w3[k] = P.en_W3[k * D.d + c];
@@ -157,8 +169,10 @@ __global__ __launch_bounds__(256) void k_en_embed_jet(Net<T> P, const double* __
       __syncthreads();
       if (threadIdx.x < mc) {
         const int m = m0 + threadIdx.x, t = P.ntype[m];
-        pair_feature_jets<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]),
-                             P.en_W1 + t * 4 * D.h1, P.en_b1 + t * D.h1, P.en_W2, P.en_b2, P.en_sig, (T)D.cutn, D,
+        const T* W1p = t < EN_LDS_TYPES ? w1t + t * 5 * kMaxH1 : P.en_W1 + t * 4 * D.h1;
+        const T* b1p = t < EN_LDS_TYPES ? w1t + t * 5 * kMaxH1 + 4 * D.h1 : P.en_b1 + t * D.h1;
+        pair_feature_jets<T>((T)(rx - P.Rn[3 * m]), (T)(ry - P.Rn[3 * m + 1]), (T)(rz - P.Rn[3 * m + 2]), W1p, b1p,
+                             fw + FW_W2T, 1, kMaxH1, fw + FW_B2, fw + FW_SIG, (T)D.cutn, D,
                              feat + threadIdx.x * JFEAT);
       }
       __syncthreads();
@@ -224,7 +238,8 @@ __global__ void k_glu_jet(const T* __restrict__ ugj, T* __restrict__ tj, int64_t
 // neighbour slot in list order, Laplacian row).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_msg_jet(Net<T> P, const double* __restrict__ R, int64_t nrows,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_msg_jet(Net<T> P, const double* __restrict__ R,
+                                                                       int64_t nrows,
                                                  const int16_t* __restrict__ nidx, const int32_t* __restrict__ ncnt,
                                                  const int* __restrict__ joff, const T* __restrict__ h0j,
                                                  const T* __restrict__ projj, T* __restrict__ hval, T* jet0,
@@ -232,11 +247,15 @@ __global__ __launch_bounds__(256) void k_msg_jet(Net<T> P, const double* __restr
   const Dims& D = P.D;
   __shared__ T feat[JCH * JFEAT];
   __shared__ int jn[JCH];
+  __shared__ T fw[2 * FW_SIZE];   // filter weights of both pair classes
   const int c = threadIdx.x;
   const bool act = c < D.d;
   const int n = D.n, d = D.d;
   const int64_t e = blockIdx.x;
   if (e >= nrows) return;
+  for (int a = 0; a < 2; ++a)
+    stage_filter<T>(P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2, P.ee_b2 + a * D.h2,
+                    P.ee_sig + a * D.G, D, fw + a * FW_SIZE, c, blockDim.x);
   const int64_t w = e / n;
   const int i = (int)(e % n);
   const int si = i < D.nu ? 0 : 1;
@@ -266,9 +285,10 @@ __global__ __launch_bounds__(256) void k_msg_jet(Net<T> P, const double* __restr
       if (threadIdx.x < jc) {
         const int j = nidx[e * D.cap_nbr + sbase + j0 + threadIdx.x];
         jn[threadIdx.x] = j;
-        pair_feature_jets<T>((T)(rx - Rw[3 * j]), (T)(ry - Rw[3 * j + 1]), (T)(rz - Rw[3 * j + 2]),
-                             P.ee_W1 + a * 4 * D.h1, P.ee_b1 + a * D.h1, P.ee_W2 + a * D.h1 * D.h2,
-                             P.ee_b2 + a * D.h2, P.ee_sig + a * D.G, (T)D.cut, D, feat + threadIdx.x * JFEAT);
+        const T* fa = fw + a * FW_SIZE;
+        pair_feature_jets<T>((T)(rx - Rw[3 * j]), (T)(ry - Rw[3 * j + 1]), (T)(rz - Rw[3 * j + 2]), fa + FW_W1,
+                             fa + FW_B1, fa + FW_W2T, 1, kMaxH1, fa + FW_B2, fa + FW_SIG, (T)D.cut, D,
+                             feat + threadIdx.x * JFEAT);
       }
       __syncthreads();
       if (!act) continue;
