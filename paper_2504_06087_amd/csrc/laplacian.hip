@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256) void k_lap_members(const Dims D, int Wc, const
 // MFMA with the same output layout, so sum_ab M_ab M_ba is a lane-wise
 // product of the two accumulators.  Rows past |T_n| are zero.
 template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, const int* __restrict__ memb,
+__global__ __launch_bounds__(256, 4) void k_det_lap(const Dims D, int Wc, int w0, const int* __restrict__ memb,
                                                  const int* __restrict__ mslot, const int* __restrict__ mcnt,
                                                  int tcap, const int32_t* __restrict__ ncnt,
                                                  const int* __restrict__ joff, const T* __restrict__ dphi0,
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_det_lap(const Dims D, int Wc, int w0, c
           // segment and G row e0, columns past N read column N-1; values
           // zeroed after), every MFMA step runs: the reads of a 32-column
           // chunk are all in flight together
-          constexpr int CH = 8;
+          constexpr int CH = 6;
           for (int cb = 0; cb < N; cb += 4 * CH) {
             double dx[CH], gyv[CH], gxv[CH], dyv[CH];
             if (pair) {
