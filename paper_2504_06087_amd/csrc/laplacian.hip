@@ -531,7 +531,7 @@ __global__ __launch_bounds__(256, 4) void k_det_lap(const Dims D, int Wc, int w0
           d4v_ m1 = {0.0, 0.0, 0.0, 0.0}, m2 = {0.0, 0.0, 0.0, 0.0};
           // unconditional reads (rows past t read member row 0 of the
           // segment and G row e0, columns past N read column N-1; values
-          // zeroed after), every MFMA step runs: the reads of a 32-column
+          // zeroed after), every MFMA step runs: the reads of a 24-column
           // chunk are all in flight together
           constexpr int CH = 6;
           for (int cb = 0; cb < N; cb += 4 * CH) {
