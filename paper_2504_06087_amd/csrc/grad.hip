@@ -21,6 +21,7 @@ namespace fire {
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return e_; } while (0)
 
 constexpr int GNS = 32;      // K-splits of the weight-gradient GEMMs
+constexpr int CNS = 1024;    // row splits of the bias-gradient column sums
 constexpr int GBLK = 1024;   // persistent workgroups of the edge kernels
 constexpr int ECH = 32;      // pairs per LDS chunk in the edge kernels
 constexpr int EFEAT = 96;    // per-pair stored values (see edge_forward)
@@ -69,9 +70,16 @@ __global__ void k_colsum(const T* __restrict__ X, RowMap m, int R, int C, int ns
   const int per = (R + ns - 1) / ns;
   const int r0 = z * per, r1 = r0 + per < R ? r0 + per : R;
   T v = 0;
-  for (int r = r0; r < r1; ++r) {
-    const uint32_t rr = (uint32_t)r, p = (uint32_t)m.rpg, q = rr / p;
-    v += X[(int64_t)q * m.gstride + (int64_t)(rr - q * p) * m.rstride + c];
+  if (r0 < r1) {
+    // row r sits at (r / rpg) gstride + (r % rpg) rstride: quotient and
+    // remainder are stepped along the chunk
+    const uint32_t p = (uint32_t)m.rpg;
+    uint32_t q = (uint32_t)r0 / p, rem = (uint32_t)r0 - q * p;
+    const T* xc = X + c;
+    for (int r = r0; r < r1; ++r) {
+      v += xc[(int64_t)q * m.gstride + (int64_t)rem * m.rstride];
+      if (++rem == p) { rem = 0; ++q; }
+    }
   }
   part[(int64_t)z * C + c] = v;
 }
@@ -951,7 +959,8 @@ static GradLayout grad_layout(const fire_handle* h, int W) {
   L.bbar = take(R * D.B * ts);
   L.trA = take(R * widest * ts);
   L.trB = take(R * widest * ts);
-  L.split = take((size_t)GNS * widest * widest * ts);
+  L.split = take(((size_t)GNS * widest * widest > (size_t)CNS * widest ? (size_t)GNS * widest * widest
+                                                                     : (size_t)CNS * widest) * ts);
   const size_t ep = (size_t)GBLK * ((size_t)msg_part_size(D) > (size_t)2 * D.d ? (size_t)msg_part_size(D) : 2 * D.d);
   const size_t enp = (size_t)GBLK * ((D.M + ENCH - 1) / ENCH) * en_off(D).size;
   L.epart = take((ep > enp ? ep : enp) * ts);
@@ -999,9 +1008,9 @@ template <typename T>
 static hipError_t bgrad(const GradLayout& L, char* ws, const T* X, RowMap xm, int R, int C, double* grad, int64_t base,
                         hipStream_t st) {
   T* part = (T*)(ws + L.split);
-  hipLaunchKernelGGL(k_colsum<T>, dim3((C + 255) / 256, GNS), dim3(256), 0, st, X, xm, R, C, GNS, part);
+  hipLaunchKernelGGL(k_colsum<T>, dim3((C + 255) / 256, CNS), dim3(256), 0, st, X, xm, R, C, CNS, part);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_splits<T>, dim3((C + 255) / 256), dim3(256), 0, st, (const T*)part, GNS, 1, C, grad,
+  hipLaunchKernelGGL(k_reduce_splits<T>, dim3((C + 255) / 256), dim3(256), 0, st, (const T*)part, CNS, 1, C, grad,
                      base, (int64_t)0, (int64_t)1 << 40, (int64_t)0, (int64_t)1);
   return hipGetLastError();
 }
