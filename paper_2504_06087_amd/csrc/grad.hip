@@ -84,17 +84,26 @@ __global__ void k_colsum(const T* __restrict__ X, RowMap m, int R, int C, int ns
   part[(int64_t)z * C + c] = v;
 }
 
-// grad[base + j] += sum_b part[b][col0 + j], j < len
-__global__ void k_reduce_cols(const void* __restrict__ part, int tsize, int nb, int64_t stride, int64_t col0, int len,
-                              double* __restrict__ grad, int64_t base) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// grad[base + j] += sum_b part[b][col0 + j], j < len: one workgroup of 256
+// threads per column j, the partials strided over its threads, then summed
+// in a fixed order (the same on every call)
+__global__ __launch_bounds__(256) void k_reduce_cols(const void* __restrict__ part, int tsize, int nb, int64_t stride,
+                                                     int64_t col0, int len, double* __restrict__ grad, int64_t base) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
   if (j >= len) return;
   double v = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = t; b < nb; b += 256) {
     const int64_t q = (int64_t)b * stride + col0 + j;
     v += tsize == 8 ? ((const double*)part)[q] : (double)((const float*)part)[q];
   }
-  grad[base + j] += v;
+  red[t] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) grad[base + j] += red[0];
 }
 
 template <typename T>
@@ -1260,7 +1269,7 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
     for (int a = 0; a < 2; ++a) {
       const int64_t o = (int64_t)a * (fo.size + 5 * d);
       auto red = [&](int64_t col, int len, int64_t base) {
-        hipLaunchKernelGGL(k_reduce_cols, dim3((len + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
+        hipLaunchKernelGGL(k_reduce_cols, dim3(len), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
                            nb_msg, (int64_t)ps, o + col, len, grad, base);
         return hipGetLastError();
       };
@@ -1314,10 +1323,10 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
   const int nb_ln = rows < GBLK ? (int)rows : GBLK;
   hipLaunchKernelGGL(k_ln_bwd<T>, dim3(nb_ln), dim3(blk), 0, st, P, Rc, rows, (const T*)ybar, sbar, epart);
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_cols, dim3((d + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
+  hipLaunchKernelGGL(k_reduce_cols, dim3(d), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
                      (int64_t)2 * d, (int64_t)0, d, grad, th("ln_g"));
   CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_cols, dim3((d + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
+  hipLaunchKernelGGL(k_reduce_cols, dim3(d), dim3(256), 0, st, (const void*)epart, (int)sizeof(T), nb_ln,
                      (int64_t)2 * d, (int64_t)d, d, grad, th("ln_b"));
   CHECK(hipGetLastError());
   {
@@ -1330,7 +1339,7 @@ static hipError_t grad_chunk(const fire_handle* h, const Net<T>& P, int w0, int 
     CHECK(hipGetLastError());
     const int nbt = nbx * nmc;
     auto red = [&](int64_t col, int len, int64_t base) {
-      hipLaunchKernelGGL(k_reduce_cols, dim3((len + 255) / 256), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
+      hipLaunchKernelGGL(k_reduce_cols, dim3(len), dim3(256), 0, st, (const void*)epart, (int)sizeof(T),
                          nbt, (int64_t)eo.size, col, len, grad, base);
       return hipGetLastError();
     };
